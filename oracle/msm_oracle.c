@@ -1,0 +1,674 @@
+/*
+ * msm_oracle.c -- TEST INFRASTRUCTURE ONLY (see msm_oracle.h).
+ *
+ * Plain FP64 reference of the multilevel summation method with B-spline
+ * interpolation.  Each routine follows one passage of the paper and is
+ * written for the reader, not for speed: no blocking, no fusion, no
+ * reordering beyond what the quoted definition states.  OpenMP only
+ * distributes independent outer iterations.
+ */
+#include "msm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------
+ * Softening function (Sec. "Splitting for Coulomb kernels"): gamma(rho) is
+ * 1/rho for rho >= 1 and, below 1, the Taylor polynomial of s^(-1/2) about
+ * s = 1 up to degree p-1 in s, evaluated at s = rho^2.
+ * ---------------------------------------------------------------------- */
+static double binom_mhalf(int k) /* binomial coefficient C(-1/2, k) */
+{
+  double c = 1.0;
+  for (int j = 0; j < k; ++j) c *= (-0.5 - j) / (double)(j + 1);
+  return c;
+}
+
+/* g(s) = sum_{k<p} C(-1/2,k) (s-1)^k and its s-derivatives */
+static double taylor_g(int p, double s, int deriv)
+{
+  double sum = 0.0;
+  for (int k = deriv; k < p; ++k) {
+    double fall = 1.0; /* k (k-1) ... (k-deriv+1) */
+    for (int j = 0; j < deriv; ++j) fall *= (double)(k - j);
+    sum += binom_mhalf(k) * fall * pow(s - 1.0, k - deriv);
+  }
+  return sum;
+}
+
+double orc_gamma(int p, double rho)
+{
+  if (rho >= 1.0) return 1.0 / rho;
+  return taylor_g(p, rho * rho, 0);
+}
+
+double orc_gamma_d1(int p, double rho)
+{
+  if (rho >= 1.0) return -1.0 / (rho * rho);
+  return 2.0 * rho * taylor_g(p, rho * rho, 1);
+}
+
+double orc_gamma_d2(int p, double rho)
+{
+  if (rho >= 1.0) return 2.0 / (rho * rho * rho);
+  double s = rho * rho;
+  return 2.0 * taylor_g(p, s, 1) + 4.0 * s * taylor_g(p, s, 2);
+}
+
+/* Partial kernels (eq. coulomb_splitting_with_softener). */
+double orc_kernel(int l, int L, double a, int p, double r)
+{
+  if (l == 0) return 1.0 / r - orc_gamma(p, r / a) / a;
+  double s0 = ldexp(a, l - 1); /* 2^(l-1) a */
+  if (l == L) return orc_gamma(p, r / s0) / s0;
+  double s1 = ldexp(a, l); /* 2^l a */
+  return orc_gamma(p, r / s0) / s0 - orc_gamma(p, r / s1) / s1;
+}
+
+double orc_k0_d1(double a, int p, double r)
+{
+  return -1.0 / (r * r) - orc_gamma_d1(p, r / a) / (a * a);
+}
+
+double orc_k0_d2(double a, int p, double r)
+{
+  return 2.0 / (r * r * r) - orc_gamma_d2(p, r / a) / (a * a * a);
+}
+
+/* ------------------------------------------------------------------------
+ * Cardinal B-splines (Sec. "B-spline interpolation"): M_1 is the indicator
+ * of [0,1) and M_k(t) = [t M_{k-1}(t) + (k-t) M_{k-1}(t-1)] / (k-1) (de Boor
+ * recursion).  The basis function centred on a grid point is
+ * Phi_p(t) = M_p(t + p/2).  M_k' = M_{k-1}(t) - M_{k-1}(t-1).
+ * cardinal_M evaluates M_k(t - j) for j = 0..k-1 bottom-up through the same
+ * recursion and returns M_k(t).
+ * ---------------------------------------------------------------------- */
+static double cardinal_M(int k, double t)
+{
+  if (k <= 0) return 0.0;
+  double B[32];
+  /* order 1: B[j] = M_1(t - j) */
+  for (int j = 0; j < k; ++j) {
+    double tj = t - j;
+    B[j] = (tj >= 0.0 && tj < 1.0) ? 1.0 : 0.0;
+  }
+  for (int ord = 2; ord <= k; ++ord) {
+    /* B[j] <- M_ord(t - j) for j = 0..k-ord */
+    for (int j = 0; j + ord <= k; ++j) {
+      double tj = t - j;
+      B[j] = (tj * B[j] + (ord - tj) * B[j + 1]) / (double)(ord - 1);
+    }
+  }
+  return B[0];
+}
+
+double orc_bspline(int p, double t) { return cardinal_M(p, t + 0.5 * p); }
+
+double orc_bspline_d1(int p, double t)
+{
+  double u = t + 0.5 * p;
+  return cardinal_M(p - 1, u) - cardinal_M(p - 1, u - 1.0);
+}
+
+double orc_bspline_d2(int p, double t)
+{
+  double u = t + 0.5 * p;
+  return cardinal_M(p - 2, u) - 2.0 * cardinal_M(p - 2, u - 1.0) +
+         cardinal_M(p - 2, u - 2.0);
+}
+
+/* ------------------------------------------------------------------------
+ * Basis functions of one level along one axis.  For a particle coordinate x
+ * the non-zero basis functions are the p grid points m = floor(x/h) - p/2 + 1
+ * ... floor(x/h) + p/2 (index set M_i of the paper).  Periodic axes use the
+ * periodic basis sum_j Phi(x/h - m - j n), i.e. the index is taken mod n.
+ * Returns -1 if a non-zero weight falls outside a non-periodic grid.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int idx[32];    /* array index (0..n-1) */
+  double w[32];   /* Phi */
+  double dw[32];  /* d Phi / dx */
+  double d2w[32]; /* d^2 Phi / dx^2 */
+} axis_basis;
+
+static int basis_axis(const orc_geom* g, int level, int ax, double x, axis_basis* b)
+{
+  const int p = g->p;
+  const double h = g->h[level - 1][ax];
+  const int n = g->n[level - 1][ax];
+  const int lo = g->lo[level - 1][ax];
+  if (g->periodic[ax]) {
+    double Lb = g->box[ax];
+    x = x - Lb * floor(x / Lb);
+  }
+  double u = x / h;
+  int base = (int)floor(u);
+  for (int k = 0; k < p; ++k) {
+    int m = base - p / 2 + 1 + k;
+    double t = u - m;
+    b->w[k] = orc_bspline(p, t);
+    b->dw[k] = orc_bspline_d1(p, t) / h;
+    b->d2w[k] = orc_bspline_d2(p, t) / (h * h);
+    int ai;
+    if (g->periodic[ax]) {
+      ai = ((m % n) + n) % n;
+    } else {
+      ai = m - lo;
+      if (ai < 0 || ai >= n) {
+        if (b->w[k] != 0.0 || b->dw[k] != 0.0) return -1;
+        ai = -1; /* zero weight, skipped */
+      }
+    }
+    b->idx[k] = ai;
+  }
+  return 0;
+}
+
+static long flat(const orc_geom* g, int level, int ix, int iy, int iz)
+{
+  const int* n = g->n[level - 1];
+  return ((long)iz * n[1] + iy) * n[0] + ix;
+}
+
+int orc_anterpolate(const orc_geom* g, int level, int n, const double* pos,
+                    const double* q, double* grid)
+{
+  /* Alg. anterpolation_double_loop: outer loop over particles, inner loop
+   * over the index set of each particle. */
+  const int p = g->p;
+  for (int i = 0; i < n; ++i) {
+    axis_basis bx, by, bz;
+    if (basis_axis(g, level, 0, pos[3 * i + 0], &bx) ||
+        basis_axis(g, level, 1, pos[3 * i + 1], &by) ||
+        basis_axis(g, level, 2, pos[3 * i + 2], &bz))
+      return -1;
+    for (int c = 0; c < p; ++c)
+      for (int b = 0; b < p; ++b)
+        for (int a = 0; a < p; ++a) {
+          if (bx.idx[a] < 0 || by.idx[b] < 0 || bz.idx[c] < 0) continue;
+          grid[flat(g, level, bx.idx[a], by.idx[b], bz.idx[c])] +=
+              q[i] * bx.w[a] * by.w[b] * bz.w[c];
+        }
+  }
+  return 0;
+}
+
+int orc_anterpolate_dipole(const orc_geom* g, int level, int n, const double* pos,
+                           const double* q, const double* v, double* grid)
+{
+  const int p = g->p;
+  for (int i = 0; i < n; ++i) {
+    axis_basis bx, by, bz;
+    if (basis_axis(g, level, 0, pos[3 * i + 0], &bx) ||
+        basis_axis(g, level, 1, pos[3 * i + 1], &by) ||
+        basis_axis(g, level, 2, pos[3 * i + 2], &bz))
+      return -1;
+    for (int c = 0; c < p; ++c)
+      for (int b = 0; b < p; ++b)
+        for (int a = 0; a < p; ++a) {
+          if (bx.idx[a] < 0 || by.idx[b] < 0 || bz.idx[c] < 0) continue;
+          double gx = bx.dw[a] * by.w[b] * bz.w[c];
+          double gy = bx.w[a] * by.dw[b] * bz.w[c];
+          double gz = bx.w[a] * by.w[b] * bz.dw[c];
+          grid[flat(g, level, bx.idx[a], by.idx[b], bz.idx[c])] +=
+              q[i] * (v[3 * i] * gx + v[3 * i + 1] * gy + v[3 * i + 2] * gz);
+        }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Stencil (eq. kernel_stencil_by_conv_with_universal_coeff):
+ *   K^l_m = sum_n omega'_{mx-nx} omega'_{my-ny} omega'_{mz-nz} k_l(|h_l o n|)
+ * written as the plain triple sum over the omega' support.  The samples of
+ * k_l are tabulated first on the box |n_k| <= W_k + M.
+ * ---------------------------------------------------------------------- */
+static double omega_at(const orc_geom* g, int j)
+{
+  j = j < 0 ? -j : j;
+  return j <= g->M ? g->omega[j] : 0.0;
+}
+
+void orc_stencil(const orc_geom* g, int level, const int W[3], double* K)
+{
+  const int M = g->M;
+  const double* h = g->h[level - 1];
+  int S[3], ns[3];
+  for (int k = 0; k < 3; ++k) {
+    S[k] = W[k] + M;
+    ns[k] = 2 * S[k] + 1;
+  }
+  double* samp = (double*)malloc(sizeof(double) * ns[0] * ns[1] * ns[2]);
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int z = -S[2]; z <= S[2]; ++z)
+    for (int y = -S[1]; y <= S[1]; ++y)
+      for (int x = -S[0]; x <= S[0]; ++x) {
+        double rx = x * h[0], ry = y * h[1], rz = z * h[2];
+        double r = sqrt(rx * rx + ry * ry + rz * rz);
+        samp[((long)(z + S[2]) * ns[1] + (y + S[1])) * ns[0] + (x + S[0])] =
+            orc_kernel(level, g->L, g->a, g->p, r);
+      }
+  int nk[3] = {2 * W[0] + 1, 2 * W[1] + 1, 2 * W[2] + 1};
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int mz = -W[2]; mz <= W[2]; ++mz)
+    for (int my = -W[1]; my <= W[1]; ++my)
+      for (int mx = -W[0]; mx <= W[0]; ++mx) {
+        double sum = 0.0;
+        for (int kz = -M; kz <= M; ++kz)
+          for (int ky = -M; ky <= M; ++ky)
+            for (int kx = -M; kx <= M; ++kx) {
+              /* n = m - k */
+              int nx = mx - kx, ny = my - ky, nz = mz - kz;
+              double s = samp[((long)(nz + S[2]) * ns[1] + (ny + S[1])) * ns[0] +
+                              (nx + S[0])];
+              sum += omega_at(g, kx) * omega_at(g, ky) * omega_at(g, kz) * s;
+            }
+        K[((long)(mz + W[2]) * nk[1] + (my + W[1])) * nk[0] + (mx + W[0])] = sum;
+      }
+  free(samp);
+}
+
+/* ------------------------------------------------------------------------
+ * Grid potential (eq. action_of_K_as_convolution): e_m = sum_n K_{m-n} q_n.
+ * Written as a sum over stencil offsets d = m - n.
+ * ---------------------------------------------------------------------- */
+static void conv_point(const orc_geom* g, int level, const int W[3], const double* K,
+                       const double* qgrid, double* egrid, long m)
+{
+  const int* n = g->n[level - 1];
+  int nk[3] = {2 * W[0] + 1, 2 * W[1] + 1, 2 * W[2] + 1};
+  int mx = (int)(m % n[0]);
+  int my = (int)((m / n[0]) % n[1]);
+  int mz = (int)(m / ((long)n[0] * n[1]));
+  double sum = 0.0;
+  for (int dz = -W[2]; dz <= W[2]; ++dz) {
+    int iz = mz - dz;
+    if (g->periodic[2]) iz = ((iz % n[2]) + n[2]) % n[2];
+    else if (iz < 0 || iz >= n[2]) continue;
+    for (int dy = -W[1]; dy <= W[1]; ++dy) {
+      int iy = my - dy;
+      if (g->periodic[1]) iy = ((iy % n[1]) + n[1]) % n[1];
+      else if (iy < 0 || iy >= n[1]) continue;
+      for (int dx = -W[0]; dx <= W[0]; ++dx) {
+        int ix = mx - dx;
+        if (g->periodic[0]) ix = ((ix % n[0]) + n[0]) % n[0];
+        else if (ix < 0 || ix >= n[0]) continue;
+        double kv = K[((long)(dz + W[2]) * nk[1] + (dy + W[1])) * nk[0] + (dx + W[0])];
+        sum += kv * qgrid[((long)iz * n[1] + iy) * n[0] + ix];
+      }
+    }
+  }
+  egrid[m] = sum;
+}
+
+void orc_conv(const orc_geom* g, int level, const int W[3], const double* K,
+              const double* qgrid, double* egrid, int npts, const int* pts)
+{
+  const int* n = g->n[level - 1];
+  if (npts < 0) {
+    long G = (long)n[0] * n[1] * n[2];
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long m = 0; m < G; ++m) conv_point(g, level, W, K, qgrid, egrid, m);
+  } else {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < npts; ++i) conv_point(g, level, W, K, qgrid, egrid, pts[i]);
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Interpolation (eqs. uoneplus_interpolation_with_index_set,
+ * analytic_uoneplus_position_grad, analytic_uoneplus_charge_grad).
+ * ---------------------------------------------------------------------- */
+int orc_interpolate(const orc_geom* g, int level, int n, const double* pos,
+                    const double* q, const double* egrid, double* phi, double* F)
+{
+  const int p = g->p;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int i = 0; i < n; ++i) {
+    axis_basis bx, by, bz;
+    if (basis_axis(g, level, 0, pos[3 * i + 0], &bx) ||
+        basis_axis(g, level, 1, pos[3 * i + 1], &by) ||
+        basis_axis(g, level, 2, pos[3 * i + 2], &bz)) {
+      bad = 1;
+      continue;
+    }
+    double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int c = 0; c < p; ++c)
+      for (int b = 0; b < p; ++b)
+        for (int a = 0; a < p; ++a) {
+          if (bx.idx[a] < 0 || by.idx[b] < 0 || bz.idx[c] < 0) continue;
+          double e = egrid[flat(g, level, bx.idx[a], by.idx[b], bz.idx[c])];
+          v += e * bx.w[a] * by.w[b] * bz.w[c];
+          gx += e * bx.dw[a] * by.w[b] * bz.w[c];
+          gy += e * bx.w[a] * by.dw[b] * bz.w[c];
+          gz += e * bx.w[a] * by.w[b] * bz.dw[c];
+        }
+    if (phi) phi[i] += v;
+    if (F) {
+      F[3 * i + 0] -= q[i] * gx;
+      F[3 * i + 1] -= q[i] * gy;
+      F[3 * i + 2] -= q[i] * gz;
+    }
+  }
+  return bad ? -1 : 0;
+}
+
+/* For L = sum_i v_i . F_i with F_i = -q_i sum_m psi_m grad phi_m(r_i) and
+ * psi = K q~ (K symmetric), the cotangents are
+ *   dL/dq_i = -sum_m [psiD_m phi_m(r_i) + psi_m v_i . grad phi_m(r_i)]
+ *   dL/dr_i = -q_i sum_m [psiD_m grad phi_m(r_i) + psi_m (Hess phi_m(r_i)) v_i]
+ * with psiD = K D and D the dipole anterpolation of q_i v_i. */
+int orc_interpolate_vjp(const orc_geom* g, int level, int n, const double* pos,
+                        const double* q, const double* v, const double* psi,
+                        const double* psiD, double* gq, double* gr)
+{
+  const int p = g->p;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int i = 0; i < n; ++i) {
+    axis_basis bx, by, bz;
+    if (basis_axis(g, level, 0, pos[3 * i + 0], &bx) ||
+        basis_axis(g, level, 1, pos[3 * i + 1], &by) ||
+        basis_axis(g, level, 2, pos[3 * i + 2], &bz)) {
+      bad = 1;
+      continue;
+    }
+    const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
+    double sq = 0.0, sr[3] = {0, 0, 0};
+    for (int c = 0; c < p; ++c)
+      for (int b = 0; b < p; ++b)
+        for (int a = 0; a < p; ++a) {
+          if (bx.idx[a] < 0 || by.idx[b] < 0 || bz.idx[c] < 0) continue;
+          long f = flat(g, level, bx.idx[a], by.idx[b], bz.idx[c]);
+          double w = bx.w[a] * by.w[b] * bz.w[c];
+          double grad[3] = {bx.dw[a] * by.w[b] * bz.w[c], bx.w[a] * by.dw[b] * bz.w[c],
+                            bx.w[a] * by.w[b] * bz.dw[c]};
+          double H[3][3];
+          H[0][0] = bx.d2w[a] * by.w[b] * bz.w[c];
+          H[1][1] = bx.w[a] * by.d2w[b] * bz.w[c];
+          H[2][2] = bx.w[a] * by.w[b] * bz.d2w[c];
+          H[0][1] = H[1][0] = bx.dw[a] * by.dw[b] * bz.w[c];
+          H[0][2] = H[2][0] = bx.dw[a] * by.w[b] * bz.dw[c];
+          H[1][2] = H[2][1] = bx.w[a] * by.dw[b] * bz.dw[c];
+          double vg = vx * grad[0] + vy * grad[1] + vz * grad[2];
+          sq += psiD[f] * w + psi[f] * vg;
+          for (int k = 0; k < 3; ++k)
+            sr[k] += psiD[f] * grad[k] +
+                     psi[f] * (H[k][0] * vx + H[k][1] * vy + H[k][2] * vz);
+        }
+    gq[i] -= sq;
+    for (int k = 0; k < 3; ++k) gr[3 * i + k] -= q[i] * sr[k];
+  }
+  return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Short-range part (eq. U_zero): pairs closer than a, minimum image on the
+ * periodic axes (valid for a <= L/2, Sec. Madelung constants).
+ * ---------------------------------------------------------------------- */
+static void min_image(const orc_geom* g, double d[3])
+{
+  for (int k = 0; k < 3; ++k)
+    if (g->periodic[k]) d[k] -= g->box[k] * round(d[k] / g->box[k]);
+}
+
+void orc_short_range(const orc_geom* g, int n, const double* pos, const double* q,
+                     int nsel, const int* sel, double* phi, double* F)
+{
+  const int cnt = nsel < 0 ? n : nsel;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int s = 0; s < cnt; ++s) {
+    int i = nsel < 0 ? s : sel[s];
+    double ph = 0.0, f[3] = {0, 0, 0};
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                     pos[3 * i + 2] - pos[3 * j + 2]};
+      min_image(g, d);
+      double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (!(r < g->a)) continue;
+      ph += q[j] * orc_kernel(0, g->L, g->a, g->p, r);
+      double c = -q[i] * q[j] * orc_k0_d1(g->a, g->p, r) / r;
+      for (int k = 0; k < 3; ++k) f[k] += c * d[k];
+    }
+    if (phi) phi[s] += ph;
+    if (F)
+      for (int k = 0; k < 3; ++k) F[3 * s + k] += f[k];
+  }
+}
+
+/* Plain cell list: cells of edge >= a; neighbour cells -1..1 per axis. */
+void orc_short_range_cells(const orc_geom* g, int n, const double* pos,
+                           const double* q, double* phi, double* F)
+{
+  int nc[3];
+  double cs[3];
+  for (int k = 0; k < 3; ++k) {
+    nc[k] = (int)floor(g->box[k] / g->a);
+    if (nc[k] < 1) nc[k] = 1;
+    cs[k] = g->box[k] / nc[k];
+  }
+  long ncell = (long)nc[0] * nc[1] * nc[2];
+  int* cell = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+  int* head = (int*)malloc(sizeof(int) * ncell);
+  int* next = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+  for (long c = 0; c < ncell; ++c) head[c] = -1;
+  for (int i = n - 1; i >= 0; --i) {
+    int ci[3];
+    for (int k = 0; k < 3; ++k) {
+      double x = pos[3 * i + k];
+      if (g->periodic[k]) x -= g->box[k] * floor(x / g->box[k]);
+      int c = (int)floor(x / cs[k]);
+      if (c < 0) c = 0;
+      if (c >= nc[k]) c = nc[k] - 1;
+      ci[k] = c;
+    }
+    long c = ((long)ci[2] * nc[1] + ci[1]) * nc[0] + ci[0];
+    cell[i] = (int)c;
+    next[i] = head[c];
+    head[c] = i;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < n; ++i) {
+    int c = cell[i];
+    int ci[3] = {c % nc[0], (c / nc[0]) % nc[1], c / (nc[0] * nc[1])};
+    /* distinct neighbour cells per axis */
+    int list[3][3], cntk[3];
+    for (int k = 0; k < 3; ++k) {
+      cntk[k] = 0;
+      for (int o = -1; o <= 1; ++o) {
+        int cc = ci[k] + o;
+        if (g->periodic[k]) cc = ((cc % nc[k]) + nc[k]) % nc[k];
+        else if (cc < 0 || cc >= nc[k]) continue;
+        int dup = 0;
+        for (int u = 0; u < cntk[k]; ++u) dup |= (list[k][u] == cc);
+        if (!dup) list[k][cntk[k]++] = cc;
+      }
+    }
+    double ph = 0.0, f[3] = {0, 0, 0};
+    for (int uz = 0; uz < cntk[2]; ++uz)
+      for (int uy = 0; uy < cntk[1]; ++uy)
+        for (int ux = 0; ux < cntk[0]; ++ux) {
+          long cc = ((long)list[2][uz] * nc[1] + list[1][uy]) * nc[0] + list[0][ux];
+          for (int j = head[cc]; j >= 0; j = next[j]) {
+            if (j == i) continue;
+            double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                           pos[3 * i + 2] - pos[3 * j + 2]};
+            min_image(g, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(r < g->a)) continue;
+            ph += q[j] * orc_kernel(0, g->L, g->a, g->p, r);
+            double cf = -q[i] * q[j] * orc_k0_d1(g->a, g->p, r) / r;
+            for (int k = 0; k < 3; ++k) f[k] += cf * d[k];
+          }
+        }
+    if (phi) phi[i] += ph;
+    if (F)
+      for (int k = 0; k < 3; ++k) F[3 * i + k] += f[k];
+  }
+  free(cell);
+  free(head);
+  free(next);
+}
+
+/* With f(r) = -k0'(r)/r the short-range force is F0_i = q_i sum_j q_j f d_ij,
+ * d_ij = r_i - r_j.  For L0 = sum_i v_i . F0_i:
+ *   dL0/dq_i = sum_j q_j f (v_i - v_j) . d_ij
+ *   dL0/dr_i = sum_j q_i q_j [ f (v_i - v_j) + (f'/r) ((v_i - v_j) . d_ij) d_ij ]
+ * with f'(r) = -k0''(r)/r + k0'(r)/r^2. */
+void orc_short_range_vjp(const orc_geom* g, int n, const double* pos,
+                         const double* q, const double* v, double* gq, double* gr)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < n; ++i) {
+    double sq = 0.0, sr[3] = {0, 0, 0};
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                     pos[3 * i + 2] - pos[3 * j + 2]};
+      min_image(g, d);
+      double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (!(r < g->a)) continue;
+      double k1 = orc_k0_d1(g->a, g->p, r), k2 = orc_k0_d2(g->a, g->p, r);
+      double f = -k1 / r;
+      double fp = -k2 / r + k1 / (r * r);
+      double dv[3] = {v[3 * i] - v[3 * j], v[3 * i + 1] - v[3 * j + 1],
+                      v[3 * i + 2] - v[3 * j + 2]};
+      double dvd = dv[0] * d[0] + dv[1] * d[1] + dv[2] * d[2];
+      sq += q[j] * f * dvd;
+      for (int k = 0; k < 3; ++k)
+        sr[k] += q[i] * q[j] * (f * dv[k] + (fp / r) * dvd * d[k]);
+    }
+    gq[i] += sq;
+    for (int k = 0; k < 3; ++k) gr[3 * i + k] += sr[k];
+  }
+}
+
+void orc_direct_coulomb(int n, const double* pos, const double* q, double* phi,
+                        double* F)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < n; ++i) {
+    double ph = 0.0, f[3] = {0, 0, 0};
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                     pos[3 * i + 2] - pos[3 * j + 2]};
+      double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      ph += q[j] / r;
+      double c = q[i] * q[j] / (r * r * r);
+      for (int k = 0; k < 3; ++k) f[k] += c * d[k];
+    }
+    if (phi) phi[i] = ph;
+    if (F)
+      for (int k = 0; k < 3; ++k) F[3 * i + k] = f[k];
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Ewald sums (Ewald 1921; slab form of Parry 1975 / Heyes, Barber and
+ * Clarke 1977).  Potential of a unit charge at the origin plus its images,
+ * tin-foil boundary; the 3-D form includes the neutralising background
+ * -pi/(alpha^2 V).  Cut-offs keep every dropped term below ~1e-19.
+ * ---------------------------------------------------------------------- */
+#define ORC_EWALD_X 6.6 /* erfc(6.6) ~ 1e-20 */
+
+double orc_ewald3d(const double box[3], double alpha, const double x[3], int reg)
+{
+  const double V = box[0] * box[1] * box[2];
+  const double rc = ORC_EWALD_X / alpha, kc = 2.0 * alpha * ORC_EWALD_X;
+  double real = 0.0;
+  int nr[3];
+  for (int k = 0; k < 3; ++k) nr[k] = (int)ceil(rc / box[k]) + 1;
+  for (int jz = -nr[2]; jz <= nr[2]; ++jz)
+    for (int jy = -nr[1]; jy <= nr[1]; ++jy)
+      for (int jx = -nr[0]; jx <= nr[0]; ++jx) {
+        double dx = x[0] + jx * box[0], dy = x[1] + jy * box[1], dz = x[2] + jz * box[2];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        if (r == 0.0) {
+          if (!reg) return INFINITY;
+          real -= 2.0 * alpha / sqrt(M_PI); /* lim erfc(ar)/r - 1/r */
+          continue;
+        }
+        if (r > rc) continue;
+        real += erfc(alpha * r) / r;
+      }
+  double recip = 0.0;
+  int nk[3];
+  for (int k = 0; k < 3; ++k) nk[k] = (int)ceil(kc * box[k] / (2.0 * M_PI)) + 1;
+  for (int kz = -nk[2]; kz <= nk[2]; ++kz)
+    for (int ky = -nk[1]; ky <= nk[1]; ++ky)
+      for (int kx = -nk[0]; kx <= nk[0]; ++kx) {
+        if (kx == 0 && ky == 0 && kz == 0) continue;
+        double gx = 2.0 * M_PI * kx / box[0], gy = 2.0 * M_PI * ky / box[1],
+               gz = 2.0 * M_PI * kz / box[2];
+        double k2 = gx * gx + gy * gy + gz * gz;
+        if (k2 > kc * kc) continue;
+        recip += exp(-k2 / (4.0 * alpha * alpha)) * cos(gx * x[0] + gy * x[1] + gz * x[2]) / k2;
+      }
+  recip *= 4.0 * M_PI / V;
+  return real + recip - M_PI / (alpha * alpha * V);
+}
+
+double orc_ewald2d(const double box[3], double alpha, const double x[3], int reg)
+{
+  const double A = box[0] * box[1];
+  const double rc = ORC_EWALD_X / alpha, kc = 2.0 * alpha * ORC_EWALD_X;
+  const double z = x[2];
+  double real = 0.0;
+  int nr[2];
+  for (int k = 0; k < 2; ++k) nr[k] = (int)ceil(rc / box[k]) + 1;
+  for (int jy = -nr[1]; jy <= nr[1]; ++jy)
+    for (int jx = -nr[0]; jx <= nr[0]; ++jx) {
+      double dx = x[0] + jx * box[0], dy = x[1] + jy * box[1];
+      double r = sqrt(dx * dx + dy * dy + z * z);
+      if (r == 0.0) {
+        if (!reg) return INFINITY;
+        real -= 2.0 * alpha / sqrt(M_PI);
+        continue;
+      }
+      if (r > rc) continue;
+      real += erfc(alpha * r) / r;
+    }
+  double recip = 0.0;
+  int nk[2];
+  for (int k = 0; k < 2; ++k) nk[k] = (int)ceil(kc * box[k] / (2.0 * M_PI)) + 1;
+  for (int ky = -nk[1]; ky <= nk[1]; ++ky)
+    for (int kx = -nk[0]; kx <= nk[0]; ++kx) {
+      if (kx == 0 && ky == 0) continue;
+      double gx = 2.0 * M_PI * kx / box[0], gy = 2.0 * M_PI * ky / box[1];
+      double k = sqrt(gx * gx + gy * gy);
+      if (k > kc) continue;
+      double t1 = 0.0, t2;
+      double u1 = k / (2.0 * alpha) + alpha * z;
+      if (k * z < 700.0) t1 = exp(k * z) * erfc(u1);
+      t2 = (-k * z < 700.0) ? exp(-k * z) * erfc(k / (2.0 * alpha) - alpha * z) : 0.0;
+      recip += cos(gx * x[0] + gy * x[1]) / k * (t1 + t2);
+    }
+  recip *= M_PI / A;
+  double k0 = -(2.0 * M_PI / A) *
+              (z * erf(alpha * z) + exp(-alpha * alpha * z * z) / (alpha * sqrt(M_PI)));
+  return real + recip + k0;
+}
+
+void orc_ewald_potentials(const double box[3], int slab, double alpha, int n,
+                          const double* pos, const double* q, double* phi)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                     pos[3 * i + 2] - pos[3 * j + 2]};
+      int reg = (j == i);
+      s += q[j] * (slab ? orc_ewald2d(box, alpha, d, reg) : orc_ewald3d(box, alpha, d, reg));
+    }
+    phi[i] = s;
+  }
+}

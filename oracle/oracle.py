@@ -1,0 +1,492 @@
+"""Plain FP64 CPU oracle of the MSM -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this module.  It shares no code with the HIP library
+``paper_2510_05961_amd``; the heavy loops live in ``msm_oracle.c`` (plain C,
+FP64, OpenMP over independent outer loops), the orchestration and the exact
+constants live here.
+
+What it computes is the MSM approximation in its level-wise form
+(Sec. "Fundamentals of the multilevel summation method"):
+
+    U      = U^0 + U^{1+}
+    U^0    = 1/2 sum_i sum_{j != i, r_ij < a} q_i q_j k_0(r_ij)
+             - 1/2 sum_i q_i^2 sum_{l >= 1} k_l(0)                (eq. U_zero)
+    U^{1+} = 1/2 sum_l (q~^l)^T K^l q~^l                 (eq. U_oneplus_grid_approx)
+    q~^l_m = sum_i q_i phi^l_m(r_i)                           (eq. grid_charge)
+
+with the grid charge of EVERY level obtained by direct anterpolation.  The
+nested scheme of eq. (u_oneplus_nested_eval) reaches exactly this value
+because B-splines nest (restriction reproduces the coarser anterpolation)
+and prolongation is the transpose of restriction.  dE/dq_i = phi_i and
+F_i = -grad_i U follow from eqs. (analytic_uoneplus_position_grad) and
+(analytic_uoneplus_charge_grad) level by level.
+
+Readings where the paper is silent (listed in the design doc):
+  * L counts grid levels l = 1..L; kernels k_0..k_L.
+  * periodic axis: N_top = max(1, floor(box/(h 2^(L-1)) + 1/2)),
+    N_1 = N_top 2^(L-1), h_l = box/N_l;
+    free axis: h_l = h 2^(l-1), grid indices -p/2+1 .. ceil(box/h_l)+p/2-1.
+  * the top level keeps every top-grid pair; on periodic axes the partial
+    kernel k_L is summed over all images with the Ewald method
+    (tin-foil boundary, neutralising background):
+        G_L(x) = psi(x) - sum_images s(|x + j|),
+        s(r)   = (1/r - gamma(r/R)/R) [r < R],  R = 2^(L-1) a.
+  * slab (x, y periodic, z free): 2-D Ewald with alpha = 3/min(Lx, Ly);
+    only non-neutral slabs depend on that convention.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+from . import constants as C
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+MAXL = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile msm_oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
+    src = os.path.join(_HERE, "msm_oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-D_DEFAULT_SOURCE", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("L", ctypes.c_int), ("M", ctypes.c_int),
+                ("a", ctypes.c_double), ("box", ctypes.c_double * 3),
+                ("periodic", ctypes.c_int * 3),
+                ("n", (ctypes.c_int * 3) * MAXL), ("lo", (ctypes.c_int * 3) * MAXL),
+                ("h", (ctypes.c_double * 3) * MAXL), ("omega", ctypes.c_double * 32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        d, i, P = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
+        G = ctypes.POINTER(_Geom)
+        for name in ("orc_gamma", "orc_gamma_d1", "orc_gamma_d2"):
+            getattr(L, name).argtypes = [i, d]
+            getattr(L, name).restype = d
+        L.orc_kernel.argtypes = [i, i, d, i, d]
+        L.orc_kernel.restype = d
+        for name in ("orc_k0_d1", "orc_k0_d2"):
+            getattr(L, name).argtypes = [d, i, d]
+            getattr(L, name).restype = d
+        for name in ("orc_bspline", "orc_bspline_d1", "orc_bspline_d2"):
+            getattr(L, name).argtypes = [i, d]
+            getattr(L, name).restype = d
+        L.orc_anterpolate.argtypes = [G, i, i, P, P, P]
+        L.orc_anterpolate.restype = i
+        L.orc_anterpolate_dipole.argtypes = [G, i, i, P, P, P, P]
+        L.orc_anterpolate_dipole.restype = i
+        L.orc_stencil.argtypes = [G, i, P, P]
+        L.orc_stencil.restype = None
+        L.orc_conv.argtypes = [G, i, P, P, P, P, i, P]
+        L.orc_conv.restype = None
+        L.orc_interpolate.argtypes = [G, i, i, P, P, P, P, P]
+        L.orc_interpolate.restype = i
+        L.orc_interpolate_vjp.argtypes = [G, i, i, P, P, P, P, P, P, P]
+        L.orc_interpolate_vjp.restype = i
+        L.orc_short_range.argtypes = [G, i, P, P, i, P, P, P]
+        L.orc_short_range.restype = None
+        L.orc_short_range_cells.argtypes = [G, i, P, P, P, P]
+        L.orc_short_range_cells.restype = None
+        L.orc_short_range_vjp.argtypes = [G, i, P, P, P, P, P]
+        L.orc_short_range_vjp.restype = None
+        L.orc_direct_coulomb.argtypes = [i, P, P, P, P]
+        L.orc_direct_coulomb.restype = None
+        for name in ("orc_ewald3d", "orc_ewald2d"):
+            getattr(L, name).argtypes = [P, d, P, i]
+            getattr(L, name).restype = d
+        L.orc_ewald_potentials.argtypes = [P, i, d, i, P, P, P]
+        L.orc_ewald_potentials.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# scalar functions (thin wrappers, used by the pins)
+# --------------------------------------------------------------------------
+def gamma(p, rho):
+    return lib().orc_gamma(p, float(rho))
+
+
+def kernel(l, L, a, p, r):
+    return lib().orc_kernel(l, L, float(a), p, float(r))
+
+
+def bspline(p, t, deriv=0):
+    f = (lib().orc_bspline, lib().orc_bspline_d1, lib().orc_bspline_d2)[deriv]
+    return f(p, float(t))
+
+
+def ewald_alpha_3d(box):
+    """Balances the real- and reciprocal-space work; the 3-D result does not
+    depend on alpha."""
+    return math.sqrt(math.pi) / (box[0] * box[1] * box[2]) ** (1.0 / 3.0)
+
+
+def ewald_alpha_slab(box):
+    """Convention fixing the constant of non-neutral slabs."""
+    return 3.0 / min(box[0], box[1])
+
+
+def ewald_psi(box, x, slab=False, alpha=None, reg=False):
+    box = _f64(box)
+    x = _f64(x)
+    if alpha is None:
+        alpha = ewald_alpha_slab(box) if slab else ewald_alpha_3d(box)
+    f = lib().orc_ewald2d if slab else lib().orc_ewald3d
+    return f(_ptr(box), float(alpha), _ptr(x), int(reg))
+
+
+def ewald_potentials(box, pos, q, slab=False, alpha=None):
+    """phi_i = sum_j q_j psi(r_i - r_j) (j = i uses the regular part)."""
+    box, pos, q = _f64(box), _f64(pos), _f64(q)
+    if alpha is None:
+        alpha = ewald_alpha_slab(box) if slab else ewald_alpha_3d(box)
+    phi = np.zeros(len(q))
+    lib().orc_ewald_potentials(_ptr(box), int(slab), float(alpha), len(q), _ptr(pos), _ptr(q),
+                               _ptr(phi))
+    return phi
+
+
+def direct_coulomb(pos, q):
+    """Exact all-pairs non-periodic Coulomb potentials and forces."""
+    pos, q = _f64(pos), _f64(q)
+    phi = np.zeros(len(q))
+    F = np.zeros((len(q), 3))
+    lib().orc_direct_coulomb(len(q), _ptr(pos), _ptr(q), _ptr(phi), _ptr(F))
+    return phi, F
+
+
+# --------------------------------------------------------------------------
+# the MSM oracle
+# --------------------------------------------------------------------------
+class OracleMSM:
+    """Level-wise FP64 MSM for one orthorhombic box.
+
+    box: 3 lengths; periodic: 3 bools (all free, all periodic, or x,y periodic
+    with z free); p: even B-spline order; h: requested level-1 spacing; a:
+    level-zero cutoff; L: number of grid levels; M: half-width of omega'
+    (default p).
+    """
+
+    def __init__(self, box, periodic, p, h, a, L, M=None):
+        self.box = [float(b) for b in box]
+        self.periodic = [bool(x) for x in periodic]
+        self.p, self.h, self.a, self.L = int(p), float(h), float(a), int(L)
+        self.M = self.p if M is None else int(M)
+        assert self.p % 2 == 0 and self.p >= 2 and 1 <= self.L <= MAXL
+        npd = sum(self.periodic)
+        assert npd in (0, 3) or self.periodic == [True, True, False], "unsupported periodicity"
+        for k in range(3):
+            if self.periodic[k]:
+                assert self.a <= self.box[k] / 2 + 1e-12, "cutoff exceeds half the box"
+        self.omega_exact = C.omega_prime(self.p, self.M)
+        self.omega = [float(w) for w in self.omega_exact]
+        self.levels = []  # per level: (n[3], lo[3], h[3])
+        for l in range(1, self.L + 1):
+            n, lo, hl = [], [], []
+            for k in range(3):
+                if self.periodic[k]:
+                    ntop = max(1, int(math.floor(self.box[k] / (self.h * 2 ** (self.L - 1)) + 0.5)))
+                    nk = ntop * 2 ** (self.L - 1) // 2 ** (l - 1)
+                    n.append(nk)
+                    lo.append(0)
+                    hl.append(self.box[k] / nk)
+                else:
+                    hk = self.h * 2 ** (l - 1)
+                    lo_k = -self.p // 2 + 1
+                    hi_k = int(math.ceil(self.box[k] / hk - 1e-9)) + self.p // 2 - 1
+                    n.append(hi_k - lo_k + 1)
+                    lo.append(lo_k)
+                    hl.append(hk)
+            self.levels.append((n, lo, hl))
+        g = _Geom()
+        g.p, g.L, g.M, g.a = self.p, self.L, self.M, self.a
+        for k in range(3):
+            g.box[k] = self.box[k]
+            g.periodic[k] = int(self.periodic[k])
+        for l, (n, lo, hl) in enumerate(self.levels):
+            for k in range(3):
+                g.n[l][k], g.lo[l][k], g.h[l][k] = n[k], lo[k], hl[k]
+        for j, w in enumerate(self.omega):
+            g.omega[j] = w
+        self._g = g
+        self._gp = ctypes.pointer(g)
+        self._stencils = {}
+
+    # ---------------------------------------------------------------- grids
+    def grid_shape(self, level):
+        n = self.levels[level - 1][0]
+        return (n[2], n[1], n[0])
+
+    def spacing(self, level):
+        return tuple(self.levels[level - 1][2])
+
+    def check_domain(self, pos):
+        for k in range(3):
+            if not self.periodic[k]:
+                x = pos[:, k]
+                if np.any(x < 0) or np.any(x > self.box[k]):
+                    raise ValueError("position outside the non-periodic domain")
+
+    def grid_charge(self, level, pos, q):
+        """q~^l by direct anterpolation (eq. grid_charge, Alg. anterpolation)."""
+        pos, q = _f64(pos), _f64(q)
+        out = np.zeros(self.grid_shape(level))
+        rc = lib().orc_anterpolate(self._gp, level, len(q), _ptr(pos), _ptr(q), _ptr(out))
+        if rc:
+            raise ValueError("particle outside the grid")
+        return out
+
+    def dipole_charge(self, level, pos, q, v):
+        pos, q, v = _f64(pos), _f64(q), _f64(v)
+        out = np.zeros(self.grid_shape(level))
+        rc = lib().orc_anterpolate_dipole(self._gp, level, len(q), _ptr(pos), _ptr(q), _ptr(v),
+                                          _ptr(out))
+        if rc:
+            raise ValueError("particle outside the grid")
+        return out
+
+    # ------------------------------------------------------------- stencils
+    def stencil(self, level):
+        """(W, K): K^l over |d_k| <= W_k, K[dz+Wz, dy+Wy, dx+Wx]."""
+        if level in self._stencils:
+            return self._stencils[level]
+        n, lo, hl = self.levels[level - 1]
+        if level < self.L:
+            W = []
+            for k in range(3):
+                w = int(math.floor(2 ** level * self.a / hl[k])) + self.M
+                if not self.periodic[k]:
+                    w = min(w, n[k] - 1)
+                W.append(w)
+            Wc = (ctypes.c_int * 3)(*W)
+            K = np.zeros((2 * W[2] + 1, 2 * W[1] + 1, 2 * W[0] + 1))
+            lib().orc_stencil(self._gp, level, Wc, _ptr(K))
+        else:
+            W, K = self._top_stencil()
+        self._stencils[level] = (W, K)
+        return W, K
+
+    def _G_top(self, x):
+        """Top-level kernel summed over the periodic images (see module doc)."""
+        L, a, p = self.L, self.a, self.p
+        npd = sum(self.periodic)
+        if npd == 0:
+            r = math.sqrt(x[0] ** 2 + x[1] ** 2 + x[2] ** 2)
+            return kernel(L, L, a, p, r)
+        slab = npd == 2
+        val = ewald_psi(self.box, x, slab=slab, reg=True)
+        R = 2 ** (L - 1) * a
+        nimg = [int(math.ceil((R + abs(x[k])) / self.box[k])) + 1 if self.periodic[k] else 0
+                for k in range(3)]
+        for jz in range(-nimg[2], nimg[2] + 1):
+            for jy in range(-nimg[1], nimg[1] + 1):
+                for jx in range(-nimg[0], nimg[0] + 1):
+                    d = (x[0] + jx * self.box[0], x[1] + jy * self.box[1], x[2] + jz * self.box[2])
+                    r = math.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+                    if r == 0.0:
+                        val += gamma(p, 0.0) / R
+                    elif r < R:
+                        val -= 1.0 / r - gamma(p, r / R) / R
+        return val
+
+    def _top_stencil(self):
+        """K^L over all top-grid offsets: sum_k omega'omega'omega' G(h_L o (d-k)).
+
+        Periodic axis with N points: offsets -N//2..N//2, where for even N the
+        two ends are the same residue and each carries half of its value (the
+        wrapped convolution adds them back together)."""
+        n, lo, hl = self.levels[self.L - 1]
+        M = self.M
+        W = []
+        for k in range(3):
+            W.append(n[k] // 2 if self.periodic[k] else n[k] - 1)
+        # table of G over the integer offsets that can occur
+        rng = [range(-W[k] - M, W[k] + M + 1) for k in range(3)]
+        cache = {}
+
+        def G(ix, iy, iz):
+            key = [ix, iy, iz]
+            for k in range(3):
+                if self.periodic[k]:
+                    key[k] %= n[k]
+            key = tuple(key)
+            if key not in cache:
+                cache[key] = self._G_top((key[0] * hl[0], key[1] * hl[1], key[2] * hl[2]))
+            return cache[key]
+
+        # table T over every offset d - k that occurs, then the plain sum
+        # K(d) = sum_k omega'(kx) omega'(ky) omega'(kz) T(d - k), vectorised over d
+        T = np.empty((len(rng[2]), len(rng[1]), len(rng[0])))
+        for a_, iz in enumerate(rng[2]):
+            for b_, iy in enumerate(rng[1]):
+                for c_, ix in enumerate(rng[0]):
+                    T[a_, b_, c_] = G(ix, iy, iz)
+        om = self.omega
+        K = np.zeros((2 * W[2] + 1, 2 * W[1] + 1, 2 * W[0] + 1))
+        for kz in range(-M, M + 1):
+            for ky in range(-M, M + 1):
+                for kx in range(-M, M + 1):
+                    # T index of offset (d - k) is d - k + W + M; d runs over -W..W
+                    K += om[abs(kx)] * om[abs(ky)] * om[abs(kz)] * T[
+                        M - kz:M - kz + 2 * W[2] + 1, M - ky:M - ky + 2 * W[1] + 1,
+                        M - kx:M - kx + 2 * W[0] + 1]
+        for k in range(3):
+            if self.periodic[k] and n[k] % 2 == 0 and n[k] > 1:
+                sl = [slice(None)] * 3
+                for end_ in (0, 2 * W[k]):
+                    sl[2 - k] = end_
+                    K[tuple(sl)] *= 0.5
+
+        return W, K
+
+    def level_potential(self, level, qgrid, points=None):
+        """e^l = K^l q~^l at all grid points (or the listed flat indices)."""
+        W, K = self.stencil(level)
+        qgrid = _f64(qgrid)
+        out = np.zeros(self.grid_shape(level))
+        Wc = (ctypes.c_int * 3)(*W)
+        if points is None:
+            lib().orc_conv(self._gp, level, Wc, _ptr(K), _ptr(qgrid), _ptr(out), -1, None)
+        else:
+            pts = np.ascontiguousarray(points, dtype=np.int32)
+            lib().orc_conv(self._gp, level, Wc, _ptr(K), _ptr(qgrid), _ptr(out), len(pts),
+                           _ptr(pts))
+        return out
+
+    def self_constant(self):
+        """sum_{l=1..L} k_l(0) (eq. U_zero, second term)."""
+        return sum(kernel(l, self.L, self.a, self.p, 0.0) for l in range(1, self.L + 1))
+
+    def support_points(self, level, pos):
+        """Flat indices of the grid points whose basis is non-zero at pos."""
+        n, lo, hl = self.levels[level - 1]
+        p = self.p
+        pts = set()
+        for r in np.atleast_2d(pos):
+            idx = []
+            for k in range(3):
+                x = r[k]
+                if self.periodic[k]:
+                    x = x - self.box[k] * math.floor(x / self.box[k])
+                base = math.floor(x / hl[k])
+                ax = []
+                for j in range(p):
+                    m = base - p // 2 + 1 + j
+                    ai = m % n[k] if self.periodic[k] else m - lo[k]
+                    if 0 <= ai < n[k]:
+                        ax.append(ai)
+                idx.append(ax)
+            for iz in idx[2]:
+                for iy in idx[1]:
+                    for ix in idx[0]:
+                        pts.add((iz * n[1] + iy) * n[0] + ix)
+        return np.array(sorted(pts), dtype=np.int32)
+
+    # --------------------------------------------------------------- energy
+    def short_range(self, pos, q, sel=None, cells=None):
+        pos, q = _f64(pos), _f64(q)
+        n = len(q)
+        if sel is None:
+            phi = np.zeros(n)
+            F = np.zeros((n, 3))
+            if cells is None:
+                cells = n > 4000
+            if cells:
+                lib().orc_short_range_cells(self._gp, n, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F))
+            else:
+                lib().orc_short_range(self._gp, n, _ptr(pos), _ptr(q), -1, None, _ptr(phi),
+                                      _ptr(F))
+        else:
+            sel = np.ascontiguousarray(sel, dtype=np.int32)
+            phi = np.zeros(len(sel))
+            F = np.zeros((len(sel), 3))
+            lib().orc_short_range(self._gp, n, _ptr(pos), _ptr(q), len(sel), _ptr(sel), _ptr(phi),
+                                  _ptr(F))
+        return phi, F
+
+    def compute(self, pos, q):
+        """Energy, per-particle potential phi_i = dE/dq_i and forces."""
+        pos, q = _f64(pos), _f64(q)
+        self.check_domain(pos)
+        n = len(q)
+        phi0, F0 = self.short_range(pos, q)
+        phi1 = np.zeros(n)
+        F1 = np.zeros((n, 3))
+        grids = []
+        for l in range(1, self.L + 1):
+            qg = self.grid_charge(l, pos, q)
+            eg = self.level_potential(l, qg)
+            lib().orc_interpolate(self._gp, l, n, _ptr(pos), _ptr(q), _ptr(eg), _ptr(phi1),
+                                  _ptr(F1))
+            grids.append((qg, eg))
+        phi = phi0 + phi1 - q * self.self_constant()
+        F = F0 + F1
+        E = 0.5 * float(np.dot(q, phi))
+        return {"E": E, "phi": phi, "F": F, "phi0": phi0, "F0": F0, "phi1": phi1, "F1": F1,
+                "grids": grids}
+
+    def sampled(self, pos, q, sel):
+        """phi_i and F_i for the listed particles only (full-size parity)."""
+        pos, q = _f64(pos), _f64(q)
+        self.check_domain(pos)
+        sel = np.asarray(sel, dtype=np.int64)
+        phi0, F0 = self.short_range(pos, q, sel=sel)
+        ps, qs = _f64(pos[sel]), _f64(q[sel])
+        phi1 = np.zeros(len(sel))
+        F1 = np.zeros((len(sel), 3))
+        for l in range(1, self.L + 1):
+            qg = self.grid_charge(l, pos, q)
+            pts = self.support_points(l, ps)
+            eg = self.level_potential(l, qg, points=pts)
+            lib().orc_interpolate(self._gp, l, len(sel), _ptr(ps), _ptr(qs), _ptr(eg), _ptr(phi1),
+                                  _ptr(F1))
+        phi = phi0 + phi1 - qs * self.self_constant()
+        return phi, F0 + F1
+
+    def backward(self, pos, q, gE, v):
+        """Cotangents (dL/dq, dL/dr) of L = gE * E + sum_i v_i . F_i."""
+        pos, q, v = _f64(pos), _f64(q), _f64(v)
+        res = self.compute(pos, q)
+        n = len(q)
+        gq = gE * res["phi"].copy()
+        gr = -gE * res["F"].copy()
+        sq = np.zeros(n)
+        sr = np.zeros((n, 3))
+        lib().orc_short_range_vjp(self._gp, n, _ptr(pos), _ptr(q), _ptr(v), _ptr(sq), _ptr(sr))
+        for l in range(1, self.L + 1):
+            psi = res["grids"][l - 1][1]
+            D = self.dipole_charge(l, pos, q, v)
+            psiD = self.level_potential(l, D)
+            lib().orc_interpolate_vjp(self._gp, l, n, _ptr(pos), _ptr(q), _ptr(v), _ptr(psi),
+                                      _ptr(psiD), _ptr(sq), _ptr(sr))
+        return gq + sq, gr + sr
