@@ -1,0 +1,174 @@
+/*
+ * msm.h -- C ABI of libmsm: multilevel summation method (MSM) electrostatics
+ * with B-spline interpolation (arXiv 2510.05961) on AMD Instinct MI355X.
+ *
+ * What is computed (Sec. "Fundamentals of the multilevel summation method"):
+ *
+ *   U = 1/2 sum_i sum_{j != i} q_i q_j k(r_ij),   k(r) = 1/r      (eq. generic_pair_potential_sum)
+ *
+ * approximated by splitting k into partial kernels k_0..k_L (eq. kernel_splitting,
+ * eq. coulomb_splitting_with_softener), summing k_0 directly over a cell list
+ * (eq. U_zero) and interpolating k_1..k_L from grids of spacing h_l = 2^(l-1) h
+ * (eqs. kernel_interpolation, grid_charge, u_oneplus_nested_eval,
+ * uoneplus_interpolation).  Outputs: the energy U (FP64), the forces
+ * F_i = -dU/dr_i (eq. analytic_uoneplus_position_grad) and the charge gradient
+ * dU/dq_i (eq. analytic_uoneplus_charge_grad).  No units are assumed (Sec. Units).
+ *
+ * Conventions for every entry point:
+ *  - Device pointers are HIP device memory owned by the caller, contiguous,
+ *    in the plan's precision (float for MSM_FP32, double for MSM_FP64), except
+ *    energies, which are always double.  Positions are [n][3] row-major,
+ *    charges [n], forces [n][3], dE/dq [n].
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it; the hot-path calls neither allocate nor synchronise.
+ *  - Errors found on the host are returned synchronously; errors that depend on
+ *    the data (non-finite input, a position outside a non-periodic box) set a
+ *    sticky device flag that msm_plan_status reports; the outputs of such a
+ *    call are then undefined (but every kernel stays within its buffers).
+ *  - A plan may be used from one stream at a time; concurrent calls on one
+ *    plan race on its internal grids.
+ *  - No C++ exception crosses this boundary.
+ */
+#ifndef LIBMSM_H
+#define LIBMSM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct msm_plan_s* msm_plan;
+
+typedef enum {
+  MSM_OK = 0,
+  MSM_ERR_INVALID_ARG = 1,       /* bad parameter, NULL pointer, wrong plan kind */
+  MSM_ERR_UNSUPPORTED = 2,       /* odd/unsupported order, periodicity other than none/xyz/xy */
+  MSM_ERR_CUTOFF_TOO_LARGE = 3,  /* a > box/2 on a periodic axis (minimum image) */
+  MSM_ERR_GRID = 4,              /* grid or stencil too large for the plan limits */
+  MSM_ERR_OUT_OF_DOMAIN = 5,     /* device flag: coordinate outside [0, box] on a free axis */
+  MSM_ERR_NONFINITE = 6,         /* device flag: NaN/Inf position or charge */
+  MSM_ERR_CAPACITY = 7,          /* n > max_n */
+  MSM_ERR_HIP = 8,               /* a HIP runtime call failed */
+  MSM_ERR_OOM = 9,               /* device allocation failed */
+  MSM_ERR_NO_DEVICE = 10         /* plan was created host-only */
+} msm_status;
+
+enum { MSM_FP32 = 0, MSM_FP64 = 1 };
+
+/*
+ * msm_plan_create -- set up the MSM for one orthorhombic box (Sec. "High-level
+ * interface": cell, pbc, level_one_spacings, level_zero_cutoff, p).
+ *   box[3]          host, box edge lengths (> 0).
+ *   periodic_mask   bit k set = axis k periodic; allowed: 0, 7, 3 (x,y periodic).
+ *   order           B-spline order p (Sec. "B-spline interpolation"): 4, 6 or 8.
+ *   h               requested level-1 spacing.  Free axes use h exactly; a
+ *                   periodic axis uses box/N_1 with N_1 = N_top 2^(L-1),
+ *                   N_top = max(1, floor(box/(h 2^(L-1)) + 1/2)).
+ *   cutoff_a        level-zero cutoff a (r_cut^(0) of eq. kernel_splitting).
+ *   levels          number of grid levels L >= 1 (kernels k_0..k_L).
+ *   precision       MSM_FP32 or MSM_FP64 for particle and grid arithmetic;
+ *                   stencils are built in FP64 and the energy is summed in FP64.
+ *   max_n           largest particle count a call may pass.
+ *   quasi_degree_M  half-width M of the quasi-interpolation sequence omega'
+ *                   (eq. kernel_stencil_by_conv_with_universal_coeff); -1 = p.
+ * On success *out owns device memory for stencils, grids and cell lists.
+ */
+msm_status msm_plan_create(msm_plan* out, const double box[3], unsigned periodic_mask, int order,
+                           double h, double cutoff_a, int levels, int precision, int max_n,
+                           int quasi_degree_M);
+
+/* Same as msm_plan_create but touches no GPU: only the host-side plan
+ * (geometry, softener, omega', J, stencils) is built, for inspection with
+ * msm_plan_describe / msm_plan_get_stencil.  Compute calls return
+ * MSM_ERR_NO_DEVICE. */
+msm_status msm_plan_create_host(msm_plan* out, const double box[3], unsigned periodic_mask,
+                                int order, double h, double cutoff_a, int levels, int precision,
+                                int max_n, int quasi_degree_M);
+
+/* Frees the plan and its device memory (synchronises the device first). */
+msm_status msm_plan_destroy(msm_plan plan);
+
+/* Writes a NUL-terminated JSON description (parameters, actual spacings, grid
+ * sizes, stencil boxes, gamma/omega'/J coefficients) into json[cap]. */
+msm_status msm_plan_describe(msm_plan plan, char* json, size_t cap);
+
+/* Host copy of the FP64 stencil of grid level `level` (1..L; level L is the
+ * dense top-level kernel).  dims_off[6] receives (len_x, len_y, len_z,
+ * off_x, off_y, off_z): the stencil covers offsets d_k = off_k .. off_k+len_k-1
+ * and K is stored [len_z][len_y][len_x].  Periodic axes are folded onto the
+ * grid (each residue once); free axes are cropped to |d| < grid size.
+ * K may be NULL to query dims only; otherwise cap is its length in doubles. */
+msm_status msm_plan_get_stencil(msm_plan plan, int level, int dims_off[6], double* K,
+                                size_t cap);
+
+/* Grid sizes of level `level`: n[3] points per axis (x, y, z). */
+msm_status msm_plan_grid_dims(msm_plan plan, int level, int n[3]);
+
+/* Bytes of caller workspace that msm_energy_forces writes and msm_backward
+ * reads for a call with n particles (saved forward state). */
+size_t msm_workspace_bytes(msm_plan plan, int n);
+
+/*
+ * msm_energy_forces -- one forward evaluation on the device.
+ *   n          particle count, 0 <= n <= max_n.
+ *   pos, q     device, inputs ([n][3], [n]) in the plan's precision.  Periodic
+ *              coordinates may take any finite value (they are wrapped); free
+ *              coordinates must lie in [0, box].
+ *   ws         device workspace of msm_workspace_bytes(plan, n) bytes, or NULL
+ *              when no msm_backward call will follow.
+ *   energy     device, 1 double: U.
+ *   forces     device [n][3] or NULL: F_i = -dU/dr_i.
+ *   dEdq       device [n] or NULL: dU/dq_i (the potential phi_i at particle i).
+ */
+msm_status msm_energy_forces(msm_plan plan, int n, const void* pos, const void* q, void* ws,
+                             double* energy, void* forces, void* dEdq, void* stream);
+
+/*
+ * msm_backward -- vector-Jacobian product of the forward outputs.
+ * For the scalar L = gE * U + sum_i gF_i . F_i it writes
+ *   grad_q[i]   = dL/dq_i   = gE dU/dq_i + d(sum gF.F)/dq_i
+ *   grad_pos[i] = dL/dr_i   = -gE F_i    + d(sum gF.F)/dr_i
+ * The force part differentiates eqs. (analytic_uoneplus_position_grad) and
+ * the short-range forces once more (B-spline Hessians, k_0'').
+ *   pos, q     the same device inputs as the forward call that filled ws.
+ *   ws         the workspace that forward call wrote.
+ *   gE         device, 1 double (may be NULL = 0).
+ *   gF         device [n][3] cotangent on the forces, or NULL (= 0).
+ *   grad_pos   device [n][3] or NULL;  grad_q  device [n] or NULL.
+ */
+msm_status msm_backward(msm_plan plan, int n, const void* pos, const void* q, const void* ws,
+                        const double* gE, const void* gF, void* grad_pos, void* grad_q,
+                        void* stream);
+
+/* Synchronises `stream`, returns the sticky device error of the plan
+ * (MSM_OK, MSM_ERR_OUT_OF_DOMAIN or MSM_ERR_NONFINITE) and clears it. */
+msm_status msm_plan_status(msm_plan plan, void* stream);
+
+/* Copies the device grid of level `level` (1..L) into dst (device, grid size
+ * elements of the plan precision): which = 0 grid charge q~^l as left by the
+ * last forward call, which = 1 accumulated potential e^{l+} (eq.
+ * u_oneplus_nested_eval; e^{1+} for level 1). */
+msm_status msm_plan_get_grid(msm_plan plan, int level, int which, void* dst, void* stream);
+
+/*
+ * Batched evaluation of many independent non-periodic systems in one launch
+ * sequence (Sec. "Madelung constants", batching by vmap, done here without
+ * padding).  All systems share order, h, cutoff_a and precision; system s has
+ * its own cubic box edge boxes[s] and level count levels[s].
+ */
+msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const double* boxes,
+                                 const int* levels, int order, double h, double cutoff_a,
+                                 int precision, int max_total_n, int quasi_degree_M);
+/* offsets: device int32 [n_sys+1] CSR ranges into pos/q/forces/dEdq;
+ * energies: device double [n_sys]. */
+msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void* pos,
+                                   const void* q, double* energies, void* forces, void* dEdq,
+                                   void* stream);
+
+const char* msm_status_string(msm_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,408 @@
+// api.hip -- the C ABI of libmsm (include/msm.h): plan lifetime, the forward
+// pass a1..a9 and its orchestration on one HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "msm.h"
+#include "plan.hpp"
+
+using namespace msm;
+
+struct msm_plan_s {
+  HostPlan hp;
+  bool device = false;
+  bool batch = false;
+  int ncell = 0;
+  // device buffers (T = plan precision)
+  void* K[kMaxLevels] = {};
+  double* K64[kMaxLevels] = {};
+  int2* rowext[kMaxLevels] = {};
+  void* qg[kMaxLevels] = {};
+  void* eg[kMaxLevels] = {};
+  void* Jd = nullptr;
+  int* cell_of = nullptr;
+  int* rank = nullptr;
+  int* counts = nullptr;
+  int* start = nullptr;
+  int* perm = nullptr;
+  void* wrapped = nullptr;
+  void* sorted = nullptr;
+  void* phi0 = nullptr;
+  void* F0 = nullptr;
+  int* flag = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+msm_status hip_alloc(msm_plan P, void** ptr, size_t bytes) {
+  *ptr = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return MSM_ERR_OOM;
+  }
+  P->allocs.push_back(*ptr);
+  return MSM_OK;
+}
+
+template <typename T>
+GridDev<T> grid_dev(const HostPlan& hp, int level) {
+  const LevelGeom& g = hp.lev[level - 1];
+  GridDev<T> d;
+  for (int k = 0; k < 3; ++k) {
+    d.n[k] = g.n[k];
+    d.lo[k] = g.lo[k];
+    d.per[k] = hp.periodic[k];
+    d.h[k] = (T)g.h[k];
+    d.inv_h[k] = (T)(1.0 / g.h[k]);
+  }
+  return d;
+}
+
+size_t tsize(const HostPlan& hp) { return hp.precision == MSM_FP64 ? 8 : 4; }
+
+// Saved forward state inside the caller's workspace.
+struct WsLayout {
+  size_t sorted, perm, start, phi, F, e1, total;
+};
+
+WsLayout ws_layout(const msm_plan P, int n) {
+  const size_t ts = tsize(P->hp);
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  WsLayout w;
+  size_t o = 0;
+  w.sorted = o;
+  o += al(4 * ts * (size_t)std::max(n, 1));
+  w.perm = o;
+  o += al(sizeof(int) * (size_t)std::max(n, 1));
+  w.start = o;
+  o += al(sizeof(int) * (size_t)(P->ncell + 1));
+  w.phi = o;
+  o += al(ts * (size_t)std::max(n, 1));
+  w.F = o;
+  o += al(3 * ts * (size_t)std::max(n, 1));
+  w.e1 = o;
+  o += al(ts * (size_t)P->hp.lev[0].G);
+  w.total = o;
+  return w;
+}
+
+template <typename T>
+msm_status upload_plan(msm_plan P) {
+  HostPlan& hp = P->hp;
+  msm_status st;
+  for (int l = 1; l <= hp.L; ++l) {
+    LevelGeom& g = hp.lev[l - 1];
+    const size_t ks = g.K.size();
+    if ((st = hip_alloc(P, (void**)&P->K64[l - 1], ks * sizeof(double)))) return st;
+    if ((st = hip_alloc(P, &P->K[l - 1], ks * sizeof(T)))) return st;
+    std::vector<T> kt(ks);
+    for (size_t i = 0; i < ks; ++i) kt[i] = (T)g.K[i];
+    // non-zero x range of every stencil row, in the precision used
+    std::vector<int2> ext((size_t)g.len[1] * g.len[2]);
+    for (int z = 0; z < g.len[2]; ++z)
+      for (int y = 0; y < g.len[1]; ++y) {
+        int first = g.len[0], last = -1;
+        for (int x = 0; x < g.len[0]; ++x)
+          if (kt[((size_t)z * g.len[1] + y) * g.len[0] + x] != T(0)) {
+            first = std::min(first, x);
+            last = x;
+          }
+        ext[(size_t)z * g.len[1] + y] = make_int2(first, last);
+      }
+    if ((st = hip_alloc(P, (void**)&P->rowext[l - 1], ext.size() * sizeof(int2)))) return st;
+    if (hipMemcpy(P->K64[l - 1], g.K.data(), ks * sizeof(double), hipMemcpyHostToDevice) ||
+        hipMemcpy(P->K[l - 1], kt.data(), ks * sizeof(T), hipMemcpyHostToDevice) ||
+        hipMemcpy(P->rowext[l - 1], ext.data(), ext.size() * sizeof(int2), hipMemcpyHostToDevice))
+      return MSM_ERR_HIP;
+    if ((st = hip_alloc(P, &P->qg[l - 1], (size_t)g.G * sizeof(T)))) return st;
+    if ((st = hip_alloc(P, &P->eg[l - 1], (size_t)g.G * sizeof(T)))) return st;
+    const bool small = g.n[0] < 48;
+    if (conv_lds_bytes<T>(g.len, small) > 160 * 1024) return MSM_ERR_GRID;
+  }
+  T J[9] = {};
+  for (int k = 0; k <= hp.p; ++k) J[k] = (T)hp.J[k];
+  if ((st = hip_alloc(P, &P->Jd, sizeof(J)))) return st;
+  if (hipMemcpy(P->Jd, J, sizeof(J), hipMemcpyHostToDevice)) return MSM_ERR_HIP;
+  P->ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
+  const size_t nmax = (size_t)std::max(hp.max_n, 1);
+  if ((st = hip_alloc(P, (void**)&P->cell_of, nmax * sizeof(int)))) return st;
+  if ((st = hip_alloc(P, (void**)&P->rank, nmax * sizeof(int)))) return st;
+  if ((st = hip_alloc(P, (void**)&P->counts, (size_t)P->ncell * sizeof(int)))) return st;
+  if ((st = hip_alloc(P, (void**)&P->start, (size_t)(P->ncell + 1) * sizeof(int)))) return st;
+  if ((st = hip_alloc(P, (void**)&P->perm, nmax * sizeof(int)))) return st;
+  if ((st = hip_alloc(P, &P->wrapped, nmax * 4 * sizeof(T)))) return st;
+  if ((st = hip_alloc(P, &P->sorted, nmax * 4 * sizeof(T)))) return st;
+  if ((st = hip_alloc(P, &P->phi0, nmax * sizeof(T)))) return st;
+  if ((st = hip_alloc(P, &P->F0, nmax * 3 * sizeof(T)))) return st;
+  if ((st = hip_alloc(P, (void**)&P->flag, sizeof(int)))) return st;
+  if (hipMemset(P->flag, 0, sizeof(int))) return MSM_ERR_HIP;
+  if (hipDeviceSynchronize()) return MSM_ERR_HIP;
+  return MSM_OK;
+}
+
+void free_plan(msm_plan P) {
+  if (!P) return;
+  if (P->device) (void)hipDeviceSynchronize();
+  for (void* p : P->allocs) (void)hipFree(p);
+  delete P;
+}
+
+template <typename T>
+msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double* energy, T* F,
+                   T* dEdq, hipStream_t s) {
+  const HostPlan& hp = P->hp;
+  const int L = hp.L, p = hp.p;
+  // where the cell list goes: the caller's workspace if given (saved state)
+  vec4_t<T>* sorted = (vec4_t<T>*)P->sorted;
+  int* perm = P->perm;
+  int* start = P->start;
+  T* save_phi = nullptr;
+  T* save_F = nullptr;
+  T* save_e1 = nullptr;
+  if (ws) {
+    WsLayout w = ws_layout(P, n);
+    char* b = (char*)ws;
+    sorted = (vec4_t<T>*)(b + w.sorted);
+    perm = (int*)(b + w.perm);
+    start = (int*)(b + w.start);
+    save_phi = (T*)(b + w.phi);
+    save_F = (T*)(b + w.F);
+    save_e1 = (T*)(b + w.e1);
+  }
+  // clear accumulators (fill kernels rather than memsets: graph-safe)
+  launch_fill<int>(P->counts, P->ncell, 0, s);
+  launch_fill<T>((T*)P->qg[0], hp.lev[0].G, T(0), s);
+  for (int l = 1; l <= L; ++l) launch_fill<T>((T*)P->eg[l - 1], hp.lev[l - 1].G, T(0), s);
+  launch_fill<double>(energy, 1, 0.0, s);
+
+  // a1 binning
+  BinParams<T> bp;
+  for (int k = 0; k < 3; ++k) {
+    bp.box[k] = (T)hp.box[k];
+    bp.cs[k] = (T)hp.cs[k];
+    bp.nc[k] = hp.nc[k];
+    bp.per[k] = hp.periodic[k];
+  }
+  launch_binning<T>(n, pos, q, bp, P->ncell, P->cell_of, P->rank, P->counts,
+                    (vec4_t<T>*)P->wrapped, start, sorted, perm, P->flag, s);
+
+  // a2 short-range pairs
+  PairParams<T> pp;
+  for (int k = 0; k < 3; ++k) {
+    pp.box[k] = (T)hp.box[k];
+    pp.inv_box[k] = (T)(1.0 / hp.box[k]);
+    pp.per[k] = hp.periodic[k];
+    pp.nc[k] = hp.nc[k];
+  }
+  pp.a2 = (T)(hp.a * hp.a);
+  pp.inv_a2 = (T)(1.0 / (hp.a * hp.a));
+  pp.inv_a = (T)(1.0 / hp.a);
+  pp.inv_a3 = (T)(1.0 / (hp.a * hp.a * hp.a));
+  for (int k = 0; k < 8; ++k) {
+    pp.c[k] = k < p ? (T)hp.gcoef[k] : T(0);
+    pp.dc[k] = (k + 1 < p) ? (T)((k + 1) * hp.gcoef[k + 1]) : T(0);
+  }
+  launch_pair<T>(p, P->ncell, sorted, start, pp, (T*)P->phi0, (T*)P->F0, s);
+
+  // a3 anterpolation onto level 1
+  const GridDev<T> g1 = grid_dev<T>(hp, 1);
+  launch_anterp<T>(p, n, sorted, g1, (T*)P->qg[0], s);
+  // a4 restriction
+  for (int l = 1; l < L; ++l)
+    launch_restrict<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
+                       (const T*)P->qg[l - 1], (T*)P->qg[l], s);
+  // a5 stencil convolution per level, a6 dense top level
+  for (int l = 1; l <= L; ++l) {
+    const LevelGeom& g = hp.lev[l - 1];
+    ConvParams<T> cp = make_conv_params<T>(g.n, hp.periodic, g.off, g.len);
+    launch_conv<T>(cp, (const T*)P->K[l - 1], P->rowext[l - 1], (const T*)P->qg[l - 1],
+                   (T*)P->eg[l - 1], s);
+  }
+  // a7 prolongation, top down
+  for (int l = L - 1; l >= 1; --l)
+    launch_prolong<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
+                      (const T*)P->eg[l], (T*)P->eg[l - 1], s);
+  // a8 + a9 interpolation, combination, energy
+  launch_interp<T>(p, n, sorted, perm, g1, (const T*)P->eg[0], (const T*)P->phi0,
+                   (const T*)P->F0, (T)hp.self_const, dEdq, F, save_phi, save_F, energy, s);
+  if (save_e1)
+    if (hipMemcpyAsync(save_e1, P->eg[0], sizeof(T) * hp.lev[0].G, hipMemcpyDeviceToDevice, s))
+      return MSM_ERR_HIP;
+  if (hipGetLastError() != hipSuccess) return MSM_ERR_HIP;
+  return MSM_OK;
+}
+
+msm_status create_common(msm_plan* out, const double box[3], unsigned mask, int order, double h,
+                         double a, int levels, int precision, int max_n, int M, bool device) {
+  if (!out) return MSM_ERR_INVALID_ARG;
+  *out = nullptr;
+  msm_plan P = new (std::nothrow) msm_plan_s;
+  if (!P) return MSM_ERR_OOM;
+  int rc;
+  try {
+    rc = build_host_plan(P->hp, box, mask, order, h, a, levels, precision, max_n, M);
+  } catch (...) {
+    rc = MSM_ERR_OOM;
+  }
+  if (rc != MSM_OK) {
+    delete P;
+    return (msm_status)rc;
+  }
+  if (device) {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+      (void)hipGetLastError();
+      delete P;
+      return MSM_ERR_HIP;
+    }
+    P->device = true;
+    msm_status st;
+    try {
+      st = precision == MSM_FP64 ? upload_plan<double>(P) : upload_plan<float>(P);
+    } catch (...) {
+      st = MSM_ERR_OOM;
+    }
+    if (st != MSM_OK) {
+      free_plan(P);
+      return st;
+    }
+  }
+  *out = P;
+  return MSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+msm_status msm_plan_create(msm_plan* out, const double box[3], unsigned periodic_mask, int order,
+                           double h, double cutoff_a, int levels, int precision, int max_n,
+                           int quasi_degree_M) {
+  return create_common(out, box, periodic_mask, order, h, cutoff_a, levels, precision, max_n,
+                       quasi_degree_M, true);
+}
+
+msm_status msm_plan_create_host(msm_plan* out, const double box[3], unsigned periodic_mask,
+                                int order, double h, double cutoff_a, int levels, int precision,
+                                int max_n, int quasi_degree_M) {
+  return create_common(out, box, periodic_mask, order, h, cutoff_a, levels, precision, max_n,
+                       quasi_degree_M, false);
+}
+
+msm_status msm_plan_destroy(msm_plan plan) {
+  if (!plan) return MSM_ERR_INVALID_ARG;
+  free_plan(plan);
+  return MSM_OK;
+}
+
+msm_status msm_plan_describe(msm_plan plan, char* json, size_t cap) {
+  if (!plan || !json || cap == 0) return MSM_ERR_INVALID_ARG;
+  std::string s;
+  try {
+    s = describe_json(plan->hp);
+  } catch (...) {
+    return MSM_ERR_OOM;
+  }
+  if (s.size() + 1 > cap) {
+    json[0] = 0;
+    return MSM_ERR_INVALID_ARG;
+  }
+  std::memcpy(json, s.c_str(), s.size() + 1);
+  return MSM_OK;
+}
+
+msm_status msm_plan_get_stencil(msm_plan plan, int level, int dims_off[6], double* K, size_t cap) {
+  if (!plan || !dims_off || level < 1 || level > plan->hp.L || plan->batch)
+    return MSM_ERR_INVALID_ARG;
+  const LevelGeom& g = plan->hp.lev[level - 1];
+  for (int k = 0; k < 3; ++k) {
+    dims_off[k] = g.len[k];
+    dims_off[3 + k] = g.off[k];
+  }
+  if (K) {
+    if (cap < g.K.size()) return MSM_ERR_INVALID_ARG;
+    std::memcpy(K, g.K.data(), g.K.size() * sizeof(double));
+  }
+  return MSM_OK;
+}
+
+msm_status msm_plan_grid_dims(msm_plan plan, int level, int n[3]) {
+  if (!plan || !n || level < 1 || level > plan->hp.L || plan->batch) return MSM_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k) n[k] = plan->hp.lev[level - 1].n[k];
+  return MSM_OK;
+}
+
+size_t msm_workspace_bytes(msm_plan plan, int n) {
+  if (!plan || n < 0 || plan->batch) return 0;
+  return ws_layout(plan, n).total;
+}
+
+msm_status msm_energy_forces(msm_plan plan, int n, const void* pos, const void* q, void* ws,
+                             double* energy, void* forces, void* dEdq, void* stream) {
+  if (!plan || plan->batch) return MSM_ERR_INVALID_ARG;
+  if (!plan->device) return MSM_ERR_NO_DEVICE;
+  if (n < 0 || !energy || (n > 0 && (!pos || !q))) return MSM_ERR_INVALID_ARG;
+  if (n > plan->hp.max_n) return MSM_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->hp.precision == MSM_FP64)
+    return forward<double>(plan, n, (const double*)pos, (const double*)q, ws, energy,
+                           (double*)forces, (double*)dEdq, s);
+  return forward<float>(plan, n, (const float*)pos, (const float*)q, ws, energy, (float*)forces,
+                        (float*)dEdq, s);
+}
+
+msm_status msm_plan_status(msm_plan plan, void* stream) {
+  if (!plan) return MSM_ERR_INVALID_ARG;
+  if (!plan->device) return MSM_ERR_NO_DEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  int f = 0;
+  if (hipStreamSynchronize(s) != hipSuccess) return MSM_ERR_HIP;
+  if (hipMemcpy(&f, plan->flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return MSM_ERR_HIP;
+  if (f) {
+    if (hipMemset(plan->flag, 0, sizeof(int)) != hipSuccess) return MSM_ERR_HIP;
+    if (hipDeviceSynchronize() != hipSuccess) return MSM_ERR_HIP;
+  }
+  if (f & kFlagNonfinite) return MSM_ERR_NONFINITE;
+  if (f & kFlagDomain) return MSM_ERR_OUT_OF_DOMAIN;
+  return MSM_OK;
+}
+
+msm_status msm_plan_get_grid(msm_plan plan, int level, int which, void* dst, void* stream) {
+  if (!plan || plan->batch || !dst || level < 1 || level > plan->hp.L || (which != 0 && which != 1))
+    return MSM_ERR_INVALID_ARG;
+  if (!plan->device) return MSM_ERR_NO_DEVICE;
+  const void* src = which == 0 ? plan->qg[level - 1] : plan->eg[level - 1];
+  if (hipMemcpyAsync(dst, src, tsize(plan->hp) * plan->hp.lev[level - 1].G,
+                     hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess)
+    return MSM_ERR_HIP;
+  return MSM_OK;
+}
+
+const char* msm_status_string(msm_status st) {
+  switch (st) {
+    case MSM_OK: return "ok";
+    case MSM_ERR_INVALID_ARG: return "invalid argument";
+    case MSM_ERR_UNSUPPORTED: return "unsupported order or periodicity";
+    case MSM_ERR_CUTOFF_TOO_LARGE: return "cutoff exceeds half of a periodic box edge";
+    case MSM_ERR_GRID: return "grid or stencil exceeds the plan limits";
+    case MSM_ERR_OUT_OF_DOMAIN: return "position outside the non-periodic box";
+    case MSM_ERR_NONFINITE: return "non-finite position or charge";
+    case MSM_ERR_CAPACITY: return "particle count exceeds max_n";
+    case MSM_ERR_HIP: return "HIP runtime error";
+    case MSM_ERR_OOM: return "out of device memory";
+    case MSM_ERR_NO_DEVICE: return "plan has no device state";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

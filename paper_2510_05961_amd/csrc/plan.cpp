@@ -1,0 +1,512 @@
+// plan.cpp -- host-side construction of an MSM plan in FP64.
+//
+// Geometry of the level grids, the softening polynomial, the restriction
+// taps J, the quasi-interpolation sequence omega', the per-level stencils K^l
+// and the dense top-level kernel, including the Ewald treatment of the
+// infinite-range top kernel on periodic axes.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <sstream>
+
+#include "msm.h"
+
+namespace msm {
+
+namespace {
+
+double binom(int n, int k) {
+  if (k < 0 || k > n) return 0.0;
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Centred cardinal B-spline at integer argument from the truncated-power
+// form M_p(x) = 1/(p-1)! sum_j (-1)^j C(p,j) (x-j)_+^(p-1).
+long double bspline_at(int p, long double x) {
+  long double s = 0.0L, fact = 1.0L;
+  for (int i = 2; i < p; ++i) fact *= i;
+  for (int j = 0; j <= p; ++j) {
+    long double t = x - j;
+    if (t > 0) s += ((j & 1) ? -1.0L : 1.0L) * binom(p, j) * powl(t, p - 1);
+  }
+  return s / fact;
+}
+
+}  // namespace
+
+// gamma(rho) for rho < 1 is the degree-(p-1) Taylor polynomial of s^(-1/2)
+// about s = 1 at s = rho^2 (Sec. "Splitting for Coulomb kernels").  Expanded
+// in powers of t = rho^2: c_k = sum_{j>=k} C(-1/2, j) C(j, k) (-1)^(j-k).
+void softener_coefficients(int p, double* c) {
+  std::vector<double> b(p);
+  double v = 1.0;
+  for (int j = 0; j < p; ++j) {
+    b[j] = v;  // C(-1/2, j)
+    v *= (-0.5 - j) / (j + 1.0);
+  }
+  for (int k = 0; k < p; ++k) {
+    double s = 0.0;
+    for (int j = k; j < p; ++j) s += b[j] * binom(j, k) * (((j - k) & 1) ? -1.0 : 1.0);
+    c[k] = s;
+  }
+}
+
+static double gamma_t(const double* c, int p, double rho) {
+  if (rho >= 1.0) return 1.0 / rho;
+  double t = rho * rho, s = c[p - 1];
+  for (int k = p - 2; k >= 0; --k) s = s * t + c[k];
+  return s;
+}
+
+// Partial kernels k_l, 1 <= l <= L (eq. coulomb_splitting_with_softener).
+static double split_kernel(const double* c, int p, int l, int L, double a, double r) {
+  double s0 = std::ldexp(a, l - 1);
+  if (l == L) return gamma_t(c, p, r / s0) / s0;
+  double s1 = std::ldexp(a, l);
+  if (r >= s1) return 0.0;
+  return gamma_t(c, p, r / s0) / s0 - gamma_t(c, p, r / s1) / s1;
+}
+
+// Quasi-interpolation sequence (eq. kernel_stencil_by_conv_with_universal_coeff).
+// The kernel is interpolated in both arguments, so the exact sequence has the
+// symbol 1/Bhat(theta)^2, Bhat = sum_n Phi_p(n) e^{i n theta}.  Bhat is a
+// polynomial in z = sin^2(theta/2) (cos n theta = T_n(1-2z)); omega'(z) is the
+// degree-M Taylor truncation of 1/Bhat(z)^2, and z^k expands to
+// 4^-k sum_j (-1)^j C(2k,k+j) e^{ij theta}.
+std::vector<double> quasi_sequence(int p, int M) {
+  const int half = p / 2;
+  // Chebyshev polynomials T_n(1-2z) as coefficient vectors in z
+  std::vector<std::vector<long double>> T(half);
+  T[0] = {1.0L};
+  if (half > 1) T[1] = {1.0L, -2.0L};
+  for (int n = 2; n < half; ++n) {
+    std::vector<long double> t(n + 1, 0.0L);
+    for (size_t i = 0; i < T[n - 1].size(); ++i) {
+      t[i] += 2.0L * T[n - 1][i];
+      t[i + 1] += -4.0L * T[n - 1][i];
+    }
+    for (size_t i = 0; i < T[n - 2].size(); ++i) t[i] -= T[n - 2][i];
+    T[n] = t;
+  }
+  std::vector<long double> B(half, 0.0L);
+  for (int n = 0; n < half; ++n) {
+    long double phi = bspline_at(p, (long double)n + half);
+    long double w = (n == 0) ? phi : 2.0L * phi;
+    for (size_t i = 0; i < T[n].size(); ++i) B[i] += w * T[n][i];
+  }
+  std::vector<long double> B2(M + 1, 0.0L);
+  for (int i = 0; i < half; ++i)
+    for (int j = 0; j < half; ++j)
+      if (i + j <= M) B2[i + j] += B[i] * B[j];
+  std::vector<long double> inv(M + 1, 0.0L);
+  inv[0] = 1.0L / B2[0];
+  for (int k = 1; k <= M; ++k) {
+    long double s = 0.0L;
+    for (int j = 1; j <= k; ++j) s += B2[j] * inv[k - j];
+    inv[k] = -s / B2[0];
+  }
+  std::vector<double> om(M + 1);
+  for (int j = 0; j <= M; ++j) {
+    long double s = 0.0L;
+    for (int k = j; k <= M; ++k)
+      s += inv[k] * ldexpl(1.0L, -2 * k) * ((j & 1) ? -1.0L : 1.0L) * binom(2 * k, k + j);
+    om[j] = (double)s;
+  }
+  return om;
+}
+
+// Separable convolution of a [n2][n1][n0] box with omega' along one axis.
+// Periodic: circular over the axis length; free: the output box shrinks by M
+// at both ends.
+static void conv_axis(const std::vector<double>& in, const int nin[3], int axis, bool circular,
+                      const std::vector<double>& om, std::vector<double>& out, int nout[3]) {
+  const int M = (int)om.size() - 1;
+  for (int k = 0; k < 3; ++k) nout[k] = nin[k];
+  if (!circular) nout[axis] = nin[axis] - 2 * M;
+  out.assign((size_t)nout[0] * nout[1] * nout[2], 0.0);
+  const long long stride[3] = {1, nin[0], (long long)nin[0] * nin[1]};
+  const long long ostride[3] = {1, nout[0], (long long)nout[0] * nout[1]};
+  for (int z = 0; z < nout[2]; ++z)
+    for (int y = 0; y < nout[1]; ++y)
+      for (int x = 0; x < nout[0]; ++x) {
+        int o[3] = {x, y, z};
+        double s = 0.0;
+        for (int k = -M; k <= M; ++k) {
+          int i[3] = {x, y, z};
+          if (circular) {
+            int n = nin[axis];
+            i[axis] = ((o[axis] - k) % n + n) % n;
+          } else {
+            i[axis] = o[axis] + M - k;
+          }
+          s += om[std::abs(k)] * in[i[0] * stride[0] + i[1] * stride[1] + i[2] * stride[2]];
+        }
+        out[x * ostride[0] + y * ostride[1] + z * ostride[2]] = s;
+      }
+}
+
+// Unfolded K^1 on |d_k| <= W_k = R_k + M, R_k = ceil(2a/h_k) - 1 (k_1 vanishes
+// for r >= 2a).
+void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::vector<double>& K,
+                    const double* gcoef) {
+  int R[3], ns[3];
+  for (int k = 0; k < 3; ++k) {
+    R[k] = (int)std::ceil(2.0 * a / h[k] - 1e-12) - 1;
+    if (R[k] < 0) R[k] = 0;
+    W[k] = R[k] + M;
+    ns[k] = 2 * (R[k] + 2 * M) + 1;  // samples padded by M for the free-axis passes
+  }
+  std::vector<double> s((size_t)ns[0] * ns[1] * ns[2], 0.0);
+  for (int z = 0; z < ns[2]; ++z)
+    for (int y = 0; y < ns[1]; ++y)
+      for (int x = 0; x < ns[0]; ++x) {
+        double dx = (x - R[0] - 2 * M) * h[0], dy = (y - R[1] - 2 * M) * h[1],
+               dz = (z - R[2] - 2 * M) * h[2];
+        double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+        s[((size_t)z * ns[1] + y) * ns[0] + x] = split_kernel(gcoef, p, 1, 2, a, r);
+      }
+  std::vector<double> om = quasi_sequence(p, M), t1, t2;
+  int n1[3], n2[3], n3[3];
+  conv_axis(s, ns, 0, false, om, t1, n1);
+  conv_axis(t1, n1, 1, false, om, t2, n2);
+  conv_axis(t2, n2, 2, false, om, K, n3);
+}
+
+// ---------------------------------------------------------------------------
+// Ewald sums for the periodic top level.  psi is the potential of a unit
+// charge and all its periodic images with tin-foil boundary conditions (and a
+// neutralising background in 3-D).  reg: at a lattice point return the
+// regular part lim (psi - 1/r).
+// ---------------------------------------------------------------------------
+static double ewald3d(const double box[3], const double x[3]) {
+  const double V = box[0] * box[1] * box[2];
+  const double alpha = 1.25 * std::sqrt(M_PI) / std::cbrt(V);
+  const double xr = 6.7;  // erfc(6.7) < 4e-21
+  const double rc = xr / alpha, kc = 2.0 * alpha * xr;
+  double real = 0.0;
+  int nr[3], nk[3];
+  for (int k = 0; k < 3; ++k) {
+    nr[k] = (int)std::ceil((rc + std::fabs(x[k])) / box[k]) + 1;
+    nk[k] = (int)std::ceil(kc * box[k] / (2.0 * M_PI)) + 1;
+  }
+  for (int i = -nr[0]; i <= nr[0]; ++i)
+    for (int j = -nr[1]; j <= nr[1]; ++j)
+      for (int k = -nr[2]; k <= nr[2]; ++k) {
+        double d[3] = {x[0] + i * box[0], x[1] + j * box[1], x[2] + k * box[2]};
+        double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (r == 0.0)
+          real += -2.0 * alpha / std::sqrt(M_PI);
+        else if (r < rc)
+          real += std::erfc(alpha * r) / r;
+      }
+  double rec = 0.0;
+  for (int i = -nk[0]; i <= nk[0]; ++i)
+    for (int j = -nk[1]; j <= nk[1]; ++j)
+      for (int k = -nk[2]; k <= nk[2]; ++k) {
+        if (!i && !j && !k) continue;
+        double g[3] = {2 * M_PI * i / box[0], 2 * M_PI * j / box[1], 2 * M_PI * k / box[2]};
+        double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        if (g2 >= kc * kc) continue;
+        rec += std::exp(-g2 / (4 * alpha * alpha)) / g2 * std::cos(g[0] * x[0] + g[1] * x[1] + g[2] * x[2]);
+      }
+  return real + 4.0 * M_PI / V * rec - M_PI / (alpha * alpha * V);
+}
+
+// Slab, x and y periodic, z free (Parry's 2-D Ewald sum).  alpha is fixed at
+// 3/min(Lx, Ly): the constant of a non-neutral slab depends on it.
+static double ewald2d(const double box[3], const double x[3]) {
+  const double A = box[0] * box[1];
+  const double alpha = 3.0 / std::min(box[0], box[1]);
+  const double xr = 6.7, rc = xr / alpha, kc = 2.0 * alpha * xr;
+  const double z = x[2];
+  double real = 0.0;
+  int nr[2], nk[2];
+  for (int k = 0; k < 2; ++k) {
+    nr[k] = (int)std::ceil((rc + std::fabs(x[k])) / box[k]) + 1;
+    nk[k] = (int)std::ceil(kc * box[k] / (2.0 * M_PI)) + 1;
+  }
+  for (int i = -nr[0]; i <= nr[0]; ++i)
+    for (int j = -nr[1]; j <= nr[1]; ++j) {
+      double d[3] = {x[0] + i * box[0], x[1] + j * box[1], z};
+      double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (r == 0.0)
+        real += -2.0 * alpha / std::sqrt(M_PI);
+      else if (r < rc)
+        real += std::erfc(alpha * r) / r;
+    }
+  double rec = 0.0;
+  for (int i = -nk[0]; i <= nk[0]; ++i)
+    for (int j = -nk[1]; j <= nk[1]; ++j) {
+      if (!i && !j) continue;
+      double g0 = 2 * M_PI * i / box[0], g1 = 2 * M_PI * j / box[1];
+      double g = std::sqrt(g0 * g0 + g1 * g1);
+      if (g >= kc) continue;
+      double u = g / (2 * alpha);
+      double t = 0.0;
+      if (g * z < 700.0) t += std::exp(g * z) * std::erfc(u + alpha * z);
+      if (-g * z < 700.0) t += std::exp(-g * z) * std::erfc(u - alpha * z);
+      rec += std::cos(g0 * x[0] + g1 * x[1]) / g * t;
+    }
+  double k0 = -(2.0 * M_PI / A) *
+              (z * std::erf(alpha * z) + std::exp(-alpha * alpha * z * z) / (alpha * std::sqrt(M_PI)));
+  return real + M_PI / A * rec + k0;
+}
+
+// Top-level kernel summed over periodic images: G(x) = psi(x) - sum_j s(|x+j|)
+// with s(r) = 1/r - gamma(r/R)/R for r < R (zero beyond), R = 2^(L-1) a, i.e.
+// the periodic sum of k_L(r) = gamma(r/R)/R with the 1/r tail Ewald-summed.
+static double periodic_top_G(const HostPlan& P, const double x[3]) {
+  const double R = std::ldexp(P.a, P.L - 1);
+  bool slab = !P.periodic[2];
+  double val = slab ? ewald2d(P.box, x) : ewald3d(P.box, x);
+  int ni[3];
+  for (int k = 0; k < 3; ++k)
+    ni[k] = P.periodic[k] ? (int)std::ceil((R + std::fabs(x[k])) / P.box[k]) + 1 : 0;
+  for (int i = -ni[0]; i <= ni[0]; ++i)
+    for (int j = -ni[1]; j <= ni[1]; ++j)
+      for (int k = -ni[2]; k <= ni[2]; ++k) {
+        double d[3] = {x[0] + i * P.box[0], x[1] + j * P.box[1], x[2] + k * P.box[2]};
+        double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (r == 0.0)
+          val += P.gamma0 / R;  // regular part: psi - 1/r already taken, + gamma(0)/R
+        else if (r < R)
+          val -= 1.0 / r - gamma_t(P.gcoef, P.p, r / R) / R;
+      }
+  return val;
+}
+
+// Dense top kernel of a free-space system: offsets |d_k| <= n_k - 1.
+void free_top_kernel(int p, int M, double a, int L, const double hL[3], const int n[3],
+                     const std::vector<double>& omega, const double* gcoef,
+                     std::vector<double>& K) {
+  int ns[3];
+  for (int k = 0; k < 3; ++k) ns[k] = 2 * (n[k] - 1 + M) + 1;
+  std::vector<double> s((size_t)ns[0] * ns[1] * ns[2]);
+  const double R = std::ldexp(a, L - 1);
+  for (int z = 0; z < ns[2]; ++z)
+    for (int y = 0; y < ns[1]; ++y)
+      for (int x = 0; x < ns[0]; ++x) {
+        double dx = (x - (ns[0] - 1) / 2) * hL[0], dy = (y - (ns[1] - 1) / 2) * hL[1],
+               dz = (z - (ns[2] - 1) / 2) * hL[2];
+        double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+        s[((size_t)z * ns[1] + y) * ns[0] + x] = gamma_t(gcoef, p, r / R) / R;
+      }
+  std::vector<double> t1, t2;
+  int n1[3], n2[3], n3[3];
+  conv_axis(s, ns, 0, false, omega, t1, n1);
+  conv_axis(t1, n1, 1, false, omega, t2, n2);
+  conv_axis(t2, n2, 2, false, omega, K, n3);
+}
+
+int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, int order, double h,
+                    double a, int levels, int precision, int max_n, int M) {
+  if (!box || !(h > 0) || !(a > 0) || levels < 1 || levels > kMaxLevels || max_n < 0)
+    return MSM_ERR_INVALID_ARG;
+  if (precision != MSM_FP32 && precision != MSM_FP64) return MSM_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (!(box[k] > 0) || !std::isfinite(box[k])) return MSM_ERR_INVALID_ARG;
+  if (order != 4 && order != 6 && order != 8) return MSM_ERR_UNSUPPORTED;
+  if (periodic_mask != 0 && periodic_mask != 7 && periodic_mask != 3) return MSM_ERR_UNSUPPORTED;
+  if (M < 0) M = order;
+  if (M > 24) return MSM_ERR_INVALID_ARG;
+  for (int k = 0; k < 3; ++k) {
+    P.box[k] = box[k];
+    P.periodic[k] = (periodic_mask >> k) & 1;
+    if (P.periodic[k] && a > 0.5 * box[k] * (1.0 + 1e-12)) return MSM_ERR_CUTOFF_TOO_LARGE;
+  }
+  P.p = order;
+  P.L = levels;
+  P.M = M;
+  P.h_req = h;
+  P.a = a;
+  P.precision = precision;
+  P.max_n = max_n;
+  softener_coefficients(order, P.gcoef);
+  P.gamma0 = P.gcoef[0];
+  P.self_const = P.gamma0 / a;
+  P.omega = quasi_sequence(order, M);
+  for (int n = -order / 2; n <= order / 2; ++n)
+    P.J[n + order / 2] = std::ldexp(binom(order, n + order / 2), 1 - order);
+
+  // level geometry
+  for (int l = 1; l <= levels; ++l) {
+    LevelGeom& g = P.lev[l - 1];
+    g.G = 1;
+    for (int k = 0; k < 3; ++k) {
+      if (P.periodic[k]) {
+        double q = box[k] / std::ldexp(h, levels - 1);
+        long long ntop = (long long)std::floor(q + 0.5);
+        if (ntop < 1) ntop = 1;
+        long long n1 = ntop << (levels - 1);
+        if (n1 > (1 << 14)) return MSM_ERR_GRID;
+        g.n[k] = (int)(n1 >> (l - 1));
+        g.lo[k] = 0;
+        g.h[k] = box[k] / g.n[k];
+      } else {
+        double hl = std::ldexp(h, l - 1);
+        int hi = (int)std::ceil(box[k] / hl - 1e-9) + order / 2 - 1;
+        if (hi > (1 << 14)) return MSM_ERR_GRID;
+        g.lo[k] = -order / 2 + 1;
+        g.n[k] = hi - g.lo[k] + 1;
+        g.h[k] = hl;
+      }
+      g.G *= g.n[k];
+    }
+    if (g.G > (1LL << 30)) return MSM_ERR_GRID;
+  }
+
+  // level-1 stencil, unfolded
+  std::vector<double> K1;
+  level1_stencil(order, M, a, P.lev[0].h, P.W1, K1, P.gcoef);
+  const int u[3] = {2 * P.W1[0] + 1, 2 * P.W1[1] + 1, 2 * P.W1[2] + 1};
+
+  // levels 1..L-1: K^l = K^1 / 2^(l-1) (Sec. "Splitting for Coulomb kernels"),
+  // folded onto periodic axes, cropped on free axes.
+  for (int l = 1; l < levels; ++l) {
+    LevelGeom& g = P.lev[l - 1];
+    const double scale = std::ldexp(1.0, -(l - 1));
+    for (int k = 0; k < 3; ++k) {
+      const int W = P.W1[k];
+      if (P.periodic[k]) {
+        if (2 * W + 1 <= g.n[k]) {
+          g.off[k] = -W;
+          g.len[k] = 2 * W + 1;
+        } else {
+          g.off[k] = -(g.n[k] / 2);
+          g.len[k] = g.n[k];
+        }
+      } else {
+        int w = std::min(W, g.n[k] - 1);
+        g.off[k] = -w;
+        g.len[k] = 2 * w + 1;
+      }
+    }
+    g.K.assign((size_t)g.len[0] * g.len[1] * g.len[2], 0.0);
+    for (int z = 0; z < u[2]; ++z)
+      for (int y = 0; y < u[1]; ++y)
+        for (int x = 0; x < u[0]; ++x) {
+          int d[3] = {x - P.W1[0], y - P.W1[1], z - P.W1[2]};
+          int idx[3];
+          bool keep = true;
+          for (int k = 0; k < 3; ++k) {
+            int e = d[k] - g.off[k];
+            if (P.periodic[k]) {
+              e = ((e % g.n[k]) + g.n[k]) % g.n[k];
+              if (e >= g.len[k]) keep = false;  // cannot happen when folded
+            } else if (e < 0 || e >= g.len[k]) {
+              keep = false;
+            }
+            idx[k] = e;
+          }
+          if (!keep) continue;
+          g.K[((size_t)idx[2] * g.len[1] + idx[1]) * g.len[0] + idx[0]] +=
+              scale * K1[((size_t)z * u[1] + y) * u[0] + x];
+        }
+  }
+
+  // top level: dense over every top-grid pair
+  {
+    LevelGeom& g = P.lev[levels - 1];
+    const int Mq = M;
+    int next[3];
+    for (int k = 0; k < 3; ++k) {
+      if (P.periodic[k]) {
+        g.off[k] = -(g.n[k] / 2);
+        g.len[k] = g.n[k];
+        next[k] = g.n[k];  // table over residues 0..n-1
+      } else {
+        g.off[k] = -(g.n[k] - 1);
+        g.len[k] = 2 * g.n[k] - 1;
+        next[k] = 2 * (g.n[k] - 1 + Mq) + 1;  // offsets -(n-1+M)..(n-1+M)
+      }
+    }
+    std::vector<double> T((size_t)next[0] * next[1] * next[2]);
+    const bool anyp = P.periodic[0] || P.periodic[1] || P.periodic[2];
+    const double R = std::ldexp(a, levels - 1);
+    for (int z = 0; z < next[2]; ++z)
+      for (int y = 0; y < next[1]; ++y)
+        for (int x = 0; x < next[0]; ++x) {
+          int i3[3] = {x, y, z};
+          double xv[3];
+          for (int k = 0; k < 3; ++k) {
+            int d = P.periodic[k] ? i3[k] : i3[k] - (g.n[k] - 1 + Mq);
+            xv[k] = d * g.h[k];
+          }
+          double val;
+          if (anyp) {
+            val = periodic_top_G(P, xv);
+          } else {
+            double r = std::sqrt(xv[0] * xv[0] + xv[1] * xv[1] + xv[2] * xv[2]);
+            val = gamma_t(P.gcoef, P.p, r / R) / R;
+          }
+          T[((size_t)z * next[1] + y) * next[0] + x] = val;
+        }
+    std::vector<double> a1 = T, a2;
+    int na[3] = {next[0], next[1], next[2]}, nb[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      conv_axis(a1, na, ax, P.periodic[ax] != 0, P.omega, a2, nb);
+      a1.swap(a2);
+      for (int k = 0; k < 3; ++k) na[k] = nb[k];
+    }
+    // a1 now indexed by residue (periodic) or by d + (n-1) (free)
+    g.K.assign((size_t)g.len[0] * g.len[1] * g.len[2], 0.0);
+    for (int z = 0; z < g.len[2]; ++z)
+      for (int y = 0; y < g.len[1]; ++y)
+        for (int x = 0; x < g.len[0]; ++x) {
+          int i3[3] = {x, y, z}, s[3];
+          for (int k = 0; k < 3; ++k) {
+            int d = g.off[k] + i3[k];
+            s[k] = P.periodic[k] ? ((d % g.n[k]) + g.n[k]) % g.n[k] : d + (g.n[k] - 1);
+          }
+          g.K[((size_t)z * g.len[1] + y) * g.len[0] + x] =
+              a1[((size_t)s[2] * na[1] + s[1]) * na[0] + s[0]];
+        }
+  }
+
+  // cell list
+  for (int k = 0; k < 3; ++k) {
+    int n = (int)std::floor(box[k] / a);
+    if (n < 1) n = 1;
+    if (n > 1024) n = 1024;
+    P.nc[k] = n;
+    P.cs[k] = box[k] / n;
+  }
+  return MSM_OK;
+}
+
+std::string describe_json(const HostPlan& P) {
+  std::ostringstream o;
+  o.precision(17);
+  o << "{\"box\":[" << P.box[0] << "," << P.box[1] << "," << P.box[2] << "],";
+  o << "\"periodic\":[" << P.periodic[0] << "," << P.periodic[1] << "," << P.periodic[2] << "],";
+  o << "\"order\":" << P.p << ",\"levels\":" << P.L << ",\"M\":" << P.M << ",\"h\":" << P.h_req
+    << ",\"cutoff\":" << P.a << ",\"precision\":\"" << (P.precision ? "fp64" : "fp32") << "\",";
+  o << "\"max_n\":" << P.max_n << ",\"self_const\":" << P.self_const << ",";
+  o << "\"gamma_t_coeffs\":[";
+  for (int k = 0; k < P.p; ++k) o << (k ? "," : "") << P.gcoef[k];
+  o << "],\"omega\":[";
+  for (size_t k = 0; k < P.omega.size(); ++k) o << (k ? "," : "") << P.omega[k];
+  o << "],\"J\":[";
+  for (int k = 0; k <= P.p; ++k) o << (k ? "," : "") << P.J[k];
+  o << "],\"cells\":[" << P.nc[0] << "," << P.nc[1] << "," << P.nc[2] << "],";
+  o << "\"stencil1_halfwidth\":[" << P.W1[0] << "," << P.W1[1] << "," << P.W1[2] << "],";
+  o << "\"levels_info\":[";
+  for (int l = 0; l < P.L; ++l) {
+    const LevelGeom& g = P.lev[l];
+    long long nnz = 0;
+    for (double v : g.K) nnz += (v != 0.0);
+    o << (l ? "," : "") << "{\"n\":[" << g.n[0] << "," << g.n[1] << "," << g.n[2] << "],\"lo\":["
+      << g.lo[0] << "," << g.lo[1] << "," << g.lo[2] << "],\"h\":[" << g.h[0] << "," << g.h[1]
+      << "," << g.h[2] << "],\"stencil_off\":[" << g.off[0] << "," << g.off[1] << "," << g.off[2]
+      << "],\"stencil_len\":[" << g.len[0] << "," << g.len[1] << "," << g.len[2]
+      << "],\"stencil_nnz\":" << nnz << "}";
+  }
+  o << "]}";
+  return o.str();
+}
+
+}  // namespace msm

@@ -1,0 +1,61 @@
+// plan.hpp -- host-side MSM plan: geometry, constants and FP64 stencils.
+#pragma once
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+namespace msm {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxOrder = 8;
+
+struct LevelGeom {
+  int n[3];        // grid points per axis
+  int lo[3];       // grid index of array element 0 (free axis: -p/2+1, periodic: 0)
+  double h[3];     // spacing
+  long long G;     // n0 n1 n2
+  // stencil (levels < L) or top-level kernel (level L) in FP64
+  int off[3];      // first offset per axis
+  int len[3];      // number of offsets per axis
+  std::vector<double> K;  // [len2][len1][len0]
+};
+
+struct HostPlan {
+  double box[3];
+  int periodic[3];
+  int p, L, M;
+  double h_req, a;
+  int precision;   // 0 fp32, 1 fp64
+  int max_n;
+  // softener gamma(rho) = sum_k gcoef[k] t^k, t = rho^2, rho < 1
+  double gcoef[kMaxOrder];
+  double gamma0;        // gamma(0)
+  double self_const;    // sum_{l>=1} k_l(0) = gamma(0)/a
+  std::vector<double> omega;  // omega'_0..omega'_M
+  double J[kMaxOrder + 1];    // restriction taps J_{-p/2..p/2}
+  LevelGeom lev[kMaxLevels];
+  int W1[3];            // unfolded level-1 stencil half-widths (R + M)
+  // cell list for the short-range part
+  int nc[3];
+  double cs[3];
+};
+
+// Builds geometry and every stencil; returns 0 or an msm_status code.
+int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, int order,
+                    double h, double a, int levels, int precision, int max_n, int M);
+
+std::string describe_json(const HostPlan& P);
+
+// Softener pieces used by the batch planner as well.
+void softener_coefficients(int p, double* c);
+std::vector<double> quasi_sequence(int p, int M);
+// Unfolded level-1 stencil of a free-space system with spacing h (all axes).
+void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::vector<double>& K,
+                    const double* gcoef);
+// Dense top-level kernel of a free-space system: offsets |d_k| <= n_k - 1.
+void free_top_kernel(int p, int M, double a, int L, const double hL[3], const int n[3],
+                     const std::vector<double>& omega, const double* gcoef,
+                     std::vector<double>& K);
+
+}  // namespace msm

@@ -1,0 +1,223 @@
+"""Python binding of libmsm (include/msm.h): argument marshalling only.
+
+Every step of the MSM runs in the HIP kernels of ``libmsm.so``; this module
+passes torch tensors' device pointers and the current HIP stream across the
+C ABI.  There is no CPU fallback: if the library is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsm.so")
+
+MSM_FP32, MSM_FP64 = 0, 1
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "cutoff too large", 4: "grid",
+          5: "out of domain", 6: "non-finite", 7: "capacity", 8: "HIP error", 9: "out of memory",
+          10: "no device"}
+
+_lib = None
+
+# every symbol declared in include/msm.h
+EXPORTS = ("msm_plan_create", "msm_plan_create_host", "msm_plan_destroy", "msm_plan_describe",
+           "msm_plan_get_stencil", "msm_plan_grid_dims", "msm_workspace_bytes",
+           "msm_energy_forces", "msm_backward", "msm_plan_status", "msm_plan_get_grid",
+           "msm_batch_plan_create", "msm_batch_energy_forces", "msm_status_string")
+
+
+class MSMError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__(f"{where}: libmsm status {code} ({STATUS.get(code, '?')})")
+
+
+def lib():
+    """Loads libmsm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2510_05961_amd.build`")
+        # torch ships its own libamdhip64.so.7; loading torch first makes
+        # libmsm bind to that same HIP runtime (one runtime per process).
+        import torch  # noqa: F401
+        L = ctypes.CDLL(LIB_PATH)
+        P, i, u, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint, ctypes.c_double, ctypes.c_size_t
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        L.msm_plan_create.argtypes = [pp, P, u, i, d, d, i, i, i, i]
+        L.msm_plan_create_host.argtypes = [pp, P, u, i, d, d, i, i, i, i]
+        L.msm_plan_destroy.argtypes = [P]
+        L.msm_plan_describe.argtypes = [P, ctypes.c_char_p, sz]
+        L.msm_plan_get_stencil.argtypes = [P, i, P, P, sz]
+        L.msm_plan_grid_dims.argtypes = [P, i, P]
+        L.msm_workspace_bytes.argtypes = [P, i]
+        L.msm_workspace_bytes.restype = sz
+        L.msm_energy_forces.argtypes = [P, i, P, P, P, P, P, P, P]
+        L.msm_backward.argtypes = [P, i, P, P, P, P, P, P, P, P]
+        L.msm_plan_status.argtypes = [P, P]
+        L.msm_plan_get_grid.argtypes = [P, i, i, P, P]
+        L.msm_batch_plan_create.argtypes = [pp, i, P, P, i, d, d, i, i, i]
+        L.msm_batch_energy_forces.argtypes = [P, P, P, P, P, P, P, P]
+        L.msm_status_string.argtypes = [i]
+        L.msm_status_string.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "msm_workspace_bytes" and name != "msm_status_string":
+                getattr(L, name).restype = i
+        _lib = L
+    return _lib
+
+
+def _check(code, where):
+    if code != 0:
+        raise MSMError(code, where)
+
+
+def _dbl3(v):
+    return (ctypes.c_double * 3)(*[float(x) for x in v])
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """An MSM plan for one orthorhombic box (msm_plan_create)."""
+
+    def __init__(self, box, periodic_mask, order, h, cutoff, levels, precision=MSM_FP32,
+                 max_n=1, quasi_degree=-1, device=True):
+        self._h = ctypes.c_void_p()
+        f = lib().msm_plan_create if device else lib().msm_plan_create_host
+        _check(f(ctypes.byref(self._h), _dbl3(box), int(periodic_mask), int(order), float(h),
+                 float(cutoff), int(levels), int(precision), int(max_n), int(quasi_degree)),
+               "msm_plan_create")
+        self.box = tuple(float(b) for b in box)
+        self.periodic_mask = int(periodic_mask)
+        self.order, self.levels = int(order), int(levels)
+        self.precision = int(precision)
+        self.max_n = int(max_n)
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().msm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.precision == MSM_FP64 else torch.float32
+
+    def describe(self):
+        buf = ctypes.create_string_buffer(1 << 20)
+        _check(lib().msm_plan_describe(self._h, buf, len(buf)), "msm_plan_describe")
+        return json.loads(buf.value.decode())
+
+    def stencil(self, level):
+        """(len[3], off[3], K[len_z, len_y, len_x]) as numpy FP64."""
+        import numpy as np
+        dims = (ctypes.c_int * 6)()
+        _check(lib().msm_plan_get_stencil(self._h, level, dims, None, 0), "get_stencil")
+        ln, off = list(dims[:3]), list(dims[3:])
+        K = np.zeros((ln[2], ln[1], ln[0]))
+        _check(lib().msm_plan_get_stencil(self._h, level, dims,
+                                          K.ctypes.data_as(ctypes.c_void_p), K.size),
+               "get_stencil")
+        return ln, off, K
+
+    def grid_dims(self, level):
+        n = (ctypes.c_int * 3)()
+        _check(lib().msm_plan_grid_dims(self._h, level, n), "grid_dims")
+        return tuple(n)
+
+    def workspace_bytes(self, n):
+        return int(lib().msm_workspace_bytes(self._h, int(n)))
+
+    def energy_forces(self, pos, q, ws=None, want_forces=True, want_dEdq=True, stream=None,
+                      out=None):
+        """Forward pass on the device; returns (energy[1] f64, forces|None, dEdq|None)."""
+        import torch
+        n = q.shape[0]
+        assert pos.is_cuda and q.is_cuda and pos.dtype == self.dtype and q.dtype == self.dtype
+        assert pos.is_contiguous() and q.is_contiguous() and tuple(pos.shape) == (n, 3)
+        if out is None:
+            E = torch.empty(1, dtype=torch.float64, device=pos.device)
+            F = torch.empty((n, 3), dtype=self.dtype, device=pos.device) if want_forces else None
+            dq = torch.empty(n, dtype=self.dtype, device=pos.device) if want_dEdq else None
+        else:
+            E, F, dq = out
+        _check(lib().msm_energy_forces(self._h, n, _ptr(pos), _ptr(q), _ptr(ws), _ptr(E),
+                                       _ptr(F), _ptr(dq), _stream(stream)), "msm_energy_forces")
+        return E, F, dq
+
+    def backward(self, pos, q, ws, gE=None, gF=None, stream=None):
+        import torch
+        n = q.shape[0]
+        gpos = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+        gq = torch.empty(n, dtype=self.dtype, device=pos.device)
+        _check(lib().msm_backward(self._h, n, _ptr(pos), _ptr(q), _ptr(ws), _ptr(gE), _ptr(gF),
+                                  _ptr(gpos), _ptr(gq), _stream(stream)), "msm_backward")
+        return gpos, gq
+
+    def status(self, stream=None):
+        return int(lib().msm_plan_status(self._h, _stream(stream)))
+
+    def grid(self, level, which):
+        import torch
+        n = self.grid_dims(level)
+        out = torch.empty((n[2], n[1], n[0]), dtype=self.dtype, device="cuda")
+        _check(lib().msm_plan_get_grid(self._h, level, which, _ptr(out), _stream()), "get_grid")
+        return out
+
+
+def _autograd_function():
+    import torch
+
+    class MSMFunction(torch.autograd.Function):
+        """(pos, q) -> (E, F, dEdq).  Differentiable in E and F; dEdq is
+        returned for convenience and carries no gradient."""
+
+        @staticmethod
+        def forward(ctx, pos, q, plan):
+            ws = torch.empty(plan.workspace_bytes(q.shape[0]), dtype=torch.uint8,
+                             device=pos.device)
+            E, F, dq = plan.energy_forces(pos, q, ws=ws)
+            ctx.plan = plan
+            ctx.save_for_backward(pos, q, ws)
+            ctx.mark_non_differentiable(dq)
+            return E, F, dq
+
+        @staticmethod
+        def backward(ctx, gE, gF, gdq):
+            pos, q, ws = ctx.saved_tensors
+            plan = ctx.plan
+            gE = gE.to(torch.float64).contiguous() if gE is not None else None
+            gF = gF.to(plan.dtype).contiguous() if gF is not None else None
+            gpos, gq = plan.backward(pos, q, ws, gE=gE, gF=gF)
+            return gpos, gq, None
+
+    return MSMFunction
+
+
+_MSMFunction = None
+
+
+def energy_forces(pos, q, plan):
+    """Differentiable forward: returns (E [1] float64, F [n,3], dEdq [n])."""
+    global _MSMFunction
+    if _MSMFunction is None:
+        _MSMFunction = _autograd_function()
+    return _MSMFunction.apply(pos, q, plan)

@@ -1,0 +1,160 @@
+"""GPU forward parity: the HIP path (through the C ABI) against the oracle.
+
+Element by element on the same seeded inputs (the oracle gets the inputs
+rounded to the run's precision), at sizes the oracle finishes in seconds;
+sampled outputs at the full workload sizes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_05961_amd import msm
+from paper_2510_05961_amd import workloads as WL
+
+from helpers import TOL, cast, config_case, gpu_forward, mask_of, periodic_of, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(pos, q, box, periodic, p, h, a, L, fp64, M=None, check_phi=True):
+    pos, q = cast(pos, q, fp64)
+    prec = msm.MSM_FP64 if fp64 else msm.MSM_FP32
+    print(f"case n={len(q)} box={box} per={periodic} p={p} h={h} a={a} L={L} "
+          f"{'fp64' if fp64 else 'fp32'}", flush=True)
+    plan = msm.Plan(box, mask_of(periodic), p, h, a, L, prec, max(len(q), 1),
+                    -1 if M is None else M)
+    g = gpu_forward(plan, pos, q)
+    assert plan.status() == 0
+    ref = O.OracleMSM(box, periodic, p, h, a, L, M).compute(pos, q)
+    tol = TOL["fp64" if fp64 else "fp32"]
+    eF = rel_rms(g["F"], ref["F"])
+    eE = abs(g["E"] - ref["E"]) / max(abs(ref["E"]), 1e-300)
+    ePhi = rel_rms(g["phi"], ref["phi"])
+    print(f"  E gpu={g['E']:.12g} ref={ref['E']:.12g} relE={eE:.2e} relF={eF:.2e} "
+          f"relPhi={ePhi:.2e}", flush=True)
+    assert eF <= tol["F"]
+    assert eE <= tol["E"]
+    if check_phi:
+        assert ePhi <= tol["phi"]
+    return plan, g, ref
+
+
+# --- the workloads at reduced size (same recipe, same density) --------------
+@pytest.mark.parametrize("cfg,scale", [(1, 1.0), (2, 0.03), (3, 0.014), (4, 0.04)])
+def test_config_reduced(cfg, scale):
+    _run(*config_case(cfg, scale))
+
+
+# --- small cases spanning several tiles and ragged tails ---------------------
+SMALL = [
+    # box, periodic, p, h, a, L, fp64, n
+    ((13.0, 11.0, 12.0), (0, 0, 0), 4, 1.0, 3.0, 3, True, 777),
+    ((13.0, 11.0, 12.0), (0, 0, 0), 6, 1.0, 3.0, 2, False, 777),
+    ((12.0, 12.0, 12.0), (1, 1, 1), 4, 0.75, 4.0, 4, True, 500),
+    ((12.0, 12.0, 12.0), (1, 1, 1), 6, 1.0, 4.0, 3, False, 513),
+    ((14.0, 13.0, 9.0), (1, 1, 0), 4, 1.0, 4.0, 3, True, 400),
+    ((14.0, 13.0, 9.0), (1, 1, 0), 8, 1.0, 4.0, 2, False, 401),
+    ((10.0, 10.0, 10.0), (1, 1, 1), 8, 1.25, 3.0, 3, True, 300),
+]
+
+
+@pytest.mark.parametrize("case", SMALL)
+def test_small_cases(case):
+    box, per, p, h, a, L, fp64, n = case
+    pos, q = WL.gaussian_charges(n, box, 0.5, seed=n)
+    _run(pos, q, box, per, p, h, a, L, fp64)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_degenerate_sizes(fp64):
+    box = (9.0, 9.0, 9.0)
+    for n in (0, 1, 2):
+        pos, q = WL.random_ions(max(n, 1), box, seed=3)
+        pos, q = pos[:n], q[:n]
+        if n == 1:
+            q = np.array([0.7])
+        pos, q = cast(pos, q, fp64)
+        for per in ((0, 0, 0), (1, 1, 1)):
+            plan = msm.Plan(box, mask_of(per), 4, 1.0, 3.0, 2,
+                            msm.MSM_FP64 if fp64 else msm.MSM_FP32, 4)
+            g = gpu_forward(plan, pos, q)
+            ref = O.OracleMSM(box, per, 4, 1.0, 3.0, 2).compute(pos, q)
+            assert g["E"] == pytest.approx(ref["E"], rel=1e-5, abs=1e-9)
+            if n:
+                np.testing.assert_allclose(g["F"], ref["F"], rtol=1e-4, atol=1e-7)
+
+
+def test_stage_grids_match_oracle():
+    """Per-stage parity: q~^l after restriction vs direct anterpolation, and
+    e^{l+} after prolongation vs the nested sum of the oracle's level
+    potentials (prolongation written out from its formula)."""
+    from test_oracle_pins import _prolong_axis
+    box, per, p, h, a, L = (12.0, 12.0, 9.0), (1, 1, 0), 4, 0.75, 3.0, 3
+    pos, q = WL.gaussian_charges(600, box, 0.5, seed=9)
+    pos, q = cast(pos, q, True)
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP64, 600)
+    gpu_forward(plan, pos, q)
+    o = O.OracleMSM(box, per, p, h, a, L)
+    J = {n: 2.0 ** (1 - p) * math.comb(p, n + p // 2) for n in range(-p // 2, p // 2 + 1)}
+    elev = []
+    for l in range(1, L + 1):
+        qg = o.grid_charge(l, pos, q)
+        np.testing.assert_allclose(plan.grid(l, 0).cpu().numpy(), qg, rtol=0,
+                                   atol=1e-12 * np.abs(qg).max())
+        elev.append(o.level_potential(l, qg))
+    nested = elev[L - 1]
+    assert np.allclose(plan.grid(L, 1).cpu().numpy(), nested, rtol=0,
+                       atol=1e-12 * np.abs(nested).max())
+    for l in range(L - 1, 0, -1):
+        n_f, lo_f, _ = o.levels[l - 1]
+        n_c, lo_c, _ = o.levels[l]
+        up = nested
+        for ax3, arr_ax in ((0, 2), (1, 1), (2, 0)):
+            up = _prolong_axis(up, arr_ax, J, lo_f[ax3], lo_c[ax3], n_f[ax3], per[ax3])
+        nested = elev[l - 1] + up
+        got = plan.grid(l, 1).cpu().numpy()
+        np.testing.assert_allclose(got, nested, rtol=0, atol=1e-12 * np.abs(nested).max())
+
+
+def test_error_flags():
+    import torch
+    box = (10.0, 10.0, 10.0)
+    plan = msm.Plan(box, 0, 4, 1.0, 3.0, 2, msm.MSM_FP32, 10)
+    pos = torch.rand(10, 3, device="cuda") * 10
+    q = torch.ones(10, device="cuda")
+    plan.energy_forces(pos, q)
+    assert plan.status() == 0
+    bad = pos.clone()
+    bad[3, 1] = 10.5  # outside the free box
+    plan.energy_forces(bad, q)
+    assert plan.status() == 5
+    assert plan.status() == 0  # cleared
+    nanq = q.clone()
+    nanq[2] = float("nan")
+    plan.energy_forces(pos, nanq)
+    assert plan.status() == 6
+    with pytest.raises(msm.MSMError):
+        plan.energy_forces(torch.rand(11, 3, device="cuda"), torch.ones(11, device="cuda"))
+
+
+# --- full workload sizes: sampled outputs + properties -----------------------
+@pytest.mark.parametrize("cfg", [2, 3, 4])
+def test_full_size_sampled(cfg):
+    pos, q, box, per, p, h, a, L, fp64 = config_case(cfg, 1.0)
+    pos, q = cast(pos, q, fp64)
+    print(f"full config {cfg}: n={len(q)}", flush=True)
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP32, len(q))
+    g = gpu_forward(plan, pos, q)
+    assert plan.status() == 0
+    # E = 1/2 sum q_i phi_i (FP64 sum of the GPU's own outputs)
+    e_half = 0.5 * float(np.dot(q, g["phi"]))
+    scale = 0.5 * float(np.sum(np.abs(q * g["phi"])))
+    assert abs(g["E"] - e_half) <= 1e-6 * scale
+    sel = np.random.default_rng(cfg).choice(len(q), 16 if cfg == 3 else 32, replace=False)
+    phi_r, F_r = O.OracleMSM(box, per, p, h, a, L).sampled(pos, q, sel)
+    eF = rel_rms(g["F"][sel], F_r)
+    eP = rel_rms(g["phi"][sel], phi_r)
+    print(f"  sampled relF={eF:.2e} relPhi={eP:.2e}", flush=True)
+    assert eF <= TOL["fp32"]["F"] and eP <= TOL["fp32"]["phi"]
