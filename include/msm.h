@@ -166,6 +166,19 @@ msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void
                                    const void* q, double* energies, void* forces, void* dEdq,
                                    void* stream);
 
+/*
+ * Stage timing with HIP events (benchmarks, MSM_PROFILE-style breakdowns).
+ * msm_plan_set_profiling(plan, 1) makes every later msm_energy_forces /
+ * msm_backward call record an event pair on its stream around each stage
+ * (binning, pair, anterpolation, restriction, conv per level, prolongation,
+ * interpolation, backward passes); 0 stops recording.  Recording adds no
+ * synchronisation.  msm_plan_get_profile synchronises on the recorded events,
+ * writes {"stage": {"ms": total, "launches": calls}, ...} into json[cap] and,
+ * if reset != 0, clears the totals.
+ */
+msm_status msm_plan_set_profiling(msm_plan plan, int enable);
+msm_status msm_plan_get_profile(msm_plan plan, char* json, size_t cap, int reset);
+
 const char* msm_status_string(msm_status status);
 
 #ifdef __cplusplus

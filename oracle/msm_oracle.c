@@ -17,6 +17,16 @@
 #include <omp.h>
 #endif
 
+/* Threads the OpenMP loops of this file run on. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * Softening function (Sec. "Splitting for Coulomb kernels"): gamma(rho) is
  * 1/rho for rho >= 1 and, below 1, the Taylor polynomial of s^(-1/2) about

@@ -34,6 +34,8 @@ typedef struct {
   double omega[32];       /* omega'_0 .. omega'_M (symmetric sequence)      */
 } orc_geom;
 
+int orc_num_threads(void);
+
 /* Softening function and its rho-derivatives (Sec. Coulomb splitting). */
 double orc_gamma(int p, double rho);
 double orc_gamma_d1(int p, double rho);

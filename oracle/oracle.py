@@ -84,6 +84,7 @@ def lib():
         for name in ("orc_gamma", "orc_gamma_d1", "orc_gamma_d2"):
             getattr(L, name).argtypes = [i, d]
             getattr(L, name).restype = d
+        L.orc_num_threads.restype = i
         L.orc_kernel.argtypes = [i, i, d, i, d]
         L.orc_kernel.restype = d
         for name in ("orc_k0_d1", "orc_k0_d2"):
@@ -132,6 +133,10 @@ def _f64(a):
 # --------------------------------------------------------------------------
 # scalar functions (thin wrappers, used by the pins)
 # --------------------------------------------------------------------------
+def num_threads():
+    return int(lib().orc_num_threads())
+
+
 def gamma(p, rho):
     return lib().orc_gamma(p, float(rho))
 

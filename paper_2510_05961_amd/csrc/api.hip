@@ -5,7 +5,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "kernels.hpp"
@@ -14,8 +17,63 @@
 
 using namespace msm;
 
+// Event-pair stage timer (enabled by msm_plan_set_profiling).
+struct StageProfiler {
+  bool on = false;
+  struct Pending {
+    std::string stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<double, long>> total;
+  hipEvent_t get() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  // returns an index to close with end(), or -1 when off
+  int begin(const char* stage, hipStream_t s) {
+    if (!on) return -1;
+    Pending p{stage, get(), get()};
+    if (!p.a || !p.b) return -1;
+    (void)hipEventRecord(p.a, s);
+    pending.push_back(p);
+    return (int)pending.size() - 1;
+  }
+  void end(int idx, hipStream_t s) {
+    if (idx >= 0) (void)hipEventRecord(pending[idx].b, s);
+  }
+  void collect() {
+    for (auto& p : pending) {
+      float ms = 0.f;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        auto& t = total[p.stage];
+        t.first += ms;
+        t.second += 1;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  ~StageProfiler() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 struct msm_plan_s {
   HostPlan hp;
+  StageProfiler prof;
   bool device = false;
   bool batch = false;
   int ncell = 0;
@@ -25,6 +83,10 @@ struct msm_plan_s {
   int2* rowext[kMaxLevels] = {};
   void* qg[kMaxLevels] = {};
   void* eg[kMaxLevels] = {};
+  // factored levels: FP64 k-samples, their row extents, FP64 partial grid
+  double* S[kMaxLevels] = {};
+  int2* srowext[kMaxLevels] = {};
+  double* ug[kMaxLevels] = {};
   void* Jd = nullptr;
   int* cell_of = nullptr;
   int* rank = nullptr;
@@ -125,8 +187,34 @@ msm_status upload_plan(msm_plan P) {
       return MSM_ERR_HIP;
     if ((st = hip_alloc(P, &P->qg[l - 1], (size_t)g.G * sizeof(T)))) return st;
     if ((st = hip_alloc(P, &P->eg[l - 1], (size_t)g.G * sizeof(T)))) return st;
-    const bool small = g.n[0] < 48;
-    if (conv_lds_bytes<T>(g.len, small) > 160 * 1024) return MSM_ERR_GRID;
+    const int zero3[3] = {0, 0, 0};
+    ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
+    if (conv_lds_bytes(cp, sizeof(T)) > 160 * 1024) return MSM_ERR_GRID;
+    if (g.factored) {
+      const size_t ss = g.S.size();
+      if ((st = hip_alloc(P, (void**)&P->S[l - 1], ss * sizeof(double)))) return st;
+      std::vector<int2> sext((size_t)g.s_len[1] * g.s_len[2]);
+      for (int z = 0; z < g.s_len[2]; ++z)
+        for (int y = 0; y < g.s_len[1]; ++y) {
+          int first = g.s_len[0], last = -1;
+          for (int x = 0; x < g.s_len[0]; ++x)
+            if (g.S[((size_t)z * g.s_len[1] + y) * g.s_len[0] + x] != 0.0) {
+              first = std::min(first, x);
+              last = x;
+            }
+          sext[(size_t)z * g.s_len[1] + y] = make_int2(first, last);
+        }
+      if ((st = hip_alloc(P, (void**)&P->srowext[l - 1], sext.size() * sizeof(int2)))) return st;
+      if ((st = hip_alloc(P, (void**)&P->ug[l - 1], (size_t)g.Gext * sizeof(double)))) return st;
+      if (hipMemcpy(P->S[l - 1], g.S.data(), ss * sizeof(double), hipMemcpyHostToDevice) ||
+          hipMemcpy(P->srowext[l - 1], sext.data(), sext.size() * sizeof(int2),
+                    hipMemcpyHostToDevice))
+        return MSM_ERR_HIP;
+      ConvParams cs = make_conv_params(g.n, g.next, g.shift, hp.periodic, g.s_off, g.s_len,
+                                       sizeof(T));
+      if (conv_lds_bytes(cs, sizeof(T)) > 160 * 1024) return MSM_ERR_GRID;
+      if (omega_lds_bytes(hp.M) > 160 * 1024) return MSM_ERR_GRID;
+    }
   }
   T J[9] = {};
   for (int k = 0; k <= hp.p; ++k) J[k] = (T)hp.J[k];
@@ -157,6 +245,82 @@ void free_plan(msm_plan P) {
 }
 
 template <typename T>
+PairParams<T> pair_params(const HostPlan& hp) {
+  PairParams<T> pp;
+  const int p = hp.p;
+  for (int k = 0; k < 3; ++k) {
+    pp.box[k] = (T)hp.box[k];
+    pp.inv_box[k] = (T)(1.0 / hp.box[k]);
+    pp.per[k] = hp.periodic[k];
+    pp.nc[k] = hp.nc[k];
+  }
+  const double a = hp.a;
+  pp.a2 = (T)(a * a);
+  pp.inv_a2 = (T)(1.0 / (a * a));
+  pp.inv_a = (T)(1.0 / a);
+  pp.inv_a3 = (T)(1.0 / (a * a * a));
+  pp.inv_a5 = (T)(1.0 / (a * a * a * a * a));
+  for (int k = 0; k < 8; ++k) {
+    pp.c[k] = k < p ? (T)hp.gcoef[k] : T(0);
+    pp.dc[k] = (k + 1 < p) ? (T)((k + 1) * hp.gcoef[k + 1]) : T(0);
+    pp.d2c[k] = (k + 2 < p) ? (T)((k + 2) * (k + 1) * hp.gcoef[k + 2]) : T(0);
+  }
+  return pp;
+}
+
+// Nested grid pass of eq. (u_oneplus_nested_eval): from the level-1 grid in
+// qg[0] to e^{1+} in eg[0] (restriction, per-level stencils and the dense top
+// level, prolongation).  Clears eg[*] first.
+template <typename T>
+void grid_pass(msm_plan P, hipStream_t s) {
+  const HostPlan& hp = P->hp;
+  const int L = hp.L, p = hp.p;
+  StageProfiler& pf = P->prof;
+  for (int l = 1; l <= L; ++l) launch_fill<T>((T*)P->eg[l - 1], hp.lev[l - 1].G, T(0), s);
+  int ev = pf.begin("restrict", s);
+  for (int l = 1; l < L; ++l)
+    launch_restrict<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
+                       (const T*)P->qg[l - 1], (T*)P->qg[l], s);
+  pf.end(ev, s);
+  static const char* names[kMaxLevels] = {"conv_l1", "conv_l2", "conv_l3", "conv_l4",
+                                          "conv_l5", "conv_l6", "conv_l7", "conv_l8",
+                                          "conv_l9", "conv_l10", "conv_l11", "conv_l12",
+                                          "conv_l13", "conv_l14", "conv_l15", "conv_l16"};
+  const int zero3[3] = {0, 0, 0};
+  for (int l = 1; l <= L; ++l) {
+    const LevelGeom& g = hp.lev[l - 1];
+    ev = pf.begin(l == L ? "conv_top" : names[l - 1], s);
+    if (g.factored) {
+      // K^l q = omega' * (S^l * q): FP64 sample convolution, then omega' per axis
+      ConvParams cs = make_conv_params(g.n, g.next, g.shift, hp.periodic, g.s_off, g.s_len,
+                                       sizeof(T));
+      if (cs.nsplit > 1) launch_fill<double>(P->ug[l - 1], g.Gext, 0.0, s);
+      launch_conv<T, double>(cs, P->S[l - 1], P->srowext[l - 1], (const T*)P->qg[l - 1],
+                             P->ug[l - 1], s);
+      OmegaParams op;
+      for (int k = 0; k < 3; ++k) {
+        op.n[k] = g.n[k];
+        op.next[k] = g.next[k];
+        op.per[k] = hp.periodic[k];
+      }
+      op.M = hp.M;
+      for (int k = 0; k < 25; ++k) op.omega[k] = k <= hp.M ? hp.omega[k] : 0.0;
+      launch_omega<T>(op, P->ug[l - 1], (T*)P->eg[l - 1], s);
+    } else {
+      ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
+      launch_conv<T, T>(cp, (const T*)P->K[l - 1], P->rowext[l - 1], (const T*)P->qg[l - 1],
+                        (T*)P->eg[l - 1], s);
+    }
+    pf.end(ev, s);
+  }
+  ev = pf.begin("prolong", s);
+  for (int l = L - 1; l >= 1; --l)
+    launch_prolong<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
+                      (const T*)P->eg[l], (T*)P->eg[l - 1], s);
+  pf.end(ev, s);
+}
+
+template <typename T>
 msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double* energy, T* F,
                    T* dEdq, hipStream_t s) {
   const HostPlan& hp = P->hp;
@@ -178,11 +342,13 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
     save_F = (T*)(b + w.F);
     save_e1 = (T*)(b + w.e1);
   }
+  StageProfiler& pf = P->prof;
   // clear accumulators (fill kernels rather than memsets: graph-safe)
+  int ev = pf.begin("fill", s);
   launch_fill<int>(P->counts, P->ncell, 0, s);
   launch_fill<T>((T*)P->qg[0], hp.lev[0].G, T(0), s);
-  for (int l = 1; l <= L; ++l) launch_fill<T>((T*)P->eg[l - 1], hp.lev[l - 1].G, T(0), s);
   launch_fill<double>(energy, 1, 0.0, s);
+  pf.end(ev, s);
 
   // a1 binning
   BinParams<T> bp;
@@ -192,53 +358,74 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
     bp.nc[k] = hp.nc[k];
     bp.per[k] = hp.periodic[k];
   }
+  ev = pf.begin("bin", s);
   launch_binning<T>(n, pos, q, bp, P->ncell, P->cell_of, P->rank, P->counts,
                     (vec4_t<T>*)P->wrapped, start, sorted, perm, P->flag, s);
+  pf.end(ev, s);
 
   // a2 short-range pairs
-  PairParams<T> pp;
-  for (int k = 0; k < 3; ++k) {
-    pp.box[k] = (T)hp.box[k];
-    pp.inv_box[k] = (T)(1.0 / hp.box[k]);
-    pp.per[k] = hp.periodic[k];
-    pp.nc[k] = hp.nc[k];
-  }
-  pp.a2 = (T)(hp.a * hp.a);
-  pp.inv_a2 = (T)(1.0 / (hp.a * hp.a));
-  pp.inv_a = (T)(1.0 / hp.a);
-  pp.inv_a3 = (T)(1.0 / (hp.a * hp.a * hp.a));
-  for (int k = 0; k < 8; ++k) {
-    pp.c[k] = k < p ? (T)hp.gcoef[k] : T(0);
-    pp.dc[k] = (k + 1 < p) ? (T)((k + 1) * hp.gcoef[k + 1]) : T(0);
-  }
+  const PairParams<T> pp = pair_params<T>(hp);
+  ev = pf.begin("pair", s);
   launch_pair<T>(p, P->ncell, sorted, start, pp, (T*)P->phi0, (T*)P->F0, s);
+  pf.end(ev, s);
 
   // a3 anterpolation onto level 1
   const GridDev<T> g1 = grid_dev<T>(hp, 1);
+  ev = pf.begin("anterp", s);
   launch_anterp<T>(p, n, sorted, g1, (T*)P->qg[0], s);
-  // a4 restriction
-  for (int l = 1; l < L; ++l)
-    launch_restrict<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
-                       (const T*)P->qg[l - 1], (T*)P->qg[l], s);
-  // a5 stencil convolution per level, a6 dense top level
-  for (int l = 1; l <= L; ++l) {
-    const LevelGeom& g = hp.lev[l - 1];
-    ConvParams<T> cp = make_conv_params<T>(g.n, hp.periodic, g.off, g.len);
-    launch_conv<T>(cp, (const T*)P->K[l - 1], P->rowext[l - 1], (const T*)P->qg[l - 1],
-                   (T*)P->eg[l - 1], s);
-  }
-  // a7 prolongation, top down
-  for (int l = L - 1; l >= 1; --l)
-    launch_prolong<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
-                      (const T*)P->eg[l], (T*)P->eg[l - 1], s);
+  pf.end(ev, s);
+  // a4 restriction, a5 per-level stencils, a6 top level, a7 prolongation
+  grid_pass<T>(P, s);
   // a8 + a9 interpolation, combination, energy
+  ev = pf.begin("interp", s);
   launch_interp<T>(p, n, sorted, perm, g1, (const T*)P->eg[0], (const T*)P->phi0,
                    (const T*)P->F0, (T)hp.self_const, dEdq, F, save_phi, save_F, energy, s);
+  pf.end(ev, s);
   if (save_e1)
     if (hipMemcpyAsync(save_e1, P->eg[0], sizeof(T) * hp.lev[0].G, hipMemcpyDeviceToDevice, s))
       return MSM_ERR_HIP;
   if (hipGetLastError() != hipSuccess) return MSM_ERR_HIP;
   return MSM_OK;
+}
+
+template <typename T>
+msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T* gF, T* grad_pos,
+                    T* grad_q, hipStream_t s) {
+  const HostPlan& hp = P->hp;
+  const int p = hp.p;
+  WsLayout w = ws_layout(P, n);
+  const char* b = (const char*)ws;
+  const vec4_t<T>* sorted = (const vec4_t<T>*)(b + w.sorted);
+  const int* perm = (const int*)(b + w.perm);
+  const int* start = (const int*)(b + w.start);
+  const T* save_phi = (const T*)(b + w.phi);
+  const T* save_F = (const T*)(b + w.F);
+  const T* save_e1 = (const T*)(b + w.e1);
+  StageProfiler& pf = P->prof;
+  if (!gF) {
+    int ev = pf.begin("bwd_energy_only", s);
+    launch_grad_energy_only<T>(n, perm, save_phi, save_F, gE, grad_q, grad_pos, s);
+    pf.end(ev, s);
+    return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
+  }
+  vec4_t<T>* v = (vec4_t<T>*)P->wrapped;  // cotangent in cell order
+  T* gq_sr = (T*)P->phi0;
+  T* gr_sr = (T*)P->F0;
+  int ev = pf.begin("bwd_pair", s);
+  launch_gather_v<T>(n, perm, gF, v, s);
+  launch_pair_vjp<T>(p, P->ncell, sorted, v, start, pair_params<T>(hp), gq_sr, gr_sr, s);
+  pf.end(ev, s);
+  const GridDev<T> g1 = grid_dev<T>(hp, 1);
+  ev = pf.begin("bwd_anterp", s);
+  launch_fill<T>((T*)P->qg[0], hp.lev[0].G, T(0), s);
+  launch_anterp_dipole<T>(p, n, sorted, v, g1, (T*)P->qg[0], s);
+  pf.end(ev, s);
+  grid_pass<T>(P, s);  // eg[0] = (A D)^{1+}
+  ev = pf.begin("bwd_interp", s);
+  launch_interp_vjp<T>(p, n, sorted, v, perm, g1, save_e1, (const T*)P->eg[0], save_phi, save_F,
+                       gq_sr, gr_sr, gE, grad_q, grad_pos, s);
+  pf.end(ev, s);
+  return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
 }
 
 msm_status create_common(msm_plan* out, const double box[3], unsigned mask, int order, double h,
@@ -360,6 +547,22 @@ msm_status msm_energy_forces(msm_plan plan, int n, const void* pos, const void* 
                         (float*)dEdq, s);
 }
 
+msm_status msm_backward(msm_plan plan, int n, const void* pos, const void* q, const void* ws,
+                        const double* gE, const void* gF, void* grad_pos, void* grad_q,
+                        void* stream) {
+  (void)pos;
+  (void)q;
+  if (!plan || plan->batch) return MSM_ERR_INVALID_ARG;
+  if (!plan->device) return MSM_ERR_NO_DEVICE;
+  if (n < 0 || !ws) return MSM_ERR_INVALID_ARG;
+  if (n > plan->hp.max_n) return MSM_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->hp.precision == MSM_FP64)
+    return backward<double>(plan, n, ws, gE, (const double*)gF, (double*)grad_pos,
+                            (double*)grad_q, s);
+  return backward<float>(plan, n, ws, gE, (const float*)gF, (float*)grad_pos, (float*)grad_q, s);
+}
+
 msm_status msm_plan_status(msm_plan plan, void* stream) {
   if (!plan) return MSM_ERR_INVALID_ARG;
   if (!plan->device) return MSM_ERR_NO_DEVICE;
@@ -385,6 +588,39 @@ msm_status msm_plan_get_grid(msm_plan plan, int level, int which, void* dst, voi
   if (hipMemcpyAsync(dst, src, tsize(plan->hp) * plan->hp.lev[level - 1].G,
                      hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess)
     return MSM_ERR_HIP;
+  return MSM_OK;
+}
+
+msm_status msm_plan_set_profiling(msm_plan plan, int enable) {
+  if (!plan) return MSM_ERR_INVALID_ARG;
+  if (!plan->device) return MSM_ERR_NO_DEVICE;
+  plan->prof.on = enable != 0;
+  return MSM_OK;
+}
+
+msm_status msm_plan_get_profile(msm_plan plan, char* json, size_t cap, int reset) {
+  if (!plan || !json || cap == 0) return MSM_ERR_INVALID_ARG;
+  if (!plan->device) return MSM_ERR_NO_DEVICE;
+  std::string out;
+  try {
+    plan->prof.collect();
+    std::ostringstream o;
+    o.precision(9);
+    o << "{";
+    bool first = true;
+    for (auto& kv : plan->prof.total) {
+      o << (first ? "" : ",") << "\"" << kv.first << "\":{\"ms\":" << kv.second.first
+        << ",\"launches\":" << kv.second.second << "}";
+      first = false;
+    }
+    o << "}";
+    out = o.str();
+    if (reset) plan->prof.total.clear();
+  } catch (...) {
+    return MSM_ERR_OOM;
+  }
+  if (out.size() + 1 > cap) return MSM_ERR_INVALID_ARG;
+  std::memcpy(json, out.c_str(), out.size() + 1);
   return MSM_OK;
 }
 

@@ -1,15 +1,353 @@
-// backward.hip -- placeholder until the adjoint kernels land.
-#include "msm.h"
-extern "C" msm_status msm_backward(msm_plan, int, const void*, const void*, const void*,
-                                   const double*, const void*, void*, void*, void*) {
-  return MSM_ERR_UNSUPPORTED;
+// backward.hip -- adjoint kernels of the MSM (vector-Jacobian product of the
+// forward outputs E and F with respect to charges and positions).
+//
+// For L = gE * U + sum_i v_i . F_i (v = cotangent of the forces):
+//  * dU/dq_i = phi_i and dU/dr_i = -F_i are the forward's own outputs;
+//  * the long-range force is F_i = -q_i sum_m e_m grad phi_m(r_i) with
+//    e = A q~ and A = K^1 + I(K^2 + ...)I^T symmetric (eq. u_oneplus_nested_eval),
+//    so with the dipole grid D_m = sum_i q_i v_i . grad phi_m(r_i):
+//      d(v.F)/dq_i = -sum_m [(A D)_m phi_m(r_i) + e_m v_i . grad phi_m(r_i)]
+//      d(v.F)/dr_i = -q_i sum_m [(A D)_m grad phi_m(r_i) + e_m (Hess phi_m(r_i)) v_i]
+//    i.e. one more anterpolation (of D), one more grid pass, and one
+//    interpolation with B-spline Hessians;
+//  * the short-range force F0_i = q_i sum_j q_j f(r) d_ij, f = -k0'(r)/r, gives
+//      d(v.F0)/dq_i = sum_j q_j f (v_i - v_j) . d_ij
+//      d(v.F0)/dr_i = sum_j q_i q_j [f (v_i - v_j) + (f'/r) ((v_i - v_j) . d_ij) d_ij]
+//    with f = 1/r^3 + 2 P'(t)/a^3 and f'/r = -3/r^5 + 4 P''(t)/a^5.
+#include "kernels.hpp"
+
+namespace msm {
+
+// v in sorted order (vec4 with w = 0) from the caller's [n][3] cotangent.
+template <typename T>
+__global__ void k_gather_v(int n, const int* __restrict__ perm, const T* __restrict__ gF,
+                           vec4_t<T>* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int o = perm[i];
+  vec4_t<T> t;
+  t.x = gF[3 * o];
+  t.y = gF[3 * o + 1];
+  t.z = gF[3 * o + 2];
+  t.w = T(0);
+  v[i] = t;
 }
-extern "C" msm_status msm_batch_plan_create(msm_plan* out, int, const double*, const int*, int,
-                                            double, double, int, int, int) {
-  if (out) *out = nullptr;
-  return MSM_ERR_UNSUPPORTED;
+
+__device__ inline int neighbour_cell_b(int c, int o, int nc, int per) {
+  if (per) {
+    if (nc == 1) return o == 0 ? 0 : -1;
+    if (nc == 2) return o < 0 ? -1 : (c + o) & 1;
+    const int v = c + o;
+    return v < 0 ? v + nc : (v >= nc ? v - nc : v);
+  }
+  const int v = c + o;
+  return (v >= 0 && v < nc) ? v : -1;
 }
-extern "C" msm_status msm_batch_energy_forces(msm_plan, const int*, const void*, const void*,
-                                              double*, void*, void*, void*) {
-  return MSM_ERR_UNSUPPORTED;
+
+template <typename T, int P>
+__global__ void __launch_bounds__(kPairThreads)
+    k_pair_vjp(const vec4_t<T>* __restrict__ sorted, const vec4_t<T>* __restrict__ v,
+               const int* __restrict__ start, PairParams<T> pp, T* __restrict__ gq,
+               T* __restrict__ gr) {
+  __shared__ vec4_t<T> tile[kPairThreads];
+  __shared__ vec4_t<T> vtile[kPairThreads];
+  const int cell = blockIdx.x;
+  const int cx = cell % pp.nc[0];
+  const int cy = (cell / pp.nc[0]) % pp.nc[1];
+  const int cz = cell / (pp.nc[0] * pp.nc[1]);
+  const int i_beg = start[cell], i_end = start[cell + 1];
+  for (int ib = i_beg; ib < i_end; ib += kPairThreads) {
+    const int i = ib + (int)threadIdx.x;
+    const bool active = i < i_end;
+    vec4_t<T> pi, vi;
+    if (active) {
+      pi = sorted[i];
+      vi = v[i];
+    } else {
+      pi.x = pi.y = pi.z = pi.w = T(0);
+      vi.x = vi.y = vi.z = vi.w = T(0);
+    }
+    T sq = T(0), rx = T(0), ry = T(0), rz = T(0);
+    for (int oz = -1; oz <= 1; ++oz) {
+      const int nz = neighbour_cell_b(cz, oz, pp.nc[2], pp.per[2]);
+      if (nz < 0) continue;
+      for (int oy = -1; oy <= 1; ++oy) {
+        const int ny = neighbour_cell_b(cy, oy, pp.nc[1], pp.per[1]);
+        if (ny < 0) continue;
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int nx = neighbour_cell_b(cx, ox, pp.nc[0], pp.per[0]);
+          if (nx < 0) continue;
+          const int nc_ = (nz * pp.nc[1] + ny) * pp.nc[0] + nx;
+          const int j_beg = start[nc_], j_end = start[nc_ + 1];
+          for (int jb = j_beg; jb < j_end; jb += kPairThreads) {
+            __syncthreads();
+            if (jb + (int)threadIdx.x < j_end) {
+              tile[threadIdx.x] = sorted[jb + threadIdx.x];
+              vtile[threadIdx.x] = v[jb + threadIdx.x];
+            }
+            __syncthreads();
+            const int cnt = min(kPairThreads, j_end - jb);
+            for (int jj = 0; jj < cnt; ++jj) {
+              const vec4_t<T> pj = tile[jj];
+              T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+              if (pp.per[0]) dx -= pp.box[0] * rint(dx * pp.inv_box[0]);
+              if (pp.per[1]) dy -= pp.box[1] * rint(dy * pp.inv_box[1]);
+              if (pp.per[2]) dz -= pp.box[2] * rint(dz * pp.inv_box[2]);
+              const T r2 = dx * dx + dy * dy + dz * dz;
+              if (r2 < pp.a2 && jb + jj != i) {
+                const vec4_t<T> vj = vtile[jj];
+                const T rinv = rsqrt_t(r2);
+                const T rinv2 = rinv * rinv;
+                const T t = r2 * pp.inv_a2;
+                T dP = pp.dc[P - 2], d2P = pp.d2c[P - 3];
+#pragma unroll
+                for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
+#pragma unroll
+                for (int k = P - 4; k >= 0; --k) d2P = d2P * t + pp.d2c[k];
+                const T f = rinv * rinv2 + T(2) * dP * pp.inv_a3;
+                const T fpr = T(-3) * rinv2 * rinv2 * rinv + T(4) * d2P * pp.inv_a5;
+                const T wx = vi.x - vj.x, wy = vi.y - vj.y, wz = vi.z - vj.z;
+                const T wd = wx * dx + wy * dy + wz * dz;
+                sq += pj.w * f * wd;
+                const T c2 = pj.w * fpr * wd;
+                rx += pj.w * f * wx + c2 * dx;
+                ry += pj.w * f * wy + c2 * dy;
+                rz += pj.w * f * wz + c2 * dz;
+              }
+            }
+          }
+        }
+      }
+    }
+    if (active) {
+      gq[i] = sq;
+      gr[3 * i] = pi.w * rx;
+      gr[3 * i + 1] = pi.w * ry;
+      gr[3 * i + 2] = pi.w * rz;
+    }
+  }
 }
+
+// D_m += q_i v_i . grad phi_m(r_i) on the level-1 grid.
+template <typename T, int P>
+__global__ void k_anterp_dipole(int n, const vec4_t<T>* __restrict__ sorted,
+                                const vec4_t<T>* __restrict__ v, GridDev<T> g,
+                                T* __restrict__ grid) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const vec4_t<T> pi = sorted[i];
+  const vec4_t<T> vi = v[i];
+  const T xs[3] = {pi.x, pi.y, pi.z};
+  T w[3][P], dw[3][P];
+  int idx[3][P];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T f;
+    const int base = grid_coord(xs[k], g.h[k], f);
+    bspline_weights<P, T>(f, w[k], dw[k], nullptr);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      idx[k][j] = axis_index(base - P / 2 + 1 + j, g.n[k], g.lo[k], g.per[k]);
+      dw[k][j] *= g.inv_h[k];
+    }
+  }
+  const T qi = pi.w;
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    if (idx[2][c] < 0) continue;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      if (idx[1][b] < 0) continue;
+      const T syz = vi.x * w[1][b] * w[2][c];
+      const T tyz = vi.y * dw[1][b] * w[2][c] + vi.z * w[1][b] * dw[2][c];
+      const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        if (idx[0][a] < 0) continue;
+        atomicAdd(&grid[row + idx[0][a]], qi * (syz * dw[0][a] + tyz * w[0][a]));
+      }
+    }
+  }
+}
+
+// Interpolation adjoint with B-spline Hessians, combined with the gE terms
+// and the short-range VJP, scattered to the caller's order.
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+    k_interp_vjp(int n, const vec4_t<T>* __restrict__ sorted, const vec4_t<T>* __restrict__ v,
+                 const int* __restrict__ perm, GridDev<T> g, const T* __restrict__ psi,
+                 const T* __restrict__ psiD, const T* __restrict__ save_phi,
+                 const T* __restrict__ save_F, const T* __restrict__ gq_sr,
+                 const T* __restrict__ gr_sr, const double* __restrict__ gE,
+                 T* __restrict__ grad_q, T* __restrict__ grad_pos) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const vec4_t<T> pi = sorted[i];
+  const vec4_t<T> vi = v[i];
+  const T xs[3] = {pi.x, pi.y, pi.z};
+  T w[3][P], dw[3][P], d2w[3][P];
+  int idx[3][P];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T f;
+    const int base = grid_coord(xs[k], g.h[k], f);
+    bspline_weights<P, T>(f, w[k], dw[k], d2w[k]);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      idx[k][j] = axis_index(base - P / 2 + 1 + j, g.n[k], g.lo[k], g.per[k]);
+      dw[k][j] *= g.inv_h[k];
+      d2w[k][j] *= g.inv_h[k] * g.inv_h[k];
+    }
+  }
+  // moments of psi (M_abc: derivative orders in x, y, z) and of psiD (N_abc)
+  T M000 = 0, M100 = 0, M010 = 0, M001 = 0, M200 = 0, M020 = 0, M002 = 0, M110 = 0, M101 = 0,
+    M011 = 0;
+  T N000 = 0, N100 = 0, N010 = 0, N001 = 0;
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    if (idx[2][c] < 0) continue;
+    T Y00 = 0, Y10 = 0, Y01 = 0, Y20 = 0, Y02 = 0, Y11 = 0, Z0 = 0, Z1x = 0, Z1y = 0;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      if (idx[1][b] < 0) continue;
+      const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
+      T S0 = 0, S1 = 0, S2 = 0, D0 = 0, D1 = 0;
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        if (idx[0][a] < 0) continue;
+        const T e = psi[row + idx[0][a]];
+        const T ed = psiD[row + idx[0][a]];
+        S0 += e * w[0][a];
+        S1 += e * dw[0][a];
+        S2 += e * d2w[0][a];
+        D0 += ed * w[0][a];
+        D1 += ed * dw[0][a];
+      }
+      const T wy = w[1][b], dwy = dw[1][b], d2wy = d2w[1][b];
+      Y00 += S0 * wy;
+      Y10 += S1 * wy;
+      Y01 += S0 * dwy;
+      Y20 += S2 * wy;
+      Y02 += S0 * d2wy;
+      Y11 += S1 * dwy;
+      Z0 += D0 * wy;
+      Z1x += D1 * wy;
+      Z1y += D0 * dwy;
+    }
+    const T wz = w[2][c], dwz = dw[2][c], d2wz = d2w[2][c];
+    M000 += Y00 * wz;
+    M100 += Y10 * wz;
+    M010 += Y01 * wz;
+    M001 += Y00 * dwz;
+    M200 += Y20 * wz;
+    M020 += Y02 * wz;
+    M002 += Y00 * d2wz;
+    M110 += Y11 * wz;
+    M101 += Y10 * dwz;
+    M011 += Y01 * dwz;
+    N000 += Z0 * wz;
+    N100 += Z1x * wz;
+    N010 += Z1y * wz;
+    N001 += Z0 * dwz;
+  }
+  (void)M000;
+  const T vx = vi.x, vy = vi.y, vz = vi.z, qi = pi.w;
+  const T sq = N000 + vx * M100 + vy * M010 + vz * M001;
+  const T sx = N100 + vx * M200 + vy * M110 + vz * M101;
+  const T sy = N010 + vx * M110 + vy * M020 + vz * M011;
+  const T sz = N001 + vx * M101 + vy * M011 + vz * M002;
+  const T ge = gE ? (T)(*gE) : T(0);
+  const int o = perm[i];
+  if (grad_q) grad_q[o] = ge * save_phi[i] + gq_sr[i] - sq;
+  if (grad_pos) {
+    grad_pos[3 * o] = -ge * save_F[3 * i] + gr_sr[3 * i] - qi * sx;
+    grad_pos[3 * o + 1] = -ge * save_F[3 * i + 1] + gr_sr[3 * i + 1] - qi * sy;
+    grad_pos[3 * o + 2] = -ge * save_F[3 * i + 2] + gr_sr[3 * i + 2] - qi * sz;
+  }
+}
+
+// Without a force cotangent: grad_q = gE phi, grad_pos = -gE F.
+template <typename T>
+__global__ void k_grad_energy_only(int n, const int* __restrict__ perm,
+                                   const T* __restrict__ save_phi, const T* __restrict__ save_F,
+                                   const double* __restrict__ gE, T* __restrict__ grad_q,
+                                   T* __restrict__ grad_pos) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T ge = gE ? (T)(*gE) : T(0);
+  const int o = perm[i];
+  if (grad_q) grad_q[o] = ge * save_phi[i];
+  if (grad_pos) {
+    grad_pos[3 * o] = -ge * save_F[3 * i];
+    grad_pos[3 * o + 1] = -ge * save_F[3 * i + 1];
+    grad_pos[3 * o + 2] = -ge * save_F[3 * i + 2];
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_gather_v(int n, const int* perm, const T* gF, vec4_t<T>* v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_v<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, gF, v);
+}
+
+template <typename T>
+void launch_pair_vjp(int p, int ncell, const vec4_t<T>* sorted, const vec4_t<T>* v,
+                     const int* start, const PairParams<T>& pp, T* gq, T* gr, hipStream_t s) {
+  if (ncell <= 0) return;
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_pair_vjp<T, 4>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, v, start, pp, gq, gr); break;
+    case 6: hipLaunchKernelGGL((k_pair_vjp<T, 6>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, v, start, pp, gq, gr); break;
+    case 8: hipLaunchKernelGGL((k_pair_vjp<T, 8>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, v, start, pp, gq, gr); break;
+  }
+}
+
+template <typename T>
+void launch_anterp_dipole(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v,
+                          const GridDev<T>& g, T* grid, hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = (n + 255) / 256;
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_anterp_dipole<T, 4>), dim3(nb), dim3(256), 0, s, n, sorted, v, g, grid); break;
+    case 6: hipLaunchKernelGGL((k_anterp_dipole<T, 6>), dim3(nb), dim3(256), 0, s, n, sorted, v, g, grid); break;
+    case 8: hipLaunchKernelGGL((k_anterp_dipole<T, 8>), dim3(nb), dim3(256), 0, s, n, sorted, v, g, grid); break;
+  }
+}
+
+template <typename T>
+void launch_interp_vjp(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v, const int* perm,
+                       const GridDev<T>& g, const T* psi, const T* psiD, const T* save_phi,
+                       const T* save_F, const T* gq_sr, const T* gr_sr, const double* gE,
+                       T* grad_q, T* grad_pos, hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = (n + 255) / 256;
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_interp_vjp<T, 4>), dim3(nb), dim3(256), 0, s, n, sorted, v, perm, g, psi, psiD, save_phi, save_F, gq_sr, gr_sr, gE, grad_q, grad_pos); break;
+    case 6: hipLaunchKernelGGL((k_interp_vjp<T, 6>), dim3(nb), dim3(256), 0, s, n, sorted, v, perm, g, psi, psiD, save_phi, save_F, gq_sr, gr_sr, gE, grad_q, grad_pos); break;
+    case 8: hipLaunchKernelGGL((k_interp_vjp<T, 8>), dim3(nb), dim3(256), 0, s, n, sorted, v, perm, g, psi, psiD, save_phi, save_F, gq_sr, gr_sr, gE, grad_q, grad_pos); break;
+  }
+}
+
+template <typename T>
+void launch_grad_energy_only(int n, const int* perm, const T* save_phi, const T* save_F,
+                             const double* gE, T* grad_q, T* grad_pos, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_grad_energy_only<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, perm,
+                     save_phi, save_F, gE, grad_q, grad_pos);
+}
+
+#define MSM_INST_BACKWARD(T)                                                                      \
+  template void launch_gather_v<T>(int, const int*, const T*, vec4_t<T>*, hipStream_t);           \
+  template void launch_pair_vjp<T>(int, int, const vec4_t<T>*, const vec4_t<T>*, const int*,      \
+                                   const PairParams<T>&, T*, T*, hipStream_t);                    \
+  template void launch_anterp_dipole<T>(int, int, const vec4_t<T>*, const vec4_t<T>*,             \
+                                        const GridDev<T>&, T*, hipStream_t);                      \
+  template void launch_interp_vjp<T>(int, int, const vec4_t<T>*, const vec4_t<T>*, const int*,    \
+                                     const GridDev<T>&, const T*, const T*, const T*, const T*,   \
+                                     const T*, const T*, const double*, T*, T*, hipStream_t);     \
+  template void launch_grad_energy_only<T>(int, const int*, const T*, const T*, const double*,    \
+                                           T*, T*, hipStream_t);
+MSM_INST_BACKWARD(float)
+MSM_INST_BACKWARD(double)
+
+}  // namespace msm

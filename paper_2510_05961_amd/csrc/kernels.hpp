@@ -20,20 +20,32 @@ struct PairParams {
   T box[3], inv_box[3];
   int per[3];
   int nc[3];
-  T a2, inv_a2, inv_a, inv_a3;
-  T c[8];   // softening polynomial in t = (r/a)^2
-  T dc[8];  // its t-derivative: dc[k] = (k+1) c[k+1]
+  T a2, inv_a2, inv_a, inv_a3, inv_a5;
+  T c[8];    // softening polynomial in t = (r/a)^2
+  T dc[8];   // its t-derivative: dc[k] = (k+1) c[k+1]
+  T d2c[8];  // second t-derivative: d2c[k] = (k+2)(k+1) c[k+2]
 };
 
-// One stencil convolution e = K q on a level grid (a5, a6).
-template <typename T>
+// One stencil convolution e_o = sum_d K_d q_{o+shift-d} (a5, a6).
 struct ConvParams {
-  int n[3];
+  int n[3];             // input grid
+  int nout[3];          // output grid (extended on free axes for the factored form)
+  int shift[3];         // input grid index of output element 0
   int per[3];
   int off[3], len[3];   // stencil offsets d_k = off_k .. off_k + len_k - 1
   int dz_per_split;     // stencil z-planes handled by one workgroup
   int nsplit;
   int lds_w, lds_h;     // staged input tile
+  int small;            // 16 x 16 tiles (else 64 x 32)
+};
+
+// omega' applied axis by axis (second half of the factored stencil).
+struct OmegaParams {
+  int n[3];      // output grid
+  int next[3];   // input (extended) grid
+  int per[3];
+  int M;
+  double omega[25];
 };
 
 template <typename T>
@@ -58,17 +70,36 @@ void launch_restrict(int p, const GridDev<T>& fine, const GridDev<T>& coarse, co
 template <typename T>
 void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, const double* J,
                     const T* ec, T* ef, hipStream_t s);
-// Returns the dynamic LDS bytes the conv kernel needs for this stencil.
-template <typename T>
-size_t conv_lds_bytes(const int len[3], bool small);
-template <typename T>
-void launch_conv(const ConvParams<T>& cp, const T* K, const int2* rowext, const T* q, T* e,
+ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3],
+                            const int per[3], const int off[3], const int len[3], int tsize);
+// dynamic LDS bytes of the conv kernel for these parameters (tsize = grid type size)
+size_t conv_lds_bytes(const ConvParams& cp, int tsize);
+template <typename TI, typename TA>
+void launch_conv(const ConvParams& cp, const TA* K, const int2* rowext, const TI* q, TA* e,
                  hipStream_t s);
-template <typename T>
-ConvParams<T> make_conv_params(const int n[3], const int per[3], const int off[3],
-                               const int len[3]);
+size_t omega_lds_bytes(int M);
+template <typename TO>
+void launch_omega(const OmegaParams& op, const double* u, TO* e, hipStream_t s);
 
 template <typename T>
 void launch_fill(T* p, long long count, T value, hipStream_t s);
+
+// backward (vector-Jacobian product)
+template <typename T>
+void launch_gather_v(int n, const int* perm, const T* gF, vec4_t<T>* v, hipStream_t s);
+template <typename T>
+void launch_pair_vjp(int p, int ncell, const vec4_t<T>* sorted, const vec4_t<T>* v,
+                     const int* start, const PairParams<T>& pp, T* gq, T* gr, hipStream_t s);
+template <typename T>
+void launch_anterp_dipole(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v,
+                          const GridDev<T>& g, T* grid, hipStream_t s);
+template <typename T>
+void launch_interp_vjp(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v, const int* perm,
+                       const GridDev<T>& g, const T* psi, const T* psiD, const T* save_phi,
+                       const T* save_F, const T* gq_sr, const T* gr_sr, const double* gE,
+                       T* grad_q, T* grad_pos, hipStream_t s);
+template <typename T>
+void launch_grad_energy_only(int n, const int* perm, const T* save_phi, const T* save_F,
+                             const double* gE, T* grad_q, T* grad_pos, hipStream_t s);
 
 }  // namespace msm

@@ -105,41 +105,44 @@ __global__ void k_prolong(GridDev<T> f, GridDev<T> c, JTaps<T> jt, const T* __re
 }
 
 // ---------------------------------------------------------------------------
-// a5 / a6: stencil convolution e_m = sum_d K_d q_{m-d} (eq.
+// a5 / a6: stencil convolution e_o = sum_d K_d q_{o+shift-d} (eq.
 // action_of_K_as_convolution).  A workgroup owns a TX x TY tile of output
 // points of one z-plane and a contiguous range of stencil z-planes; for each
 // plane it stages the input window (with periodic wrap or zero padding)
 // through LDS, and every thread keeps R consecutive x outputs in registers.
 // The stencil coefficients are uniform across the workgroup (scalar loads);
-// per stencil row only the non-zero x range is visited.
+// per stencil row only the non-zero x range is visited.  TI is the grid type
+// (what LDS holds), TA the stencil / accumulation / output type: the factored
+// levels accumulate the k-sample convolution in FP64.
 // ---------------------------------------------------------------------------
 constexpr int kConvCH = 8;
 
-template <typename T, int R, int TXT, int TYT>
+template <typename TI, typename TA, int R, int TXT, int TYT>
 __global__ void __launch_bounds__(TXT * TYT)
-    k_conv(ConvParams<T> cp, const T* __restrict__ K, const int2* __restrict__ rowext,
-           const T* __restrict__ q, T* __restrict__ e) {
+    k_conv(ConvParams cp, const TA* __restrict__ K, const int2* __restrict__ rowext,
+           const TI* __restrict__ q, TA* __restrict__ e) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* lds = reinterpret_cast<T*>(smem_raw);
+  TI* lds = reinterpret_cast<TI*>(smem_raw);
   const int tx = threadIdx.x % TXT, ty = threadIdx.x / TXT;
   const int n0 = cp.n[0], n1 = cp.n[1], n2 = cp.n[2];
+  const int o0 = cp.nout[0], o1 = cp.nout[1], o2 = cp.nout[2];
   const int lx = cp.len[0], ly = cp.len[1];
   const int x0 = blockIdx.x * (TXT * R), y0 = blockIdx.y * TYT;
-  const int z = blockIdx.z % n2, split = blockIdx.z / n2;
+  const int z = blockIdx.z % o2, split = blockIdx.z / o2;
   const int jz0 = split * cp.dz_per_split;
   const int jz1 = min(cp.len[2], jz0 + cp.dz_per_split);
   const int LW = cp.lds_w, LH = cp.lds_h;
-  const int xs = x0 - (cp.off[0] + lx - 1);
-  const int ys = y0 - (cp.off[1] + ly - 1);
-  T total[R];
+  const int xs = x0 + cp.shift[0] - (cp.off[0] + lx - 1);
+  const int ys = y0 + cp.shift[1] - (cp.off[1] + ly - 1);
+  TA total[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) total[r] = T(0);
+  for (int r = 0; r < R; ++r) total[r] = TA(0);
   for (int jz = jz0; jz < jz1; ++jz) {
-    int zi = z - (cp.off[2] + jz);
+    int zi = z + cp.shift[2] - (cp.off[2] + jz);
     if (cp.per[2]) zi = wrap_index(zi, n2);
     else if (zi < 0 || zi >= n2) continue;  // uniform over the workgroup
     __syncthreads();
-    const T* qz = q + (long long)zi * n1 * n0;
+    const TI* qz = q + (long long)zi * n1 * n0;
     for (int idx = threadIdx.x; idx < LW * LH; idx += TXT * TYT) {
       const int ry = idx / LW, rx = idx - ry * LW;
       int yi = ys + ry, xi = xs + rx;
@@ -148,53 +151,116 @@ __global__ void __launch_bounds__(TXT * TYT)
       else ok = (yi >= 0 && yi < n1);
       if (cp.per[0]) xi = wrap_index(xi, n0);
       else ok = ok && (xi >= 0 && xi < n0);
-      lds[idx] = ok ? qz[(long long)yi * n0 + xi] : T(0);
+      lds[idx] = ok ? qz[(long long)yi * n0 + xi] : TI(0);
     }
     __syncthreads();
-    T acc[R];
+    TA acc[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = T(0);
-    const T* Kz = K + (long long)jz * ly * lx;
+    for (int r = 0; r < R; ++r) acc[r] = TA(0);
+    const TA* Kz = K + (long long)jz * ly * lx;
     const int2* ext_z = rowext + jz * ly;
     for (int jy = 0; jy < ly; ++jy) {
       const int2 ext = ext_z[jy];
       if (ext.x > ext.y) continue;
-      const T* lrow = lds + (ty - jy + ly - 1) * LW + tx * R;
-      const T* Krow = Kz + jy * lx;
+      const TI* lrow = lds + (ty - jy + ly - 1) * LW + tx * R;
+      const TA* Krow = Kz + jy * lx;
       int jx = ext.x;
       for (; jx + kConvCH - 1 <= ext.y; jx += kConvCH) {
-        T win[kConvCH + R - 1];
-        const T* wp = lrow + (lx - jx - kConvCH);
+        TA win[kConvCH + R - 1];
+        const TI* wp = lrow + (lx - jx - kConvCH);
 #pragma unroll
-        for (int u = 0; u < kConvCH + R - 1; ++u) win[u] = wp[u];
+        for (int u = 0; u < kConvCH + R - 1; ++u) win[u] = (TA)wp[u];
 #pragma unroll
         for (int c = 0; c < kConvCH; ++c) {
-          const T kv = Krow[jx + c];
+          const TA kv = Krow[jx + c];
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] = fma(kv, win[kConvCH - 1 - c + r], acc[r]);
         }
       }
       for (; jx <= ext.y; ++jx) {
-        const T kv = Krow[jx];
-        const T* wp = lrow + (lx - 1 - jx);
+        const TA kv = Krow[jx];
+        const TI* wp = lrow + (lx - 1 - jx);
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = fma(kv, wp[r], acc[r]);
+        for (int r = 0; r < R; ++r) acc[r] = fma(kv, (TA)wp[r], acc[r]);
       }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) total[r] += acc[r];
   }
   const int y = y0 + ty;
-  if (y < n1) {
-    T* erow = e + ((long long)z * n1 + y) * n0;
+  if (y < o1) {
+    TA* erow = e + ((long long)z * o1 + y) * o0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int x = x0 + tx * R + r;
-      if (x < n0) {
+      if (x < o0) {
         if (cp.nsplit > 1) atomicAdd(&erow[x], total[r]);
         else erow[x] = total[r];
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Second half of the factored stencil: e_m = sum_k omega'_kx omega'_ky
+// omega'_kz u_{m-k}, applied one axis at a time inside LDS on a T^3 output
+// tile (u lives on the extended domain of the free axes).
+// ---------------------------------------------------------------------------
+template <typename TO, int T>
+__global__ void __launch_bounds__(256)
+    k_omega(OmegaParams op, const double* __restrict__ u, TO* __restrict__ e) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* buf = reinterpret_cast<double*>(smem_raw);
+  const int M = op.M, W = T + 2 * M;
+  double* reg0 = buf;                 // [W][W][W]   u window
+  double* reg1 = reg0 + W * W * W;    // [W][W][T]   after the x pass
+  double* reg2 = reg1 + W * W * T;    // [W][T][T]   after the y pass
+  const int m0[3] = {(int)blockIdx.x * T, (int)blockIdx.y * T, (int)blockIdx.z * T};
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int idx = tid; idx < W * W * W; idx += nt) {
+    const int rx = idx % W, ry = (idx / W) % W, rz = idx / (W * W);
+    const int r3[3] = {rx, ry, rz};
+    long long off = 0, stride = 1;
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+      int m = m0[k] - M + r3[k];  // grid index of u needed
+      int ui;
+      if (op.per[k]) {
+        ui = wrap_index(m, op.n[k]);
+      } else {
+        ui = m + M;  // extended index
+        ok = ok && (ui >= 0 && ui < op.next[k]);
+      }
+      off += (long long)ui * stride;
+      stride *= op.next[k];
+    }
+    reg0[idx] = ok ? u[off] : 0.0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < W * W * T; idx += nt) {
+    const int x = idx % T, ry = (idx / T) % W, rz = idx / (T * W);
+    const double* row = reg0 + (rz * W + ry) * W;
+    double s = 0.0;
+    for (int k = -M; k <= M; ++k) s += op.omega[k < 0 ? -k : k] * row[x + M - k];
+    reg1[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < W * T * T; idx += nt) {
+    const int x = idx % T, y = (idx / T) % T, rz = idx / (T * T);
+    double s = 0.0;
+    for (int k = -M; k <= M; ++k)
+      s += op.omega[k < 0 ? -k : k] * reg1[(rz * W + (y + M - k)) * T + x];
+    reg2[idx] = s;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < T * T * T; idx += nt) {
+    const int x = idx % T, y = (idx / T) % T, z = idx / (T * T);
+    const int mx = m0[0] + x, my = m0[1] + y, mz = m0[2] + z;
+    if (mx >= op.n[0] || my >= op.n[1] || mz >= op.n[2]) continue;
+    double s = 0.0;
+    for (int k = -M; k <= M; ++k)
+      s += op.omega[k < 0 ? -k : k] * reg2[((z + M - k) * T + y) * T + x];
+    e[((long long)mz * op.n[1] + my) * op.n[0] + mx] = (TO)s;
   }
 }
 
@@ -242,53 +308,66 @@ void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, con
   }
 }
 
-// big tiles: 8x8 threads... see k_conv; small tiles for grids narrower than 64
-static bool conv_small(const int n[3]) { return n[0] < 48; }
+// big tiles (64 x 32 outputs, 256 threads) for wide grids, small tiles
+// (16 x 16 outputs, 64 threads) for grids narrower than 48 points
+static bool conv_small(const int nout[3]) { return nout[0] < 48; }
 
-template <typename T>
-ConvParams<T> make_conv_params(const int n[3], const int per[3], const int off[3],
-                               const int len[3]) {
-  ConvParams<T> cp;
+ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3],
+                            const int per[3], const int off[3], const int len[3], int tsize) {
+  ConvParams cp;
   for (int k = 0; k < 3; ++k) {
     cp.n[k] = n[k];
+    cp.nout[k] = nout[k];
+    cp.shift[k] = shift[k];
     cp.per[k] = per[k];
     cp.off[k] = off[k];
     cp.len[k] = len[k];
   }
-  const bool small = conv_small(n);
+  const bool small = conv_small(nout);
   const int TXo = small ? 16 : 64, TY = small ? 16 : 32;
   cp.lds_w = TXo + len[0] - 1;
-  if (sizeof(T) == 4) cp.lds_w |= 1;  // odd row stride spreads rows over LDS banks
+  if (tsize == 4) cp.lds_w |= 1;  // odd row stride spreads rows over LDS banks
   cp.lds_h = TY + len[1] - 1;
-  const long long tiles = (long long)((n[0] + TXo - 1) / TXo) * ((n[1] + TY - 1) / TY) * n[2];
+  const long long tiles =
+      (long long)((nout[0] + TXo - 1) / TXo) * ((nout[1] + TY - 1) / TY) * nout[2];
   long long want = (2048 + tiles - 1) / tiles;
   if (want < 1) want = 1;
   if (want > len[2]) want = len[2];
   cp.dz_per_split = (int)((len[2] + want - 1) / want);
   cp.nsplit = (len[2] + cp.dz_per_split - 1) / cp.dz_per_split;
+  cp.small = small;
   return cp;
 }
 
-template <typename T>
-size_t conv_lds_bytes(const int len[3], bool small) {
-  const int TXo = small ? 16 : 64, TY = small ? 16 : 32;
-  int w = TXo + len[0] - 1;
-  if (sizeof(T) == 4) w |= 1;
-  return (size_t)w * (TY + len[1] - 1) * sizeof(T);
+size_t conv_lds_bytes(const ConvParams& cp, int tsize) {
+  return (size_t)cp.lds_w * cp.lds_h * tsize;
 }
 
-template <typename T>
-void launch_conv(const ConvParams<T>& cp, const T* K, const int2* rowext, const T* q, T* e,
+template <typename TI, typename TA>
+void launch_conv(const ConvParams& cp, const TA* K, const int2* rowext, const TI* q, TA* e,
                  hipStream_t s) {
-  const bool small = conv_small(cp.n);
-  const size_t lds = (size_t)cp.lds_w * cp.lds_h * sizeof(T);
-  if (small) {
-    dim3 grid((cp.n[0] + 15) / 16, (cp.n[1] + 15) / 16, cp.n[2] * cp.nsplit);
-    hipLaunchKernelGGL((k_conv<T, 4, 4, 16>), grid, dim3(64), lds, s, cp, K, rowext, q, e);
+  const size_t lds = (size_t)cp.lds_w * cp.lds_h * sizeof(TI);
+  if (cp.small) {
+    dim3 grid((cp.nout[0] + 15) / 16, (cp.nout[1] + 15) / 16, cp.nout[2] * cp.nsplit);
+    hipLaunchKernelGGL((k_conv<TI, TA, 4, 4, 16>), grid, dim3(64), lds, s, cp, K, rowext, q, e);
   } else {
-    dim3 grid((cp.n[0] + 63) / 64, (cp.n[1] + 31) / 32, cp.n[2] * cp.nsplit);
-    hipLaunchKernelGGL((k_conv<T, 8, 8, 32>), grid, dim3(256), lds, s, cp, K, rowext, q, e);
+    dim3 grid((cp.nout[0] + 63) / 64, (cp.nout[1] + 31) / 32, cp.nout[2] * cp.nsplit);
+    hipLaunchKernelGGL((k_conv<TI, TA, 8, 8, 32>), grid, dim3(256), lds, s, cp, K, rowext, q, e);
   }
+}
+
+size_t omega_lds_bytes(int M) {
+  const int T = M <= 6 ? 8 : 4, W = T + 2 * M;
+  return sizeof(double) * ((size_t)W * W * W + (size_t)W * W * T + (size_t)W * T * T);
+}
+
+template <typename TO>
+void launch_omega(const OmegaParams& op, const double* u, TO* e, hipStream_t s) {
+  const int T = op.M <= 6 ? 8 : 4;
+  dim3 grid((op.n[0] + T - 1) / T, (op.n[1] + T - 1) / T, (op.n[2] + T - 1) / T);
+  const size_t lds = omega_lds_bytes(op.M);
+  if (T == 8) hipLaunchKernelGGL((k_omega<TO, 8>), grid, dim3(256), lds, s, op, u, e);
+  else hipLaunchKernelGGL((k_omega<TO, 4>), grid, dim3(256), lds, s, op, u, e);
 }
 
 template <typename T>
@@ -304,13 +383,14 @@ void launch_fill(T* p, long long count, T value, hipStream_t s) {
                                    const T*, T*, hipStream_t);                                    \
   template void launch_prolong<T>(int, const GridDev<T>&, const GridDev<T>&, const double*,      \
                                   const T*, T*, hipStream_t);                                     \
-  template ConvParams<T> make_conv_params<T>(const int*, const int*, const int*, const int*);     \
-  template size_t conv_lds_bytes<T>(const int*, bool);                                            \
-  template void launch_conv<T>(const ConvParams<T>&, const T*, const int2*, const T*, T*,         \
-                               hipStream_t);                                                      \
+  template void launch_conv<T, T>(const ConvParams&, const T*, const int2*, const T*, T*,         \
+                                  hipStream_t);                                                   \
+  template void launch_omega<T>(const OmegaParams&, const double*, T*, hipStream_t);              \
   template void launch_fill<T>(T*, long long, T, hipStream_t);
 MSM_INST_GRID(float)
 MSM_INST_GRID(double)
 template void launch_fill<int>(int*, long long, int, hipStream_t);
+template void launch_conv<float, double>(const ConvParams&, const double*, const int2*,
+                                         const float*, double*, hipStream_t);
 
 }  // namespace msm

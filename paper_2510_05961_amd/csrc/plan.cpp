@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <sstream>
 
 #include "msm.h"
@@ -408,6 +409,76 @@ int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, in
         }
   }
 
+  // factored form for the intermediate levels: S^l = S^1 / 2^(l-1) with
+  // S^1(d) = k_1(|h_1 o d|) on |d_k| <= R_k (the same R as for K^1)
+  {
+    int R[3];
+    for (int k = 0; k < 3; ++k) R[k] = P.W1[k] - M;
+    const LevelGeom& g1 = P.lev[0];
+    std::vector<double> S1((size_t)(2 * R[0] + 1) * (2 * R[1] + 1) * (2 * R[2] + 1));
+    for (int z = -R[2]; z <= R[2]; ++z)
+      for (int y = -R[1]; y <= R[1]; ++y)
+        for (int x = -R[0]; x <= R[0]; ++x) {
+          double dx = x * g1.h[0], dy = y * g1.h[1], dz = z * g1.h[2];
+          double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+          S1[((size_t)(z + R[2]) * (2 * R[1] + 1) + (y + R[1])) * (2 * R[0] + 1) + (x + R[0])] =
+              split_kernel(P.gcoef, order, 1, 2, a, r);
+        }
+    for (int l = 1; l < levels; ++l) {
+      LevelGeom& g = P.lev[l - 1];
+      const double scale = std::ldexp(1.0, -(l - 1));
+      g.Gext = 1;
+      for (int k = 0; k < 3; ++k) {
+        if (P.periodic[k]) {
+          g.next[k] = g.n[k];
+          g.shift[k] = 0;
+          if (2 * R[k] + 1 <= g.n[k]) {
+            g.s_off[k] = -R[k];
+            g.s_len[k] = 2 * R[k] + 1;
+          } else {
+            g.s_off[k] = -(g.n[k] / 2);
+            g.s_len[k] = g.n[k];
+          }
+        } else {
+          g.next[k] = g.n[k] + 2 * M;
+          g.shift[k] = -M;
+          int w = std::min(R[k], g.n[k] - 1 + M);
+          g.s_off[k] = -w;
+          g.s_len[k] = 2 * w + 1;
+        }
+        g.Gext *= g.next[k];
+      }
+      g.S.assign((size_t)g.s_len[0] * g.s_len[1] * g.s_len[2], 0.0);
+      for (int z = -R[2]; z <= R[2]; ++z)
+        for (int y = -R[1]; y <= R[1]; ++y)
+          for (int x = -R[0]; x <= R[0]; ++x) {
+            const int d[3] = {x, y, z};
+            int idx[3];
+            bool keep = true;
+            for (int k = 0; k < 3; ++k) {
+              int e = d[k] - g.s_off[k];
+              if (P.periodic[k]) e = ((e % g.n[k]) + g.n[k]) % g.n[k];
+              else if (e < 0 || e >= g.s_len[k]) keep = false;
+              idx[k] = e;
+            }
+            if (!keep) continue;
+            g.S[((size_t)idx[2] * g.s_len[1] + idx[1]) * g.s_len[0] + idx[0]] +=
+                scale * S1[((size_t)(z + R[2]) * (2 * R[1] + 1) + (y + R[1])) * (2 * R[0] + 1) +
+                           (x + R[0])];
+          }
+      long long nnzK = 0, nnzS = 0;
+      for (double v : g.K) nnzK += (v != 0.0);
+      for (double v : g.S) nnzS += (v != 0.0);
+      // work: taps x outputs; the factored form adds (2M+1) taps per axis
+      const double direct = (double)nnzK * g.G;
+      const double fact = (double)nnzS * g.Gext + 3.0 * (2 * M + 1) * g.G;
+      // MSM_FACTORED=0 keeps every level on the direct stencil (tests compare both)
+      const char* env = std::getenv("MSM_FACTORED");
+      const bool allow = !(env && env[0] == '0');
+      g.factored = allow && fact < 0.8 * direct;
+    }
+  }
+
   // top level: dense over every top-grid pair
   {
     LevelGeom& g = P.lev[levels - 1];
@@ -503,7 +574,15 @@ std::string describe_json(const HostPlan& P) {
       << g.lo[0] << "," << g.lo[1] << "," << g.lo[2] << "],\"h\":[" << g.h[0] << "," << g.h[1]
       << "," << g.h[2] << "],\"stencil_off\":[" << g.off[0] << "," << g.off[1] << "," << g.off[2]
       << "],\"stencil_len\":[" << g.len[0] << "," << g.len[1] << "," << g.len[2]
-      << "],\"stencil_nnz\":" << nnz << "}";
+      << "],\"stencil_nnz\":" << nnz;
+    if (g.factored) {
+      long long snz = 0;
+      for (double v : g.S) snz += (v != 0.0);
+      o << ",\"factored\":true,\"samples_len\":[" << g.s_len[0] << "," << g.s_len[1] << ","
+        << g.s_len[2] << "],\"samples_nnz\":" << snz << ",\"ext\":[" << g.next[0] << ","
+        << g.next[1] << "," << g.next[2] << "]";
+    }
+    o << "}";
   }
   o << "]}";
   return o.str();

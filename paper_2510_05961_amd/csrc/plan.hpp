@@ -19,6 +19,16 @@ struct LevelGeom {
   int off[3];      // first offset per axis
   int len[3];      // number of offsets per axis
   std::vector<double> K;  // [len2][len1][len0]
+  // Factored form K^l = (omega' x omega' x omega') * S^l (eq.
+  // kernel_stencil_by_conv_with_universal_coeff), used when cheaper: the
+  // samples S^l(d) = k_l(|h_l o d|) are convolved first, on an output domain
+  // extended by M on free axes, then omega' is applied axis by axis.
+  bool factored = false;
+  int s_off[3], s_len[3];  // sample box offsets (folded on periodic axes)
+  std::vector<double> S;   // [s_len2][s_len1][s_len0]
+  int next[3];             // extended output dims: n + 2M on free axes, n on periodic
+  int shift[3];            // grid index of extended element 0 (-M free, 0 periodic)
+  long long Gext;
 };
 
 struct HostPlan {

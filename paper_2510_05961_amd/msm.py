@@ -24,7 +24,8 @@ _lib = None
 EXPORTS = ("msm_plan_create", "msm_plan_create_host", "msm_plan_destroy", "msm_plan_describe",
            "msm_plan_get_stencil", "msm_plan_grid_dims", "msm_workspace_bytes",
            "msm_energy_forces", "msm_backward", "msm_plan_status", "msm_plan_get_grid",
-           "msm_batch_plan_create", "msm_batch_energy_forces", "msm_status_string")
+           "msm_batch_plan_create", "msm_batch_energy_forces", "msm_status_string",
+           "msm_plan_set_profiling", "msm_plan_get_profile")
 
 
 class MSMError(RuntimeError):
@@ -60,6 +61,8 @@ def lib():
         L.msm_plan_get_grid.argtypes = [P, i, i, P, P]
         L.msm_batch_plan_create.argtypes = [pp, i, P, P, i, d, d, i, i, i]
         L.msm_batch_energy_forces.argtypes = [P, P, P, P, P, P, P, P]
+        L.msm_plan_set_profiling.argtypes = [P, i]
+        L.msm_plan_get_profile.argtypes = [P, ctypes.c_char_p, sz, i]
         L.msm_status_string.argtypes = [i]
         L.msm_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -174,6 +177,15 @@ class Plan:
 
     def status(self, stream=None):
         return int(lib().msm_plan_status(self._h, _stream(stream)))
+
+    def set_profiling(self, on=True):
+        _check(lib().msm_plan_set_profiling(self._h, int(bool(on))), "set_profiling")
+
+    def profile(self, reset=False):
+        """{stage: {"ms": total, "launches": n}} since the last reset."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().msm_plan_get_profile(self._h, buf, len(buf), int(bool(reset))), "get_profile")
+        return json.loads(buf.value.decode())
 
     def grid(self, level, which):
         import torch

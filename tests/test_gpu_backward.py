@@ -1,0 +1,133 @@
+"""GPU adjoint (msm_backward, torch.autograd) against the oracle's adjoint and
+finite differences."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_05961_amd import msm
+from paper_2510_05961_amd import workloads as WL
+
+from helpers import TOL, cast, config_case, mask_of, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_fwd_bwd(plan, pos, q, gE, v):
+    import torch
+    dt = plan.dtype
+    P = torch.tensor(pos, dtype=dt, device="cuda")
+    Q = torch.tensor(q, dtype=dt, device="cuda")
+    ws = torch.empty(plan.workspace_bytes(len(q)), dtype=torch.uint8, device="cuda")
+    E, F, dq = plan.energy_forces(P, Q, ws=ws)
+    gEt = torch.tensor([gE], dtype=torch.float64, device="cuda")
+    gF = torch.tensor(v, dtype=dt, device="cuda") if v is not None else None
+    gpos, gq = plan.backward(P, Q, ws, gE=gEt, gF=gF)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    return gpos.double().cpu().numpy(), gq.double().cpu().numpy()
+
+
+CASES = [
+    # box, periodic, p, h, a, L, fp64, n
+    ((12.0, 12.0, 12.0), (1, 1, 1), 4, 0.75, 4.0, 3, True, 300),
+    ((11.0, 12.0, 13.0), (0, 0, 0), 6, 1.0, 3.0, 3, True, 250),
+    ((12.0, 12.0, 9.0), (1, 1, 0), 4, 1.0, 4.0, 3, True, 200),
+    ((12.0, 12.0, 12.0), (1, 1, 1), 4, 0.75, 4.0, 3, False, 301),
+    ((11.0, 12.0, 13.0), (0, 0, 0), 4, 1.0, 3.0, 2, False, 257),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_backward_matches_oracle_adjoint(case):
+    box, per, p, h, a, L, fp64, n = case
+    pos, q = WL.gaussian_charges(n, box, 0.5, seed=n + 1)
+    pos, q = cast(pos, q, fp64)
+    v = WL.force_cotangent(n, seed=40)
+    if not fp64:
+        v = v.astype(np.float32).astype(np.float64)
+    print(f"case n={n} per={per} p={p} {'fp64' if fp64 else 'fp32'}", flush=True)
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP64 if fp64 else msm.MSM_FP32, n)
+    gpos, gq = _gpu_fwd_bwd(plan, pos, q, 0.7, v)
+    rq, rpos = O.OracleMSM(box, per, p, h, a, L).backward(pos, q, 0.7, v)
+    tol = TOL["fp64" if fp64 else "fp32"]["F"]
+    e_pos, e_q = rel_rms(gpos, rpos), rel_rms(gq, rq)
+    print(f"  grad_pos rel={e_pos:.2e} grad_q rel={e_q:.2e}", flush=True)
+    assert e_pos <= tol and e_q <= tol
+    # energy-only cotangent path
+    gpos0, gq0 = _gpu_fwd_bwd(plan, pos, q, 1.3, None)
+    ref = O.OracleMSM(box, per, p, h, a, L).compute(pos, q)
+    assert rel_rms(gq0, 1.3 * ref["phi"]) <= tol
+    assert rel_rms(gpos0, -1.3 * ref["F"]) <= tol
+
+
+def test_backward_finite_differences_fp64():
+    """Central differences of L = gE E + sum v.F evaluated by the GPU forward
+    itself, against the GPU backward (FP64 path)."""
+    import torch
+    box, per, p, h, a, L = (10.0, 10.0, 10.0), (1, 1, 1), 4, 0.625, 3.5, 3
+    n = 120
+    pos, q = WL.gaussian_charges(n, box, 0.5, seed=77)
+    v = WL.force_cotangent(n, seed=40)
+    gE = 0.9
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP64, n)
+    gpos, gq = _gpu_fwd_bwd(plan, pos, q, gE, v)
+
+    def Lval(pp, qq):
+        P = torch.tensor(pp, dtype=torch.float64, device="cuda")
+        Q = torch.tensor(qq, dtype=torch.float64, device="cuda")
+        E, F, _ = plan.energy_forces(P, Q)
+        return gE * E.item() + float(np.sum(v * F.cpu().numpy()))
+
+    eps = 1e-5
+    rng = np.random.default_rng(5)
+    for i in rng.choice(n, 16, replace=False):
+        for k in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[i, k] += eps
+            pm[i, k] -= eps
+            fd = (Lval(pp, q) - Lval(pm, q)) / (2 * eps)
+            assert gpos[i, k] == pytest.approx(fd, rel=1e-6, abs=1e-7)
+        qp, qm = q.copy(), q.copy()
+        qp[i] += eps
+        qm[i] -= eps
+        fdq = (Lval(pos, qp) - Lval(pos, qm)) / (2 * eps)
+        assert gq[i] == pytest.approx(fdq, rel=1e-6, abs=1e-7)
+
+
+def test_autograd_gradcheck_fp64():
+    import torch
+    box, per, p, h, a, L = (9.0, 9.0, 9.0), (0, 0, 0), 4, 1.0, 3.0, 2
+    n = 12
+    pos, q = WL.gaussian_charges(n, box, 0.5, seed=3)
+    pos = 0.5 + pos * (8.0 / 9.0)
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP64, n)
+    P = torch.tensor(pos, dtype=torch.float64, device="cuda", requires_grad=True)
+    Q = torch.tensor(q, dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def f(pp, qq):
+        E, F, _ = msm.energy_forces(pp, qq, plan)
+        return E, F
+
+    assert torch.autograd.gradcheck(f, (P, Q), eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+@pytest.mark.parametrize("cfg,scale", [(4, 0.04)])
+def test_config4_autograd_vs_oracle(cfg, scale):
+    """The differentiation workload (learnable Gaussian charges, periodic) at
+    reduced size: autograd of a force-matching loss vs the oracle adjoint."""
+    import torch
+    pos, q, box, per, p, h, a, L, fp64 = config_case(cfg, scale)
+    pos, q = cast(pos, q, False)
+    n = len(q)
+    v = WL.force_cotangent(n, seed=40).astype(np.float32).astype(np.float64)
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP32, n)
+    P = torch.tensor(pos, dtype=torch.float32, device="cuda", requires_grad=True)
+    Q = torch.tensor(q, dtype=torch.float32, device="cuda", requires_grad=True)
+    E, F, _ = msm.energy_forces(P, Q, plan)
+    loss = E.sum() + (F * torch.tensor(v, dtype=torch.float32, device="cuda")).sum()
+    loss.backward()
+    rq, rpos = O.OracleMSM(box, per, p, h, a, L).backward(pos, q, 1.0, v)
+    e_pos = rel_rms(P.grad.double().cpu().numpy(), rpos)
+    e_q = rel_rms(Q.grad.double().cpu().numpy(), rq)
+    print(f"config4 reduced n={n}: grad_pos rel={e_pos:.2e} grad_q rel={e_q:.2e}", flush=True)
+    assert e_pos <= TOL["fp32"]["F"] and e_q <= TOL["fp32"]["F"]
