@@ -160,8 +160,14 @@ msm_status msm_plan_get_grid(msm_plan plan, int level, int which, void* dst, voi
 msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const double* boxes,
                                  const int* levels, int order, double h, double cutoff_a,
                                  int precision, int max_total_n, int quasi_degree_M);
-/* offsets: device int32 [n_sys+1] CSR ranges into pos/q/forces/dEdq;
- * energies: device double [n_sys]. */
+/* offsets: device int32 [n_sys+1] CSR ranges into pos/q/forces/dEdq, with
+ * offsets[0] = 0, non-decreasing, offsets[n_sys] <= max_total_n (checked on the
+ * device: malformed offsets set the sticky flag, msm_plan_status then returns
+ * MSM_ERR_INVALID_ARG); energies: device double [n_sys].  Positions of system s
+ * must lie in [0, boxes[s]]^3.  The launch sequence is captured in a hipGraph
+ * on the first call and replayed while the pointers and stream stay the same
+ * (MSM_BATCH_GRAPH=0 launches directly).  The conv tile shape is chosen at
+ * plan creation by timing the candidates; msm_plan_describe reports it. */
 msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void* pos,
                                    const void* q, double* energies, void* forces, void* dEdq,
                                    void* stream);

@@ -14,95 +14,11 @@
 #include "kernels.hpp"
 #include "msm.h"
 #include "plan.hpp"
+#include "plan_state.hpp"
 
 using namespace msm;
 
-// Event-pair stage timer (enabled by msm_plan_set_profiling).
-struct StageProfiler {
-  bool on = false;
-  struct Pending {
-    std::string stage;
-    hipEvent_t a, b;
-  };
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> pool;
-  std::map<std::string, std::pair<double, long>> total;
-  hipEvent_t get() {
-    hipEvent_t e = nullptr;
-    if (!pool.empty()) {
-      e = pool.back();
-      pool.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
-      e = nullptr;
-    }
-    return e;
-  }
-  // returns an index to close with end(), or -1 when off
-  int begin(const char* stage, hipStream_t s) {
-    if (!on) return -1;
-    Pending p{stage, get(), get()};
-    if (!p.a || !p.b) return -1;
-    (void)hipEventRecord(p.a, s);
-    pending.push_back(p);
-    return (int)pending.size() - 1;
-  }
-  void end(int idx, hipStream_t s) {
-    if (idx >= 0) (void)hipEventRecord(pending[idx].b, s);
-  }
-  void collect() {
-    for (auto& p : pending) {
-      float ms = 0.f;
-      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-        auto& t = total[p.stage];
-        t.first += ms;
-        t.second += 1;
-      }
-      pool.push_back(p.a);
-      pool.push_back(p.b);
-    }
-    pending.clear();
-  }
-  ~StageProfiler() {
-    for (auto& p : pending) {
-      (void)hipEventDestroy(p.a);
-      (void)hipEventDestroy(p.b);
-    }
-    for (auto e : pool) (void)hipEventDestroy(e);
-  }
-};
-
-struct msm_plan_s {
-  HostPlan hp;
-  StageProfiler prof;
-  bool device = false;
-  bool batch = false;
-  int ncell = 0;
-  // device buffers (T = plan precision)
-  void* K[kMaxLevels] = {};
-  double* K64[kMaxLevels] = {};
-  int2* rowext[kMaxLevels] = {};
-  void* qg[kMaxLevels] = {};
-  void* eg[kMaxLevels] = {};
-  // factored levels: FP64 k-samples, their row extents, FP64 partial grid
-  double* S[kMaxLevels] = {};
-  int2* srowext[kMaxLevels] = {};
-  double* ug[kMaxLevels] = {};
-  void* Jd = nullptr;
-  int* cell_of = nullptr;
-  int* rank = nullptr;
-  int* counts = nullptr;
-  int* start = nullptr;
-  int* perm = nullptr;
-  void* wrapped = nullptr;
-  void* sorted = nullptr;
-  void* phi0 = nullptr;
-  void* F0 = nullptr;
-  int* flag = nullptr;
-  std::vector<void*> allocs;
-};
-
-namespace {
-
+namespace msm {
 msm_status hip_alloc(msm_plan P, void** ptr, size_t bytes) {
   *ptr = nullptr;
   if (bytes == 0) bytes = 16;
@@ -114,6 +30,9 @@ msm_status hip_alloc(msm_plan P, void** ptr, size_t bytes) {
   P->allocs.push_back(*ptr);
   return MSM_OK;
 }
+}  // namespace msm
+
+namespace {
 
 template <typename T>
 GridDev<T> grid_dev(const HostPlan& hp, int level) {
@@ -240,6 +159,7 @@ msm_status upload_plan(msm_plan P) {
 void free_plan(msm_plan P) {
   if (!P) return;
   if (P->device) (void)hipDeviceSynchronize();
+  if (P->bs) destroy_batch(P->bs);
   for (void* p : P->allocs) (void)hipFree(p);
   delete P;
 }
@@ -495,7 +415,7 @@ msm_status msm_plan_describe(msm_plan plan, char* json, size_t cap) {
   if (!plan || !json || cap == 0) return MSM_ERR_INVALID_ARG;
   std::string s;
   try {
-    s = describe_json(plan->hp);
+    s = plan->batch ? describe_batch(*plan->bs) : describe_json(plan->hp);
   } catch (...) {
     return MSM_ERR_OOM;
   }
@@ -575,6 +495,7 @@ msm_status msm_plan_status(msm_plan plan, void* stream) {
     if (hipMemset(plan->flag, 0, sizeof(int)) != hipSuccess) return MSM_ERR_HIP;
     if (hipDeviceSynchronize() != hipSuccess) return MSM_ERR_HIP;
   }
+  if (f & kFlagOffsets) return MSM_ERR_INVALID_ARG;
   if (f & kFlagNonfinite) return MSM_ERR_NONFINITE;
   if (f & kFlagDomain) return MSM_ERR_OUT_OF_DOMAIN;
   return MSM_OK;

@@ -1,11 +1,931 @@
-// batch.hip -- batched evaluation of many independent systems.
+// batch.hip -- the MSM for many independent free-space systems at once.
+//
+// Sec. "Madelung constants" evaluates one model over many structures by
+// padding them to a common shape (vmap).  Here there is no padding: system s
+// keeps its own box, level count and grids, its particles are the CSR range
+// offsets[s]..offsets[s+1], and every stage is ONE launch over all systems:
+//   system ids -> pair sums (one workgroup per system, all pairs in LDS) ->
+//   anterpolation -> restriction -> stencil convolution (a task list of
+//   output tiles across systems; shared K^1, K^2 = K^1/2 and one dense top
+//   table per level count) -> prolongation -> interpolation with per-system
+//   FP64 energies.
+// The launch sequence is captured once in a hipGraph and replayed; the conv
+// tile shape is chosen at plan time by timing the candidates (autotuner).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
 #include "msm.h"
-extern "C" msm_status msm_batch_plan_create(msm_plan* out, int, const double*, const int*, int,
-                                            double, double, int, int, int) {
-  if (out) *out = nullptr;
-  return MSM_ERR_UNSUPPORTED;
+#include "plan.hpp"
+#include "plan_state.hpp"
+
+namespace msm {
+
+struct ConvTask {
+  long long goff;  // grid offset of the system's level grid
+  int n;           // cubic grid size
+  int x0, y0, z;   // output tile origin
+};
+
+struct BatchConv {
+  int level;
+  int top;       // 1: dense top kernel of the systems whose top level is `level`
+  double scale;  // multiplies the stencil (K^l = K^1 / 2^(l-1))
+  int off, len;  // cubic stencil box: offsets off .. off+len-1 per axis
+  void* K = nullptr;
+  int2* rowext = nullptr;
+  ConvTask* tasks = nullptr;
+  int ntasks = 0;
+};
+
+struct BatchState {
+  int n_sys = 0, Lmax = 0, p = 0, M = 0, precision = 0, max_total_n = 0;
+  double h = 0, a = 0, self_const = 0;
+  double gcoef[kMaxOrder] = {};
+  double J[kMaxOrder + 1] = {};
+  std::vector<double> omega, box;
+  std::vector<int> L;
+  std::vector<int> n[kMaxLevels];
+  std::vector<long long> goff[kMaxLevels];
+  long long Gtot[kMaxLevels] = {};
+  int* d_n[kMaxLevels] = {};
+  long long* d_goff[kMaxLevels] = {};
+  void* qcat[kMaxLevels] = {};
+  void* ecat[kMaxLevels] = {};
+  void* d_box = nullptr;
+  int* sys_of = nullptr;
+  void* phi0 = nullptr;
+  void* F0 = nullptr;
+  int* flag = nullptr;
+  std::vector<BatchConv> convs;
+  int tile_cfg = 0;
+  std::string tuning;
+  // graph cache
+  hipStream_t gstream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  const void* key[7] = {};
+};
+
+void destroy_batch(BatchState* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  delete b;
 }
-extern "C" msm_status msm_batch_energy_forces(msm_plan, const int*, const void*, const void*,
-                                              double*, void*, void*, void*) {
-  return MSM_ERR_UNSUPPORTED;
+
+// tile shapes the autotuner chooses from: (R outputs per thread, threads in x, in y)
+struct TileCfg {
+  int R, TXT, TYT;
+};
+static const TileCfg kTiles[3] = {{4, 4, 16}, {4, 8, 16}, {2, 8, 8}};
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__global__ void k_batch_sysid(int n_sys, const int* __restrict__ off, int max_n,
+                              int* __restrict__ sys_of, int* __restrict__ flag) {
+  const int s = blockIdx.x;
+  const int b = off[s], e = off[s + 1];
+  if (threadIdx.x == 0 && (b < 0 || e < b || e > max_n || (s == 0 && b != 0)))
+    atomicOr(flag, kFlagOffsets);
+  const int lo = max(b, 0), hi = min(e, max_n);
+  for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) sys_of[i] = s;
+}
+
+template <typename T>
+__device__ inline void load_clamped(const T* pos, int i, T box, T& x, T& y, T& z, int& bad) {
+  T v[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (!isfinite(v[k])) {
+      bad |= kFlagNonfinite;
+      v[k] = T(0);
+    }
+    if (v[k] < T(0) || v[k] > box) {
+      bad |= kFlagDomain;
+      v[k] = v[k] < T(0) ? T(0) : box;
+    }
+  }
+  x = v[0];
+  y = v[1];
+  z = v[2];
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(kPairThreads)
+    k_batch_pair(const int* __restrict__ off, int max_n, const T* __restrict__ pos,
+                 const T* __restrict__ q, const T* __restrict__ boxes, PairParams<T> pp,
+                 T* __restrict__ phi0, T* __restrict__ F0, int* __restrict__ flag) {
+  __shared__ vec4_t<T> tile[kPairThreads];
+  const int s = blockIdx.x;
+  const int b = max(off[s], 0), e = min(off[s + 1], max_n);
+  const T box = boxes[s];
+  int bad = 0;
+  for (int ib = b; ib < e; ib += kPairThreads) {
+    const int i = ib + (int)threadIdx.x;
+    const bool active = i < e;
+    T xi = 0, yi = 0, zi = 0, qi = 0;
+    if (active) {
+      load_clamped(pos, i, box, xi, yi, zi, bad);
+      qi = q[i];
+      if (!isfinite(qi)) {
+        bad |= kFlagNonfinite;
+        qi = T(0);
+      }
+    }
+    T ph = 0, fx = 0, fy = 0, fz = 0;
+    for (int jb = b; jb < e; jb += kPairThreads) {
+      __syncthreads();
+      const int j = jb + (int)threadIdx.x;
+      if (j < e) {
+        vec4_t<T> t;
+        int dummy = 0;
+        load_clamped(pos, j, box, t.x, t.y, t.z, dummy);
+        T qj = q[j];
+        t.w = isfinite(qj) ? qj : T(0);
+        tile[threadIdx.x] = t;
+      }
+      __syncthreads();
+      const int cnt = min(kPairThreads, e - jb);
+      for (int jj = 0; jj < cnt; ++jj) {
+        const vec4_t<T> pj = tile[jj];
+        const T dx = xi - pj.x, dy = yi - pj.y, dz = zi - pj.z;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < pp.a2 && jb + jj != i) {
+          const T rinv = rsqrt_t(r2);
+          const T t = r2 * pp.inv_a2;
+          T Pt = pp.c[P - 1], dP = pp.dc[P - 2];
+#pragma unroll
+          for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
+#pragma unroll
+          for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
+          ph += pj.w * (rinv - Pt * pp.inv_a);
+          const T fs = pj.w * (rinv * rinv * rinv + T(2) * dP * pp.inv_a3);
+          fx += fs * dx;
+          fy += fs * dy;
+          fz += fs * dz;
+        }
+      }
+    }
+    if (active) {
+      phi0[i] = ph;
+      F0[3 * i] = qi * fx;
+      F0[3 * i + 1] = qi * fy;
+      F0[3 * i + 2] = qi * fz;
+    }
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+template <typename T, int P>
+__global__ void k_batch_anterp(const int* __restrict__ off, int n_sys, int max_n,
+                               const T* __restrict__ pos, const T* __restrict__ q,
+                               const int* __restrict__ sys_of, const T* __restrict__ boxes,
+                               const int* __restrict__ n1, const long long* __restrict__ goff1,
+                               T h, T* __restrict__ grid) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = min(max(off[n_sys], 0), max_n);
+  if (i >= total) return;
+  const int s = sys_of[i];
+  if (s < 0 || s >= n_sys) return;
+  T xs[3];
+  int bad = 0;
+  load_clamped(pos, i, boxes[s], xs[0], xs[1], xs[2], bad);
+  T qi = q[i];
+  if (!isfinite(qi)) qi = T(0);
+  const int n = n1[s], lo = -P / 2 + 1;
+  T w[3][P];
+  int idx[3][P];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T f;
+    const int base = grid_coord(xs[k], h, f);
+    bspline_weights<P, T>(f, w[k], nullptr, nullptr);
+#pragma unroll
+    for (int j = 0; j < P; ++j) idx[k][j] = axis_index(base - P / 2 + 1 + j, n, lo, 0);
+  }
+  T* g = grid + goff1[s];
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    if (idx[2][c] < 0) continue;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      if (idx[1][b] < 0) continue;
+      const T wyz = qi * w[2][c] * w[1][b];
+      const long long row = ((long long)idx[2][c] * n + idx[1][b]) * n;
+#pragma unroll
+      for (int a = 0; a < P; ++a)
+        if (idx[0][a] >= 0) atomicAdd(&g[row + idx[0][a]], wyz * w[0][a]);
+    }
+  }
+}
+
+// system owning flat grid point gid (goff: n_sys+1 prefix offsets)
+__device__ inline int find_system(const long long* goff, int n_sys, long long gid) {
+  int lo = 0, hi = n_sys;  // goff[lo] <= gid < goff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (goff[mid] <= gid) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, int P>
+__global__ void k_batch_restrict(int n_sys, long long Gc, const long long* __restrict__ goff_c,
+                                 const int* __restrict__ n_c, const long long* __restrict__ goff_f,
+                                 const int* __restrict__ n_f, JTapsB<T> jt,
+                                 const T* __restrict__ qf, T* __restrict__ qc) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= Gc) return;
+  const int s = find_system(goff_c, n_sys, gid);
+  const int nc = n_c[s], nf = n_f[s];
+  const long long loc = gid - goff_c[s];
+  const int ic[3] = {(int)(loc % nc), (int)((loc / nc) % nc), (int)(loc / ((long long)nc * nc))};
+  const int lo = -P / 2 + 1;
+  int idx[3][P + 1];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int t = 0; t <= P; ++t) idx[k][t] = axis_index(2 * (ic[k] + lo) + t - P / 2, nf, lo, 0);
+  const T* f = qf + goff_f[s];
+  T sum = 0;
+#pragma unroll
+  for (int tz = 0; tz <= P; ++tz) {
+    if (idx[2][tz] < 0) continue;
+    T sy = 0;
+#pragma unroll
+    for (int ty = 0; ty <= P; ++ty) {
+      if (idx[1][ty] < 0) continue;
+      const T* row = f + ((long long)idx[2][tz] * nf + idx[1][ty]) * nf;
+      T sx = 0;
+#pragma unroll
+      for (int tx = 0; tx <= P; ++tx)
+        if (idx[0][tx] >= 0) sx += jt.J[tx] * row[idx[0][tx]];
+      sy += jt.J[ty] * sx;
+    }
+    sum += jt.J[tz] * sy;
+  }
+  qc[gid] = sum;
+}
+
+template <typename T, int P>
+__global__ void k_batch_prolong(int n_sys, long long Gf, const long long* __restrict__ goff_f,
+                                const int* __restrict__ n_f, const long long* __restrict__ goff_c,
+                                const int* __restrict__ n_c, JTapsB<T> jt,
+                                const T* __restrict__ ec, T* __restrict__ ef) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= Gf) return;
+  const int s = find_system(goff_f, n_sys, gid);
+  const int nf = n_f[s], nc = n_c[s];
+  if (nc == 0) return;  // this system's top level is the fine level
+  const long long loc = gid - goff_f[s];
+  const int im[3] = {(int)(loc % nf), (int)((loc / nf) % nf), (int)(loc / ((long long)nf * nf))};
+  const int lo = -P / 2 + 1;
+  constexpr int NC = P / 2 + 1;
+  int idx[3][NC];
+  T wt[3][NC];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int m = im[k] + lo;
+    const int v = -(m - P / 2);
+    const int n_lo = -(v >= 0 ? v / 2 : -((-v + 1) / 2));  // ceil((m - P/2)/2)
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const int nn = n_lo + t;
+      const int kk = m - 2 * nn;
+      if (kk >= -P / 2 && kk <= P / 2) {
+        idx[k][t] = axis_index(nn, nc, lo, 0);
+        wt[k][t] = jt.J[kk + P / 2];
+      } else {
+        idx[k][t] = -1;
+        wt[k][t] = 0;
+      }
+    }
+  }
+  const T* c = ec + goff_c[s];
+  T sum = 0;
+#pragma unroll
+  for (int tz = 0; tz < NC; ++tz) {
+    if (idx[2][tz] < 0) continue;
+    T sy = 0;
+#pragma unroll
+    for (int ty = 0; ty < NC; ++ty) {
+      if (idx[1][ty] < 0) continue;
+      const T* row = c + ((long long)idx[2][tz] * nc + idx[1][ty]) * nc;
+      T sx = 0;
+#pragma unroll
+      for (int tx = 0; tx < NC; ++tx)
+        if (idx[0][tx] >= 0) sx += wt[0][tx] * row[idx[0][tx]];
+      sy += wt[1][ty] * sx;
+    }
+    sum += wt[2][tz] * sy;
+  }
+  ef[gid] += sum;
+}
+
+constexpr int kBConvCH = 8;
+
+// Stencil convolution over a task list: each workgroup computes one output
+// tile (one z plane) of one system's grid, all stencil planes; free axes.
+template <typename T, int R, int TXT, int TYT>
+__global__ void __launch_bounds__(TXT * TYT)
+    k_batch_conv(const ConvTask* __restrict__ tasks, int off, int len, int lds_w, T scale,
+                 const T* __restrict__ K, const int2* __restrict__ rowext,
+                 const T* __restrict__ qcat, T* __restrict__ ecat) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const ConvTask tk = tasks[blockIdx.x];
+  const int n = tk.n;
+  const int tx = threadIdx.x % TXT, ty = threadIdx.x / TXT;
+  const int LW = lds_w, LH = TYT + len - 1;
+  const int xs = tk.x0 - (off + len - 1), ys = tk.y0 - (off + len - 1);
+  const T* q = qcat + tk.goff;
+  T total[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) total[r] = 0;
+  for (int jz = 0; jz < len; ++jz) {
+    const int zi = tk.z - (off + jz);
+    if (zi < 0 || zi >= n) continue;  // uniform over the workgroup
+    __syncthreads();
+    const T* qz = q + (long long)zi * n * n;
+    for (int idx = threadIdx.x; idx < LW * LH; idx += TXT * TYT) {
+      const int ry = idx / LW, rx = idx - ry * LW;
+      const int yi = ys + ry, xi = xs + rx;
+      lds[idx] = (yi >= 0 && yi < n && xi >= 0 && xi < n) ? qz[(long long)yi * n + xi] : T(0);
+    }
+    __syncthreads();
+    const T* Kz = K + (long long)jz * len * len;
+    const int2* ext_z = rowext + jz * len;
+    // rows whose input y lies inside the grid for some output row of the tile
+    const int jy_lo = max(0, tk.y0 - off - (n - 1));
+    const int jy_hi = min(len - 1, tk.y0 + TYT - 1 - off);
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0;
+    for (int jy = jy_lo; jy <= jy_hi; ++jy) {
+      int2 ext = ext_z[jy];
+      // x offsets whose inputs can lie inside the grid for this tile
+      ext.x = max(ext.x, tk.x0 - off - (n - 1));
+      ext.y = min(ext.y, tk.x0 + TXT * R - 1 - off);
+      if (ext.x > ext.y) continue;
+      const T* lrow = lds + (ty - jy + len - 1) * LW + tx * R;
+      const T* Krow = Kz + jy * len;
+      int jx = ext.x;
+      for (; jx + kBConvCH - 1 <= ext.y; jx += kBConvCH) {
+        T win[kBConvCH + R - 1];
+        const T* wp = lrow + (len - jx - kBConvCH);
+#pragma unroll
+        for (int u = 0; u < kBConvCH + R - 1; ++u) win[u] = wp[u];
+#pragma unroll
+        for (int c = 0; c < kBConvCH; ++c) {
+          const T kv = Krow[jx + c];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r] = fma(kv, win[kBConvCH - 1 - c + r], acc[r]);
+        }
+      }
+      for (; jx <= ext.y; ++jx) {
+        const T kv = Krow[jx];
+        const T* wp = lrow + (len - 1 - jx);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fma(kv, wp[r], acc[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) total[r] += acc[r];
+  }
+  const int y = tk.y0 + ty;
+  if (y < n) {
+    T* erow = ecat + tk.goff + ((long long)tk.z * n + y) * n;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int x = tk.x0 + tx * R + r;
+      if (x < n) erow[x] = scale * total[r];
+    }
+  }
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+    k_batch_interp(const int* __restrict__ off, int n_sys, int max_n, const T* __restrict__ pos,
+                   const T* __restrict__ q, const int* __restrict__ sys_of,
+                   const T* __restrict__ boxes, const int* __restrict__ n1,
+                   const long long* __restrict__ goff1, T h, T inv_h,
+                   const T* __restrict__ ecat1, const T* __restrict__ phi0,
+                   const T* __restrict__ F0, T self_const, T* __restrict__ dEdq,
+                   T* __restrict__ F, double* __restrict__ energies) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = min(max(off[n_sys], 0), max_n);
+  if (i >= total) return;
+  const int s = sys_of[i];
+  if (s < 0 || s >= n_sys) return;
+  T xs[3];
+  int bad = 0;
+  load_clamped(pos, i, boxes[s], xs[0], xs[1], xs[2], bad);
+  T qi = q[i];
+  if (!isfinite(qi)) qi = T(0);
+  const int n = n1[s], lo = -P / 2 + 1;
+  T w[3][P], dw[3][P];
+  int idx[3][P];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T f;
+    const int base = grid_coord(xs[k], h, f);
+    bspline_weights<P, T>(f, w[k], dw[k], nullptr);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      idx[k][j] = axis_index(base - P / 2 + 1 + j, n, lo, 0);
+      dw[k][j] *= inv_h;
+    }
+  }
+  const T* e1 = ecat1 + goff1[s];
+  T v = 0, gx = 0, gy = 0, gz = 0;
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    if (idx[2][c] < 0) continue;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      if (idx[1][b] < 0) continue;
+      const long long row = ((long long)idx[2][c] * n + idx[1][b]) * n;
+      T sv = 0, sd = 0;
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        if (idx[0][a] < 0) continue;
+        const T e = e1[row + idx[0][a]];
+        sv += e * w[0][a];
+        sd += e * dw[0][a];
+      }
+      v += sv * w[1][b] * w[2][c];
+      gx += sd * w[1][b] * w[2][c];
+      gy += sv * dw[1][b] * w[2][c];
+      gz += sv * w[1][b] * dw[2][c];
+    }
+  }
+  const T phi = phi0[i] + v - qi * self_const;
+  if (dEdq) dEdq[i] = phi;
+  if (F) {
+    F[3 * i] = F0[3 * i] - qi * gx;
+    F[3 * i + 1] = F0[3 * i + 1] - qi * gy;
+    F[3 * i + 2] = F0[3 * i + 2] - qi * gz;
+  }
+  atomicAdd(&energies[s], 0.5 * (double)qi * (double)phi);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <typename T>
+static void launch_batch_conv(const BatchConv& bc, int cfg, const T* qcat, T* ecat,
+                              hipStream_t s) {
+  if (bc.ntasks <= 0) return;
+  const TileCfg tc = kTiles[cfg];
+  int lds_w = tc.TXT * tc.R + bc.len - 1;
+  if (sizeof(T) == 4) lds_w |= 1;
+  const size_t lds = (size_t)lds_w * (tc.TYT + bc.len - 1) * sizeof(T);
+  const T scale = (T)bc.scale;
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((k_batch_conv<T, 4, 4, 16>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, (const T*)bc.K, bc.rowext, qcat, ecat); break;
+    case 1: hipLaunchKernelGGL((k_batch_conv<T, 4, 8, 16>), dim3(bc.ntasks), dim3(128), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, (const T*)bc.K, bc.rowext, qcat, ecat); break;
+    default: hipLaunchKernelGGL((k_batch_conv<T, 2, 8, 8>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, (const T*)bc.K, bc.rowext, qcat, ecat); break;
+  }
+}
+
+static std::vector<ConvTask> build_tasks(const BatchState& B, int level, int top, int cfg) {
+  std::vector<ConvTask> t;
+  const int TXo = kTiles[cfg].TXT * kTiles[cfg].R, TY = kTiles[cfg].TYT;
+  for (int s = 0; s < B.n_sys; ++s) {
+    if (level > B.L[s]) continue;
+    if ((B.L[s] == level) != (top != 0)) continue;
+    const int n = B.n[level - 1][s];
+    for (int z = 0; z < n; ++z)
+      for (int y0 = 0; y0 < n; y0 += TY)
+        for (int x0 = 0; x0 < n; x0 += TXo) t.push_back({B.goff[level - 1][s], n, x0, y0, z});
+  }
+  return t;
+}
+
+template <typename T>
+static msm_status upload_stencil(msm_plan P, const std::vector<double>& K, int len, void** dK,
+                                 int2** dext) {
+  std::vector<T> kt(K.size());
+  for (size_t i = 0; i < K.size(); ++i) kt[i] = (T)K[i];
+  std::vector<int2> ext((size_t)len * len);
+  for (int z = 0; z < len; ++z)
+    for (int y = 0; y < len; ++y) {
+      int first = len, last = -1;
+      for (int x = 0; x < len; ++x)
+        if (kt[((size_t)z * len + y) * len + x] != T(0)) {
+          first = std::min(first, x);
+          last = x;
+        }
+      ext[(size_t)z * len + y] = make_int2(first, last);
+    }
+  msm_status st;
+  if ((st = hip_alloc(P, dK, kt.size() * sizeof(T)))) return st;
+  if ((st = hip_alloc(P, (void**)dext, ext.size() * sizeof(int2)))) return st;
+  if (hipMemcpy(*dK, kt.data(), kt.size() * sizeof(T), hipMemcpyHostToDevice) ||
+      hipMemcpy(*dext, ext.data(), ext.size() * sizeof(int2), hipMemcpyHostToDevice))
+    return MSM_ERR_HIP;
+  return MSM_OK;
+}
+
+template <typename T>
+static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const T* q,
+                                double* energies, T* F, T* dEdq, hipStream_t s) {
+  BatchState& B = *P->bs;
+  const int p = B.p, NS = B.n_sys, maxn = B.max_total_n;
+  launch_fill<int>(B.sys_of, std::max(maxn, 1), -1, s);
+  launch_fill<T>((T*)B.qcat[0], B.Gtot[0], T(0), s);
+  launch_fill<double>(energies, NS, 0.0, s);
+  hipLaunchKernelGGL(k_batch_sysid, dim3(NS), dim3(256), 0, s, NS, off, maxn, B.sys_of, B.flag);
+  PairParams<T> pp;
+  const double a = B.a;
+  pp.a2 = (T)(a * a);
+  pp.inv_a2 = (T)(1.0 / (a * a));
+  pp.inv_a = (T)(1.0 / a);
+  pp.inv_a3 = (T)(1.0 / (a * a * a));
+  pp.inv_a5 = (T)(1.0 / (a * a * a * a * a));
+  for (int k = 0; k < 8; ++k) {
+    pp.c[k] = k < p ? (T)B.gcoef[k] : T(0);
+    pp.dc[k] = (k + 1 < p) ? (T)((k + 1) * B.gcoef[k + 1]) : T(0);
+    pp.d2c[k] = 0;
+  }
+  for (int k = 0; k < 3; ++k) {
+    pp.box[k] = pp.inv_box[k] = 0;
+    pp.per[k] = 0;
+    pp.nc[k] = 1;
+  }
+  const T* boxes = (const T*)B.d_box;
+  int ev = P->prof.begin("batch_pair", s);
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_batch_pair<T, 4>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (T*)B.phi0, (T*)B.F0, B.flag); break;
+    case 6: hipLaunchKernelGGL((k_batch_pair<T, 6>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (T*)B.phi0, (T*)B.F0, B.flag); break;
+    default: hipLaunchKernelGGL((k_batch_pair<T, 8>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (T*)B.phi0, (T*)B.F0, B.flag); break;
+  }
+  P->prof.end(ev, s);
+  const int nb = (std::max(maxn, 1) + 255) / 256;
+  const T h = (T)B.h;
+  ev = P->prof.begin("batch_anterp", s);
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_batch_anterp<T, 4>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, (T*)B.qcat[0]); break;
+    case 6: hipLaunchKernelGGL((k_batch_anterp<T, 6>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, (T*)B.qcat[0]); break;
+    default: hipLaunchKernelGGL((k_batch_anterp<T, 8>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, (T*)B.qcat[0]); break;
+  }
+  P->prof.end(ev, s);
+  JTapsB<T> jt;
+  for (int k = 0; k < 9; ++k) jt.J[k] = k <= p ? (T)B.J[k] : T(0);
+  ev = P->prof.begin("batch_restrict", s);
+  for (int l = 1; l < B.Lmax; ++l) {
+    const long long Gc = B.Gtot[l];
+    if (Gc <= 0) continue;
+    const unsigned g = (unsigned)((Gc + 255) / 256);
+    switch (p) {
+      case 4: hipLaunchKernelGGL((k_batch_restrict<T, 4>), dim3(g), dim3(256), 0, s, NS, Gc, B.d_goff[l], B.d_n[l], B.d_goff[l - 1], B.d_n[l - 1], jt, (const T*)B.qcat[l - 1], (T*)B.qcat[l]); break;
+      case 6: hipLaunchKernelGGL((k_batch_restrict<T, 6>), dim3(g), dim3(256), 0, s, NS, Gc, B.d_goff[l], B.d_n[l], B.d_goff[l - 1], B.d_n[l - 1], jt, (const T*)B.qcat[l - 1], (T*)B.qcat[l]); break;
+      default: hipLaunchKernelGGL((k_batch_restrict<T, 8>), dim3(g), dim3(256), 0, s, NS, Gc, B.d_goff[l], B.d_n[l], B.d_goff[l - 1], B.d_n[l - 1], jt, (const T*)B.qcat[l - 1], (T*)B.qcat[l]); break;
+    }
+  }
+  P->prof.end(ev, s);
+  for (const BatchConv& bc : B.convs) {
+    ev = P->prof.begin(bc.level == 1 ? "batch_conv_l1" : (bc.top ? "batch_conv_top" : "batch_conv_l2+"), s);
+    launch_batch_conv<T>(bc, B.tile_cfg, (const T*)B.qcat[bc.level - 1], (T*)B.ecat[bc.level - 1], s);
+    P->prof.end(ev, s);
+  }
+  ev = P->prof.begin("batch_prolong", s);
+  for (int l = B.Lmax - 1; l >= 1; --l) {
+    const long long Gf = B.Gtot[l - 1];
+    if (Gf <= 0) continue;
+    const unsigned g = (unsigned)((Gf + 255) / 256);
+    switch (p) {
+      case 4: hipLaunchKernelGGL((k_batch_prolong<T, 4>), dim3(g), dim3(256), 0, s, NS, Gf, B.d_goff[l - 1], B.d_n[l - 1], B.d_goff[l], B.d_n[l], jt, (const T*)B.ecat[l], (T*)B.ecat[l - 1]); break;
+      case 6: hipLaunchKernelGGL((k_batch_prolong<T, 6>), dim3(g), dim3(256), 0, s, NS, Gf, B.d_goff[l - 1], B.d_n[l - 1], B.d_goff[l], B.d_n[l], jt, (const T*)B.ecat[l], (T*)B.ecat[l - 1]); break;
+      default: hipLaunchKernelGGL((k_batch_prolong<T, 8>), dim3(g), dim3(256), 0, s, NS, Gf, B.d_goff[l - 1], B.d_n[l - 1], B.d_goff[l], B.d_n[l], jt, (const T*)B.ecat[l], (T*)B.ecat[l - 1]); break;
+    }
+  }
+  P->prof.end(ev, s);
+  const T sc = (T)B.self_const, ih = (T)(1.0 / B.h);
+  ev = P->prof.begin("batch_interp", s);
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_batch_interp<T, 4>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, ih, (const T*)B.ecat[0], (const T*)B.phi0, (const T*)B.F0, sc, dEdq, F, energies); break;
+    case 6: hipLaunchKernelGGL((k_batch_interp<T, 6>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, ih, (const T*)B.ecat[0], (const T*)B.phi0, (const T*)B.F0, sc, dEdq, F, energies); break;
+    default: hipLaunchKernelGGL((k_batch_interp<T, 8>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, ih, (const T*)B.ecat[0], (const T*)B.phi0, (const T*)B.F0, sc, dEdq, F, energies); break;
+  }
+  P->prof.end(ev, s);
+  return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
+}
+
+// Times the level-1 convolution for every tile shape on the plan's (zero)
+// grids and keeps the fastest.
+template <typename T>
+static msm_status autotune(msm_plan P) {
+  BatchState& B = *P->bs;
+  hipStream_t s = nullptr;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) || hipEventCreate(&b)) return MSM_ERR_HIP;
+  BatchConv& l1 = B.convs[0];
+  float best = 1e30f;
+  int best_cfg = 0;
+  std::ostringstream log;
+  for (int cfg = 0; cfg < 3; ++cfg) {
+    std::vector<ConvTask> t = build_tasks(B, 1, 0, cfg);
+    ConvTask* dt = nullptr;
+    if (hipMalloc((void**)&dt, std::max<size_t>(t.size(), 1) * sizeof(ConvTask))) return MSM_ERR_OOM;
+    if (hipMemcpy(dt, t.data(), t.size() * sizeof(ConvTask), hipMemcpyHostToDevice)) return MSM_ERR_HIP;
+    BatchConv trial = l1;
+    trial.tasks = dt;
+    trial.ntasks = (int)t.size();
+    launch_batch_conv<T>(trial, cfg, (const T*)B.qcat[0], (T*)B.ecat[0], s);  // warm-up
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < 3; ++r)
+      launch_batch_conv<T>(trial, cfg, (const T*)B.qcat[0], (T*)B.ecat[0], s);
+    (void)hipEventRecord(b, s);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipFree(dt);
+    log << (cfg ? "," : "") << "{\"R\":" << kTiles[cfg].R << ",\"tx\":" << kTiles[cfg].TXT
+        << ",\"ty\":" << kTiles[cfg].TYT << ",\"ms\":" << ms / 3 << "}";
+    if (ms < best) {
+      best = ms;
+      best_cfg = cfg;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (hipGetLastError() != hipSuccess) return MSM_ERR_HIP;
+  B.tile_cfg = best_cfg;
+  B.tuning = "[" + log.str() + "]";
+  return MSM_OK;
+}
+
+template <typename T>
+static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1,
+                               const std::vector<std::vector<double>>& tops,
+                               const std::vector<int>& top_len) {
+  BatchState& B = *P->bs;
+  msm_status st;
+  for (int l = 1; l <= B.Lmax; ++l) {
+    const size_t g = (size_t)std::max<long long>(B.Gtot[l - 1], 1);
+    if ((st = hip_alloc(P, &B.qcat[l - 1], g * sizeof(T)))) return st;
+    if ((st = hip_alloc(P, &B.ecat[l - 1], g * sizeof(T)))) return st;
+    if ((st = hip_alloc(P, (void**)&B.d_n[l - 1], B.n_sys * sizeof(int)))) return st;
+    if ((st = hip_alloc(P, (void**)&B.d_goff[l - 1], (B.n_sys + 1) * sizeof(long long))))
+      return st;
+    if (hipMemcpy(B.d_n[l - 1], B.n[l - 1].data(), B.n_sys * sizeof(int), hipMemcpyHostToDevice) ||
+        hipMemcpy(B.d_goff[l - 1], B.goff[l - 1].data(), (B.n_sys + 1) * sizeof(long long),
+                  hipMemcpyHostToDevice))
+      return MSM_ERR_HIP;
+    launch_fill<T>((T*)B.qcat[l - 1], (long long)g, T(0), nullptr);
+    launch_fill<T>((T*)B.ecat[l - 1], (long long)g, T(0), nullptr);
+  }
+  std::vector<T> bx(B.n_sys);
+  for (int s = 0; s < B.n_sys; ++s) bx[s] = (T)B.box[s];
+  if ((st = hip_alloc(P, &B.d_box, B.n_sys * sizeof(T)))) return st;
+  if (hipMemcpy(B.d_box, bx.data(), B.n_sys * sizeof(T), hipMemcpyHostToDevice)) return MSM_ERR_HIP;
+  const size_t nmax = (size_t)std::max(B.max_total_n, 1);
+  if ((st = hip_alloc(P, (void**)&B.sys_of, nmax * sizeof(int)))) return st;
+  if ((st = hip_alloc(P, &B.phi0, nmax * sizeof(T)))) return st;
+  if ((st = hip_alloc(P, &B.F0, nmax * 3 * sizeof(T)))) return st;
+  if ((st = hip_alloc(P, (void**)&B.flag, sizeof(int)))) return st;
+  if (hipMemset(B.flag, 0, sizeof(int))) return MSM_ERR_HIP;
+  P->flag = B.flag;
+  // stencils: K^1 (intermediate levels, scaled per level) and the top tables
+  void* dK1 = nullptr;
+  int2* dK1ext = nullptr;
+  if ((st = upload_stencil<T>(P, K1, 2 * W1 + 1, &dK1, &dK1ext))) return st;
+  for (int l = 1; l <= B.Lmax; ++l) {
+    BatchConv inter;
+    inter.level = l;
+    inter.top = 0;
+    inter.scale = std::ldexp(1.0, -(l - 1));
+    inter.off = -W1;
+    inter.len = 2 * W1 + 1;
+    inter.K = dK1;
+    inter.rowext = dK1ext;
+    BatchConv top;
+    top.level = l;
+    top.top = 1;
+    top.scale = 1.0;
+    top.len = top_len[l];
+    top.off = -(top_len[l] - 1) / 2;
+    if (top_len[l] > 0) {
+      if ((st = upload_stencil<T>(P, tops[l], top_len[l], &top.K, &top.rowext))) return st;
+    }
+    for (BatchConv* bc : {&inter, &top}) {
+      if (bc->top && top_len[l] == 0) continue;
+      bool any = false;
+      for (int s = 0; s < B.n_sys; ++s)
+        if (l <= B.L[s] && ((B.L[s] == l) == (bc->top != 0))) any = true;
+      if (!any) continue;
+      int lw = kTiles[0].TXT * kTiles[0].R + bc->len - 1;
+      for (int c = 0; c < 3; ++c) {
+        int w = kTiles[c].TXT * kTiles[c].R + bc->len - 1;
+        if ((size_t)(w | 1) * (kTiles[c].TYT + bc->len - 1) * sizeof(T) > 160 * 1024)
+          return MSM_ERR_GRID;
+        (void)lw;
+      }
+      B.convs.push_back(*bc);
+    }
+  }
+  if (hipDeviceSynchronize()) return MSM_ERR_HIP;
+  // autotune the tile shape on the level-1 convolution, then build the task lists
+  if ((st = autotune<T>(P))) return st;
+  for (BatchConv& bc : B.convs) {
+    std::vector<ConvTask> t = build_tasks(B, bc.level, bc.top, B.tile_cfg);
+    if ((st = hip_alloc(P, (void**)&bc.tasks, std::max<size_t>(t.size(), 1) * sizeof(ConvTask))))
+      return st;
+    if (!t.empty() &&
+        hipMemcpy(bc.tasks, t.data(), t.size() * sizeof(ConvTask), hipMemcpyHostToDevice))
+      return MSM_ERR_HIP;
+    bc.ntasks = (int)t.size();
+  }
+  if (hipStreamCreateWithFlags(&B.gstream, hipStreamNonBlocking) ||
+      hipEventCreateWithFlags(&B.ev_fork, hipEventDisableTiming) ||
+      hipEventCreateWithFlags(&B.ev_join, hipEventDisableTiming))
+    return MSM_ERR_HIP;
+  return MSM_OK;
+}
+
+}  // namespace msm
+
+using namespace msm;
+
+extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const double* boxes,
+                                            const int* levels, int order, double h,
+                                            double cutoff_a, int precision, int max_total_n,
+                                            int quasi_degree_M) {
+  if (!out) return MSM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n_sys < 1 || !boxes || !levels || !(h > 0) || !(cutoff_a > 0) || max_total_n < 0)
+    return MSM_ERR_INVALID_ARG;
+  if (precision != MSM_FP32 && precision != MSM_FP64) return MSM_ERR_INVALID_ARG;
+  if (order != 4 && order != 6 && order != 8) return MSM_ERR_UNSUPPORTED;
+  const int M = quasi_degree_M < 0 ? order : quasi_degree_M;
+  if (M > 24) return MSM_ERR_INVALID_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return MSM_ERR_HIP;
+  }
+  msm_plan P = new (std::nothrow) msm_plan_s;
+  if (!P) return MSM_ERR_OOM;
+  P->batch = true;
+  P->device = true;
+  P->bs = new (std::nothrow) BatchState;
+  if (!P->bs) {
+    delete P;
+    return MSM_ERR_OOM;
+  }
+  BatchState& B = *P->bs;
+  msm_status st = MSM_OK;
+  try {
+    B.n_sys = n_sys;
+    B.p = order;
+    B.M = M;
+    B.h = h;
+    B.a = cutoff_a;
+    B.precision = precision;
+    B.max_total_n = max_total_n;
+    B.box.assign(boxes, boxes + n_sys);
+    B.L.assign(levels, levels + n_sys);
+    for (int s = 0; s < n_sys; ++s) {
+      if (!(B.box[s] > 0) || !std::isfinite(B.box[s]) || B.L[s] < 1 || B.L[s] > kMaxLevels)
+        st = MSM_ERR_INVALID_ARG;
+      B.Lmax = std::max(B.Lmax, B.L[s]);
+    }
+    if (st == MSM_OK) {
+      softener_coefficients(order, B.gcoef);
+      B.self_const = B.gcoef[0] / cutoff_a;
+      B.omega = quasi_sequence(order, M);
+      for (int k = 0; k <= order; ++k) {
+        double c = 1.0;
+        for (int i = 1; i <= k; ++i) c = c * (order - k + i) / i;
+        B.J[k] = std::ldexp(c, 1 - order);
+      }
+      for (int l = 1; l <= B.Lmax; ++l) {
+        B.n[l - 1].assign(n_sys, 0);
+        B.goff[l - 1].assign(n_sys + 1, 0);
+        long long acc = 0;
+        for (int s = 0; s < n_sys; ++s) {
+          B.goff[l - 1][s] = acc;
+          if (l <= B.L[s]) {
+            const double hl = std::ldexp(h, l - 1);
+            const int nn = (int)std::ceil(B.box[s] / hl - 1e-9) + order - 1;
+            if (nn > 512) st = MSM_ERR_GRID;
+            B.n[l - 1][s] = nn;
+            acc += (long long)nn * nn * nn;
+          }
+        }
+        B.goff[l - 1][n_sys] = acc;
+        B.Gtot[l - 1] = acc;
+      }
+    }
+    std::vector<double> K1;
+    int W[3] = {0, 0, 0};
+    std::vector<std::vector<double>> tops(kMaxLevels + 1);
+    std::vector<int> top_len(kMaxLevels + 1, 0);
+    if (st == MSM_OK) {
+      const double h3[3] = {h, h, h};
+      level1_stencil(order, M, cutoff_a, h3, W, K1, B.gcoef);
+      for (int l = 1; l <= B.Lmax; ++l) {
+        int nmax = 0;
+        for (int s = 0; s < n_sys; ++s)
+          if (B.L[s] == l) nmax = std::max(nmax, B.n[l - 1][s]);
+        if (!nmax) continue;
+        const double hl = std::ldexp(h, l - 1);
+        const double hl3[3] = {hl, hl, hl};
+        const int n3[3] = {nmax, nmax, nmax};
+        free_top_kernel(order, M, cutoff_a, l, hl3, n3, B.omega, B.gcoef, tops[l]);
+        top_len[l] = 2 * nmax - 1;
+      }
+      st = precision == MSM_FP64 ? upload_batch<double>(P, K1, W[0], tops, top_len)
+                                 : upload_batch<float>(P, K1, W[0], tops, top_len);
+    }
+  } catch (...) {
+    st = MSM_ERR_OOM;
+  }
+  if (st != MSM_OK) {
+    msm_plan_destroy(P);
+    return st;
+  }
+  *out = P;
+  return MSM_OK;
+}
+
+extern "C" msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void* pos,
+                                              const void* q, double* energies, void* forces,
+                                              void* dEdq, void* stream) {
+  if (!plan || !plan->batch || !plan->bs) return MSM_ERR_INVALID_ARG;
+  if (!offsets || !pos || !q || !energies) return MSM_ERR_INVALID_ARG;
+  BatchState& B = *plan->bs;
+  hipStream_t s = (hipStream_t)stream;
+  const void* key[7] = {offsets, pos, q, energies, forces, dEdq, (const void*)s};
+  const char* env = std::getenv("MSM_BATCH_GRAPH");
+  const bool use_graph = !(env && env[0] == '0') && !plan->prof.on;
+  auto enqueue = [&](hipStream_t st) {
+    return B.precision == MSM_FP64
+               ? enqueue_batch<double>(plan, offsets, (const double*)pos, (const double*)q,
+                                       energies, (double*)forces, (double*)dEdq, st)
+               : enqueue_batch<float>(plan, offsets, (const float*)pos, (const float*)q,
+                                      energies, (float*)forces, (float*)dEdq, st);
+  };
+  if (!use_graph) return enqueue(s);
+  if (!B.exec || std::memcmp(key, B.key, sizeof(key)) != 0) {
+    if (B.exec) {
+      (void)hipGraphExecDestroy(B.exec);
+      B.exec = nullptr;
+    }
+    if (B.graph) {
+      (void)hipGraphDestroy(B.graph);
+      B.graph = nullptr;
+    }
+    if (hipStreamBeginCapture(B.gstream, hipStreamCaptureModeThreadLocal)) return MSM_ERR_HIP;
+    msm_status st = enqueue(B.gstream);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(B.gstream, &g) || st != MSM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st != MSM_OK ? st : MSM_ERR_HIP;
+    }
+    B.graph = g;
+    if (hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0)) {
+      B.exec = nullptr;
+      return MSM_ERR_HIP;
+    }
+    std::memcpy(B.key, key, sizeof(key));
+  }
+  if (hipEventRecord(B.ev_fork, s) || hipStreamWaitEvent(B.gstream, B.ev_fork, 0) ||
+      hipGraphLaunch(B.exec, B.gstream) || hipEventRecord(B.ev_join, B.gstream) ||
+      hipStreamWaitEvent(s, B.ev_join, 0))
+    return MSM_ERR_HIP;
+  return MSM_OK;
+}
+
+// JSON of the batch plan (systems, grids, autotuner result) for describe.
+std::string describe_batch(const msm::BatchState& B) {
+  std::ostringstream o;
+  o.precision(17);
+  long long G1 = B.Gtot[0];
+  o << "{\"batch\":true,\"n_sys\":" << B.n_sys << ",\"order\":" << B.p << ",\"M\":" << B.M
+    << ",\"h\":" << B.h << ",\"cutoff\":" << B.a << ",\"max_levels\":" << B.Lmax
+    << ",\"precision\":\"" << (B.precision ? "fp64" : "fp32") << "\",\"grid1_points\":" << G1
+    << ",\"tile_cfg\":" << B.tile_cfg << ",\"autotune\":" << (B.tuning.empty() ? "[]" : B.tuning)
+    << ",\"convs\":[";
+  for (size_t i = 0; i < B.convs.size(); ++i)
+    o << (i ? "," : "") << "{\"level\":" << B.convs[i].level << ",\"top\":" << B.convs[i].top
+      << ",\"len\":" << B.convs[i].len << ",\"tasks\":" << B.convs[i].ntasks << "}";
+  o << "]}";
+  return o.str();
 }

@@ -39,6 +39,12 @@ struct ConvParams {
   int small;            // 16 x 16 tiles (else 64 x 32)
 };
 
+// restriction taps J_{-p/2..p/2} passed by value
+template <typename T>
+struct JTapsB {
+  T J[9];
+};
+
 // omega' applied axis by axis (second half of the factored stencil).
 struct OmegaParams {
   int n[3];      // output grid

@@ -1,0 +1,113 @@
+// plan_state.hpp -- the opaque msm_plan object shared by the C-ABI files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "msm.h"
+#include "plan.hpp"
+
+namespace msm {
+struct BatchState;  // batch.hip
+void destroy_batch(BatchState* b);
+// sticky device error bits: 1 domain, 2 non-finite, 4 malformed batch offsets
+constexpr int kFlagOffsets = 4;
+}  // namespace msm
+
+// Event-pair stage timer (enabled by msm_plan_set_profiling).
+struct StageProfiler {
+  bool on = false;
+  struct Pending {
+    std::string stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<double, long>> total;
+  hipEvent_t get() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  // returns an index to close with end(), or -1 when off
+  int begin(const char* stage, hipStream_t s) {
+    if (!on) return -1;
+    Pending p{stage, get(), get()};
+    if (!p.a || !p.b) return -1;
+    (void)hipEventRecord(p.a, s);
+    pending.push_back(p);
+    return (int)pending.size() - 1;
+  }
+  void end(int idx, hipStream_t s) {
+    if (idx >= 0) (void)hipEventRecord(pending[idx].b, s);
+  }
+  void collect() {
+    for (auto& p : pending) {
+      float ms = 0.f;
+      if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        auto& t = total[p.stage];
+        t.first += ms;
+        t.second += 1;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+  ~StageProfiler() {
+    for (auto& p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct msm_plan_s {
+  // batched plans (msm_batch_plan_create) keep their state here
+  msm::BatchState* bs = nullptr;
+  msm::HostPlan hp;
+  StageProfiler prof;
+  bool device = false;
+  bool batch = false;
+  int ncell = 0;
+  // device buffers (T = plan precision)
+  void* K[msm::kMaxLevels] = {};
+  double* K64[msm::kMaxLevels] = {};
+  int2* rowext[msm::kMaxLevels] = {};
+  void* qg[msm::kMaxLevels] = {};
+  void* eg[msm::kMaxLevels] = {};
+  // factored levels: FP64 k-samples, their row extents, FP64 partial grid
+  double* S[msm::kMaxLevels] = {};
+  int2* srowext[msm::kMaxLevels] = {};
+  double* ug[msm::kMaxLevels] = {};
+  void* Jd = nullptr;
+  int* cell_of = nullptr;
+  int* rank = nullptr;
+  int* counts = nullptr;
+  int* start = nullptr;
+  int* perm = nullptr;
+  void* wrapped = nullptr;
+  void* sorted = nullptr;
+  void* phi0 = nullptr;
+  void* F0 = nullptr;
+  int* flag = nullptr;
+  std::vector<void*> allocs;
+};
+
+
+namespace msm {
+// device allocation owned by the plan (freed with it)
+msm_status hip_alloc(msm_plan P, void** ptr, size_t bytes);
+}  // namespace msm
+std::string describe_batch(const msm::BatchState& B);

@@ -195,6 +195,50 @@ class Plan:
         return out
 
 
+class BatchPlan:
+    """Many free-space systems in one launch sequence (msm_batch_plan_create)."""
+
+    def __init__(self, boxes, levels, order, h, cutoff, precision=MSM_FP32, max_total_n=1,
+                 quasi_degree=-1):
+        import numpy as np
+        self._h = ctypes.c_void_p()
+        b = np.ascontiguousarray(boxes, dtype=np.float64)
+        lv = np.ascontiguousarray(levels, dtype=np.int32)
+        self.n_sys = len(b)
+        _check(lib().msm_batch_plan_create(ctypes.byref(self._h), self.n_sys,
+                                           b.ctypes.data_as(ctypes.c_void_p),
+                                           lv.ctypes.data_as(ctypes.c_void_p), int(order),
+                                           float(h), float(cutoff), int(precision),
+                                           int(max_total_n), int(quasi_degree)),
+               "msm_batch_plan_create")
+        self.precision = int(precision)
+
+    close = Plan.close
+    __del__ = Plan.__del__
+    dtype = Plan.dtype
+    describe = Plan.describe
+    status = Plan.status
+    set_profiling = Plan.set_profiling
+    profile = Plan.profile
+
+    def energy_forces(self, offsets, pos, q, stream=None, out=None):
+        """offsets: int32 cuda [n_sys+1]; returns (energies f64 [n_sys], F, dEdq)."""
+        import torch
+        n = q.shape[0]
+        assert offsets.dtype == torch.int32 and offsets.is_cuda
+        assert pos.dtype == self.dtype and q.dtype == self.dtype
+        if out is None:
+            E = torch.empty(self.n_sys, dtype=torch.float64, device=pos.device)
+            F = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+            dq = torch.empty(n, dtype=self.dtype, device=pos.device)
+        else:
+            E, F, dq = out
+        _check(lib().msm_batch_energy_forces(self._h, _ptr(offsets), _ptr(pos), _ptr(q), _ptr(E),
+                                             _ptr(F), _ptr(dq), _stream(stream)),
+               "msm_batch_energy_forces")
+        return E, F, dq
+
+
 def _autograd_function():
     import torch
 

@@ -1,0 +1,103 @@
+"""Batched path (many free-space systems, one launch sequence, hipGraph)
+against the oracle per system and against single-system plans."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_05961_amd import msm
+from paper_2510_05961_amd import workloads as WL
+
+from helpers import TOL, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(n_sys, seed):
+    off, boxes, pos, q = WL.clusters(n_sys, 2, 70, 6.0, 14.0, 0.5, seed)
+    levels = np.where(boxes <= 10.0, 2, 3).astype(np.int32)
+    return off, boxes, pos, q, levels
+
+
+def _run_batch(bp, off, pos, q):
+    import torch
+    dt = bp.dtype
+    O_ = torch.tensor(off, dtype=torch.int32, device="cuda")
+    P = torch.tensor(pos, dtype=dt, device="cuda")
+    Q = torch.tensor(q, dtype=dt, device="cuda")
+    E, F, dq = bp.energy_forces(O_, P, Q)
+    torch.cuda.synchronize()
+    return E.cpu().numpy(), F.double().cpu().numpy(), dq.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_batch_matches_oracle_per_system(fp64):
+    off, boxes, pos, q, levels = _small_batch(40, seed=11)
+    dt = np.float64 if fp64 else np.float32
+    pos, q = pos.astype(dt).astype(np.float64), q.astype(dt).astype(np.float64)
+    bp = msm.BatchPlan(boxes, levels, 4, 1.0, 3.0, msm.MSM_FP64 if fp64 else msm.MSM_FP32,
+                       int(off[-1]))
+    print(bp.describe(), flush=True)
+    E, F, dq = _run_batch(bp, off, pos, q)
+    assert bp.status() == 0
+    tol = TOL["fp64" if fp64 else "fp32"]
+    for s in range(len(boxes)):
+        a, b = off[s], off[s + 1]
+        b3 = (boxes[s],) * 3
+        ref = O.OracleMSM(b3, (0, 0, 0), 4, 1.0, 3.0, int(levels[s])).compute(pos[a:b], q[a:b])
+        if b - a >= 2:
+            assert rel_rms(F[a:b], ref["F"]) <= tol["F"], s
+        assert abs(E[s] - ref["E"]) <= tol["E"] * max(abs(ref["E"]), 1e-3), s
+        if b > a:
+            assert rel_rms(dq[a:b], ref["phi"]) <= tol["phi"], s
+
+
+def test_batch_equals_single_system_plans():
+    import torch
+    off, boxes, pos, q, levels = _small_batch(12, seed=12)
+    bp = msm.BatchPlan(boxes, levels, 4, 1.0, 3.0, msm.MSM_FP64, int(off[-1]))
+    E, F, dq = _run_batch(bp, off, pos, q)
+    for s in range(len(boxes)):
+        a, b = off[s], off[s + 1]
+        pl = msm.Plan((boxes[s],) * 3, 0, 4, 1.0, 3.0, int(levels[s]), msm.MSM_FP64, max(b - a, 1))
+        Es, Fs, dqs = pl.energy_forces(torch.tensor(pos[a:b], device="cuda"),
+                                       torch.tensor(q[a:b], device="cuda"))
+        assert E[s] == pytest.approx(Es.item(), rel=1e-11, abs=1e-12)
+        if b > a:
+            np.testing.assert_allclose(F[a:b], Fs.cpu().numpy(), rtol=1e-9, atol=1e-11)
+
+
+def test_batch_graph_replays_match_eager():
+    import torch
+    off, boxes, pos, q, levels = _small_batch(30, seed=13)
+    bp = msm.BatchPlan(boxes, levels, 4, 1.0, 3.0, msm.MSM_FP32, int(off[-1]))
+    O_ = torch.tensor(off, dtype=torch.int32, device="cuda")
+    P = torch.tensor(pos, dtype=torch.float32, device="cuda")
+    Q = torch.tensor(q, dtype=torch.float32, device="cuda")
+    os.environ["MSM_BATCH_GRAPH"] = "0"
+    try:
+        E0, F0, d0 = bp.energy_forces(O_, P, Q)
+        torch.cuda.synchronize()
+        E0, F0 = E0.clone(), F0.clone()
+    finally:
+        os.environ.pop("MSM_BATCH_GRAPH")
+    out = (torch.empty_like(E0), torch.empty_like(F0), torch.empty_like(d0))
+    for rep in range(4):
+        junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        bp.energy_forces(O_, P, Q, out=out)
+        torch.cuda.synchronize()
+        assert torch.allclose(out[0], E0, rtol=1e-5, atol=1e-6), rep
+        assert torch.allclose(out[1], F0, rtol=1e-4, atol=1e-5), rep
+        del junk
+
+
+def test_batch_malformed_offsets_flagged():
+    import torch
+    off, boxes, pos, q, levels = _small_batch(5, seed=14)
+    bp = msm.BatchPlan(boxes, levels, 4, 1.0, 3.0, msm.MSM_FP32, int(off[-1]))
+    bad = off.copy()
+    bad[2], bad[3] = bad[3], bad[2]  # decreasing range
+    _run_batch(bp, bad, pos, q)
+    assert bp.status() == 1
+    assert bp.status() == 0
