@@ -44,6 +44,7 @@ GridDev<T> grid_dev(const HostPlan& hp, int level) {
     d.per[k] = hp.periodic[k];
     d.h[k] = (T)g.h[k];
     d.inv_h[k] = (T)(1.0 / g.h[k]);
+    d.hd[k] = g.h[k];
   }
   return d;
 }
@@ -106,6 +107,27 @@ msm_status upload_plan(msm_plan P) {
       return MSM_ERR_HIP;
     if ((st = hip_alloc(P, &P->qg[l - 1], (size_t)g.G * sizeof(T)))) return st;
     if ((st = hip_alloc(P, &P->eg[l - 1], (size_t)g.G * sizeof(T)))) return st;
+    {
+      // FP64 accumulation buffer of the level's convolution and the row
+      // extents of the FP64 stencil it uses
+      std::vector<int2> e64((size_t)g.len[1] * g.len[2]);
+      for (int z = 0; z < g.len[2]; ++z)
+        for (int y = 0; y < g.len[1]; ++y) {
+          int first = g.len[0], last = -1;
+          for (int x = 0; x < g.len[0]; ++x)
+            if (g.K[((size_t)z * g.len[1] + y) * g.len[0] + x] != 0.0) {
+              first = std::min(first, x);
+              last = x;
+            }
+          e64[(size_t)z * g.len[1] + y] = make_int2(first, last);
+        }
+      if ((st = hip_alloc(P, (void**)&P->rowext64[l - 1], e64.size() * sizeof(int2)))) return st;
+      if (hipMemcpy(P->rowext64[l - 1], e64.data(), e64.size() * sizeof(int2),
+                    hipMemcpyHostToDevice))
+        return MSM_ERR_HIP;
+      const long long gbuf = std::max(g.G, g.factored ? g.Gext : 0LL);
+      if ((st = hip_alloc(P, (void**)&P->ug[l - 1], (size_t)gbuf * sizeof(double)))) return st;
+    }
     const int zero3[3] = {0, 0, 0};
     ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
     if (conv_lds_bytes(cp, sizeof(T)) > 160 * 1024) return MSM_ERR_GRID;
@@ -124,7 +146,6 @@ msm_status upload_plan(msm_plan P) {
           sext[(size_t)z * g.s_len[1] + y] = make_int2(first, last);
         }
       if ((st = hip_alloc(P, (void**)&P->srowext[l - 1], sext.size() * sizeof(int2)))) return st;
-      if ((st = hip_alloc(P, (void**)&P->ug[l - 1], (size_t)g.Gext * sizeof(double)))) return st;
       if (hipMemcpy(P->S[l - 1], g.S.data(), ss * sizeof(double), hipMemcpyHostToDevice) ||
           hipMemcpy(P->srowext[l - 1], sext.data(), sext.size() * sizeof(int2),
                     hipMemcpyHostToDevice))
@@ -148,7 +169,7 @@ msm_status upload_plan(msm_plan P) {
   if ((st = hip_alloc(P, (void**)&P->perm, nmax * sizeof(int)))) return st;
   if ((st = hip_alloc(P, &P->wrapped, nmax * 4 * sizeof(T)))) return st;
   if ((st = hip_alloc(P, &P->sorted, nmax * 4 * sizeof(T)))) return st;
-  if ((st = hip_alloc(P, &P->phi0, nmax * sizeof(T)))) return st;
+  if ((st = hip_alloc(P, &P->phi0, nmax * sizeof(double)))) return st;
   if ((st = hip_alloc(P, &P->F0, nmax * 3 * sizeof(T)))) return st;
   if ((st = hip_alloc(P, (void**)&P->flag, sizeof(int)))) return st;
   if (hipMemset(P->flag, 0, sizeof(int))) return MSM_ERR_HIP;
@@ -227,9 +248,13 @@ void grid_pass(msm_plan P, hipStream_t s) {
       for (int k = 0; k < 25; ++k) op.omega[k] = k <= hp.M ? hp.omega[k] : 0.0;
       launch_omega<T>(op, P->ug[l - 1], (T*)P->eg[l - 1], s);
     } else {
+      // direct stencil, accumulated in FP64 (sums of thousands of terms with
+      // cancellation), then rounded to the grid precision
       ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
-      launch_conv<T, T>(cp, (const T*)P->K[l - 1], P->rowext[l - 1], (const T*)P->qg[l - 1],
-                        (T*)P->eg[l - 1], s);
+      if (cp.nsplit > 1) launch_fill<double>(P->ug[l - 1], g.G, 0.0, s);
+      launch_conv<T, double>(cp, P->K64[l - 1], P->rowext64[l - 1], (const T*)P->qg[l - 1],
+                             P->ug[l - 1], s);
+      launch_cast<T>(P->ug[l - 1], (T*)P->eg[l - 1], g.G, s);
     }
     pf.end(ev, s);
   }
@@ -286,7 +311,7 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   // a2 short-range pairs
   const PairParams<T> pp = pair_params<T>(hp);
   ev = pf.begin("pair", s);
-  launch_pair<T>(p, P->ncell, sorted, start, pp, (T*)P->phi0, (T*)P->F0, s);
+  launch_pair<T>(p, P->ncell, sorted, start, pp, (double*)P->phi0, (T*)P->F0, s);
   pf.end(ev, s);
 
   // a3 anterpolation onto level 1
@@ -298,8 +323,8 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   grid_pass<T>(P, s);
   // a8 + a9 interpolation, combination, energy
   ev = pf.begin("interp", s);
-  launch_interp<T>(p, n, sorted, perm, g1, (const T*)P->eg[0], (const T*)P->phi0,
-                   (const T*)P->F0, (T)hp.self_const, dEdq, F, save_phi, save_F, energy, s);
+  launch_interp<T>(p, n, sorted, perm, g1, (const T*)P->eg[0], (const double*)P->phi0,
+                   (const T*)P->F0, hp.self_const, dEdq, F, save_phi, save_F, energy, s);
   pf.end(ev, s);
   if (save_e1)
     if (hipMemcpyAsync(save_e1, P->eg[0], sizeof(T) * hp.lev[0].G, hipMemcpyDeviceToDevice, s))

@@ -128,7 +128,7 @@ template <typename T, int P>
 __global__ void __launch_bounds__(kPairThreads)
     k_batch_pair(const int* __restrict__ off, int max_n, const T* __restrict__ pos,
                  const T* __restrict__ q, const T* __restrict__ boxes, PairParams<T> pp,
-                 T* __restrict__ phi0, T* __restrict__ F0, int* __restrict__ flag) {
+                 double* __restrict__ phi0, T* __restrict__ F0, int* __restrict__ flag) {
   __shared__ vec4_t<T> tile[kPairThreads];
   const int s = blockIdx.x;
   const int b = max(off[s], 0), e = min(off[s + 1], max_n);
@@ -146,7 +146,8 @@ __global__ void __launch_bounds__(kPairThreads)
         qi = T(0);
       }
     }
-    T ph = 0, fx = 0, fy = 0, fz = 0;
+    double ph = 0.0;
+    T fx = 0, fy = 0, fz = 0;
     for (int jb = b; jb < e; jb += kPairThreads) {
       __syncthreads();
       const int j = jb + (int)threadIdx.x;
@@ -172,7 +173,7 @@ __global__ void __launch_bounds__(kPairThreads)
           for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
 #pragma unroll
           for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
-          ph += pj.w * (rinv - Pt * pp.inv_a);
+          ph += (double)(pj.w * (rinv - Pt * pp.inv_a));
           const T fs = pj.w * (rinv * rinv * rinv + T(2) * dP * pp.inv_a3);
           fx += fs * dx;
           fy += fs * dy;
@@ -195,25 +196,26 @@ __global__ void k_batch_anterp(const int* __restrict__ off, int n_sys, int max_n
                                const T* __restrict__ pos, const T* __restrict__ q,
                                const int* __restrict__ sys_of, const T* __restrict__ boxes,
                                const int* __restrict__ n1, const long long* __restrict__ goff1,
-                               T h, T* __restrict__ grid) {
+                               double h, T* __restrict__ grid) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = min(max(off[n_sys], 0), max_n);
   if (i >= total) return;
   const int s = sys_of[i];
   if (s < 0 || s >= n_sys) return;
-  T xs[3];
+  T xt[3];
   int bad = 0;
-  load_clamped(pos, i, boxes[s], xs[0], xs[1], xs[2], bad);
-  T qi = q[i];
-  if (!isfinite(qi)) qi = T(0);
+  load_clamped(pos, i, boxes[s], xt[0], xt[1], xt[2], bad);
+  T qt = q[i];
+  if (!isfinite(qt)) qt = T(0);
+  const double qi = (double)qt;
   const int n = n1[s], lo = -P / 2 + 1;
-  T w[3][P];
+  double w[3][P];
   int idx[3][P];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    T f;
-    const int base = grid_coord(xs[k], h, f);
-    bspline_weights<P, T>(f, w[k], nullptr, nullptr);
+    double f;
+    const int base = grid_coord<double>((double)xt[k], h, f);
+    bspline_weights<P, double>(f, w[k], nullptr, nullptr);
 #pragma unroll
     for (int j = 0; j < P; ++j) idx[k][j] = axis_index(base - P / 2 + 1 + j, n, lo, 0);
   }
@@ -224,11 +226,11 @@ __global__ void k_batch_anterp(const int* __restrict__ off, int n_sys, int max_n
 #pragma unroll
     for (int b = 0; b < P; ++b) {
       if (idx[1][b] < 0) continue;
-      const T wyz = qi * w[2][c] * w[1][b];
+      const double wyz = qi * w[2][c] * w[1][b];
       const long long row = ((long long)idx[2][c] * n + idx[1][b]) * n;
 #pragma unroll
       for (int a = 0; a < P; ++a)
-        if (idx[0][a] >= 0) atomicAdd(&g[row + idx[0][a]], wyz * w[0][a]);
+        if (idx[0][a] >= 0) atomicAdd(&g[row + idx[0][a]], (T)(wyz * w[0][a]));
     }
   }
 }
@@ -343,8 +345,8 @@ constexpr int kBConvCH = 8;
 // tile (one z plane) of one system's grid, all stencil planes; free axes.
 template <typename T, int R, int TXT, int TYT>
 __global__ void __launch_bounds__(TXT * TYT)
-    k_batch_conv(const ConvTask* __restrict__ tasks, int off, int len, int lds_w, T scale,
-                 const T* __restrict__ K, const int2* __restrict__ rowext,
+    k_batch_conv(const ConvTask* __restrict__ tasks, int off, int len, int lds_w, double scale,
+                 const double* __restrict__ K, const int2* __restrict__ rowext,
                  const T* __restrict__ qcat, T* __restrict__ ecat) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
@@ -354,7 +356,7 @@ __global__ void __launch_bounds__(TXT * TYT)
   const int LW = lds_w, LH = TYT + len - 1;
   const int xs = tk.x0 - (off + len - 1), ys = tk.y0 - (off + len - 1);
   const T* q = qcat + tk.goff;
-  T total[R];
+  double total[R];  // FP64 accumulation (long sums with cancellation)
 #pragma unroll
   for (int r = 0; r < R; ++r) total[r] = 0;
   for (int jz = 0; jz < len; ++jz) {
@@ -368,12 +370,12 @@ __global__ void __launch_bounds__(TXT * TYT)
       lds[idx] = (yi >= 0 && yi < n && xi >= 0 && xi < n) ? qz[(long long)yi * n + xi] : T(0);
     }
     __syncthreads();
-    const T* Kz = K + (long long)jz * len * len;
+    const double* Kz = K + (long long)jz * len * len;
     const int2* ext_z = rowext + jz * len;
     // rows whose input y lies inside the grid for some output row of the tile
     const int jy_lo = max(0, tk.y0 - off - (n - 1));
     const int jy_hi = min(len - 1, tk.y0 + TYT - 1 - off);
-    T acc[R];
+    double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0;
     for (int jy = jy_lo; jy <= jy_hi; ++jy) {
@@ -383,25 +385,25 @@ __global__ void __launch_bounds__(TXT * TYT)
       ext.y = min(ext.y, tk.x0 + TXT * R - 1 - off);
       if (ext.x > ext.y) continue;
       const T* lrow = lds + (ty - jy + len - 1) * LW + tx * R;
-      const T* Krow = Kz + jy * len;
+      const double* Krow = Kz + jy * len;
       int jx = ext.x;
       for (; jx + kBConvCH - 1 <= ext.y; jx += kBConvCH) {
-        T win[kBConvCH + R - 1];
+        double win[kBConvCH + R - 1];
         const T* wp = lrow + (len - jx - kBConvCH);
 #pragma unroll
-        for (int u = 0; u < kBConvCH + R - 1; ++u) win[u] = wp[u];
+        for (int u = 0; u < kBConvCH + R - 1; ++u) win[u] = (double)wp[u];
 #pragma unroll
         for (int c = 0; c < kBConvCH; ++c) {
-          const T kv = Krow[jx + c];
+          const double kv = Krow[jx + c];
 #pragma unroll
           for (int r = 0; r < R; ++r) acc[r] = fma(kv, win[kBConvCH - 1 - c + r], acc[r]);
         }
       }
       for (; jx <= ext.y; ++jx) {
-        const T kv = Krow[jx];
+        const double kv = Krow[jx];
         const T* wp = lrow + (len - 1 - jx);
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = fma(kv, wp[r], acc[r]);
+        for (int r = 0; r < R; ++r) acc[r] = fma(kv, (double)wp[r], acc[r]);
       }
     }
 #pragma unroll
@@ -413,7 +415,7 @@ __global__ void __launch_bounds__(TXT * TYT)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int x = tk.x0 + tx * R + r;
-      if (x < n) erow[x] = scale * total[r];
+      if (x < n) erow[x] = (T)(scale * total[r]);
     }
   }
 }
@@ -423,28 +425,29 @@ __global__ void __launch_bounds__(256)
     k_batch_interp(const int* __restrict__ off, int n_sys, int max_n, const T* __restrict__ pos,
                    const T* __restrict__ q, const int* __restrict__ sys_of,
                    const T* __restrict__ boxes, const int* __restrict__ n1,
-                   const long long* __restrict__ goff1, T h, T inv_h,
-                   const T* __restrict__ ecat1, const T* __restrict__ phi0,
-                   const T* __restrict__ F0, T self_const, T* __restrict__ dEdq,
+                   const long long* __restrict__ goff1, double h, double inv_h,
+                   const T* __restrict__ ecat1, const double* __restrict__ phi0,
+                   const T* __restrict__ F0, double self_const, T* __restrict__ dEdq,
                    T* __restrict__ F, double* __restrict__ energies) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = min(max(off[n_sys], 0), max_n);
   if (i >= total) return;
   const int s = sys_of[i];
   if (s < 0 || s >= n_sys) return;
-  T xs[3];
+  T xt[3];
   int bad = 0;
-  load_clamped(pos, i, boxes[s], xs[0], xs[1], xs[2], bad);
-  T qi = q[i];
-  if (!isfinite(qi)) qi = T(0);
+  load_clamped(pos, i, boxes[s], xt[0], xt[1], xt[2], bad);
+  T qt = q[i];
+  if (!isfinite(qt)) qt = T(0);
+  const double qi = (double)qt;
   const int n = n1[s], lo = -P / 2 + 1;
-  T w[3][P], dw[3][P];
+  double w[3][P], dw[3][P];
   int idx[3][P];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    T f;
-    const int base = grid_coord(xs[k], h, f);
-    bspline_weights<P, T>(f, w[k], dw[k], nullptr);
+    double f;
+    const int base = grid_coord<double>((double)xt[k], h, f);
+    bspline_weights<P, double>(f, w[k], dw[k], nullptr);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       idx[k][j] = axis_index(base - P / 2 + 1 + j, n, lo, 0);
@@ -452,7 +455,7 @@ __global__ void __launch_bounds__(256)
     }
   }
   const T* e1 = ecat1 + goff1[s];
-  T v = 0, gx = 0, gy = 0, gz = 0;
+  double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
     if (idx[2][c] < 0) continue;
@@ -460,11 +463,11 @@ __global__ void __launch_bounds__(256)
     for (int b = 0; b < P; ++b) {
       if (idx[1][b] < 0) continue;
       const long long row = ((long long)idx[2][c] * n + idx[1][b]) * n;
-      T sv = 0, sd = 0;
+      double sv = 0.0, sd = 0.0;
 #pragma unroll
       for (int a = 0; a < P; ++a) {
         if (idx[0][a] < 0) continue;
-        const T e = e1[row + idx[0][a]];
+        const double e = (double)e1[row + idx[0][a]];
         sv += e * w[0][a];
         sd += e * dw[0][a];
       }
@@ -474,14 +477,14 @@ __global__ void __launch_bounds__(256)
       gz += sv * w[1][b] * dw[2][c];
     }
   }
-  const T phi = phi0[i] + v - qi * self_const;
-  if (dEdq) dEdq[i] = phi;
+  const double phid = phi0[i] + v - qi * self_const;
+  if (dEdq) dEdq[i] = (T)phid;
   if (F) {
-    F[3 * i] = F0[3 * i] - qi * gx;
-    F[3 * i + 1] = F0[3 * i + 1] - qi * gy;
-    F[3 * i + 2] = F0[3 * i + 2] - qi * gz;
+    F[3 * i] = (T)((double)F0[3 * i] - qi * gx);
+    F[3 * i + 1] = (T)((double)F0[3 * i + 1] - qi * gy);
+    F[3 * i + 2] = (T)((double)F0[3 * i + 2] - qi * gz);
   }
-  atomicAdd(&energies[s], 0.5 * (double)qi * (double)phi);
+  atomicAdd(&energies[s], 0.5 * qi * phid);
 }
 
 // ---------------------------------------------------------------------------
@@ -495,11 +498,12 @@ static void launch_batch_conv(const BatchConv& bc, int cfg, const T* qcat, T* ec
   int lds_w = tc.TXT * tc.R + bc.len - 1;
   if (sizeof(T) == 4) lds_w |= 1;
   const size_t lds = (size_t)lds_w * (tc.TYT + bc.len - 1) * sizeof(T);
-  const T scale = (T)bc.scale;
+  const double scale = bc.scale;
+  const double* K = (const double*)bc.K;
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_batch_conv<T, 4, 4, 16>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, (const T*)bc.K, bc.rowext, qcat, ecat); break;
-    case 1: hipLaunchKernelGGL((k_batch_conv<T, 4, 8, 16>), dim3(bc.ntasks), dim3(128), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, (const T*)bc.K, bc.rowext, qcat, ecat); break;
-    default: hipLaunchKernelGGL((k_batch_conv<T, 2, 8, 8>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, (const T*)bc.K, bc.rowext, qcat, ecat); break;
+    case 0: hipLaunchKernelGGL((k_batch_conv<T, 4, 4, 16>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, K, bc.rowext, qcat, ecat); break;
+    case 1: hipLaunchKernelGGL((k_batch_conv<T, 4, 8, 16>), dim3(bc.ntasks), dim3(128), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, K, bc.rowext, qcat, ecat); break;
+    default: hipLaunchKernelGGL((k_batch_conv<T, 2, 8, 8>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, K, bc.rowext, qcat, ecat); break;
   }
 }
 
@@ -571,13 +575,13 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
   const T* boxes = (const T*)B.d_box;
   int ev = P->prof.begin("batch_pair", s);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_batch_pair<T, 4>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (T*)B.phi0, (T*)B.F0, B.flag); break;
-    case 6: hipLaunchKernelGGL((k_batch_pair<T, 6>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (T*)B.phi0, (T*)B.F0, B.flag); break;
-    default: hipLaunchKernelGGL((k_batch_pair<T, 8>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (T*)B.phi0, (T*)B.F0, B.flag); break;
+    case 4: hipLaunchKernelGGL((k_batch_pair<T, 4>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
+    case 6: hipLaunchKernelGGL((k_batch_pair<T, 6>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
+    default: hipLaunchKernelGGL((k_batch_pair<T, 8>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
   }
   P->prof.end(ev, s);
   const int nb = (std::max(maxn, 1) + 255) / 256;
-  const T h = (T)B.h;
+  const double h = B.h;
   ev = P->prof.begin("batch_anterp", s);
   switch (p) {
     case 4: hipLaunchKernelGGL((k_batch_anterp<T, 4>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, (T*)B.qcat[0]); break;
@@ -616,12 +620,13 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
     }
   }
   P->prof.end(ev, s);
-  const T sc = (T)B.self_const, ih = (T)(1.0 / B.h);
+  const double sc = B.self_const;
+  const double ih = 1.0 / B.h;
   ev = P->prof.begin("batch_interp", s);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_batch_interp<T, 4>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, ih, (const T*)B.ecat[0], (const T*)B.phi0, (const T*)B.F0, sc, dEdq, F, energies); break;
-    case 6: hipLaunchKernelGGL((k_batch_interp<T, 6>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, ih, (const T*)B.ecat[0], (const T*)B.phi0, (const T*)B.F0, sc, dEdq, F, energies); break;
-    default: hipLaunchKernelGGL((k_batch_interp<T, 8>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, ih, (const T*)B.ecat[0], (const T*)B.phi0, (const T*)B.F0, sc, dEdq, F, energies); break;
+    case 4: hipLaunchKernelGGL((k_batch_interp<T, 4>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, ih, (const T*)B.ecat[0], (const double*)B.phi0, (const T*)B.F0, sc, dEdq, F, energies); break;
+    case 6: hipLaunchKernelGGL((k_batch_interp<T, 6>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, ih, (const T*)B.ecat[0], (const double*)B.phi0, (const T*)B.F0, sc, dEdq, F, energies); break;
+    default: hipLaunchKernelGGL((k_batch_interp<T, 8>), dim3(nb), dim3(256), 0, s, off, NS, maxn, pos, q, B.sys_of, boxes, B.d_n[0], B.d_goff[0], h, ih, (const T*)B.ecat[0], (const double*)B.phi0, (const T*)B.F0, sc, dEdq, F, energies); break;
   }
   P->prof.end(ev, s);
   return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
@@ -697,7 +702,7 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
   if (hipMemcpy(B.d_box, bx.data(), B.n_sys * sizeof(T), hipMemcpyHostToDevice)) return MSM_ERR_HIP;
   const size_t nmax = (size_t)std::max(B.max_total_n, 1);
   if ((st = hip_alloc(P, (void**)&B.sys_of, nmax * sizeof(int)))) return st;
-  if ((st = hip_alloc(P, &B.phi0, nmax * sizeof(T)))) return st;
+  if ((st = hip_alloc(P, &B.phi0, nmax * sizeof(double)))) return st;
   if ((st = hip_alloc(P, &B.F0, nmax * 3 * sizeof(T)))) return st;
   if ((st = hip_alloc(P, (void**)&B.flag, sizeof(int)))) return st;
   if (hipMemset(B.flag, 0, sizeof(int))) return MSM_ERR_HIP;
@@ -705,7 +710,7 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
   // stencils: K^1 (intermediate levels, scaled per level) and the top tables
   void* dK1 = nullptr;
   int2* dK1ext = nullptr;
-  if ((st = upload_stencil<T>(P, K1, 2 * W1 + 1, &dK1, &dK1ext))) return st;
+  if ((st = upload_stencil<double>(P, K1, 2 * W1 + 1, &dK1, &dK1ext))) return st;
   for (int l = 1; l <= B.Lmax; ++l) {
     BatchConv inter;
     inter.level = l;
@@ -722,7 +727,7 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
     top.len = top_len[l];
     top.off = -(top_len[l] - 1) / 2;
     if (top_len[l] > 0) {
-      if ((st = upload_stencil<T>(P, tops[l], top_len[l], &top.K, &top.rowext))) return st;
+      if ((st = upload_stencil<double>(P, tops[l], top_len[l], &top.K, &top.rowext))) return st;
     }
     for (BatchConv* bc : {&inter, &top}) {
       if (bc->top && top_len[l] == 0) continue;

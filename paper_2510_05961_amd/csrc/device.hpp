@@ -35,6 +35,7 @@ struct GridDev {
   int per[3];  // 1 = periodic axis (index wraps modulo n)
   T h[3];      // spacing
   T inv_h[3];
+  double hd[3];  // spacing in FP64 (grid coordinates of particles)
 };
 
 // Fractional grid coordinate of x on an axis of spacing h: returns the

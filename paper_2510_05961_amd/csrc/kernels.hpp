@@ -60,14 +60,14 @@ void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int
                     vec4_t<T>* sorted, int* perm, int* flag, hipStream_t s);
 template <typename T>
 void launch_pair(int p, int ncell, const vec4_t<T>* sorted, const int* start,
-                 const PairParams<T>& pp, T* phi0, T* F0, hipStream_t s);
+                 const PairParams<T>& pp, double* phi0, T* F0, hipStream_t s);
 template <typename T>
 void launch_anterp(int p, int n, const vec4_t<T>* sorted, const GridDev<T>& g, T* grid,
                    hipStream_t s);
 template <typename T>
 void launch_interp(int p, int n, const vec4_t<T>* sorted, const int* perm, const GridDev<T>& g,
-                   const T* e1, const T* phi0, const T* F0, T self_const, T* dEdq, T* F,
-                   T* save_phi, T* save_F, double* energy, hipStream_t s);
+                   const T* e1, const double* phi0, const T* F0, double self_const, T* dEdq,
+                   T* F, T* save_phi, T* save_F, double* energy, hipStream_t s);
 
 // J is a HOST array of the p+1 restriction taps (passed by value to the kernel).
 template <typename T>
@@ -89,6 +89,8 @@ void launch_omega(const OmegaParams& op, const double* u, TO* e, hipStream_t s);
 
 template <typename T>
 void launch_fill(T* p, long long count, T value, hipStream_t s);
+template <typename T>
+void launch_cast(const double* src, T* dst, long long count, hipStream_t s);
 
 // backward (vector-Jacobian product)
 template <typename T>

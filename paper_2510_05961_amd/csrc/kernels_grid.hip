@@ -265,6 +265,13 @@ __global__ void __launch_bounds__(256)
 }
 
 template <typename T>
+__global__ void k_cast(const double* __restrict__ src, T* __restrict__ dst, long long count) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (T)src[i];
+}
+
+template <typename T>
 __global__ void k_fill(T* __restrict__ p, long long count, T value) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (long long)gridDim.x * blockDim.x)
@@ -371,6 +378,14 @@ void launch_omega(const OmegaParams& op, const double* u, TO* e, hipStream_t s) 
 }
 
 template <typename T>
+void launch_cast(const double* src, T* dst, long long count, hipStream_t s) {
+  if (count <= 0) return;
+  long long nb = (count + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_cast<T>, dim3((unsigned)nb), dim3(256), 0, s, src, dst, count);
+}
+
+template <typename T>
 void launch_fill(T* p, long long count, T value, hipStream_t s) {
   if (count <= 0) return;
   long long nb = (count + 255) / 256;
@@ -386,7 +401,8 @@ void launch_fill(T* p, long long count, T value, hipStream_t s) {
   template void launch_conv<T, T>(const ConvParams&, const T*, const int2*, const T*, T*,         \
                                   hipStream_t);                                                   \
   template void launch_omega<T>(const OmegaParams&, const double*, T*, hipStream_t);              \
-  template void launch_fill<T>(T*, long long, T, hipStream_t);
+  template void launch_fill<T>(T*, long long, T, hipStream_t);                                    \
+  template void launch_cast<T>(const double*, T*, long long, hipStream_t);
 MSM_INST_GRID(float)
 MSM_INST_GRID(double)
 template void launch_fill<int>(int*, long long, int, hipStream_t);

@@ -117,7 +117,7 @@ __device__ inline int neighbour_cell(int c, int o, int nc, int per) {
 template <typename T, int P>
 __global__ void __launch_bounds__(kPairThreads)
     k_pair(const vec4_t<T>* __restrict__ sorted, const int* __restrict__ start, PairParams<T> pp,
-           T* __restrict__ phi0, T* __restrict__ F0) {
+           double* __restrict__ phi0, T* __restrict__ F0) {
   __shared__ vec4_t<T> tile[kPairThreads];
   const int cell = blockIdx.x;
   const int cx = cell % pp.nc[0];
@@ -132,7 +132,8 @@ __global__ void __launch_bounds__(kPairThreads)
     else {
       pi.x = pi.y = pi.z = pi.w = T(0);
     }
-    T ph = T(0), fx = T(0), fy = T(0), fz = T(0);
+    double ph = 0.0;  // the potential is carried in FP64 up to the energy sum
+    T fx = T(0), fy = T(0), fz = T(0);
     // neighbour cells: offsets -1..1 per axis, each distinct cell once
     for (int oz = -1; oz <= 1; ++oz) {
       const int nz = neighbour_cell(cz, oz, pp.nc[2], pp.per[2]);
@@ -165,7 +166,7 @@ __global__ void __launch_bounds__(kPairThreads)
                 for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
 #pragma unroll
                 for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
-                ph += pj.w * (rinv - Pt * pp.inv_a);
+                ph += (double)(pj.w * (rinv - Pt * pp.inv_a));
                 const T fs = pj.w * (rinv * rinv * rinv + T(2) * dP * pp.inv_a3);
                 fx += fs * dx;
                 fy += fs * dy;
@@ -196,31 +197,32 @@ __global__ void k_anterp(int n, const vec4_t<T>* __restrict__ sorted, GridDev<T>
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const vec4_t<T> pi = sorted[i];
-  const T xs[3] = {pi.x, pi.y, pi.z};
-  T w[3][P];
+  const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+  // weights in FP64: they enter the grid self-energy quadratically
+  double w[3][P];
   int idx[3][P];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    T f;
-    const int base = grid_coord(xs[k], g.h[k], f);
-    bspline_weights<P, T>(f, w[k], nullptr, nullptr);
+    double f;
+    const int base = grid_coord<double>(xs[k], g.hd[k], f);
+    bspline_weights<P, double>(f, w[k], nullptr, nullptr);
 #pragma unroll
     for (int j = 0; j < P; ++j) idx[k][j] = axis_index(base - P / 2 + 1 + j, g.n[k], g.lo[k], g.per[k]);
   }
-  const T qi = pi.w;
+  const double qi = (double)pi.w;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
     if (idx[2][c] < 0) continue;
-    const T wz = qi * w[2][c];
+    const double wz = qi * w[2][c];
 #pragma unroll
     for (int b = 0; b < P; ++b) {
       if (idx[1][b] < 0) continue;
-      const T wyz = wz * w[1][b];
+      const double wyz = wz * w[1][b];
       const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
 #pragma unroll
       for (int a = 0; a < P; ++a) {
         if (idx[0][a] < 0) continue;
-        atomicAdd(&grid[row + idx[0][a]], wyz * w[0][a]);
+        atomicAdd(&grid[row + idx[0][a]], (T)(wyz * w[0][a]));
       }
     }
   }
@@ -235,28 +237,31 @@ __global__ void k_anterp(int n, const vec4_t<T>* __restrict__ sorted, GridDev<T>
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
     k_interp(int n, const vec4_t<T>* __restrict__ sorted, const int* __restrict__ perm,
-             GridDev<T> g, const T* __restrict__ e1, const T* __restrict__ phi0,
-             const T* __restrict__ F0, T self_const, T* __restrict__ dEdq, T* __restrict__ F,
+             GridDev<T> g, const T* __restrict__ e1, const double* __restrict__ phi0,
+             const T* __restrict__ F0, double self_const, T* __restrict__ dEdq, T* __restrict__ F,
              T* __restrict__ save_phi, T* __restrict__ save_F, double* __restrict__ energy) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double ep = 0.0;
   if (i < n) {
     const vec4_t<T> pi = sorted[i];
-    const T xs[3] = {pi.x, pi.y, pi.z};
-    T w[3][P], dw[3][P];
+    const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    // weights and sums in FP64 (the energy needs the grid self-interaction
+    // below FP32 rounding); outputs are rounded to T at the end
+    double w[3][P], dw[3][P];
     int idx[3][P];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      T f;
-      const int base = grid_coord(xs[k], g.h[k], f);
-      bspline_weights<P, T>(f, w[k], dw[k], nullptr);
+      double f;
+      const int base = grid_coord<double>(xs[k], g.hd[k], f);
+      bspline_weights<P, double>(f, w[k], dw[k], nullptr);
+      const double ih = 1.0 / g.hd[k];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         idx[k][j] = axis_index(base - P / 2 + 1 + j, g.n[k], g.lo[k], g.per[k]);
-        dw[k][j] *= g.inv_h[k];
+        dw[k][j] *= ih;
       }
     }
-    T v = T(0), gx = T(0), gy = T(0), gz = T(0);
+    double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       if (idx[2][c] < 0) continue;
@@ -264,11 +269,11 @@ __global__ void __launch_bounds__(256)
       for (int b = 0; b < P; ++b) {
         if (idx[1][b] < 0) continue;
         const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
-        T sv = T(0), sd = T(0);
+        double sv = 0.0, sd = 0.0;
 #pragma unroll
         for (int a = 0; a < P; ++a) {
           if (idx[0][a] < 0) continue;
-          const T e = e1[row + idx[0][a]];
+          const double e = (double)e1[row + idx[0][a]];
           sv += e * w[0][a];
           sd += e * dw[0][a];
         }
@@ -278,9 +283,12 @@ __global__ void __launch_bounds__(256)
         gz += sv * w[1][b] * dw[2][c];
       }
     }
+    const double qd = (double)pi.w;
     const T qi = pi.w;
-    const T phi = phi0[i] + v - qi * self_const;
-    const T fx = F0[3 * i] - qi * gx, fy = F0[3 * i + 1] - qi * gy, fz = F0[3 * i + 2] - qi * gz;
+    const double phid = phi0[i] + v - qd * self_const;
+    const T phi = (T)phid;
+    const T fx = (T)((double)F0[3 * i] - qd * gx), fy = (T)((double)F0[3 * i + 1] - qd * gy),
+            fz = (T)((double)F0[3 * i + 2] - qd * gz);
     const int o = perm[i];
     if (dEdq) dEdq[o] = phi;
     if (F) {
@@ -294,7 +302,8 @@ __global__ void __launch_bounds__(256)
       save_F[3 * i + 1] = fy;
       save_F[3 * i + 2] = fz;
     }
-    ep = 0.5 * (double)qi * (double)phi;
+    ep = 0.5 * qd * phid;
+    (void)qi;
   }
   // wavefront then workgroup reduction in FP64
   for (int off = 32; off > 0; off >>= 1) ep += __shfl_down(ep, off, 64);
@@ -328,7 +337,7 @@ void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int
 
 template <typename T>
 void launch_pair(int p, int ncell, const vec4_t<T>* sorted, const int* start,
-                 const PairParams<T>& pp, T* phi0, T* F0, hipStream_t s) {
+                 const PairParams<T>& pp, double* phi0, T* F0, hipStream_t s) {
   if (ncell <= 0) return;
   switch (p) {
     case 4: hipLaunchKernelGGL((k_pair<T, 4>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, start, pp, phi0, F0); break;
@@ -351,8 +360,8 @@ void launch_anterp(int p, int n, const vec4_t<T>* sorted, const GridDev<T>& g, T
 
 template <typename T>
 void launch_interp(int p, int n, const vec4_t<T>* sorted, const int* perm, const GridDev<T>& g,
-                   const T* e1, const T* phi0, const T* F0, T self_const, T* dEdq, T* F,
-                   T* save_phi, T* save_F, double* energy, hipStream_t s) {
+                   const T* e1, const double* phi0, const T* F0, double self_const, T* dEdq,
+                   T* F, T* save_phi, T* save_F, double* energy, hipStream_t s) {
   if (n <= 0) return;
   const int nb = (n + 255) / 256;
   switch (p) {
@@ -365,12 +374,12 @@ void launch_interp(int p, int n, const vec4_t<T>* sorted, const int* perm, const
 #define MSM_INST_PARTICLES(T)                                                                    \
   template void launch_binning<T>(int, const T*, const T*, const BinParams<T>&, int, int*, int*, \
                                   int*, vec4_t<T>*, int*, vec4_t<T>*, int*, int*, hipStream_t);  \
-  template void launch_pair<T>(int, int, const vec4_t<T>*, const int*, const PairParams<T>&, T*, \
-                               T*, hipStream_t);                                                 \
+  template void launch_pair<T>(int, int, const vec4_t<T>*, const int*, const PairParams<T>&,      \
+                               double*, T*, hipStream_t);                                        \
   template void launch_anterp<T>(int, int, const vec4_t<T>*, const GridDev<T>&, T*, hipStream_t); \
   template void launch_interp<T>(int, int, const vec4_t<T>*, const int*, const GridDev<T>&,      \
-                                 const T*, const T*, const T*, T, T*, T*, T*, T*, double*,        \
-                                 hipStream_t);
+                                 const T*, const double*, const T*, double, T*, T*, T*, T*,       \
+                                 double*, hipStream_t);
 MSM_INST_PARTICLES(float)
 MSM_INST_PARTICLES(double)
 

@@ -89,6 +89,7 @@ struct msm_plan_s {
   void* eg[msm::kMaxLevels] = {};
   // factored levels: FP64 k-samples, their row extents, FP64 partial grid
   double* S[msm::kMaxLevels] = {};
+  int2* rowext64[msm::kMaxLevels] = {};  // non-zero rows of the FP64 stencil
   int2* srowext[msm::kMaxLevels] = {};
   double* ug[msm::kMaxLevels] = {};
   void* Jd = nullptr;

@@ -108,7 +108,8 @@ def test_autograd_gradcheck_fp64():
         E, F, _ = msm.energy_forces(pp, qq, plan)
         return E, F
 
-    assert torch.autograd.gradcheck(f, (P, Q), eps=1e-6, atol=1e-6, rtol=1e-5)
+    # FP64 atomics make repeated backward passes differ at round-off level
+    assert torch.autograd.gradcheck(f, (P, Q), eps=1e-6, atol=1e-6, rtol=1e-5, nondet_tol=1e-12)
 
 
 @pytest.mark.parametrize("cfg,scale", [(4, 0.04)])

@@ -80,8 +80,12 @@ def test_degenerate_sizes(fp64):
             plan = msm.Plan(box, mask_of(per), 4, 1.0, 3.0, 2,
                             msm.MSM_FP64 if fp64 else msm.MSM_FP32, 4)
             g = gpu_forward(plan, pos, q)
-            ref = O.OracleMSM(box, per, 4, 1.0, 3.0, 2).compute(pos, q)
-            assert g["E"] == pytest.approx(ref["E"], rel=1e-5, abs=1e-9)
+            o = O.OracleMSM(box, per, 4, 1.0, 3.0, 2)
+            ref = o.compute(pos, q)
+            # for n <= 2 the energy is a small residual of the grid self-energy
+            # 1/2 sum q^2 sum_l k_l(0); FP32 is held to 1e-6 of that scale
+            scale = 0.5 * float(np.sum(q * q)) * o.self_constant()
+            assert abs(g["E"] - ref["E"]) <= (1e-11 if fp64 else 1e-6) * max(scale, 1e-30)
             if n:
                 np.testing.assert_allclose(g["F"], ref["F"], rtol=1e-4, atol=1e-7)
 
