@@ -28,6 +28,7 @@ METRIC = "MSM energy+forces particles/s at fixed force error; batched/autograd v
 
 # MI355X published peaks
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
@@ -40,6 +41,96 @@ def _pair_count(pos, box, a):
     return int((t.count_neighbors(t, a) - len(p)) // 2)
 
 
+def _time(fn, torch, reps):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def _autograd_vs_plain(torch, msm, WL, np):
+    """Learnable-charge workload (200,000 Gaussian charges, 60 A periodic
+    cube, p=4, h=1.5, a=10, L=4, FP32): plain forward vs forward + backward
+    of L = E + sum v.F (v ~ N(0,1))."""
+    cfg = WL.CONFIGS[4]
+    pos64, q64, box = WL.make_config(4, 1.0)
+    n = len(q64)
+    dev = torch.device("cuda:0")
+    P = torch.tensor(pos64, dtype=torch.float32, device=dev)
+    Q = torch.tensor(q64, dtype=torch.float32, device=dev)
+    v = torch.tensor(WL.force_cotangent(n, seed=40), dtype=torch.float32, device=dev)
+    plan = msm.Plan(box, cfg["periodic"], cfg["p"], cfg["h"], cfg["a"], cfg["L"],
+                    msm.MSM_FP32, n)
+    ws = torch.empty(plan.workspace_bytes(n), dtype=torch.uint8, device=dev)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    F = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    dq = torch.empty(n, dtype=torch.float32, device=dev)
+    gE = torch.ones(1, dtype=torch.float64, device=dev)
+    t_fwd = _time(lambda: plan.energy_forces(P, Q, out=(E, F, dq)), torch, 20)
+
+    def fwd_bwd():
+        plan.energy_forces(P, Q, ws=ws, out=(E, F, dq))
+        plan.backward(P, Q, ws, gE=gE, gF=v)
+    t_fb = _time(fwd_bwd, torch, 20)
+    # the same through torch.autograd
+    Pg = P.clone().requires_grad_(True)
+    Qg = Q.clone().requires_grad_(True)
+
+    def autograd_step():
+        Pg.grad = None
+        Qg.grad = None
+        e, f, _ = msm.energy_forces(Pg, Qg, plan)
+        (e.sum() + (f * v).sum()).backward()
+    t_ag = _time(autograd_step, torch, 10)
+    return {"workload": "200,000 Gaussian charges, 60 A periodic cube, p=4, h=1.5, a=10, L=4, "
+                        "FP32", "n": n,
+            "forward_particles_per_s": round(n / t_fwd, 1),
+            "forward_backward_particles_per_s": round(n / t_fb, 1),
+            "torch_autograd_particles_per_s": round(n / t_ag, 1),
+            "forward_backward_over_forward_time": round(t_fb / t_fwd, 3)}
+
+
+def _batched_vs_plain(torch, msm, WL, np):
+    """4,096 free-space clusters of 8-256 charges in 10-30 A boxes (p=4, h=1,
+    a=6, FP32): one batched launch sequence vs one plan per system run one
+    after another (timed on the first 256 systems, per particle)."""
+    off, boxes, pos, q, levels = WL.make_batch(4096, seed=5)
+    dev = torch.device("cuda:0")
+    O_ = torch.tensor(off, dtype=torch.int32, device=dev)
+    P = torch.tensor(pos, dtype=torch.float32, device=dev)
+    Q = torch.tensor(q, dtype=torch.float32, device=dev)
+    ntot = int(off[-1])
+    bp = msm.BatchPlan(boxes, levels, 4, 1.0, 6.0, msm.MSM_FP32, ntot)
+    E = torch.empty(len(boxes), dtype=torch.float64, device=dev)
+    F = torch.empty((ntot, 3), dtype=torch.float32, device=dev)
+    dq = torch.empty(ntot, dtype=torch.float32, device=dev)
+    t_b = _time(lambda: bp.energy_forces(O_, P, Q, out=(E, F, dq)), torch, 10)
+    ns = 256
+    plans, args_ = [], []
+    for s in range(ns):
+        a, b = int(off[s]), int(off[s + 1])
+        pl = msm.Plan((float(boxes[s]),) * 3, 0, 4, 1.0, 6.0, int(levels[s]), msm.MSM_FP32,
+                      max(b - a, 1))
+        plans.append(pl)
+        args_.append((P[a:b], Q[a:b], (torch.empty(1, dtype=torch.float64, device=dev),
+                                       F[a:b], dq[a:b])))
+
+    def plain():
+        for pl, (pp, qq, o) in zip(plans, args_):
+            pl.energy_forces(pp, qq, out=o)
+    t_p = _time(plain, torch, 3)
+    n_sub = int(off[ns])
+    return {"workload": "4,096 free-space clusters, 8-256 charges, 10-30 A boxes, p=4, h=1, "
+                        "a=6, FP32", "n_systems": len(boxes), "n": ntot,
+            "batched_particles_per_s": round(ntot / t_b, 1),
+            "plain_particles_per_s": round(n_sub / t_p, 1),
+            "plain_sample_systems": ns,
+            "batched_over_plain": round((ntot / t_b) / (n_sub / t_p), 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,6 +138,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the autograd (C4) and batched (C5) comparisons")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the timed region, one device-to-device copy of this many MiB "
+                         "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (got --gpus {args.gpus}); "
@@ -93,25 +189,46 @@ def main():
     ms_per_step = dt / args.steps * 1e3
     value = n * args.steps / dt
 
-    # algorithmic work per launch
+    # algorithmic work per launch (per unit: 2 flops per in-grid (output,
+    # input) pair with a non-zero coefficient for a convolution, all periodic
+    # here; 28 + 4p flops per unique in-cutoff pair for the pair sum)
     lev = desc["levels_info"]
-    conv_flops = {}
-    for l, info in enumerate(lev, start=1):
-        G = info["n"][0] * info["n"][1] * info["n"][2]
-        # periodic axes everywhere: every output sees every non-zero tap
-        conv_flops[l] = 2.0 * G * info["stencil_nnz"]
+    l1 = lev[0]
+    G1 = l1["n"][0] * l1["n"][1] * l1["n"][2]
+    direct_flops_l1 = 2.0 * G1 * l1["stencil_nnz"]
+    if l1.get("factored"):
+        Gext = l1["ext"][0] * l1["ext"][1] * l1["ext"][2]
+        conv_l1_flops = 2.0 * Gext * l1["samples_nnz"]
+    else:
+        conv_l1_flops = direct_flops_l1
     npairs = _pair_count(pos32.astype(np.float64), 100.0, cfg["a"])
     pair_flops = (28 + 4 * cfg["p"]) * npairs
-    per_stage = {k: v["ms"] / max(v["launches"], 1) for k, v in stages.items()}
-    candidates = {"conv_l1": ("mfma_or_alu_conv", conv_flops[1]), "pair": ("pair", pair_flops)}
-    dom = max(candidates, key=lambda k: per_stage.get(k, 0.0))
-    dur_s = per_stage[dom] * 1e-3
-    achieved = candidates[dom][1] / dur_s / 1e12
+    per_step = {k: v["ms"] / args.steps for k, v in stages.items()}
+    per_launch = {k: v["ms"] / max(v["launches"], 1) for k, v in stages.items()}
+    # kernel -> (algorithmic flops per launch, peak of its arithmetic type)
+    candidates = {"conv_l1": (conv_l1_flops, PEAK_FP64_TFLOPS, "fp64"),
+                  "pair": (pair_flops, PEAK_FP32_VECTOR_TFLOPS, "fp32")}
+    dom = max(candidates, key=lambda k: per_launch.get(k, 0.0))
+    flops, peak, adt = candidates[dom]
+    dur_s = per_launch[dom] * 1e-3
+    achieved = flops / dur_s / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
-                "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
-                "algorithmic_per_launch": candidates[dom][1],
-                "avg_launch_ms": round(per_stage[dom], 5)}
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": None, "arith": adt,
+                "algorithmic_per_launch": flops,
+                "avg_launch_ms": round(per_launch[dom], 5)}
+    others = {}
+    for k, (fl, pk, at) in candidates.items():
+        if k in per_launch:
+            a_ = fl / (per_launch[k] * 1e-3) / 1e12
+            others[k] = {"achieved": round(a_, 3), "peak": pk, "arith": at,
+                         "frac": round(a_ / pk, 4), "avg_launch_ms": round(per_launch[k], 5)}
+    # the level-1 stencil as the method defines it (direct-form flops) over
+    # the time of the whole level-1 application (sample convolution + omega')
+    t_l1 = per_step.get("conv_l1", 0.0) + per_step.get("omega_l1", 0.0)
+    if t_l1 > 0:
+        others["level1_stencil_direct_equivalent"] = {
+            "tflops": round(direct_flops_l1 / (t_l1 * 1e-3) / 1e12, 3), "ms": round(t_l1, 5)}
 
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "particles/s", "n_gpus": 1,
@@ -123,9 +240,24 @@ def main():
                    "n": n, "box": box[0], "order": cfg["p"], "h": lev[0]["h"][0],
                    "cutoff": cfg["a"], "levels": cfg["L"], "precision": "fp32"},
         "roofline": roofline,
-        "stages_ms_per_step": {k: round(v, 5) for k, v in per_stage.items()},
+        "kernels": others,
+        "stages_ms_per_step": {k: round(v, 5) for k, v in per_step.items()},
         "pairs_in_cutoff": npairs,
     }
+
+    if args.calib_copy_mb > 0:
+        nb = args.calib_copy_mb * (1 << 20)
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = nb
+        del src, dst
+
+    if not args.no_extras:
+        result["autograd"] = _autograd_vs_plain(torch, msm, WL, np)
+        result["batched"] = _batched_vs_plain(torch, msm, WL, np)
 
     if not args.no_error_check:
         from oracle import oracle as O

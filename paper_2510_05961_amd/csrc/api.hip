@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -81,75 +82,53 @@ template <typename T>
 msm_status upload_plan(msm_plan P) {
   HostPlan& hp = P->hp;
   msm_status st;
-  for (int l = 1; l <= hp.L; ++l) {
-    LevelGeom& g = hp.lev[l - 1];
-    const size_t ks = g.K.size();
-    if ((st = hip_alloc(P, (void**)&P->K64[l - 1], ks * sizeof(double)))) return st;
-    if ((st = hip_alloc(P, &P->K[l - 1], ks * sizeof(T)))) return st;
-    std::vector<T> kt(ks);
-    for (size_t i = 0; i < ks; ++i) kt[i] = (T)g.K[i];
-    // non-zero x range of every stencil row, in the precision used
-    std::vector<int2> ext((size_t)g.len[1] * g.len[2]);
-    for (int z = 0; z < g.len[2]; ++z)
-      for (int y = 0; y < g.len[1]; ++y) {
-        int first = g.len[0], last = -1;
-        for (int x = 0; x < g.len[0]; ++x)
-          if (kt[((size_t)z * g.len[1] + y) * g.len[0] + x] != T(0)) {
+  // an FP64 stencil [len2][len1][len0] as the convolution reads it: rows
+  // padded with zeros to conv_row_stride(len0), kConvRowPad zero rows before
+  // and after every plane, plus the [first, last] non-zero x range of every
+  // (unpadded) row
+  auto upload_stencil = [&](const std::vector<double>& A, const int len[3], double** dA,
+                            int2** dext) -> msm_status {
+    const int lxp = conv_row_stride(len[0]);
+    const int lyp = len[1] + 2 * kConvRowPad;
+    const size_t rows = (size_t)len[1] * len[2];
+    std::vector<double> pad((size_t)len[2] * lyp * lxp, 0.0);
+    std::vector<int2> ext(rows);
+    for (int z = 0; z < len[2]; ++z)
+      for (int y = 0; y < len[1]; ++y) {
+        const size_t r = (size_t)z * len[1] + y;
+        const size_t rp = (size_t)z * lyp + y + kConvRowPad;
+        int first = len[0], last = -1;
+        for (int x = 0; x < len[0]; ++x) {
+          const double v = A[r * len[0] + x];
+          pad[rp * lxp + x] = v;
+          if (v != 0.0) {
             first = std::min(first, x);
             last = x;
           }
-        ext[(size_t)z * g.len[1] + y] = make_int2(first, last);
+        }
+        ext[r] = make_int2(first, last);
       }
-    if ((st = hip_alloc(P, (void**)&P->rowext[l - 1], ext.size() * sizeof(int2)))) return st;
-    if (hipMemcpy(P->K64[l - 1], g.K.data(), ks * sizeof(double), hipMemcpyHostToDevice) ||
-        hipMemcpy(P->K[l - 1], kt.data(), ks * sizeof(T), hipMemcpyHostToDevice) ||
-        hipMemcpy(P->rowext[l - 1], ext.data(), ext.size() * sizeof(int2), hipMemcpyHostToDevice))
+    msm_status s2;
+    if ((s2 = hip_alloc(P, (void**)dA, pad.size() * sizeof(double)))) return s2;
+    if ((s2 = hip_alloc(P, (void**)dext, ext.size() * sizeof(int2)))) return s2;
+    if (hipMemcpy(*dA, pad.data(), pad.size() * sizeof(double), hipMemcpyHostToDevice) ||
+        hipMemcpy(*dext, ext.data(), ext.size() * sizeof(int2), hipMemcpyHostToDevice))
       return MSM_ERR_HIP;
+    return MSM_OK;
+  };
+  for (int l = 1; l <= hp.L; ++l) {
+    LevelGeom& g = hp.lev[l - 1];
+    if ((st = upload_stencil(g.K, g.len, &P->K64[l - 1], &P->rowext64[l - 1]))) return st;
     if ((st = hip_alloc(P, &P->qg[l - 1], (size_t)g.G * sizeof(T)))) return st;
     if ((st = hip_alloc(P, &P->eg[l - 1], (size_t)g.G * sizeof(T)))) return st;
-    {
-      // FP64 accumulation buffer of the level's convolution and the row
-      // extents of the FP64 stencil it uses
-      std::vector<int2> e64((size_t)g.len[1] * g.len[2]);
-      for (int z = 0; z < g.len[2]; ++z)
-        for (int y = 0; y < g.len[1]; ++y) {
-          int first = g.len[0], last = -1;
-          for (int x = 0; x < g.len[0]; ++x)
-            if (g.K[((size_t)z * g.len[1] + y) * g.len[0] + x] != 0.0) {
-              first = std::min(first, x);
-              last = x;
-            }
-          e64[(size_t)z * g.len[1] + y] = make_int2(first, last);
-        }
-      if ((st = hip_alloc(P, (void**)&P->rowext64[l - 1], e64.size() * sizeof(int2)))) return st;
-      if (hipMemcpy(P->rowext64[l - 1], e64.data(), e64.size() * sizeof(int2),
-                    hipMemcpyHostToDevice))
-        return MSM_ERR_HIP;
-      const long long gbuf = std::max(g.G, g.factored ? g.Gext : 0LL);
-      if ((st = hip_alloc(P, (void**)&P->ug[l - 1], (size_t)gbuf * sizeof(double)))) return st;
-    }
+    // FP64 accumulation buffer of the level's convolution
+    const long long gbuf = std::max(g.G, g.factored ? g.Gext : 0LL);
+    if ((st = hip_alloc(P, (void**)&P->ug[l - 1], (size_t)gbuf * sizeof(double)))) return st;
     const int zero3[3] = {0, 0, 0};
     ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
     if (conv_lds_bytes(cp, sizeof(T)) > 160 * 1024) return MSM_ERR_GRID;
     if (g.factored) {
-      const size_t ss = g.S.size();
-      if ((st = hip_alloc(P, (void**)&P->S[l - 1], ss * sizeof(double)))) return st;
-      std::vector<int2> sext((size_t)g.s_len[1] * g.s_len[2]);
-      for (int z = 0; z < g.s_len[2]; ++z)
-        for (int y = 0; y < g.s_len[1]; ++y) {
-          int first = g.s_len[0], last = -1;
-          for (int x = 0; x < g.s_len[0]; ++x)
-            if (g.S[((size_t)z * g.s_len[1] + y) * g.s_len[0] + x] != 0.0) {
-              first = std::min(first, x);
-              last = x;
-            }
-          sext[(size_t)z * g.s_len[1] + y] = make_int2(first, last);
-        }
-      if ((st = hip_alloc(P, (void**)&P->srowext[l - 1], sext.size() * sizeof(int2)))) return st;
-      if (hipMemcpy(P->S[l - 1], g.S.data(), ss * sizeof(double), hipMemcpyHostToDevice) ||
-          hipMemcpy(P->srowext[l - 1], sext.data(), sext.size() * sizeof(int2),
-                    hipMemcpyHostToDevice))
-        return MSM_ERR_HIP;
+      if ((st = upload_stencil(g.S, g.s_len, &P->S[l - 1], &P->srowext[l - 1]))) return st;
       ConvParams cs = make_conv_params(g.n, g.next, g.shift, hp.periodic, g.s_off, g.s_len,
                                        sizeof(T));
       if (conv_lds_bytes(cs, sizeof(T)) > 160 * 1024) return MSM_ERR_GRID;
@@ -169,10 +148,23 @@ msm_status upload_plan(msm_plan P) {
   if ((st = hip_alloc(P, (void**)&P->perm, nmax * sizeof(int)))) return st;
   if ((st = hip_alloc(P, &P->wrapped, nmax * 4 * sizeof(T)))) return st;
   if ((st = hip_alloc(P, &P->sorted, nmax * 4 * sizeof(T)))) return st;
+  {
+    const size_t ncl = (size_t)cluster_capacity((int)nmax, P->ncell);
+    if ((st = hip_alloc(P, (void**)&P->cl_start, (size_t)(P->ncell + 1) * sizeof(int)))) return st;
+    if ((st = hip_alloc(P, &P->cpos, ncl * 8 * 4 * sizeof(T)))) return st;
+    if ((st = hip_alloc(P, &P->cv, ncl * 8 * 4 * sizeof(T)))) return st;
+    if ((st = hip_alloc(P, &P->cbox, ncl * 2 * 4 * sizeof(T)))) return st;
+    if ((st = hip_alloc(P, (void**)&P->cinfo, ncl * sizeof(int4)))) return st;
+  }
   if ((st = hip_alloc(P, &P->phi0, nmax * sizeof(double)))) return st;
   if ((st = hip_alloc(P, &P->F0, nmax * 3 * sizeof(T)))) return st;
   if ((st = hip_alloc(P, (void**)&P->flag, sizeof(int)))) return st;
   if (hipMemset(P->flag, 0, sizeof(int))) return MSM_ERR_HIP;
+  if (hipStreamCreateWithFlags(&P->sb, hipStreamNonBlocking) ||
+      hipStreamCreateWithFlags(&P->sc, hipStreamNonBlocking))
+    return MSM_ERR_HIP;
+  for (auto& e : P->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming)) return MSM_ERR_HIP;
   if (hipDeviceSynchronize()) return MSM_ERR_HIP;
   return MSM_OK;
 }
@@ -181,6 +173,10 @@ void free_plan(msm_plan P) {
   if (!P) return;
   if (P->device) (void)hipDeviceSynchronize();
   if (P->bs) destroy_batch(P->bs);
+  for (auto& e : P->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (P->sb) (void)hipStreamDestroy(P->sb);
+  if (P->sc) (void)hipStreamDestroy(P->sc);
   for (void* p : P->allocs) (void)hipFree(p);
   delete P;
 }
@@ -192,9 +188,11 @@ PairParams<T> pair_params(const HostPlan& hp) {
   for (int k = 0; k < 3; ++k) {
     pp.box[k] = (T)hp.box[k];
     pp.inv_box[k] = (T)(1.0 / hp.box[k]);
+    pp.cs[k] = (T)hp.cs[k];
     pp.per[k] = hp.periodic[k];
     pp.nc[k] = hp.nc[k];
   }
+  pp.ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
   const double a = hp.a;
   pp.a2 = (T)(a * a);
   pp.inv_a2 = (T)(1.0 / (a * a));
@@ -209,60 +207,120 @@ PairParams<T> pair_params(const HostPlan& hp) {
   return pp;
 }
 
-// Nested grid pass of eq. (u_oneplus_nested_eval): from the level-1 grid in
-// qg[0] to e^{1+} in eg[0] (restriction, per-level stencils and the dense top
-// level, prolongation).  Clears eg[*] first.
+// Accumulators a grid pass adds into atomically (the FP64 convolution
+// buffers of levels whose stencil planes are split across workgroups); they
+// must be zero when grid_pass starts.
 template <typename T>
-void grid_pass(msm_plan P, hipStream_t s) {
+void grid_zero_jobs(msm_plan P, ZeroJobs& z) {
+  const HostPlan& hp = P->hp;
+  const int zero3[3] = {0, 0, 0};
+  for (int l = 1; l <= hp.L; ++l) {
+    const LevelGeom& g = hp.lev[l - 1];
+    const ConvParams cp = g.factored ? make_conv_params(g.n, g.next, g.shift, hp.periodic,
+                                                        g.s_off, g.s_len, sizeof(T))
+                                     : make_conv_params(g.n, g.n, zero3, hp.periodic, g.off,
+                                                        g.len, sizeof(T));
+    if (cp.nsplit > 1 && z.n < kZeroJobs) {
+      z.ptr[z.n] = P->ug[l - 1];
+      z.words[z.n] = 2 * (g.factored ? g.Gext : g.G);
+      z.n += 1;
+    }
+  }
+}
+
+// One level of eq. (u_oneplus_nested_eval): e^l = K^l q~^l into eg[l-1].
+template <typename T>
+void conv_level(msm_plan P, int l, hipStream_t s) {
+  const HostPlan& hp = P->hp;
+  StageProfiler& pf = P->prof;
+  static const char* conv_names[kMaxLevels] = {
+      "conv_l1", "conv_l2", "conv_l3", "conv_l4", "conv_l5", "conv_l6", "conv_l7", "conv_l8",
+      "conv_l9", "conv_l10", "conv_l11", "conv_l12", "conv_l13", "conv_l14", "conv_l15", "conv_l16"};
+  static const char* omega_names[kMaxLevels] = {
+      "omega_l1", "omega_l2", "omega_l3", "omega_l4", "omega_l5", "omega_l6",
+      "omega_l7", "omega_l8", "omega_l9", "omega_l10", "omega_l11", "omega_l12",
+      "omega_l13", "omega_l14", "omega_l15", "omega_l16"};
+  const LevelGeom& g = hp.lev[l - 1];
+  const char* cname = l == hp.L ? "conv_top" : conv_names[l - 1];
+  if (g.factored) {
+    // K^l q = omega' * (S^l * q): FP64 sample convolution, then omega' per axis
+    ConvParams cs = make_conv_params(g.n, g.next, g.shift, hp.periodic, g.s_off, g.s_len,
+                                     sizeof(T));
+    int ev = pf.begin(cname, s);
+    launch_conv<T, double>(cs, P->S[l - 1], P->srowext[l - 1], (const T*)P->qg[l - 1],
+                           P->ug[l - 1], s);
+    pf.end(ev, s);
+    OmegaParams op;
+    for (int k = 0; k < 3; ++k) {
+      op.n[k] = g.n[k];
+      op.next[k] = g.next[k];
+      op.per[k] = hp.periodic[k];
+    }
+    op.M = hp.M;
+    for (int k = 0; k < 25; ++k) op.omega[k] = k <= hp.M ? hp.omega[k] : 0.0;
+    ev = pf.begin(omega_names[l - 1], s);
+    launch_omega<T>(op, P->ug[l - 1], (T*)P->eg[l - 1], s);
+    pf.end(ev, s);
+  } else {
+    // direct stencil, accumulated in FP64 (sums of thousands of terms with
+    // cancellation), then rounded to the grid precision
+    const int zero3[3] = {0, 0, 0};
+    ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
+    int ev = pf.begin(cname, s);
+    launch_conv<T, double>(cp, P->K64[l - 1], P->rowext64[l - 1], (const T*)P->qg[l - 1],
+                           P->ug[l - 1], s);
+    pf.end(ev, s);
+    ev = pf.begin("grid_cast", s);
+    launch_cast<T>(P->ug[l - 1], (T*)P->eg[l - 1], g.G, s);
+    pf.end(ev, s);
+  }
+}
+
+// Nested grid pass of eq. (u_oneplus_nested_eval): from the level-1 grid in
+// qg[0] to e^{1+} in eg[0].  Two branches: the coarse one (restriction,
+// levels 2..L, prolongation down to level 2) on sb, level 1 on sa; they join
+// before the last prolongation.  sb == sa runs everything in order.  Every
+// eg[l] is overwritten (omega' or cast) before prolongation adds into it.
+template <typename T>
+void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb) {
   const HostPlan& hp = P->hp;
   const int L = hp.L, p = hp.p;
   StageProfiler& pf = P->prof;
-  for (int l = 1; l <= L; ++l) launch_fill<T>((T*)P->eg[l - 1], hp.lev[l - 1].G, T(0), s);
-  int ev = pf.begin("restrict", s);
+  const bool fork = sb != sa && L > 1;
+  if (fork) {
+    (void)hipEventRecord(P->ev[2], sa);
+    (void)hipStreamWaitEvent(sb, P->ev[2], 0);
+  }
+  hipStream_t sc = fork ? sb : sa;
+  int ev = pf.begin("restrict", sc);
   for (int l = 1; l < L; ++l)
     launch_restrict<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
-                       (const T*)P->qg[l - 1], (T*)P->qg[l], s);
-  pf.end(ev, s);
-  static const char* names[kMaxLevels] = {"conv_l1", "conv_l2", "conv_l3", "conv_l4",
-                                          "conv_l5", "conv_l6", "conv_l7", "conv_l8",
-                                          "conv_l9", "conv_l10", "conv_l11", "conv_l12",
-                                          "conv_l13", "conv_l14", "conv_l15", "conv_l16"};
-  const int zero3[3] = {0, 0, 0};
-  for (int l = 1; l <= L; ++l) {
-    const LevelGeom& g = hp.lev[l - 1];
-    ev = pf.begin(l == L ? "conv_top" : names[l - 1], s);
-    if (g.factored) {
-      // K^l q = omega' * (S^l * q): FP64 sample convolution, then omega' per axis
-      ConvParams cs = make_conv_params(g.n, g.next, g.shift, hp.periodic, g.s_off, g.s_len,
-                                       sizeof(T));
-      if (cs.nsplit > 1) launch_fill<double>(P->ug[l - 1], g.Gext, 0.0, s);
-      launch_conv<T, double>(cs, P->S[l - 1], P->srowext[l - 1], (const T*)P->qg[l - 1],
-                             P->ug[l - 1], s);
-      OmegaParams op;
-      for (int k = 0; k < 3; ++k) {
-        op.n[k] = g.n[k];
-        op.next[k] = g.next[k];
-        op.per[k] = hp.periodic[k];
-      }
-      op.M = hp.M;
-      for (int k = 0; k < 25; ++k) op.omega[k] = k <= hp.M ? hp.omega[k] : 0.0;
-      launch_omega<T>(op, P->ug[l - 1], (T*)P->eg[l - 1], s);
-    } else {
-      // direct stencil, accumulated in FP64 (sums of thousands of terms with
-      // cancellation), then rounded to the grid precision
-      ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
-      if (cp.nsplit > 1) launch_fill<double>(P->ug[l - 1], g.G, 0.0, s);
-      launch_conv<T, double>(cp, P->K64[l - 1], P->rowext64[l - 1], (const T*)P->qg[l - 1],
-                             P->ug[l - 1], s);
-      launch_cast<T>(P->ug[l - 1], (T*)P->eg[l - 1], g.G, s);
-    }
-    pf.end(ev, s);
-  }
-  ev = pf.begin("prolong", s);
-  for (int l = L - 1; l >= 1; --l)
+                       (const T*)P->qg[l - 1], (T*)P->qg[l], sc);
+  pf.end(ev, sc);
+  for (int l = 2; l <= L; ++l) conv_level<T>(P, l, sc);
+  ev = pf.begin("prolong", sc);
+  for (int l = L - 1; l >= 2; --l)
     launch_prolong<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
-                      (const T*)P->eg[l], (T*)P->eg[l - 1], s);
-  pf.end(ev, s);
+                      (const T*)P->eg[l], (T*)P->eg[l - 1], sc);
+  pf.end(ev, sc);
+  if (fork) (void)hipEventRecord(P->ev[3], sb);
+  conv_level<T>(P, 1, sa);
+  if (fork) (void)hipStreamWaitEvent(sa, P->ev[3], 0);
+  if (L > 1) {
+    ev = pf.begin("prolong", sa);
+    launch_prolong<T>(p, grid_dev<T>(hp, 1), grid_dev<T>(hp, 2), hp.J, (const T*)P->eg[1],
+                      (T*)P->eg[0], sa);
+    pf.end(ev, sa);
+  }
+}
+
+// Whether the forward runs as a DAG over three streams (MSM_STREAMS=0: one).
+static bool use_streams() {
+  static const bool on = [] {
+    const char* e = getenv("MSM_STREAMS");
+    return !(e && atoi(e) == 0);
+  }();
+  return on;
 }
 
 template <typename T>
@@ -288,14 +346,24 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
     save_e1 = (T*)(b + w.e1);
   }
   StageProfiler& pf = P->prof;
-  // clear accumulators (fill kernels rather than memsets: graph-safe)
+  // clear accumulators with one kernel (not a memset: graph-safe)
   int ev = pf.begin("fill", s);
-  launch_fill<int>(P->counts, P->ncell, 0, s);
-  launch_fill<T>((T*)P->qg[0], hp.lev[0].G, T(0), s);
-  launch_fill<double>(energy, 1, 0.0, s);
+  {
+    ZeroJobs z;
+    z.n = 0;
+    z.ptr[z.n] = P->counts;
+    z.words[z.n++] = P->ncell;
+    z.ptr[z.n] = P->qg[0];
+    z.words[z.n++] = hp.lev[0].G * (long long)(sizeof(T) / 4);
+    z.ptr[z.n] = energy;
+    z.words[z.n++] = 2;
+    grid_zero_jobs<T>(P, z);
+    launch_zero_multi(z, s);
+  }
   pf.end(ev, s);
 
-  // a1 binning
+  // a1 binning (cell counts, scans of cell starts and cluster offsets,
+  // scatter), then Morton order inside cells and the 8-particle clusters
   BinParams<T> bp;
   for (int k = 0; k < 3; ++k) {
     bp.box[k] = (T)hp.box[k];
@@ -305,22 +373,41 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   }
   ev = pf.begin("bin", s);
   launch_binning<T>(n, pos, q, bp, P->ncell, P->cell_of, P->rank, P->counts,
-                    (vec4_t<T>*)P->wrapped, start, sorted, perm, P->flag, s);
+                    (vec4_t<T>*)P->wrapped, start, P->cl_start, sorted, perm, P->flag, s);
+  pf.end(ev, s);
+  ev = pf.begin("cluster", s);
+  launch_cluster_layout<T>(1, 0, P->ncell, start, P->cl_start, bp, (const vec4_t<T>*)P->wrapped,
+                           sorted, perm, (vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cbox, P->cinfo, s);
   pf.end(ev, s);
 
-  // a2 short-range pairs
+  // a2 short-range pairs (8 x 8 cluster pairs), on its own stream: it only
+  // needs the cluster layout, and interpolation waits for it
+  const bool dag = use_streams();
+  hipStream_t sp = dag ? P->sc : s;
+  if (dag) {
+    (void)hipEventRecord(P->ev[0], s);
+    (void)hipStreamWaitEvent(sp, P->ev[0], 0);
+  }
   const PairParams<T> pp = pair_params<T>(hp);
-  ev = pf.begin("pair", s);
-  launch_pair<T>(p, P->ncell, sorted, start, pp, (double*)P->phi0, (T*)P->F0, s);
-  pf.end(ev, s);
+  ev = pf.begin("pair", sp);
+  launch_pair_cl<T>(p, n, P->ncell, P->cl_start, (const vec4_t<T>*)P->cpos,
+                    (const vec4_t<T>*)P->cbox, P->cinfo, pp, (double*)P->phi0, (T*)P->F0, sp);
+  pf.end(ev, sp);
+  if (dag) (void)hipEventRecord(P->ev[1], sp);
 
   // a3 anterpolation onto level 1
   const GridDev<T> g1 = grid_dev<T>(hp, 1);
   ev = pf.begin("anterp", s);
-  launch_anterp<T>(p, n, sorted, g1, (T*)P->qg[0], s);
+  CellGrid cg;
+  for (int k = 0; k < 3; ++k) {
+    cg.nc[k] = hp.nc[k];
+    cg.cs[k] = hp.cs[k];
+  }
+  launch_anterp<T>(p, n, P->ncell, start, cg, sorted, g1, (T*)P->qg[0], s);
   pf.end(ev, s);
   // a4 restriction, a5 per-level stencils, a6 top level, a7 prolongation
-  grid_pass<T>(P, s);
+  grid_pass<T>(P, s, dag ? P->sb : s);
+  if (dag) (void)hipStreamWaitEvent(s, P->ev[1], 0);
   // a8 + a9 interpolation, combination, energy
   ev = pf.begin("interp", s);
   launch_interp<T>(p, n, sorted, perm, g1, (const T*)P->eg[0], (const double*)P->phi0,
@@ -358,14 +445,36 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
   T* gr_sr = (T*)P->F0;
   int ev = pf.begin("bwd_pair", s);
   launch_gather_v<T>(n, perm, gF, v, s);
-  launch_pair_vjp<T>(p, P->ncell, sorted, v, start, pair_params<T>(hp), gq_sr, gr_sr, s);
+  {
+    // cluster layout of the saved (already Morton-ordered) cell list
+    BinParams<T> bp;
+    for (int k = 0; k < 3; ++k) {
+      bp.box[k] = (T)hp.box[k];
+      bp.cs[k] = (T)hp.cs[k];
+      bp.nc[k] = hp.nc[k];
+      bp.per[k] = hp.periodic[k];
+    }
+    launch_cluster_layout<T>(0, 1, P->ncell, start, P->cl_start, bp, nullptr,
+                             const_cast<vec4_t<T>*>(sorted), const_cast<int*>(perm),
+                             (vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cbox, P->cinfo, s);
+  }
+  launch_pair_vjp_cl<T>(p, n, P->ncell, P->cl_start, P->cinfo, perm, gF,
+                        (const vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cv, (const vec4_t<T>*)P->cbox,
+                        pair_params<T>(hp), gq_sr, gr_sr, s);
   pf.end(ev, s);
   const GridDev<T> g1 = grid_dev<T>(hp, 1);
   ev = pf.begin("bwd_anterp", s);
-  launch_fill<T>((T*)P->qg[0], hp.lev[0].G, T(0), s);
+  {
+    ZeroJobs z;
+    z.n = 0;
+    z.ptr[z.n] = P->qg[0];
+    z.words[z.n++] = hp.lev[0].G * (long long)(sizeof(T) / 4);
+    grid_zero_jobs<T>(P, z);
+    launch_zero_multi(z, s);
+  }
   launch_anterp_dipole<T>(p, n, sorted, v, g1, (T*)P->qg[0], s);
   pf.end(ev, s);
-  grid_pass<T>(P, s);  // eg[0] = (A D)^{1+}
+  grid_pass<T>(P, s, s);  // eg[0] = (A D)^{1+}
   ev = pf.begin("bwd_interp", s);
   launch_interp_vjp<T>(p, n, sorted, v, perm, g1, save_e1, (const T*)P->eg[0], save_phi, save_F,
                        gq_sr, gr_sr, gE, grad_q, grad_pos, s);

@@ -33,102 +33,6 @@ __global__ void k_gather_v(int n, const int* __restrict__ perm, const T* __restr
   v[i] = t;
 }
 
-__device__ inline int neighbour_cell_b(int c, int o, int nc, int per) {
-  if (per) {
-    if (nc == 1) return o == 0 ? 0 : -1;
-    if (nc == 2) return o < 0 ? -1 : (c + o) & 1;
-    const int v = c + o;
-    return v < 0 ? v + nc : (v >= nc ? v - nc : v);
-  }
-  const int v = c + o;
-  return (v >= 0 && v < nc) ? v : -1;
-}
-
-template <typename T, int P>
-__global__ void __launch_bounds__(kPairThreads)
-    k_pair_vjp(const vec4_t<T>* __restrict__ sorted, const vec4_t<T>* __restrict__ v,
-               const int* __restrict__ start, PairParams<T> pp, T* __restrict__ gq,
-               T* __restrict__ gr) {
-  __shared__ vec4_t<T> tile[kPairThreads];
-  __shared__ vec4_t<T> vtile[kPairThreads];
-  const int cell = blockIdx.x;
-  const int cx = cell % pp.nc[0];
-  const int cy = (cell / pp.nc[0]) % pp.nc[1];
-  const int cz = cell / (pp.nc[0] * pp.nc[1]);
-  const int i_beg = start[cell], i_end = start[cell + 1];
-  for (int ib = i_beg; ib < i_end; ib += kPairThreads) {
-    const int i = ib + (int)threadIdx.x;
-    const bool active = i < i_end;
-    vec4_t<T> pi, vi;
-    if (active) {
-      pi = sorted[i];
-      vi = v[i];
-    } else {
-      pi.x = pi.y = pi.z = pi.w = T(0);
-      vi.x = vi.y = vi.z = vi.w = T(0);
-    }
-    T sq = T(0), rx = T(0), ry = T(0), rz = T(0);
-    for (int oz = -1; oz <= 1; ++oz) {
-      const int nz = neighbour_cell_b(cz, oz, pp.nc[2], pp.per[2]);
-      if (nz < 0) continue;
-      for (int oy = -1; oy <= 1; ++oy) {
-        const int ny = neighbour_cell_b(cy, oy, pp.nc[1], pp.per[1]);
-        if (ny < 0) continue;
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int nx = neighbour_cell_b(cx, ox, pp.nc[0], pp.per[0]);
-          if (nx < 0) continue;
-          const int nc_ = (nz * pp.nc[1] + ny) * pp.nc[0] + nx;
-          const int j_beg = start[nc_], j_end = start[nc_ + 1];
-          for (int jb = j_beg; jb < j_end; jb += kPairThreads) {
-            __syncthreads();
-            if (jb + (int)threadIdx.x < j_end) {
-              tile[threadIdx.x] = sorted[jb + threadIdx.x];
-              vtile[threadIdx.x] = v[jb + threadIdx.x];
-            }
-            __syncthreads();
-            const int cnt = min(kPairThreads, j_end - jb);
-            for (int jj = 0; jj < cnt; ++jj) {
-              const vec4_t<T> pj = tile[jj];
-              T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-              if (pp.per[0]) dx -= pp.box[0] * rint(dx * pp.inv_box[0]);
-              if (pp.per[1]) dy -= pp.box[1] * rint(dy * pp.inv_box[1]);
-              if (pp.per[2]) dz -= pp.box[2] * rint(dz * pp.inv_box[2]);
-              const T r2 = dx * dx + dy * dy + dz * dz;
-              if (r2 < pp.a2 && jb + jj != i) {
-                const vec4_t<T> vj = vtile[jj];
-                const T rinv = rsqrt_t(r2);
-                const T rinv2 = rinv * rinv;
-                const T t = r2 * pp.inv_a2;
-                T dP = pp.dc[P - 2], d2P = pp.d2c[P - 3];
-#pragma unroll
-                for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
-#pragma unroll
-                for (int k = P - 4; k >= 0; --k) d2P = d2P * t + pp.d2c[k];
-                const T f = rinv * rinv2 + T(2) * dP * pp.inv_a3;
-                const T fpr = T(-3) * rinv2 * rinv2 * rinv + T(4) * d2P * pp.inv_a5;
-                const T wx = vi.x - vj.x, wy = vi.y - vj.y, wz = vi.z - vj.z;
-                const T wd = wx * dx + wy * dy + wz * dz;
-                sq += pj.w * f * wd;
-                const T c2 = pj.w * fpr * wd;
-                rx += pj.w * f * wx + c2 * dx;
-                ry += pj.w * f * wy + c2 * dy;
-                rz += pj.w * f * wz + c2 * dz;
-              }
-            }
-          }
-        }
-      }
-    }
-    if (active) {
-      gq[i] = sq;
-      gr[3 * i] = pi.w * rx;
-      gr[3 * i + 1] = pi.w * ry;
-      gr[3 * i + 2] = pi.w * rz;
-    }
-  }
-}
-
-// D_m += q_i v_i . grad phi_m(r_i) on the level-1 grid.
 template <typename T, int P>
 __global__ void k_anterp_dipole(int n, const vec4_t<T>* __restrict__ sorted,
                                 const vec4_t<T>* __restrict__ v, GridDev<T> g,
@@ -292,17 +196,6 @@ void launch_gather_v(int n, const int* perm, const T* gF, vec4_t<T>* v, hipStrea
 }
 
 template <typename T>
-void launch_pair_vjp(int p, int ncell, const vec4_t<T>* sorted, const vec4_t<T>* v,
-                     const int* start, const PairParams<T>& pp, T* gq, T* gr, hipStream_t s) {
-  if (ncell <= 0) return;
-  switch (p) {
-    case 4: hipLaunchKernelGGL((k_pair_vjp<T, 4>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, v, start, pp, gq, gr); break;
-    case 6: hipLaunchKernelGGL((k_pair_vjp<T, 6>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, v, start, pp, gq, gr); break;
-    case 8: hipLaunchKernelGGL((k_pair_vjp<T, 8>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, v, start, pp, gq, gr); break;
-  }
-}
-
-template <typename T>
 void launch_anterp_dipole(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v,
                           const GridDev<T>& g, T* grid, hipStream_t s) {
   if (n <= 0) return;
@@ -338,8 +231,6 @@ void launch_grad_energy_only(int n, const int* perm, const T* save_phi, const T*
 
 #define MSM_INST_BACKWARD(T)                                                                      \
   template void launch_gather_v<T>(int, const int*, const T*, vec4_t<T>*, hipStream_t);           \
-  template void launch_pair_vjp<T>(int, int, const vec4_t<T>*, const vec4_t<T>*, const int*,      \
-                                   const PairParams<T>&, T*, T*, hipStream_t);                    \
   template void launch_anterp_dipole<T>(int, int, const vec4_t<T>*, const vec4_t<T>*,             \
                                         const GridDev<T>&, T*, hipStream_t);                      \
   template void launch_interp_vjp<T>(int, int, const vec4_t<T>*, const vec4_t<T>*, const int*,    \

@@ -29,6 +29,8 @@
 
 namespace msm {
 
+constexpr int kPairThreads = 128;  // brute-force pair kernel of the batch path
+
 struct ConvTask {
   long long goff;  // grid offset of the system's level grid
   int n;           // cubic grid size
@@ -571,6 +573,7 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
     pp.box[k] = pp.inv_box[k] = 0;
     pp.per[k] = 0;
     pp.nc[k] = 1;
+    pp.cs[k] = 0;
   }
   const T* boxes = (const T*)B.d_box;
   int ev = P->prof.begin("batch_pair", s);

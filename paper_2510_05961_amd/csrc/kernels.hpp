@@ -5,8 +5,6 @@
 
 namespace msm {
 
-constexpr int kPairThreads = 128;
-
 template <typename T>
 struct BinParams {
   T box[3];
@@ -18,8 +16,10 @@ struct BinParams {
 template <typename T>
 struct PairParams {
   T box[3], inv_box[3];
+  T cs[3];     // cell edge
   int per[3];
   int nc[3];
+  int ncell;
   T a2, inv_a2, inv_a, inv_a3, inv_a5;
   T c[8];    // softening polynomial in t = (r/a)^2
   T dc[8];   // its t-derivative: dc[k] = (k+1) c[k+1]
@@ -35,9 +35,13 @@ struct ConvParams {
   int off[3], len[3];   // stencil offsets d_k = off_k .. off_k + len_k - 1
   int dz_per_split;     // stencil z-planes handled by one workgroup
   int nsplit;
+  int lxp;              // row stride of the stencil (len[0] + kConvCH - 1, zero padded)
   int lds_w, lds_h;     // staged input tile
-  int small;            // 16 x 16 tiles (else 64 x 32)
+  int shape;            // tile shape (kernels_grid.hip)
 };
+constexpr int kConvCH = 4;      // taps per register window of the convolution
+constexpr int kConvRowPad = 3;  // zero rows around each stencil plane (Q - 1 for Q <= 4)
+int conv_row_stride(int len0);
 
 // restriction taps J_{-p/2..p/2} passed by value
 template <typename T>
@@ -54,16 +58,43 @@ struct OmegaParams {
   double omega[25];
 };
 
+// Binning: counts, the scans of cell starts and cluster offsets (cl_start),
+// and the scatter into cell order.
 template <typename T>
 void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
                     int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
-                    vec4_t<T>* sorted, int* perm, int* flag, hipStream_t s);
+                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag, hipStream_t s);
+
+// Zero several buffers (sizes in 4-byte words) with one launch.
+constexpr int kZeroJobs = 24;
+struct ZeroJobs {
+  void* ptr[kZeroJobs];
+  long long words[kZeroJobs];
+  int n;
+};
+void launch_zero_multi(const ZeroJobs& jobs, hipStream_t s);
+// Cluster layout of the cell-sorted particles (sort != 0: also reorders each
+// cell along a Morton curve, in place) and the short-range pair sum over 8 x 8
+// cluster pairs.  Buffers hold cluster_capacity(n, ncell) clusters.
+int cluster_capacity(int n, int ncell);
+// scan != 0: compute cl_start from start here (else it is already there)
 template <typename T>
-void launch_pair(int p, int ncell, const vec4_t<T>* sorted, const int* start,
-                 const PairParams<T>& pp, double* phi0, T* F0, hipStream_t s);
+void launch_cluster_layout(int sort, int scan, int ncell, const int* start, int* cl_start,
+                           const BinParams<T>& bp, const vec4_t<T>* wrapped, vec4_t<T>* sorted,
+                           int* perm, vec4_t<T>* cpos, vec4_t<T>* cbox, int4* cinfo,
+                           hipStream_t s);
 template <typename T>
-void launch_anterp(int p, int n, const vec4_t<T>* sorted, const GridDev<T>& g, T* grid,
-                   hipStream_t s);
+void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
+                    const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
+                    double* phi0, T* F0, hipStream_t s);
+// cell list geometry in FP64 (bricks of the staged anterpolation)
+struct CellGrid {
+  int nc[3];
+  double cs[3];
+};
+template <typename T>
+void launch_anterp(int p, int n, int ncell, const int* start, const CellGrid& cg,
+                   const vec4_t<T>* sorted, const GridDev<T>& g, T* grid, hipStream_t s);
 template <typename T>
 void launch_interp(int p, int n, const vec4_t<T>* sorted, const int* perm, const GridDev<T>& g,
                    const T* e1, const double* phi0, const T* F0, double self_const, T* dEdq,
@@ -96,8 +127,10 @@ void launch_cast(const double* src, T* dst, long long count, hipStream_t s);
 template <typename T>
 void launch_gather_v(int n, const int* perm, const T* gF, vec4_t<T>* v, hipStream_t s);
 template <typename T>
-void launch_pair_vjp(int p, int ncell, const vec4_t<T>* sorted, const vec4_t<T>* v,
-                     const int* start, const PairParams<T>& pp, T* gq, T* gr, hipStream_t s);
+void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4* cinfo,
+                        const int* perm, const T* gF, const vec4_t<T>* cpos, vec4_t<T>* cv,
+                        const vec4_t<T>* cbox, const PairParams<T>& pp, T* gq, T* gr,
+                        hipStream_t s);
 template <typename T>
 void launch_anterp_dipole(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v,
                           const GridDev<T>& g, T* grid, hipStream_t s);

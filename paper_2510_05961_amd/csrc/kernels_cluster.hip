@@ -1,0 +1,445 @@
+// kernels_cluster.hip -- the short-range part U^0 (eq. U_zero) as a sum over
+// 8 x 8 cluster pairs, and its vector-Jacobian product.
+//
+// Layout.  Binning sorts particles by cell (cells of edge >= a).  Inside
+// every cell the particles are then ordered along a Morton curve of a 16^3
+// sub-grid (ties broken by the caller's index, so the order is
+// deterministic) and cut into clusters of 8 consecutive particles; the last
+// cluster of a cell is padded with far-away zero charges.  Each cluster keeps
+// its bounding box.
+//
+// Pair sum.  One wave per i-cluster.  Lane (il, jl) = (lane / 8, lane % 8)
+// holds i-member il and, for every j-cluster that survives the box test,
+// evaluates the pair (il, jl) of the 8 x 8 block.  Periodic images are
+// handled by a uniform shift per neighbour cell (27 offsets, each (cell,
+// shift) combination distinct), which is exact whenever the cell edge is >= a
+// and every periodic edge is >= 2a: then at most one image of a particle lies
+// inside the cutoff and it lies in one of the 27 shifted neighbour cells.
+#include "kernels.hpp"
+
+namespace msm {
+
+constexpr int kClusterThreads = 256;  // 4 waves = 4 i-clusters per workgroup
+constexpr int kPrepThreads = 256;
+constexpr int kPrepSortMax = 4096;    // cells larger than this keep their order
+
+// Cluster offsets: cl_start[c] = sum_{c' < c} ceil(count_c' / 8), one workgroup.
+__global__ void __launch_bounds__(1024) k_cluster_scan(int ncell, const int* __restrict__ start,
+                                                       int* __restrict__ cl_start) {
+  __shared__ int buf[1024];
+  __shared__ int carry;
+  const int t = threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < ncell; base += 1024) {
+    const int c = base + t;
+    const int v = c < ncell ? (start[c + 1] - start[c] + 7) / 8 : 0;
+    buf[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int add = (t >= off) ? buf[t - off] : 0;
+      __syncthreads();
+      buf[t] += add;
+      __syncthreads();
+    }
+    if (c < ncell) cl_start[c] = carry + buf[t] - v;
+    __syncthreads();
+    if (t == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+  if (t == 0) cl_start[ncell] = carry;
+}
+
+__device__ inline unsigned spread3(unsigned v) {  // 4 bits -> every third bit
+  v &= 0xF;
+  v = (v | (v << 4)) & 0x0C3;
+  v = (v | (v << 2)) & 0x249;
+  return v;
+}
+
+// One workgroup per cell.  With sort != 0 the cell's particles are reordered
+// in place (sorted[], perm[] of the segment; positions re-read from wrapped[]
+// in the caller's order); the cluster slots, boxes and info are written in
+// both modes from the (possibly new) order.
+template <typename T>
+__global__ void __launch_bounds__(kPrepThreads)
+    k_cluster_prep(int sort, const int* __restrict__ start, const int* __restrict__ cl_start,
+                   BinParams<T> bp, const vec4_t<T>* __restrict__ wrapped,
+                   vec4_t<T>* __restrict__ sorted, int* __restrict__ perm,
+                   vec4_t<T>* __restrict__ cpos, vec4_t<T>* __restrict__ cbox,
+                   int4* __restrict__ cinfo) {
+  __shared__ unsigned long long key[kPrepSortMax];
+  const int cell = blockIdx.x;
+  const int t = threadIdx.x;
+  const int beg = start[cell], cnt = start[cell + 1] - beg;
+  const int cbeg = cl_start[cell], ncl = cl_start[cell + 1] - cbeg;
+  if (cnt == 0) return;
+  const int cx = cell % bp.nc[0];
+  const int cy = (cell / bp.nc[0]) % bp.nc[1];
+  const int cz = cell / (bp.nc[0] * bp.nc[1]);
+  if (sort && cnt > 1 && cnt <= kPrepSortMax) {
+    int npow = 1;
+    while (npow < cnt) npow <<= 1;
+    const T lo[3] = {(T)cx * bp.cs[0], (T)cy * bp.cs[1], (T)cz * bp.cs[2]};
+    for (int i = t; i < npow; i += kPrepThreads) {
+      unsigned long long k = ~0ull;
+      if (i < cnt) {
+        const vec4_t<T> v = sorted[beg + i];
+        const T x[3] = {v.x, v.y, v.z};
+        unsigned m = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          int s = (int)((x[d] - lo[d]) * (T(16) / bp.cs[d]));
+          s = s < 0 ? 0 : (s > 15 ? 15 : s);
+          m |= spread3((unsigned)s) << d;
+        }
+        k = ((unsigned long long)m << 32) | (unsigned)perm[beg + i];
+      }
+      key[i] = k;
+    }
+    __syncthreads();
+    // bitonic sort of key[0 .. npow)
+    for (int k = 2; k <= npow; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = t; i < npow; i += kPrepThreads) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const unsigned long long a = key[i], b = key[ixj];
+            const bool up = (i & k) == 0;
+            if ((a > b) == up) {
+              key[i] = b;
+              key[ixj] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = t; i < cnt; i += kPrepThreads) {
+      const int src = (int)(key[i] & 0xFFFFFFFFu);
+      sorted[beg + i] = wrapped[src];
+      perm[beg + i] = src;
+    }
+    __syncthreads();
+  }
+  // padded cluster slots (read back through sorted[]: each thread reads what
+  // it or another thread of this workgroup wrote before the barrier above)
+  for (int s = t; s < ncl * 8; s += kPrepThreads) {
+    vec4_t<T> v;
+    if (s < cnt) {
+      v = sorted[beg + s];
+    } else {  // padding: a zero charge far outside every cutoff
+      v.x = v.y = v.z = T(1e15);
+      v.w = T(0);
+    }
+    cpos[(size_t)cbeg * 8 + s] = v;
+  }
+  for (int c = t; c < ncl; c += kPrepThreads) {
+    const int m = min(8, cnt - 8 * c);
+    vec4_t<T> lo, hi;
+    lo = sorted[beg + 8 * c];
+    hi = lo;
+    for (int r = 1; r < m; ++r) {
+      const vec4_t<T> v = sorted[beg + 8 * c + r];
+      lo.x = min(lo.x, v.x);
+      lo.y = min(lo.y, v.y);
+      lo.z = min(lo.z, v.z);
+      hi.x = max(hi.x, v.x);
+      hi.y = max(hi.y, v.y);
+      hi.z = max(hi.z, v.z);
+    }
+    cbox[2 * (size_t)(cbeg + c)] = lo;
+    cbox[2 * (size_t)(cbeg + c) + 1] = hi;
+    cinfo[cbeg + c] = make_int4(beg + 8 * c, m, cell, 0);
+  }
+}
+
+// Neighbour cell along one axis at offset o in {-1, 0, 1}: the cell index
+// (or -1 outside a free axis) and the image shift in units of the box edge.
+__device__ inline int neighbour_shift(int c, int o, int nc, int per, int& sh) {
+  const int v = c + o;
+  sh = 0;
+  if (per) {
+    if (v < 0) {
+      sh = -1;
+      return v + nc;
+    }
+    if (v >= nc) {
+      sh = 1;
+      return v - nc;
+    }
+    return v;
+  }
+  return (v >= 0 && v < nc) ? v : -1;
+}
+
+template <typename T>
+__device__ inline T box_gap2(T jlo_x, T jlo_y, T jlo_z, T jhi_x, T jhi_y, T jhi_z, T ilo_x,
+                             T ilo_y, T ilo_z, T ihi_x, T ihi_y, T ihi_z) {
+  const T gx = max(T(0), max(jlo_x - ihi_x, ilo_x - jhi_x));
+  const T gy = max(T(0), max(jlo_y - ihi_y, ilo_y - jhi_y));
+  const T gz = max(T(0), max(jlo_z - ihi_z, ilo_z - jhi_z));
+  return gx * gx + gy * gy + gz * gz;
+}
+
+// Sum over the 8 lanes of one i-member (lanes 8 il .. 8 il + 7).
+template <typename V>
+__device__ inline V sum8(V v) {
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 1);
+  return v;
+}
+
+// Visits every j-cluster whose box (shifted image) lies within the cutoff of
+// the i-cluster's box and calls body(jc, sx, sy, sz, self_block) uniformly
+// over the wave.  The i-box and everything below are wave-uniform.
+template <typename T, typename Body>
+__device__ inline void for_each_cluster_pair(const PairParams<T>& pp, const int* cl_start,
+                                             const vec4_t<T>* cbox, int ic, int cell,
+                                             const vec4_t<T>& blo, const vec4_t<T>& bhi,
+                                             Body&& body) {
+  const int lane = threadIdx.x & 63;
+  const int cx = cell % pp.nc[0];
+  const int cy = (cell / pp.nc[0]) % pp.nc[1];
+  const int cz = cell / (pp.nc[0] * pp.nc[1]);
+  for (int oz = -1; oz <= 1; ++oz) {
+    int shz;
+    const int nz = neighbour_shift(cz, oz, pp.nc[2], pp.per[2], shz);
+    if (nz < 0) continue;
+    const T sz = (T)shz * pp.box[2];
+    for (int oy = -1; oy <= 1; ++oy) {
+      int shy;
+      const int ny = neighbour_shift(cy, oy, pp.nc[1], pp.per[1], shy);
+      if (ny < 0) continue;
+      const T sy = (T)shy * pp.box[1];
+      for (int ox = -1; ox <= 1; ++ox) {
+        int shx;
+        const int nx = neighbour_shift(cx, ox, pp.nc[0], pp.per[0], shx);
+        if (nx < 0) continue;
+        const T sx = (T)shx * pp.box[0];
+        // i-box moved by minus the shift of the j image
+        const T ilx = blo.x - sx, ily = blo.y - sy, ilz = blo.z - sz;
+        const T ihx = bhi.x - sx, ihy = bhi.y - sy, ihz = bhi.z - sz;
+        // whole-cell test with a margin for the rounding of the binning
+        {
+          const T mx = pp.cs[0] * T(1e-3), my = pp.cs[1] * T(1e-3), mz = pp.cs[2] * T(1e-3);
+          const T g2 = box_gap2<T>((T)nx * pp.cs[0] - mx, (T)ny * pp.cs[1] - my,
+                                   (T)nz * pp.cs[2] - mz, (T)(nx + 1) * pp.cs[0] + mx,
+                                   (T)(ny + 1) * pp.cs[1] + my, (T)(nz + 1) * pp.cs[2] + mz,
+                                   ilx, ily, ilz, ihx, ihy, ihz);
+          if (!(g2 < pp.a2)) continue;
+        }
+        const int ncell = (nz * pp.nc[1] + ny) * pp.nc[0] + nx;
+        const int jb0 = cl_start[ncell], jb1 = cl_start[ncell + 1];
+        const bool zero_shift = (shx | shy | shz) == 0;
+        for (int jb = jb0; jb < jb1; jb += 64) {
+          const int jc = jb + lane;
+          bool hit = false;
+          if (jc < jb1) {
+            const vec4_t<T> lo = cbox[2 * (size_t)jc], hi = cbox[2 * (size_t)jc + 1];
+            hit = box_gap2<T>(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, ilx, ily, ilz, ihx, ihy, ihz) <
+                  pp.a2;
+          }
+          unsigned long long mask = __ballot(hit);
+          while (mask) {
+            const int b = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+            const int j = jb + b;
+            body(j, sx, sy, sz, zero_shift && j == ic);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(kClusterThreads)
+    k_pair_cl(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
+              const vec4_t<T>* __restrict__ cbox, const int4* __restrict__ cinfo,
+              PairParams<T> pp, double* __restrict__ phi0, T* __restrict__ F0) {
+  const int lane = threadIdx.x & 63;
+  const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * (kClusterThreads / 64) +
+                                                (int)(threadIdx.x >> 6));
+  if (ic >= cl_start[pp.ncell]) return;
+  const int il = lane >> 3, jl = lane & 7;
+  const int4 inf = cinfo[ic];
+  const vec4_t<T> pi = cpos[(size_t)ic * 8 + il];
+  const vec4_t<T> blo = cbox[2 * (size_t)ic], bhi = cbox[2 * (size_t)ic + 1];
+  const T two_inv_a3 = T(2) * pp.inv_a3;
+  double ph = 0.0;  // the potential is carried in FP64 up to the energy sum
+  T fx = T(0), fy = T(0), fz = T(0);
+  for_each_cluster_pair<T>(pp, cl_start, cbox, ic, inf.z, blo, bhi,
+                           [&](int jc, T sx, T sy, T sz, bool self_block) {
+    const vec4_t<T> pj = cpos[(size_t)jc * 8 + jl];
+    const T dx = (pi.x - sx) - pj.x, dy = (pi.y - sy) - pj.y, dz = (pi.z - sz) - pj.z;
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    const bool ok = r2 < pp.a2 && !(self_block && il == jl);
+    const T rinv = rsqrt_t(r2);
+    const T t = r2 * pp.inv_a2;
+    T Pt = pp.c[P - 1], dP = pp.dc[P - 2];
+#pragma unroll
+    for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
+#pragma unroll
+    for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
+    const T e = rinv - Pt * pp.inv_a;
+    const T f = rinv * rinv * rinv + dP * two_inv_a3;
+    const T qe = ok ? pj.w * e : T(0);
+    const T fs = ok ? pj.w * f : T(0);
+    ph += (double)qe;
+    fx += fs * dx;
+    fy += fs * dy;
+    fz += fs * dz;
+  });
+  ph = sum8(ph);
+  fx = sum8(fx);
+  fy = sum8(fy);
+  fz = sum8(fz);
+  if (jl == 0 && il < inf.y) {
+    const int i = inf.x + il;
+    phi0[i] = ph;
+    F0[3 * (size_t)i] = pi.w * fx;
+    F0[3 * (size_t)i + 1] = pi.w * fy;
+    F0[3 * (size_t)i + 2] = pi.w * fz;
+  }
+}
+
+// Cotangent of the forces in cluster-slot order (zero in padding slots).
+template <typename T>
+__global__ void k_gather_v_cl(int nslot_max, const int* __restrict__ cl_start, int ncell,
+                              const int4* __restrict__ cinfo, const int* __restrict__ perm,
+                              const T* __restrict__ gF, vec4_t<T>* __restrict__ cv) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslot_max || s >= 8 * cl_start[ncell]) return;
+  const int4 inf = cinfo[s >> 3];
+  const int r = s & 7;
+  vec4_t<T> v;
+  v.x = v.y = v.z = v.w = T(0);
+  if (r < inf.y) {
+    const int u = perm[inf.x + r];
+    v.x = gF[3 * (size_t)u];
+    v.y = gF[3 * (size_t)u + 1];
+    v.z = gF[3 * (size_t)u + 2];
+  }
+  cv[s] = v;
+}
+
+// VJP of the short-range part for a force cotangent v (eq. U_zero):
+//   d/dq_i  sum_k v_k . F0_k   = sum_j q_j f(r) (v_i - v_j) . d_ij
+//   d/dr_i  sum_k v_k . F0_k   = q_i sum_j q_j [f (v_i - v_j) + (f'/r) ((v_i - v_j) . d) d]
+// with f = 1/r^3 + 2 P'(t)/a^3 and f'/r = -3/r^5 + 4 P''(t)/a^5.
+template <typename T, int P>
+__global__ void __launch_bounds__(kClusterThreads)
+    k_pair_vjp_cl(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
+                  const vec4_t<T>* __restrict__ cv, const vec4_t<T>* __restrict__ cbox,
+                  const int4* __restrict__ cinfo, PairParams<T> pp, T* __restrict__ gq,
+                  T* __restrict__ gr) {
+  const int lane = threadIdx.x & 63;
+  const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * (kClusterThreads / 64) +
+                                                (int)(threadIdx.x >> 6));
+  if (ic >= cl_start[pp.ncell]) return;
+  const int il = lane >> 3, jl = lane & 7;
+  const int4 inf = cinfo[ic];
+  const vec4_t<T> pi = cpos[(size_t)ic * 8 + il];
+  const vec4_t<T> vi = cv[(size_t)ic * 8 + il];
+  const vec4_t<T> blo = cbox[2 * (size_t)ic], bhi = cbox[2 * (size_t)ic + 1];
+  T sq = T(0), rx = T(0), ry = T(0), rz = T(0);
+  for_each_cluster_pair<T>(pp, cl_start, cbox, ic, inf.z, blo, bhi,
+                           [&](int jc, T sx, T sy, T sz, bool self_block) {
+    const vec4_t<T> pj = cpos[(size_t)jc * 8 + jl];
+    const vec4_t<T> vj = cv[(size_t)jc * 8 + jl];
+    const T dx = (pi.x - sx) - pj.x, dy = (pi.y - sy) - pj.y, dz = (pi.z - sz) - pj.z;
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    const bool ok = r2 < pp.a2 && !(self_block && il == jl);
+    const T rinv = rsqrt_t(r2);
+    const T rinv2 = rinv * rinv;
+    const T t = r2 * pp.inv_a2;
+    T dP = pp.dc[P - 2], d2P = pp.d2c[P - 3];
+#pragma unroll
+    for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
+#pragma unroll
+    for (int k = P - 4; k >= 0; --k) d2P = d2P * t + pp.d2c[k];
+    const T f = rinv * rinv2 + T(2) * dP * pp.inv_a3;
+    const T fpr = T(-3) * rinv2 * rinv2 * rinv + T(4) * d2P * pp.inv_a5;
+    const T wx = vi.x - vj.x, wy = vi.y - vj.y, wz = vi.z - vj.z;
+    const T wd = wx * dx + wy * dy + wz * dz;
+    const T qf = ok ? pj.w * f : T(0);
+    const T c2 = ok ? pj.w * fpr * wd : T(0);
+    sq += qf * wd;
+    rx += qf * wx + c2 * dx;
+    ry += qf * wy + c2 * dy;
+    rz += qf * wz + c2 * dz;
+  });
+  sq = sum8(sq);
+  rx = sum8(rx);
+  ry = sum8(ry);
+  rz = sum8(rz);
+  if (jl == 0 && il < inf.y) {
+    const int i = inf.x + il;
+    gq[i] = sq;
+    gr[3 * (size_t)i] = pi.w * rx;
+    gr[3 * (size_t)i + 1] = pi.w * ry;
+    gr[3 * (size_t)i + 2] = pi.w * rz;
+  }
+}
+
+template <typename T>
+void launch_cluster_layout(int sort, int scan, int ncell, const int* start, int* cl_start,
+                           const BinParams<T>& bp, const vec4_t<T>* wrapped, vec4_t<T>* sorted,
+                           int* perm, vec4_t<T>* cpos, vec4_t<T>* cbox, int4* cinfo,
+                           hipStream_t s) {
+  if (ncell <= 0) return;
+  if (scan) hipLaunchKernelGGL(k_cluster_scan, dim3(1), dim3(1024), 0, s, ncell, start, cl_start);
+  hipLaunchKernelGGL(k_cluster_prep<T>, dim3(ncell), dim3(kPrepThreads), 0, s, sort, start,
+                     cl_start, bp, wrapped, sorted, perm, cpos, cbox, cinfo);
+}
+
+int cluster_capacity(int n, int ncell) { return n / 8 + ncell + 1; }
+
+template <typename T>
+void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
+                    const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
+                    double* phi0, T* F0, hipStream_t s) {
+  if (n <= 0) return;
+  const int ncl = cluster_capacity(n, ncell);
+  const dim3 grid((ncl + 3) / 4), block(kClusterThreads);
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_pair_cl<T, 4>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+    case 6: hipLaunchKernelGGL((k_pair_cl<T, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+    case 8: hipLaunchKernelGGL((k_pair_cl<T, 8>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+  }
+}
+
+template <typename T>
+void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4* cinfo,
+                        const int* perm, const T* gF, const vec4_t<T>* cpos, vec4_t<T>* cv,
+                        const vec4_t<T>* cbox, const PairParams<T>& pp, T* gq, T* gr,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  const int ncl = cluster_capacity(n, ncell);
+  hipLaunchKernelGGL(k_gather_v_cl<T>, dim3((8 * ncl + 255) / 256), dim3(256), 0, s, 8 * ncl,
+                     cl_start, ncell, cinfo, perm, gF, cv);
+  const dim3 grid((ncl + 3) / 4), block(kClusterThreads);
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_pair_vjp_cl<T, 4>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, gq, gr); break;
+    case 6: hipLaunchKernelGGL((k_pair_vjp_cl<T, 6>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, gq, gr); break;
+    case 8: hipLaunchKernelGGL((k_pair_vjp_cl<T, 8>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, gq, gr); break;
+  }
+}
+
+#define MSM_INST_CLUSTER(T)                                                                    \
+  template void launch_cluster_layout<T>(int, int, int, const int*, int*, const BinParams<T>&, \
+                                         const vec4_t<T>*, vec4_t<T>*, int*, vec4_t<T>*,       \
+                                         vec4_t<T>*, int4*, hipStream_t);                      \
+  template void launch_pair_cl<T>(int, int, int, const int*, const vec4_t<T>*,                 \
+                                  const vec4_t<T>*, const int4*, const PairParams<T>&,         \
+                                  double*, T*, hipStream_t);                                   \
+  template void launch_pair_vjp_cl<T>(int, int, int, const int*, const int4*, const int*,      \
+                                      const T*, const vec4_t<T>*, vec4_t<T>*,                  \
+                                      const vec4_t<T>*, const PairParams<T>&, T*, T*,          \
+                                      hipStream_t);
+MSM_INST_CLUSTER(float)
+MSM_INST_CLUSTER(double)
+
+}  // namespace msm

@@ -1,5 +1,7 @@
 // kernels_grid.hip -- grid-side kernels of the MSM: restriction, prolongation
 // and the per-level stencil convolution (also used for the dense top level).
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace msm {
@@ -106,37 +108,46 @@ __global__ void k_prolong(GridDev<T> f, GridDev<T> c, JTaps<T> jt, const T* __re
 
 // ---------------------------------------------------------------------------
 // a5 / a6: stencil convolution e_o = sum_d K_d q_{o+shift-d} (eq.
-// action_of_K_as_convolution).  A workgroup owns a TX x TY tile of output
-// points of one z-plane and a contiguous range of stencil z-planes; for each
-// plane it stages the input window (with periodic wrap or zero padding)
-// through LDS, and every thread keeps R consecutive x outputs in registers.
-// The stencil coefficients are uniform across the workgroup (scalar loads);
-// per stencil row only the non-zero x range is visited.  TI is the grid type
-// (what LDS holds), TA the stencil / accumulation / output type: the factored
-// levels accumulate the k-sample convolution in FP64.
+// action_of_K_as_convolution).  A workgroup owns a (TXT R) x (TYT Q) tile of
+// output points of one z-plane and a contiguous range of stencil z-planes.
+// For each stencil plane it stages the input window (periodic wrap or zero
+// padding) through LDS; every thread keeps R consecutive x outputs of Q
+// consecutive rows in registers.  The thread walks the input rows of its
+// window: one input row serves its Q output rows through Q different stencil
+// rows, so each LDS value, converted once to the accumulation type, feeds up
+// to Q R CH multiply-adds.  Taps go in chunks of CH over the union of the Q
+// rows' non-zero x ranges; stencil rows are stored with CH-1 trailing zeros
+// (row stride lxp) so no remainder loop is needed, and every plane carries
+// kConvRowPad zero rows before and after it so that all Q rows can be read
+// unconditionally.  The coefficients are
+// uniform across the workgroup (scalar loads).  TI is the grid type (what
+// LDS holds), TA the stencil / accumulation / output type (FP64 here).
 // ---------------------------------------------------------------------------
-constexpr int kConvCH = 8;
-
-template <typename TI, typename TA, int R, int TXT, int TYT>
+template <typename TI, typename TA, int R, int Q, int TXT, int TYT>
 __global__ void __launch_bounds__(TXT * TYT)
     k_conv(ConvParams cp, const TA* __restrict__ K, const int2* __restrict__ rowext,
            const TI* __restrict__ q, TA* __restrict__ e) {
+  constexpr int CH = kConvCH;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TI* lds = reinterpret_cast<TI*>(smem_raw);
   const int tx = threadIdx.x % TXT, ty = threadIdx.x / TXT;
   const int n0 = cp.n[0], n1 = cp.n[1], n2 = cp.n[2];
   const int o0 = cp.nout[0], o1 = cp.nout[1], o2 = cp.nout[2];
-  const int lx = cp.len[0], ly = cp.len[1];
-  const int x0 = blockIdx.x * (TXT * R), y0 = blockIdx.y * TYT;
+  const int lx = cp.len[0], ly = cp.len[1], lxp = cp.lxp;
+  const int bx = blockIdx.x, by = blockIdx.y;
   const int z = blockIdx.z % o2, split = blockIdx.z / o2;
+  const int x0 = bx * (TXT * R), y0 = by * (TYT * Q);
   const int jz0 = split * cp.dz_per_split;
   const int jz1 = min(cp.len[2], jz0 + cp.dz_per_split);
   const int LW = cp.lds_w, LH = cp.lds_h;
-  const int xs = x0 + cp.shift[0] - (cp.off[0] + lx - 1);
+  // input index of LDS element (row 0, column 0)
+  const int xs = x0 + cp.shift[0] - (cp.off[0] + lx - 1) - (CH - 1);
   const int ys = y0 + cp.shift[1] - (cp.off[1] + ly - 1);
-  TA total[R];
+  TA acc[Q][R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) total[r] = TA(0);
+  for (int a = 0; a < Q; ++a)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[a][r] = TA(0);
   for (int jz = jz0; jz < jz1; ++jz) {
     int zi = z + cp.shift[2] - (cp.off[2] + jz);
     if (cp.per[2]) zi = wrap_index(zi, n2);
@@ -154,48 +165,52 @@ __global__ void __launch_bounds__(TXT * TYT)
       lds[idx] = ok ? qz[(long long)yi * n0 + xi] : TI(0);
     }
     __syncthreads();
-    TA acc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = TA(0);
-    const TA* Kz = K + (long long)jz * ly * lx;
+    // plane jz of the stencil: ly + 2 kConvRowPad rows of stride lxp
+    const TA* Kz = K + ((long long)jz * (ly + 2 * kConvRowPad) + kConvRowPad) * lxp;
     const int2* ext_z = rowext + jz * ly;
-    for (int jy = 0; jy < ly; ++jy) {
-      const int2 ext = ext_z[jy];
-      if (ext.x > ext.y) continue;
-      const TI* lrow = lds + (ty - jy + ly - 1) * LW + tx * R;
-      const TA* Krow = Kz + jy * lx;
-      int jx = ext.x;
-      for (; jx + kConvCH - 1 <= ext.y; jx += kConvCH) {
-        TA win[kConvCH + R - 1];
-        const TI* wp = lrow + (lx - jx - kConvCH);
-#pragma unroll
-        for (int u = 0; u < kConvCH + R - 1; ++u) win[u] = (TA)wp[u];
-#pragma unroll
-        for (int c = 0; c < kConvCH; ++c) {
-          const TA kv = Krow[jx + c];
-#pragma unroll
-          for (int r = 0; r < R; ++r) acc[r] = fma(kv, win[kConvCH - 1 - c + r], acc[r]);
-        }
+    for (int v = 0; v < Q + ly - 1; ++v) {
+      // output row a of the thread uses stencil row jy = a + ly - 1 - v
+      const int alo = max(0, v - ly + 1), ahi = min(Q - 1, v);
+      int first = lx, last = -1;
+      for (int a = alo; a <= ahi; ++a) {
+        const int2 ex = ext_z[a + ly - 1 - v];
+        first = min(first, ex.x);
+        last = max(last, ex.y);
       }
-      for (; jx <= ext.y; ++jx) {
-        const TA kv = Krow[jx];
-        const TI* wp = lrow + (lx - 1 - jx);
+      const TI* lrow = lds + (ty * Q + v) * LW + tx * R + (lx - 1);
+      for (int j0 = first; j0 <= last; j0 += CH) {
+        TA win[CH + R - 1];
+        const TI* wp = lrow - j0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = fma(kv, (TA)wp[r], acc[r]);
+        for (int u = 0; u < CH + R - 1; ++u) win[u] = (TA)wp[u];
+        // rows outside the stencil (a < alo or a > ahi) are zero padding;
+        // all Q CH coefficients are loaded first, then the multiply-adds go
+        // tap by tap across all Q R accumulators (independent chains)
+        TA kv[Q][CH];
+#pragma unroll
+        for (int a = 0; a < Q; ++a)
+#pragma unroll
+          for (int c = 0; c < CH; ++c) kv[a][c] = Kz[(long long)(a + ly - 1 - v) * lxp + j0 + c];
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+#pragma unroll
+          for (int a = 0; a < Q; ++a)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[a][r] = fma(kv[a][c], win[CH - 1 - c + r], acc[a][r]);
       }
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) total[r] += acc[r];
   }
-  const int y = y0 + ty;
-  if (y < o1) {
+#pragma unroll
+  for (int a = 0; a < Q; ++a) {
+    const int y = y0 + ty * Q + a;
+    if (y >= o1) continue;
     TA* erow = e + ((long long)z * o1 + y) * o0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int x = x0 + tx * R + r;
       if (x < o0) {
-        if (cp.nsplit > 1) atomicAdd(&erow[x], total[r]);
-        else erow[x] = total[r];
+        if (cp.nsplit > 1) atomicAdd(&erow[x], acc[a][r]);
+        else erow[x] = acc[a][r];
       }
     }
   }
@@ -315,9 +330,15 @@ void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, con
   }
 }
 
-// big tiles (64 x 32 outputs, 256 threads) for wide grids, small tiles
-// (16 x 16 outputs, 64 threads) for grids narrower than 48 points
-static bool conv_small(const int nout[3]) { return nout[0] < 48; }
+// Tile shapes {R, Q, TXT, TYT}: 0 = 64 x 64 outputs, 256 threads; 1 = 32 x
+// 32, 64 threads; 2 = 16 x 16, 64 threads (R = Q = 2).
+struct ConvShape {
+  int R, Q, TXT, TYT;
+  double eff;  // relative multiply-add throughput of the shape
+};
+static const ConvShape kShapes[3] = {{4, 4, 16, 16, 1.0}, {4, 4, 8, 8, 0.9}, {2, 2, 8, 8, 0.55}};
+
+int conv_row_stride(int len0) { return len0 + kConvCH - 1; }
 
 ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3],
                             const int per[3], const int off[3], const int len[3], int tsize) {
@@ -330,19 +351,46 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
     cp.off[k] = off[k];
     cp.len[k] = len[k];
   }
-  const bool small = conv_small(nout);
-  const int TXo = small ? 16 : 64, TY = small ? 16 : 32;
-  cp.lds_w = TXo + len[0] - 1;
-  if (tsize == 4) cp.lds_w |= 1;  // odd row stride spreads rows over LDS banks
+  cp.lxp = conv_row_stride(len[0]);
+  // shape: fewest padded outputs per unit throughput, penalised when the
+  // launch cannot reach 2048 waves even with one stencil plane per split
+  double best = 0;
+  int pick = -1;
+  for (int c = 0; c < 3; ++c) {
+    const ConvShape& sh = kShapes[c];
+    const int TX = sh.TXT * sh.R, TY = sh.TYT * sh.Q;
+    const size_t lds = (size_t)(TX + len[0] - 1 + kConvCH - 1) * (TY + len[1] - 1) * tsize;
+    if (lds > 64 * 1024) continue;
+    const double tiles = (double)((nout[0] + TX - 1) / TX) * ((nout[1] + TY - 1) / TY) * nout[2];
+    const double waves = tiles * len[2] * (sh.TXT * sh.TYT / 64);
+    double cost = tiles * TX * TY / sh.eff;
+    if (waves < 2048) cost *= 2048.0 / waves;
+    if (pick < 0 || cost < best) {
+      best = cost;
+      pick = c;
+    }
+  }
+  if (pick < 0) pick = 2;
+  const ConvShape& sh = kShapes[pick];
+  const int TX = sh.TXT * sh.R, TY = sh.TYT * sh.Q;
+  cp.shape = pick;
+  cp.lds_w = TX + len[0] - 1 + kConvCH - 1;
   cp.lds_h = TY + len[1] - 1;
-  const long long tiles =
-      (long long)((nout[0] + TXo - 1) / TXo) * ((nout[1] + TY - 1) / TY) * nout[2];
-  long long want = (2048 + tiles - 1) / tiles;
+  // waves wanted per launch (the stencil z-planes are split across
+  // workgroups until the launch has this many); MSM_CONV_WAVES overrides
+  static const long long target = [] {
+    const char* e = getenv("MSM_CONV_WAVES");
+    const long long v = e ? atoll(e) : 0;
+    return v > 0 ? v : 4096LL;
+  }();
+  const long long wpb = sh.TXT * sh.TYT / 64;
+  const long long blocks =
+      (long long)((nout[0] + TX - 1) / TX) * ((nout[1] + TY - 1) / TY) * nout[2];
+  long long want = (target + blocks * wpb - 1) / (blocks * wpb);
   if (want < 1) want = 1;
   if (want > len[2]) want = len[2];
   cp.dz_per_split = (int)((len[2] + want - 1) / want);
   cp.nsplit = (len[2] + cp.dz_per_split - 1) / cp.dz_per_split;
-  cp.small = small;
   return cp;
 }
 
@@ -354,12 +402,13 @@ template <typename TI, typename TA>
 void launch_conv(const ConvParams& cp, const TA* K, const int2* rowext, const TI* q, TA* e,
                  hipStream_t s) {
   const size_t lds = (size_t)cp.lds_w * cp.lds_h * sizeof(TI);
-  if (cp.small) {
-    dim3 grid((cp.nout[0] + 15) / 16, (cp.nout[1] + 15) / 16, cp.nout[2] * cp.nsplit);
-    hipLaunchKernelGGL((k_conv<TI, TA, 4, 4, 16>), grid, dim3(64), lds, s, cp, K, rowext, q, e);
-  } else {
-    dim3 grid((cp.nout[0] + 63) / 64, (cp.nout[1] + 31) / 32, cp.nout[2] * cp.nsplit);
-    hipLaunchKernelGGL((k_conv<TI, TA, 8, 8, 32>), grid, dim3(256), lds, s, cp, K, rowext, q, e);
+  const ConvShape& sh = kShapes[cp.shape];
+  const int TX = sh.TXT * sh.R, TY = sh.TYT * sh.Q;
+  dim3 grid((cp.nout[0] + TX - 1) / TX, (cp.nout[1] + TY - 1) / TY, cp.nout[2] * cp.nsplit);
+  switch (cp.shape) {
+    case 0: hipLaunchKernelGGL((k_conv<TI, TA, 4, 4, 16, 16>), grid, dim3(256), lds, s, cp, K, rowext, q, e); break;
+    case 1: hipLaunchKernelGGL((k_conv<TI, TA, 4, 4, 8, 8>), grid, dim3(64), lds, s, cp, K, rowext, q, e); break;
+    default: hipLaunchKernelGGL((k_conv<TI, TA, 2, 2, 8, 8>), grid, dim3(64), lds, s, cp, K, rowext, q, e); break;
   }
 }
 
@@ -398,8 +447,6 @@ void launch_fill(T* p, long long count, T value, hipStream_t s) {
                                    const T*, T*, hipStream_t);                                    \
   template void launch_prolong<T>(int, const GridDev<T>&, const GridDev<T>&, const double*,      \
                                   const T*, T*, hipStream_t);                                     \
-  template void launch_conv<T, T>(const ConvParams&, const T*, const int2*, const T*, T*,         \
-                                  hipStream_t);                                                   \
   template void launch_omega<T>(const OmegaParams&, const double*, T*, hipStream_t);              \
   template void launch_fill<T>(T*, long long, T, hipStream_t);                                    \
   template void launch_cast<T>(const double*, T*, long long, hipStream_t);
@@ -408,5 +455,7 @@ MSM_INST_GRID(double)
 template void launch_fill<int>(int*, long long, int, hipStream_t);
 template void launch_conv<float, double>(const ConvParams&, const double*, const int2*,
                                          const float*, double*, hipStream_t);
+template void launch_conv<double, double>(const ConvParams&, const double*, const int2*,
+                                          const double*, double*, hipStream_t);
 
 }  // namespace msm

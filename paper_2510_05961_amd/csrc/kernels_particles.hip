@@ -1,6 +1,5 @@
 // kernels_particles.hip -- particle-side kernels of the MSM forward pass:
-// cell binning (count, scan, scatter), the short-range pair sum over the cell
-// list, anterpolation onto the level-1 grid, and interpolation fused with the
+// cell binning (count, scan, scatter), anterpolation onto the level-1 grid, and interpolation fused with the
 // final combination of short- and long-range parts and the FP64 energy sum.
 #include "kernels.hpp"
 
@@ -56,30 +55,68 @@ __global__ void k_bin_count(int n, const T* __restrict__ pos, const T* __restric
   wrapped[i] = w;
 }
 
-// Exclusive scan of the cell counts into start[0..ncell] (one workgroup).
+// Exclusive scans of the cell counts into start[0..ncell] and of the
+// per-cell cluster counts ceil(count / 8) into cl_start[0..ncell] (one
+// workgroup).
 __global__ void __launch_bounds__(1024) k_scan(int ncell, const int* __restrict__ counts,
-                                               int* __restrict__ start) {
-  __shared__ int buf[1024];
-  __shared__ int carry;
+                                               int* __restrict__ start,
+                                               int* __restrict__ cl_start) {
+  __shared__ int buf[1024], cbuf[1024];
+  __shared__ int carry, ccarry;
   const int t = threadIdx.x;
-  if (t == 0) carry = 0;
+  if (t == 0) {
+    carry = 0;
+    ccarry = 0;
+  }
   __syncthreads();
   for (int base = 0; base < ncell; base += 1024) {
-    int v = (base + t < ncell) ? counts[base + t] : 0;
+    const int v = (base + t < ncell) ? counts[base + t] : 0;
+    const int cv = (v + 7) / 8;
     buf[t] = v;
+    cbuf[t] = cv;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-      int add = (t >= off) ? buf[t - off] : 0;
+      const int add = (t >= off) ? buf[t - off] : 0;
+      const int cadd = (t >= off) ? cbuf[t - off] : 0;
       __syncthreads();
       buf[t] += add;
+      cbuf[t] += cadd;
       __syncthreads();
     }
-    if (base + t < ncell) start[base + t] = carry + buf[t] - v;
+    if (base + t < ncell) {
+      start[base + t] = carry + buf[t] - v;
+      cl_start[base + t] = ccarry + cbuf[t] - cv;
+    }
     __syncthreads();
-    if (t == 1023) carry += buf[1023];
+    if (t == 1023) {
+      carry += buf[1023];
+      ccarry += cbuf[1023];
+    }
     __syncthreads();
   }
-  if (t == 0) start[ncell] = carry;
+  if (t == 0) {
+    start[ncell] = carry;
+    cl_start[ncell] = ccarry;
+  }
+}
+
+// Zeroes up to kZeroJobs buffers (4-byte words) in one launch.
+__global__ void k_zero_multi(ZeroJobs jobs) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (int j = 0; j < jobs.n; ++j) {
+    unsigned* p = reinterpret_cast<unsigned*>(jobs.ptr[j]);
+    const long long w = jobs.words[j];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < w; i += stride) p[i] = 0u;
+  }
+}
+
+void launch_zero_multi(const ZeroJobs& jobs, hipStream_t s) {
+  long long maxw = 0;
+  for (int j = 0; j < jobs.n; ++j) maxw = jobs.words[j] > maxw ? jobs.words[j] : maxw;
+  if (maxw == 0) return;
+  long long nb = (maxw + 255) / 256;
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL(k_zero_multi, dim3((unsigned)nb), dim3(256), 0, s, jobs);
 }
 
 template <typename T>
@@ -94,137 +131,104 @@ __global__ void k_bin_scatter(int n, const int* __restrict__ cell_of, const int*
 }
 
 // ---------------------------------------------------------------------------
-// a2: short-range pair sum (eq. U_zero).  One workgroup per home cell; the
-// particles of each neighbour cell are staged through LDS in tiles and every
-// thread sweeps the tile for its own home particle:
-//   phi0_i = sum_j q_j k0(r),  F0_i = q_i sum_j q_j (1/r^3 + 2 P'(t)/a^3) d_ij,
-// k0(r) = 1/r - P(t)/a, t = r^2/a^2, P the softening polynomial in t.
+// a3: anterpolation (eq. grid_charge): q~^1_m += q_i phi_m(r_i) over the p^3
+// grid points of each particle, B-spline weights in FP64.
 // ---------------------------------------------------------------------------
-// Cell index along one axis at offset o in {-1, 0, 1} from cell c, or -1 when
-// that neighbour does not exist or repeats one already visited: periodic axes
-// with one cell visit only o = 0, with two cells only o = 0 and o = 1.
-__device__ inline int neighbour_cell(int c, int o, int nc, int per) {
-  if (per) {
-    if (nc == 1) return o == 0 ? 0 : -1;
-    if (nc == 2) return o < 0 ? -1 : (c + o) & 1;
-    const int v = c + o;
-    return v < 0 ? v + nc : (v >= nc ? v - nc : v);
-  }
-  const int v = c + o;
-  return (v >= 0 && v < nc) ? v : -1;
-}
+// Staged per cell: one workgroup accumulates the charges of one
+// cell into an LDS brick covering every grid point they can touch, then adds
+// the brick to the grid with one atomic per non-zero point (coalesced along x,
+// and conflicting only where the bricks of neighbouring cells overlap).  A
+// brick larger than kBrickMax points (cells much wider than h) falls back to
+// per-particle global atomics.
+constexpr int kBrickMax = 8192;
 
 template <typename T, int P>
-__global__ void __launch_bounds__(kPairThreads)
-    k_pair(const vec4_t<T>* __restrict__ sorted, const int* __restrict__ start, PairParams<T> pp,
-           double* __restrict__ phi0, T* __restrict__ F0) {
-  __shared__ vec4_t<T> tile[kPairThreads];
+__global__ void __launch_bounds__(256)
+    k_anterp_brick(const int* __restrict__ start, const vec4_t<T>* __restrict__ sorted,
+                   GridDev<T> g, CellGrid cg, T* __restrict__ grid) {
+  __shared__ T brick[kBrickMax];
   const int cell = blockIdx.x;
-  const int cx = cell % pp.nc[0];
-  const int cy = (cell / pp.nc[0]) % pp.nc[1];
-  const int cz = cell / (pp.nc[0] * pp.nc[1]);
-  const int i_beg = start[cell], i_end = start[cell + 1];
-  for (int ib = i_beg; ib < i_end; ib += kPairThreads) {
-    const int i = ib + (int)threadIdx.x;
-    const bool active = i < i_end;
-    vec4_t<T> pi;
-    if (active) pi = sorted[i];
-    else {
-      pi.x = pi.y = pi.z = pi.w = T(0);
+  const int beg = start[cell], end = start[cell + 1];
+  if (beg == end) return;
+  const int cc[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
+  // absolute grid index range of the brick (one point of margin each side
+  // for the rounding of the binning)
+  int lo[3], ext[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = (int)floor(cc[k] * cg.cs[k] / g.hd[k]) - P / 2 - 1;
+    const int hi = (int)floor((cc[k] + 1) * cg.cs[k] / g.hd[k]) + P / 2 + 1;
+    ext[k] = hi - lo[k] + 1;
+  }
+  const int vol = ext[0] * ext[1] * ext[2];
+  const bool staged = vol <= kBrickMax;
+  if (staged) {
+    for (int b = threadIdx.x; b < vol; b += blockDim.x) brick[b] = T(0);
+    __syncthreads();
+  }
+  for (int i = beg + (int)threadIdx.x; i < end; i += blockDim.x) {
+    const vec4_t<T> pi = sorted[i];
+    const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    double w[3][P];
+    int m0[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double f;
+      m0[k] = grid_coord<double>(xs[k], g.hd[k], f) - P / 2 + 1;
+      bspline_weights<P, double>(f, w[k], nullptr, nullptr);
     }
-    double ph = 0.0;  // the potential is carried in FP64 up to the energy sum
-    T fx = T(0), fy = T(0), fz = T(0);
-    // neighbour cells: offsets -1..1 per axis, each distinct cell once
-    for (int oz = -1; oz <= 1; ++oz) {
-      const int nz = neighbour_cell(cz, oz, pp.nc[2], pp.per[2]);
-      if (nz < 0) continue;
-      for (int oy = -1; oy <= 1; ++oy) {
-        const int ny = neighbour_cell(cy, oy, pp.nc[1], pp.per[1]);
-        if (ny < 0) continue;
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int nx = neighbour_cell(cx, ox, pp.nc[0], pp.per[0]);
-          if (nx < 0) continue;
-          const int nc_ = (nz * pp.nc[1] + ny) * pp.nc[0] + nx;
-          const int j_beg = start[nc_], j_end = start[nc_ + 1];
-          for (int jb = j_beg; jb < j_end; jb += kPairThreads) {
-            __syncthreads();
-            if (jb + (int)threadIdx.x < j_end) tile[threadIdx.x] = sorted[jb + threadIdx.x];
-            __syncthreads();
-            const int cnt = min(kPairThreads, j_end - jb);
-            for (int jj = 0; jj < cnt; ++jj) {
-              const vec4_t<T> pj = tile[jj];
-              T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-              if (pp.per[0]) dx -= pp.box[0] * rint(dx * pp.inv_box[0]);
-              if (pp.per[1]) dy -= pp.box[1] * rint(dy * pp.inv_box[1]);
-              if (pp.per[2]) dz -= pp.box[2] * rint(dz * pp.inv_box[2]);
-              const T r2 = dx * dx + dy * dy + dz * dz;
-              if (r2 < pp.a2 && jb + jj != i) {
-                const T rinv = rsqrt_t(r2);
-                const T t = r2 * pp.inv_a2;
-                T Pt = pp.c[P - 1], dP = pp.dc[P - 2];
+    const double qi = (double)pi.w;
+    bool inside = staged;
 #pragma unroll
-                for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
+    for (int k = 0; k < 3; ++k) inside = inside && m0[k] >= lo[k] && m0[k] + P - 1 < lo[k] + ext[k];
+    if (inside) {
+      const int b0 = ((m0[2] - lo[2]) * ext[1] + (m0[1] - lo[1])) * ext[0] + (m0[0] - lo[0]);
 #pragma unroll
-                for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
-                ph += (double)(pj.w * (rinv - Pt * pp.inv_a));
-                const T fs = pj.w * (rinv * rinv * rinv + T(2) * dP * pp.inv_a3);
-                fx += fs * dx;
-                fy += fs * dy;
-                fz += fs * dz;
-              }
-            }
+      for (int c = 0; c < P; ++c) {
+        const double wz = qi * w[2][c];
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+          const double wyz = wz * w[1][b];
+          const int row = b0 + (c * ext[1] + b) * ext[0];
+#pragma unroll
+          for (int a = 0; a < P; ++a) atomicAdd(&brick[row + a], (T)(wyz * w[0][a]));
+        }
+      }
+    } else {
+      int idx[3][P];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < P; ++j) idx[k][j] = axis_index(m0[k] + j, g.n[k], g.lo[k], g.per[k]);
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        if (idx[2][c] < 0) continue;
+        const double wz = qi * w[2][c];
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+          if (idx[1][b] < 0) continue;
+          const double wyz = wz * w[1][b];
+          const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
+#pragma unroll
+          for (int a = 0; a < P; ++a) {
+            if (idx[0][a] < 0) continue;
+            atomicAdd(&grid[row + idx[0][a]], (T)(wyz * w[0][a]));
           }
         }
       }
     }
-    if (active) {
-      phi0[i] = ph;
-      F0[3 * i] = pi.w * fx;
-      F0[3 * i + 1] = pi.w * fy;
-      F0[3 * i + 2] = pi.w * fz;
-    }
   }
-}
-
-// ---------------------------------------------------------------------------
-// a3: anterpolation (eq. grid_charge): q~^1_m += q_i phi_m(r_i) over the p^3
-// grid points of each particle (particles are in cell order, so neighbouring
-// threads update neighbouring grid points).
-// ---------------------------------------------------------------------------
-template <typename T, int P>
-__global__ void k_anterp(int n, const vec4_t<T>* __restrict__ sorted, GridDev<T> g,
-                         T* __restrict__ grid) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const vec4_t<T> pi = sorted[i];
-  const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
-  // weights in FP64: they enter the grid self-energy quadratically
-  double w[3][P];
-  int idx[3][P];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    double f;
-    const int base = grid_coord<double>(xs[k], g.hd[k], f);
-    bspline_weights<P, double>(f, w[k], nullptr, nullptr);
-#pragma unroll
-    for (int j = 0; j < P; ++j) idx[k][j] = axis_index(base - P / 2 + 1 + j, g.n[k], g.lo[k], g.per[k]);
-  }
-  const double qi = (double)pi.w;
-#pragma unroll
-  for (int c = 0; c < P; ++c) {
-    if (idx[2][c] < 0) continue;
-    const double wz = qi * w[2][c];
-#pragma unroll
-    for (int b = 0; b < P; ++b) {
-      if (idx[1][b] < 0) continue;
-      const double wyz = wz * w[1][b];
-      const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
-#pragma unroll
-      for (int a = 0; a < P; ++a) {
-        if (idx[0][a] < 0) continue;
-        atomicAdd(&grid[row + idx[0][a]], (T)(wyz * w[0][a]));
-      }
-    }
+  if (!staged) return;
+  __syncthreads();
+  for (int b = threadIdx.x; b < vol; b += blockDim.x) {
+    const T v = brick[b];
+    if (v == T(0)) continue;
+    const int bx = b % ext[0], by = (b / ext[0]) % ext[1], bz = b / (ext[0] * ext[1]);
+    const int ix = axis_index(lo[0] + bx, g.n[0], g.lo[0], g.per[0]);
+    const int iy = axis_index(lo[1] + by, g.n[1], g.lo[1], g.per[1]);
+    const int iz = axis_index(lo[2] + bz, g.n[2], g.lo[2], g.per[2]);
+    if (ix < 0 || iy < 0 || iz < 0) continue;
+    atomicAdd(&grid[((long long)iz * g.n[1] + iy) * g.n[0] + ix], v);
   }
 }
 
@@ -324,37 +328,25 @@ __global__ void __launch_bounds__(256)
 template <typename T>
 void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
                     int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
-                    vec4_t<T>* sorted, int* perm, int* flag, hipStream_t s) {
+                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag, hipStream_t s) {
   const int nb = (n + 255) / 256;
   if (n > 0)
     hipLaunchKernelGGL(k_bin_count<T>, dim3(nb), dim3(256), 0, s, n, pos, q, bp, cell_of, rank,
                        counts, wrapped, flag);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ncell, counts, start);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ncell, counts, start, cl_start);
   if (n > 0)
     hipLaunchKernelGGL(k_bin_scatter<T>, dim3(nb), dim3(256), 0, s, n, cell_of, rank, start,
                        wrapped, sorted, perm);
 }
 
 template <typename T>
-void launch_pair(int p, int ncell, const vec4_t<T>* sorted, const int* start,
-                 const PairParams<T>& pp, double* phi0, T* F0, hipStream_t s) {
-  if (ncell <= 0) return;
-  switch (p) {
-    case 4: hipLaunchKernelGGL((k_pair<T, 4>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, start, pp, phi0, F0); break;
-    case 6: hipLaunchKernelGGL((k_pair<T, 6>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, start, pp, phi0, F0); break;
-    case 8: hipLaunchKernelGGL((k_pair<T, 8>), dim3(ncell), dim3(kPairThreads), 0, s, sorted, start, pp, phi0, F0); break;
-  }
-}
-
-template <typename T>
-void launch_anterp(int p, int n, const vec4_t<T>* sorted, const GridDev<T>& g, T* grid,
-                   hipStream_t s) {
+void launch_anterp(int p, int n, int ncell, const int* start, const CellGrid& cg,
+                   const vec4_t<T>* sorted, const GridDev<T>& g, T* grid, hipStream_t s) {
   if (n <= 0) return;
-  const int nb = (n + 255) / 256;
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_anterp<T, 4>), dim3(nb), dim3(256), 0, s, n, sorted, g, grid); break;
-    case 6: hipLaunchKernelGGL((k_anterp<T, 6>), dim3(nb), dim3(256), 0, s, n, sorted, g, grid); break;
-    case 8: hipLaunchKernelGGL((k_anterp<T, 8>), dim3(nb), dim3(256), 0, s, n, sorted, g, grid); break;
+    case 4: hipLaunchKernelGGL((k_anterp_brick<T, 4>), dim3(ncell), dim3(256), 0, s, start, sorted, g, cg, grid); break;
+    case 6: hipLaunchKernelGGL((k_anterp_brick<T, 6>), dim3(ncell), dim3(256), 0, s, start, sorted, g, cg, grid); break;
+    case 8: hipLaunchKernelGGL((k_anterp_brick<T, 8>), dim3(ncell), dim3(256), 0, s, start, sorted, g, cg, grid); break;
   }
 }
 
@@ -373,10 +365,10 @@ void launch_interp(int p, int n, const vec4_t<T>* sorted, const int* perm, const
 
 #define MSM_INST_PARTICLES(T)                                                                    \
   template void launch_binning<T>(int, const T*, const T*, const BinParams<T>&, int, int*, int*, \
-                                  int*, vec4_t<T>*, int*, vec4_t<T>*, int*, int*, hipStream_t);  \
-  template void launch_pair<T>(int, int, const vec4_t<T>*, const int*, const PairParams<T>&,      \
-                               double*, T*, hipStream_t);                                        \
-  template void launch_anterp<T>(int, int, const vec4_t<T>*, const GridDev<T>&, T*, hipStream_t); \
+                                  int*, vec4_t<T>*, int*, int*, vec4_t<T>*, int*, int*,         \
+                                  hipStream_t);                                                 \
+  template void launch_anterp<T>(int, int, int, const int*, const CellGrid&, const vec4_t<T>*,   \
+                                 const GridDev<T>&, T*, hipStream_t);                             \
   template void launch_interp<T>(int, int, const vec4_t<T>*, const int*, const GridDev<T>&,      \
                                  const T*, const double*, const T*, double, T*, T*, T*, T*,       \
                                  double*, hipStream_t);

@@ -81,15 +81,14 @@ struct msm_plan_s {
   bool device = false;
   bool batch = false;
   int ncell = 0;
-  // device buffers (T = plan precision)
-  void* K[msm::kMaxLevels] = {};
+  // device buffers (T = plan precision); stencils in FP64 with zero-padded
+  // rows (conv_row_stride) and per-row non-zero x ranges
   double* K64[msm::kMaxLevels] = {};
-  int2* rowext[msm::kMaxLevels] = {};
+  int2* rowext64[msm::kMaxLevels] = {};
   void* qg[msm::kMaxLevels] = {};
   void* eg[msm::kMaxLevels] = {};
   // factored levels: FP64 k-samples, their row extents, FP64 partial grid
   double* S[msm::kMaxLevels] = {};
-  int2* rowext64[msm::kMaxLevels] = {};  // non-zero rows of the FP64 stencil
   int2* srowext[msm::kMaxLevels] = {};
   double* ug[msm::kMaxLevels] = {};
   void* Jd = nullptr;
@@ -98,11 +97,23 @@ struct msm_plan_s {
   int* counts = nullptr;
   int* start = nullptr;
   int* perm = nullptr;
+  // 8-particle clusters of the short-range sum: offsets per cell, padded
+  // slots (x, y, z, q), boxes (lo, hi), info (first sorted index, count,
+  // cell), force cotangent in slot order (backward)
+  int* cl_start = nullptr;
+  void* cpos = nullptr;
+  void* cbox = nullptr;
+  int4* cinfo = nullptr;
+  void* cv = nullptr;
   void* wrapped = nullptr;
   void* sorted = nullptr;
   void* phi0 = nullptr;
   void* F0 = nullptr;
   int* flag = nullptr;
+  // side streams of the forward DAG (default priority, non-blocking) and the
+  // fork/join events between them and the caller's stream
+  hipStream_t sb = nullptr, sc = nullptr;
+  hipEvent_t ev[4] = {};
   std::vector<void*> allocs;
 };
 
