@@ -175,7 +175,10 @@ msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void
 /*
  * Stage timing with HIP events (benchmarks, MSM_PROFILE-style breakdowns).
  * msm_plan_set_profiling(plan, 1) makes every later msm_energy_forces /
- * msm_backward call record an event pair on its stream around each stage
+ * msm_backward call record an event pair around each stage, on the stream
+ * the stage runs on (the forward runs the pair sum and the coarse levels on
+ * two plan-owned streams beside the caller's; MSM_STREAMS=0 keeps everything
+ * on the caller's stream)
  * (binning, pair, anterpolation, restriction, conv per level, prolongation,
  * interpolation, backward passes); 0 stops recording.  Recording adds no
  * synchronisation.  msm_plan_get_profile synchronises on the recorded events,
@@ -184,6 +187,13 @@ msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void
  */
 msm_status msm_plan_set_profiling(msm_plan plan, int enable);
 msm_status msm_plan_get_profile(msm_plan plan, char* json, size_t cap, int reset);
+/*
+ * Restrict the recording to the stages named in stages (comma separated,
+ * e.g. "conv_l1,pair"; NULL or "" records every stage).  Fewer event pairs
+ * keep the timing of a multi-stream forward close to an unprofiled one.
+ * The string is copied.  MSM_ERR_INVALID_ARG for a NULL plan.
+ */
+msm_status msm_plan_set_profile_stages(msm_plan plan, const char* stages);
 
 const char* msm_status_string(msm_status status);
 

@@ -140,10 +140,12 @@ msm_status upload_plan(msm_plan P) {
   if ((st = hip_alloc(P, &P->Jd, sizeof(J)))) return st;
   if (hipMemcpy(P->Jd, J, sizeof(J), hipMemcpyHostToDevice)) return MSM_ERR_HIP;
   P->ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
+  if ((long long)P->ncell * kCountCopies > (1LL << 30)) return MSM_ERR_GRID;
   const size_t nmax = (size_t)std::max(hp.max_n, 1);
   if ((st = hip_alloc(P, (void**)&P->cell_of, nmax * sizeof(int)))) return st;
   if ((st = hip_alloc(P, (void**)&P->rank, nmax * sizeof(int)))) return st;
-  if ((st = hip_alloc(P, (void**)&P->counts, (size_t)P->ncell * sizeof(int)))) return st;
+  if ((st = hip_alloc(P, (void**)&P->counts, (size_t)P->ncell * kCountCopies * sizeof(int))))
+    return st;
   if ((st = hip_alloc(P, (void**)&P->start, (size_t)(P->ncell + 1) * sizeof(int)))) return st;
   if ((st = hip_alloc(P, (void**)&P->perm, nmax * sizeof(int)))) return st;
   if ((st = hip_alloc(P, &P->wrapped, nmax * 4 * sizeof(T)))) return st;
@@ -228,7 +230,10 @@ void grid_zero_jobs(msm_plan P, ZeroJobs& z) {
   }
 }
 
-// One level of eq. (u_oneplus_nested_eval): e^l = K^l q~^l into eg[l-1].
+// One level of eq. (u_oneplus_nested_eval): e^l = K^l q~^l, into eg[l-1]
+// for a factored level (omega' writes the grid precision) and into the FP64
+// buffer ug[l-1] for a direct one (the prolongation that finalises the level
+// reads it there).
 template <typename T>
 void conv_level(msm_plan P, int l, hipStream_t s) {
   const HostPlan& hp = P->hp;
@@ -263,24 +268,22 @@ void conv_level(msm_plan P, int l, hipStream_t s) {
     pf.end(ev, s);
   } else {
     // direct stencil, accumulated in FP64 (sums of thousands of terms with
-    // cancellation), then rounded to the grid precision
+    // cancellation)
     const int zero3[3] = {0, 0, 0};
     ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
     int ev = pf.begin(cname, s);
     launch_conv<T, double>(cp, P->K64[l - 1], P->rowext64[l - 1], (const T*)P->qg[l - 1],
                            P->ug[l - 1], s);
     pf.end(ev, s);
-    ev = pf.begin("grid_cast", s);
-    launch_cast<T>(P->ug[l - 1], (T*)P->eg[l - 1], g.G, s);
-    pf.end(ev, s);
   }
 }
 
 // Nested grid pass of eq. (u_oneplus_nested_eval): from the level-1 grid in
-// qg[0] to e^{1+} in eg[0].  Two branches: the coarse one (restriction,
-// levels 2..L, prolongation down to level 2) on sb, level 1 on sa; they join
-// before the last prolongation.  sb == sa runs everything in order.  Every
-// eg[l] is overwritten (omega' or cast) before prolongation adds into it.
+// qg[0] to e^{1+} in eg[0].  Two branches: level 1 on sa and the coarse one
+// (restriction, levels 2..L, prolongation down to level 2) on sb; they join
+// before the last prolongation.  sb == sa runs everything in order.
+// Prolongation finalises each level: e^l = (its own convolution output) +
+// I e^{l+1}, reading a direct level's output from its FP64 buffer.
 template <typename T>
 void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb) {
   const HostPlan& hp = P->hp;
@@ -291,6 +294,9 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb) {
     (void)hipEventRecord(P->ev[2], sa);
     (void)hipStreamWaitEvent(sb, P->ev[2], 0);
   }
+  // level 1 first: the host enqueues it before the coarse branch's launches,
+  // so it starts as soon as anterpolation ends
+  conv_level<T>(P, 1, sa);
   hipStream_t sc = fork ? sb : sa;
   int ev = pf.begin("restrict", sc);
   for (int l = 1; l < L; ++l)
@@ -298,29 +304,41 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb) {
                        (const T*)P->qg[l - 1], (T*)P->qg[l], sc);
   pf.end(ev, sc);
   for (int l = 2; l <= L; ++l) conv_level<T>(P, l, sc);
+  // 0-based level l of the output e^l: grid precision in eg[l] for a factored
+  // level, FP64 in ug[l] for a direct one (until its prolongation)
+  auto coarse_src64 = [&](int l) -> const double* {
+    return (l == L - 1 && !hp.lev[l].factored) ? P->ug[l] : nullptr;
+  };
+  auto fine_src64 = [&](int l) -> const double* {
+    return hp.lev[l].factored ? nullptr : P->ug[l];
+  };
   ev = pf.begin("prolong", sc);
-  for (int l = L - 1; l >= 2; --l)
-    launch_prolong<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
-                      (const T*)P->eg[l], (T*)P->eg[l - 1], sc);
+  for (int l = L - 2; l >= 1; --l)
+    launch_prolong<T>(p, grid_dev<T>(hp, l + 1), grid_dev<T>(hp, l + 2), hp.J,
+                      (const T*)P->eg[l + 1], coarse_src64(l + 1), (T*)P->eg[l],
+                      fine_src64(l), sc);
   pf.end(ev, sc);
-  if (fork) (void)hipEventRecord(P->ev[3], sb);
-  conv_level<T>(P, 1, sa);
-  if (fork) (void)hipStreamWaitEvent(sa, P->ev[3], 0);
+  if (fork) {
+    (void)hipEventRecord(P->ev[3], sb);
+    (void)hipStreamWaitEvent(sa, P->ev[3], 0);
+  }
   if (L > 1) {
     ev = pf.begin("prolong", sa);
     launch_prolong<T>(p, grid_dev<T>(hp, 1), grid_dev<T>(hp, 2), hp.J, (const T*)P->eg[1],
-                      (T*)P->eg[0], sa);
+                      coarse_src64(1), (T*)P->eg[0], fine_src64(0), sa);
     pf.end(ev, sa);
+  } else if (!hp.lev[0].factored) {
+    int e2 = pf.begin("grid_cast", sa);
+    launch_cast<T>(P->ug[0], (T*)P->eg[0], hp.lev[0].G, sa);
+    pf.end(e2, sa);
   }
 }
 
-// Whether the forward runs as a DAG over three streams (MSM_STREAMS=0: one).
+// Whether the forward runs as a DAG over three streams (MSM_STREAMS=0: one;
+// read on every call).
 static bool use_streams() {
-  static const bool on = [] {
-    const char* e = getenv("MSM_STREAMS");
-    return !(e && atoi(e) == 0);
-  }();
-  return on;
+  const char* e = getenv("MSM_STREAMS");
+  return !(e && atoi(e) == 0);
 }
 
 template <typename T>
@@ -352,7 +370,7 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
     ZeroJobs z;
     z.n = 0;
     z.ptr[z.n] = P->counts;
-    z.words[z.n++] = P->ncell;
+    z.words[z.n++] = (long long)P->ncell * kCountCopies;
     z.ptr[z.n] = P->qg[0];
     z.words[z.n++] = hp.lev[0].G * (long long)(sizeof(T) / 4);
     z.ptr[z.n] = energy;
@@ -639,9 +657,18 @@ msm_status msm_plan_get_grid(msm_plan plan, int level, int which, void* dst, voi
   if (!plan || plan->batch || !dst || level < 1 || level > plan->hp.L || (which != 0 && which != 1))
     return MSM_ERR_INVALID_ARG;
   if (!plan->device) return MSM_ERR_NO_DEVICE;
+  const HostPlan& hp = plan->hp;
+  const long long G = hp.lev[level - 1].G;
+  if (which == 1 && level == hp.L && hp.L > 1 && !hp.lev[level - 1].factored) {
+    // the top level's potential lives in its FP64 buffer (prolongation reads
+    // it there); hand it out in the grid precision
+    if (hp.precision == MSM_FP64) launch_cast<double>(plan->ug[level - 1], (double*)dst, G, (hipStream_t)stream);
+    else launch_cast<float>(plan->ug[level - 1], (float*)dst, G, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
+  }
   const void* src = which == 0 ? plan->qg[level - 1] : plan->eg[level - 1];
-  if (hipMemcpyAsync(dst, src, tsize(plan->hp) * plan->hp.lev[level - 1].G,
-                     hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess)
+  if (hipMemcpyAsync(dst, src, tsize(hp) * G, hipMemcpyDeviceToDevice, (hipStream_t)stream) !=
+      hipSuccess)
     return MSM_ERR_HIP;
   return MSM_OK;
 }
@@ -650,6 +677,28 @@ msm_status msm_plan_set_profiling(msm_plan plan, int enable) {
   if (!plan) return MSM_ERR_INVALID_ARG;
   if (!plan->device) return MSM_ERR_NO_DEVICE;
   plan->prof.on = enable != 0;
+  return MSM_OK;
+}
+
+msm_status msm_plan_set_profile_stages(msm_plan plan, const char* stages) {
+  if (!plan) return MSM_ERR_INVALID_ARG;
+  try {
+    plan->prof.only.clear();
+    if (stages) {
+      std::string cur;
+      for (const char* c = stages;; ++c) {
+        if (*c == ',' || *c == 0) {
+          if (!cur.empty()) plan->prof.only.push_back(cur);
+          cur.clear();
+          if (*c == 0) break;
+        } else if (*c != ' ') {
+          cur.push_back(*c);
+        }
+      }
+    }
+  } catch (...) {
+    return MSM_ERR_OOM;
+  }
   return MSM_OK;
 }
 

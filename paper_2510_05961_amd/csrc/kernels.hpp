@@ -58,8 +58,10 @@ struct OmegaParams {
   double omega[25];
 };
 
-// Binning: counts, the scans of cell starts and cluster offsets (cl_start),
-// and the scatter into cell order.
+// Binning: counts (kCountCopies counters per cell, ncell * kCountCopies
+// ints), the scans of cell starts and cluster offsets (cl_start), and the
+// scatter into cell order.
+constexpr int kCountCopies = 8;
 template <typename T>
 void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
                     int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
@@ -104,9 +106,14 @@ void launch_interp(int p, int n, const vec4_t<T>* sorted, const int* perm, const
 template <typename T>
 void launch_restrict(int p, const GridDev<T>& fine, const GridDev<T>& coarse, const double* J,
                      const T* qf, T* qc, hipStream_t s);
+// Coarse grid from ecT or ec64 (one of them null); ef64 != null: ef =
+// (T) ef64 + prolongation, else ef += prolongation.
 template <typename T>
 void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, const double* J,
-                    const T* ec, T* ef, hipStream_t s);
+                    const T* ecT, const double* ec64, T* ef, const double* ef64,
+                    hipStream_t s);
+
+
 ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3],
                             const int per[3], const int off[3], const int len[3], int tsize);
 // dynamic LDS bytes of the conv kernel for these parameters (tsize = grid type size)

@@ -15,95 +15,144 @@ __device__ inline int floor_div2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2
 
 // ---------------------------------------------------------------------------
 // a4: restriction (eq. restriction_prolongation_explicit_formulas, first line)
-//   q~^{l+1}_m = sum_n J_{n-2m} q~^l_n,  J_n = J_nx J_ny J_nz,
-// applied as three 1-D tap sets of p+1 taps per coarse point.
+//   q~^{l+1}_m = sum_n J_{n-2m} q~^l_n,  J_n = J_nx J_ny J_nz, p+1 taps per axis;
+// a7: prolongation, its transpose (the paper's corrected form)
+//   e^l_m += sum_n J_{m-2n} e^{l+1}_n, at most p/2+1 coarse points per axis.
+// A workgroup stages the fine (restriction) or coarse (prolongation) window
+// of a block in LDS (periodic wrap; zeros outside a free axis) and applies
+// the 1-D taps axis by axis: x, then y, then z.
 // ---------------------------------------------------------------------------
+constexpr int kRestrictB = 4;  // coarse points per axis per workgroup
+constexpr int kProlongB = 8;   // fine points per axis per workgroup
+
 template <typename T, int P>
-__global__ void k_restrict(GridDev<T> f, GridDev<T> c, JTaps<T> jt, const T* __restrict__ qf,
-                           T* __restrict__ qc) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long G = (long long)c.n[0] * c.n[1] * c.n[2];
-  if (gid >= G) return;
-  const int ic[3] = {(int)(gid % c.n[0]), (int)((gid / c.n[0]) % c.n[1]),
-                     (int)(gid / ((long long)c.n[0] * c.n[1]))};
-  int idx[3][P + 1];
+__global__ void __launch_bounds__(256)
+    k_restrict_tiled(GridDev<T> f, GridDev<T> c, JTaps<T> jt, const T* __restrict__ qf,
+                     T* __restrict__ qc) {
+  constexpr int B = kRestrictB, W = 2 * B + P - 1;
+  __shared__ T F[W * W * W];
+  __shared__ T X1[W * W * B];
+  __shared__ T X2[W * B * B];
+  const int nbx = (c.n[0] + B - 1) / B, nby = (c.n[1] + B - 1) / B;
+  const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+  const int c0[3] = {bx * B, by * B, bz * B};
+  // absolute fine index of window element 0 per axis
+  int f0[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int m = ic[k] + c.lo[k];
-#pragma unroll
-    for (int t = 0; t <= P; ++t) idx[k][t] = axis_index(2 * m + t - P / 2, f.n[k], f.lo[k], f.per[k]);
+  for (int k = 0; k < 3; ++k) f0[k] = 2 * (c0[k] + c.lo[k]) - P / 2;
+  for (int i = threadIdx.x; i < W * W * W; i += blockDim.x) {
+    const int x = i % W, y = (i / W) % W, z = i / (W * W);
+    const int ix = axis_index(f0[0] + x, f.n[0], f.lo[0], f.per[0]);
+    const int iy = axis_index(f0[1] + y, f.n[1], f.lo[1], f.per[1]);
+    const int iz = axis_index(f0[2] + z, f.n[2], f.lo[2], f.per[2]);
+    F[i] = (ix < 0 || iy < 0 || iz < 0) ? T(0)
+                                          : qf[((long long)iz * f.n[1] + iy) * f.n[0] + ix];
   }
-  T s = T(0);
+  __syncthreads();
+  for (int i = threadIdx.x; i < W * W * B; i += blockDim.x) {
+    const int x = i % B, yz = i / B;
+    const T* row = F + yz * W + 2 * x;
+    T sx = T(0);
 #pragma unroll
-  for (int tz = 0; tz <= P; ++tz) {
-    if (idx[2][tz] < 0) continue;
+    for (int t = 0; t <= P; ++t) sx += jt.J[t] * row[t];
+    X1[i] = sx;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < W * B * B; i += blockDim.x) {
+    const int x = i % B, y = (i / B) % B, z = i / (B * B);
     T sy = T(0);
 #pragma unroll
-    for (int ty = 0; ty <= P; ++ty) {
-      if (idx[1][ty] < 0) continue;
-      const T* row = qf + ((long long)idx[2][tz] * f.n[1] + idx[1][ty]) * f.n[0];
-      T sx = T(0);
-#pragma unroll
-      for (int tx = 0; tx <= P; ++tx)
-        if (idx[0][tx] >= 0) sx += jt.J[tx] * row[idx[0][tx]];
-      sy += jt.J[ty] * sx;
-    }
-    s += jt.J[tz] * sy;
+    for (int t = 0; t <= P; ++t) sy += jt.J[t] * X1[(z * W + 2 * y + t) * B + x];
+    X2[i] = sy;
   }
-  qc[gid] = s;
+  __syncthreads();
+  for (int i = threadIdx.x; i < B * B * B; i += blockDim.x) {
+    const int x = i % B, y = (i / B) % B, z = i / (B * B);
+    const int gx = c0[0] + x, gy = c0[1] + y, gz = c0[2] + z;
+    if (gx >= c.n[0] || gy >= c.n[1] || gz >= c.n[2]) continue;
+    T s = T(0);
+#pragma unroll
+    for (int t = 0; t <= P; ++t) s += jt.J[t] * X2[((2 * z + t) * B + y) * B + x];
+    qc[((long long)gz * c.n[1] + gy) * c.n[0] + gx] = s;
+  }
 }
 
-// ---------------------------------------------------------------------------
-// a7: prolongation, the transpose of restriction (paper's corrected form)
-//   e^l_m += sum_n J_{m-2n} e^{l+1}_n,
-// gathered per fine point over the at most p/2+1 coarse points per axis.
-// ---------------------------------------------------------------------------
+// The coarse grid comes from ecT (grid precision) or ec64 (FP64); with ef64
+// the fine result is (T) ef64 + prolongation (the level's own FP64
+// convolution output, cast here), else ef += prolongation.
 template <typename T, int P>
-__global__ void k_prolong(GridDev<T> f, GridDev<T> c, JTaps<T> jt, const T* __restrict__ ec,
-                          T* __restrict__ ef) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long G = (long long)f.n[0] * f.n[1] * f.n[2];
-  if (gid >= G) return;
-  const int im[3] = {(int)(gid % f.n[0]), (int)((gid / f.n[0]) % f.n[1]),
-                     (int)(gid / ((long long)f.n[0] * f.n[1]))};
-  constexpr int NC = P / 2 + 1;
-  int idx[3][NC];
-  T wt[3][NC];
+__global__ void __launch_bounds__(256)
+    k_prolong_tiled(GridDev<T> f, GridDev<T> c, JTaps<T> jt, const T* __restrict__ ecT,
+                    const double* __restrict__ ec64, T* __restrict__ ef,
+                    const double* __restrict__ ef64) {
+  constexpr int B = kProlongB, W = B / 2 + P / 2 + 2;  // coarse window per axis
+  __shared__ T C[W * W * W];
+  __shared__ T X1[W * W * B];
+  __shared__ T X2[W * B * B];
+  const int nbx = (f.n[0] + B - 1) / B, nby = (f.n[1] + B - 1) / B;
+  const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+  const int fb[3] = {bx * B, by * B, bz * B};
+  // absolute coarse index of window element 0 per axis: ceil((m0 - P/2)/2)
+  int n0[3], m0[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int m = im[k] + f.lo[k];
-    const int n_lo = -floor_div2(-(m - P / 2));  // ceil((m - P/2)/2)
-#pragma unroll
-    for (int t = 0; t < NC; ++t) {
-      const int n = n_lo + t;
-      const int kk = m - 2 * n;  // tap index, in [-P/2, P/2] when valid
-      if (kk >= -P / 2 && kk <= P / 2) {
-        idx[k][t] = axis_index(n, c.n[k], c.lo[k], c.per[k]);
-        wt[k][t] = jt.J[kk + P / 2];
-      } else {
-        idx[k][t] = -1;
-        wt[k][t] = T(0);
-      }
-    }
+    m0[k] = fb[k] + f.lo[k];
+    n0[k] = -floor_div2(-(m0[k] - P / 2));
   }
-  T s = T(0);
+  for (int i = threadIdx.x; i < W * W * W; i += blockDim.x) {
+    const int x = i % W, y = (i / W) % W, z = i / (W * W);
+    const int ix = axis_index(n0[0] + x, c.n[0], c.lo[0], c.per[0]);
+    const int iy = axis_index(n0[1] + y, c.n[1], c.lo[1], c.per[1]);
+    const int iz = axis_index(n0[2] + z, c.n[2], c.lo[2], c.per[2]);
+    const long long ci = ((long long)iz * c.n[1] + iy) * c.n[0] + ix;
+    C[i] = (ix < 0 || iy < 0 || iz < 0) ? T(0) : (ec64 ? (T)ec64[ci] : ecT[ci]);
+  }
+  __syncthreads();
+  // fine point m (absolute) takes coarse n with |m - 2n| <= P/2, in order
+  // of increasing n starting at ceil((m - P/2)/2); window offset of that n:
+  // ceil((m - P/2)/2) - n0
+  for (int i = threadIdx.x; i < W * W * B; i += blockDim.x) {
+    const int x = i % B, yz = i / B;
+    const int m = m0[0] + x;
+    const int nl = -floor_div2(-(m - P / 2));
+    T sx = T(0);
 #pragma unroll
-  for (int tz = 0; tz < NC; ++tz) {
-    if (idx[2][tz] < 0) continue;
+    for (int t = 0; t < P / 2 + 1; ++t) {
+      const int kk = m - 2 * (nl + t);
+      if (kk >= -P / 2) sx += jt.J[kk + P / 2] * C[yz * W + (nl + t - n0[0])];
+    }
+    X1[i] = sx;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < W * B * B; i += blockDim.x) {
+    const int x = i % B, y = (i / B) % B, z = i / (B * B);
+    const int m = m0[1] + y;
+    const int nl = -floor_div2(-(m - P / 2));
     T sy = T(0);
 #pragma unroll
-    for (int ty = 0; ty < NC; ++ty) {
-      if (idx[1][ty] < 0) continue;
-      const T* row = ec + ((long long)idx[2][tz] * c.n[1] + idx[1][ty]) * c.n[0];
-      T sx = T(0);
-#pragma unroll
-      for (int tx = 0; tx < NC; ++tx)
-        if (idx[0][tx] >= 0) sx += wt[0][tx] * row[idx[0][tx]];
-      sy += wt[1][ty] * sx;
+    for (int t = 0; t < P / 2 + 1; ++t) {
+      const int kk = m - 2 * (nl + t);
+      if (kk >= -P / 2) sy += jt.J[kk + P / 2] * X1[(z * W + (nl + t - n0[1])) * B + x];
     }
-    s += wt[2][tz] * sy;
+    X2[i] = sy;
   }
-  ef[gid] += s;
+  __syncthreads();
+  for (int i = threadIdx.x; i < B * B * B; i += blockDim.x) {
+    const int x = i % B, y = (i / B) % B, z = i / (B * B);
+    const int gx = fb[0] + x, gy = fb[1] + y, gz = fb[2] + z;
+    if (gx >= f.n[0] || gy >= f.n[1] || gz >= f.n[2]) continue;
+    const int m = m0[2] + z;
+    const int nl = -floor_div2(-(m - P / 2));
+    T s = T(0);
+#pragma unroll
+    for (int t = 0; t < P / 2 + 1; ++t) {
+      const int kk = m - 2 * (nl + t);
+      if (kk >= -P / 2) s += jt.J[kk + P / 2] * X2[((nl + t - n0[2]) * B + y) * B + x];
+    }
+    const long long fi = ((long long)gz * f.n[1] + gy) * f.n[0] + gx;
+    if (ef64) ef[fi] = (T)ef64[fi] + s;
+    else ef[fi] += s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -307,26 +356,29 @@ static JTaps<T> make_taps(const double* J, int p) {
 template <typename T>
 void launch_restrict(int p, const GridDev<T>& fine, const GridDev<T>& coarse, const double* J,
                      const T* qf, T* qc, hipStream_t s) {
-  const long long G = (long long)coarse.n[0] * coarse.n[1] * coarse.n[2];
-  const int nb = (int)((G + 255) / 256);
+  constexpr int B = kRestrictB;
+  const long long nb = (long long)((coarse.n[0] + B - 1) / B) * ((coarse.n[1] + B - 1) / B) *
+                       ((coarse.n[2] + B - 1) / B);
   JTaps<T> jt = make_taps<T>(J, p);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_restrict<T, 4>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, qf, qc); break;
-    case 6: hipLaunchKernelGGL((k_restrict<T, 6>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, qf, qc); break;
-    case 8: hipLaunchKernelGGL((k_restrict<T, 8>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, qf, qc); break;
+    case 4: hipLaunchKernelGGL((k_restrict_tiled<T, 4>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, qf, qc); break;
+    case 6: hipLaunchKernelGGL((k_restrict_tiled<T, 6>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, qf, qc); break;
+    case 8: hipLaunchKernelGGL((k_restrict_tiled<T, 8>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, qf, qc); break;
   }
 }
 
 template <typename T>
 void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, const double* J,
-                    const T* ec, T* ef, hipStream_t s) {
-  const long long G = (long long)fine.n[0] * fine.n[1] * fine.n[2];
-  const int nb = (int)((G + 255) / 256);
+                    const T* ecT, const double* ec64, T* ef, const double* ef64,
+                    hipStream_t s) {
+  constexpr int B = kProlongB;
+  const long long nb = (long long)((fine.n[0] + B - 1) / B) * ((fine.n[1] + B - 1) / B) *
+                       ((fine.n[2] + B - 1) / B);
   JTaps<T> jt = make_taps<T>(J, p);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_prolong<T, 4>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, ec, ef); break;
-    case 6: hipLaunchKernelGGL((k_prolong<T, 6>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, ec, ef); break;
-    case 8: hipLaunchKernelGGL((k_prolong<T, 8>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, ec, ef); break;
+    case 4: hipLaunchKernelGGL((k_prolong_tiled<T, 4>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, ecT, ec64, ef, ef64); break;
+    case 6: hipLaunchKernelGGL((k_prolong_tiled<T, 6>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, ecT, ec64, ef, ef64); break;
+    case 8: hipLaunchKernelGGL((k_prolong_tiled<T, 8>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, ecT, ec64, ef, ef64); break;
   }
 }
 
@@ -381,7 +433,7 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
   static const long long target = [] {
     const char* e = getenv("MSM_CONV_WAVES");
     const long long v = e ? atoll(e) : 0;
-    return v > 0 ? v : 4096LL;
+    return v > 0 ? v : 8192LL;
   }();
   const long long wpb = sh.TXT * sh.TYT / 64;
   const long long blocks =
@@ -446,7 +498,7 @@ void launch_fill(T* p, long long count, T value, hipStream_t s) {
   template void launch_restrict<T>(int, const GridDev<T>&, const GridDev<T>&, const double*,     \
                                    const T*, T*, hipStream_t);                                    \
   template void launch_prolong<T>(int, const GridDev<T>&, const GridDev<T>&, const double*,      \
-                                  const T*, T*, hipStream_t);                                     \
+                                  const T*, const double*, T*, const double*, hipStream_t);       \
   template void launch_omega<T>(const OmegaParams&, const double*, T*, hipStream_t);              \
   template void launch_fill<T>(T*, long long, T, hipStream_t);                                    \
   template void launch_cast<T>(const double*, T*, long long, hipStream_t);

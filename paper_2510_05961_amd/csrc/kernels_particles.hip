@@ -45,8 +45,10 @@ __global__ void k_bin_count(int n, const T* __restrict__ pos, const T* __restric
   }
   if (bad) atomicOr(flag, bad);
   const int cell = (c[2] * bp.nc[1] + c[1]) * bp.nc[0] + c[0];
-  cell_of[i] = cell;
-  rank[i] = atomicAdd(&counts[cell], 1);
+  // kCountCopies counters per cell spread the atomic traffic of dense cells
+  const int slot = cell * kCountCopies + (i & (kCountCopies - 1));
+  cell_of[i] = slot;
+  rank[i] = atomicAdd(&counts[slot], 1);
   vec4_t<T> w;
   w.x = x[0];
   w.y = x[1];
@@ -57,8 +59,9 @@ __global__ void k_bin_count(int n, const T* __restrict__ pos, const T* __restric
 
 // Exclusive scans of the cell counts into start[0..ncell] and of the
 // per-cell cluster counts ceil(count / 8) into cl_start[0..ncell] (one
-// workgroup).
-__global__ void __launch_bounds__(1024) k_scan(int ncell, const int* __restrict__ counts,
+// workgroup).  The kCountCopies counters of every cell are replaced in place
+// by the offset of their first particle (the scatter's base per slot).
+__global__ void __launch_bounds__(1024) k_scan(int ncell, int* __restrict__ counts,
                                                int* __restrict__ start,
                                                int* __restrict__ cl_start) {
   __shared__ int buf[1024], cbuf[1024];
@@ -70,7 +73,14 @@ __global__ void __launch_bounds__(1024) k_scan(int ncell, const int* __restrict_
   }
   __syncthreads();
   for (int base = 0; base < ncell; base += 1024) {
-    const int v = (base + t < ncell) ? counts[base + t] : 0;
+    const int cell = base + t;
+    int sub[kCountCopies];
+    int v = 0;
+#pragma unroll
+    for (int k = 0; k < kCountCopies; ++k) {
+      sub[k] = cell < ncell ? counts[cell * kCountCopies + k] : 0;
+      v += sub[k];
+    }
     const int cv = (v + 7) / 8;
     buf[t] = v;
     cbuf[t] = cv;
@@ -83,9 +93,15 @@ __global__ void __launch_bounds__(1024) k_scan(int ncell, const int* __restrict_
       cbuf[t] += cadd;
       __syncthreads();
     }
-    if (base + t < ncell) {
-      start[base + t] = carry + buf[t] - v;
-      cl_start[base + t] = ccarry + cbuf[t] - cv;
+    if (cell < ncell) {
+      int o = carry + buf[t] - v;
+      start[cell] = o;
+      cl_start[cell] = ccarry + cbuf[t] - cv;
+#pragma unroll
+      for (int k = 0; k < kCountCopies; ++k) {
+        counts[cell * kCountCopies + k] = o;
+        o += sub[k];
+      }
     }
     __syncthreads();
     if (t == 1023) {
@@ -121,11 +137,12 @@ void launch_zero_multi(const ZeroJobs& jobs, hipStream_t s) {
 
 template <typename T>
 __global__ void k_bin_scatter(int n, const int* __restrict__ cell_of, const int* __restrict__ rank,
-                              const int* __restrict__ start, const vec4_t<T>* __restrict__ wrapped,
+                              const int* __restrict__ slot_base,
+                              const vec4_t<T>* __restrict__ wrapped,
                               vec4_t<T>* __restrict__ sorted, int* __restrict__ perm) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int dst = start[cell_of[i]] + rank[i];
+  const int dst = slot_base[cell_of[i]] + rank[i];
   sorted[dst] = wrapped[i];
   perm[dst] = i;
 }
@@ -335,7 +352,7 @@ void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int
                        counts, wrapped, flag);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ncell, counts, start, cl_start);
   if (n > 0)
-    hipLaunchKernelGGL(k_bin_scatter<T>, dim3(nb), dim3(256), 0, s, n, cell_of, rank, start,
+    hipLaunchKernelGGL(k_bin_scatter<T>, dim3(nb), dim3(256), 0, s, n, cell_of, rank, counts,
                        wrapped, sorted, perm);
 }
 

@@ -22,6 +22,7 @@ constexpr int kFlagOffsets = 4;
 // Event-pair stage timer (enabled by msm_plan_set_profiling).
 struct StageProfiler {
   bool on = false;
+  std::vector<std::string> only;  // stages to record (empty: all)
   struct Pending {
     std::string stage;
     hipEvent_t a, b;
@@ -42,6 +43,11 @@ struct StageProfiler {
   // returns an index to close with end(), or -1 when off
   int begin(const char* stage, hipStream_t s) {
     if (!on) return -1;
+    if (!only.empty()) {
+      bool want = false;
+      for (const auto& o : only) want = want || o == stage;
+      if (!want) return -1;
+    }
     Pending p{stage, get(), get()};
     if (!p.a || !p.b) return -1;
     (void)hipEventRecord(p.a, s);

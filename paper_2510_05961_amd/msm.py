@@ -25,7 +25,7 @@ EXPORTS = ("msm_plan_create", "msm_plan_create_host", "msm_plan_destroy", "msm_p
            "msm_plan_get_stencil", "msm_plan_grid_dims", "msm_workspace_bytes",
            "msm_energy_forces", "msm_backward", "msm_plan_status", "msm_plan_get_grid",
            "msm_batch_plan_create", "msm_batch_energy_forces", "msm_status_string",
-           "msm_plan_set_profiling", "msm_plan_get_profile")
+           "msm_plan_set_profiling", "msm_plan_get_profile", "msm_plan_set_profile_stages")
 
 
 class MSMError(RuntimeError):
@@ -63,6 +63,7 @@ def lib():
         L.msm_batch_energy_forces.argtypes = [P, P, P, P, P, P, P, P]
         L.msm_plan_set_profiling.argtypes = [P, i]
         L.msm_plan_get_profile.argtypes = [P, ctypes.c_char_p, sz, i]
+        L.msm_plan_set_profile_stages.argtypes = [P, ctypes.c_char_p]
         L.msm_status_string.argtypes = [i]
         L.msm_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -181,6 +182,11 @@ class Plan:
     def set_profiling(self, on=True):
         _check(lib().msm_plan_set_profiling(self._h, int(bool(on))), "set_profiling")
 
+    def set_profile_stages(self, stages=None):
+        """Record only these stages (iterable of names; None: all)."""
+        arg = None if not stages else ",".join(stages).encode()
+        _check(lib().msm_plan_set_profile_stages(self._h, arg), "set_profile_stages")
+
     def profile(self, reset=False):
         """{stage: {"ms": total, "launches": n}} since the last reset."""
         buf = ctypes.create_string_buffer(1 << 16)
@@ -219,6 +225,7 @@ class BatchPlan:
     describe = Plan.describe
     status = Plan.status
     set_profiling = Plan.set_profiling
+    set_profile_stages = Plan.set_profile_stages
     profile = Plan.profile
 
     def energy_forces(self, offsets, pos, q, stream=None, out=None):
