@@ -41,6 +41,23 @@ def _pair_count(pos, box, a):
     return int((t.count_neighbors(t, a) - len(p)) // 2)
 
 
+def _measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE
+    counter runs recorded in profiles/, or None when that kernel's source has
+    changed since (first 16 hex digits of the file's SHA-256 differ)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_water100k_fp32.md")
+    try:
+        line = next(l for l in open(path) if l.startswith("traffic-json: "))
+        rec = json.loads(line[len("traffic-json: "):])[kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, StopIteration, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return int(rec["bytes"])
+
+
 def _time(fn, torch, reps):
     fn()
     torch.cuda.synchronize()
@@ -233,7 +250,7 @@ def main():
     achieved = flops / dur_s / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": None, "arith": adt,
+                "traffic": _measured_traffic(dom), "arith": adt,
                 "algorithmic_per_launch": flops,
                 "avg_launch_ms": round(per_launch[dom], 5)}
     kernels = {}
@@ -241,7 +258,8 @@ def main():
         if k in per_launch:
             a_ = fl / (per_launch[k] * 1e-3) / 1e12
             kernels[k] = {"achieved": round(a_, 3), "peak": pk, "arith": at,
-                          "frac": round(a_ / pk, 4), "avg_launch_ms": round(per_launch[k], 5)}
+                          "frac": round(a_ / pk, 4), "avg_launch_ms": round(per_launch[k], 5),
+                          "traffic": _measured_traffic(k)}
     if standalone:
         for k, (fl, pk, at) in candidates.items():
             if k in standalone:
