@@ -126,12 +126,12 @@ msm_status upload_plan(msm_plan P) {
     if ((st = hip_alloc(P, (void**)&P->ug[l - 1], (size_t)gbuf * sizeof(double)))) return st;
     const int zero3[3] = {0, 0, 0};
     ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
-    if (conv_lds_bytes(cp, sizeof(T)) > 160 * 1024) return MSM_ERR_GRID;
+    if (conv_lds_bytes(cp, sizeof(T)) > 64 * 1024 || cp.lds_w > kConvMaxLW) return MSM_ERR_GRID;
     if (g.factored) {
       if ((st = upload_stencil(g.S, g.s_len, &P->S[l - 1], &P->srowext[l - 1]))) return st;
       ConvParams cs = make_conv_params(g.n, g.next, g.shift, hp.periodic, g.s_off, g.s_len,
                                        sizeof(T));
-      if (conv_lds_bytes(cs, sizeof(T)) > 160 * 1024) return MSM_ERR_GRID;
+      if (conv_lds_bytes(cs, sizeof(T)) > 64 * 1024 || cs.lds_w > kConvMaxLW) return MSM_ERR_GRID;
       if (omega_lds_bytes(hp.M) > 160 * 1024) return MSM_ERR_GRID;
     }
   }
@@ -461,7 +461,7 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
   vec4_t<T>* v = (vec4_t<T>*)P->wrapped;  // cotangent in cell order
   T* gq_sr = (T*)P->phi0;
   T* gr_sr = (T*)P->F0;
-  int ev = pf.begin("bwd_pair", s);
+  int ev = pf.begin("bwd_layout", s);
   launch_gather_v<T>(n, perm, gF, v, s);
   {
     // cluster layout of the saved (already Morton-ordered) cell list
@@ -476,10 +476,20 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
                              const_cast<vec4_t<T>*>(sorted), const_cast<int*>(perm),
                              (vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cbox, P->cinfo, s);
   }
+  pf.end(ev, s);
+  // the pair-sum VJP beside the grid part (as in the forward)
+  const bool dag = use_streams();
+  hipStream_t sp = dag ? P->sc : s;
+  if (dag) {
+    (void)hipEventRecord(P->ev[0], s);
+    (void)hipStreamWaitEvent(sp, P->ev[0], 0);
+  }
+  ev = pf.begin("bwd_pair", sp);
   launch_pair_vjp_cl<T>(p, n, P->ncell, P->cl_start, P->cinfo, perm, gF,
                         (const vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cv, (const vec4_t<T>*)P->cbox,
-                        pair_params<T>(hp), gq_sr, gr_sr, s);
-  pf.end(ev, s);
+                        pair_params<T>(hp), gq_sr, gr_sr, sp);
+  pf.end(ev, sp);
+  if (dag) (void)hipEventRecord(P->ev[1], sp);
   const GridDev<T> g1 = grid_dev<T>(hp, 1);
   ev = pf.begin("bwd_anterp", s);
   {
@@ -492,7 +502,8 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
   }
   launch_anterp_dipole<T>(p, n, sorted, v, g1, (T*)P->qg[0], s);
   pf.end(ev, s);
-  grid_pass<T>(P, s, s);  // eg[0] = (A D)^{1+}
+  grid_pass<T>(P, s, dag ? P->sb : s);  // eg[0] = (A D)^{1+}
+  if (dag) (void)hipStreamWaitEvent(s, P->ev[1], 0);
   ev = pf.begin("bwd_interp", s);
   launch_interp_vjp<T>(p, n, sorted, v, perm, g1, save_e1, (const T*)P->eg[0], save_phi, save_F,
                        gq_sr, gr_sr, gE, grad_q, grad_pos, s);

@@ -40,6 +40,7 @@ struct ConvParams {
   int shape;            // tile shape (kernels_grid.hip)
 };
 constexpr int kConvCH = 4;      // taps per register window of the convolution
+constexpr int kConvMaxLW = 512; // widest staged window row
 constexpr int kConvRowPad = 3;  // zero rows around each stencil plane (Q - 1 for Q <= 4)
 int conv_row_stride(int len0);
 

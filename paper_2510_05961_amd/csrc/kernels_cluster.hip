@@ -182,6 +182,20 @@ __device__ inline T box_gap2(T jlo_x, T jlo_y, T jlo_z, T jhi_x, T jhi_y, T jhi_
   return gx * gx + gy * gy + gz * gz;
 }
 
+// A wave-uniform value held in a VGPR: one VALU instruction may read only
+// one SGPR, so the leading Horner coefficient lives in a VGPR (loaded once)
+// instead of being copied from its SGPR at every pair block.
+__device__ inline float in_vgpr(float x) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+__device__ inline double in_vgpr(double x) {
+  double r;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+
 // Sum over the 8 lanes of one i-member (lanes 8 il .. 8 il + 7).
 template <typename V>
 __device__ inline V sum8(V v) {
@@ -193,12 +207,13 @@ __device__ inline V sum8(V v) {
 
 // Visits every j-cluster whose box (shifted image) lies within the cutoff of
 // the i-cluster's box and calls body(jc, sx, sy, sz, self_block) uniformly
-// over the wave.  The i-box and everything below are wave-uniform.
-template <typename T, typename Body>
+// over the wave, and flush() after each neighbour cell.  The i-box and
+// everything below are wave-uniform.
+template <typename T, typename Body, typename Flush>
 __device__ inline void for_each_cluster_pair(const PairParams<T>& pp, const int* cl_start,
                                              const vec4_t<T>* cbox, int ic, int cell,
                                              const vec4_t<T>& blo, const vec4_t<T>& bhi,
-                                             Body&& body) {
+                                             Body&& body, Flush&& flush) {
   const int lane = threadIdx.x & 63;
   const int cx = cell % pp.nc[0];
   const int cy = (cell / pp.nc[0]) % pp.nc[1];
@@ -249,6 +264,7 @@ __device__ inline void for_each_cluster_pair(const PairParams<T>& pp, const int*
             body(j, sx, sy, sz, zero_shift && j == ic);
           }
         }
+        flush();
       }
     }
   }
@@ -268,30 +284,41 @@ __global__ void __launch_bounds__(kClusterThreads)
   const vec4_t<T> pi = cpos[(size_t)ic * 8 + il];
   const vec4_t<T> blo = cbox[2 * (size_t)ic], bhi = cbox[2 * (size_t)ic + 1];
   const T two_inv_a3 = T(2) * pp.inv_a3;
+  const T c_top = in_vgpr(pp.c[P - 1]), dc_top = in_vgpr(pp.dc[P - 2]);
+  const T a2v = in_vgpr(pp.a2);
   double ph = 0.0;  // the potential is carried in FP64 up to the energy sum
+  T phc = T(0);     // ... after a partial sum over one neighbour cell
   T fx = T(0), fy = T(0), fz = T(0);
-  for_each_cluster_pair<T>(pp, cl_start, cbox, ic, inf.z, blo, bhi,
-                           [&](int jc, T sx, T sy, T sz, bool self_block) {
-    const vec4_t<T> pj = cpos[(size_t)jc * 8 + jl];
-    const T dx = (pi.x - sx) - pj.x, dy = (pi.y - sy) - pj.y, dz = (pi.z - sz) - pj.z;
-    const T r2 = dx * dx + dy * dy + dz * dz;
-    const bool ok = r2 < pp.a2 && !(self_block && il == jl);
-    const T rinv = rsqrt_t(r2);
-    const T t = r2 * pp.inv_a2;
-    T Pt = pp.c[P - 1], dP = pp.dc[P - 2];
+  for_each_cluster_pair<T>(
+      pp, cl_start, cbox, ic, inf.z, blo, bhi,
+      [&](int jc, T sx, T sy, T sz, bool self_block) {
+        const vec4_t<T> pj = cpos[(size_t)jc * 8 + jl];
+        const T dx = (pi.x - sx) - pj.x, dy = (pi.y - sy) - pj.y, dz = (pi.z - sz) - pj.z;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const bool ok = r2 < pp.a2 && !(self_block && il == jl);
+        // pairs outside the cutoff (and the self pair) get r = a and a zero
+        // charge, so every intermediate stays finite
+        const T r2c = ok ? r2 : a2v;
+        const T qj = ok ? pj.w : T(0);
+        const T rinv = rsqrt_t(r2c);
+        const T t = r2c * pp.inv_a2;
+        T Pt = c_top, dP = dc_top;
 #pragma unroll
-    for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
+        for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
 #pragma unroll
-    for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
-    const T e = rinv - Pt * pp.inv_a;
-    const T f = rinv * rinv * rinv + dP * two_inv_a3;
-    const T qe = ok ? pj.w * e : T(0);
-    const T fs = ok ? pj.w * f : T(0);
-    ph += (double)qe;
-    fx += fs * dx;
-    fy += fs * dy;
-    fz += fs * dz;
-  });
+        for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
+        const T e = rinv - Pt * pp.inv_a;
+        const T f = rinv * rinv * rinv + dP * two_inv_a3;
+        const T fs = qj * f;
+        phc += qj * e;
+        fx += fs * dx;
+        fy += fs * dy;
+        fz += fs * dz;
+      },
+      [&]() {
+        ph += (double)phc;
+        phc = T(0);
+      });
   ph = sum8(ph);
   fx = sum8(fx);
   fy = sum8(fy);
@@ -344,33 +371,39 @@ __global__ void __launch_bounds__(kClusterThreads)
   const vec4_t<T> pi = cpos[(size_t)ic * 8 + il];
   const vec4_t<T> vi = cv[(size_t)ic * 8 + il];
   const vec4_t<T> blo = cbox[2 * (size_t)ic], bhi = cbox[2 * (size_t)ic + 1];
+  const T dc_top = in_vgpr(pp.dc[P - 2]), d2c_top = in_vgpr(pp.d2c[P - 3]);
+  const T a2v = in_vgpr(pp.a2);
   T sq = T(0), rx = T(0), ry = T(0), rz = T(0);
-  for_each_cluster_pair<T>(pp, cl_start, cbox, ic, inf.z, blo, bhi,
-                           [&](int jc, T sx, T sy, T sz, bool self_block) {
-    const vec4_t<T> pj = cpos[(size_t)jc * 8 + jl];
-    const vec4_t<T> vj = cv[(size_t)jc * 8 + jl];
-    const T dx = (pi.x - sx) - pj.x, dy = (pi.y - sy) - pj.y, dz = (pi.z - sz) - pj.z;
-    const T r2 = dx * dx + dy * dy + dz * dz;
-    const bool ok = r2 < pp.a2 && !(self_block && il == jl);
-    const T rinv = rsqrt_t(r2);
-    const T rinv2 = rinv * rinv;
-    const T t = r2 * pp.inv_a2;
-    T dP = pp.dc[P - 2], d2P = pp.d2c[P - 3];
+  for_each_cluster_pair<T>(
+      pp, cl_start, cbox, ic, inf.z, blo, bhi,
+      [&](int jc, T sx, T sy, T sz, bool self_block) {
+        const vec4_t<T> pj = cpos[(size_t)jc * 8 + jl];
+        const vec4_t<T> vj = cv[(size_t)jc * 8 + jl];
+        const T dx = (pi.x - sx) - pj.x, dy = (pi.y - sy) - pj.y, dz = (pi.z - sz) - pj.z;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const bool ok = r2 < pp.a2 && !(self_block && il == jl);
+        const T r2c = ok ? r2 : a2v;
+        const T qj = ok ? pj.w : T(0);
+        const T rinv = rsqrt_t(r2c);
+        const T rinv2 = rinv * rinv;
+        const T t = r2c * pp.inv_a2;
+        T dP = dc_top, d2P = d2c_top;
 #pragma unroll
-    for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
+        for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
 #pragma unroll
-    for (int k = P - 4; k >= 0; --k) d2P = d2P * t + pp.d2c[k];
-    const T f = rinv * rinv2 + T(2) * dP * pp.inv_a3;
-    const T fpr = T(-3) * rinv2 * rinv2 * rinv + T(4) * d2P * pp.inv_a5;
-    const T wx = vi.x - vj.x, wy = vi.y - vj.y, wz = vi.z - vj.z;
-    const T wd = wx * dx + wy * dy + wz * dz;
-    const T qf = ok ? pj.w * f : T(0);
-    const T c2 = ok ? pj.w * fpr * wd : T(0);
-    sq += qf * wd;
-    rx += qf * wx + c2 * dx;
-    ry += qf * wy + c2 * dy;
-    rz += qf * wz + c2 * dz;
-  });
+        for (int k = P - 4; k >= 0; --k) d2P = d2P * t + pp.d2c[k];
+        const T f = rinv * rinv2 + T(2) * dP * pp.inv_a3;
+        const T fpr = T(-3) * rinv2 * rinv2 * rinv + T(4) * d2P * pp.inv_a5;
+        const T wx = vi.x - vj.x, wy = vi.y - vj.y, wz = vi.z - vj.z;
+        const T wd = wx * dx + wy * dy + wz * dz;
+        const T qf = qj * f;
+        const T c2 = qj * fpr * wd;
+        sq += qf * wd;
+        rx += qf * wx + c2 * dx;
+        ry += qf * wy + c2 * dy;
+        rz += qf * wz + c2 * dz;
+      },
+      []() {});
   sq = sum8(sq);
   rx = sum8(rx);
   ry = sum8(ry);

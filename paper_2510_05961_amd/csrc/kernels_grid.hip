@@ -197,21 +197,34 @@ __global__ void __launch_bounds__(TXT * TYT)
   for (int a = 0; a < Q; ++a)
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[a][r] = TA(0);
+  // input column of every window column (-1: outside a free axis), once per
+  // workgroup; the staging below then needs no per-element division
+  __shared__ int colsrc[kConvMaxLW];
+  for (int c = threadIdx.x; c < LW; c += TXT * TYT) {
+    int xi = xs + c;
+    if (cp.per[0]) xi = wrap_index(xi, n0);
+    else if (xi < 0 || xi >= n0) xi = -1;
+    colsrc[c] = xi;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int jz = jz0; jz < jz1; ++jz) {
     int zi = z + cp.shift[2] - (cp.off[2] + jz);
     if (cp.per[2]) zi = wrap_index(zi, n2);
     else if (zi < 0 || zi >= n2) continue;  // uniform over the workgroup
     __syncthreads();
     const TI* qz = q + (long long)zi * n1 * n0;
-    for (int idx = threadIdx.x; idx < LW * LH; idx += TXT * TYT) {
-      const int ry = idx / LW, rx = idx - ry * LW;
-      int yi = ys + ry, xi = xs + rx;
+    // one wave per window row, lanes along x
+    for (int ry = wave; ry < LH; ry += (TXT * TYT) >> 6) {
+      int yi = ys + ry;
       bool ok = true;
       if (cp.per[1]) yi = wrap_index(yi, n1);
       else ok = (yi >= 0 && yi < n1);
-      if (cp.per[0]) xi = wrap_index(xi, n0);
-      else ok = ok && (xi >= 0 && xi < n0);
-      lds[idx] = ok ? qz[(long long)yi * n0 + xi] : TI(0);
+      const TI* src = qz + (long long)(ok ? yi : 0) * n0;
+      TI* dst = lds + ry * LW;
+      for (int c = lane; c < LW; c += 64) {
+        const int xi = colsrc[c];
+        dst[c] = (ok && xi >= 0) ? src[xi] : TI(0);
+      }
     }
     __syncthreads();
     // plane jz of the stencil: ly + 2 kConvRowPad rows of stride lxp
@@ -412,7 +425,7 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
     const ConvShape& sh = kShapes[c];
     const int TX = sh.TXT * sh.R, TY = sh.TYT * sh.Q;
     const size_t lds = (size_t)(TX + len[0] - 1 + kConvCH - 1) * (TY + len[1] - 1) * tsize;
-    if (lds > 64 * 1024) continue;
+    if (lds > 64 * 1024 || TX + len[0] - 1 + kConvCH - 1 > kConvMaxLW) continue;
     const double tiles = (double)((nout[0] + TX - 1) / TX) * ((nout[1] + TY - 1) / TY) * nout[2];
     const double waves = tiles * len[2] * (sh.TXT * sh.TYT / 64);
     double cost = tiles * TX * TY / sh.eff;

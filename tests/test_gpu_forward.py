@@ -57,6 +57,9 @@ SMALL = [
     ((14.0, 13.0, 9.0), (1, 1, 0), 4, 1.0, 4.0, 3, True, 400),
     ((14.0, 13.0, 9.0), (1, 1, 0), 8, 1.0, 4.0, 2, False, 401),
     ((10.0, 10.0, 10.0), (1, 1, 1), 8, 1.25, 3.0, 3, True, 300),
+    # a single level (the top level is level 1)
+    ((11.0, 10.0, 12.0), (0, 0, 0), 4, 1.0, 3.0, 1, True, 200),
+    ((12.0, 12.0, 12.0), (1, 1, 1), 4, 1.0, 4.0, 1, False, 256),
 ]
 
 
@@ -162,3 +165,48 @@ def test_full_size_sampled(cfg):
     eP = rel_rms(g["phi"][sel], phi_r)
     print(f"  sampled relF={eF:.2e} relPhi={eP:.2e}", flush=True)
     assert eF <= TOL["fp32"]["F"] and eP <= TOL["fp32"]["phi"]
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_streams_match_single_stream(fp64):
+    """The three-stream forward (pair sum and coarse levels beside level 1)
+    against everything on the caller's stream: equal up to the order of the
+    atomic additions."""
+    import os
+    box, per, p, h, a, L = (24.0, 24.0, 24.0), (1, 1, 1), 4, 0.75, 4.0, 4
+    pos, q = WL.gaussian_charges(3000, box, 0.5, seed=21)
+    pos, q = cast(pos, q, fp64)
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP64 if fp64 else msm.MSM_FP32, 3000)
+    out = {}
+    for mode in ("0", "1"):
+        os.environ["MSM_STREAMS"] = mode
+        try:
+            out[mode] = gpu_forward(plan, pos, q)
+        finally:
+            del os.environ["MSM_STREAMS"]
+    tol = 1e-12 if fp64 else 1e-6
+    assert abs(out["0"]["E"] - out["1"]["E"]) <= tol * abs(out["0"]["E"])
+    assert rel_rms(out["1"]["F"], out["0"]["F"]) <= tol
+    assert rel_rms(out["1"]["phi"], out["0"]["phi"]) <= tol
+
+
+def test_profile_stage_filter():
+    import torch
+    box = (16.0, 16.0, 16.0)
+    pos, q = WL.gaussian_charges(500, box, 0.5, seed=4)
+    plan = msm.Plan(box, 7, 4, 1.0, 4.0, 3, msm.MSM_FP32, 500)
+    P = torch.tensor(pos, dtype=torch.float32, device="cuda")
+    Q = torch.tensor(q, dtype=torch.float32, device="cuda")
+    plan.set_profile_stages(["pair", "interp"])
+    plan.set_profiling(True)
+    plan.energy_forces(P, Q)
+    plan.energy_forces(P, Q)
+    plan.set_profiling(False)
+    prof = plan.profile(reset=True)
+    assert set(prof) == {"pair", "interp"}
+    assert all(v["launches"] == 2 and v["ms"] > 0 for v in prof.values())
+    plan.set_profile_stages(None)
+    plan.set_profiling(True)
+    plan.energy_forces(P, Q)
+    plan.set_profiling(False)
+    assert {"bin", "pair", "anterp", "conv_l1", "interp"} <= set(plan.profile(reset=True))
