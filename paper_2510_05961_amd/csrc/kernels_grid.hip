@@ -2,6 +2,7 @@
 // and the per-level stencil convolution (also used for the dense top level).
 #include <cstdlib>
 
+#include "conv_tile.hpp"
 #include "kernels.hpp"
 
 namespace msm {
@@ -158,19 +159,13 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // a5 / a6: stencil convolution e_o = sum_d K_d q_{o+shift-d} (eq.
 // action_of_K_as_convolution).  A workgroup owns a (TXT R) x (TYT Q) tile of
-// output points of one z-plane and a contiguous range of stencil z-planes.
+// output points of one z-plane and a contiguous range of stencil z-planes
+// (split across workgroups, FP64 atomics, when a launch needs more waves).
 // For each stencil plane it stages the input window (periodic wrap or zero
-// padding) through LDS; every thread keeps R consecutive x outputs of Q
-// consecutive rows in registers.  The thread walks the input rows of its
-// window: one input row serves its Q output rows through Q different stencil
-// rows, so each LDS value, converted once to the accumulation type, feeds up
-// to Q R CH multiply-adds.  Taps go in chunks of CH over the union of the Q
-// rows' non-zero x ranges; stencil rows are stored with CH-1 trailing zeros
-// (row stride lxp) so no remainder loop is needed, and every plane carries
-// kConvRowPad zero rows before and after it so that all Q rows can be read
-// unconditionally.  The coefficients are
-// uniform across the workgroup (scalar loads).  TI is the grid type (what
-// LDS holds), TA the stencil / accumulation / output type (FP64 here).
+// padding) through LDS, one wave per window row, and adds the plane with
+// conv_plane (conv_tile.hpp): R x Q outputs per thread in registers, taps in
+// chunks over padded stencil rows, workgroup-uniform coefficients.  TI is the
+// grid type (what LDS holds), TA the stencil / accumulation / output type.
 // ---------------------------------------------------------------------------
 template <typename TI, typename TA, int R, int Q, int TXT, int TYT>
 __global__ void __launch_bounds__(TXT * TYT)
@@ -229,38 +224,8 @@ __global__ void __launch_bounds__(TXT * TYT)
     __syncthreads();
     // plane jz of the stencil: ly + 2 kConvRowPad rows of stride lxp
     const TA* Kz = K + ((long long)jz * (ly + 2 * kConvRowPad) + kConvRowPad) * lxp;
-    const int2* ext_z = rowext + jz * ly;
-    for (int v = 0; v < Q + ly - 1; ++v) {
-      // output row a of the thread uses stencil row jy = a + ly - 1 - v
-      const int alo = max(0, v - ly + 1), ahi = min(Q - 1, v);
-      int first = lx, last = -1;
-      for (int a = alo; a <= ahi; ++a) {
-        const int2 ex = ext_z[a + ly - 1 - v];
-        first = min(first, ex.x);
-        last = max(last, ex.y);
-      }
-      const TI* lrow = lds + (ty * Q + v) * LW + tx * R + (lx - 1);
-      for (int j0 = first; j0 <= last; j0 += CH) {
-        TA win[CH + R - 1];
-        const TI* wp = lrow - j0;
-#pragma unroll
-        for (int u = 0; u < CH + R - 1; ++u) win[u] = (TA)wp[u];
-        // rows outside the stencil (a < alo or a > ahi) are zero padding;
-        // all Q CH coefficients are loaded first, then the multiply-adds go
-        // tap by tap across all Q R accumulators (independent chains)
-        TA kv[Q][CH];
-#pragma unroll
-        for (int a = 0; a < Q; ++a)
-#pragma unroll
-          for (int c = 0; c < CH; ++c) kv[a][c] = Kz[(long long)(a + ly - 1 - v) * lxp + j0 + c];
-#pragma unroll
-        for (int c = 0; c < CH; ++c)
-#pragma unroll
-          for (int a = 0; a < Q; ++a)
-#pragma unroll
-            for (int r = 0; r < R; ++r) acc[a][r] = fma(kv[a][c], win[CH - 1 - c + r], acc[a][r]);
-      }
-    }
+    conv_plane<TI, TA, R, Q>(lds, LW, tx, ty, Kz, rowext + jz * ly, lx, ly, lxp, 0, lx - 1, 0,
+                             Q + ly - 2, acc);
   }
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
