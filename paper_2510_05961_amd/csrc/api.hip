@@ -124,6 +124,8 @@ msm_status upload_plan(msm_plan P) {
     // FP64 accumulation buffer of the level's convolution
     const long long gbuf = std::max(g.G, g.factored ? g.Gext : 0LL);
     if ((st = hip_alloc(P, (void**)&P->ug[l - 1], (size_t)gbuf * sizeof(double)))) return st;
+    if (g.factored && (st = hip_alloc(P, (void**)&P->ut[l - 1], (size_t)g.Gext * sizeof(double))))
+      return st;
     const int zero3[3] = {0, 0, 0};
     ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
     if (conv_lds_bytes(cp, sizeof(T)) > 64 * 1024 || cp.lds_w > kConvMaxLW) return MSM_ERR_GRID;
@@ -132,7 +134,6 @@ msm_status upload_plan(msm_plan P) {
       ConvParams cs = make_conv_params(g.n, g.next, g.shift, hp.periodic, g.s_off, g.s_len,
                                        sizeof(T));
       if (conv_lds_bytes(cs, sizeof(T)) > 64 * 1024 || cs.lds_w > kConvMaxLW) return MSM_ERR_GRID;
-      if (omega_lds_bytes(hp.M) > 160 * 1024) return MSM_ERR_GRID;
     }
   }
   T J[9] = {};
@@ -264,7 +265,7 @@ void conv_level(msm_plan P, int l, hipStream_t s) {
     op.M = hp.M;
     for (int k = 0; k < 25; ++k) op.omega[k] = k <= hp.M ? hp.omega[k] : 0.0;
     ev = pf.begin(omega_names[l - 1], s);
-    launch_omega<T>(op, P->ug[l - 1], (T*)P->eg[l - 1], s);
+    launch_omega<T>(op, P->ug[l - 1], P->ut[l - 1], (T*)P->eg[l - 1], s);
     pf.end(ev, s);
   } else {
     // direct stencil, accumulated in FP64 (sums of thousands of terms with

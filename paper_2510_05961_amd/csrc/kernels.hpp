@@ -59,6 +59,14 @@ struct OmegaParams {
   double omega[25];
 };
 
+// One axis pass of omega': dims of its input and output (they differ only
+// along the pass's axis), whether that axis is periodic, the taps.
+struct OmegaPass {
+  int in[3], out[3];
+  int per, M;
+  double omega[25];
+};
+
 // Binning: counts (kCountCopies counters per cell, ncell * kCountCopies
 // ints), the scans of cell starts and cluster offsets (cl_start), and the
 // scatter into cell order.
@@ -122,9 +130,10 @@ size_t conv_lds_bytes(const ConvParams& cp, int tsize);
 template <typename TI, typename TA>
 void launch_conv(const ConvParams& cp, const TA* K, const int2* rowext, const TI* q, TA* e,
                  hipStream_t s);
-size_t omega_lds_bytes(int M);
+// Three passes; u (extended grid) is overwritten by the y pass, t holds the
+// x pass (both at least next0 next1 next2 doubles).
 template <typename TO>
-void launch_omega(const OmegaParams& op, const double* u, TO* e, hipStream_t s);
+void launch_omega(const OmegaParams& op, double* u, double* t, TO* e, hipStream_t s);
 
 template <typename T>
 void launch_fill(T* p, long long count, T value, hipStream_t s);

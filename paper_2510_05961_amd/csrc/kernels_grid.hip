@@ -245,65 +245,41 @@ __global__ void __launch_bounds__(TXT * TYT)
 
 // ---------------------------------------------------------------------------
 // Second half of the factored stencil: e_m = sum_k omega'_kx omega'_ky
-// omega'_kz u_{m-k}, applied one axis at a time inside LDS on a T^3 output
-// tile (u lives on the extended domain of the free axes).
+// omega'_kz u_{m-k}, one axis per launch (x, then y, then z).  Each thread
+// owns one output point and sums its 2M+1 taps in order k = -M..M; a wave
+// covers 64 consecutive x, so every tap is a coalesced read (the x pass's
+// neighbouring taps come from the same cache lines).  Along a periodic axis
+// the input index wraps; along a free one the input lives on the extended
+// domain (index m + M - k) and is zero outside it.  The passes keep no
+// tile in LDS, so they run beside the level-1 convolution's workgroups.
 // ---------------------------------------------------------------------------
-template <typename TO, int T>
+template <typename TO, int AX>
 __global__ void __launch_bounds__(256)
-    k_omega(OmegaParams op, const double* __restrict__ u, TO* __restrict__ e) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* buf = reinterpret_cast<double*>(smem_raw);
-  const int M = op.M, W = T + 2 * M;
-  double* reg0 = buf;                 // [W][W][W]   u window
-  double* reg1 = reg0 + W * W * W;    // [W][W][T]   after the x pass
-  double* reg2 = reg1 + W * W * T;    // [W][T][T]   after the y pass
-  const int m0[3] = {(int)blockIdx.x * T, (int)blockIdx.y * T, (int)blockIdx.z * T};
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int idx = tid; idx < W * W * W; idx += nt) {
-    const int rx = idx % W, ry = (idx / W) % W, rz = idx / (W * W);
-    const int r3[3] = {rx, ry, rz};
-    long long off = 0, stride = 1;
-    bool ok = true;
-    for (int k = 0; k < 3; ++k) {
-      int m = m0[k] - M + r3[k];  // grid index of u needed
-      int ui;
-      if (op.per[k]) {
-        ui = wrap_index(m, op.n[k]);
-      } else {
-        ui = m + M;  // extended index
-        ok = ok && (ui >= 0 && ui < op.next[k]);
-      }
-      off += (long long)ui * stride;
-      stride *= op.next[k];
+    k_omega_pass(OmegaPass pa, const double* __restrict__ in, TO* __restrict__ out) {
+  const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= pa.out[0] || y >= pa.out[1]) return;
+  const int c[3] = {x, y, z};
+  const int m = c[AX], nin = pa.in[AX], M = pa.M;
+  const long long stride = AX == 0 ? 1LL : AX == 1 ? (long long)pa.in[0] : (long long)pa.in[0] * pa.in[1];
+  long long base = 0;
+  {
+    const int cx = AX == 0 ? 0 : x, cy = AX == 1 ? 0 : y, cz = AX == 2 ? 0 : z;
+    base = ((long long)cz * pa.in[1] + cy) * pa.in[0] + cx;
+  }
+  double s = 0.0;
+  for (int k = -M; k <= M; ++k) {
+    int i;
+    if (pa.per) {
+      i = m - k;
+      if (i < 0 || i >= nin) i = wrap_index(i, nin);
+    } else {
+      i = m + M - k;
+      if (i < 0 || i >= nin) continue;
     }
-    reg0[idx] = ok ? u[off] : 0.0;
+    s += pa.omega[k < 0 ? -k : k] * in[base + i * stride];
   }
-  __syncthreads();
-  for (int idx = tid; idx < W * W * T; idx += nt) {
-    const int x = idx % T, ry = (idx / T) % W, rz = idx / (T * W);
-    const double* row = reg0 + (rz * W + ry) * W;
-    double s = 0.0;
-    for (int k = -M; k <= M; ++k) s += op.omega[k < 0 ? -k : k] * row[x + M - k];
-    reg1[idx] = s;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < W * T * T; idx += nt) {
-    const int x = idx % T, y = (idx / T) % T, rz = idx / (T * T);
-    double s = 0.0;
-    for (int k = -M; k <= M; ++k)
-      s += op.omega[k < 0 ? -k : k] * reg1[(rz * W + (y + M - k)) * T + x];
-    reg2[idx] = s;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < T * T * T; idx += nt) {
-    const int x = idx % T, y = (idx / T) % T, z = idx / (T * T);
-    const int mx = m0[0] + x, my = m0[1] + y, mz = m0[2] + z;
-    if (mx >= op.n[0] || my >= op.n[1] || mz >= op.n[2]) continue;
-    double s = 0.0;
-    for (int k = -M; k <= M; ++k)
-      s += op.omega[k < 0 ? -k : k] * reg2[((z + M - k) * T + y) * T + x];
-    e[((long long)mz * op.n[1] + my) * op.n[0] + mx] = (TO)s;
-  }
+  out[((long long)z * pa.out[1] + y) * pa.out[0] + x] = (TO)s;
 }
 
 template <typename T>
@@ -442,18 +418,31 @@ void launch_conv(const ConvParams& cp, const TA* K, const int2* rowext, const TI
   }
 }
 
-size_t omega_lds_bytes(int M) {
-  const int T = M <= 6 ? 8 : 4, W = T + 2 * M;
-  return sizeof(double) * ((size_t)W * W * W + (size_t)W * W * T + (size_t)W * T * T);
+template <typename TO, int AX>
+static void omega_pass(const OmegaParams& op, const int in[3], const int out[3],
+                       const double* u, TO* e, hipStream_t s) {
+  OmegaPass pa;
+  for (int k = 0; k < 3; ++k) {
+    pa.in[k] = in[k];
+    pa.out[k] = out[k];
+  }
+  pa.per = op.per[AX];
+  pa.M = op.M;
+  for (int k = 0; k < 25; ++k) pa.omega[k] = op.omega[k];
+  dim3 grid((out[0] + 63) / 64, (out[1] + 3) / 4, out[2]);
+  hipLaunchKernelGGL((k_omega_pass<TO, AX>), grid, dim3(64, 4), 0, s, pa, u, e);
 }
 
+// u (extended grid next) -> t (n0, next1, next2) -> u (n0, n1, next2) -> e
 template <typename TO>
-void launch_omega(const OmegaParams& op, const double* u, TO* e, hipStream_t s) {
-  const int T = op.M <= 6 ? 8 : 4;
-  dim3 grid((op.n[0] + T - 1) / T, (op.n[1] + T - 1) / T, (op.n[2] + T - 1) / T);
-  const size_t lds = omega_lds_bytes(op.M);
-  if (T == 8) hipLaunchKernelGGL((k_omega<TO, 8>), grid, dim3(256), lds, s, op, u, e);
-  else hipLaunchKernelGGL((k_omega<TO, 4>), grid, dim3(256), lds, s, op, u, e);
+void launch_omega(const OmegaParams& op, double* u, double* t, TO* e, hipStream_t s) {
+  const int d0[3] = {op.next[0], op.next[1], op.next[2]};
+  const int d1[3] = {op.n[0], op.next[1], op.next[2]};
+  const int d2[3] = {op.n[0], op.n[1], op.next[2]};
+  const int d3[3] = {op.n[0], op.n[1], op.n[2]};
+  omega_pass<double, 0>(op, d0, d1, u, t, s);
+  omega_pass<double, 1>(op, d1, d2, t, u, s);
+  omega_pass<TO, 2>(op, d2, d3, u, e, s);
 }
 
 template <typename T>
@@ -477,7 +466,7 @@ void launch_fill(T* p, long long count, T value, hipStream_t s) {
                                    const T*, T*, hipStream_t);                                    \
   template void launch_prolong<T>(int, const GridDev<T>&, const GridDev<T>&, const double*,      \
                                   const T*, const double*, T*, const double*, hipStream_t);       \
-  template void launch_omega<T>(const OmegaParams&, const double*, T*, hipStream_t);              \
+  template void launch_omega<T>(const OmegaParams&, double*, double*, T*, hipStream_t);                    \
   template void launch_fill<T>(T*, long long, T, hipStream_t);                                    \
   template void launch_cast<T>(const double*, T*, long long, hipStream_t);
 MSM_INST_GRID(float)

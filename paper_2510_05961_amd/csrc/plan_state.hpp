@@ -97,6 +97,7 @@ struct msm_plan_s {
   double* S[msm::kMaxLevels] = {};
   int2* srowext[msm::kMaxLevels] = {};
   double* ug[msm::kMaxLevels] = {};
+  double* ut[msm::kMaxLevels] = {};  // omega' x-pass output (factored levels)
   void* Jd = nullptr;
   int* cell_of = nullptr;
   int* rank = nullptr;
