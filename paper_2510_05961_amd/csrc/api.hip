@@ -78,6 +78,68 @@ WsLayout ws_layout(const msm_plan P, int n) {
   return w;
 }
 
+// The stencil of a level as uploaded: radial kernels sampled on offsets
+// symmetric about 0 have mirrored z-planes, and the convolution then adds
+// the two input planes of a mirrored pair before one pass over the shared
+// coefficients.  A periodic table over all n residues (n even, offsets
+// -n/2..n/2-1) first gets its plane -n/2 split in two halves at -n/2 and
+// +n/2 (the same input plane mod n; halving is exact).  Pairs that agree to
+// 1e-12 of the largest coefficient are replaced by their mean, so they
+// match bit for bit; any larger difference leaves the stencil as it is.
+// MSM_FOLD=0 (read at plan creation) keeps every stencil unfolded.
+static ConvGeom mirror_stencil(const std::vector<double>& A, const int off[3], const int len[3],
+                               bool per_z, int nz, std::vector<double>& B) {
+  ConvGeom g;
+  for (int k = 0; k < 3; ++k) {
+    g.off[k] = off[k];
+    g.len[k] = len[k];
+  }
+  g.fold = 0;
+  B = A;
+  const char* env = std::getenv("MSM_FOLD");
+  if ((env && env[0] == '0') || len[2] < 2) return g;
+  const size_t plane = (size_t)len[0] * len[1];
+  std::vector<double> C;
+  int lz = len[2];
+  if (per_z && len[2] == nz && nz % 2 == 0 && off[2] == -(nz / 2)) {
+    lz = nz + 1;
+    C.resize(plane * lz);
+    for (size_t i = 0; i < plane; ++i) C[i] = C[plane * nz + i] = 0.5 * A[i];
+    std::copy(A.begin() + plane, A.begin() + plane * nz, C.begin() + plane);
+  } else {
+    C = A;
+  }
+  double amax = 0.0;
+  for (double v : C) amax = std::max(amax, std::fabs(v));
+  const double tol = 1e-12 * amax;
+  for (int j = 0; j < lz / 2; ++j)
+    for (size_t i = 0; i < plane; ++i)
+      if (!(std::fabs(C[plane * j + i] - C[plane * (lz - 1 - j) + i]) <= tol)) return g;
+  for (int j = 0; j < lz / 2; ++j)
+    for (size_t i = 0; i < plane; ++i) {
+      double& u = C[plane * j + i];
+      double& w = C[plane * (lz - 1 - j) + i];
+      u = w = 0.5 * (u + w);
+    }
+  B.swap(C);
+  g.len[2] = lz;
+  g.fold = 1;
+  return g;
+}
+
+// Convolution parameters of level l: its direct stencil K, or on a factored
+// level its samples S (output on the extended grid), as uploaded.
+template <typename T>
+static ConvParams level_conv(const msm_plan P, int l, bool samples) {
+  const HostPlan& hp = P->hp;
+  const LevelGeom& g = hp.lev[l - 1];
+  const int zero3[3] = {0, 0, 0};
+  const ConvGeom& c = samples ? P->sgeom[l - 1] : P->kgeom[l - 1];
+  return samples ? make_conv_params(g.n, g.next, g.shift, hp.periodic, c.off, c.len, sizeof(T),
+                                    c.fold)
+                 : make_conv_params(g.n, g.n, zero3, hp.periodic, c.off, c.len, sizeof(T), c.fold);
+}
+
 template <typename T>
 msm_status upload_plan(msm_plan P) {
   HostPlan& hp = P->hp;
@@ -86,8 +148,11 @@ msm_status upload_plan(msm_plan P) {
   // padded with zeros to conv_row_stride(len0), kConvRowPad zero rows before
   // and after every plane, plus the [first, last] non-zero x range of every
   // (unpadded) row
-  auto upload_stencil = [&](const std::vector<double>& A, const int len[3], double** dA,
-                            int2** dext) -> msm_status {
+  auto upload_stencil = [&](const std::vector<double>& A0, const int off[3], const int len0[3],
+                            int nz, double** dA, int2** dext, ConvGeom* cg) -> msm_status {
+    std::vector<double> A;
+    *cg = mirror_stencil(A0, off, len0, hp.periodic[2] != 0, nz, A);
+    const int* len = cg->len;
     const int lxp = conv_row_stride(len[0]);
     const int lyp = len[1] + 2 * kConvRowPad;
     const size_t rows = (size_t)len[1] * len[2];
@@ -118,7 +183,8 @@ msm_status upload_plan(msm_plan P) {
   };
   for (int l = 1; l <= hp.L; ++l) {
     LevelGeom& g = hp.lev[l - 1];
-    if ((st = upload_stencil(g.K, g.len, &P->K64[l - 1], &P->rowext64[l - 1]))) return st;
+    if ((st = upload_stencil(g.K, g.off, g.len, g.n[2], &P->K64[l - 1], &P->rowext64[l - 1],
+                             &P->kgeom[l - 1]))) return st;
     if ((st = hip_alloc(P, &P->qg[l - 1], (size_t)g.G * sizeof(T)))) return st;
     if ((st = hip_alloc(P, &P->eg[l - 1], (size_t)g.G * sizeof(T)))) return st;
     // FP64 accumulation buffer of the level's convolution
@@ -126,13 +192,12 @@ msm_status upload_plan(msm_plan P) {
     if ((st = hip_alloc(P, (void**)&P->ug[l - 1], (size_t)gbuf * sizeof(double)))) return st;
     if (g.factored && (st = hip_alloc(P, (void**)&P->ut[l - 1], (size_t)g.Gext * sizeof(double))))
       return st;
-    const int zero3[3] = {0, 0, 0};
-    ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
+    ConvParams cp = level_conv<T>(P, l, false);
     if (conv_lds_bytes(cp, sizeof(T)) > 64 * 1024 || cp.lds_w > kConvMaxLW) return MSM_ERR_GRID;
     if (g.factored) {
-      if ((st = upload_stencil(g.S, g.s_len, &P->S[l - 1], &P->srowext[l - 1]))) return st;
-      ConvParams cs = make_conv_params(g.n, g.next, g.shift, hp.periodic, g.s_off, g.s_len,
-                                       sizeof(T));
+      if ((st = upload_stencil(g.S, g.s_off, g.s_len, g.n[2], &P->S[l - 1], &P->srowext[l - 1],
+                               &P->sgeom[l - 1]))) return st;
+      ConvParams cs = level_conv<T>(P, l, true);
       if (conv_lds_bytes(cs, sizeof(T)) > 64 * 1024 || cs.lds_w > kConvMaxLW) return MSM_ERR_GRID;
     }
   }
@@ -216,13 +281,9 @@ PairParams<T> pair_params(const HostPlan& hp) {
 template <typename T>
 void grid_zero_jobs(msm_plan P, ZeroJobs& z) {
   const HostPlan& hp = P->hp;
-  const int zero3[3] = {0, 0, 0};
   for (int l = 1; l <= hp.L; ++l) {
     const LevelGeom& g = hp.lev[l - 1];
-    const ConvParams cp = g.factored ? make_conv_params(g.n, g.next, g.shift, hp.periodic,
-                                                        g.s_off, g.s_len, sizeof(T))
-                                     : make_conv_params(g.n, g.n, zero3, hp.periodic, g.off,
-                                                        g.len, sizeof(T));
+    const ConvParams cp = level_conv<T>(P, l, g.factored);
     if (cp.nsplit > 1 && z.n < kZeroJobs) {
       z.ptr[z.n] = P->ug[l - 1];
       z.words[z.n] = 2 * (g.factored ? g.Gext : g.G);
@@ -250,8 +311,7 @@ void conv_level(msm_plan P, int l, hipStream_t s) {
   const char* cname = l == hp.L ? "conv_top" : conv_names[l - 1];
   if (g.factored) {
     // K^l q = omega' * (S^l * q): FP64 sample convolution, then omega' per axis
-    ConvParams cs = make_conv_params(g.n, g.next, g.shift, hp.periodic, g.s_off, g.s_len,
-                                     sizeof(T));
+    ConvParams cs = level_conv<T>(P, l, true);
     int ev = pf.begin(cname, s);
     launch_conv<T, double>(cs, P->S[l - 1], P->srowext[l - 1], (const T*)P->qg[l - 1],
                            P->ug[l - 1], s);
@@ -270,8 +330,7 @@ void conv_level(msm_plan P, int l, hipStream_t s) {
   } else {
     // direct stencil, accumulated in FP64 (sums of thousands of terms with
     // cancellation)
-    const int zero3[3] = {0, 0, 0};
-    ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, g.off, g.len, sizeof(T));
+    ConvParams cp = level_conv<T>(P, l, false);
     int ev = pf.begin(cname, s);
     launch_conv<T, double>(cp, P->K64[l - 1], P->rowext64[l - 1], (const T*)P->qg[l - 1],
                            P->ug[l - 1], s);

@@ -38,6 +38,14 @@ struct ConvParams {
   int lxp;              // row stride of the stencil (len[0] + kConvCH - 1, zero padded)
   int lds_w, lds_h;     // staged input tile
   int shape;            // tile shape (kernels_grid.hip)
+  int fold;             // plane j and plane len2-1-j share coefficients
+  int nplanes;          // stencil planes the kernel walks: len2, or (len2+1)/2 folded
+};
+// A stencil as the convolution walks it: offsets and lengths per axis and
+// whether z-plane j and z-plane len2-1-j hold the same coefficients.
+struct ConvGeom {
+  int off[3], len[3];
+  int fold;
 };
 constexpr int kConvCH = 4;      // taps per register window of the convolution
 constexpr int kConvMaxLW = 512; // widest staged window row
@@ -124,7 +132,8 @@ void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, con
 
 
 ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3],
-                            const int per[3], const int off[3], const int len[3], int tsize);
+                            const int per[3], const int off[3], const int len[3], int tsize,
+                            int fold);
 // dynamic LDS bytes of the conv kernel for these parameters (tsize = grid type size)
 size_t conv_lds_bytes(const ConvParams& cp, int tsize);
 template <typename TI, typename TA>

@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(TXT * TYT)
   const int z = blockIdx.z % o2, split = blockIdx.z / o2;
   const int x0 = bx * (TXT * R), y0 = by * (TYT * Q);
   const int jz0 = split * cp.dz_per_split;
-  const int jz1 = min(cp.len[2], jz0 + cp.dz_per_split);
+  const int jz1 = min(cp.nplanes, jz0 + cp.dz_per_split);
   const int LW = cp.lds_w, LH = cp.lds_h;
   // input index of LDS element (row 0, column 0)
   const int xs = x0 + cp.shift[0] - (cp.off[0] + lx - 1) - (CH - 1);
@@ -203,22 +203,46 @@ __global__ void __launch_bounds__(TXT * TYT)
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int jz = jz0; jz < jz1; ++jz) {
-    int zi = z + cp.shift[2] - (cp.off[2] + jz);
-    if (cp.per[2]) zi = wrap_index(zi, n2);
-    else if (zi < 0 || zi >= n2) continue;  // uniform over the workgroup
+    // input plane of stencil plane jz and, folded, of its mirror plane
+    // len2-1-jz (same coefficients); a null pointer stands for an all-zero
+    // plane outside a free axis (uniform over the workgroup)
+    const TI* qa = nullptr;
+    const TI* qb = nullptr;
+    {
+      int zi = z + cp.shift[2] - (cp.off[2] + jz);
+      if (cp.per[2]) zi = wrap_index(zi, n2);
+      if (zi >= 0 && zi < n2) qa = q + (long long)zi * n1 * n0;
+      const int jm = cp.len[2] - 1 - jz;
+      if (cp.fold && jm != jz) {
+        int zm = z + cp.shift[2] - (cp.off[2] + jm);
+        if (cp.per[2]) zm = wrap_index(zm, n2);
+        if (zm >= 0 && zm < n2) qb = q + (long long)zm * n1 * n0;
+      }
+    }
+    if (!qa && !qb) continue;
+    if (!qa) {
+      qa = qb;
+      qb = nullptr;
+    }
     __syncthreads();
-    const TI* qz = q + (long long)zi * n1 * n0;
     // one wave per window row, lanes along x
     for (int ry = wave; ry < LH; ry += (TXT * TYT) >> 6) {
       int yi = ys + ry;
       bool ok = true;
       if (cp.per[1]) yi = wrap_index(yi, n1);
       else ok = (yi >= 0 && yi < n1);
-      const TI* src = qz + (long long)(ok ? yi : 0) * n0;
+      const long long ro = (long long)(ok ? yi : 0) * n0;
       TI* dst = lds + ry * LW;
-      for (int c = lane; c < LW; c += 64) {
-        const int xi = colsrc[c];
-        dst[c] = (ok && xi >= 0) ? src[xi] : TI(0);
+      if (qb) {
+        for (int c = lane; c < LW; c += 64) {
+          const int xi = colsrc[c];
+          dst[c] = (ok && xi >= 0) ? qa[ro + xi] + qb[ro + xi] : TI(0);
+        }
+      } else {
+        for (int c = lane; c < LW; c += 64) {
+          const int xi = colsrc[c];
+          dst[c] = (ok && xi >= 0) ? qa[ro + xi] : TI(0);
+        }
       }
     }
     __syncthreads();
@@ -347,8 +371,11 @@ static const ConvShape kShapes[3] = {{4, 4, 16, 16, 1.0}, {4, 4, 8, 8, 0.9}, {2,
 int conv_row_stride(int len0) { return len0 + kConvCH - 1; }
 
 ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3],
-                            const int per[3], const int off[3], const int len[3], int tsize) {
+                            const int per[3], const int off[3], const int len[3], int tsize,
+                            int fold) {
   ConvParams cp;
+  cp.fold = fold && len[2] > 1;
+  cp.nplanes = cp.fold ? (len[2] + 1) / 2 : len[2];
   for (int k = 0; k < 3; ++k) {
     cp.n[k] = n[k];
     cp.nout[k] = nout[k];
@@ -368,7 +395,7 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
     const size_t lds = (size_t)(TX + len[0] - 1 + kConvCH - 1) * (TY + len[1] - 1) * tsize;
     if (lds > 64 * 1024 || TX + len[0] - 1 + kConvCH - 1 > kConvMaxLW) continue;
     const double tiles = (double)((nout[0] + TX - 1) / TX) * ((nout[1] + TY - 1) / TY) * nout[2];
-    const double waves = tiles * len[2] * (sh.TXT * sh.TYT / 64);
+    const double waves = tiles * cp.nplanes * (sh.TXT * sh.TYT / 64);
     double cost = tiles * TX * TY / sh.eff;
     if (waves < 2048) cost *= 2048.0 / waves;
     if (pick < 0 || cost < best) {
@@ -394,9 +421,9 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
       (long long)((nout[0] + TX - 1) / TX) * ((nout[1] + TY - 1) / TY) * nout[2];
   long long want = (target + blocks * wpb - 1) / (blocks * wpb);
   if (want < 1) want = 1;
-  if (want > len[2]) want = len[2];
-  cp.dz_per_split = (int)((len[2] + want - 1) / want);
-  cp.nsplit = (len[2] + cp.dz_per_split - 1) / cp.dz_per_split;
+  if (want > cp.nplanes) want = cp.nplanes;
+  cp.dz_per_split = (int)((cp.nplanes + want - 1) / want);
+  cp.nsplit = (cp.nplanes + cp.dz_per_split - 1) / cp.dz_per_split;
   return cp;
 }
 

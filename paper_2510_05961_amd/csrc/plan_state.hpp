@@ -91,6 +91,8 @@ struct msm_plan_s {
   // rows (conv_row_stride) and per-row non-zero x ranges
   double* K64[msm::kMaxLevels] = {};
   int2* rowext64[msm::kMaxLevels] = {};
+  // geometry of the uploaded stencils (direct K, factored-level samples S)
+  msm::ConvGeom kgeom[msm::kMaxLevels] = {}, sgeom[msm::kMaxLevels] = {};
   void* qg[msm::kMaxLevels] = {};
   void* eg[msm::kMaxLevels] = {};
   // factored levels: FP64 k-samples, their row extents, FP64 partial grid

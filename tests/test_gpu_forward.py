@@ -190,6 +190,39 @@ def test_streams_match_single_stream(fp64):
     assert rel_rms(out["1"]["phi"], out["0"]["phi"]) <= tol
 
 
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("geom", ["periodic", "slab", "free"])
+def test_folded_matches_unfolded(fp64, geom):
+    """Mirrored stencil z-planes summed before one pass over their shared
+    coefficients, against the plain walk over every plane (MSM_FOLD=0).  The
+    periodic case has even top-level grids (their residue tables are split
+    at n/2), the slab a free z axis, the free case direct stencils only."""
+    import os
+    if geom == "periodic":
+        box, per, L = (24.0, 24.0, 24.0), (1, 1, 1), 4
+    elif geom == "slab":
+        box, per, L = (20.0, 20.0, 14.0), (1, 1, 0), 3
+    else:
+        box, per, L = (14.0, 14.0, 14.0), (0, 0, 0), 3
+    p, h, a = 4, 0.75, 4.0
+    pos, q = WL.gaussian_charges(2000, box, 0.5, seed=23)
+    pos, q = cast(pos, q, fp64)
+    prec = msm.MSM_FP64 if fp64 else msm.MSM_FP32
+    os.environ["MSM_FOLD"] = "0"
+    try:
+        plain = msm.Plan(box, mask_of(per), p, h, a, L, prec, 2000)
+    finally:
+        del os.environ["MSM_FOLD"]
+    folded = msm.Plan(box, mask_of(per), p, h, a, L, prec, 2000)
+    g0, g1 = gpu_forward(plain, pos, q), gpu_forward(folded, pos, q)
+    # FP64: the mirrored coefficients are averaged (changes of 1e-12 of the
+    # largest at most); FP32: one more rounding of the summed input planes
+    tol = 1e-10 if fp64 else 1e-6
+    assert abs(g0["E"] - g1["E"]) <= tol * abs(g0["E"])
+    assert rel_rms(g1["F"], g0["F"]) <= tol
+    assert rel_rms(g1["phi"], g0["phi"]) <= tol
+
+
 def test_profile_stage_filter():
     import torch
     box = (16.0, 16.0, 16.0)
