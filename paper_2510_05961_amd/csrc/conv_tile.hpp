@@ -17,14 +17,16 @@ namespace msm {
 // a + ly - 1 - v, so every LDS value, converted once to TA, feeds up to
 // Q R kConvCH multiply-adds.  Taps run in chunks of kConvCH over the union
 // of the Q rows' ranges, clipped to [jlo, jhi]; rows v outside [vlo, vhi]
-// are skipped (both clips are for inputs that are known to be zero).
+// are skipped (both clips are for inputs that are known to be zero), and
+// only every vstep-th row from vlo is walked (the rows of one plane can be
+// shared out among the waves of a workgroup).
 template <typename TI, typename TA, int R, int Q>
 __device__ inline void conv_plane(const TI* __restrict__ lds, int LW, int tx, int ty,
                                   const TA* __restrict__ Kz, const int2* __restrict__ ext_z,
                                   int lx, int ly, int lxp, int jlo, int jhi, int vlo, int vhi,
-                                  TA (&acc)[Q][R]) {
+                                  TA (&acc)[Q][R], int vstep = 1) {
   constexpr int CH = kConvCH;
-  for (int v = vlo; v <= vhi; ++v) {
+  for (int v = vlo; v <= vhi; v += vstep) {
     // output row a of the thread uses stencil row jy = a + ly - 1 - v
     const int alo = max(0, v - ly + 1), ahi = min(Q - 1, v);
     int first = lx, last = -1;

@@ -134,7 +134,8 @@ void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, con
 ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3],
                             const int per[3], const int off[3], const int len[3], int tsize,
                             int fold);
-// dynamic LDS bytes of the conv kernel for these parameters (tsize = grid type size)
+// LDS bytes of the conv kernel for these parameters, staged window plus its
+// static arrays (tsize = grid type size)
 size_t conv_lds_bytes(const ConvParams& cp, int tsize);
 template <typename TI, typename TA>
 void launch_conv(const ConvParams& cp, const TA* K, const int2* rowext, const TI* q, TA* e,

@@ -164,17 +164,24 @@ __global__ void __launch_bounds__(256)
 // For each stencil plane it stages the input window (periodic wrap or zero
 // padding) through LDS, one wave per window row, and adds the plane with
 // conv_plane (conv_tile.hpp): R x Q outputs per thread in registers, taps in
-// chunks over padded stencil rows, workgroup-uniform coefficients.  TI is the
+// chunks over padded stencil rows, workgroup-uniform coefficients.  With
+// WS > 1 the workgroup holds WS copies of the TXT x TYT thread tile; copy w
+// walks window rows w, w + WS, ... of every plane and the copies' sums meet
+// in LDS at the end (more waves per output tile on small grids).  TI is the
 // grid type (what LDS holds), TA the stencil / accumulation / output type.
 // ---------------------------------------------------------------------------
-template <typename TI, typename TA, int R, int Q, int TXT, int TYT>
-__global__ void __launch_bounds__(TXT * TYT)
+template <typename TI, typename TA, int R, int Q, int TXT, int TYT, int WS>
+__global__ void __launch_bounds__(TXT * TYT * WS)
     k_conv(ConvParams cp, const TA* __restrict__ K, const int2* __restrict__ rowext,
            const TI* __restrict__ q, TA* __restrict__ e) {
   constexpr int CH = kConvCH;
+  constexpr int NTILE = TXT * TYT, NT = NTILE * WS;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TI* lds = reinterpret_cast<TI*>(smem_raw);
-  const int tx = threadIdx.x % TXT, ty = threadIdx.x / TXT;
+  // ws (wave-uniform) selects the copy; a constant 0 without the split
+  const int tt = WS > 1 ? (int)threadIdx.x % NTILE : (int)threadIdx.x;
+  const int ws = WS > 1 ? (int)threadIdx.x / NTILE : 0;
+  const int tx = tt % TXT, ty = tt / TXT;
   const int n0 = cp.n[0], n1 = cp.n[1], n2 = cp.n[2];
   const int o0 = cp.nout[0], o1 = cp.nout[1], o2 = cp.nout[2];
   const int lx = cp.len[0], ly = cp.len[1], lxp = cp.lxp;
@@ -195,7 +202,7 @@ __global__ void __launch_bounds__(TXT * TYT)
   // input column of every window column (-1: outside a free axis), once per
   // workgroup; the staging below then needs no per-element division
   __shared__ int colsrc[kConvMaxLW];
-  for (int c = threadIdx.x; c < LW; c += TXT * TYT) {
+  for (int c = threadIdx.x; c < LW; c += NT) {
     int xi = xs + c;
     if (cp.per[0]) xi = wrap_index(xi, n0);
     else if (xi < 0 || xi >= n0) xi = -1;
@@ -226,7 +233,7 @@ __global__ void __launch_bounds__(TXT * TYT)
     }
     __syncthreads();
     // one wave per window row, lanes along x
-    for (int ry = wave; ry < LH; ry += (TXT * TYT) >> 6) {
+    for (int ry = wave; ry < LH; ry += NT >> 6) {
       int yi = ys + ry;
       bool ok = true;
       if (cp.per[1]) yi = wrap_index(yi, n1);
@@ -248,8 +255,26 @@ __global__ void __launch_bounds__(TXT * TYT)
     __syncthreads();
     // plane jz of the stencil: ly + 2 kConvRowPad rows of stride lxp
     const TA* Kz = K + ((long long)jz * (ly + 2 * kConvRowPad) + kConvRowPad) * lxp;
-    conv_plane<TI, TA, R, Q>(lds, LW, tx, ty, Kz, rowext + jz * ly, lx, ly, lxp, 0, lx - 1, 0,
-                             Q + ly - 2, acc);
+    conv_plane<TI, TA, R, Q>(lds, LW, tx, ty, Kz, rowext + jz * ly, lx, ly, lxp, 0, lx - 1, ws,
+                             Q + ly - 2, acc, WS);
+  }
+  if constexpr (WS > 1) {
+    // copies 1..WS-1 hand their sums to copy 0
+    __shared__ TA red[WS - 1][Q * R][NTILE];
+    if (ws > 0) {
+#pragma unroll
+      for (int a = 0; a < Q; ++a)
+#pragma unroll
+        for (int r = 0; r < R; ++r) red[ws - 1][a * R + r][tt] = acc[a][r];
+    }
+    __syncthreads();
+    if (ws > 0) return;
+#pragma unroll
+    for (int w = 0; w < WS - 1; ++w)
+#pragma unroll
+      for (int a = 0; a < Q; ++a)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[a][r] += red[w][a * R + r][tt];
   }
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
@@ -360,15 +385,24 @@ void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, con
   }
 }
 
-// Tile shapes {R, Q, TXT, TYT}: 0 = 64 x 64 outputs, 256 threads; 1 = 32 x
-// 32, 64 threads; 2 = 16 x 16, 64 threads (R = Q = 2).
+// Tile shapes {R, Q, TXT, TYT, WS}: 0 = 64 x 64 outputs, 256 threads; 1 =
+// 32 x 32 outputs, 4 x 64 threads splitting the stencil rows; 2 = 16 x 16
+// outputs (R = Q = 2), 4 x 64 threads splitting the stencil rows.
 struct ConvShape {
-  int R, Q, TXT, TYT;
+  int R, Q, TXT, TYT, WS;
   double eff;  // relative multiply-add throughput of the shape
 };
-static const ConvShape kShapes[3] = {{4, 4, 16, 16, 1.0}, {4, 4, 8, 8, 0.9}, {2, 2, 8, 8, 0.55}};
+static const ConvShape kShapes[3] = {
+    {4, 4, 16, 16, 1, 1.0}, {4, 4, 8, 8, 4, 0.9}, {2, 2, 8, 8, 4, 0.55}};
 
 int conv_row_stride(int len0) { return len0 + kConvCH - 1; }
+
+// static LDS of k_conv: the column table and the row-split reduction buffer
+// (FP64 accumulators)
+static size_t conv_static_lds(const ConvShape& sh) {
+  return sizeof(int) * kConvMaxLW +
+         (size_t)(sh.WS - 1) * sh.Q * sh.R * sh.TXT * sh.TYT * sizeof(double);
+}
 
 ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3],
                             const int per[3], const int off[3], const int len[3], int tsize,
@@ -392,10 +426,11 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
   for (int c = 0; c < 3; ++c) {
     const ConvShape& sh = kShapes[c];
     const int TX = sh.TXT * sh.R, TY = sh.TYT * sh.Q;
-    const size_t lds = (size_t)(TX + len[0] - 1 + kConvCH - 1) * (TY + len[1] - 1) * tsize;
+    const size_t lds = (size_t)(TX + len[0] - 1 + kConvCH - 1) * (TY + len[1] - 1) * tsize +
+                       conv_static_lds(sh);
     if (lds > 64 * 1024 || TX + len[0] - 1 + kConvCH - 1 > kConvMaxLW) continue;
     const double tiles = (double)((nout[0] + TX - 1) / TX) * ((nout[1] + TY - 1) / TY) * nout[2];
-    const double waves = tiles * cp.nplanes * (sh.TXT * sh.TYT / 64);
+    const double waves = tiles * cp.nplanes * (sh.TXT * sh.TYT * sh.WS / 64);
     double cost = tiles * TX * TY / sh.eff;
     if (waves < 2048) cost *= 2048.0 / waves;
     if (pick < 0 || cost < best) {
@@ -416,7 +451,7 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
     const long long v = e ? atoll(e) : 0;
     return v > 0 ? v : 8192LL;
   }();
-  const long long wpb = sh.TXT * sh.TYT / 64;
+  const long long wpb = sh.TXT * sh.TYT * sh.WS / 64;
   const long long blocks =
       (long long)((nout[0] + TX - 1) / TX) * ((nout[1] + TY - 1) / TY) * nout[2];
   long long want = (target + blocks * wpb - 1) / (blocks * wpb);
@@ -428,7 +463,7 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
 }
 
 size_t conv_lds_bytes(const ConvParams& cp, int tsize) {
-  return (size_t)cp.lds_w * cp.lds_h * tsize;
+  return (size_t)cp.lds_w * cp.lds_h * tsize + conv_static_lds(kShapes[cp.shape]);
 }
 
 template <typename TI, typename TA>
@@ -439,9 +474,9 @@ void launch_conv(const ConvParams& cp, const TA* K, const int2* rowext, const TI
   const int TX = sh.TXT * sh.R, TY = sh.TYT * sh.Q;
   dim3 grid((cp.nout[0] + TX - 1) / TX, (cp.nout[1] + TY - 1) / TY, cp.nout[2] * cp.nsplit);
   switch (cp.shape) {
-    case 0: hipLaunchKernelGGL((k_conv<TI, TA, 4, 4, 16, 16>), grid, dim3(256), lds, s, cp, K, rowext, q, e); break;
-    case 1: hipLaunchKernelGGL((k_conv<TI, TA, 4, 4, 8, 8>), grid, dim3(64), lds, s, cp, K, rowext, q, e); break;
-    default: hipLaunchKernelGGL((k_conv<TI, TA, 2, 2, 8, 8>), grid, dim3(64), lds, s, cp, K, rowext, q, e); break;
+    case 0: hipLaunchKernelGGL((k_conv<TI, TA, 4, 4, 16, 16, 1>), grid, dim3(256), lds, s, cp, K, rowext, q, e); break;
+    case 1: hipLaunchKernelGGL((k_conv<TI, TA, 4, 4, 8, 8, 4>), grid, dim3(256), lds, s, cp, K, rowext, q, e); break;
+    default: hipLaunchKernelGGL((k_conv<TI, TA, 2, 2, 8, 8, 4>), grid, dim3(256), lds, s, cp, K, rowext, q, e); break;
   }
 }
 
