@@ -69,7 +69,9 @@ enum { MSM_FP32 = 0, MSM_FP64 = 1 };
  *   levels          number of grid levels L >= 1 (kernels k_0..k_L).
  *   precision       MSM_FP32 or MSM_FP64 for particle and grid arithmetic;
  *                   stencils are built in FP64 and the energy is summed in FP64.
- *   max_n           largest particle count a call may pass.
+ *   max_n           largest particle count a call may pass (the particle
+ *                   buffers must stay below 4 GiB: max_n up to about 2^26
+ *                   in FP32 and 2^25 in FP64, else MSM_ERR_CAPACITY).
  *   quasi_degree_M  half-width M of the quasi-interpolation sequence omega'
  *                   (eq. kernel_stencil_by_conv_with_universal_coeff); -1 = p.
  * On success *out owns device memory for stencils, grids and cell lists.

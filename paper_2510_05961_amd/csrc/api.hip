@@ -218,11 +218,23 @@ msm_status upload_plan(msm_plan P) {
   if ((st = hip_alloc(P, &P->sorted, nmax * 4 * sizeof(T)))) return st;
   {
     const size_t ncl = (size_t)cluster_capacity((int)nmax, P->ncell);
+    // cluster slots plus the null j-group, addressed with 32-bit byte offsets
+    const size_t slots = ncl * 8 + kGroupSize;
+    if (slots * 4 * sizeof(T) >= (size_t(1) << 32)) return MSM_ERR_CAPACITY;
     if ((st = hip_alloc(P, (void**)&P->cl_start, (size_t)(P->ncell + 1) * sizeof(int)))) return st;
-    if ((st = hip_alloc(P, &P->cpos, ncl * 8 * 4 * sizeof(T)))) return st;
-    if ((st = hip_alloc(P, &P->cv, ncl * 8 * 4 * sizeof(T)))) return st;
-    if ((st = hip_alloc(P, &P->cbox, ncl * 2 * 4 * sizeof(T)))) return st;
+    if ((st = hip_alloc(P, &P->cpos, slots * 4 * sizeof(T)))) return st;
+    if ((st = hip_alloc(P, &P->cv, slots * 4 * sizeof(T)))) return st;
+    if ((st = hip_alloc(P, &P->cbox, ncl * 2 * 2 * 4 * sizeof(T)))) return st;
     if ((st = hip_alloc(P, (void**)&P->cinfo, ncl * sizeof(int4)))) return st;
+    // the null j-group: zero charges far outside every cutoff, zero vectors
+    P->null_h = (int)(2 * ncl);
+    std::vector<T> far(4 * kGroupSize, T(1e15)), zero(4 * kGroupSize, T(0));
+    for (int r = 0; r < kGroupSize; ++r) far[4 * r + 3] = T(0);
+    if (hipMemcpy((T*)P->cpos + ncl * 8 * 4, far.data(), far.size() * sizeof(T),
+                  hipMemcpyHostToDevice) ||
+        hipMemcpy((T*)P->cv + ncl * 8 * 4, zero.data(), zero.size() * sizeof(T),
+                  hipMemcpyHostToDevice))
+      return MSM_ERR_HIP;
   }
   if ((st = hip_alloc(P, &P->phi0, nmax * sizeof(double)))) return st;
   if ((st = hip_alloc(P, &P->F0, nmax * 3 * sizeof(T)))) return st;
@@ -268,9 +280,17 @@ PairParams<T> pair_params(const HostPlan& hp) {
   pp.inv_a3 = (T)(1.0 / (a * a * a));
   pp.inv_a5 = (T)(1.0 / (a * a * a * a * a));
   for (int k = 0; k < 8; ++k) {
-    pp.c[k] = k < p ? (T)hp.gcoef[k] : T(0);
-    pp.dc[k] = (k + 1 < p) ? (T)((k + 1) * hp.gcoef[k + 1]) : T(0);
-    pp.d2c[k] = (k + 2 < p) ? (T)((k + 2) * (k + 1) * hp.gcoef[k + 2]) : T(0);
+    const double c = k < p ? hp.gcoef[k] : 0.0;
+    const double dc = (k + 1 < p) ? (k + 1) * hp.gcoef[k + 1] : 0.0;
+    const double d2c = (k + 2 < p) ? (k + 2) * (k + 1) * hp.gcoef[k + 2] : 0.0;
+    pp.c[k] = (T)c;
+    pp.dc[k] = (T)dc;
+    pp.d2c[k] = (T)d2c;
+    // t^k = r^2k / a^2k, scaled in FP64 before the cast
+    const double a2k = std::pow(a, 2 * k);
+    pp.er[k] = (T)(c / (a2k * a));
+    pp.fr[k] = (T)(2.0 * dc / (a2k * a * a * a));
+    pp.gr[k] = (T)(4.0 * d2c / (a2k * a * a * a * a * a));
   }
   return pp;
 }
@@ -469,7 +489,8 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   const PairParams<T> pp = pair_params<T>(hp);
   ev = pf.begin("pair", sp);
   launch_pair_cl<T>(p, n, P->ncell, P->cl_start, (const vec4_t<T>*)P->cpos,
-                    (const vec4_t<T>*)P->cbox, P->cinfo, pp, (double*)P->phi0, (T*)P->F0, sp);
+                    (const vec4_t<T>*)P->cbox, P->cinfo, pp, P->null_h, (double*)P->phi0,
+                    (T*)P->F0, sp);
   pf.end(ev, sp);
   if (dag) (void)hipEventRecord(P->ev[1], sp);
 
@@ -547,7 +568,7 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
   ev = pf.begin("bwd_pair", sp);
   launch_pair_vjp_cl<T>(p, n, P->ncell, P->cl_start, P->cinfo, perm, gF,
                         (const vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cv, (const vec4_t<T>*)P->cbox,
-                        pair_params<T>(hp), gq_sr, gr_sr, sp);
+                        pair_params<T>(hp), P->null_h, gq_sr, gr_sr, sp);
   pf.end(ev, sp);
   if (dag) (void)hipEventRecord(P->ev[1], sp);
   const GridDev<T> g1 = grid_dev<T>(hp, 1);

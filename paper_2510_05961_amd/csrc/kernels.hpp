@@ -24,6 +24,9 @@ struct PairParams {
   T c[8];    // softening polynomial in t = (r/a)^2
   T dc[8];   // its t-derivative: dc[k] = (k+1) c[k+1]
   T d2c[8];  // second t-derivative: d2c[k] = (k+2)(k+1) c[k+2]
+  // the same in r^2: gamma(r/a)/a = sum er[k] r^2k, 2 gamma'(t)/a^3 =
+  // sum fr[k] r^2k, 4 gamma''(t)/a^5 = sum gr[k] r^2k
+  T er[8], fr[8], gr[8];
 };
 
 // One stencil convolution e_o = sum_d K_d q_{o+shift-d} (a5, a6).
@@ -93,9 +96,14 @@ struct ZeroJobs {
 };
 void launch_zero_multi(const ZeroJobs& jobs, hipStream_t s);
 // Cluster layout of the cell-sorted particles (sort != 0: also reorders each
-// cell along a Morton curve, in place) and the short-range pair sum over 8 x 8
-// cluster pairs.  Buffers hold cluster_capacity(n, ncell) clusters.
+// cell along a Morton curve, in place) and the short-range pair sum over 8 x 4
+// blocks (an i-cluster against a j-group, half a cluster).  Buffers hold
+// cluster_capacity(n, ncell) clusters: 8 slots each in cpos and cv, two
+// boxes (lo, hi per j-group) in cbox; cpos and cv hold one more j-group, the
+// null group (far-away zero charges, zero vectors) at index null_h, set once
+// by the caller.
 int cluster_capacity(int n, int ncell);
+constexpr int kGroupSize = 4;  // particles per j-group
 // scan != 0: compute cl_start from start here (else it is already there)
 template <typename T>
 void launch_cluster_layout(int sort, int scan, int ncell, const int* start, int* cl_start,
@@ -105,7 +113,7 @@ void launch_cluster_layout(int sort, int scan, int ncell, const int* start, int*
 template <typename T>
 void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
                     const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
-                    double* phi0, T* F0, hipStream_t s);
+                    int null_h, double* phi0, T* F0, hipStream_t s);
 // cell list geometry in FP64 (bricks of the staged anterpolation)
 struct CellGrid {
   int nc[3];
@@ -156,8 +164,8 @@ void launch_gather_v(int n, const int* perm, const T* gF, vec4_t<T>* v, hipStrea
 template <typename T>
 void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4* cinfo,
                         const int* perm, const T* gF, const vec4_t<T>* cpos, vec4_t<T>* cv,
-                        const vec4_t<T>* cbox, const PairParams<T>& pp, T* gq, T* gr,
-                        hipStream_t s);
+                        const vec4_t<T>* cbox, const PairParams<T>& pp, int null_h, T* gq,
+                        T* gr, hipStream_t s);
 template <typename T>
 void launch_anterp_dipole(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v,
                           const GridDev<T>& g, T* grid, hipStream_t s);

@@ -1,25 +1,29 @@
 // kernels_cluster.hip -- the short-range part U^0 (eq. U_zero) as a sum over
-// 8 x 8 cluster pairs, and its vector-Jacobian product.
+// 8 x 4 cluster blocks, and its vector-Jacobian product.
 //
 // Layout.  Binning sorts particles by cell (cells of edge >= a).  Inside
 // every cell the particles are then ordered along a Morton curve of a 16^3
 // sub-grid (ties broken by the caller's index, so the order is
 // deterministic) and cut into clusters of 8 consecutive particles; the last
-// cluster of a cell is padded with far-away zero charges.  Each cluster keeps
-// its bounding box.
+// cluster of a cell is padded with far-away zero charges.  Each half of a
+// cluster (4 particles, a "j-group") keeps its bounding box.
 //
-// Pair sum.  One wave per i-cluster.  Lane (il, jl) = (lane / 8, lane % 8)
-// holds i-member il and, for every j-cluster that survives the box test,
-// evaluates the pair (il, jl) of the 8 x 8 block.  Periodic images are
-// handled by a uniform shift per neighbour cell (27 offsets, each (cell,
-// shift) combination distinct), which is exact whenever the cell edge is >= a
-// and every periodic edge is >= 2a: then at most one image of a particle lies
-// inside the cutoff and it lies in one of the 27 shifted neighbour cells.
+// Pair sum.  One wave per i-cluster.  Every j-group of the 27 neighbour
+// cells whose box lies within the cutoff of the i-cluster's box goes into a
+// per-wave list; the wave then takes two list entries per step, lane
+// (slot, il, jl) = (lane / 32, lane / 4 % 8, lane % 4) evaluating i-member il
+// against member jl of entry slot.  Periodic images are handled by a uniform
+// shift per neighbour cell (27 offsets, each (cell, shift) combination
+// distinct), which is exact whenever the cell edge is >= a and every
+// periodic edge is >= 2a: then at most one image of a particle lies inside
+// the cutoff and it lies in one of the 27 shifted neighbour cells.
 #include "kernels.hpp"
 
 namespace msm {
 
 constexpr int kClusterThreads = 256;  // 4 waves = 4 i-clusters per workgroup
+constexpr int kGroup = kGroupSize;    // particles per j-group (half a cluster)
+constexpr int kSlots = 64 / (8 * kGroup);  // j-groups per wave step
 constexpr int kPrepThreads = 256;
 constexpr int kPrepSortMax = 4096;    // cells larger than this keep their order
 
@@ -134,24 +138,32 @@ __global__ void __launch_bounds__(kPrepThreads)
     }
     cpos[(size_t)cbeg * 8 + s] = v;
   }
-  for (int c = t; c < ncl; c += kPrepThreads) {
-    const int m = min(8, cnt - 8 * c);
+  // boxes of the j-groups (an empty group: a point far outside every cutoff)
+  for (int h = t; h < 2 * ncl; h += kPrepThreads) {
+    const int m = min(kGroup, cnt - kGroup * h);
     vec4_t<T> lo, hi;
-    lo = sorted[beg + 8 * c];
-    hi = lo;
-    for (int r = 1; r < m; ++r) {
-      const vec4_t<T> v = sorted[beg + 8 * c + r];
-      lo.x = min(lo.x, v.x);
-      lo.y = min(lo.y, v.y);
-      lo.z = min(lo.z, v.z);
-      hi.x = max(hi.x, v.x);
-      hi.y = max(hi.y, v.y);
-      hi.z = max(hi.z, v.z);
+    if (m <= 0) {
+      lo.x = lo.y = lo.z = T(1e15);
+      lo.w = T(0);
+      hi = lo;
+    } else {
+      lo = sorted[beg + kGroup * h];
+      hi = lo;
+      for (int r = 1; r < m; ++r) {
+        const vec4_t<T> v = sorted[beg + kGroup * h + r];
+        lo.x = min(lo.x, v.x);
+        lo.y = min(lo.y, v.y);
+        lo.z = min(lo.z, v.z);
+        hi.x = max(hi.x, v.x);
+        hi.y = max(hi.y, v.y);
+        hi.z = max(hi.z, v.z);
+      }
     }
-    cbox[2 * (size_t)(cbeg + c)] = lo;
-    cbox[2 * (size_t)(cbeg + c) + 1] = hi;
-    cinfo[cbeg + c] = make_int4(beg + 8 * c, m, cell, 0);
+    cbox[2 * (2 * (size_t)cbeg + h)] = lo;
+    cbox[2 * (2 * (size_t)cbeg + h) + 1] = hi;
   }
+  for (int c = t; c < ncl; c += kPrepThreads)
+    cinfo[cbeg + c] = make_int4(beg + 8 * c, min(8, cnt - 8 * c), cell, 0);
 }
 
 // Neighbour cell along one axis at offset o in {-1, 0, 1}: the cell index
@@ -196,25 +208,42 @@ __device__ inline double in_vgpr(double x) {
   return r;
 }
 
-// Sum over the 8 lanes of one i-member (lanes 8 il .. 8 il + 7).
+// Sum over the 8 lanes of one i-member (jl and slot: lane bits 0, 1 and 5).
 template <typename V>
-__device__ inline V sum8(V v) {
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 2);
+__device__ inline V sum_i(V v) {
   v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 32);
   return v;
 }
 
-// Visits every j-cluster whose box (shifted image) lies within the cutoff of
-// the i-cluster's box and calls body(jc, sx, sy, sz, self_block) uniformly
-// over the wave, and flush() after each neighbour cell.  The i-box and
-// everything below are wave-uniform.
-template <typename T, typename Body, typename Flush>
-__device__ inline void for_each_cluster_pair(const PairParams<T>& pp, const int* cl_start,
-                                             const vec4_t<T>* cbox, int ic, int cell,
-                                             const vec4_t<T>& blo, const vec4_t<T>& bhi,
-                                             Body&& body, Flush&& flush) {
+// Member r of j-group h (a 32-bit byte offset from the array base, so the
+// load takes the base from scalar registers).
+template <typename T>
+__device__ inline vec4_t<T> group_member(const vec4_t<T>* base, int h, int r) {
+  const unsigned off = ((unsigned)h * kGroup + (unsigned)r) * (unsigned)sizeof(vec4_t<T>);
+  return *reinterpret_cast<const vec4_t<T>*>(reinterpret_cast<const char*>(base) + off);
+}
+
+// Visits every j-group whose box (shifted image) lies within the cutoff of
+// the i-cluster's box: per neighbour cell the surviving groups are listed in
+// the wave's LDS list (padded to a multiple of kSlots with null_h, a group
+// of far-away zero charges), and body(h, d, sx, sy, sz, self_h) runs once per
+// step with h = this lane's entry and d = load(h), the lane's j data (loaded
+// one step ahead, so the memory latency overlaps the previous step's
+// arithmetic); self_h is the group index at which lane (il, jl) would meet
+// its own particle (-1 if none in this cell).  flush() runs after each
+// neighbour cell.  The i-box is wave-uniform.
+template <typename T, typename Load, typename Body, typename Flush>
+__device__ inline void for_each_group_block(const PairParams<T>& pp, const int* cl_start,
+                                            const vec4_t<T>* cbox, int ic, int cell,
+                                            const vec4_t<T>& blo, const vec4_t<T>& bhi,
+                                            int* list, int null_h, Load&& load, Body&& body,
+                                            Flush&& flush) {
   const int lane = threadIdx.x & 63;
+  const int slot = lane >> 5, il = (lane >> 2) & 7, jl = lane & 3;
+  // the group holding i-member il, where jl is il itself
+  const int own_h = (jl == (il & 3)) ? 2 * ic + (il >> 2) : -1;
   const int cx = cell % pp.nc[0];
   const int cy = (cell / pp.nc[0]) % pp.nc[1];
   const int cz = cell / (pp.nc[0] * pp.nc[1]);
@@ -246,23 +275,40 @@ __device__ inline void for_each_cluster_pair(const PairParams<T>& pp, const int*
           if (!(g2 < pp.a2)) continue;
         }
         const int ncell = (nz * pp.nc[1] + ny) * pp.nc[0] + nx;
-        const int jb0 = cl_start[ncell], jb1 = cl_start[ncell + 1];
-        const bool zero_shift = (shx | shy | shz) == 0;
+        const int jb0 = 2 * cl_start[ncell], jb1 = 2 * cl_start[ncell + 1];
+        const int self_h = ((shx | shy | shz) == 0 && ncell == cell) ? own_h : -1;
         for (int jb = jb0; jb < jb1; jb += 64) {
-          const int jc = jb + lane;
+          const int h = jb + lane;
           bool hit = false;
-          if (jc < jb1) {
-            const vec4_t<T> lo = cbox[2 * (size_t)jc], hi = cbox[2 * (size_t)jc + 1];
+          if (h < jb1) {
+            const vec4_t<T> lo = cbox[2 * (size_t)h], hi = cbox[2 * (size_t)h + 1];
             hit = box_gap2<T>(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, ilx, ily, ilz, ihx, ihy, ihz) <
                   pp.a2;
           }
-          unsigned long long mask = __ballot(hit);
-          while (mask) {
-            const int b = __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
-            const int j = jb + b;
-            body(j, sx, sy, sz, zero_shift && j == ic);
+          const unsigned long long mask = __ballot(hit);
+          if (mask == 0) continue;
+          const int cnt = __popcll(mask);
+          const int pos = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+          if (hit) list[pos] = h;
+          if (lane >= cnt && lane < cnt + (kSlots - cnt % kSlots) % kSlots) list[lane] = null_h;
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          // two steps per trip, each loading the next step's data before its
+          // own arithmetic (the null group stands in past the end)
+          int ha = list[slot];
+          auto da = load(ha);
+          for (int it = 0; it < cnt; it += 2 * kSlots) {
+            const int hb = it + kSlots < cnt ? list[it + kSlots + slot] : null_h;
+            const auto db = load(hb);
+            body(ha, da, sx, sy, sz, self_h);
+            if (it + kSlots >= cnt) break;
+            ha = it + 2 * kSlots < cnt ? list[it + 2 * kSlots + slot] : null_h;
+            da = load(ha);
+            body(hb, db, sx, sy, sz, self_h);
           }
+          // every lane's reads are issued before the next chunk's writes
+          __builtin_amdgcn_wave_barrier();
         }
         flush();
       }
@@ -270,45 +316,72 @@ __device__ inline void for_each_cluster_pair(const PairParams<T>& pp, const int*
   }
 }
 
+// Position and force cotangent of one j particle (pair VJP).
+template <typename T>
+struct JData {
+  vec4_t<T> p, v;
+};
+
+// Box of i-cluster ic: the union of its j-groups' boxes (an empty second
+// group is left out).
+template <typename T>
+__device__ inline void cluster_box(const vec4_t<T>* cbox, int ic, int m, vec4_t<T>& lo,
+                                   vec4_t<T>& hi) {
+  lo = cbox[4 * (size_t)ic];
+  hi = cbox[4 * (size_t)ic + 1];
+  if (m > kGroup) {
+    const vec4_t<T> l2 = cbox[4 * (size_t)ic + 2], h2 = cbox[4 * (size_t)ic + 3];
+    lo.x = min(lo.x, l2.x);
+    lo.y = min(lo.y, l2.y);
+    lo.z = min(lo.z, l2.z);
+    hi.x = max(hi.x, h2.x);
+    hi.y = max(hi.y, h2.y);
+    hi.z = max(hi.z, h2.z);
+  }
+}
+
+// U^0 per particle: phi0_i = sum_j q_j (1/r - gamma(r/a)/a) over j != i with
+// r < a, and F0_i = q_i sum_j q_j f(r) d_ij with f = -(1/r) d/dr of that
+// kernel.  Both polynomials are taken in r^2 directly (PairParams er, fr).
 template <typename T, int P>
 __global__ void __launch_bounds__(kClusterThreads)
     k_pair_cl(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
               const vec4_t<T>* __restrict__ cbox, const int4* __restrict__ cinfo,
-              PairParams<T> pp, double* __restrict__ phi0, T* __restrict__ F0) {
+              PairParams<T> pp, int null_h, double* __restrict__ phi0, T* __restrict__ F0) {
+  __shared__ int lists[kClusterThreads / 64][64];
   const int lane = threadIdx.x & 63;
   const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * (kClusterThreads / 64) +
                                                 (int)(threadIdx.x >> 6));
   if (ic >= cl_start[pp.ncell]) return;
-  const int il = lane >> 3, jl = lane & 7;
+  const int il = (lane >> 2) & 7, jl = lane & 3;
   const int4 inf = cinfo[ic];
   const vec4_t<T> pi = cpos[(size_t)ic * 8 + il];
-  const vec4_t<T> blo = cbox[2 * (size_t)ic], bhi = cbox[2 * (size_t)ic + 1];
-  const T two_inv_a3 = T(2) * pp.inv_a3;
-  const T c_top = in_vgpr(pp.c[P - 1]), dc_top = in_vgpr(pp.dc[P - 2]);
+  vec4_t<T> blo, bhi;
+  cluster_box<T>(cbox, ic, inf.y, blo, bhi);
+  const T e_top = in_vgpr(pp.er[P - 1]), f_top = in_vgpr(pp.fr[P - 2]);
   const T a2v = in_vgpr(pp.a2);
   double ph = 0.0;  // the potential is carried in FP64 up to the energy sum
   T phc = T(0);     // ... after a partial sum over one neighbour cell
   T fx = T(0), fy = T(0), fz = T(0);
-  for_each_cluster_pair<T>(
-      pp, cl_start, cbox, ic, inf.z, blo, bhi,
-      [&](int jc, T sx, T sy, T sz, bool self_block) {
-        const vec4_t<T> pj = cpos[(size_t)jc * 8 + jl];
+  for_each_group_block<T>(
+      pp, cl_start, cbox, ic, inf.z, blo, bhi, lists[threadIdx.x >> 6], null_h,
+      [&](int h) { return group_member<T>(cpos, h, jl); },
+      [&](int h, const vec4_t<T>& pj, T sx, T sy, T sz, int self_h) {
         const T dx = (pi.x - sx) - pj.x, dy = (pi.y - sy) - pj.y, dz = (pi.z - sz) - pj.z;
         const T r2 = dx * dx + dy * dy + dz * dz;
-        const bool ok = r2 < pp.a2 && !(self_block && il == jl);
+        const bool ok = r2 < pp.a2 && h != self_h;
         // pairs outside the cutoff (and the self pair) get r = a and a zero
         // charge, so every intermediate stays finite
         const T r2c = ok ? r2 : a2v;
         const T qj = ok ? pj.w : T(0);
         const T rinv = rsqrt_t(r2c);
-        const T t = r2c * pp.inv_a2;
-        T Pt = c_top, dP = dc_top;
+        T pe = e_top, pf = f_top;
 #pragma unroll
-        for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
+        for (int k = P - 2; k >= 0; --k) pe = pe * r2c + pp.er[k];
 #pragma unroll
-        for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
-        const T e = rinv - Pt * pp.inv_a;
-        const T f = rinv * rinv * rinv + dP * two_inv_a3;
+        for (int k = P - 3; k >= 0; --k) pf = pf * r2c + pp.fr[k];
+        const T e = rinv - pe;
+        const T f = rinv * rinv * rinv + pf;
         const T fs = qj * f;
         phc += qj * e;
         fx += fs * dx;
@@ -319,11 +392,11 @@ __global__ void __launch_bounds__(kClusterThreads)
         ph += (double)phc;
         phc = T(0);
       });
-  ph = sum8(ph);
-  fx = sum8(fx);
-  fy = sum8(fy);
-  fz = sum8(fz);
-  if (jl == 0 && il < inf.y) {
+  ph = sum_i(ph);
+  fx = sum_i(fx);
+  fy = sum_i(fy);
+  fz = sum_i(fz);
+  if ((lane & ~0x1C) == 0 && il < inf.y) {  // slot 0, jl 0
     const int i = inf.x + il;
     phi0[i] = ph;
     F0[3 * (size_t)i] = pi.w * fx;
@@ -360,40 +433,42 @@ template <typename T, int P>
 __global__ void __launch_bounds__(kClusterThreads)
     k_pair_vjp_cl(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
                   const vec4_t<T>* __restrict__ cv, const vec4_t<T>* __restrict__ cbox,
-                  const int4* __restrict__ cinfo, PairParams<T> pp, T* __restrict__ gq,
-                  T* __restrict__ gr) {
+                  const int4* __restrict__ cinfo, PairParams<T> pp, int null_h,
+                  T* __restrict__ gq, T* __restrict__ gr) {
+  __shared__ int lists[kClusterThreads / 64][64];
   const int lane = threadIdx.x & 63;
   const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * (kClusterThreads / 64) +
                                                 (int)(threadIdx.x >> 6));
   if (ic >= cl_start[pp.ncell]) return;
-  const int il = lane >> 3, jl = lane & 7;
+  const int il = (lane >> 2) & 7, jl = lane & 3;
   const int4 inf = cinfo[ic];
   const vec4_t<T> pi = cpos[(size_t)ic * 8 + il];
   const vec4_t<T> vi = cv[(size_t)ic * 8 + il];
-  const vec4_t<T> blo = cbox[2 * (size_t)ic], bhi = cbox[2 * (size_t)ic + 1];
-  const T dc_top = in_vgpr(pp.dc[P - 2]), d2c_top = in_vgpr(pp.d2c[P - 3]);
+  vec4_t<T> blo, bhi;
+  cluster_box<T>(cbox, ic, inf.y, blo, bhi);
+  const T f_top = in_vgpr(pp.fr[P - 2]), g_top = in_vgpr(pp.gr[P - 3]);
   const T a2v = in_vgpr(pp.a2);
   T sq = T(0), rx = T(0), ry = T(0), rz = T(0);
-  for_each_cluster_pair<T>(
-      pp, cl_start, cbox, ic, inf.z, blo, bhi,
-      [&](int jc, T sx, T sy, T sz, bool self_block) {
-        const vec4_t<T> pj = cpos[(size_t)jc * 8 + jl];
-        const vec4_t<T> vj = cv[(size_t)jc * 8 + jl];
+  for_each_group_block<T>(
+      pp, cl_start, cbox, ic, inf.z, blo, bhi, lists[threadIdx.x >> 6], null_h,
+      [&](int h) { return JData<T>{group_member<T>(cpos, h, jl), group_member<T>(cv, h, jl)}; },
+      [&](int h, const JData<T>& jd, T sx, T sy, T sz, int self_h) {
+        const vec4_t<T>& pj = jd.p;
+        const vec4_t<T>& vj = jd.v;
         const T dx = (pi.x - sx) - pj.x, dy = (pi.y - sy) - pj.y, dz = (pi.z - sz) - pj.z;
         const T r2 = dx * dx + dy * dy + dz * dz;
-        const bool ok = r2 < pp.a2 && !(self_block && il == jl);
+        const bool ok = r2 < pp.a2 && h != self_h;
         const T r2c = ok ? r2 : a2v;
         const T qj = ok ? pj.w : T(0);
         const T rinv = rsqrt_t(r2c);
         const T rinv2 = rinv * rinv;
-        const T t = r2c * pp.inv_a2;
-        T dP = dc_top, d2P = d2c_top;
+        T pf = f_top, pg = g_top;
 #pragma unroll
-        for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
+        for (int k = P - 3; k >= 0; --k) pf = pf * r2c + pp.fr[k];
 #pragma unroll
-        for (int k = P - 4; k >= 0; --k) d2P = d2P * t + pp.d2c[k];
-        const T f = rinv * rinv2 + T(2) * dP * pp.inv_a3;
-        const T fpr = T(-3) * rinv2 * rinv2 * rinv + T(4) * d2P * pp.inv_a5;
+        for (int k = P - 4; k >= 0; --k) pg = pg * r2c + pp.gr[k];
+        const T f = rinv * rinv2 + pf;
+        const T fpr = T(-3) * rinv2 * rinv2 * rinv + pg;
         const T wx = vi.x - vj.x, wy = vi.y - vj.y, wz = vi.z - vj.z;
         const T wd = wx * dx + wy * dy + wz * dz;
         const T qf = qj * f;
@@ -404,11 +479,11 @@ __global__ void __launch_bounds__(kClusterThreads)
         rz += qf * wz + c2 * dz;
       },
       []() {});
-  sq = sum8(sq);
-  rx = sum8(rx);
-  ry = sum8(ry);
-  rz = sum8(rz);
-  if (jl == 0 && il < inf.y) {
+  sq = sum_i(sq);
+  rx = sum_i(rx);
+  ry = sum_i(ry);
+  rz = sum_i(rz);
+  if ((lane & ~0x1C) == 0 && il < inf.y) {  // slot 0, jl 0
     const int i = inf.x + il;
     gq[i] = sq;
     gr[3 * (size_t)i] = pi.w * rx;
@@ -433,21 +508,21 @@ int cluster_capacity(int n, int ncell) { return n / 8 + ncell + 1; }
 template <typename T>
 void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
                     const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
-                    double* phi0, T* F0, hipStream_t s) {
+                    int nh, double* phi0, T* F0, hipStream_t s) {
   if (n <= 0) return;
   const int ncl = cluster_capacity(n, ncell);
   const dim3 grid((ncl + 3) / 4), block(kClusterThreads);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_pair_cl<T, 4>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
-    case 6: hipLaunchKernelGGL((k_pair_cl<T, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
-    case 8: hipLaunchKernelGGL((k_pair_cl<T, 8>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+    case 4: hipLaunchKernelGGL((k_pair_cl<T, 4>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, nh, phi0, F0); break;
+    case 6: hipLaunchKernelGGL((k_pair_cl<T, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, nh, phi0, F0); break;
+    case 8: hipLaunchKernelGGL((k_pair_cl<T, 8>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, nh, phi0, F0); break;
   }
 }
 
 template <typename T>
 void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4* cinfo,
                         const int* perm, const T* gF, const vec4_t<T>* cpos, vec4_t<T>* cv,
-                        const vec4_t<T>* cbox, const PairParams<T>& pp, T* gq, T* gr,
+                        const vec4_t<T>* cbox, const PairParams<T>& pp, int nh, T* gq, T* gr,
                         hipStream_t s) {
   if (n <= 0) return;
   const int ncl = cluster_capacity(n, ncell);
@@ -455,9 +530,9 @@ void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4
                      cl_start, ncell, cinfo, perm, gF, cv);
   const dim3 grid((ncl + 3) / 4), block(kClusterThreads);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_pair_vjp_cl<T, 4>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, gq, gr); break;
-    case 6: hipLaunchKernelGGL((k_pair_vjp_cl<T, 6>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, gq, gr); break;
-    case 8: hipLaunchKernelGGL((k_pair_vjp_cl<T, 8>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, gq, gr); break;
+    case 4: hipLaunchKernelGGL((k_pair_vjp_cl<T, 4>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
+    case 6: hipLaunchKernelGGL((k_pair_vjp_cl<T, 6>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
+    case 8: hipLaunchKernelGGL((k_pair_vjp_cl<T, 8>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
   }
 }
 
@@ -466,11 +541,11 @@ void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4
                                          const vec4_t<T>*, vec4_t<T>*, int*, vec4_t<T>*,       \
                                          vec4_t<T>*, int4*, hipStream_t);                      \
   template void launch_pair_cl<T>(int, int, int, const int*, const vec4_t<T>*,                 \
-                                  const vec4_t<T>*, const int4*, const PairParams<T>&,         \
+                                  const vec4_t<T>*, const int4*, const PairParams<T>&, int,    \
                                   double*, T*, hipStream_t);                                   \
   template void launch_pair_vjp_cl<T>(int, int, int, const int*, const int4*, const int*,      \
                                       const T*, const vec4_t<T>*, vec4_t<T>*,                  \
-                                      const vec4_t<T>*, const PairParams<T>&, T*, T*,          \
+                                      const vec4_t<T>*, const PairParams<T>&, int, T*, T*,     \
                                       hipStream_t);
 MSM_INST_CLUSTER(float)
 MSM_INST_CLUSTER(double)

@@ -87,6 +87,7 @@ struct msm_plan_s {
   bool device = false;
   bool batch = false;
   int ncell = 0;
+  int null_h = 0;  // index of the null j-group in cpos / cv
   // device buffers (T = plan precision); stencils in FP64 with zero-padded
   // rows (conv_row_stride) and per-row non-zero x ranges
   double* K64[msm::kMaxLevels] = {};
