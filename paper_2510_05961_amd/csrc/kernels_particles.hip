@@ -1,6 +1,9 @@
 // kernels_particles.hip -- particle-side kernels of the MSM forward pass:
 // cell binning (count, scan, scatter), anterpolation onto the level-1 grid, and interpolation fused with the
 // final combination of short- and long-range parts and the FP64 energy sum.
+#include <algorithm>
+#include <cmath>
+
 #include "kernels.hpp"
 
 namespace msm {
@@ -151,19 +154,24 @@ __global__ void k_bin_scatter(int n, const int* __restrict__ cell_of, const int*
 // a3: anterpolation (eq. grid_charge): q~^1_m += q_i phi_m(r_i) over the p^3
 // grid points of each particle, B-spline weights in FP64.
 // ---------------------------------------------------------------------------
-// Staged per cell: one workgroup accumulates the charges of one
-// cell into an LDS brick covering every grid point they can touch, then adds
-// the brick to the grid with one atomic per non-zero point (coalesced along x,
-// and conflicting only where the bricks of neighbouring cells overlap).  A
-// brick larger than kBrickMax points (cells much wider than h) falls back to
-// per-particle global atomics.
-constexpr int kBrickMax = 8192;
+// Staged per cell: one workgroup accumulates the charges of one cell into
+// an LDS brick covering every grid point they can touch, then adds the brick
+// to the grid with one atomic per non-zero point (coalesced along x, and
+// conflicting only where the bricks of neighbouring cells overlap).  The
+// brick holds 64-bit fixed-point sums: every contribution is rounded to a
+// multiple of 2^-S with 2^S sum_cell |q_i| < 2^62 (no sum can overflow, since
+// B-spline weights lie in [0, 1]), and integer LDS adds are exact, so the
+// brick does not depend on the order of the adds; the rounding is below 2^-62
+// of the cell's total |q| per contribution.  A brick larger than brick_cap
+// points (cells much wider than h) falls back to per-particle global atomics.
+constexpr int kBrickMax = 8192;  // largest brick in LDS (64 KB)
 
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
     k_anterp_brick(const int* __restrict__ start, const vec4_t<T>* __restrict__ sorted,
-                   GridDev<T> g, CellGrid cg, T* __restrict__ grid) {
-  __shared__ T brick[kBrickMax];
+                   GridDev<T> g, CellGrid cg, int brick_cap, T* __restrict__ grid) {
+  extern __shared__ long long brick[];
+  __shared__ double qsum[4];
   const int cell = blockIdx.x;
   const int beg = start[cell], end = start[cell + 1];
   if (beg == end) return;
@@ -178,10 +186,19 @@ __global__ void __launch_bounds__(256)
     ext[k] = hi - lo[k] + 1;
   }
   const int vol = ext[0] * ext[1] * ext[2];
-  const bool staged = vol <= kBrickMax;
+  const bool staged = vol <= brick_cap;
+  double scale = 1.0;
   if (staged) {
-    for (int b = threadIdx.x; b < vol; b += blockDim.x) brick[b] = T(0);
+    for (int b = threadIdx.x; b < vol; b += blockDim.x) brick[b] = 0;
+    double aq = 0.0;
+    for (int i = beg + (int)threadIdx.x; i < end; i += blockDim.x) aq += fabs((double)sorted[i].w);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) aq += __shfl_xor(aq, o);
+    if ((threadIdx.x & 63) == 0) qsum[threadIdx.x >> 6] = aq;
     __syncthreads();
+    int ex;
+    (void)frexp(qsum[0] + qsum[1] + qsum[2] + qsum[3], &ex);  // total < 2^ex
+    scale = ldexp(1.0, 62 - max(ex, -900));  // stays a finite power of two
   }
   for (int i = beg + (int)threadIdx.x; i < end; i += blockDim.x) {
     const vec4_t<T> pi = sorted[i];
@@ -195,6 +212,7 @@ __global__ void __launch_bounds__(256)
       bspline_weights<P, double>(f, w[k], nullptr, nullptr);
     }
     const double qi = (double)pi.w;
+    const double qs = qi * scale;
     bool inside = staged;
 #pragma unroll
     for (int k = 0; k < 3; ++k) inside = inside && m0[k] >= lo[k] && m0[k] + P - 1 < lo[k] + ext[k];
@@ -202,13 +220,15 @@ __global__ void __launch_bounds__(256)
       const int b0 = ((m0[2] - lo[2]) * ext[1] + (m0[1] - lo[1])) * ext[0] + (m0[0] - lo[0]);
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const double wz = qi * w[2][c];
+        const double wz = qs * w[2][c];
 #pragma unroll
         for (int b = 0; b < P; ++b) {
           const double wyz = wz * w[1][b];
           const int row = b0 + (c * ext[1] + b) * ext[0];
 #pragma unroll
-          for (int a = 0; a < P; ++a) atomicAdd(&brick[row + a], (T)(wyz * w[0][a]));
+          for (int a = 0; a < P; ++a)
+            atomicAdd((unsigned long long*)&brick[row + a],
+                      (unsigned long long)__double2ll_rn(wyz * w[0][a]));
         }
       }
     } else {
@@ -237,9 +257,11 @@ __global__ void __launch_bounds__(256)
   }
   if (!staged) return;
   __syncthreads();
+  const double inv_scale = 1.0 / scale;  // a power of two
   for (int b = threadIdx.x; b < vol; b += blockDim.x) {
-    const T v = brick[b];
-    if (v == T(0)) continue;
+    const long long s = brick[b];
+    if (s == 0) continue;
+    const T v = (T)((double)s * inv_scale);
     const int bx = b % ext[0], by = (b / ext[0]) % ext[1], bz = b / (ext[0] * ext[1]);
     const int ix = axis_index(lo[0] + bx, g.n[0], g.lo[0], g.per[0]);
     const int iy = axis_index(lo[1] + by, g.n[1], g.lo[1], g.per[1]);
@@ -360,10 +382,16 @@ template <typename T>
 void launch_anterp(int p, int n, int ncell, const int* start, const CellGrid& cg,
                    const vec4_t<T>* sorted, const GridDev<T>& g, T* grid, hipStream_t s) {
   if (n <= 0) return;
+  // LDS for the largest brick a cell can need: per axis at most
+  // ceil(cs / h) + p + 3 points (one more for the rounding of cs / h)
+  long long cap = 1;
+  for (int k = 0; k < 3; ++k) cap *= (long long)std::ceil(cg.cs[k] / g.hd[k]) + p + 4;
+  const int bc = (int)std::min<long long>(cap, kBrickMax);
+  const size_t lds = (size_t)bc * sizeof(long long);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_anterp_brick<T, 4>), dim3(ncell), dim3(256), 0, s, start, sorted, g, cg, grid); break;
-    case 6: hipLaunchKernelGGL((k_anterp_brick<T, 6>), dim3(ncell), dim3(256), 0, s, start, sorted, g, cg, grid); break;
-    case 8: hipLaunchKernelGGL((k_anterp_brick<T, 8>), dim3(ncell), dim3(256), 0, s, start, sorted, g, cg, grid); break;
+    case 4: hipLaunchKernelGGL((k_anterp_brick<T, 4>), dim3(ncell), dim3(256), lds, s, start, sorted, g, cg, bc, grid); break;
+    case 6: hipLaunchKernelGGL((k_anterp_brick<T, 6>), dim3(ncell), dim3(256), lds, s, start, sorted, g, cg, bc, grid); break;
+    case 8: hipLaunchKernelGGL((k_anterp_brick<T, 8>), dim3(ncell), dim3(256), lds, s, start, sorted, g, cg, bc, grid); break;
   }
 }
 

@@ -223,6 +223,26 @@ def test_folded_matches_unfolded(fp64, geom):
     assert rel_rms(g1["phi"], g0["phi"]) <= tol
 
 
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("scale", [1e-12, 1e12])
+def test_charge_scale_homogeneity(fp64, scale):
+    """E and F are quadratic in the charges, phi = dE/dq linear: scaling every
+    charge by s scales them by s^2 and s.  The level-1 charges are summed in
+    LDS as 64-bit fixed point with a power-of-two scale chosen per cell from
+    its total |q|, so tiny and huge charges keep full relative precision."""
+    box = (18.0, 18.0, 18.0)
+    pos, q = WL.gaussian_charges(1500, box, 0.5, seed=31)
+    pos, q = cast(pos, q, fp64)
+    plan = msm.Plan(box, 7, 4, 0.75, 4.0, 3, msm.MSM_FP64 if fp64 else msm.MSM_FP32, 1500)
+    g1 = gpu_forward(plan, pos, q)
+    gs = gpu_forward(plan, pos, (q * scale).astype(q.dtype))
+    assert plan.status() == 0
+    tol = 1e-12 if fp64 else 1e-6
+    assert abs(gs["E"] / scale**2 - g1["E"]) <= tol * abs(g1["E"])
+    assert rel_rms(gs["F"] / scale**2, g1["F"]) <= tol
+    assert rel_rms(gs["phi"] / scale, g1["phi"]) <= tol
+
+
 def test_profile_stage_filter():
     import torch
     box = (16.0, 16.0, 16.0)
