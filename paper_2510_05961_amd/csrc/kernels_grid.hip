@@ -1,5 +1,6 @@
 // kernels_grid.hip -- grid-side kernels of the MSM: restriction, prolongation
 // and the per-level stencil convolution (also used for the dense top level).
+#include <algorithm>
 #include <cstdlib>
 
 #include "conv_tile.hpp"
@@ -259,13 +260,15 @@ __global__ void __launch_bounds__(TXT * TYT * WS)
                              Q + ly - 2, acc, WS);
   }
   if constexpr (WS > 1) {
-    // copies 1..WS-1 hand their sums to copy 0
-    __shared__ TA red[WS - 1][Q * R][NTILE];
+    // copies 1..WS-1 hand their sums to copy 0 through the (no longer
+    // needed) window memory: red[w][a R + r][tt]
+    TA* red = reinterpret_cast<TA*>(smem_raw);
+    __syncthreads();
     if (ws > 0) {
 #pragma unroll
       for (int a = 0; a < Q; ++a)
 #pragma unroll
-        for (int r = 0; r < R; ++r) red[ws - 1][a * R + r][tt] = acc[a][r];
+        for (int r = 0; r < R; ++r) red[((ws - 1) * Q * R + a * R + r) * NTILE + tt] = acc[a][r];
     }
     __syncthreads();
     if (ws > 0) return;
@@ -274,7 +277,7 @@ __global__ void __launch_bounds__(TXT * TYT * WS)
 #pragma unroll
       for (int a = 0; a < Q; ++a)
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[a][r] += red[w][a * R + r][tt];
+        for (int r = 0; r < R; ++r) acc[a][r] += red[(w * Q * R + a * R + r) * NTILE + tt];
   }
 #pragma unroll
   for (int a = 0; a < Q; ++a) {
@@ -394,14 +397,16 @@ struct ConvShape {
 };
 static const ConvShape kShapes[3] = {
     {4, 4, 16, 16, 1, 1.0}, {4, 4, 8, 8, 4, 0.9}, {2, 2, 8, 8, 4, 0.55}};
+constexpr int kNumShapes = 3;
 
 int conv_row_stride(int len0) { return len0 + kConvCH - 1; }
 
-// static LDS of k_conv: the column table and the row-split reduction buffer
-// (FP64 accumulators)
-static size_t conv_static_lds(const ConvShape& sh) {
-  return sizeof(int) * kConvMaxLW +
-         (size_t)(sh.WS - 1) * sh.Q * sh.R * sh.TXT * sh.TYT * sizeof(double);
+// LDS of k_conv: the staged window (tsize bytes per point) or, reusing it
+// at the end, the row-split reduction buffer (FP64 accumulators), plus the
+// static column table
+static size_t conv_lds_total(const ConvShape& sh, size_t window_bytes) {
+  const size_t red = (size_t)(sh.WS - 1) * sh.Q * sh.R * sh.TXT * sh.TYT * sizeof(double);
+  return std::max(window_bytes, red) + sizeof(int) * kConvMaxLW;
 }
 
 ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3],
@@ -423,11 +428,11 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
   // launch cannot reach 2048 waves even with one stencil plane per split
   double best = 0;
   int pick = -1;
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < kNumShapes; ++c) {
     const ConvShape& sh = kShapes[c];
     const int TX = sh.TXT * sh.R, TY = sh.TYT * sh.Q;
-    const size_t lds = (size_t)(TX + len[0] - 1 + kConvCH - 1) * (TY + len[1] - 1) * tsize +
-                       conv_static_lds(sh);
+    const size_t lds =
+        conv_lds_total(sh, (size_t)(TX + len[0] - 1 + kConvCH - 1) * (TY + len[1] - 1) * tsize);
     if (lds > 64 * 1024 || TX + len[0] - 1 + kConvCH - 1 > kConvMaxLW) continue;
     const double tiles = (double)((nout[0] + TX - 1) / TX) * ((nout[1] + TY - 1) / TY) * nout[2];
     const double waves = tiles * cp.nplanes * (sh.TXT * sh.TYT * sh.WS / 64);
@@ -463,14 +468,15 @@ ConvParams make_conv_params(const int n[3], const int nout[3], const int shift[3
 }
 
 size_t conv_lds_bytes(const ConvParams& cp, int tsize) {
-  return (size_t)cp.lds_w * cp.lds_h * tsize + conv_static_lds(kShapes[cp.shape]);
+  return conv_lds_total(kShapes[cp.shape], (size_t)cp.lds_w * cp.lds_h * tsize);
 }
 
 template <typename TI, typename TA>
 void launch_conv(const ConvParams& cp, const TA* K, const int2* rowext, const TI* q, TA* e,
                  hipStream_t s) {
-  const size_t lds = (size_t)cp.lds_w * cp.lds_h * sizeof(TI);
   const ConvShape& sh = kShapes[cp.shape];
+  const size_t lds = conv_lds_total(sh, (size_t)cp.lds_w * cp.lds_h * sizeof(TI)) -
+                     sizeof(int) * kConvMaxLW;
   const int TX = sh.TXT * sh.R, TY = sh.TYT * sh.Q;
   dim3 grid((cp.nout[0] + TX - 1) / TX, (cp.nout[1] + TY - 1) / TY, cp.nout[2] * cp.nsplit);
   switch (cp.shape) {

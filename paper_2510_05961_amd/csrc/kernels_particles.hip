@@ -305,6 +305,9 @@ __global__ void __launch_bounds__(256)
       }
     }
     double v = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    // the P points of a row are consecutive in memory unless the row wraps
+    // or leaves a free axis: then one vector load per row
+    const bool run = idx[0][0] >= 0 && idx[0][P - 1] == idx[0][0] + P - 1;
 #pragma unroll
     for (int c = 0; c < P; ++c) {
       if (idx[2][c] < 0) continue;
@@ -312,11 +315,17 @@ __global__ void __launch_bounds__(256)
       for (int b = 0; b < P; ++b) {
         if (idx[1][b] < 0) continue;
         const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
+        T ev[P];
+        if (run) {
+          __builtin_memcpy(ev, e1 + row + idx[0][0], sizeof(ev));
+        } else {
+#pragma unroll
+          for (int a = 0; a < P; ++a) ev[a] = idx[0][a] >= 0 ? e1[row + idx[0][a]] : T(0);
+        }
         double sv = 0.0, sd = 0.0;
 #pragma unroll
         for (int a = 0; a < P; ++a) {
-          if (idx[0][a] < 0) continue;
-          const double e = (double)e1[row + idx[0][a]];
+          const double e = (double)ev[a];
           sv += e * w[0][a];
           sd += e * dw[0][a];
         }
