@@ -16,6 +16,7 @@
 #include "msm.h"
 #include "plan.hpp"
 #include "plan_state.hpp"
+#include "stencil_fold.hpp"
 
 using namespace msm;
 
@@ -81,12 +82,9 @@ WsLayout ws_layout(const msm_plan P, int n) {
 // The stencil of a level as uploaded: radial kernels sampled on offsets
 // symmetric about 0 have mirrored z-planes, and the convolution then adds
 // the two input planes of a mirrored pair before one pass over the shared
-// coefficients.  A periodic table over all n residues (n even, offsets
-// -n/2..n/2-1) first gets its plane -n/2 split in two halves at -n/2 and
-// +n/2 (the same input plane mod n; halving is exact).  Pairs that agree to
-// 1e-12 of the largest coefficient are replaced by their mean, so they
-// match bit for bit; any larger difference leaves the stencil as it is.
-// MSM_FOLD=0 (read at plan creation) keeps every stencil unfolded.
+// coefficients (make_planes_mirror).  A periodic table over all n residues
+// (n even, offsets -n/2..n/2-1) first gets its plane -n/2 split in two
+// halves at -n/2 and +n/2 (the same input plane mod n; halving is exact).
 static ConvGeom mirror_stencil(const std::vector<double>& A, const int off[3], const int len[3],
                                bool per_z, int nz, std::vector<double>& B) {
   ConvGeom g;
@@ -96,8 +94,7 @@ static ConvGeom mirror_stencil(const std::vector<double>& A, const int off[3], c
   }
   g.fold = 0;
   B = A;
-  const char* env = std::getenv("MSM_FOLD");
-  if ((env && env[0] == '0') || len[2] < 2) return g;
+  if (!fold_allowed() || len[2] < 2) return g;
   const size_t plane = (size_t)len[0] * len[1];
   std::vector<double> C;
   int lz = len[2];
@@ -109,18 +106,7 @@ static ConvGeom mirror_stencil(const std::vector<double>& A, const int off[3], c
   } else {
     C = A;
   }
-  double amax = 0.0;
-  for (double v : C) amax = std::max(amax, std::fabs(v));
-  const double tol = 1e-12 * amax;
-  for (int j = 0; j < lz / 2; ++j)
-    for (size_t i = 0; i < plane; ++i)
-      if (!(std::fabs(C[plane * j + i] - C[plane * (lz - 1 - j) + i]) <= tol)) return g;
-  for (int j = 0; j < lz / 2; ++j)
-    for (size_t i = 0; i < plane; ++i) {
-      double& u = C[plane * j + i];
-      double& w = C[plane * (lz - 1 - j) + i];
-      u = w = 0.5 * (u + w);
-    }
+  if (!make_planes_mirror(C, len[0], len[1], lz)) return g;
   B.swap(C);
   g.len[2] = lz;
   g.fold = 1;

@@ -26,6 +26,7 @@
 #include "msm.h"
 #include "plan.hpp"
 #include "plan_state.hpp"
+#include "stencil_fold.hpp"
 
 namespace msm {
 
@@ -42,6 +43,7 @@ struct BatchConv {
   int top;       // 1: dense top kernel of the systems whose top level is `level`
   double scale;  // multiplies the stencil (K^l = K^1 / 2^(l-1))
   int off, len;  // cubic stencil box: offsets off .. off+len-1 per axis
+  int fold = 0;  // z-planes j and len-1-j share coefficients
   void* K = nullptr;
   int2* rowext = nullptr;
   ConvTask* tasks = nullptr;
@@ -345,10 +347,12 @@ constexpr int kBConvCH = 8;
 
 // Stencil convolution over a task list: each workgroup computes one output
 // tile (one z plane) of one system's grid, all stencil planes; free axes.
+// With fold, plane jz and its mirror len-1-jz hold the same coefficients:
+// their two input planes are added while staging and walked once.
 template <typename T, int R, int TXT, int TYT>
 __global__ void __launch_bounds__(TXT * TYT)
-    k_batch_conv(const ConvTask* __restrict__ tasks, int off, int len, int lds_w, double scale,
-                 const double* __restrict__ K, const int2* __restrict__ rowext,
+    k_batch_conv(const ConvTask* __restrict__ tasks, int off, int len, int fold, int lds_w,
+                 double scale, const double* __restrict__ K, const int2* __restrict__ rowext,
                  const T* __restrict__ qcat, T* __restrict__ ecat) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
@@ -361,15 +365,25 @@ __global__ void __launch_bounds__(TXT * TYT)
   double total[R];  // FP64 accumulation (long sums with cancellation)
 #pragma unroll
   for (int r = 0; r < R; ++r) total[r] = 0;
-  for (int jz = 0; jz < len; ++jz) {
-    const int zi = tk.z - (off + jz);
-    if (zi < 0 || zi >= n) continue;  // uniform over the workgroup
+  const int nplanes = fold ? (len + 1) / 2 : len;
+  for (int jz = 0; jz < nplanes; ++jz) {
+    const int za = tk.z - (off + jz), jm = len - 1 - jz;
+    const int zb = (fold && jm != jz) ? tk.z - (off + jm) : -1;
+    const bool va = za >= 0 && za < n, vb = zb >= 0 && zb < n;
+    if (!va && !vb) continue;  // uniform over the workgroup
     __syncthreads();
-    const T* qz = q + (long long)zi * n * n;
+    const T* qa = q + (long long)(va ? za : zb) * n * n;
+    const T* qb = q + (long long)(vb ? zb : 0) * n * n;
+    const bool two = va && vb;
     for (int idx = threadIdx.x; idx < LW * LH; idx += TXT * TYT) {
       const int ry = idx / LW, rx = idx - ry * LW;
       const int yi = ys + ry, xi = xs + rx;
-      lds[idx] = (yi >= 0 && yi < n && xi >= 0 && xi < n) ? qz[(long long)yi * n + xi] : T(0);
+      T v = T(0);
+      if (yi >= 0 && yi < n && xi >= 0 && xi < n) {
+        const long long o = (long long)yi * n + xi;
+        v = two ? qa[o] + qb[o] : qa[o];
+      }
+      lds[idx] = v;
     }
     __syncthreads();
     const double* Kz = K + (long long)jz * len * len;
@@ -503,9 +517,9 @@ static void launch_batch_conv(const BatchConv& bc, int cfg, const T* qcat, T* ec
   const double scale = bc.scale;
   const double* K = (const double*)bc.K;
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_batch_conv<T, 4, 4, 16>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, K, bc.rowext, qcat, ecat); break;
-    case 1: hipLaunchKernelGGL((k_batch_conv<T, 4, 8, 16>), dim3(bc.ntasks), dim3(128), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, K, bc.rowext, qcat, ecat); break;
-    default: hipLaunchKernelGGL((k_batch_conv<T, 2, 8, 8>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, lds_w, scale, K, bc.rowext, qcat, ecat); break;
+    case 0: hipLaunchKernelGGL((k_batch_conv<T, 4, 4, 16>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, bc.fold, lds_w, scale, K, bc.rowext, qcat, ecat); break;
+    case 1: hipLaunchKernelGGL((k_batch_conv<T, 4, 8, 16>), dim3(bc.ntasks), dim3(128), lds, s, bc.tasks, bc.off, bc.len, bc.fold, lds_w, scale, K, bc.rowext, qcat, ecat); break;
+    default: hipLaunchKernelGGL((k_batch_conv<T, 2, 8, 8>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, bc.fold, lds_w, scale, K, bc.rowext, qcat, ecat); break;
   }
 }
 
@@ -523,9 +537,13 @@ static std::vector<ConvTask> build_tasks(const BatchState& B, int level, int top
   return t;
 }
 
+// A cubic stencil [len]^3 to the device; *fold says whether its z-planes
+// mirror (make_planes_mirror, which may average the mirrored pairs first).
 template <typename T>
-static msm_status upload_stencil(msm_plan P, const std::vector<double>& K, int len, void** dK,
-                                 int2** dext) {
+static msm_status upload_stencil(msm_plan P, const std::vector<double>& K0, int len, void** dK,
+                                 int2** dext, int* fold) {
+  std::vector<double> K = K0;
+  *fold = fold_allowed() && make_planes_mirror(K, len, len, len);
   std::vector<T> kt(K.size());
   for (size_t i = 0; i < K.size(); ++i) kt[i] = (T)K[i];
   std::vector<int2> ext((size_t)len * len);
@@ -713,7 +731,8 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
   // stencils: K^1 (intermediate levels, scaled per level) and the top tables
   void* dK1 = nullptr;
   int2* dK1ext = nullptr;
-  if ((st = upload_stencil<double>(P, K1, 2 * W1 + 1, &dK1, &dK1ext))) return st;
+  int fold1 = 0;
+  if ((st = upload_stencil<double>(P, K1, 2 * W1 + 1, &dK1, &dK1ext, &fold1))) return st;
   for (int l = 1; l <= B.Lmax; ++l) {
     BatchConv inter;
     inter.level = l;
@@ -723,6 +742,7 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
     inter.len = 2 * W1 + 1;
     inter.K = dK1;
     inter.rowext = dK1ext;
+    inter.fold = fold1;
     BatchConv top;
     top.level = l;
     top.top = 1;
@@ -730,7 +750,8 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
     top.len = top_len[l];
     top.off = -(top_len[l] - 1) / 2;
     if (top_len[l] > 0) {
-      if ((st = upload_stencil<double>(P, tops[l], top_len[l], &top.K, &top.rowext))) return st;
+      if ((st = upload_stencil<double>(P, tops[l], top_len[l], &top.K, &top.rowext, &top.fold)))
+        return st;
     }
     for (BatchConv* bc : {&inter, &top}) {
       if (bc->top && top_len[l] == 0) continue;
