@@ -567,7 +567,14 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
     grid_zero_jobs<T>(P, z);
     launch_zero_multi(z, s);
   }
-  launch_anterp_dipole<T>(p, n, sorted, v, g1, (T*)P->qg[0], s);
+  {
+    CellGrid cg;
+    for (int k = 0; k < 3; ++k) {
+      cg.nc[k] = hp.nc[k];
+      cg.cs[k] = hp.cs[k];
+    }
+    launch_anterp_dipole<T>(p, n, P->ncell, start, cg, sorted, v, g1, (T*)P->qg[0], s);
+  }
   pf.end(ev, s);
   grid_pass<T>(P, s, dag ? P->sb : s);  // eg[0] = (A D)^{1+}
   if (dag) (void)hipStreamWaitEvent(s, P->ev[1], 0);

@@ -14,6 +14,9 @@
 //      d(v.F0)/dq_i = sum_j q_j f (v_i - v_j) . d_ij
 //      d(v.F0)/dr_i = sum_j q_i q_j [f (v_i - v_j) + (f'/r) ((v_i - v_j) . d_ij) d_ij]
 //    with f = 1/r^3 + 2 P'(t)/a^3 and f'/r = -3/r^5 + 4 P''(t)/a^5.
+#include <algorithm>
+#include <cmath>
+
 #include "kernels.hpp"
 
 namespace msm {
@@ -33,44 +36,121 @@ __global__ void k_gather_v(int n, const int* __restrict__ perm, const T* __restr
   v[i] = t;
 }
 
+// The dipole grid in the brick form of the forward anterpolation: one
+// workgroup per cell, 64-bit fixed-point sums in LDS (exact integer adds; the
+// power-of-two scale bounds every sum by 2^62, since |contribution| <=
+// |q| (|vx| + |vy| + |vz|) max(1/h) for B-spline weights in [0, 1] and
+// derivatives in [-1/h, 1/h]), then one atomic per non-zero point.  Cells
+// whose brick exceeds brick_cap points fall back to per-particle atomics.
 template <typename T, int P>
-__global__ void k_anterp_dipole(int n, const vec4_t<T>* __restrict__ sorted,
-                                const vec4_t<T>* __restrict__ v, GridDev<T> g,
-                                T* __restrict__ grid) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const vec4_t<T> pi = sorted[i];
-  const vec4_t<T> vi = v[i];
-  const T xs[3] = {pi.x, pi.y, pi.z};
-  T w[3][P], dw[3][P];
-  int idx[3][P];
+__global__ void __launch_bounds__(256)
+    k_anterp_dipole_brick(const int* __restrict__ start, const vec4_t<T>* __restrict__ sorted,
+                          const vec4_t<T>* __restrict__ v, GridDev<T> g, CellGrid cg,
+                          int brick_cap, T* __restrict__ grid) {
+  extern __shared__ long long brick[];
+  __shared__ double bsum[4];
+  const int cell = blockIdx.x;
+  const int beg = start[cell], end = start[cell + 1];
+  if (beg == end) return;
+  const int cc[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
+  int lo[3], ext[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    T f;
-    const int base = grid_coord(xs[k], g.h[k], f);
-    bspline_weights<P, T>(f, w[k], dw[k], nullptr);
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      idx[k][j] = axis_index(base - P / 2 + 1 + j, g.n[k], g.lo[k], g.per[k]);
-      dw[k][j] *= g.inv_h[k];
-    }
+    lo[k] = (int)floor(cc[k] * cg.cs[k] / g.hd[k]) - P / 2 - 1;
+    const int hi = (int)floor((cc[k] + 1) * cg.cs[k] / g.hd[k]) + P / 2 + 1;
+    ext[k] = hi - lo[k] + 1;
   }
-  const T qi = pi.w;
+  const int vol = ext[0] * ext[1] * ext[2];
+  const bool staged = vol <= brick_cap;
+  const double ih[3] = {1.0 / g.hd[0], 1.0 / g.hd[1], 1.0 / g.hd[2]};
+  double scale = 1.0;
+  if (staged) {
+    for (int b = threadIdx.x; b < vol; b += blockDim.x) brick[b] = 0;
+    double bound = 0.0;
+    for (int i = beg + (int)threadIdx.x; i < end; i += blockDim.x) {
+      const vec4_t<T> vi = v[i];
+      bound += fabs((double)sorted[i].w) *
+               (fabs((double)vi.x) + fabs((double)vi.y) + fabs((double)vi.z));
+    }
 #pragma unroll
-  for (int c = 0; c < P; ++c) {
-    if (idx[2][c] < 0) continue;
+    for (int o = 32; o >= 1; o >>= 1) bound += __shfl_xor(bound, o);
+    if ((threadIdx.x & 63) == 0) bsum[threadIdx.x >> 6] = bound;
+    __syncthreads();
+    int ex;
+    (void)frexp((bsum[0] + bsum[1] + bsum[2] + bsum[3]) * fmax(ih[0], fmax(ih[1], ih[2])), &ex);
+    scale = ldexp(1.0, 62 - max(ex, -900));
+  }
+  for (int i = beg + (int)threadIdx.x; i < end; i += blockDim.x) {
+    const vec4_t<T> pi = sorted[i];
+    const vec4_t<T> vi = v[i];
+    const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    double w[3][P], dw[3][P];
+    int m0[3];
 #pragma unroll
-    for (int b = 0; b < P; ++b) {
-      if (idx[1][b] < 0) continue;
-      const T syz = vi.x * w[1][b] * w[2][c];
-      const T tyz = vi.y * dw[1][b] * w[2][c] + vi.z * w[1][b] * dw[2][c];
-      const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
+    for (int k = 0; k < 3; ++k) {
+      double f;
+      m0[k] = grid_coord<double>(xs[k], g.hd[k], f) - P / 2 + 1;
+      bspline_weights<P, double>(f, w[k], dw[k], nullptr);
 #pragma unroll
-      for (int a = 0; a < P; ++a) {
-        if (idx[0][a] < 0) continue;
-        atomicAdd(&grid[row + idx[0][a]], qi * (syz * dw[0][a] + tyz * w[0][a]));
+      for (int j = 0; j < P; ++j) dw[k][j] *= ih[k];
+    }
+    bool inside = staged;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) inside = inside && m0[k] >= lo[k] && m0[k] + P - 1 < lo[k] + ext[k];
+    const double qd = (double)pi.w;
+    const double vx = (double)vi.x, vy = (double)vi.y, vz = (double)vi.z;
+    if (inside) {
+      const double qs = qd * scale;
+      const int b0 = ((m0[2] - lo[2]) * ext[1] + (m0[1] - lo[1])) * ext[0] + (m0[0] - lo[0]);
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+          const double syz = qs * vx * w[1][b] * w[2][c];
+          const double tyz = qs * (vy * dw[1][b] * w[2][c] + vz * w[1][b] * dw[2][c]);
+          const int row = b0 + (c * ext[1] + b) * ext[0];
+#pragma unroll
+          for (int a = 0; a < P; ++a)
+            atomicAdd((unsigned long long*)&brick[row + a],
+                      (unsigned long long)__double2ll_rn(syz * dw[0][a] + tyz * w[0][a]));
+        }
+      }
+    } else {
+      int idx[3][P];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < P; ++j) idx[k][j] = axis_index(m0[k] + j, g.n[k], g.lo[k], g.per[k]);
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        if (idx[2][c] < 0) continue;
+#pragma unroll
+        for (int b = 0; b < P; ++b) {
+          if (idx[1][b] < 0) continue;
+          const double syz = qd * vx * w[1][b] * w[2][c];
+          const double tyz = qd * (vy * dw[1][b] * w[2][c] + vz * w[1][b] * dw[2][c]);
+          const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
+#pragma unroll
+          for (int a = 0; a < P; ++a) {
+            if (idx[0][a] < 0) continue;
+            atomicAdd(&grid[row + idx[0][a]], (T)(syz * dw[0][a] + tyz * w[0][a]));
+          }
+        }
       }
     }
+  }
+  if (!staged) return;
+  __syncthreads();
+  const double inv_scale = 1.0 / scale;  // a power of two
+  for (int b = threadIdx.x; b < vol; b += blockDim.x) {
+    const long long sum = brick[b];
+    if (sum == 0) continue;
+    const int bx = b % ext[0], by = (b / ext[0]) % ext[1], bz = b / (ext[0] * ext[1]);
+    const int ix = axis_index(lo[0] + bx, g.n[0], g.lo[0], g.per[0]);
+    const int iy = axis_index(lo[1] + by, g.n[1], g.lo[1], g.per[1]);
+    const int iz = axis_index(lo[2] + bz, g.n[2], g.lo[2], g.per[2]);
+    if (ix < 0 || iy < 0 || iz < 0) continue;
+    atomicAdd(&grid[((long long)iz * g.n[1] + iy) * g.n[0] + ix], (T)((double)sum * inv_scale));
   }
 }
 
@@ -107,6 +187,9 @@ __global__ void __launch_bounds__(256)
   T M000 = 0, M100 = 0, M010 = 0, M001 = 0, M200 = 0, M020 = 0, M002 = 0, M110 = 0, M101 = 0,
     M011 = 0;
   T N000 = 0, N100 = 0, N010 = 0, N001 = 0;
+  // rows of p consecutive grid values (no wrap, inside a free axis): one
+  // vector load each
+  const bool run = idx[0][0] >= 0 && idx[0][P - 1] == idx[0][0] + P - 1;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
     if (idx[2][c] < 0) continue;
@@ -116,11 +199,21 @@ __global__ void __launch_bounds__(256)
       if (idx[1][b] < 0) continue;
       const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
       T S0 = 0, S1 = 0, S2 = 0, D0 = 0, D1 = 0;
+      T pv[P], pd[P];
+      if (run) {
+        __builtin_memcpy(pv, psi + row + idx[0][0], sizeof(pv));
+        __builtin_memcpy(pd, psiD + row + idx[0][0], sizeof(pd));
+      } else {
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          pv[a] = idx[0][a] >= 0 ? psi[row + idx[0][a]] : T(0);
+          pd[a] = idx[0][a] >= 0 ? psiD[row + idx[0][a]] : T(0);
+        }
+      }
 #pragma unroll
       for (int a = 0; a < P; ++a) {
-        if (idx[0][a] < 0) continue;
-        const T e = psi[row + idx[0][a]];
-        const T ed = psiD[row + idx[0][a]];
+        const T e = pv[a];
+        const T ed = pd[a];
         S0 += e * w[0][a];
         S1 += e * dw[0][a];
         S2 += e * d2w[0][a];
@@ -196,14 +289,18 @@ void launch_gather_v(int n, const int* perm, const T* gF, vec4_t<T>* v, hipStrea
 }
 
 template <typename T>
-void launch_anterp_dipole(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v,
-                          const GridDev<T>& g, T* grid, hipStream_t s) {
+void launch_anterp_dipole(int p, int n, int ncell, const int* start, const CellGrid& cg,
+                          const vec4_t<T>* sorted, const vec4_t<T>* v, const GridDev<T>& g,
+                          T* grid, hipStream_t s) {
   if (n <= 0) return;
-  const int nb = (n + 255) / 256;
+  long long cap = 1;  // as in launch_anterp
+  for (int k = 0; k < 3; ++k) cap *= (long long)std::ceil(cg.cs[k] / g.hd[k]) + p + 4;
+  const int bc = (int)std::min<long long>(cap, 8192);
+  const size_t lds = (size_t)bc * sizeof(long long);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_anterp_dipole<T, 4>), dim3(nb), dim3(256), 0, s, n, sorted, v, g, grid); break;
-    case 6: hipLaunchKernelGGL((k_anterp_dipole<T, 6>), dim3(nb), dim3(256), 0, s, n, sorted, v, g, grid); break;
-    case 8: hipLaunchKernelGGL((k_anterp_dipole<T, 8>), dim3(nb), dim3(256), 0, s, n, sorted, v, g, grid); break;
+    case 4: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 4>), dim3(ncell), dim3(256), lds, s, start, sorted, v, g, cg, bc, grid); break;
+    case 6: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 6>), dim3(ncell), dim3(256), lds, s, start, sorted, v, g, cg, bc, grid); break;
+    case 8: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 8>), dim3(ncell), dim3(256), lds, s, start, sorted, v, g, cg, bc, grid); break;
   }
 }
 
@@ -231,8 +328,9 @@ void launch_grad_energy_only(int n, const int* perm, const T* save_phi, const T*
 
 #define MSM_INST_BACKWARD(T)                                                                      \
   template void launch_gather_v<T>(int, const int*, const T*, vec4_t<T>*, hipStream_t);           \
-  template void launch_anterp_dipole<T>(int, int, const vec4_t<T>*, const vec4_t<T>*,             \
-                                        const GridDev<T>&, T*, hipStream_t);                      \
+  template void launch_anterp_dipole<T>(int, int, int, const int*, const CellGrid&,                \
+                                        const vec4_t<T>*, const vec4_t<T>*, const GridDev<T>&, T*,  \
+                                        hipStream_t);                                             \
   template void launch_interp_vjp<T>(int, int, const vec4_t<T>*, const vec4_t<T>*, const int*,    \
                                      const GridDev<T>&, const T*, const T*, const T*, const T*,   \
                                      const T*, const T*, const double*, T*, T*, hipStream_t);     \

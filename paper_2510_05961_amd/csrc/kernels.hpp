@@ -167,8 +167,9 @@ void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4
                         const vec4_t<T>* cbox, const PairParams<T>& pp, int null_h, T* gq,
                         T* gr, hipStream_t s);
 template <typename T>
-void launch_anterp_dipole(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v,
-                          const GridDev<T>& g, T* grid, hipStream_t s);
+void launch_anterp_dipole(int p, int n, int ncell, const int* start, const CellGrid& cg,
+                          const vec4_t<T>* sorted, const vec4_t<T>* v, const GridDev<T>& g,
+                          T* grid, hipStream_t s);
 template <typename T>
 void launch_interp_vjp(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v, const int* perm,
                        const GridDev<T>& g, const T* psi, const T* psiD, const T* save_phi,
