@@ -184,8 +184,11 @@ msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void
  * (binning, pair, anterpolation, restriction, conv per level, prolongation,
  * interpolation, backward passes); 0 stops recording.  Recording adds no
  * synchronisation.  msm_plan_get_profile synchronises on the recorded events,
- * writes {"stage": {"ms": total, "launches": calls}, ...} into json[cap] and,
- * if reset != 0, clears the totals.
+ * writes {"stage": {"ms": total, "launches": calls, "start_ms": s,
+ * "end_ms": e}, ...} into json[cap] and, if reset != 0, clears the totals;
+ * s and e sum the stage's start and end times after the first stage of its
+ * call ("fill" for the forward, "bwd_layout" for the backward), so s/calls
+ * and e/calls place the stage on the call's timeline across streams.
  */
 msm_status msm_plan_set_profiling(msm_plan plan, int enable);
 msm_status msm_plan_get_profile(msm_plan plan, char* json, size_t cap, int reset);

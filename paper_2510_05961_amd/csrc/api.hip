@@ -799,12 +799,19 @@ msm_status msm_plan_get_profile(msm_plan plan, char* json, size_t cap, int reset
     bool first = true;
     for (auto& kv : plan->prof.total) {
       o << (first ? "" : ",") << "\"" << kv.first << "\":{\"ms\":" << kv.second.first
-        << ",\"launches\":" << kv.second.second << "}";
+        << ",\"launches\":" << kv.second.second;
+      auto it = plan->prof.offsets.find(kv.first);
+      if (it != plan->prof.offsets.end())
+        o << ",\"start_ms\":" << it->second.first << ",\"end_ms\":" << it->second.second;
+      o << "}";
       first = false;
     }
     o << "}";
     out = o.str();
-    if (reset) plan->prof.total.clear();
+    if (reset) {
+      plan->prof.total.clear();
+      plan->prof.offsets.clear();
+    }
   } catch (...) {
     return MSM_ERR_OOM;
   }

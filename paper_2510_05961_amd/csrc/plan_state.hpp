@@ -30,6 +30,9 @@ struct StageProfiler {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<double, long>> total;
+  // start and end of each stage after the first stage of its call ("fill" in
+  // the forward, "bwd_layout" in the backward), summed like total
+  std::map<std::string, std::pair<double, double>> offsets;
   hipEvent_t get() {
     hipEvent_t e = nullptr;
     if (!pool.empty()) {
@@ -58,13 +61,24 @@ struct StageProfiler {
     if (idx >= 0) (void)hipEventRecord(pending[idx].b, s);
   }
   void collect() {
+    hipEvent_t anchor = nullptr;
     for (auto& p : pending) {
       float ms = 0.f;
+      if (p.stage == "fill" || p.stage == "bwd_layout") anchor = p.a;
       if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
         auto& t = total[p.stage];
         t.first += ms;
         t.second += 1;
+        float t0 = 0.f, t1 = 0.f;
+        if (anchor && hipEventElapsedTime(&t0, anchor, p.a) == hipSuccess &&
+            hipEventElapsedTime(&t1, anchor, p.b) == hipSuccess) {
+          auto& o = offsets[p.stage];
+          o.first += t0;
+          o.second += t1;
+        }
       }
+    }
+    for (auto& p : pending) {
       pool.push_back(p.a);
       pool.push_back(p.b);
     }
