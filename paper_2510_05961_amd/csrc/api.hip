@@ -227,7 +227,8 @@ msm_status upload_plan(msm_plan P) {
   if ((st = hip_alloc(P, (void**)&P->flag, sizeof(int)))) return st;
   if (hipMemset(P->flag, 0, sizeof(int))) return MSM_ERR_HIP;
   if (hipStreamCreateWithFlags(&P->sb, hipStreamNonBlocking) ||
-      hipStreamCreateWithFlags(&P->sc, hipStreamNonBlocking))
+      hipStreamCreateWithFlags(&P->sc, hipStreamNonBlocking) ||
+      hipStreamCreateWithFlags(&P->sd, hipStreamNonBlocking))
     return MSM_ERR_HIP;
   for (auto& e : P->ev)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming)) return MSM_ERR_HIP;
@@ -243,6 +244,7 @@ void free_plan(msm_plan P) {
     if (e) (void)hipEventDestroy(e);
   if (P->sb) (void)hipStreamDestroy(P->sb);
   if (P->sc) (void)hipStreamDestroy(P->sc);
+  if (P->sd) (void)hipStreamDestroy(P->sd);
   for (void* p : P->allocs) (void)hipFree(p);
   delete P;
 }
@@ -345,13 +347,16 @@ void conv_level(msm_plan P, int l, hipStream_t s) {
 }
 
 // Nested grid pass of eq. (u_oneplus_nested_eval): from the level-1 grid in
-// qg[0] to e^{1+} in eg[0].  Two branches: level 1 on sa and the coarse one
-// (restriction, levels 2..L, prolongation down to level 2) on sb; they join
-// before the last prolongation.  sb == sa runs everything in order.
+// qg[0] to e^{1+} in eg[0].  Level 1 runs on sa; the coarse branch on sb:
+// restriction to level 2, level 2's convolution, then (after the join
+// below) prolongation down to level 2.  Below level 2 the restrictions and
+// convolutions run on sd beside level 2's convolution (they need only q~^2),
+// and join sb before its prolongations.  The branches join sa before the
+// last prolongation.  sb == sa (or sd == sb) runs the parts in order.
 // Prolongation finalises each level: e^l = (its own convolution output) +
 // I e^{l+1}, reading a direct level's output from its FP64 buffer.
 template <typename T>
-void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb) {
+void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb, hipStream_t sd) {
   const HostPlan& hp = P->hp;
   const int L = hp.L, p = hp.p;
   StageProfiler& pf = P->prof;
@@ -364,12 +369,31 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb) {
   // so it starts as soon as anterpolation ends
   conv_level<T>(P, 1, sa);
   hipStream_t sc = fork ? sb : sa;
-  int ev = pf.begin("restrict", sc);
-  for (int l = 1; l < L; ++l)
-    launch_restrict<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
-                       (const T*)P->qg[l - 1], (T*)P->qg[l], sc);
-  pf.end(ev, sc);
-  for (int l = 2; l <= L; ++l) conv_level<T>(P, l, sc);
+  if (L > 1) {
+    int ev = pf.begin("restrict", sc);
+    launch_restrict<T>(p, grid_dev<T>(hp, 1), grid_dev<T>(hp, 2), hp.J, (const T*)P->qg[0],
+                       (T*)P->qg[1], sc);
+    pf.end(ev, sc);
+  }
+  const bool fork2 = fork && sd != sc && L > 2;
+  hipStream_t se = fork2 ? sd : sc;
+  if (fork2) {
+    (void)hipEventRecord(P->ev[4], sc);
+    (void)hipStreamWaitEvent(sd, P->ev[4], 0);
+  }
+  if (L > 1) conv_level<T>(P, 2, sc);
+  if (L > 2) {
+    int ev = pf.begin("restrict", se);
+    for (int l = 2; l < L; ++l)
+      launch_restrict<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
+                         (const T*)P->qg[l - 1], (T*)P->qg[l], se);
+    pf.end(ev, se);
+  }
+  for (int l = 3; l <= L; ++l) conv_level<T>(P, l, se);
+  if (fork2) {
+    (void)hipEventRecord(P->ev[5], sd);
+    (void)hipStreamWaitEvent(sc, P->ev[5], 0);
+  }
   // 0-based level l of the output e^l: grid precision in eg[l] for a factored
   // level, FP64 in ug[l] for a direct one (until its prolongation)
   auto coarse_src64 = [&](int l) -> const double* {
@@ -378,7 +402,7 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb) {
   auto fine_src64 = [&](int l) -> const double* {
     return hp.lev[l].factored ? nullptr : P->ug[l];
   };
-  ev = pf.begin("prolong", sc);
+  int ev = pf.begin("prolong", sc);
   for (int l = L - 2; l >= 1; --l)
     launch_prolong<T>(p, grid_dev<T>(hp, l + 1), grid_dev<T>(hp, l + 2), hp.J,
                       (const T*)P->eg[l + 1], coarse_src64(l + 1), (T*)P->eg[l],
@@ -491,7 +515,7 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   launch_anterp<T>(p, n, P->ncell, start, cg, sorted, g1, (T*)P->qg[0], s);
   pf.end(ev, s);
   // a4 restriction, a5 per-level stencils, a6 top level, a7 prolongation
-  grid_pass<T>(P, s, dag ? P->sb : s);
+  grid_pass<T>(P, s, dag ? P->sb : s, dag ? P->sd : s);
   if (dag) (void)hipStreamWaitEvent(s, P->ev[1], 0);
   // a8 + a9 interpolation, combination, energy
   ev = pf.begin("interp", s);
@@ -576,7 +600,7 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
     launch_anterp_dipole<T>(p, n, P->ncell, start, cg, sorted, v, g1, (T*)P->qg[0], s);
   }
   pf.end(ev, s);
-  grid_pass<T>(P, s, dag ? P->sb : s);  // eg[0] = (A D)^{1+}
+  grid_pass<T>(P, s, dag ? P->sb : s, dag ? P->sd : s);  // eg[0] = (A D)^{1+}
   if (dag) (void)hipStreamWaitEvent(s, P->ev[1], 0);
   ev = pf.begin("bwd_interp", s);
   launch_interp_vjp<T>(p, n, sorted, v, perm, g1, save_e1, (const T*)P->eg[0], save_phi, save_F,

@@ -136,8 +136,8 @@ struct msm_plan_s {
   int* flag = nullptr;
   // side streams of the forward DAG (default priority, non-blocking) and the
   // fork/join events between them and the caller's stream
-  hipStream_t sb = nullptr, sc = nullptr;
-  hipEvent_t ev[4] = {};
+  hipStream_t sb = nullptr, sc = nullptr, sd = nullptr;
+  hipEvent_t ev[6] = {};
   std::vector<void*> allocs;
 };
 
