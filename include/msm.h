@@ -179,7 +179,7 @@ msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void
  * msm_plan_set_profiling(plan, 1) makes every later msm_energy_forces /
  * msm_backward call record an event pair around each stage, on the stream
  * the stage runs on (the forward runs the pair sum and the coarse levels on
- * two plan-owned streams beside the caller's; MSM_STREAMS=0 keeps everything
+ * three plan-owned streams beside the caller's; MSM_STREAMS=0 keeps everything
  * on the caller's stream)
  * (binning, pair, anterpolation, restriction, conv per level, prolongation,
  * interpolation, backward passes); 0 stops recording.  Recording adds no

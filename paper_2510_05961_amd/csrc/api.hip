@@ -424,7 +424,7 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb, hipStream_t sd) {
   }
 }
 
-// Whether the forward runs as a DAG over three streams (MSM_STREAMS=0: one;
+// Whether the forward runs as a DAG over four streams (MSM_STREAMS=0: one;
 // read on every call).
 static bool use_streams() {
   const char* e = getenv("MSM_STREAMS");

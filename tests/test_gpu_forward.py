@@ -169,7 +169,7 @@ def test_full_size_sampled(cfg):
 
 @pytest.mark.parametrize("fp64", [True, False])
 def test_streams_match_single_stream(fp64):
-    """The three-stream forward (pair sum and coarse levels beside level 1)
+    """The four-stream forward (pair sum and coarse levels beside level 1)
     against everything on the caller's stream: equal up to the order of the
     atomic additions."""
     import os
