@@ -187,7 +187,7 @@ msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void
  * writes {"stage": {"ms": total, "launches": calls, "start_ms": s,
  * "end_ms": e}, ...} into json[cap] and, if reset != 0, clears the totals;
  * s and e sum the stage's start and end times after the first stage of its
- * call ("fill" for the forward, "bwd_layout" for the backward), so s/calls
+ * call ("bin" for the forward, "bwd_layout" for the backward), so s/calls
  * and e/calls place the stage on the call's timeline across streams.
  */
 msm_status msm_plan_set_profiling(msm_plan plan, int enable);

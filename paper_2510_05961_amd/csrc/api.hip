@@ -198,6 +198,8 @@ msm_status upload_plan(msm_plan P) {
   if ((st = hip_alloc(P, (void**)&P->rank, nmax * sizeof(int)))) return st;
   if ((st = hip_alloc(P, (void**)&P->counts, (size_t)P->ncell * kCountCopies * sizeof(int))))
     return st;
+  // zero on entry to every binning (the cluster layout clears them after use)
+  if (hipMemset(P->counts, 0, (size_t)P->ncell * kCountCopies * sizeof(int))) return MSM_ERR_HIP;
   if ((st = hip_alloc(P, (void**)&P->start, (size_t)(P->ncell + 1) * sizeof(int)))) return st;
   if ((st = hip_alloc(P, (void**)&P->perm, nmax * sizeof(int)))) return st;
   if ((st = hip_alloc(P, &P->wrapped, nmax * 4 * sizeof(T)))) return st;
@@ -454,21 +456,15 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
     save_e1 = (T*)(b + w.e1);
   }
   StageProfiler& pf = P->prof;
-  // clear accumulators with one kernel (not a memset: graph-safe)
-  int ev = pf.begin("fill", s);
-  {
-    ZeroJobs z;
-    z.n = 0;
-    z.ptr[z.n] = P->counts;
-    z.words[z.n++] = (long long)P->ncell * kCountCopies;
-    z.ptr[z.n] = P->qg[0];
-    z.words[z.n++] = hp.lev[0].G * (long long)(sizeof(T) / 4);
-    z.ptr[z.n] = energy;
-    z.words[z.n++] = 2;
-    grid_zero_jobs<T>(P, z);
-    launch_zero_multi(z, s);
-  }
-  pf.end(ev, s);
+  // accumulators of the pass, cleared by the binning's scatter (a kernel,
+  // not a memset: graph-safe); the cell counters are zero on entry
+  ZeroJobs z;
+  z.n = 0;
+  z.ptr[z.n] = P->qg[0];
+  z.words[z.n++] = hp.lev[0].G * (long long)(sizeof(T) / 4);
+  z.ptr[z.n] = energy;
+  z.words[z.n++] = 2;
+  grid_zero_jobs<T>(P, z);
 
   // a1 binning (cell counts, scans of cell starts and cluster offsets,
   // scatter), then Morton order inside cells and the 8-particle clusters
@@ -479,13 +475,14 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
     bp.nc[k] = hp.nc[k];
     bp.per[k] = hp.periodic[k];
   }
-  ev = pf.begin("bin", s);
+  int ev = pf.begin("bin", s);
   launch_binning<T>(n, pos, q, bp, P->ncell, P->cell_of, P->rank, P->counts,
-                    (vec4_t<T>*)P->wrapped, start, P->cl_start, sorted, perm, P->flag, s);
+                    (vec4_t<T>*)P->wrapped, start, P->cl_start, sorted, perm, P->flag, z, s);
   pf.end(ev, s);
   ev = pf.begin("cluster", s);
   launch_cluster_layout<T>(1, 0, P->ncell, start, P->cl_start, bp, (const vec4_t<T>*)P->wrapped,
-                           sorted, perm, (vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cbox, P->cinfo, s);
+                           sorted, perm, (vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cbox, P->cinfo,
+                           P->counts, s);
   pf.end(ev, s);
 
   // a2 short-range pairs (8 x 8 cluster pairs), on its own stream: it only
@@ -565,7 +562,7 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
     }
     launch_cluster_layout<T>(0, 1, P->ncell, start, P->cl_start, bp, nullptr,
                              const_cast<vec4_t<T>*>(sorted), const_cast<int*>(perm),
-                             (vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cbox, P->cinfo, s);
+                             (vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cbox, P->cinfo, nullptr, s);
   }
   pf.end(ev, s);
   // the pair-sum VJP beside the grid part (as in the forward)

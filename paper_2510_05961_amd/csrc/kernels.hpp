@@ -78,15 +78,6 @@ struct OmegaPass {
   double omega[25];
 };
 
-// Binning: counts (kCountCopies counters per cell, ncell * kCountCopies
-// ints), the scans of cell starts and cluster offsets (cl_start), and the
-// scatter into cell order.
-constexpr int kCountCopies = 8;
-template <typename T>
-void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
-                    int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
-                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag, hipStream_t s);
-
 // Zero several buffers (sizes in 4-byte words) with one launch.
 constexpr int kZeroJobs = 24;
 struct ZeroJobs {
@@ -95,6 +86,18 @@ struct ZeroJobs {
   int n;
 };
 void launch_zero_multi(const ZeroJobs& jobs, hipStream_t s);
+
+// Binning: counts (kCountCopies counters per cell, ncell * kCountCopies
+// ints, zero on entry), the scans of cell starts and cluster offsets
+// (cl_start), and the scatter into cell order, which also clears the
+// buffers in `zero`.  The counts are left holding slot bases; the cluster
+// layout's kernel sets them back to zero for the next binning.
+constexpr int kCountCopies = 8;
+template <typename T>
+void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
+                    int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
+                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag,
+                    const ZeroJobs& zero, hipStream_t s);
 // Cluster layout of the cell-sorted particles (sort != 0: also reorders each
 // cell along a Morton curve, in place) and the short-range pair sum over 8 x 4
 // blocks (an i-cluster against a j-group, half a cluster).  Buffers hold
@@ -109,7 +112,7 @@ template <typename T>
 void launch_cluster_layout(int sort, int scan, int ncell, const int* start, int* cl_start,
                            const BinParams<T>& bp, const vec4_t<T>* wrapped, vec4_t<T>* sorted,
                            int* perm, vec4_t<T>* cpos, vec4_t<T>* cbox, int4* cinfo,
-                           hipStream_t s);
+                           int* counts, hipStream_t s);
 template <typename T>
 void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
                     const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,

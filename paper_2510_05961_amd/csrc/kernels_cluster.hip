@@ -71,10 +71,13 @@ __global__ void __launch_bounds__(kPrepThreads)
                    BinParams<T> bp, const vec4_t<T>* __restrict__ wrapped,
                    vec4_t<T>* __restrict__ sorted, int* __restrict__ perm,
                    vec4_t<T>* __restrict__ cpos, vec4_t<T>* __restrict__ cbox,
-                   int4* __restrict__ cinfo) {
+                   int4* __restrict__ cinfo, int* __restrict__ counts) {
   __shared__ unsigned long long key[kPrepSortMax];
   const int cell = blockIdx.x;
   const int t = threadIdx.x;
+  // the binning's counters of this cell (read by the scatter, which ran
+  // before this kernel) go back to zero for the next binning
+  if (counts && t < kCountCopies) counts[cell * kCountCopies + t] = 0;
   const int beg = start[cell], cnt = start[cell + 1] - beg;
   const int cbeg = cl_start[cell], ncl = cl_start[cell + 1] - cbeg;
   if (cnt == 0) return;
@@ -496,11 +499,11 @@ template <typename T>
 void launch_cluster_layout(int sort, int scan, int ncell, const int* start, int* cl_start,
                            const BinParams<T>& bp, const vec4_t<T>* wrapped, vec4_t<T>* sorted,
                            int* perm, vec4_t<T>* cpos, vec4_t<T>* cbox, int4* cinfo,
-                           hipStream_t s) {
+                           int* counts, hipStream_t s) {
   if (ncell <= 0) return;
   if (scan) hipLaunchKernelGGL(k_cluster_scan, dim3(1), dim3(1024), 0, s, ncell, start, cl_start);
   hipLaunchKernelGGL(k_cluster_prep<T>, dim3(ncell), dim3(kPrepThreads), 0, s, sort, start,
-                     cl_start, bp, wrapped, sorted, perm, cpos, cbox, cinfo);
+                     cl_start, bp, wrapped, sorted, perm, cpos, cbox, cinfo, counts);
 }
 
 int cluster_capacity(int n, int ncell) { return n / 8 + ncell + 1; }
@@ -539,7 +542,7 @@ void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4
 #define MSM_INST_CLUSTER(T)                                                                    \
   template void launch_cluster_layout<T>(int, int, int, const int*, int*, const BinParams<T>&, \
                                          const vec4_t<T>*, vec4_t<T>*, int*, vec4_t<T>*,       \
-                                         vec4_t<T>*, int4*, hipStream_t);                      \
+                                         vec4_t<T>*, int4*, int*, hipStream_t);                \
   template void launch_pair_cl<T>(int, int, int, const int*, const vec4_t<T>*,                 \
                                   const vec4_t<T>*, const int4*, const PairParams<T>&, int,    \
                                   double*, T*, hipStream_t);                                   \

@@ -138,12 +138,20 @@ void launch_zero_multi(const ZeroJobs& jobs, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_multi, dim3((unsigned)nb), dim3(256), 0, s, jobs);
 }
 
+// Scatter to cell order; the same threads also clear the accumulators of
+// the rest of the pass (zero: up to kZeroJobs buffers of 4-byte words).
 template <typename T>
 __global__ void k_bin_scatter(int n, const int* __restrict__ cell_of, const int* __restrict__ rank,
                               const int* __restrict__ slot_base,
                               const vec4_t<T>* __restrict__ wrapped,
-                              vec4_t<T>* __restrict__ sorted, int* __restrict__ perm) {
+                              vec4_t<T>* __restrict__ sorted, int* __restrict__ perm,
+                              ZeroJobs zero) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (int j = 0; j < zero.n; ++j) {
+    unsigned* p = reinterpret_cast<unsigned*>(zero.ptr[j]);
+    for (long long k = i; k < zero.words[j]; k += stride) p[k] = 0u;
+  }
   if (i >= n) return;
   const int dst = slot_base[cell_of[i]] + rank[i];
   sorted[dst] = wrapped[i];
@@ -376,7 +384,8 @@ __global__ void __launch_bounds__(256)
 template <typename T>
 void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
                     int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
-                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag, hipStream_t s) {
+                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag,
+                    const ZeroJobs& zero, hipStream_t s) {
   const int nb = (n + 255) / 256;
   if (n > 0)
     hipLaunchKernelGGL(k_bin_count<T>, dim3(nb), dim3(256), 0, s, n, pos, q, bp, cell_of, rank,
@@ -384,7 +393,9 @@ void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ncell, counts, start, cl_start);
   if (n > 0)
     hipLaunchKernelGGL(k_bin_scatter<T>, dim3(nb), dim3(256), 0, s, n, cell_of, rank, counts,
-                       wrapped, sorted, perm);
+                       wrapped, sorted, perm, zero);
+  else
+    launch_zero_multi(zero, s);
 }
 
 template <typename T>
@@ -420,7 +431,7 @@ void launch_interp(int p, int n, const vec4_t<T>* sorted, const int* perm, const
 #define MSM_INST_PARTICLES(T)                                                                    \
   template void launch_binning<T>(int, const T*, const T*, const BinParams<T>&, int, int*, int*, \
                                   int*, vec4_t<T>*, int*, int*, vec4_t<T>*, int*, int*,         \
-                                  hipStream_t);                                                 \
+                                  const ZeroJobs&, hipStream_t);                                \
   template void launch_anterp<T>(int, int, int, const int*, const CellGrid&, const vec4_t<T>*,   \
                                  const GridDev<T>&, T*, hipStream_t);                             \
   template void launch_interp<T>(int, int, const vec4_t<T>*, const int*, const GridDev<T>&,      \

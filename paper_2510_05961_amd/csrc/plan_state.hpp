@@ -30,7 +30,7 @@ struct StageProfiler {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, std::pair<double, long>> total;
-  // start and end of each stage after the first stage of its call ("fill" in
+  // start and end of each stage after the first stage of its call ("bin" in
   // the forward, "bwd_layout" in the backward), summed like total
   std::map<std::string, std::pair<double, double>> offsets;
   hipEvent_t get() {
@@ -64,7 +64,7 @@ struct StageProfiler {
     hipEvent_t anchor = nullptr;
     for (auto& p : pending) {
       float ms = 0.f;
-      if (p.stage == "fill" || p.stage == "bwd_layout") anchor = p.a;
+      if (p.stage == "bin" || p.stage == "bwd_layout") anchor = p.a;
       if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
         auto& t = total[p.stage];
         t.first += ms;

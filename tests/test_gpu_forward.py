@@ -264,9 +264,9 @@ def test_profile_stage_filter():
     plan.set_profiling(False)
     prof = plan.profile(reset=True)
     assert {"bin", "pair", "anterp", "conv_l1", "interp"} <= set(prof)
-    # timeline offsets after the call's first stage: the call starts with the
-    # clear, binning precedes anterpolation, interpolation comes last
-    assert prof["fill"]["start_ms"] == 0.0
+    # timeline offsets after the call's first stage: the call starts with
+    # binning, which precedes anterpolation; interpolation comes last
+    assert prof["bin"]["start_ms"] == 0.0
     assert all(0.0 <= v["start_ms"] <= v["end_ms"] for v in prof.values())
     assert prof["bin"]["end_ms"] <= prof["anterp"]["start_ms"]
     assert prof["interp"]["start_ms"] >= max(prof["pair"]["end_ms"], prof["conv_l1"]["end_ms"])
