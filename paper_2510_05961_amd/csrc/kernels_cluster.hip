@@ -26,6 +26,7 @@ constexpr int kGroup = kGroupSize;    // particles per j-group (half a cluster)
 constexpr int kSlots = 64 / (8 * kGroup);  // j-groups per wave step
 constexpr int kPrepThreads = 256;
 constexpr int kPrepSortMax = 4096;    // cells larger than this keep their order
+constexpr int kSmallCell = 128;       // cells up to this size are staged in LDS
 
 // Cluster offsets: cl_start[c] = sum_{c' < c} ceil(count_c' / 8), one workgroup.
 __global__ void __launch_bounds__(1024) k_cluster_scan(int ncell, const int* __restrict__ start,
@@ -84,24 +85,111 @@ __global__ void __launch_bounds__(kPrepThreads)
   const int cx = cell % bp.nc[0];
   const int cy = (cell / bp.nc[0]) % bp.nc[1];
   const int cz = cell / (bp.nc[0] * bp.nc[1]);
+  const T lo3[3] = {(T)cx * bp.cs[0], (T)cy * bp.cs[1], (T)cz * bp.cs[2]};
+  auto morton = [&](const vec4_t<T>& v) {
+    const T x[3] = {v.x, v.y, v.z};
+    unsigned m = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int s = (int)((x[d] - lo3[d]) * (T(16) / bp.cs[d]));
+      s = s < 0 ? 0 : (s > 15 ? 15 : s);
+      m |= spread3((unsigned)s) << d;
+    }
+    return m;
+  };
+  if (cnt <= kSmallCell) {
+    // the whole cell in LDS: one read of the cell list, a sort in the
+    // registers of one wave (lane t holds elements t and t + 64 of a bitonic
+    // network over 128 slots, sentinels ~0 past cnt), then every output is
+    // written from LDS
+    __shared__ vec4_t<T> part[kSmallCell];
+    __shared__ int pidx[kSmallCell];
+    for (int i = t; i < cnt; i += kPrepThreads) {
+      part[i] = sorted[beg + i];
+      pidx[i] = perm[beg + i];
+    }
+    __syncthreads();
+    const bool sorting = sort && cnt > 1;
+    if (sorting) {
+      if (t < 64) {
+        // key: Morton code | caller's index | position in the cell
+        auto key_of = [&](int i) -> unsigned long long {
+          if (i >= cnt) return ~0ull;
+          return ((unsigned long long)morton(part[i]) << 44) |
+                 ((unsigned long long)(unsigned)pidx[i] << 12) | (unsigned long long)i;
+        };
+        unsigned long long e0 = key_of(t), e1 = key_of(t + 64);
+        for (int k = 2; k <= 128; k <<= 1) {
+          for (int j = k >> 1; j > 0; j >>= 1) {
+            // element i keeps the smaller of (i, i ^ j) when "i is the lower
+            // index" equals "the block of size k ascends", else the larger
+            const bool up0 = (t & k) == 0, up1 = ((t + 64) & k) == 0;
+            if (j == 64) {
+              const unsigned long long a = e0 < e1 ? e0 : e1, b = e0 < e1 ? e1 : e0;
+              e0 = up0 ? a : b;
+              e1 = up1 ? b : a;
+            } else {
+              const unsigned long long p0 = __shfl_xor(e0, j), p1 = __shfl_xor(e1, j);
+              const bool lower = (t & j) == 0;
+              e0 = (lower == up0) ? (e0 < p0 ? e0 : p0) : (e0 < p0 ? p0 : e0);
+              e1 = (lower == up1) ? (e1 < p1 ? e1 : p1) : (e1 < p1 ? p1 : e1);
+            }
+          }
+        }
+        key[t] = e0;
+        key[t + 64] = e1;
+      }
+      __syncthreads();
+    }
+    auto src_of = [&](int slot) { return sorting ? (int)(key[slot] & 0xFFFu) : slot; };
+    for (int s = t; s < ncl * 8; s += kPrepThreads) {
+      vec4_t<T> v;
+      if (s < cnt) {
+        const int q = src_of(s);
+        v = part[q];
+        if (sorting) {
+          sorted[beg + s] = v;
+          perm[beg + s] = pidx[q];
+        }
+      } else {  // padding: a zero charge far outside every cutoff
+        v.x = v.y = v.z = T(1e15);
+        v.w = T(0);
+      }
+      cpos[(size_t)cbeg * 8 + s] = v;
+    }
+    for (int h = t; h < 2 * ncl; h += kPrepThreads) {
+      const int m = min(kGroup, cnt - kGroup * h);
+      vec4_t<T> lo, hi;
+      if (m <= 0) {
+        lo.x = lo.y = lo.z = T(1e15);
+        lo.w = T(0);
+        hi = lo;
+      } else {
+        lo = part[src_of(kGroup * h)];
+        hi = lo;
+        for (int r = 1; r < m; ++r) {
+          const vec4_t<T> v = part[src_of(kGroup * h + r)];
+          lo.x = min(lo.x, v.x);
+          lo.y = min(lo.y, v.y);
+          lo.z = min(lo.z, v.z);
+          hi.x = max(hi.x, v.x);
+          hi.y = max(hi.y, v.y);
+          hi.z = max(hi.z, v.z);
+        }
+      }
+      cbox[2 * (2 * (size_t)cbeg + h)] = lo;
+      cbox[2 * (2 * (size_t)cbeg + h) + 1] = hi;
+    }
+    for (int c = t; c < ncl; c += kPrepThreads)
+      cinfo[cbeg + c] = make_int4(beg + 8 * c, min(8, cnt - 8 * c), cell, 0);
+    return;
+  }
   if (sort && cnt > 1 && cnt <= kPrepSortMax) {
     int npow = 1;
     while (npow < cnt) npow <<= 1;
-    const T lo[3] = {(T)cx * bp.cs[0], (T)cy * bp.cs[1], (T)cz * bp.cs[2]};
     for (int i = t; i < npow; i += kPrepThreads) {
       unsigned long long k = ~0ull;
-      if (i < cnt) {
-        const vec4_t<T> v = sorted[beg + i];
-        const T x[3] = {v.x, v.y, v.z};
-        unsigned m = 0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          int s = (int)((x[d] - lo[d]) * (T(16) / bp.cs[d]));
-          s = s < 0 ? 0 : (s > 15 ? 15 : s);
-          m |= spread3((unsigned)s) << d;
-        }
-        k = ((unsigned long long)m << 32) | (unsigned)perm[beg + i];
-      }
+      if (i < cnt) k = ((unsigned long long)morton(sorted[beg + i]) << 32) | (unsigned)perm[beg + i];
       key[i] = k;
     }
     __syncthreads();
