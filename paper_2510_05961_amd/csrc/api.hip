@@ -485,7 +485,7 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
                            P->counts, s);
   pf.end(ev, s);
 
-  // a2 short-range pairs (8 x 8 cluster pairs), on its own stream: it only
+  // a2 short-range pairs (8 x 4 blocks), on its own stream: it only
   // needs the cluster layout, and interpolation waits for it
   const bool dag = use_streams();
   hipStream_t sp = dag ? P->sc : s;

@@ -1,6 +1,5 @@
 // conv_tile.hpp -- the inner loop of the stencil convolution (eq.
-// action_of_K_as_convolution), shared by the single-system and the batched
-// convolution kernels.
+// action_of_K_as_convolution) over one stencil plane.
 #pragma once
 
 #include "kernels.hpp"

@@ -62,10 +62,15 @@ __device__ inline unsigned spread3(unsigned v) {  // 4 bits -> every third bit
   return v;
 }
 
-// One workgroup per cell.  With sort != 0 the cell's particles are reordered
-// in place (sorted[], perm[] of the segment; positions re-read from wrapped[]
-// in the caller's order); the cluster slots, boxes and info are written in
-// both modes from the (possibly new) order.
+// One workgroup per cell.  With sort != 0 the cell's particles are put in
+// Morton order of a 16^3 sub-grid, ties broken by the caller's index, in
+// place (sorted[], perm[] of the segment).  Cells of up to kSmallCell
+// particles are staged in LDS and sorted in one wave's registers; larger
+// ones are sorted in LDS and their positions re-read from wrapped[] in the
+// caller's order; cells larger than kPrepSortMax keep the cell order.  The
+// cluster slots, j-group boxes and cluster info are written in both modes
+// from the (possibly new) order, and the cell's binning counters are set
+// back to zero (counts != nullptr).
 template <typename T>
 __global__ void __launch_bounds__(kPrepThreads)
     k_cluster_prep(int sort, const int* __restrict__ start, const int* __restrict__ cl_start,
