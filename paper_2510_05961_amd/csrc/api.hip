@@ -233,7 +233,11 @@ msm_status upload_plan(msm_plan P) {
       hipStreamCreateWithFlags(&P->sd, hipStreamNonBlocking))
     return MSM_ERR_HIP;
   for (auto& e : P->ev)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming)) return MSM_ERR_HIP;
+    // fork/join events between this plan's streams on one GPU: no timing and
+    // no system-scope fence (nothing on the host or another device waits on
+    // them; the streams share the device's caches)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence))
+      return MSM_ERR_HIP;
   if (hipDeviceSynchronize()) return MSM_ERR_HIP;
   return MSM_OK;
 }
