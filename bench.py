@@ -148,6 +148,71 @@ def _batched_vs_plain(torch, msm, WL, np):
             "batched_over_plain": round((ntot / t_b) / (n_sub / t_p), 2)}
 
 
+def _grid_pass_sweep(torch, msm, steps):
+    """HBM rate of the grid passes (anterpolation, restriction, prolongation,
+    interpolation) on level-1 grids of 128^3 to 512^3 points and 1e7 to 6e7
+    charges: periodic cube of edge n1 h (h = 1), uniform random positions,
+    charges +-1 in equal numbers, FP32, p = 4, a = 3, levels down to an 8^3
+    top grid.  Every stage runs on one stream (no overlap), timed by the
+    plan's stage events; algorithmic bytes per pass count 4-byte grid values
+    and 16 bytes (position + charge) per charge read or (force + potential)
+    written:
+      anterpolation  16 N + 4 G1
+      restriction    sum_l 4 (G_l + G_l+1)
+      prolongation   sum_l 4 (G_l+1 + 2 G_l)
+      interpolation  16 N + 4 G1 + 16 N
+    (6e7 is near the largest count an FP32 plan accepts: its cluster buffers
+    use 32-bit byte offsets.)"""
+    cases = [(128, 10_000_000), (256, 10_000_000), (512, 10_000_000), (512, 60_000_000)]
+    dev = torch.device("cuda:0")
+    out = []
+    os.environ["MSM_STREAMS"] = "0"
+    try:
+        for n1, n in cases:
+            g = torch.Generator(device=dev)
+            g.manual_seed(1000 + n1 + n // 1_000_000)
+            box = float(n1)
+            L = (n1 // 8).bit_length()  # top grid 8^3
+            P = torch.rand((n, 3), generator=g, device=dev, dtype=torch.float32) * box
+            Q = torch.ones(n, dtype=torch.float32, device=dev)
+            Q[torch.randperm(n, generator=g, device=dev)[: n // 2]] = -1.0
+            plan = msm.Plan((box,) * 3, 7, 4, 1.0, 3.0, L, msm.MSM_FP32, n)
+            lev = plan.describe()["levels_info"]
+            G = [li["n"][0] * li["n"][1] * li["n"][2] for li in lev]
+            E = torch.empty(1, dtype=torch.float64, device=dev)
+            F = torch.empty((n, 3), dtype=torch.float32, device=dev)
+            dq = torch.empty(n, dtype=torch.float32, device=dev)
+            plan.energy_forces(P, Q, out=(E, F, dq))
+            torch.cuda.synchronize()
+            if plan.status() != 0:
+                raise RuntimeError("device error flag set in the grid-pass sweep")
+            names = ["anterp", "restrict", "prolong", "interp"]
+            plan.set_profile_stages(names)
+            plan.profile(reset=True)
+            plan.set_profiling(True)
+            for _ in range(steps):
+                plan.energy_forces(P, Q, out=(E, F, dq))
+            torch.cuda.synchronize()
+            plan.set_profiling(False)
+            prof = plan.profile(reset=True)
+            alg = {"anterp": 16 * n + 4 * G[0],
+                   "restrict": sum(4 * (G[l] + G[l + 1]) for l in range(L - 1)),
+                   "prolong": sum(4 * (G[l + 1] + 2 * G[l]) for l in range(L - 1)),
+                   "interp": 32 * n + 4 * G[0]}
+            rec = {"grid1": [n1] * 3, "n": n, "levels": L}
+            for k in names:
+                ms = prof[k]["ms"] / steps
+                gbs = alg[k] / (ms * 1e-3) / 1e9
+                rec[k] = {"ms": round(ms, 4), "bytes": alg[k], "GBps": round(gbs, 1),
+                          "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+            out.append(rec)
+            del plan, P, Q, E, F, dq
+            torch.cuda.empty_cache()
+    finally:
+        del os.environ["MSM_STREAMS"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,6 +225,10 @@ def main():
     ap.add_argument("--standalone", action="store_true",
                     help="after the timed region, time every stage with all kernels on one "
                          "stream (no overlap) and report those durations too")
+    ap.add_argument("--grid-sweep", action="store_true",
+                    help="also time the grid passes on 128^3-512^3 level-1 grids with 1e7-6e7 "
+                         "charges (HBM fraction of anterpolation, restriction, prolongation, "
+                         "interpolation)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, one device-to-device copy of this many MiB "
                          "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -212,6 +281,19 @@ def main():
     dt = t1 - t0
     ms_per_step = dt / args.steps * 1e3
     value = n * args.steps / dt
+
+    # the cell-list build (binning and the cluster layout) opens every call on
+    # the caller's stream before any other stage can start; the paper's timings
+    # leave the neighbour list out, so the step is also reported without it
+    plan.set_profile_stages(["bin", "cluster"])
+    plan.set_profiling(True)
+    for _ in range(args.steps):
+        plan.energy_forces(P, Q, out=out)
+    torch.cuda.synchronize()
+    plan.set_profiling(False)
+    nl = plan.profile(reset=True)
+    nl_ms = (nl["cluster"]["end_ms"] / max(nl["cluster"]["launches"], 1)
+             if "cluster" in nl else 0.0)
 
     standalone = None
     if args.standalone:
@@ -286,6 +368,8 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "pairs_in_cutoff": npairs,
+        "neighbour_list_ms": round(nl_ms, 4),
+        "ms_per_step_excluding_neighbour_list": round(ms_per_step - nl_ms, 4),
     }
     if standalone:
         result["stages_ms_standalone"] = {k: round(v, 5) for k, v in standalone.items()}
@@ -299,6 +383,9 @@ def main():
         torch.cuda.synchronize()
         result["calib_copy_bytes"] = nb
         del src, dst
+
+    if args.grid_sweep:
+        result["grid_pass_sweep"] = _grid_pass_sweep(torch, msm, max(args.steps // 10, 3))
 
     if not args.no_extras:
         result["autograd"] = _autograd_vs_plain(torch, msm, WL, np)
