@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "brick.hpp"
 #include "kernels.hpp"
 
 namespace msm {
@@ -37,37 +38,32 @@ __global__ void k_gather_v(int n, const int* __restrict__ perm, const T* __restr
 }
 
 // The dipole grid in the brick form of the forward anterpolation: one
-// workgroup per cell, 64-bit fixed-point sums in LDS (exact integer adds; the
+// workgroup per super-cell (as in the forward), 64-bit fixed-point sums in LDS (exact integer adds; the
 // power-of-two scale bounds every sum by 2^62, since |contribution| <=
 // |q| (|vx| + |vy| + |vz|) max(1/h) for B-spline weights in [0, 1] and
-// derivatives in [-1/h, 1/h]), then one atomic per non-zero point.  Cells
-// whose brick exceeds brick_cap points fall back to per-particle atomics.
+// derivatives in [-1/h, 1/h]), then one atomic per non-zero point.  Bricks
+// larger than brick_cap points fall back to per-particle atomics.
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
     k_anterp_dipole_brick(const int* __restrict__ start, const vec4_t<T>* __restrict__ sorted,
                           const vec4_t<T>* __restrict__ v, GridDev<T> g, CellGrid cg,
-                          int brick_cap, T* __restrict__ grid) {
+                          BrickGeom bg, int brick_cap, T* __restrict__ grid) {
   extern __shared__ long long brick[];
   __shared__ double bsum[4];
-  const int cell = blockIdx.x;
-  const int beg = start[cell], end = start[cell + 1];
-  if (beg == end) return;
-  const int cc[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
+  __shared__ BrickRuns runs;
+  int c0[3], c1[3], nruns;
+  const int count = brick_runs(blockIdx.x, start, cg, bg, c0, c1, runs, nruns);
+  if (count == 0) return;
   int lo[3], ext[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    lo[k] = (int)floor(cc[k] * cg.cs[k] / g.hd[k]) - P / 2 - 1;
-    const int hi = (int)floor((cc[k] + 1) * cg.cs[k] / g.hd[k]) + P / 2 + 1;
-    ext[k] = hi - lo[k] + 1;
-  }
-  const int vol = ext[0] * ext[1] * ext[2];
+  const int vol = brick_box<P>(c0, c1, cg, g.hd, lo, ext);
   const bool staged = vol <= brick_cap;
   const double ih[3] = {1.0 / g.hd[0], 1.0 / g.hd[1], 1.0 / g.hd[2]};
   double scale = 1.0;
   if (staged) {
     for (int b = threadIdx.x; b < vol; b += blockDim.x) brick[b] = 0;
     double bound = 0.0;
-    for (int i = beg + (int)threadIdx.x; i < end; i += blockDim.x) {
+    for (int j = threadIdx.x; j < count; j += blockDim.x) {
+      const int i = brick_particle(runs, nruns, j);
       const vec4_t<T> vi = v[i];
       bound += fabs((double)sorted[i].w) *
                (fabs((double)vi.x) + fabs((double)vi.y) + fabs((double)vi.z));
@@ -80,7 +76,8 @@ __global__ void __launch_bounds__(256)
     (void)frexp((bsum[0] + bsum[1] + bsum[2] + bsum[3]) * fmax(ih[0], fmax(ih[1], ih[2])), &ex);
     scale = ldexp(1.0, 62 - max(ex, -900));
   }
-  for (int i = beg + (int)threadIdx.x; i < end; i += blockDim.x) {
+  for (int jp = threadIdx.x; jp < count; jp += blockDim.x) {
+    const int i = brick_particle(runs, nruns, jp);
     const vec4_t<T> pi = sorted[i];
     const vec4_t<T> vi = v[i];
     const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
@@ -293,14 +290,14 @@ void launch_anterp_dipole(int p, int n, int ncell, const int* start, const CellG
                           const vec4_t<T>* sorted, const vec4_t<T>* v, const GridDev<T>& g,
                           T* grid, hipStream_t s) {
   if (n <= 0) return;
-  long long cap = 1;  // as in launch_anterp
-  for (int k = 0; k < 3; ++k) cap *= (long long)std::ceil(cg.cs[k] / g.hd[k]) + p + 4;
-  const int bc = (int)std::min<long long>(cap, 8192);
+  const BrickGeom bg = brick_geom(p, n, ncell, cg, g.hd);
+  const int bc = brick_lds_cap(p, bg, cg, g.hd);
   const size_t lds = (size_t)bc * sizeof(long long);
+  const unsigned nb = (unsigned)bg.nsc[0] * bg.nsc[1] * bg.nsc[2];
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 4>), dim3(ncell), dim3(256), lds, s, start, sorted, v, g, cg, bc, grid); break;
-    case 6: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 6>), dim3(ncell), dim3(256), lds, s, start, sorted, v, g, cg, bc, grid); break;
-    case 8: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 8>), dim3(ncell), dim3(256), lds, s, start, sorted, v, g, cg, bc, grid); break;
+    case 4: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 4>), dim3(nb), dim3(256), lds, s, start, sorted, v, g, cg, bg, bc, grid); break;
+    case 6: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 6>), dim3(nb), dim3(256), lds, s, start, sorted, v, g, cg, bg, bc, grid); break;
+    case 8: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 8>), dim3(nb), dim3(256), lds, s, start, sorted, v, g, cg, bg, bc, grid); break;
   }
 }
 

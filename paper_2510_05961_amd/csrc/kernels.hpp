@@ -122,6 +122,20 @@ struct CellGrid {
   int nc[3];
   double cs[3];
 };
+// Cells of one anterpolation brick: kc^3 cells of the cell list (a
+// super-cell), nsc super-cells per axis.  Sparse cells share a brick so
+// that the brick's clearing and flushing stay below the work of its charges.
+struct BrickGeom {
+  int kc;
+  int nsc[3];
+};
+constexpr int kBrickMaxCells = 8;  // kc limit (kc^2 runs of cells per brick)
+// kc for a call with n charges: BrickGeom of the cell grid (MSM_BRICK_CELLS=k
+// forces k, as far as the brick still fits).
+BrickGeom brick_geom(int p, int n, int ncell, const CellGrid& cg, const double hd[3]);
+// LDS elements of the bricks of this geometry (at most kBrickMax)
+int brick_lds_cap(int p, const BrickGeom& bg, const CellGrid& cg, const double hd[3]);
+constexpr int kBrickMax = 8192;  // largest brick in LDS (64 KB)
 template <typename T>
 void launch_anterp(int p, int n, int ncell, const int* start, const CellGrid& cg,
                    const vec4_t<T>* sorted, const GridDev<T>& g, T* grid, hipStream_t s);

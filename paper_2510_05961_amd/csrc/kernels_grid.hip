@@ -2,6 +2,7 @@
 // and the per-level stencil convolution (also used for the dense top level).
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "conv_tile.hpp"
 #include "kernels.hpp"
@@ -14,6 +15,18 @@ struct JTaps {
 };
 
 __device__ inline int floor_div2(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+
+// Prolongation tap t of a fine point m whose first coarse point is
+// nl = ceil((m - P/2)/2): J_{m - 2(nl + t)}.  With e = (m - P/2) mod 2 that is
+// entry P - e - 2t of the table (zero when negative), so the unrolled t and
+// the parity select the tap without a run-time index into the by-value table
+// (which would put the table in memory and add a load per tap).
+template <typename T, int P>
+__device__ inline T prolong_tap(const JTaps<T>& jt, int e, int t) {
+  const T even = jt.J[P - 2 * t];
+  const T odd = (P - 1 - 2 * t >= 0) ? jt.J[max(P - 1 - 2 * t, 0)] : T(0);
+  return e ? odd : even;
+}
 
 // ---------------------------------------------------------------------------
 // a4: restriction (eq. restriction_prolongation_explicit_formulas, first line)
@@ -116,26 +129,22 @@ __global__ void __launch_bounds__(256)
   for (int i = threadIdx.x; i < W * W * B; i += blockDim.x) {
     const int x = i % B, yz = i / B;
     const int m = m0[0] + x;
-    const int nl = -floor_div2(-(m - P / 2));
+    const int nl = -floor_div2(-(m - P / 2)), e = (m - P / 2) & 1;
     T sx = T(0);
 #pragma unroll
-    for (int t = 0; t < P / 2 + 1; ++t) {
-      const int kk = m - 2 * (nl + t);
-      if (kk >= -P / 2) sx += jt.J[kk + P / 2] * C[yz * W + (nl + t - n0[0])];
-    }
+    for (int t = 0; t < P / 2 + 1; ++t)
+      sx += prolong_tap<T, P>(jt, e, t) * C[yz * W + (nl + t - n0[0])];
     X1[i] = sx;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < W * B * B; i += blockDim.x) {
     const int x = i % B, y = (i / B) % B, z = i / (B * B);
     const int m = m0[1] + y;
-    const int nl = -floor_div2(-(m - P / 2));
+    const int nl = -floor_div2(-(m - P / 2)), e = (m - P / 2) & 1;
     T sy = T(0);
 #pragma unroll
-    for (int t = 0; t < P / 2 + 1; ++t) {
-      const int kk = m - 2 * (nl + t);
-      if (kk >= -P / 2) sy += jt.J[kk + P / 2] * X1[(z * W + (nl + t - n0[1])) * B + x];
-    }
+    for (int t = 0; t < P / 2 + 1; ++t)
+      sy += prolong_tap<T, P>(jt, e, t) * X1[(z * W + (nl + t - n0[1])) * B + x];
     X2[i] = sy;
   }
   __syncthreads();
@@ -144,13 +153,11 @@ __global__ void __launch_bounds__(256)
     const int gx = fb[0] + x, gy = fb[1] + y, gz = fb[2] + z;
     if (gx >= f.n[0] || gy >= f.n[1] || gz >= f.n[2]) continue;
     const int m = m0[2] + z;
-    const int nl = -floor_div2(-(m - P / 2));
+    const int nl = -floor_div2(-(m - P / 2)), e = (m - P / 2) & 1;
     T s = T(0);
 #pragma unroll
-    for (int t = 0; t < P / 2 + 1; ++t) {
-      const int kk = m - 2 * (nl + t);
-      if (kk >= -P / 2) s += jt.J[kk + P / 2] * X2[((nl + t - n0[2]) * B + y) * B + x];
-    }
+    for (int t = 0; t < P / 2 + 1; ++t)
+      s += prolong_tap<T, P>(jt, e, t) * X2[((nl + t - n0[2]) * B + y) * B + x];
     const long long fi = ((long long)gz * f.n[1] + gy) * f.n[0] + gx;
     if (ef64) ef[fi] = (T)ef64[fi] + s;
     else ef[fi] += s;
@@ -359,13 +366,266 @@ static JTaps<T> make_taps(const double* J, int p) {
   return jt;
 }
 
+// Large grids: streaming forms of the two passes.  A workgroup owns a
+// kStreamBX x kStreamBY column of output points and walks a range of output
+// planes along z.  Each input plane is staged in LDS once, filtered along x
+// and y (one value per thread), and kept in a shift register of the thread
+// for the z taps, so every input plane is read from HBM once per column
+// (plus the x-y halo) instead of once per small cube; the next plane's
+// loads are issued before the current plane's filters.  Tap orders match
+// the tiled kernels above.
+constexpr int kStreamBX = 32, kStreamBY = 8;  // 256 threads, one output column each
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+    k_restrict_stream(GridDev<T> f, GridDev<T> c, JTaps<T> jt, int zchunk,
+                      const T* __restrict__ qf, T* __restrict__ qc) {
+  constexpr int BX = kStreamBX, BY = kStreamBY;
+  constexpr int WX = 2 * BX + P - 1, WY = 2 * BY + P - 1, NW = WX * WY;
+  constexpr int NL = (NW + 255) / 256;  // window loads per thread
+  __shared__ T F[NW];
+  __shared__ T X1[WY * BX];
+  const int nbx = (c.n[0] + BX - 1) / BX, nby = (c.n[1] + BY - 1) / BY;
+  const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+  const int cx0 = bx * BX, cy0 = by * BY;
+  const int cz0 = bz * zchunk, cz1 = min(c.n[2], cz0 + zchunk);
+  if (cz0 >= cz1) return;
+  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  // absolute fine index of window element 0 in x and y, of plane 0 in z
+  const int fx0 = 2 * (cx0 + c.lo[0]) - P / 2, fy0 = 2 * (cy0 + c.lo[1]) - P / 2;
+  const int fz0 = 2 * (cz0 + c.lo[2]) - P / 2;
+  int off[NL];  // in-plane offset of each loaded window element, -1: zero
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    off[k] = -1;
+    if (e < NW) {
+      const int ix = axis_index(fx0 + e % WX, f.n[0], f.lo[0], f.per[0]);
+      const int iy = axis_index(fy0 + e / WX, f.n[1], f.lo[1], f.per[1]);
+      if (ix >= 0 && iy >= 0) off[k] = iy * f.n[0] + ix;
+    }
+  }
+  const long long plane = (long long)f.n[0] * f.n[1];
+  // Loads are unconditional (elements outside the grid read element 0 of a
+  // valid plane and are replaced by zero when staged), so every wave keeps
+  // the same number of loads in flight and the waits stay partial.
+  auto load = [&](int fz, T (&r)[NL], bool& zok) {
+    const int iz = axis_index(fz, f.n[2], f.lo[2], f.per[2]);
+    zok = iz >= 0;
+    const T* src = qf + (long long)max(iz, 0) * plane;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) r[k] = src[max(off[k], 0)];
+  };
+  // fine planes fz0 .. fz0 + np - 1 in order: after plane i >= P (i - P
+  // even) the last P + 1 planes are the z taps of coarse plane cz0 + (i - P)/2
+  const int np = 2 * (cz1 - cz0) + P - 1;
+  T ring[P + 1];
+#pragma unroll
+  for (int t = 0; t <= P; ++t) ring[t] = T(0);
+  // plane i: stage it (loaded two planes earlier), start loading plane i + 2
+  // into the same registers, filter
+  auto step = [&](int i, T (&r)[NL], bool& zok) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < NW) F[e] = (zok && off[k] >= 0) ? r[k] : T(0);
+    }
+    __syncthreads();
+    load(fz0 + min(i + 2, np - 1), r, zok);  // past the end: a spare load
+    for (int j = threadIdx.x; j < WY * BX; j += 256) {
+      const int x = j % BX, y = j / BX;
+      const T* row = F + y * WX + 2 * x;
+      T sx = T(0);
+#pragma unroll
+      for (int t = 0; t <= P; ++t) sx += jt.J[t] * row[t];
+      X1[j] = sx;
+    }
+    __syncthreads();
+    T sy = T(0);
+#pragma unroll
+    for (int t = 0; t <= P; ++t) sy += jt.J[t] * X1[(2 * ty + t) * BX + tx];
+#pragma unroll
+    for (int t = 0; t < P; ++t) ring[t] = ring[t + 1];
+    ring[P] = sy;
+    if (i >= P && ((i - P) & 1) == 0) {
+      const int gz = cz0 + (i - P) / 2, gx = cx0 + tx, gy = cy0 + ty;
+      if (gx < c.n[0] && gy < c.n[1]) {
+        T sum = T(0);
+#pragma unroll
+        for (int t = 0; t <= P; ++t) sum += jt.J[t] * ring[t];
+        qc[((long long)gz * c.n[1] + gy) * c.n[0] + gx] = sum;
+      }
+    }
+  };
+  T ra[NL], rb[NL];
+  bool za, zb;
+  load(fz0, ra, za);
+  load(fz0 + 1, rb, zb);  // np >= P + 1 >= 2
+  for (int i = 0; i < np; i += 2) {
+    step(i, ra, za);
+    if (i + 1 < np) step(i + 1, rb, zb);
+  }
+}
+
+// SC / SF: type of the coarse source and of the fine term (T, or FP64 from a
+// direct level's convolution buffer); fsrc may be ef itself (ef += ...).
+template <typename T, int P, typename SC, typename SF>
+__global__ void __launch_bounds__(256)
+    k_prolong_stream(GridDev<T> f, GridDev<T> c, JTaps<T> jt, int zchunk,
+                     const SC* __restrict__ csrc, const SF* fsrc, T* ef) {
+  constexpr int BX = kStreamBX, BY = kStreamBY;
+  constexpr int CW = BX / 2 + P / 2 + 2, CH = BY / 2 + P / 2 + 2, NC = CW * CH;
+  constexpr int NL = (NC + 255) / 256;
+  __shared__ T C[NC];
+  __shared__ T X1[CH * BX];
+  const int nbx = (f.n[0] + BX - 1) / BX, nby = (f.n[1] + BY - 1) / BY;
+  const int bx = blockIdx.x % nbx, by = (blockIdx.x / nbx) % nby, bz = blockIdx.x / (nbx * nby);
+  const int fx0 = bx * BX, fy0 = by * BY;
+  const int fz0 = bz * zchunk, fz1 = min(f.n[2], fz0 + zchunk);
+  if (fz0 >= fz1) return;
+  const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+  // absolute fine index of the column's first point; coarse window start:
+  // ceil((m - P/2)/2) of that point, per axis
+  const int mx0 = fx0 + f.lo[0], my0 = fy0 + f.lo[1];
+  const int n0x = -floor_div2(-(mx0 - P / 2)), n0y = -floor_div2(-(my0 - P / 2));
+  int off[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int e = threadIdx.x + 256 * k;
+    off[k] = -1;
+    if (e < NC) {
+      const int ix = axis_index(n0x + e % CW, c.n[0], c.lo[0], c.per[0]);
+      const int iy = axis_index(n0y + e / CW, c.n[1], c.lo[1], c.per[1]);
+      if (ix >= 0 && iy >= 0) off[k] = iy * c.n[0] + ix;
+    }
+  }
+  const long long cplane = (long long)c.n[0] * c.n[1];
+  // unconditional loads as in the restriction; sources are kept in their
+  // own type until they are used
+  SC r[NL];
+  bool rz = false;
+  auto load = [&](int nz) {
+    const int iz = axis_index(nz, c.n[2], c.lo[2], c.per[2]);
+    rz = iz >= 0;
+    const long long base = (long long)max(iz, 0) * cplane;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) r[k] = csrc[base + max(off[k], 0)];
+  };
+  // fine x and y of this thread and their first coarse point
+  const int gx = fx0 + tx, gy = fy0 + ty;
+  const bool own = gx < f.n[0] && gy < f.n[1];
+  const int my = my0 + ty, nly = -floor_div2(-(my - P / 2)), ey = (my - P / 2) & 1;
+  // coarse planes nz (absolute) in order; after plane nz the fine planes
+  // 2 nz - P/2 and 2 nz - P/2 + 1 have all their z taps: ring[j] holds the
+  // x-y filtered plane nz - j
+  const int mz_lo = fz0 + f.lo[2], mz_hi = fz1 - 1 + f.lo[2];
+  const int nz_lo = -floor_div2(-(mz_lo - P / 2)), nz_hi = floor_div2(mz_hi + P / 2);
+  T ring[P / 2 + 1];
+#pragma unroll
+  for (int j = 0; j <= P / 2; ++j) ring[j] = T(0);
+  const long long fplane = (long long)f.n[0] * f.n[1];
+  // fine values that coarse plane nz completes (planes 2 nz - P/2 and
+  // 2 nz - P/2 + 1 of this column), or 0 outside the workgroup's range
+  // (read unconditionally at a clamped index; only written points use them)
+  const long long fcol = (long long)min(gy, f.n[1] - 1) * f.n[0] + min(gx, f.n[0] - 1);
+  auto fine_load = [&](int nz, SF& v0, SF& v1) {
+    const int me = 2 * nz - P / 2;
+    const int z0 = min(max(me - f.lo[2], 0), f.n[2] - 1);
+    const int z1 = min(max(me + 1 - f.lo[2], 0), f.n[2] - 1);
+    v0 = fsrc[(long long)z0 * fplane + fcol];
+    v1 = fsrc[(long long)z1 * fplane + fcol];
+  };
+  // coarse plane nz: its fine values v0, v1 were read two planes earlier;
+  // after the outputs they are reused for plane nz + 2
+  auto step = [&](int nz, SF& v0, SF& v1) {
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < NC) C[e] = (rz && off[k] >= 0) ? (T)r[k] : T(0);
+    }
+    __syncthreads();
+    load(min(nz + 1, nz_hi));  // past the end: a spare load
+    for (int j = threadIdx.x; j < CH * BX; j += 256) {
+      const int x = j % BX, cy = j / BX;
+      const int m = mx0 + x;
+      const int nl = -floor_div2(-(m - P / 2)), e = (m - P / 2) & 1;
+      T sx = T(0);
+#pragma unroll
+      for (int t = 0; t < P / 2 + 1; ++t)
+        sx += prolong_tap<T, P>(jt, e, t) * C[cy * CW + (nl + t - n0x)];
+      X1[j] = sx;
+    }
+    __syncthreads();
+    T sy = T(0);
+#pragma unroll
+    for (int t = 0; t < P / 2 + 1; ++t)
+      sy += prolong_tap<T, P>(jt, ey, t) * X1[(nly + t - n0y) * BX + tx];
+#pragma unroll
+    for (int j = P / 2; j > 0; --j) ring[j] = ring[j - 1];
+    ring[0] = sy;
+    // coarse planes in increasing order: fine plane me takes nz - P/2 .. nz
+    // (J index 2j), plane me + 1 takes nz - P/2 + 1 .. nz (J index 2j + 1)
+    const int me = 2 * nz - P / 2;
+    const long long fi0 = (long long)(me - f.lo[2]) * fplane + (long long)gy * f.n[0] + gx;
+    if (own && me >= mz_lo && me <= mz_hi) {
+      T s0 = T(0);
+#pragma unroll
+      for (int j = P / 2; j >= 0; --j) s0 += jt.J[2 * j] * ring[j];
+      ef[fi0] = (T)v0 + s0;
+    }
+    if (own && me + 1 >= mz_lo && me + 1 <= mz_hi) {
+      T s1 = T(0);
+#pragma unroll
+      for (int j = P / 2 - 1; j >= 0; --j) s1 += jt.J[2 * j + 1] * ring[j];
+      ef[fi0 + fplane] = (T)v1 + s1;
+    }
+    fine_load(nz + 2, v0, v1);  // past the end: a spare load
+  };
+  SF va0, va1, vb0, vb1;
+  load(nz_lo);
+  fine_load(nz_lo, va0, va1);
+  fine_load(nz_lo + 1, vb0, vb1);
+  for (int nz = nz_lo; nz <= nz_hi; nz += 2) {
+    step(nz, va0, va1);
+    if (nz + 1 <= nz_hi) step(nz + 1, vb0, vb1);
+  }
+}
+
+// Streaming passes for fine grids of at least this many points
+// (MSM_GRID_STREAM=1 / 0 forces them on / off).
+constexpr long long kStreamMinFine = 1LL << 21;
+static bool use_stream(long long fine_points) {
+  const char* e = std::getenv("MSM_GRID_STREAM");
+  if (e && e[0] == '1') return true;
+  if (e && e[0] == '0') return false;
+  return fine_points >= kStreamMinFine;
+}
+// z planes per workgroup: at least 4, and enough chunks for about 2048
+// workgroups over the (x, y) columns
+static int stream_zchunk(long long columns, int nz) {
+  const long long want = std::max<long long>(1, (2048 + columns - 1) / columns);
+  return std::max<int>(4, (int)((nz + want - 1) / want));
+}
+
 template <typename T>
 void launch_restrict(int p, const GridDev<T>& fine, const GridDev<T>& coarse, const double* J,
                      const T* qf, T* qc, hipStream_t s) {
+  JTaps<T> jt = make_taps<T>(J, p);
+  if (use_stream((long long)fine.n[0] * fine.n[1] * fine.n[2])) {
+    const long long cols = (long long)((coarse.n[0] + kStreamBX - 1) / kStreamBX) *
+                           ((coarse.n[1] + kStreamBY - 1) / kStreamBY);
+    const int zc = stream_zchunk(cols, coarse.n[2]);
+    const unsigned nb = (unsigned)(cols * ((coarse.n[2] + zc - 1) / zc));
+    switch (p) {
+      case 4: hipLaunchKernelGGL((k_restrict_stream<T, 4>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, zc, qf, qc); break;
+      case 6: hipLaunchKernelGGL((k_restrict_stream<T, 6>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, zc, qf, qc); break;
+      case 8: hipLaunchKernelGGL((k_restrict_stream<T, 8>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, zc, qf, qc); break;
+    }
+    return;
+  }
   constexpr int B = kRestrictB;
   const long long nb = (long long)((coarse.n[0] + B - 1) / B) * ((coarse.n[1] + B - 1) / B) *
                        ((coarse.n[2] + B - 1) / B);
-  JTaps<T> jt = make_taps<T>(J, p);
   switch (p) {
     case 4: hipLaunchKernelGGL((k_restrict_tiled<T, 4>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, qf, qc); break;
     case 6: hipLaunchKernelGGL((k_restrict_tiled<T, 6>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, qf, qc); break;
@@ -377,10 +637,33 @@ template <typename T>
 void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, const double* J,
                     const T* ecT, const double* ec64, T* ef, const double* ef64,
                     hipStream_t s) {
+  JTaps<T> jt = make_taps<T>(J, p);
+  if (use_stream((long long)fine.n[0] * fine.n[1] * fine.n[2])) {
+    const long long cols = (long long)((fine.n[0] + kStreamBX - 1) / kStreamBX) *
+                           ((fine.n[1] + kStreamBY - 1) / kStreamBY);
+    const int zc = stream_zchunk(cols, fine.n[2]);
+    const unsigned nb = (unsigned)(cols * ((fine.n[2] + zc - 1) / zc));
+    auto go = [&](auto csrc, auto fsrc) {
+      using SC = std::remove_const_t<std::remove_pointer_t<decltype(csrc)>>;
+      using SF = std::remove_const_t<std::remove_pointer_t<decltype(fsrc)>>;
+      switch (p) {
+        case 4: hipLaunchKernelGGL((k_prolong_stream<T, 4, SC, SF>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, zc, csrc, fsrc, ef); break;
+        case 6: hipLaunchKernelGGL((k_prolong_stream<T, 6, SC, SF>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, zc, csrc, fsrc, ef); break;
+        case 8: hipLaunchKernelGGL((k_prolong_stream<T, 8, SC, SF>), dim3(nb), dim3(256), 0, s, fine, coarse, jt, zc, csrc, fsrc, ef); break;
+      }
+    };
+    if (ec64) {
+      if (ef64) go(ec64, ef64);
+      else go(ec64, (const T*)ef);
+    } else {
+      if (ef64) go(ecT, ef64);
+      else go(ecT, (const T*)ef);
+    }
+    return;
+  }
   constexpr int B = kProlongB;
   const long long nb = (long long)((fine.n[0] + B - 1) / B) * ((fine.n[1] + B - 1) / B) *
                        ((fine.n[2] + B - 1) / B);
-  JTaps<T> jt = make_taps<T>(J, p);
   switch (p) {
     case 4: hipLaunchKernelGGL((k_prolong_tiled<T, 4>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, ecT, ec64, ef, ef64); break;
     case 6: hipLaunchKernelGGL((k_prolong_tiled<T, 6>), dim3((unsigned)nb), dim3(256), 0, s, fine, coarse, jt, ecT, ec64, ef, ef64); break;

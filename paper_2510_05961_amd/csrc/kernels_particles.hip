@@ -3,7 +3,9 @@
 // final combination of short- and long-range parts and the FP64 energy sum.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
+#include "brick.hpp"
 #include "kernels.hpp"
 
 namespace msm {
@@ -162,44 +164,38 @@ __global__ void k_bin_scatter(int n, const int* __restrict__ cell_of, const int*
 // a3: anterpolation (eq. grid_charge): q~^1_m += q_i phi_m(r_i) over the p^3
 // grid points of each particle, B-spline weights in FP64.
 // ---------------------------------------------------------------------------
-// Staged per cell: one workgroup accumulates the charges of one cell into
-// an LDS brick covering every grid point they can touch, then adds the brick
-// to the grid with one atomic per non-zero point (coalesced along x, and
-// conflicting only where the bricks of neighbouring cells overlap).  The
+// Staged per super-cell (kc^3 cells of the cell list, kc > 1 where cells are
+// sparse): one workgroup accumulates the charges of its cells into an LDS
+// brick covering every grid point they can touch, then adds the brick to
+// the grid with one atomic per non-zero point (coalesced along x, and
+// conflicting only where neighbouring bricks overlap).  The
 // brick holds 64-bit fixed-point sums: every contribution is rounded to a
 // multiple of 2^-S with 2^S sum_cell |q_i| < 2^62 (no sum can overflow, since
 // B-spline weights lie in [0, 1]), and integer LDS adds are exact, so the
 // brick does not depend on the order of the adds; the rounding is below 2^-62
-// of the cell's total |q| per contribution.  A brick larger than brick_cap
+// of the brick's total |q| per contribution.  A brick larger than brick_cap
 // points (cells much wider than h) falls back to per-particle global atomics.
-constexpr int kBrickMax = 8192;  // largest brick in LDS (64 KB)
 
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
     k_anterp_brick(const int* __restrict__ start, const vec4_t<T>* __restrict__ sorted,
-                   GridDev<T> g, CellGrid cg, int brick_cap, T* __restrict__ grid) {
+                   GridDev<T> g, CellGrid cg, BrickGeom bg, int brick_cap,
+                   T* __restrict__ grid) {
   extern __shared__ long long brick[];
   __shared__ double qsum[4];
-  const int cell = blockIdx.x;
-  const int beg = start[cell], end = start[cell + 1];
-  if (beg == end) return;
-  const int cc[3] = {cell % cg.nc[0], (cell / cg.nc[0]) % cg.nc[1], cell / (cg.nc[0] * cg.nc[1])};
-  // absolute grid index range of the brick (one point of margin each side
-  // for the rounding of the binning)
+  __shared__ BrickRuns runs;
+  int c0[3], c1[3], nruns;
+  const int count = brick_runs(blockIdx.x, start, cg, bg, c0, c1, runs, nruns);
+  if (count == 0) return;
   int lo[3], ext[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    lo[k] = (int)floor(cc[k] * cg.cs[k] / g.hd[k]) - P / 2 - 1;
-    const int hi = (int)floor((cc[k] + 1) * cg.cs[k] / g.hd[k]) + P / 2 + 1;
-    ext[k] = hi - lo[k] + 1;
-  }
-  const int vol = ext[0] * ext[1] * ext[2];
+  const int vol = brick_box<P>(c0, c1, cg, g.hd, lo, ext);
   const bool staged = vol <= brick_cap;
   double scale = 1.0;
   if (staged) {
     for (int b = threadIdx.x; b < vol; b += blockDim.x) brick[b] = 0;
     double aq = 0.0;
-    for (int i = beg + (int)threadIdx.x; i < end; i += blockDim.x) aq += fabs((double)sorted[i].w);
+    for (int j = threadIdx.x; j < count; j += blockDim.x)
+      aq += fabs((double)sorted[brick_particle(runs, nruns, j)].w);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) aq += __shfl_xor(aq, o);
     if ((threadIdx.x & 63) == 0) qsum[threadIdx.x >> 6] = aq;
@@ -208,8 +204,8 @@ __global__ void __launch_bounds__(256)
     (void)frexp(qsum[0] + qsum[1] + qsum[2] + qsum[3], &ex);  // total < 2^ex
     scale = ldexp(1.0, 62 - max(ex, -900));  // stays a finite power of two
   }
-  for (int i = beg + (int)threadIdx.x; i < end; i += blockDim.x) {
-    const vec4_t<T> pi = sorted[i];
+  for (int jp = threadIdx.x; jp < count; jp += blockDim.x) {
+    const vec4_t<T> pi = sorted[brick_particle(runs, nruns, jp)];
     const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
     double w[3][P];
     int m0[3];
@@ -398,20 +394,59 @@ void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int
     launch_zero_multi(zero, s);
 }
 
+BrickGeom brick_geom(int p, int n, int ncell, const CellGrid& cg, const double hd[3]) {
+  // LDS for the largest brick of kc^3 cells: per axis at most
+  // ceil(kc cs / h) + p + 3 points (one more for the rounding of cs / h)
+  auto cap = [&](int kc) {
+    long long c = 1;
+    for (int k = 0; k < 3; ++k) c *= (long long)std::ceil(kc * cg.cs[k] / hd[k]) + p + 4;
+    return c;
+  };
+  auto bricks = [&](int kc) {
+    long long m = 1;
+    for (int k = 0; k < 3; ++k) m *= (cg.nc[k] + kc - 1) / kc;
+    return m;
+  };
+  // grow the super-cell while clearing and flushing its brick (2 cap) costs
+  // more than the charges' p^3 contributions, the brick fits and at least
+  // kMinBricks workgroups remain
+  constexpr long long kMinBricks = 4096;
+  const double per_cell = (double)n / std::max(ncell, 1) * p * p * p;
+  int kc = 1;
+  const char* env = std::getenv("MSM_BRICK_CELLS");
+  if (env && std::atoi(env) > 0) {
+    const int want = std::min(std::atoi(env), kBrickMaxCells);
+    while (kc < want && cap(kc + 1) <= kBrickMax) ++kc;
+  } else {
+    while (kc < kBrickMaxCells && cap(kc + 1) <= kBrickMax && bricks(kc + 1) >= kMinBricks &&
+           2.0 * cap(kc) > per_cell * kc * kc * kc)
+      ++kc;
+  }
+  BrickGeom bg;
+  bg.kc = kc;
+  for (int k = 0; k < 3; ++k) bg.nsc[k] = (cg.nc[k] + kc - 1) / kc;
+  return bg;
+}
+
+// brick LDS in elements: the largest brick of this geometry, at most kBrickMax
+int brick_lds_cap(int p, const BrickGeom& bg, const CellGrid& cg, const double hd[3]) {
+  long long c = 1;
+  for (int k = 0; k < 3; ++k) c *= (long long)std::ceil(bg.kc * cg.cs[k] / hd[k]) + p + 4;
+  return (int)std::min<long long>(c, kBrickMax);
+}
+
 template <typename T>
 void launch_anterp(int p, int n, int ncell, const int* start, const CellGrid& cg,
                    const vec4_t<T>* sorted, const GridDev<T>& g, T* grid, hipStream_t s) {
   if (n <= 0) return;
-  // LDS for the largest brick a cell can need: per axis at most
-  // ceil(cs / h) + p + 3 points (one more for the rounding of cs / h)
-  long long cap = 1;
-  for (int k = 0; k < 3; ++k) cap *= (long long)std::ceil(cg.cs[k] / g.hd[k]) + p + 4;
-  const int bc = (int)std::min<long long>(cap, kBrickMax);
+  const BrickGeom bg = brick_geom(p, n, ncell, cg, g.hd);
+  const int bc = brick_lds_cap(p, bg, cg, g.hd);
   const size_t lds = (size_t)bc * sizeof(long long);
+  const unsigned nb = (unsigned)bg.nsc[0] * bg.nsc[1] * bg.nsc[2];
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_anterp_brick<T, 4>), dim3(ncell), dim3(256), lds, s, start, sorted, g, cg, bc, grid); break;
-    case 6: hipLaunchKernelGGL((k_anterp_brick<T, 6>), dim3(ncell), dim3(256), lds, s, start, sorted, g, cg, bc, grid); break;
-    case 8: hipLaunchKernelGGL((k_anterp_brick<T, 8>), dim3(ncell), dim3(256), lds, s, start, sorted, g, cg, bc, grid); break;
+    case 4: hipLaunchKernelGGL((k_anterp_brick<T, 4>), dim3(nb), dim3(256), lds, s, start, sorted, g, cg, bg, bc, grid); break;
+    case 6: hipLaunchKernelGGL((k_anterp_brick<T, 6>), dim3(nb), dim3(256), lds, s, start, sorted, g, cg, bg, bc, grid); break;
+    case 8: hipLaunchKernelGGL((k_anterp_brick<T, 8>), dim3(nb), dim3(256), lds, s, start, sorted, g, cg, bg, bc, grid); break;
   }
 }
 

@@ -60,6 +60,29 @@ def test_backward_matches_oracle_adjoint(case):
     assert rel_rms(gpos0, -1.3 * ref["F"]) <= tol
 
 
+@pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[3]])
+def test_backward_super_cell_bricks(case):
+    """The dipole anterpolation with bricks of 2^3 cells (forced with
+    MSM_BRICK_CELLS) against the oracle's adjoint."""
+    import os
+    box, per, p, h, a, L, fp64, n = case
+    pos, q = WL.gaussian_charges(n, box, 0.5, seed=n + 7)
+    pos, q = cast(pos, q, fp64)
+    v = WL.force_cotangent(n, seed=41)
+    if not fp64:
+        v = v.astype(np.float32).astype(np.float64)
+    print(f"case n={n} per={per} {'fp64' if fp64 else 'fp32'} bricks of 2^3 cells", flush=True)
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP64 if fp64 else msm.MSM_FP32, n)
+    os.environ["MSM_BRICK_CELLS"] = "2"
+    try:
+        gpos, gq = _gpu_fwd_bwd(plan, pos, q, 0.7, v)
+    finally:
+        del os.environ["MSM_BRICK_CELLS"]
+    rq, rpos = O.OracleMSM(box, per, p, h, a, L).backward(pos, q, 0.7, v)
+    tol = TOL["fp64" if fp64 else "fp32"]["F"]
+    assert rel_rms(gpos, rpos) <= tol and rel_rms(gq, rq) <= tol
+
+
 def test_backward_finite_differences_fp64():
     """Central differences of L = gE E + sum v.F evaluated by the GPU forward
     itself, against the GPU backward (FP64 path)."""

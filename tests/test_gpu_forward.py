@@ -93,16 +93,30 @@ def test_degenerate_sizes(fp64):
                 np.testing.assert_allclose(g["F"], ref["F"], rtol=1e-4, atol=1e-7)
 
 
-def test_stage_grids_match_oracle():
+@pytest.mark.parametrize("stream", ["0", "1"])
+@pytest.mark.parametrize("geom", [((12.0, 12.0, 9.0), (1, 1, 0), 4),
+                                  ((10.0, 11.0, 9.0), (0, 0, 0), 6),
+                                  ((12.0, 12.0, 12.0), (1, 1, 1), 8)])
+def test_stage_grids_match_oracle(stream, geom):
     """Per-stage parity: q~^l after restriction vs direct anterpolation, and
     e^{l+} after prolongation vs the nested sum of the oracle's level
-    potentials (prolongation written out from its formula)."""
+    potentials (prolongation written out from its formula).  stream = 1
+    forces the streaming restriction and prolongation of large grids
+    (MSM_GRID_STREAM), 0 the tiled ones."""
+    import os
     from test_oracle_pins import _prolong_axis
-    box, per, p, h, a, L = (12.0, 12.0, 9.0), (1, 1, 0), 4, 0.75, 3.0, 3
+    box, per, p = geom
+    h, a, L = 0.75, 3.0, 3
     pos, q = WL.gaussian_charges(600, box, 0.5, seed=9)
     pos, q = cast(pos, q, True)
     plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP64, 600)
-    gpu_forward(plan, pos, q)
+    print(f"case per={per} p={p} MSM_GRID_STREAM={stream}", flush=True)
+    os.environ["MSM_GRID_STREAM"] = stream
+    try:
+        gpu_forward(plan, pos, q)
+    finally:
+        del os.environ["MSM_GRID_STREAM"]
+    assert plan.status() == 0
     o = O.OracleMSM(box, per, p, h, a, L)
     J = {n: 2.0 ** (1 - p) * math.comb(p, n + p // 2) for n in range(-p // 2, p // 2 + 1)}
     elev = []
@@ -122,7 +136,9 @@ def test_stage_grids_match_oracle():
             up = _prolong_axis(up, arr_ax, J, lo_f[ax3], lo_c[ax3], n_f[ax3], per[ax3])
         nested = elev[l - 1] + up
         got = plan.grid(l, 1).cpu().numpy()
-        np.testing.assert_allclose(got, nested, rtol=0, atol=1e-12 * np.abs(nested).max())
+        # FP64 rounding of the nested sums (9 taps per axis at p = 8 on a
+        # periodic grid) reaches a few 1e-12 of the largest value
+        np.testing.assert_allclose(got, nested, rtol=0, atol=1e-11 * np.abs(nested).max())
 
 
 def test_error_flags():
@@ -221,6 +237,47 @@ def test_folded_matches_unfolded(fp64, geom):
     assert abs(g0["E"] - g1["E"]) <= tol * abs(g0["E"])
     assert rel_rms(g1["F"], g0["F"]) <= tol
     assert rel_rms(g1["phi"], g0["phi"]) <= tol
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("geom", ["periodic", "slab", "free"])
+def test_super_cell_bricks(fp64, geom):
+    """Anterpolation bricks that gather kc^3 cells of the cell list (forced
+    with MSM_BRICK_CELLS; kc = 4 leaves ragged super-cells at the far faces)
+    against one brick per cell and against the oracle.  The bricks only
+    change the fixed-point scale (per brick) and which adds meet in LDS."""
+    import os
+    if geom == "periodic":
+        box, per, L = (24.0, 24.0, 24.0), (1, 1, 1), 4
+    elif geom == "slab":
+        box, per, L = (24.0, 20.0, 14.0), (1, 1, 0), 3
+    else:
+        box, per, L = (18.0, 18.0, 18.0), (0, 0, 0), 3
+    p, h, a = 4, 0.75, 4.0
+    pos, q = WL.gaussian_charges(2000, box, 0.5, seed=29)
+    pos, q = cast(pos, q, fp64)
+    prec = msm.MSM_FP64 if fp64 else msm.MSM_FP32
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, prec, 2000)
+    res = {}
+    for kc in (1, 2, 4):
+        print(f"case {geom} {'fp64' if fp64 else 'fp32'} bricks of {kc}^3 cells", flush=True)
+        os.environ["MSM_BRICK_CELLS"] = str(kc)
+        try:
+            res[kc] = gpu_forward(plan, pos, q)
+            res[kc]["q1"] = plan.grid(1, 0).double().cpu().numpy()
+        finally:
+            del os.environ["MSM_BRICK_CELLS"]
+        assert plan.status() == 0
+    tol = 1e-12 if fp64 else 1e-6
+    for kc in (2, 4):
+        assert rel_rms(res[kc]["q1"], res[1]["q1"]) <= tol
+        assert abs(res[kc]["E"] - res[1]["E"]) <= tol * abs(res[1]["E"])
+        assert rel_rms(res[kc]["F"], res[1]["F"]) <= tol
+        assert rel_rms(res[kc]["phi"], res[1]["phi"]) <= tol
+    ref = O.OracleMSM(box, per, p, h, a, L).compute(pos, q)
+    t = TOL["fp64" if fp64 else "fp32"]
+    assert abs(res[4]["E"] - ref["E"]) <= t["E"] * abs(ref["E"])
+    assert rel_rms(res[4]["F"], ref["F"]) <= t["F"]
 
 
 @pytest.mark.parametrize("fp64", [True, False])
