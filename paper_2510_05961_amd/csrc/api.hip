@@ -462,10 +462,18 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   StageProfiler& pf = P->prof;
   // accumulators of the pass, cleared by the binning's scatter (a kernel,
   // not a memset: graph-safe); the cell counters are zero on entry
+  const GridDev<T> g1 = grid_dev<T>(hp, 1);
+  CellGrid cg;
+  for (int k = 0; k < 3; ++k) {
+    cg.nc[k] = hp.nc[k];
+    cg.cs[k] = hp.cs[k];
+  }
   ZeroJobs z;
   z.n = 0;
-  z.ptr[z.n] = P->qg[0];
-  z.words[z.n++] = hp.lev[0].G * (long long)(sizeof(T) / 4);
+  if (!anterp_tiled(p, n, cg, g1.n, g1.per, g1.hd)) {  // (tiles write every value)
+    z.ptr[z.n] = P->qg[0];
+    z.words[z.n++] = hp.lev[0].G * (long long)(sizeof(T) / 4);
+  }
   z.ptr[z.n] = energy;
   z.words[z.n++] = 2;
   grid_zero_jobs<T>(P, z);
@@ -506,13 +514,7 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   if (dag) (void)hipEventRecord(P->ev[1], sp);
 
   // a3 anterpolation onto level 1
-  const GridDev<T> g1 = grid_dev<T>(hp, 1);
   ev = pf.begin("anterp", s);
-  CellGrid cg;
-  for (int k = 0; k < 3; ++k) {
-    cg.nc[k] = hp.nc[k];
-    cg.cs[k] = hp.cs[k];
-  }
   launch_anterp<T>(p, n, P->ncell, start, cg, sorted, g1, (T*)P->qg[0], s);
   pf.end(ev, s);
   // a4 restriction, a5 per-level stencils, a6 top level, a7 prolongation

@@ -136,6 +136,10 @@ BrickGeom brick_geom(int p, int n, int ncell, const CellGrid& cg, const double h
 // LDS elements of the bricks of this geometry (at most kBrickMax)
 int brick_lds_cap(int p, const BrickGeom& bg, const CellGrid& cg, const double hd[3]);
 constexpr int kBrickMax = 8192;  // largest brick in LDS (64 KB)
+// Whether launch_anterp sums level 1 in tiles that write every grid value
+// (large grids); then the grid need not be cleared before it.
+bool anterp_tiled(int p, int n, const CellGrid& cg, const int gn[3], const int gper[3],
+                  const double hd[3]);
 template <typename T>
 void launch_anterp(int p, int n, int ncell, const int* start, const CellGrid& cg,
                    const vec4_t<T>* sorted, const GridDev<T>& g, T* grid, hipStream_t s);

@@ -394,6 +394,187 @@ void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int
     launch_zero_multi(zero, s);
 }
 
+// Large level-1 grids: one workgroup owns a tile of kTileX x kTileY x kTileZ
+// grid points and gathers every charge whose support meets it, from the
+// cells around the tile (periodic images included: a cell reached across a
+// periodic face shifts its charges' grid indices by one period).  The tile
+// is summed in LDS in the same 64-bit fixed point as the bricks (scale from
+// the total |q| of the gathered cells) and written with plain stores, so
+// HBM sees each grid value once, with no atomics and no clearing.  A charge
+// is spread by every tile its support meets (about two at p = 4) and read by
+// every tile whose margin its cell meets.
+constexpr int kTileX = 32, kTileY = 8, kTileZ = 8;
+constexpr int kTileRuns = 256;  // cell runs per tile (x segments of cell rows)
+constexpr int kTileSegs = 8;    // x segments per cell row (periodic splits)
+
+template <typename T, int P>
+__global__ void __launch_bounds__(256)
+    k_anterp_tile(const int* __restrict__ start, const vec4_t<T>* __restrict__ sorted,
+                  GridDev<T> g, CellGrid cg, T* __restrict__ grid) {
+  __shared__ long long acc[kTileX * kTileY * kTileZ];
+  __shared__ int rbeg[kTileRuns], roff[kTileRuns + 1], rsh[kTileRuns][3];
+  __shared__ double qsum[4];
+  const int T3[3] = {kTileX, kTileY, kTileZ};
+  int nt[3], t0[3], t1[3];
+  for (int k = 0; k < 3; ++k) nt[k] = (g.n[k] + T3[k] - 1) / T3[k];
+  {
+    const int b = blockIdx.x;
+    const int ti[3] = {b % nt[0], (b / nt[0]) % nt[1], b / (nt[0] * nt[1])};
+    for (int k = 0; k < 3; ++k) {
+      t0[k] = ti[k] * T3[k];
+      t1[k] = min(g.n[k], t0[k] + T3[k]);
+    }
+  }
+  // cells whose charges can reach grid indices [t0, t1) (one cell of margin
+  // for the rounding of the binning); free axes clipped to the grid of cells
+  int clo[3], chi[3];
+  for (int k = 0; k < 3; ++k) {
+    const double a0 = (double)(t0[k] + g.lo[k] - P / 2) * g.hd[k];
+    const double a1 = (double)(t1[k] + g.lo[k] + P / 2 - 1) * g.hd[k];
+    clo[k] = (int)floor(a0 / cg.cs[k]) - 1;
+    chi[k] = (int)floor(a1 / cg.cs[k]) + 1;
+    if (!g.per[k]) {
+      clo[k] = max(clo[k], 0);
+      chi[k] = min(chi[k], cg.nc[k] - 1);
+    }
+  }
+  // x segments: consecutive cells of one periodic image
+  int sa[kTileSegs], sb[kTileSegs], ss[kTileSegs], nseg = 0;
+  for (int c = clo[0]; c <= chi[0] && nseg < kTileSegs;) {
+    const int img = g.per[0] ? (c >= 0 ? c / cg.nc[0] : -((-c + cg.nc[0] - 1) / cg.nc[0])) : 0;
+    const int e = min(chi[0], (img + 1) * cg.nc[0] - 1);
+    sa[nseg] = c - img * cg.nc[0];
+    sb[nseg] = e - img * cg.nc[0];
+    ss[nseg] = img * g.n[0];
+    ++nseg;
+    c = e + 1;
+  }
+  const int ny = max(chi[1] - clo[1] + 1, 0), nz = max(chi[2] - clo[2] + 1, 0);
+  const int nruns = ny * nz * nseg;  // <= kTileRuns (checked by the host)
+  for (int i = threadIdx.x; i < kTileX * kTileY * kTileZ; i += blockDim.x) acc[i] = 0;
+  if (threadIdx.x < nruns) {
+    const int r = threadIdx.x, sg = r % nseg, row = r / nseg;
+    int cy = clo[1] + row % ny, cz = clo[2] + row / ny, sy = 0, sz = 0;
+    if (g.per[1]) {
+      sy = cy >= 0 ? cy / cg.nc[1] : -((-cy + cg.nc[1] - 1) / cg.nc[1]);
+      cy -= sy * cg.nc[1];
+    }
+    if (g.per[2]) {
+      sz = cz >= 0 ? cz / cg.nc[2] : -((-cz + cg.nc[2] - 1) / cg.nc[2]);
+      cz -= sz * cg.nc[2];
+    }
+    const int rowc = (cz * cg.nc[1] + cy) * cg.nc[0];
+    const int b = start[rowc + sa[sg]];
+    rbeg[r] = b;
+    roff[r + 1] = start[rowc + sb[sg] + 1] - b;
+    rsh[r][0] = ss[sg];
+    rsh[r][1] = sy * g.n[1];
+    rsh[r][2] = sz * g.n[2];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0;
+    roff[0] = 0;
+    for (int r = 0; r < nruns; ++r) {
+      a += roff[r + 1];
+      roff[r + 1] = a;
+    }
+  }
+  __syncthreads();
+  const int count = roff[nruns];
+  auto particle = [&](int j, int& r) {
+    r = 0;
+#pragma unroll
+    for (int step = kTileRuns / 2; step > 0; step >>= 1)
+      if (r + step < nruns && roff[r + step] <= j) r += step;
+    return rbeg[r] + (j - roff[r]);
+  };
+  double aq = 0.0;
+  for (int j = threadIdx.x; j < count; j += blockDim.x) {
+    int r;
+    aq += fabs((double)sorted[particle(j, r)].w);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) aq += __shfl_xor(aq, o);
+  if ((threadIdx.x & 63) == 0) qsum[threadIdx.x >> 6] = aq;
+  __syncthreads();
+  int ex;
+  (void)frexp(qsum[0] + qsum[1] + qsum[2] + qsum[3], &ex);
+  const double scale = ldexp(1.0, 62 - max(ex, -900));
+  for (int j = threadIdx.x; j < count; j += blockDim.x) {
+    int r;
+    const vec4_t<T> pi = sorted[particle(j, r)];
+    const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    double w[3][P];
+    bool in[3][P];
+    int i0[3];  // tile-local index of support point 0 per axis
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double f;
+      const int m0 = grid_coord<double>(xs[k], g.hd[k], f) - P / 2 + 1 + rsh[r][k];
+      bspline_weights<P, double>(f, w[k], nullptr, nullptr);
+      i0[k] = m0 - g.lo[k] - t0[k];
+#pragma unroll
+      for (int a = 0; a < P; ++a) in[k][a] = i0[k] + a >= 0 && i0[k] + a < t1[k] - t0[k];
+    }
+    const double qs = (double)pi.w * scale;
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+#pragma unroll
+      for (int b = 0; b < P; ++b) {
+        const double wyz = qs * w[2][c] * w[1][b];
+        const int row = ((i0[2] + c) * kTileY + (i0[1] + b)) * kTileX + i0[0];
+#pragma unroll
+        for (int a = 0; a < P; ++a)
+          if (in[2][c] && in[1][b] && in[0][a])
+            atomicAdd((unsigned long long*)&acc[row + a],
+                      (unsigned long long)__double2ll_rn(wyz * w[0][a]));
+      }
+    }
+  }
+  __syncthreads();
+  const double inv_scale = 1.0 / scale;
+  const int ex0 = t1[0] - t0[0], ex1 = t1[1] - t0[1], vol = ex0 * ex1 * (t1[2] - t0[2]);
+  for (int i = threadIdx.x; i < vol; i += blockDim.x) {
+    const int x = i % ex0, y = (i / ex0) % ex1, z = i / (ex0 * ex1);
+    grid[((long long)(t0[2] + z) * g.n[1] + (t0[1] + y)) * g.n[0] + (t0[0] + x)] =
+        (T)((double)acc[(z * kTileY + y) * kTileX + x] * inv_scale);
+  }
+}
+
+// Whether launch_anterp takes the tiled path (large grids; the tile's
+// cell runs must fit kTileRuns).  The tiled path writes every grid value,
+// so the caller need not clear the grid first.
+bool anterp_tiled(int p, int n, const CellGrid& cg, const int gn[3], const int gper[3],
+                  const double hd[3]) {
+  if (n <= 0) return false;
+  // measured on periodic 128^3-512^3 grids: tiles win where charges are
+  // sparse (0.075 per grid point: 1.9 against 3.5 ms), per-cell bricks where
+  // they are dense (0.45 per point: 5.1 against 7.9 ms), since a tile spreads
+  // each charge of its margin again (MSM_ANTERP_TILES=1 / 0 forces a path)
+  const char* env = std::getenv("MSM_ANTERP_TILES");
+  const long long G = (long long)gn[0] * gn[1] * gn[2];
+  const bool want = env && env[0] ? env[0] == '1' : (G >= (1LL << 21) && n <= 0.15 * (double)G);
+  if (!want) return false;
+  const int T3[3] = {kTileX, kTileY, kTileZ};
+  long long runs = 1;
+  for (int k = 0; k < 3; ++k) {
+    // cells a tile can gather along axis k (margin and rounding included)
+    const int ext = std::min(T3[k], gn[k]);
+    const long long cells = (long long)std::ceil((ext + p) * hd[k] / cg.cs[k]) + 3;
+    const long long nck = std::max(cg.nc[k], 1);
+    if (k == 0) {
+      // consecutive cells meet at most ceil(cells / nc) + 1 periodic images
+      const long long segs = gper[0] ? (cells + nck - 1) / nck + 1 : 1;
+      if (segs > kTileSegs) return false;
+      runs *= segs;
+    } else {
+      runs *= gper[k] ? cells : std::min(cells, nck);
+    }
+  }
+  return runs <= kTileRuns;
+}
+
 BrickGeom brick_geom(int p, int n, int ncell, const CellGrid& cg, const double hd[3]) {
   // LDS for the largest brick of kc^3 cells: per axis at most
   // ceil(kc cs / h) + p + 3 points (one more for the rounding of cs / h)
@@ -439,6 +620,17 @@ template <typename T>
 void launch_anterp(int p, int n, int ncell, const int* start, const CellGrid& cg,
                    const vec4_t<T>* sorted, const GridDev<T>& g, T* grid, hipStream_t s) {
   if (n <= 0) return;
+  if (anterp_tiled(p, n, cg, g.n, g.per, g.hd)) {
+    const unsigned nb = (unsigned)(((g.n[0] + kTileX - 1) / kTileX) *
+                                   ((g.n[1] + kTileY - 1) / kTileY) *
+                                   ((g.n[2] + kTileZ - 1) / kTileZ));
+    switch (p) {
+      case 4: hipLaunchKernelGGL((k_anterp_tile<T, 4>), dim3(nb), dim3(256), 0, s, start, sorted, g, cg, grid); break;
+      case 6: hipLaunchKernelGGL((k_anterp_tile<T, 6>), dim3(nb), dim3(256), 0, s, start, sorted, g, cg, grid); break;
+      case 8: hipLaunchKernelGGL((k_anterp_tile<T, 8>), dim3(nb), dim3(256), 0, s, start, sorted, g, cg, grid); break;
+    }
+    return;
+  }
   const BrickGeom bg = brick_geom(p, n, ncell, cg, g.hd);
   const int bc = brick_lds_cap(p, bg, cg, g.hd);
   const size_t lds = (size_t)bc * sizeof(long long);

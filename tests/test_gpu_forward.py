@@ -281,6 +281,51 @@ def test_super_cell_bricks(fp64, geom):
 
 
 @pytest.mark.parametrize("fp64", [True, False])
+@pytest.mark.parametrize("geom", ["periodic", "slab", "free", "tiny"])
+def test_anterp_tiles(fp64, geom):
+    """Level-1 charges summed in grid tiles that gather the charges of the
+    cells around them (the path of large grids, forced with
+    MSM_ANTERP_TILES=1; the tiles write every grid value, so the grid is not
+    cleared first) against the per-cell bricks and the oracle.  "tiny" is a
+    periodic grid smaller than one tile, whose tiles gather several images
+    of each cell."""
+    import os
+    if geom == "periodic":
+        box, per, L, n = (24.0, 24.0, 24.0), (1, 1, 1), 4, 2000
+    elif geom == "slab":
+        box, per, L, n = (24.0, 20.0, 14.0), (1, 1, 0), 3, 2000
+    elif geom == "free":
+        box, per, L, n = (18.0, 18.0, 18.0), (0, 0, 0), 3, 2000
+    else:
+        box, per, L, n = (9.0, 9.0, 9.0), (1, 1, 1), 2, 300
+    p, h, a = 4, 0.75, 4.0
+    pos, q = WL.gaussian_charges(n, box, 0.5, seed=37)
+    pos, q = cast(pos, q, fp64)
+    prec = msm.MSM_FP64 if fp64 else msm.MSM_FP32
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, prec, n)
+    res = {}
+    for tiles in ("0", "1"):
+        print(f"case {geom} {'fp64' if fp64 else 'fp32'} MSM_ANTERP_TILES={tiles}", flush=True)
+        os.environ["MSM_ANTERP_TILES"] = tiles
+        try:
+            # twice: the second call must not see the first one's grid
+            gpu_forward(plan, pos, q)
+            res[tiles] = gpu_forward(plan, pos, q)
+            res[tiles]["q1"] = plan.grid(1, 0).double().cpu().numpy()
+        finally:
+            del os.environ["MSM_ANTERP_TILES"]
+        assert plan.status() == 0
+    tol = 1e-12 if fp64 else 1e-6
+    assert rel_rms(res["1"]["q1"], res["0"]["q1"]) <= tol
+    assert abs(res["1"]["E"] - res["0"]["E"]) <= tol * abs(res["0"]["E"])
+    assert rel_rms(res["1"]["F"], res["0"]["F"]) <= tol
+    ref = O.OracleMSM(box, per, p, h, a, L).compute(pos, q)
+    t = TOL["fp64" if fp64 else "fp32"]
+    assert abs(res["1"]["E"] - ref["E"]) <= t["E"] * abs(ref["E"])
+    assert rel_rms(res["1"]["F"], ref["F"]) <= t["F"]
+
+
+@pytest.mark.parametrize("fp64", [True, False])
 @pytest.mark.parametrize("scale", [1e-12, 1e12])
 def test_charge_scale_homogeneity(fp64, scale):
     """E and F are quadratic in the charges, phi = dE/dq linear: scaling every
