@@ -225,8 +225,8 @@ def main():
     ap.add_argument("--standalone", action="store_true",
                     help="after the timed region, time every stage with all kernels on one "
                          "stream (no overlap) and report those durations too")
-    ap.add_argument("--grid-sweep", action="store_true",
-                    help="also time the grid passes on 128^3-512^3 level-1 grids with 1e7-6e7 "
+    ap.add_argument("--no-grid-sweep", action="store_true",
+                    help="skip the grid-pass timing on 128^3-512^3 level-1 grids with 1e7-6e7 "
                          "charges (HBM fraction of anterpolation, restriction, prolongation, "
                          "interpolation)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -384,8 +384,11 @@ def main():
         result["calib_copy_bytes"] = nb
         del src, dst
 
-    if args.grid_sweep:
-        result["grid_pass_sweep"] = _grid_pass_sweep(torch, msm, max(args.steps // 10, 3))
+    if not args.no_grid_sweep:
+        try:
+            result["grid_pass_sweep"] = _grid_pass_sweep(torch, msm, max(args.steps // 10, 3))
+        except RuntimeError as e:  # (MSMError and out-of-memory included) keep the headline line
+            result["grid_pass_sweep"] = {"error": str(e)}
 
     if not args.no_extras:
         result["autograd"] = _autograd_vs_plain(torch, msm, WL, np)
