@@ -183,6 +183,33 @@ def test_full_size_sampled(cfg):
     assert eF <= TOL["fp32"]["F"] and eP <= TOL["fp32"]["phi"]
 
 
+@pytest.mark.parametrize("n", [100_000, 600_000])
+def test_large_grid_sampled(n):
+    """A 128^3 periodic level-1 grid (h = 1, a = 3, p = 4, L = 5, FP32) with
+    charges +-1 at uniform random positions: the sizes at which the library
+    picks its large-grid passes by itself (streaming restriction and
+    prolongation; tiled anterpolation at 0.05 charges per grid point,
+    super-cell bricks at 0.29).  Sampled outputs against the oracle, and
+    E = 1/2 sum q phi over all charges."""
+    rng = np.random.default_rng(n)
+    box = (128.0, 128.0, 128.0)
+    pos = rng.random((n, 3)) * 128.0
+    q = np.where(rng.permutation(n) < n // 2, 1.0, -1.0)
+    pos, q = cast(pos, q, False)
+    print(f"large grid: n={n}", flush=True)
+    plan = msm.Plan(box, 7, 4, 1.0, 3.0, 5, msm.MSM_FP32, n)
+    assert plan.grid_dims(1) == (128, 128, 128)
+    g = gpu_forward(plan, pos, q)
+    assert plan.status() == 0
+    e_half = 0.5 * float(np.dot(q, g["phi"]))
+    assert abs(g["E"] - e_half) <= 1e-6 * 0.5 * float(np.sum(np.abs(q * g["phi"])))
+    sel = rng.choice(n, 32, replace=False)
+    phi_r, F_r = O.OracleMSM(box, (1, 1, 1), 4, 1.0, 3.0, 5).sampled(pos, q, sel)
+    eF, eP = rel_rms(g["F"][sel], F_r), rel_rms(g["phi"][sel], phi_r)
+    print(f"  sampled relF={eF:.2e} relPhi={eP:.2e}", flush=True)
+    assert eF <= TOL["fp32"]["F"] and eP <= TOL["fp32"]["phi"]
+
+
 @pytest.mark.parametrize("fp64", [True, False])
 def test_streams_match_single_stream(fp64):
     """The four-stream forward (pair sum and coarse levels beside level 1)
