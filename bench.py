@@ -72,7 +72,7 @@ def _autograd_vs_plain(torch, msm, WL, np):
     """Learnable-charge workload (200,000 Gaussian charges, 60 A periodic
     cube, p=4, h=1.5, a=10, L=4, FP32): plain forward vs forward + backward
     of L = E + sum v.F (v ~ N(0,1))."""
-    cfg = WL.CONFIGS[4]
+    cfg = WL.WORKLOADS[4]
     pos64, q64, box = WL.make_config(4, 1.0)
     n = len(q64)
     dev = torch.device("cuda:0")
@@ -234,8 +234,8 @@ def main():
                          "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (got --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: libmsm runs on exactly one GPU (got --gpus {args.gpus}); "
+              "sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -243,7 +243,7 @@ def main():
     from paper_2510_05961_amd import msm
     from paper_2510_05961_amd import workloads as WL
 
-    cfg = WL.CONFIGS[2]
+    cfg = WL.WORKLOADS[2]
     pos64, q64, box = WL.make_config(2, 1.0)
     n = len(q64)
     pos32, q32 = pos64.astype(np.float32), q64.astype(np.float32)

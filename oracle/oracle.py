@@ -22,7 +22,7 @@ and prolongation is the transpose of restriction.  dE/dq_i = phi_i and
 F_i = -grad_i U follow from eqs. (analytic_uoneplus_position_grad) and
 (analytic_uoneplus_charge_grad) level by level.
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent:
   * L counts grid levels l = 1..L; kernels k_0..k_L.
   * periodic axis: N_top = max(1, floor(box/(h 2^(L-1)) + 1/2)),
     N_1 = N_top 2^(L-1), h_l = box/N_l;

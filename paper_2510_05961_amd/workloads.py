@@ -96,7 +96,7 @@ def force_cotangent(n, seed=40):
 # --- the five workloads -----------------------------------------------------
 # Parameters: box, periodic mask (bit k = axis k), order p, spacing h, cutoff
 # a, levels L, precision.
-CONFIGS = {
+WORKLOADS = {
     1: dict(name="C1 non-periodic 1k ions, FP64", box=(20.0, 20.0, 20.0), periodic=0,
             p=4, h=2.0, a=8.0, L=3, fp64=True),
     2: dict(name="C2 periodic water 33,333 molecules (99,999 sites), 100 A box, FP32",
@@ -113,7 +113,7 @@ CONFIGS = {
 def make_config(cfg, scale=1.0):
     """Inputs of workload ``cfg`` (1..4); ``scale`` < 1 shrinks N and the box
     at fixed density for the small parity cases."""
-    c = CONFIGS[cfg]
+    c = WORKLOADS[cfg]
     if cfg == 1:
         n = max(2, int(round(1000 * scale)))
         L = 20.0 * scale ** (1.0 / 3.0)

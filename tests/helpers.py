@@ -49,6 +49,6 @@ def gpu_forward(plan, pos, q, ws=False):
 
 def config_case(cfg, scale):
     """(pos, q, box, periodic, p, h, a, L, fp64) of workload cfg at a scale."""
-    c = WL.CONFIGS[cfg]
+    c = WL.WORKLOADS[cfg]
     pos, q, box = WL.make_config(cfg, scale)
     return pos, q, box, periodic_of(c["periodic"]), c["p"], c["h"], c["a"], c["L"], c["fp64"]
