@@ -274,20 +274,24 @@ def test_super_cell_bricks(fp64, geom):
     against one brick per cell and against the oracle.  The bricks only
     change the fixed-point scale (per brick) and which adds meet in LDS."""
     import os
+    # h = 1.5 with cells of about 4: bricks of up to 4^3 (p = 4), 3^3 (p = 6,
+    # 8) cells fit in LDS, so the forced sizes below take effect, and 6, 5, 3
+    # or 4 cells per axis leave ragged super-cells
     if geom == "periodic":
-        box, per, L = (24.0, 24.0, 24.0), (1, 1, 1), 4
+        box, per, L, p = (24.0, 24.0, 24.0), (1, 1, 1), 3, 4
     elif geom == "slab":
-        box, per, L = (24.0, 20.0, 14.0), (1, 1, 0), 3
+        box, per, L, p = (24.0, 20.0, 14.0), (1, 1, 0), 3, 6
     else:
-        box, per, L = (18.0, 18.0, 18.0), (0, 0, 0), 3
-    p, h, a = 4, 0.75, 4.0
+        box, per, L, p = (18.0, 18.0, 18.0), (0, 0, 0), 3, 8
+    h, a = 1.5, 4.0
     pos, q = WL.gaussian_charges(2000, box, 0.5, seed=29)
     pos, q = cast(pos, q, fp64)
     prec = msm.MSM_FP64 if fp64 else msm.MSM_FP32
     plan = msm.Plan(box, mask_of(per), p, h, a, L, prec, 2000)
     res = {}
-    for kc in (1, 2, 4):
-        print(f"case {geom} {'fp64' if fp64 else 'fp32'} bricks of {kc}^3 cells", flush=True)
+    for kc in (1, 2, 3, 4):
+        print(f"case {geom} p={p} {'fp64' if fp64 else 'fp32'} bricks of up to {kc}^3 cells",
+              flush=True)
         os.environ["MSM_BRICK_CELLS"] = str(kc)
         try:
             res[kc] = gpu_forward(plan, pos, q)
@@ -296,7 +300,7 @@ def test_super_cell_bricks(fp64, geom):
             del os.environ["MSM_BRICK_CELLS"]
         assert plan.status() == 0
     tol = 1e-12 if fp64 else 1e-6
-    for kc in (2, 4):
+    for kc in (2, 3, 4):
         assert rel_rms(res[kc]["q1"], res[1]["q1"]) <= tol
         assert abs(res[kc]["E"] - res[1]["E"]) <= tol * abs(res[1]["E"])
         assert rel_rms(res[kc]["F"], res[1]["F"]) <= tol
@@ -318,14 +322,14 @@ def test_anterp_tiles(fp64, geom):
     of each cell."""
     import os
     if geom == "periodic":
-        box, per, L, n = (24.0, 24.0, 24.0), (1, 1, 1), 4, 2000
+        box, per, L, n, p = (24.0, 24.0, 24.0), (1, 1, 1), 4, 2000, 4
     elif geom == "slab":
-        box, per, L, n = (24.0, 20.0, 14.0), (1, 1, 0), 3, 2000
+        box, per, L, n, p = (24.0, 20.0, 14.0), (1, 1, 0), 3, 2000, 6
     elif geom == "free":
-        box, per, L, n = (18.0, 18.0, 18.0), (0, 0, 0), 3, 2000
+        box, per, L, n, p = (18.0, 18.0, 18.0), (0, 0, 0), 3, 2000, 4
     else:
-        box, per, L, n = (9.0, 9.0, 9.0), (1, 1, 1), 2, 300
-    p, h, a = 4, 0.75, 4.0
+        box, per, L, n, p = (9.0, 9.0, 9.0), (1, 1, 1), 2, 300, 8
+    h, a = 0.75, 4.0
     pos, q = WL.gaussian_charges(n, box, 0.5, seed=37)
     pos, q = cast(pos, q, fp64)
     prec = msm.MSM_FP64 if fp64 else msm.MSM_FP32
