@@ -187,7 +187,7 @@ def _grid_pass_sweep(torch, msm, steps):
             if plan.status() != 0:
                 raise RuntimeError("device error flag set in the grid-pass sweep")
             names = ["anterp", "restrict", "prolong", "interp"]
-            plan.set_profile_stages(names)
+            plan.set_profile_stages(names + ["bin", "cluster", "pair"])
             plan.profile(reset=True)
             plan.set_profiling(True)
             for _ in range(steps):
@@ -199,7 +199,10 @@ def _grid_pass_sweep(torch, msm, steps):
                    "restrict": sum(4 * (G[l] + G[l + 1]) for l in range(L - 1)),
                    "prolong": sum(4 * (G[l + 1] + 2 * G[l]) for l in range(L - 1)),
                    "interp": 32 * n + 4 * G[0]}
-            rec = {"grid1": [n1] * 3, "n": n, "levels": L}
+            # the cell-list build and the pair sum, for scale (not grid passes)
+            rec = {"grid1": [n1] * 3, "n": n, "levels": L,
+                   "other_ms": {k: round(prof[k]["ms"] / steps, 4)
+                                for k in ("bin", "cluster", "pair") if k in prof}}
             for k in names:
                 ms = prof[k]["ms"] / steps
                 gbs = alg[k] / (ms * 1e-3) / 1e9

@@ -201,6 +201,8 @@ msm_status upload_plan(msm_plan P) {
   // zero on entry to every binning (the cluster layout clears them after use)
   if (hipMemset(P->counts, 0, (size_t)P->ncell * kCountCopies * sizeof(int))) return MSM_ERR_HIP;
   if ((st = hip_alloc(P, (void**)&P->start, (size_t)(P->ncell + 1) * sizeof(int)))) return st;
+  if ((st = hip_alloc(P, (void**)&P->scan_tmp, (size_t)scan_tmp_ints(P->ncell) * sizeof(int))))
+    return st;
   if ((st = hip_alloc(P, (void**)&P->perm, nmax * sizeof(int)))) return st;
   if ((st = hip_alloc(P, &P->wrapped, nmax * 4 * sizeof(T)))) return st;
   if ((st = hip_alloc(P, &P->sorted, nmax * 4 * sizeof(T)))) return st;
@@ -489,7 +491,8 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   }
   int ev = pf.begin("bin", s);
   launch_binning<T>(n, pos, q, bp, P->ncell, P->cell_of, P->rank, P->counts,
-                    (vec4_t<T>*)P->wrapped, start, P->cl_start, sorted, perm, P->flag, z, s);
+                    (vec4_t<T>*)P->wrapped, start, P->cl_start, sorted, perm, P->flag,
+                    P->scan_tmp, z, s);
   pf.end(ev, s);
   ev = pf.begin("cluster", s);
   launch_cluster_layout<T>(1, 0, P->ncell, start, P->cl_start, bp, (const vec4_t<T>*)P->wrapped,

@@ -91,12 +91,15 @@ void launch_zero_multi(const ZeroJobs& jobs, hipStream_t s);
 // ints, zero on entry), the scans of cell starts and cluster offsets
 // (cl_start), and the scatter into cell order, which also clears the
 // buffers in `zero`.  The counts are left holding slot bases; the cluster
-// layout's kernel sets them back to zero for the next binning.
+// layout's kernel sets them back to zero for the next binning.  scan_tmp
+// (scan_tmp_ints(ncell) ints, or null: one-workgroup scan) lets many cells
+// be scanned by many workgroups.
 constexpr int kCountCopies = 8;
+int scan_tmp_ints(int ncell);
 template <typename T>
 void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
                     int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
-                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag,
+                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag, int* scan_tmp,
                     const ZeroJobs& zero, hipStream_t s);
 // Cluster layout of the cell-sorted particles (sort != 0: also reorders each
 // cell along a Morton curve, in place) and the short-range pair sum over 8 x 4

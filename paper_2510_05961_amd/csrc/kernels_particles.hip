@@ -66,60 +66,124 @@ __global__ void k_bin_count(int n, const T* __restrict__ pos, const T* __restric
 // per-cell cluster counts ceil(count / 8) into cl_start[0..ncell] (one
 // workgroup).  The kCountCopies counters of every cell are replaced in place
 // by the offset of their first particle (the scatter's base per slot).
+// Inclusive scan of (v, cv) over the 1024 threads of a workgroup.
+__device__ inline void scan1024(int& v, int& cv, int* buf, int* cbuf) {
+  const int t = threadIdx.x;
+  buf[t] = v;
+  cbuf[t] = cv;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int add = (t >= off) ? buf[t - off] : 0;
+    const int cadd = (t >= off) ? cbuf[t - off] : 0;
+    __syncthreads();
+    buf[t] += add;
+    cbuf[t] += cadd;
+    __syncthreads();
+  }
+  v = buf[t];
+  cv = cbuf[t];
+}
+
+// Counts of one cell (its kCountCopies counters) and its cluster count.
+__device__ inline int cell_count(int cell, int ncell, const int* counts, int (&sub)[kCountCopies]) {
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < kCountCopies; ++k) {
+    sub[k] = cell < ncell ? counts[cell * kCountCopies + k] : 0;
+    v += sub[k];
+  }
+  return v;
+}
+
+// Writes the cell's start, cluster offset and per-slot scatter bases.
+__device__ inline void cell_store(int cell, int o, int co, int* counts, int* start, int* cl_start,
+                                  const int (&sub)[kCountCopies]) {
+  start[cell] = o;
+  cl_start[cell] = co;
+#pragma unroll
+  for (int k = 0; k < kCountCopies; ++k) {
+    counts[cell * kCountCopies + k] = o;
+    o += sub[k];
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_scan(int ncell, int* __restrict__ counts,
                                                int* __restrict__ start,
                                                int* __restrict__ cl_start) {
   __shared__ int buf[1024], cbuf[1024];
-  __shared__ int carry, ccarry;
-  const int t = threadIdx.x;
-  if (t == 0) {
-    carry = 0;
-    ccarry = 0;
-  }
-  __syncthreads();
+  int carry = 0, ccarry = 0;  // the same in every thread
   for (int base = 0; base < ncell; base += 1024) {
-    const int cell = base + t;
+    const int cell = base + threadIdx.x;
     int sub[kCountCopies];
-    int v = 0;
-#pragma unroll
-    for (int k = 0; k < kCountCopies; ++k) {
-      sub[k] = cell < ncell ? counts[cell * kCountCopies + k] : 0;
-      v += sub[k];
-    }
-    const int cv = (v + 7) / 8;
-    buf[t] = v;
-    cbuf[t] = cv;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int add = (t >= off) ? buf[t - off] : 0;
-      const int cadd = (t >= off) ? cbuf[t - off] : 0;
-      __syncthreads();
-      buf[t] += add;
-      cbuf[t] += cadd;
-      __syncthreads();
-    }
-    if (cell < ncell) {
-      int o = carry + buf[t] - v;
-      start[cell] = o;
-      cl_start[cell] = ccarry + cbuf[t] - cv;
-#pragma unroll
-      for (int k = 0; k < kCountCopies; ++k) {
-        counts[cell * kCountCopies + k] = o;
-        o += sub[k];
-      }
-    }
-    __syncthreads();
-    if (t == 1023) {
-      carry += buf[1023];
-      ccarry += cbuf[1023];
-    }
+    const int v = cell_count(cell, ncell, counts, sub), cv = (v + 7) / 8;
+    int sv = v, scv = cv;
+    scan1024(sv, scv, buf, cbuf);
+    if (cell < ncell) cell_store(cell, carry + sv - v, ccarry + scv - cv, counts, start, cl_start, sub);
+    carry += buf[1023];
+    ccarry += cbuf[1023];
     __syncthreads();
   }
-  if (t == 0) {
+  if (threadIdx.x == 0) {
     start[ncell] = carry;
     cl_start[ncell] = ccarry;
   }
 }
+
+// Many cells: the same scan in three launches over blocks of 1024 cells
+// (block totals; their exclusive scan in one workgroup; the blocks' own
+// scans plus their offsets).  tmp holds 2 ints per block.
+__global__ void __launch_bounds__(1024) k_scan_totals(int ncell, const int* __restrict__ counts,
+                                                      int* __restrict__ tmp) {
+  __shared__ int buf[1024], cbuf[1024];
+  const int cell = blockIdx.x * 1024 + threadIdx.x;
+  int sub[kCountCopies];
+  int v = cell_count(cell, ncell, counts, sub), cv = (v + 7) / 8;
+  scan1024(v, cv, buf, cbuf);
+  if (threadIdx.x == 1023) {
+    tmp[2 * blockIdx.x] = v;
+    tmp[2 * blockIdx.x + 1] = cv;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_offsets(int nblk, int* __restrict__ tmp) {
+  __shared__ int buf[1024], cbuf[1024];
+  int carry = 0, ccarry = 0;
+  for (int base = 0; base < nblk; base += 1024) {
+    const int b = base + threadIdx.x;
+    const int v = b < nblk ? tmp[2 * b] : 0, cv = b < nblk ? tmp[2 * b + 1] : 0;
+    int sv = v, scv = cv;
+    scan1024(sv, scv, buf, cbuf);
+    __syncthreads();  // every thread has read tmp before it is overwritten
+    if (b < nblk) {
+      tmp[2 * b] = carry + sv - v;
+      tmp[2 * b + 1] = ccarry + scv - cv;
+    }
+    carry += buf[1023];
+    ccarry += cbuf[1023];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_apply(int ncell, int* __restrict__ counts,
+                                                     int* __restrict__ start,
+                                                     int* __restrict__ cl_start,
+                                                     const int* __restrict__ tmp) {
+  __shared__ int buf[1024], cbuf[1024];
+  const int cell = blockIdx.x * 1024 + threadIdx.x;
+  int sub[kCountCopies];
+  const int v = cell_count(cell, ncell, counts, sub), cv = (v + 7) / 8;
+  int sv = v, scv = cv;
+  scan1024(sv, scv, buf, cbuf);
+  const int o = tmp[2 * blockIdx.x], co = tmp[2 * blockIdx.x + 1];
+  if (cell < ncell) cell_store(cell, o + sv - v, co + scv - cv, counts, start, cl_start, sub);
+  if (cell == ncell - 1) {
+    start[ncell] = o + sv;
+    cl_start[ncell] = co + scv;
+  }
+}
+
+int scan_tmp_ints(int ncell) { return 2 * ((ncell + 1023) / 1024); }
+constexpr int kScanOneBlock = 16384;  // up to this many cells: k_scan alone
 
 // Zeroes up to kZeroJobs buffers (4-byte words) in one launch.
 __global__ void k_zero_multi(ZeroJobs jobs) {
@@ -380,13 +444,21 @@ __global__ void __launch_bounds__(256)
 template <typename T>
 void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
                     int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
-                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag,
+                    int* cl_start, vec4_t<T>* sorted, int* perm, int* flag, int* scan_tmp,
                     const ZeroJobs& zero, hipStream_t s) {
   const int nb = (n + 255) / 256;
   if (n > 0)
     hipLaunchKernelGGL(k_bin_count<T>, dim3(nb), dim3(256), 0, s, n, pos, q, bp, cell_of, rank,
                        counts, wrapped, flag);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ncell, counts, start, cl_start);
+  if (ncell <= kScanOneBlock || !scan_tmp) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ncell, counts, start, cl_start);
+  } else {
+    const int nblk = (ncell + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_totals, dim3(nblk), dim3(1024), 0, s, ncell, counts, scan_tmp);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, s, nblk, scan_tmp);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(1024), 0, s, ncell, counts, start, cl_start,
+                       scan_tmp);
+  }
   if (n > 0)
     hipLaunchKernelGGL(k_bin_scatter<T>, dim3(nb), dim3(256), 0, s, n, cell_of, rank, counts,
                        wrapped, sorted, perm, zero);
@@ -657,7 +729,7 @@ void launch_interp(int p, int n, const vec4_t<T>* sorted, const int* perm, const
 
 #define MSM_INST_PARTICLES(T)                                                                    \
   template void launch_binning<T>(int, const T*, const T*, const BinParams<T>&, int, int*, int*, \
-                                  int*, vec4_t<T>*, int*, int*, vec4_t<T>*, int*, int*,         \
+                                  int*, vec4_t<T>*, int*, int*, vec4_t<T>*, int*, int*, int*,   \
                                   const ZeroJobs&, hipStream_t);                                \
   template void launch_anterp<T>(int, int, int, const int*, const CellGrid&, const vec4_t<T>*,   \
                                  const GridDev<T>&, T*, hipStream_t);                             \

@@ -125,6 +125,7 @@ struct msm_plan_s {
   // slots (x, y, z, q), boxes (lo, hi), info (first sorted index, count,
   // cell), force cotangent in slot order (backward)
   int* cl_start = nullptr;
+  int* scan_tmp = nullptr;  // block totals of the many-workgroup cell scan
   void* cpos = nullptr;
   void* cbox = nullptr;
   int4* cinfo = nullptr;
