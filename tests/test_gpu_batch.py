@@ -101,3 +101,34 @@ def test_batch_malformed_offsets_flagged():
     _run_batch(bp, bad, pos, q)
     assert bp.status() == 1
     assert bp.status() == 0
+
+
+def test_batch_full_size_sampled():
+    """The full batched workload (4,096 clusters of 8-256 charges in 10-30 A
+    boxes, p = 4, h = 1, a = 6, FP32; two or three levels by box size) in the
+    launch configuration the benchmark times; a sample of systems (the
+    largest and smallest box, the most charges, five at random) against the
+    oracle, and every system's E = 1/2 sum q phi."""
+    off, boxes, pos, q, levels = WL.make_batch(4096, seed=5)
+    pos32, q32 = pos.astype(np.float32), q.astype(np.float32)
+    bp = msm.BatchPlan(boxes, levels, 4, 1.0, 6.0, msm.MSM_FP32, int(off[-1]))
+    E, F, dq = _run_batch(bp, off, pos32, q32)
+    assert bp.status() == 0
+    qd = q32.astype(np.float64)
+    for s in range(len(boxes)):
+        a, b = off[s], off[s + 1]
+        half = 0.5 * float(np.dot(qd[a:b], dq[a:b]))
+        scale = 0.5 * float(np.sum(np.abs(qd[a:b] * dq[a:b])))
+        assert abs(E[s] - half) <= 1e-6 * max(scale, 1e-6), s
+    counts = np.diff(off)
+    pick = {int(np.argmax(boxes)), int(np.argmin(boxes)), int(np.argmax(counts))}
+    pick |= set(np.random.default_rng(3).choice(len(boxes), 5, replace=False).tolist())
+    tol = TOL["fp32"]
+    for s in sorted(pick):
+        a, b = off[s], off[s + 1]
+        print(f"system {s}: n={b - a} box={boxes[s]:.2f} L={levels[s]}", flush=True)
+        ref = O.OracleMSM((boxes[s],) * 3, (0, 0, 0), 4, 1.0, 6.0, int(levels[s])).compute(
+            pos32[a:b].astype(np.float64), qd[a:b])
+        assert rel_rms(F[a:b], ref["F"]) <= tol["F"], s
+        assert abs(E[s] - ref["E"]) <= tol["E"] * max(abs(ref["E"]), 1e-3), s
+        assert rel_rms(dq[a:b], ref["phi"]) <= tol["phi"], s
