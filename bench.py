@@ -110,6 +110,29 @@ def _autograd_vs_plain(torch, msm, WL, np):
             "forward_backward_over_forward_time": round(t_fb / t_fwd, 3)}
 
 
+def _slab(torch, msm, WL, np):
+    """The slab workload: 10^6 charges +-1, 100 x 100 x 60 A, periodic in x
+    and y, p = 6, h = 1.25, a = 12, L = 5, FP32 (pair-dominated: about 5.5e9
+    unique pairs within a)."""
+    cfg = WL.WORKLOADS[3]
+    pos64, q64, box = WL.make_config(3, 1.0)
+    n = len(q64)
+    dev = torch.device("cuda:0")
+    P = torch.tensor(pos64, dtype=torch.float32, device=dev)
+    Q = torch.tensor(q64, dtype=torch.float32, device=dev)
+    plan = msm.Plan(box, cfg["periodic"], cfg["p"], cfg["h"], cfg["a"], cfg["L"],
+                    msm.MSM_FP32, n)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    F = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    dq = torch.empty(n, dtype=torch.float32, device=dev)
+    t = _time(lambda: plan.energy_forces(P, Q, out=(E, F, dq)), torch, 10)
+    if plan.status() != 0:
+        raise RuntimeError("device error flag set in the slab workload")
+    return {"workload": "slab, 10^6 charges +-1, 100 x 100 x 60 A, periodic x and y, p=6, "
+                        "h=1.25, a=12, L=5, FP32", "n": n,
+            "particles_per_s": round(n / t, 1), "ms_per_step": round(t * 1e3, 3)}
+
+
 def _batched_vs_plain(torch, msm, WL, np):
     """4,096 free-space clusters of 8-256 charges in 10-30 A boxes (p=4, h=1,
     a=6, FP32): one batched launch sequence vs one plan per system run one
@@ -224,7 +247,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the autograd (C4) and batched (C5) comparisons")
+                    help="skip the autograd, batched and slab workloads")
     ap.add_argument("--standalone", action="store_true",
                     help="after the timed region, time every stage with all kernels on one "
                          "stream (no overlap) and report those durations too")
@@ -396,6 +419,7 @@ def main():
     if not args.no_extras:
         result["autograd"] = _autograd_vs_plain(torch, msm, WL, np)
         result["batched"] = _batched_vs_plain(torch, msm, WL, np)
+        result["slab"] = _slab(torch, msm, WL, np)
 
     if not args.no_error_check:
         from oracle import oracle as O
