@@ -497,14 +497,18 @@ __global__ void __launch_bounds__(256)
       t1[k] = min(g.n[k], t0[k] + T3[k]);
     }
   }
-  // cells whose charges can reach grid indices [t0, t1) (one cell of margin
-  // for the rounding of the binning); free axes clipped to the grid of cells
+  // cells whose charges can reach grid indices [t0, t1): a charge touches
+  // the tile only if its coordinate lies in [(t0 + lo - P/2 - 1) h,
+  // (t1 + lo + P/2) h) (its first support point is floor(x/h) - P/2 + 1,
+  // give or take one for the rounding of grid_coord); one more grid spacing
+  // on each side covers the rounding of the binning.  Free axes are clipped
+  // to the grid of cells.
   int clo[3], chi[3];
   for (int k = 0; k < 3; ++k) {
-    const double a0 = (double)(t0[k] + g.lo[k] - P / 2) * g.hd[k];
-    const double a1 = (double)(t1[k] + g.lo[k] + P / 2 - 1) * g.hd[k];
-    clo[k] = (int)floor(a0 / cg.cs[k]) - 1;
-    chi[k] = (int)floor(a1 / cg.cs[k]) + 1;
+    const double a0 = (double)(t0[k] + g.lo[k] - P / 2 - 2) * g.hd[k];
+    const double a1 = (double)(t1[k] + g.lo[k] + P / 2 + 1) * g.hd[k];
+    clo[k] = (int)floor(a0 / cg.cs[k]);
+    chi[k] = (int)floor(a1 / cg.cs[k]);
     if (!g.per[k]) {
       clo[k] = max(clo[k], 0);
       chi[k] = min(chi[k], cg.nc[k] - 1);
@@ -631,9 +635,10 @@ bool anterp_tiled(int p, int n, const CellGrid& cg, const int gn[3], const int g
   const int T3[3] = {kTileX, kTileY, kTileZ};
   long long runs = 1;
   for (int k = 0; k < 3; ++k) {
-    // cells a tile can gather along axis k (margin and rounding included)
+    // cells a tile can gather along axis k (k_anterp_tile's cell range spans
+    // (ext + p + 3) h; floor at both ends adds up to two cells)
     const int ext = std::min(T3[k], gn[k]);
-    const long long cells = (long long)std::ceil((ext + p) * hd[k] / cg.cs[k]) + 3;
+    const long long cells = (long long)std::ceil((ext + p + 3) * hd[k] / cg.cs[k]) + 2;
     const long long nck = std::max(cg.nc[k], 1);
     if (k == 0) {
       // consecutive cells meet at most ceil(cells / nc) + 1 periodic images
