@@ -625,9 +625,10 @@ bool anterp_tiled(int p, int n, const CellGrid& cg, const int gn[3], const int g
                   const double hd[3]) {
   if (n <= 0) return false;
   // measured on periodic 128^3-512^3 grids: tiles win where charges are
-  // sparse (0.075 per grid point: 1.9 against 3.5 ms), per-cell bricks where
-  // they are dense (0.45 per point: 5.1 against 7.9 ms), since a tile spreads
-  // each charge of its margin again (MSM_ANTERP_TILES=1 / 0 forces a path)
+  // sparse (0.075 per grid point: 1.6 against 3.5 ms), bricks where they are
+  // dense (0.45 per point: 5.1 against 6.5 ms; 0.6: 0.96 against 1.13 ms),
+  // since a tile spreads each charge of its margin again (MSM_ANTERP_TILES=1
+  // / 0 forces a path)
   const char* env = std::getenv("MSM_ANTERP_TILES");
   const long long G = (long long)gn[0] * gn[1] * gn[2];
   const bool want = env && env[0] ? env[0] == '1' : (G >= (1LL << 21) && n <= 0.15 * (double)G);
