@@ -666,10 +666,13 @@ BrickGeom brick_geom(int p, int n, int ncell, const CellGrid& cg, const double h
     for (int k = 0; k < 3; ++k) m *= (cg.nc[k] + kc - 1) / kc;
     return m;
   };
-  // grow the super-cell while clearing and flushing its brick (2 cap) costs
-  // more than the charges' p^3 contributions, the brick fits and at least
-  // kMinBricks workgroups remain
+  // grow the super-cell while its brick's points (each cleared, read and
+  // added to HBM with a global atomic: weighed as kFlushWeight LDS adds) cost
+  // more than the charges' p^3 LDS adds, the brick fits and at least
+  // kMinBricks workgroups remain (a larger brick also overlaps its
+  // neighbours less, so the grid takes fewer atomics per point)
   constexpr long long kMinBricks = 4096;
+  constexpr double kFlushWeight = 10.0;  // (2 was 25% slower on 128^3-256^3 grids)
   const double per_cell = (double)n / std::max(ncell, 1) * p * p * p;
   int kc = 1;
   const char* env = std::getenv("MSM_BRICK_CELLS");
@@ -678,7 +681,7 @@ BrickGeom brick_geom(int p, int n, int ncell, const CellGrid& cg, const double h
     while (kc < want && cap(kc + 1) <= kBrickMax) ++kc;
   } else {
     while (kc < kBrickMaxCells && cap(kc + 1) <= kBrickMax && bricks(kc + 1) >= kMinBricks &&
-           2.0 * cap(kc) > per_cell * kc * kc * kc)
+           kFlushWeight * cap(kc) > per_cell * kc * kc * kc)
       ++kc;
   }
   BrickGeom bg;
