@@ -375,6 +375,7 @@ static JTaps<T> make_taps(const double* J, int p) {
 // loads are issued before the current plane's filters.  Tap orders match
 // the tiled kernels above.
 constexpr int kStreamBX = 32, kStreamBY = 8;  // 256 threads, one output column each
+constexpr int kProlongBX = 64, kProlongBY = 4;  // prolongation: a wave per 64-point fine row
 
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
@@ -473,7 +474,7 @@ template <typename T, int P, typename SC, typename SF>
 __global__ void __launch_bounds__(256)
     k_prolong_stream(GridDev<T> f, GridDev<T> c, JTaps<T> jt, int zchunk,
                      const SC* __restrict__ csrc, const SF* fsrc, T* ef) {
-  constexpr int BX = kStreamBX, BY = kStreamBY;
+  constexpr int BX = kProlongBX, BY = kProlongBY;
   constexpr int CW = BX / 2 + P / 2 + 2, CH = BY / 2 + P / 2 + 2, NC = CW * CH;
   constexpr int NL = (NC + 255) / 256;
   __shared__ T C[NC];
@@ -639,8 +640,8 @@ void launch_prolong(int p, const GridDev<T>& fine, const GridDev<T>& coarse, con
                     hipStream_t s) {
   JTaps<T> jt = make_taps<T>(J, p);
   if (use_stream((long long)fine.n[0] * fine.n[1] * fine.n[2])) {
-    const long long cols = (long long)((fine.n[0] + kStreamBX - 1) / kStreamBX) *
-                           ((fine.n[1] + kStreamBY - 1) / kStreamBY);
+    const long long cols = (long long)((fine.n[0] + kProlongBX - 1) / kProlongBX) *
+                           ((fine.n[1] + kProlongBY - 1) / kProlongBY);
     const int zc = stream_zchunk(cols, fine.n[2]);
     const unsigned nb = (unsigned)(cols * ((fine.n[2] + zc - 1) / zc));
     auto go = [&](auto csrc, auto fsrc) {
