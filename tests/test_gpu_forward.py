@@ -167,7 +167,7 @@ def test_error_flags():
 def test_full_size_sampled(cfg):
     pos, q, box, per, p, h, a, L, fp64 = config_case(cfg, 1.0)
     pos, q = cast(pos, q, fp64)
-    print(f"full config {cfg}: n={len(q)}", flush=True)
+    print(f"full workload {cfg}: n={len(q)}", flush=True)
     plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP32, len(q))
     g = gpu_forward(plan, pos, q)
     assert plan.status() == 0
