@@ -44,6 +44,7 @@ struct BatchConv {
   double scale;  // multiplies the stencil (K^l = K^1 / 2^(l-1))
   int off, len;  // cubic stencil box: offsets off .. off+len-1 per axis
   int fold = 0;  // z-planes j and len-1-j share coefficients
+  int cfg = 0;   // tile shape (kTiles), chosen per convolution by the autotuner
   void* K = nullptr;
   int2* rowext = nullptr;
   ConvTask* tasks = nullptr;
@@ -626,7 +627,7 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
   P->prof.end(ev, s);
   for (const BatchConv& bc : B.convs) {
     ev = P->prof.begin(bc.level == 1 ? "batch_conv_l1" : (bc.top ? "batch_conv_top" : "batch_conv_l2+"), s);
-    launch_batch_conv<T>(bc, B.tile_cfg, (const T*)B.qcat[bc.level - 1], (T*)B.ecat[bc.level - 1], s);
+    launch_batch_conv<T>(bc, bc.cfg, (const T*)B.qcat[bc.level - 1], (T*)B.ecat[bc.level - 1], s);
     P->prof.end(ev, s);
   }
   ev = P->prof.begin("batch_prolong", s);
@@ -653,46 +654,55 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
   return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
 }
 
-// Times the level-1 convolution for every tile shape on the plan's (zero)
-// grids and keeps the fastest.
+// Times every convolution of the plan (each level's intermediate and top
+// kernels: their grids differ in size) for every tile shape on the plan's
+// (zero) grids and keeps the fastest shape per convolution.
 template <typename T>
 static msm_status autotune(msm_plan P) {
   BatchState& B = *P->bs;
   hipStream_t s = nullptr;
   hipEvent_t a, b;
   if (hipEventCreate(&a) || hipEventCreate(&b)) return MSM_ERR_HIP;
-  BatchConv& l1 = B.convs[0];
-  float best = 1e30f;
-  int best_cfg = 0;
   std::ostringstream log;
-  for (int cfg = 0; cfg < 3; ++cfg) {
-    std::vector<ConvTask> t = build_tasks(B, 1, 0, cfg);
-    ConvTask* dt = nullptr;
-    if (hipMalloc((void**)&dt, std::max<size_t>(t.size(), 1) * sizeof(ConvTask))) return MSM_ERR_OOM;
-    if (hipMemcpy(dt, t.data(), t.size() * sizeof(ConvTask), hipMemcpyHostToDevice)) return MSM_ERR_HIP;
-    BatchConv trial = l1;
-    trial.tasks = dt;
-    trial.ntasks = (int)t.size();
-    launch_batch_conv<T>(trial, cfg, (const T*)B.qcat[0], (T*)B.ecat[0], s);  // warm-up
-    (void)hipEventRecord(a, s);
-    for (int r = 0; r < 3; ++r)
-      launch_batch_conv<T>(trial, cfg, (const T*)B.qcat[0], (T*)B.ecat[0], s);
-    (void)hipEventRecord(b, s);
-    (void)hipEventSynchronize(b);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, a, b);
-    (void)hipFree(dt);
-    log << (cfg ? "," : "") << "{\"R\":" << kTiles[cfg].R << ",\"tx\":" << kTiles[cfg].TXT
-        << ",\"ty\":" << kTiles[cfg].TYT << ",\"ms\":" << ms / 3 << "}";
-    if (ms < best) {
-      best = ms;
-      best_cfg = cfg;
+  for (size_t ci = 0; ci < B.convs.size(); ++ci) {
+    BatchConv& bc = B.convs[ci];
+    float best = 1e30f;
+    int best_cfg = 0;
+    log << (ci ? "," : "") << "{\"level\":" << bc.level << ",\"top\":" << bc.top << ",\"ms\":[";
+    for (int cfg = 0; cfg < 3; ++cfg) {
+      std::vector<ConvTask> t = build_tasks(B, bc.level, bc.top, cfg);
+      ConvTask* dt = nullptr;
+      if (hipMalloc((void**)&dt, std::max<size_t>(t.size(), 1) * sizeof(ConvTask)))
+        return MSM_ERR_OOM;
+      if (!t.empty() &&
+          hipMemcpy(dt, t.data(), t.size() * sizeof(ConvTask), hipMemcpyHostToDevice))
+        return MSM_ERR_HIP;
+      BatchConv trial = bc;
+      trial.tasks = dt;
+      trial.ntasks = (int)t.size();
+      const T* q = (const T*)B.qcat[bc.level - 1];
+      T* e = (T*)B.ecat[bc.level - 1];
+      launch_batch_conv<T>(trial, cfg, q, e, s);  // warm-up
+      (void)hipEventRecord(a, s);
+      for (int r = 0; r < 3; ++r) launch_batch_conv<T>(trial, cfg, q, e, s);
+      (void)hipEventRecord(b, s);
+      (void)hipEventSynchronize(b);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      (void)hipFree(dt);
+      log << (cfg ? "," : "") << ms / 3;
+      if (ms < best) {
+        best = ms;
+        best_cfg = cfg;
+      }
     }
+    bc.cfg = best_cfg;
+    log << "],\"cfg\":" << best_cfg << "}";
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (hipGetLastError() != hipSuccess) return MSM_ERR_HIP;
-  B.tile_cfg = best_cfg;
+  B.tile_cfg = B.convs.empty() ? 0 : B.convs[0].cfg;
   B.tuning = "[" + log.str() + "]";
   return MSM_OK;
 }
@@ -770,10 +780,10 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
     }
   }
   if (hipDeviceSynchronize()) return MSM_ERR_HIP;
-  // autotune the tile shape on the level-1 convolution, then build the task lists
+  // autotune the tile shape of each convolution, then build the task lists
   if ((st = autotune<T>(P))) return st;
   for (BatchConv& bc : B.convs) {
-    std::vector<ConvTask> t = build_tasks(B, bc.level, bc.top, B.tile_cfg);
+    std::vector<ConvTask> t = build_tasks(B, bc.level, bc.top, bc.cfg);
     if ((st = hip_alloc(P, (void**)&bc.tasks, std::max<size_t>(t.size(), 1) * sizeof(ConvTask))))
       return st;
     if (!t.empty() &&
@@ -954,7 +964,8 @@ std::string describe_batch(const msm::BatchState& B) {
     << ",\"convs\":[";
   for (size_t i = 0; i < B.convs.size(); ++i)
     o << (i ? "," : "") << "{\"level\":" << B.convs[i].level << ",\"top\":" << B.convs[i].top
-      << ",\"len\":" << B.convs[i].len << ",\"tasks\":" << B.convs[i].ntasks << "}";
+      << ",\"len\":" << B.convs[i].len << ",\"tasks\":" << B.convs[i].ntasks
+      << ",\"tile_cfg\":" << B.convs[i].cfg << "}";
   o << "]}";
   return o.str();
 }
