@@ -108,8 +108,11 @@ msm_status msm_plan_get_stencil(msm_plan plan, int level, int dims_off[6], doubl
 msm_status msm_plan_grid_dims(msm_plan plan, int level, int n[3]);
 
 /* Bytes of caller workspace that msm_energy_forces writes and msm_backward
- * reads for a call with n particles (saved forward state). */
-size_t msm_workspace_bytes(msm_plan plan, int n);
+ * reads for a call with n particles (saved forward state: the cell-ordered
+ * particles and their permutation, the cell starts, phi, F and e^{1+}).
+ * flags: 0 (the one layout; other values are reserved and return 0).
+ * Returns 0 for a NULL or batch plan or n < 0. */
+size_t msm_workspace_bytes(msm_plan plan, int n, int flags);
 
 /*
  * msm_energy_forces -- one forward evaluation on the device.
@@ -157,11 +160,19 @@ msm_status msm_plan_get_grid(msm_plan plan, int level, int which, void* dst, voi
  * Batched evaluation of many independent non-periodic systems in one launch
  * sequence (Sec. "Madelung constants", batching by vmap, done here without
  * padding).  All systems share order, h, cutoff_a and precision; system s has
- * its own cubic box edge boxes[s] and level count levels[s].
+ * its own box and level count.
+ *   boxes[n_sys][3]  host, edge lengths of each system's box; the batched
+ *                    kernels take cubic boxes (the three edges equal, else
+ *                    MSM_ERR_UNSUPPORTED).
+ *   levels[n_sys]    host, grid levels L of each system.
+ *   periodic_mask    must be 0 (free space; otherwise MSM_ERR_UNSUPPORTED).
+ * The other arguments are those of msm_plan_create (max_total_n bounds the
+ * summed particle count of a call).
  */
 msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const double* boxes,
-                                 const int* levels, int order, double h, double cutoff_a,
-                                 int precision, int max_total_n, int quasi_degree_M);
+                                 const int* levels, unsigned periodic_mask, int order, double h,
+                                 double cutoff_a, int precision, int max_total_n,
+                                 int quasi_degree_M);
 /* offsets: device int32 [n_sys+1] CSR ranges into pos/q/forces/dEdq, with
  * offsets[0] = 0, non-decreasing, offsets[n_sys] <= max_total_n (checked on the
  * device: malformed offsets set the sticky flag, msm_plan_status then returns
@@ -169,10 +180,12 @@ msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const double* boxes,
  * must lie in [0, boxes[s]]^3.  The launch sequence is captured in a hipGraph
  * on the first call and replayed while the pointers and stream stay the same
  * (MSM_BATCH_GRAPH=0 launches directly).  The conv tile shape is chosen at
- * plan creation by timing the candidates; msm_plan_describe reports it. */
+ * plan creation by timing the candidates (MSM_BATCH_TILE=0|1|2 pins one);
+ * msm_plan_describe reports it.  ws must be NULL: there is no batched
+ * backward whose saved state it would hold (non-NULL: MSM_ERR_UNSUPPORTED). */
 msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void* pos,
-                                   const void* q, double* energies, void* forces, void* dEdq,
-                                   void* stream);
+                                   const void* q, void* ws, double* energies, void* forces,
+                                   void* dEdq, void* stream);
 
 /*
  * Stage timing with HIP events (benchmarks, MSM_PROFILE-style breakdowns).

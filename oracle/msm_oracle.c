@@ -453,111 +453,172 @@ void orc_short_range(const orc_geom* g, int n, const double* pos, const double* 
   }
 }
 
-/* Plain cell list: cells of edge >= a; neighbour cells -1..1 per axis. */
-void orc_short_range_cells(const orc_geom* g, int n, const double* pos,
-                           const double* q, double* phi, double* F)
-{
+/* Plain cell list: cells of edge >= a, so every partner within a lies in the
+ * -1..1 neighbour cells of a particle's own cell (distinct cells only: an axis
+ * with fewer than 3 cells lists each cell once). */
+typedef struct {
   int nc[3];
   double cs[3];
+  int* cell;
+  int* head;
+  int* next;
+} cell_list;
+
+static void cell_list_build(const orc_geom* g, int n, const double* pos, cell_list* cl)
+{
   for (int k = 0; k < 3; ++k) {
-    nc[k] = (int)floor(g->box[k] / g->a);
-    if (nc[k] < 1) nc[k] = 1;
-    cs[k] = g->box[k] / nc[k];
+    cl->nc[k] = (int)floor(g->box[k] / g->a);
+    if (cl->nc[k] < 1) cl->nc[k] = 1;
+    cl->cs[k] = g->box[k] / cl->nc[k];
   }
-  long ncell = (long)nc[0] * nc[1] * nc[2];
-  int* cell = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
-  int* head = (int*)malloc(sizeof(int) * ncell);
-  int* next = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
-  for (long c = 0; c < ncell; ++c) head[c] = -1;
+  long ncell = (long)cl->nc[0] * cl->nc[1] * cl->nc[2];
+  cl->cell = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+  cl->head = (int*)malloc(sizeof(int) * ncell);
+  cl->next = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+  for (long c = 0; c < ncell; ++c) cl->head[c] = -1;
   for (int i = n - 1; i >= 0; --i) {
     int ci[3];
     for (int k = 0; k < 3; ++k) {
       double x = pos[3 * i + k];
       if (g->periodic[k]) x -= g->box[k] * floor(x / g->box[k]);
-      int c = (int)floor(x / cs[k]);
+      int c = (int)floor(x / cl->cs[k]);
       if (c < 0) c = 0;
-      if (c >= nc[k]) c = nc[k] - 1;
+      if (c >= cl->nc[k]) c = cl->nc[k] - 1;
       ci[k] = c;
     }
-    long c = ((long)ci[2] * nc[1] + ci[1]) * nc[0] + ci[0];
-    cell[i] = (int)c;
-    next[i] = head[c];
-    head[c] = i;
+    long c = ((long)ci[2] * cl->nc[1] + ci[1]) * cl->nc[0] + ci[0];
+    cl->cell[i] = (int)c;
+    cl->next[i] = cl->head[c];
+    cl->head[c] = i;
   }
+}
+
+static void cell_list_free(cell_list* cl)
+{
+  free(cl->cell);
+  free(cl->head);
+  free(cl->next);
+}
+
+/* The distinct neighbour cells of particle i: out[] receives up to 27 cell
+ * indices, the count is returned. */
+static int cell_list_neighbours(const orc_geom* g, const cell_list* cl, int i, long out[27])
+{
+  const int* nc = cl->nc;
+  int c = cl->cell[i];
+  int ci[3] = {c % nc[0], (c / nc[0]) % nc[1], c / (nc[0] * nc[1])};
+  int list[3][3], cntk[3];
+  for (int k = 0; k < 3; ++k) {
+    cntk[k] = 0;
+    for (int o = -1; o <= 1; ++o) {
+      int cc = ci[k] + o;
+      if (g->periodic[k]) cc = ((cc % nc[k]) + nc[k]) % nc[k];
+      else if (cc < 0 || cc >= nc[k]) continue;
+      int dup = 0;
+      for (int u = 0; u < cntk[k]; ++u) dup |= (list[k][u] == cc);
+      if (!dup) list[k][cntk[k]++] = cc;
+    }
+  }
+  int m = 0;
+  for (int uz = 0; uz < cntk[2]; ++uz)
+    for (int uy = 0; uy < cntk[1]; ++uy)
+      for (int ux = 0; ux < cntk[0]; ++ux)
+        out[m++] = ((long)list[2][uz] * nc[1] + list[1][uy]) * nc[0] + list[0][ux];
+  return m;
+}
+
+/* Pair (i, j) of the short-range sum: d = r_i - r_j (minimum image); returns 0
+ * when r >= a, else adds q_j k0(r) to *ph and -q_i q_j k0'(r)/r d to f. */
+static int sr_pair(const orc_geom* g, const double* pos, const double* q, int i, int j,
+                   double* ph, double f[3])
+{
+  double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                 pos[3 * i + 2] - pos[3 * j + 2]};
+  min_image(g, d);
+  double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  if (!(r < g->a)) return 0;
+  *ph += q[j] * orc_kernel(0, g->L, g->a, g->p, r);
+  double c = -q[i] * q[j] * orc_k0_d1(g->a, g->p, r) / r;
+  for (int k = 0; k < 3; ++k) f[k] += c * d[k];
+  return 1;
+}
+
+void orc_short_range_cells(const orc_geom* g, int n, const double* pos,
+                           const double* q, double* phi, double* F)
+{
+  cell_list cl;
+  cell_list_build(g, n, pos, &cl);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int i = 0; i < n; ++i) {
-    int c = cell[i];
-    int ci[3] = {c % nc[0], (c / nc[0]) % nc[1], c / (nc[0] * nc[1])};
-    /* distinct neighbour cells per axis */
-    int list[3][3], cntk[3];
-    for (int k = 0; k < 3; ++k) {
-      cntk[k] = 0;
-      for (int o = -1; o <= 1; ++o) {
-        int cc = ci[k] + o;
-        if (g->periodic[k]) cc = ((cc % nc[k]) + nc[k]) % nc[k];
-        else if (cc < 0 || cc >= nc[k]) continue;
-        int dup = 0;
-        for (int u = 0; u < cntk[k]; ++u) dup |= (list[k][u] == cc);
-        if (!dup) list[k][cntk[k]++] = cc;
-      }
-    }
+    long nb[27];
+    int m = cell_list_neighbours(g, &cl, i, nb);
     double ph = 0.0, f[3] = {0, 0, 0};
-    for (int uz = 0; uz < cntk[2]; ++uz)
-      for (int uy = 0; uy < cntk[1]; ++uy)
-        for (int ux = 0; ux < cntk[0]; ++ux) {
-          long cc = ((long)list[2][uz] * nc[1] + list[1][uy]) * nc[0] + list[0][ux];
-          for (int j = head[cc]; j >= 0; j = next[j]) {
-            if (j == i) continue;
-            double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
-                           pos[3 * i + 2] - pos[3 * j + 2]};
-            min_image(g, d);
-            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (!(r < g->a)) continue;
-            ph += q[j] * orc_kernel(0, g->L, g->a, g->p, r);
-            double cf = -q[i] * q[j] * orc_k0_d1(g->a, g->p, r) / r;
-            for (int k = 0; k < 3; ++k) f[k] += cf * d[k];
-          }
-        }
+    for (int u = 0; u < m; ++u)
+      for (int j = cl.head[nb[u]]; j >= 0; j = cl.next[j])
+        if (j != i) sr_pair(g, pos, q, i, j, &ph, f);
     if (phi) phi[i] += ph;
     if (F)
       for (int k = 0; k < 3; ++k) F[3 * i + k] += f[k];
   }
-  free(cell);
-  free(head);
-  free(next);
+  cell_list_free(&cl);
 }
 
 /* With f(r) = -k0'(r)/r the short-range force is F0_i = q_i sum_j q_j f d_ij,
- * d_ij = r_i - r_j.  For L0 = sum_i v_i . F0_i:
- *   dL0/dq_i = sum_j q_j f (v_i - v_j) . d_ij
- *   dL0/dr_i = sum_j q_i q_j [ f (v_i - v_j) + (f'/r) ((v_i - v_j) . d_ij) d_ij ]
+ * d_ij = r_i - r_j.  For L0 = sum_i v_i . F0_i the pair (i, j) adds
+ *   dL0/dq_i = q_j f (v_i - v_j) . d_ij
+ *   dL0/dr_i = q_i q_j [ f (v_i - v_j) + (f'/r) ((v_i - v_j) . d_ij) d_ij ]
  * with f'(r) = -k0''(r)/r + k0'(r)/r^2. */
-void orc_short_range_vjp(const orc_geom* g, int n, const double* pos,
-                         const double* q, const double* v, double* gq, double* gr)
+static void vjp_pair(const orc_geom* g, const double* pos, const double* q, const double* v,
+                     int i, int j, double* sq, double sr[3])
 {
+  double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                 pos[3 * i + 2] - pos[3 * j + 2]};
+  min_image(g, d);
+  double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  if (!(r < g->a)) return;
+  double k1 = orc_k0_d1(g->a, g->p, r), k2 = orc_k0_d2(g->a, g->p, r);
+  double f = -k1 / r;
+  double fp = -k2 / r + k1 / (r * r);
+  double dv[3] = {v[3 * i] - v[3 * j], v[3 * i + 1] - v[3 * j + 1],
+                  v[3 * i + 2] - v[3 * j + 2]};
+  double dvd = dv[0] * d[0] + dv[1] * d[1] + dv[2] * d[2];
+  *sq += q[j] * f * dvd;
+  for (int k = 0; k < 3; ++k)
+    sr[k] += q[i] * q[j] * (f * dv[k] + (fp / r) * dvd * d[k]);
+}
+
+void orc_short_range_vjp(const orc_geom* g, int n, const double* pos, const double* q,
+                         const double* v, int nsel, const int* sel, double* gq, double* gr)
+{
+  const int cnt = nsel < 0 ? n : nsel;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int s = 0; s < cnt; ++s) {
+    int i = nsel < 0 ? s : sel[s];
+    double sq = 0.0, sr[3] = {0, 0, 0};
+    for (int j = 0; j < n; ++j)
+      if (j != i) vjp_pair(g, pos, q, v, i, j, &sq, sr);
+    gq[s] += sq;
+    for (int k = 0; k < 3; ++k) gr[3 * s + k] += sr[k];
+  }
+}
+
+void orc_short_range_vjp_cells(const orc_geom* g, int n, const double* pos,
+                               const double* q, const double* v, double* gq, double* gr)
+{
+  cell_list cl;
+  cell_list_build(g, n, pos, &cl);
 #pragma omp parallel for schedule(dynamic, 16)
   for (int i = 0; i < n; ++i) {
+    long nb[27];
+    int m = cell_list_neighbours(g, &cl, i, nb);
     double sq = 0.0, sr[3] = {0, 0, 0};
-    for (int j = 0; j < n; ++j) {
-      if (j == i) continue;
-      double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
-                     pos[3 * i + 2] - pos[3 * j + 2]};
-      min_image(g, d);
-      double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      if (!(r < g->a)) continue;
-      double k1 = orc_k0_d1(g->a, g->p, r), k2 = orc_k0_d2(g->a, g->p, r);
-      double f = -k1 / r;
-      double fp = -k2 / r + k1 / (r * r);
-      double dv[3] = {v[3 * i] - v[3 * j], v[3 * i + 1] - v[3 * j + 1],
-                      v[3 * i + 2] - v[3 * j + 2]};
-      double dvd = dv[0] * d[0] + dv[1] * d[1] + dv[2] * d[2];
-      sq += q[j] * f * dvd;
-      for (int k = 0; k < 3; ++k)
-        sr[k] += q[i] * q[j] * (f * dv[k] + (fp / r) * dvd * d[k]);
-    }
+    for (int u = 0; u < m; ++u)
+      for (int j = cl.head[nb[u]]; j >= 0; j = cl.next[j])
+        if (j != i) vjp_pair(g, pos, q, v, i, j, &sq, sr);
     gq[i] += sq;
     for (int k = 0; k < 3; ++k) gr[3 * i + k] += sr[k];
   }
+  cell_list_free(&cl);
 }
 
 void orc_direct_coulomb(int n, const double* pos, const double* q, double* phi,

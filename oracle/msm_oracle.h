@@ -79,9 +79,14 @@ void orc_short_range(const orc_geom* g, int n, const double* pos, const double* 
 /* Same sum through a plain cell list (all particles). */
 void orc_short_range_cells(const orc_geom* g, int n, const double* pos,
                            const double* q, double* phi, double* F);
-/* VJP of the short-range forces against cotangent v. */
-void orc_short_range_vjp(const orc_geom* g, int n, const double* pos,
-                         const double* q, const double* v, double* gq, double* gr);
+/* VJP of the short-range forces against cotangent v: adds d(sum_k v_k.F0_k)/dq_i
+ * and /dr_i.  Brute force over all pairs for the listed particles (nsel < 0:
+ * all; output row s belongs to particle sel[s]). */
+void orc_short_range_vjp(const orc_geom* g, int n, const double* pos, const double* q,
+                         const double* v, int nsel, const int* sel, double* gq, double* gr);
+/* Same VJP through the plain cell list (all particles). */
+void orc_short_range_vjp_cells(const orc_geom* g, int n, const double* pos,
+                               const double* q, const double* v, double* gq, double* gr);
 
 /* Exact non-periodic Coulomb sums: phi_i = sum_{j!=i} q_j / r, F_i. */
 void orc_direct_coulomb(int n, const double* pos, const double* q, double* phi,

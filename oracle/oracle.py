@@ -109,8 +109,10 @@ def lib():
         L.orc_short_range.restype = None
         L.orc_short_range_cells.argtypes = [G, i, P, P, P, P]
         L.orc_short_range_cells.restype = None
-        L.orc_short_range_vjp.argtypes = [G, i, P, P, P, P, P]
+        L.orc_short_range_vjp.argtypes = [G, i, P, P, P, i, P, P, P]
         L.orc_short_range_vjp.restype = None
+        L.orc_short_range_vjp_cells.argtypes = [G, i, P, P, P, P, P]
+        L.orc_short_range_vjp_cells.restype = None
         L.orc_direct_coulomb.argtypes = [i, P, P, P, P]
         L.orc_direct_coulomb.restype = None
         for name in ("orc_ewald3d", "orc_ewald2d"):
@@ -478,16 +480,38 @@ class OracleMSM:
         phi = phi0 + phi1 - qs * self.self_constant()
         return phi, F0 + F1
 
-    def backward(self, pos, q, gE, v):
+    def short_range_vjp(self, pos, q, v, sel=None, cells=None):
+        """Cotangents of sum_i v_i . F0_i (short-range forces): (dq, dr), for
+        all particles or the listed ones (brute force over all partners)."""
+        pos, q, v = _f64(pos), _f64(q), _f64(v)
+        n = len(q)
+        if sel is None:
+            sq = np.zeros(n)
+            sr = np.zeros((n, 3))
+            if cells is None:
+                cells = n > 4000
+            if cells:
+                lib().orc_short_range_vjp_cells(self._gp, n, _ptr(pos), _ptr(q), _ptr(v),
+                                                _ptr(sq), _ptr(sr))
+            else:
+                lib().orc_short_range_vjp(self._gp, n, _ptr(pos), _ptr(q), _ptr(v), -1, None,
+                                          _ptr(sq), _ptr(sr))
+        else:
+            sel = np.ascontiguousarray(sel, dtype=np.int32)
+            sq = np.zeros(len(sel))
+            sr = np.zeros((len(sel), 3))
+            lib().orc_short_range_vjp(self._gp, n, _ptr(pos), _ptr(q), _ptr(v), len(sel),
+                                      _ptr(sel), _ptr(sq), _ptr(sr))
+        return sq, sr
+
+    def backward(self, pos, q, gE, v, cells=None):
         """Cotangents (dL/dq, dL/dr) of L = gE * E + sum_i v_i . F_i."""
         pos, q, v = _f64(pos), _f64(q), _f64(v)
         res = self.compute(pos, q)
         n = len(q)
         gq = gE * res["phi"].copy()
         gr = -gE * res["F"].copy()
-        sq = np.zeros(n)
-        sr = np.zeros((n, 3))
-        lib().orc_short_range_vjp(self._gp, n, _ptr(pos), _ptr(q), _ptr(v), _ptr(sq), _ptr(sr))
+        sq, sr = self.short_range_vjp(pos, q, v, cells=cells)
         for l in range(1, self.L + 1):
             psi = res["grids"][l - 1][1]
             D = self.dipole_charge(l, pos, q, v)
@@ -495,3 +519,22 @@ class OracleMSM:
             lib().orc_interpolate_vjp(self._gp, l, n, _ptr(pos), _ptr(q), _ptr(v), _ptr(psi),
                                       _ptr(psiD), _ptr(sq), _ptr(sr))
         return gq + sq, gr + sr
+
+    def sampled_backward(self, pos, q, gE, v, sel):
+        """backward() for the listed particles only: the grid charges and
+        dipole grids of every level come from all particles, the level
+        potentials are evaluated only at the grid points the listed
+        particles touch (full-size parity)."""
+        pos, q, v = _f64(pos), _f64(q), _f64(v)
+        self.check_domain(pos)
+        sel = np.asarray(sel, dtype=np.int64)
+        phi, F = self.sampled(pos, q, sel)
+        sq, sr = self.short_range_vjp(pos, q, v, sel=sel)
+        ps, qs, vs = _f64(pos[sel]), _f64(q[sel]), _f64(v[sel])
+        for l in range(1, self.L + 1):
+            pts = self.support_points(l, ps)
+            psi = self.level_potential(l, self.grid_charge(l, pos, q), points=pts)
+            psiD = self.level_potential(l, self.dipole_charge(l, pos, q, v), points=pts)
+            lib().orc_interpolate_vjp(self._gp, l, len(sel), _ptr(ps), _ptr(qs), _ptr(vs),
+                                      _ptr(psi), _ptr(psiD), _ptr(sq), _ptr(sr))
+        return gE * phi + sq, -gE * F + sr

@@ -715,8 +715,8 @@ msm_status msm_plan_grid_dims(msm_plan plan, int level, int n[3]) {
   return MSM_OK;
 }
 
-size_t msm_workspace_bytes(msm_plan plan, int n) {
-  if (!plan || n < 0 || plan->batch) return 0;
+size_t msm_workspace_bytes(msm_plan plan, int n, int flags) {
+  if (!plan || n < 0 || plan->batch || flags != 0) return 0;
   return ws_layout(plan, n).total;
 }
 

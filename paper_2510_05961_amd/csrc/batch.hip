@@ -657,12 +657,33 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
 // Times every convolution of the plan (each level's intermediate and top
 // kernels: their grids differ in size) for every tile shape on the plan's
 // (zero) grids and keeps the fastest shape per convolution.
+// MSM_BATCH_TILE=c (0, 1 or 2) pins shape c for every convolution instead.
 template <typename T>
 static msm_status autotune(msm_plan P) {
   BatchState& B = *P->bs;
+  const char* pin = std::getenv("MSM_BATCH_TILE");
+  if (pin && pin[0] >= '0' && pin[0] <= '2' && pin[1] == 0) {
+    std::ostringstream log;
+    for (size_t ci = 0; ci < B.convs.size(); ++ci) {
+      B.convs[ci].cfg = pin[0] - '0';
+      log << (ci ? "," : "") << "{\"level\":" << B.convs[ci].level << ",\"top\":"
+          << B.convs[ci].top << ",\"pinned\":true,\"cfg\":" << B.convs[ci].cfg << "}";
+    }
+    B.tile_cfg = B.convs.empty() ? 0 : B.convs[0].cfg;
+    B.tuning = "[" + log.str() + "]";
+    return MSM_OK;
+  }
   hipStream_t s = nullptr;
-  hipEvent_t a, b;
-  if (hipEventCreate(&a) || hipEventCreate(&b)) return MSM_ERR_HIP;
+  hipEvent_t a = nullptr, b = nullptr;
+  ConvTask* dt = nullptr;
+  // every exit releases the events and the trial task list
+  auto done = [&](msm_status st) {
+    if (dt) (void)hipFree(dt);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return st;
+  };
+  if (hipEventCreate(&a) || hipEventCreate(&b)) return done(MSM_ERR_HIP);
   std::ostringstream log;
   for (size_t ci = 0; ci < B.convs.size(); ++ci) {
     BatchConv& bc = B.convs[ci];
@@ -671,12 +692,14 @@ static msm_status autotune(msm_plan P) {
     log << (ci ? "," : "") << "{\"level\":" << bc.level << ",\"top\":" << bc.top << ",\"ms\":[";
     for (int cfg = 0; cfg < 3; ++cfg) {
       std::vector<ConvTask> t = build_tasks(B, bc.level, bc.top, cfg);
-      ConvTask* dt = nullptr;
-      if (hipMalloc((void**)&dt, std::max<size_t>(t.size(), 1) * sizeof(ConvTask)))
-        return MSM_ERR_OOM;
+      if (hipMalloc((void**)&dt, std::max<size_t>(t.size(), 1) * sizeof(ConvTask))) {
+        dt = nullptr;
+        (void)hipGetLastError();
+        return done(MSM_ERR_OOM);
+      }
       if (!t.empty() &&
           hipMemcpy(dt, t.data(), t.size() * sizeof(ConvTask), hipMemcpyHostToDevice))
-        return MSM_ERR_HIP;
+        return done(MSM_ERR_HIP);
       BatchConv trial = bc;
       trial.tasks = dt;
       trial.ntasks = (int)t.size();
@@ -686,10 +709,11 @@ static msm_status autotune(msm_plan P) {
       (void)hipEventRecord(a, s);
       for (int r = 0; r < 3; ++r) launch_batch_conv<T>(trial, cfg, q, e, s);
       (void)hipEventRecord(b, s);
-      (void)hipEventSynchronize(b);
+      if (hipEventSynchronize(b)) return done(MSM_ERR_HIP);
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, a, b);
       (void)hipFree(dt);
+      dt = nullptr;
       log << (cfg ? "," : "") << ms / 3;
       if (ms < best) {
         best = ms;
@@ -699,12 +723,10 @@ static msm_status autotune(msm_plan P) {
     bc.cfg = best_cfg;
     log << "],\"cfg\":" << best_cfg << "}";
   }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
-  if (hipGetLastError() != hipSuccess) return MSM_ERR_HIP;
+  if (hipGetLastError() != hipSuccess) return done(MSM_ERR_HIP);
   B.tile_cfg = B.convs.empty() ? 0 : B.convs[0].cfg;
   B.tuning = "[" + log.str() + "]";
-  return MSM_OK;
+  return done(MSM_OK);
 }
 
 template <typename T>
@@ -803,13 +825,21 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
 using namespace msm;
 
 extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const double* boxes,
-                                            const int* levels, int order, double h,
-                                            double cutoff_a, int precision, int max_total_n,
-                                            int quasi_degree_M) {
+                                            const int* levels, unsigned periodic_mask, int order,
+                                            double h, double cutoff_a, int precision,
+                                            int max_total_n, int quasi_degree_M) {
   if (!out) return MSM_ERR_INVALID_ARG;
   *out = nullptr;
   if (n_sys < 1 || !boxes || !levels || !(h > 0) || !(cutoff_a > 0) || max_total_n < 0)
     return MSM_ERR_INVALID_ARG;
+  // the batched kernels take free-space systems in cubic boxes
+  if (periodic_mask != 0) return MSM_ERR_UNSUPPORTED;
+  for (int s = 0; s < n_sys; ++s) {
+    const double* b = boxes + 3 * (size_t)s;
+    if (!(b[0] > 0) || !std::isfinite(b[0])) return MSM_ERR_INVALID_ARG;
+    if (std::fabs(b[1] - b[0]) > 1e-12 * b[0] || std::fabs(b[2] - b[0]) > 1e-12 * b[0])
+      return MSM_ERR_UNSUPPORTED;
+  }
   if (precision != MSM_FP32 && precision != MSM_FP64) return MSM_ERR_INVALID_ARG;
   if (order != 4 && order != 6 && order != 8) return MSM_ERR_UNSUPPORTED;
   const int M = quasi_degree_M < 0 ? order : quasi_degree_M;
@@ -838,7 +868,8 @@ extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const doub
     B.a = cutoff_a;
     B.precision = precision;
     B.max_total_n = max_total_n;
-    B.box.assign(boxes, boxes + n_sys);
+    B.box.resize(n_sys);
+    for (int s = 0; s < n_sys; ++s) B.box[s] = boxes[3 * (size_t)s];
     B.L.assign(levels, levels + n_sys);
     for (int s = 0; s < n_sys; ++s) {
       if (!(B.box[s] > 0) || !std::isfinite(B.box[s]) || B.L[s] < 1 || B.L[s] > kMaxLevels)
@@ -905,10 +936,11 @@ extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const doub
 }
 
 extern "C" msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets, const void* pos,
-                                              const void* q, double* energies, void* forces,
-                                              void* dEdq, void* stream) {
+                                              const void* q, void* ws, double* energies,
+                                              void* forces, void* dEdq, void* stream) {
   if (!plan || !plan->batch || !plan->bs) return MSM_ERR_INVALID_ARG;
   if (!offsets || !pos || !q || !energies) return MSM_ERR_INVALID_ARG;
+  if (ws) return MSM_ERR_UNSUPPORTED;  // there is no batched backward to save state for
   BatchState& B = *plan->bs;
   hipStream_t s = (hipStream_t)stream;
   const void* key[7] = {offsets, pos, q, energies, forces, dEdq, (const void*)s};

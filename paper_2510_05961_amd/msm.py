@@ -53,14 +53,14 @@ def lib():
         L.msm_plan_describe.argtypes = [P, ctypes.c_char_p, sz]
         L.msm_plan_get_stencil.argtypes = [P, i, P, P, sz]
         L.msm_plan_grid_dims.argtypes = [P, i, P]
-        L.msm_workspace_bytes.argtypes = [P, i]
+        L.msm_workspace_bytes.argtypes = [P, i, i]
         L.msm_workspace_bytes.restype = sz
         L.msm_energy_forces.argtypes = [P, i, P, P, P, P, P, P, P]
         L.msm_backward.argtypes = [P, i, P, P, P, P, P, P, P, P]
         L.msm_plan_status.argtypes = [P, P]
         L.msm_plan_get_grid.argtypes = [P, i, i, P, P]
-        L.msm_batch_plan_create.argtypes = [pp, i, P, P, i, d, d, i, i, i]
-        L.msm_batch_energy_forces.argtypes = [P, P, P, P, P, P, P, P]
+        L.msm_batch_plan_create.argtypes = [pp, i, P, P, u, i, d, d, i, i, i]
+        L.msm_batch_energy_forces.argtypes = [P, P, P, P, P, P, P, P, P]
         L.msm_plan_set_profiling.argtypes = [P, i]
         L.msm_plan_get_profile.argtypes = [P, ctypes.c_char_p, sz, i]
         L.msm_plan_set_profile_stages.argtypes = [P, ctypes.c_char_p]
@@ -148,7 +148,7 @@ class Plan:
         return tuple(n)
 
     def workspace_bytes(self, n):
-        return int(lib().msm_workspace_bytes(self._h, int(n)))
+        return int(lib().msm_workspace_bytes(self._h, int(n), 0))
 
     def energy_forces(self, pos, q, ws=None, want_forces=True, want_dEdq=True, stream=None,
                       out=None):
@@ -205,15 +205,20 @@ class BatchPlan:
     """Many free-space systems in one launch sequence (msm_batch_plan_create)."""
 
     def __init__(self, boxes, levels, order, h, cutoff, precision=MSM_FP32, max_total_n=1,
-                 quasi_degree=-1):
+                 quasi_degree=-1, periodic_mask=0):
+        """boxes: [n_sys, 3] edge lengths, or [n_sys] edges of cubes."""
         import numpy as np
         self._h = ctypes.c_void_p()
-        b = np.ascontiguousarray(boxes, dtype=np.float64)
+        b = np.asarray(boxes, dtype=np.float64)
+        if b.ndim == 1:
+            b = np.stack([b, b, b], axis=1)
+        b = np.ascontiguousarray(b)
         lv = np.ascontiguousarray(levels, dtype=np.int32)
         self.n_sys = len(b)
         _check(lib().msm_batch_plan_create(ctypes.byref(self._h), self.n_sys,
                                            b.ctypes.data_as(ctypes.c_void_p),
-                                           lv.ctypes.data_as(ctypes.c_void_p), int(order),
+                                           lv.ctypes.data_as(ctypes.c_void_p),
+                                           int(periodic_mask), int(order),
                                            float(h), float(cutoff), int(precision),
                                            int(max_total_n), int(quasi_degree)),
                "msm_batch_plan_create")
@@ -240,7 +245,7 @@ class BatchPlan:
             dq = torch.empty(n, dtype=self.dtype, device=pos.device)
         else:
             E, F, dq = out
-        _check(lib().msm_batch_energy_forces(self._h, _ptr(offsets), _ptr(pos), _ptr(q), _ptr(E),
+        _check(lib().msm_batch_energy_forces(self._h, _ptr(offsets), _ptr(pos), _ptr(q), None, _ptr(E),
                                              _ptr(F), _ptr(dq), _stream(stream)),
                "msm_batch_energy_forces")
         return E, F, dq

@@ -30,6 +30,28 @@ def rel_rms(a, b):
     return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))
 
 
+def per_particle_ratio(a, b):
+    """max_i |a_i - b_i| / rms_i |b_i| (rows of [n,3] arrays, elements of
+    [n] arrays): the worst particle against the typical magnitude."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    if b.ndim == 1:
+        a, b = a[:, None], b[:, None]
+    if len(b) == 0:
+        return 0.0
+    err = np.linalg.norm(a - b, axis=1)
+    rms = math.sqrt(float(np.mean(np.sum(b * b, axis=1))))
+    return float(err.max() / rms) if rms > 0 else float(err.max())
+
+
+def assert_parity(a, b, bar, what=""):
+    """The parity bar on relative RMS error, and a per-particle bound: no
+    particle may be off by more than 10 x bar x the RMS magnitude (so a few
+    wrong particles cannot hide under a global RMS)."""
+    e, m = rel_rms(a, b), per_particle_ratio(a, b)
+    assert e <= bar and m <= 10 * bar, f"{what}: rel RMS {e:.3e}, worst particle {m:.3e} (bar {bar:g})"
+    return e, m
+
+
 def gpu_forward(plan, pos, q, ws=False):
     import torch
     dt = plan.dtype

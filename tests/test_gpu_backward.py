@@ -7,7 +7,7 @@ from oracle import oracle as O
 from paper_2510_05961_amd import msm
 from paper_2510_05961_amd import workloads as WL
 
-from helpers import TOL, cast, config_case, mask_of, rel_rms
+from helpers import TOL, assert_parity, cast, config_case, mask_of, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -52,12 +52,13 @@ def test_backward_matches_oracle_adjoint(case):
     tol = TOL["fp64" if fp64 else "fp32"]["F"]
     e_pos, e_q = rel_rms(gpos, rpos), rel_rms(gq, rq)
     print(f"  grad_pos rel={e_pos:.2e} grad_q rel={e_q:.2e}", flush=True)
-    assert e_pos <= tol and e_q <= tol
+    assert_parity(gpos, rpos, tol, "grad_pos")
+    assert_parity(gq, rq, tol, "grad_q")
     # energy-only cotangent path
     gpos0, gq0 = _gpu_fwd_bwd(plan, pos, q, 1.3, None)
     ref = O.OracleMSM(box, per, p, h, a, L).compute(pos, q)
-    assert rel_rms(gq0, 1.3 * ref["phi"]) <= tol
-    assert rel_rms(gpos0, -1.3 * ref["F"]) <= tol
+    assert_parity(gq0, 1.3 * ref["phi"], tol, "grad_q (gE only)")
+    assert_parity(gpos0, -1.3 * ref["F"], tol, "grad_pos (gE only)")
 
 
 @pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[3]])
@@ -80,7 +81,8 @@ def test_backward_super_cell_bricks(case):
         del os.environ["MSM_BRICK_CELLS"]
     rq, rpos = O.OracleMSM(box, per, p, h, a, L).backward(pos, q, 0.7, v)
     tol = TOL["fp64" if fp64 else "fp32"]["F"]
-    assert rel_rms(gpos, rpos) <= tol and rel_rms(gq, rq) <= tol
+    assert_parity(gpos, rpos, tol, "grad_pos")
+    assert_parity(gq, rq, tol, "grad_q")
 
 
 def test_backward_finite_differences_fp64():
@@ -154,4 +156,26 @@ def test_config4_autograd_vs_oracle(cfg, scale):
     e_pos = rel_rms(P.grad.double().cpu().numpy(), rpos)
     e_q = rel_rms(Q.grad.double().cpu().numpy(), rq)
     print(f"config4 reduced n={n}: grad_pos rel={e_pos:.2e} grad_q rel={e_q:.2e}", flush=True)
-    assert e_pos <= TOL["fp32"]["F"] and e_q <= TOL["fp32"]["F"]
+    assert_parity(P.grad.double().cpu().numpy(), rpos, TOL["fp32"]["F"], "grad_pos")
+    assert_parity(Q.grad.double().cpu().numpy(), rq, TOL["fp32"]["F"], "grad_q")
+
+
+def test_config4_full_size_backward_sampled():
+    """The differentiation workload at full size (200,000 Gaussian charges,
+    60 A periodic cube, p = 4, h = 1.5, a = 10, L = 4, FP32): forward and
+    msm_backward with gE = 1 and gF ~ N(0, 1) (seed 40) against the oracle's
+    adjoint at 32 sampled charges."""
+    import torch
+    pos, q, box, per, p, h, a, L, fp64 = config_case(4, 1.0)
+    pos, q = cast(pos, q, False)
+    n = len(q)
+    v = WL.force_cotangent(n, seed=40).astype(np.float32).astype(np.float64)
+    print(f"config4 full size n={n}", flush=True)
+    plan = msm.Plan(box, mask_of(per), p, h, a, L, msm.MSM_FP32, n)
+    gpos, gq = _gpu_fwd_bwd(plan, pos, q, 1.0, v)
+    sel = np.random.default_rng(44).choice(n, 32, replace=False)
+    rq, rpos = O.OracleMSM(box, per, p, h, a, L).sampled_backward(pos, q, 1.0, v, sel)
+    e_pos, e_q = rel_rms(gpos[sel], rpos), rel_rms(gq[sel], rq)
+    print(f"  sampled grad_pos rel={e_pos:.2e} grad_q rel={e_q:.2e}", flush=True)
+    assert_parity(gpos[sel], rpos, TOL["fp32"]["F"], "grad_pos")
+    assert_parity(gq[sel], rq, TOL["fp32"]["F"], "grad_q")

@@ -9,7 +9,7 @@ from oracle import oracle as O
 from paper_2510_05961_amd import msm
 from paper_2510_05961_amd import workloads as WL
 
-from helpers import TOL, rel_rms
+from helpers import TOL, assert_parity, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -47,10 +47,10 @@ def test_batch_matches_oracle_per_system(fp64):
         b3 = (boxes[s],) * 3
         ref = O.OracleMSM(b3, (0, 0, 0), 4, 1.0, 3.0, int(levels[s])).compute(pos[a:b], q[a:b])
         if b - a >= 2:
-            assert rel_rms(F[a:b], ref["F"]) <= tol["F"], s
+            assert_parity(F[a:b], ref["F"], tol["F"], f"F of system {s}")
         assert abs(E[s] - ref["E"]) <= tol["E"] * max(abs(ref["E"]), 1e-3), s
         if b > a:
-            assert rel_rms(dq[a:b], ref["phi"]) <= tol["phi"], s
+            assert_parity(dq[a:b], ref["phi"], tol["phi"], f"phi of system {s}")
 
 
 def test_batch_equals_single_system_plans():
@@ -129,6 +129,6 @@ def test_batch_full_size_sampled():
         print(f"system {s}: n={b - a} box={boxes[s]:.2f} L={levels[s]}", flush=True)
         ref = O.OracleMSM((boxes[s],) * 3, (0, 0, 0), 4, 1.0, 6.0, int(levels[s])).compute(
             pos32[a:b].astype(np.float64), qd[a:b])
-        assert rel_rms(F[a:b], ref["F"]) <= tol["F"], s
+        assert_parity(F[a:b], ref["F"], tol["F"], f"F of system {s}")
         assert abs(E[s] - ref["E"]) <= tol["E"] * max(abs(ref["E"]), 1e-3), s
-        assert rel_rms(dq[a:b], ref["phi"]) <= tol["phi"], s
+        assert_parity(dq[a:b], ref["phi"], tol["phi"], f"phi of system {s}")

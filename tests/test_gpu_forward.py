@@ -13,7 +13,7 @@ from oracle import oracle as O
 from paper_2510_05961_amd import msm
 from paper_2510_05961_amd import workloads as WL
 
-from helpers import TOL, cast, config_case, gpu_forward, mask_of, periodic_of, rel_rms
+from helpers import TOL, assert_parity, cast, config_case, gpu_forward, mask_of, periodic_of, rel_rms
 
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +34,10 @@ def _run(pos, q, box, periodic, p, h, a, L, fp64, M=None, check_phi=True):
     ePhi = rel_rms(g["phi"], ref["phi"])
     print(f"  E gpu={g['E']:.12g} ref={ref['E']:.12g} relE={eE:.2e} relF={eF:.2e} "
           f"relPhi={ePhi:.2e}", flush=True)
-    assert eF <= tol["F"]
+    assert_parity(g["F"], ref["F"], tol["F"], "F")
     assert eE <= tol["E"]
     if check_phi:
-        assert ePhi <= tol["phi"]
+        assert_parity(g["phi"], ref["phi"], tol["phi"], "phi")
     return plan, g, ref
 
 
@@ -180,7 +180,8 @@ def test_full_size_sampled(cfg):
     eF = rel_rms(g["F"][sel], F_r)
     eP = rel_rms(g["phi"][sel], phi_r)
     print(f"  sampled relF={eF:.2e} relPhi={eP:.2e}", flush=True)
-    assert eF <= TOL["fp32"]["F"] and eP <= TOL["fp32"]["phi"]
+    assert_parity(g["F"][sel], F_r, TOL["fp32"]["F"], "F")
+    assert_parity(g["phi"][sel], phi_r, TOL["fp32"]["phi"], "phi")
 
 
 @pytest.mark.parametrize("n", [100_000, 600_000])
@@ -207,7 +208,8 @@ def test_large_grid_sampled(n):
     phi_r, F_r = O.OracleMSM(box, (1, 1, 1), 4, 1.0, 3.0, 5).sampled(pos, q, sel)
     eF, eP = rel_rms(g["F"][sel], F_r), rel_rms(g["phi"][sel], phi_r)
     print(f"  sampled relF={eF:.2e} relPhi={eP:.2e}", flush=True)
-    assert eF <= TOL["fp32"]["F"] and eP <= TOL["fp32"]["phi"]
+    assert_parity(g["F"][sel], F_r, TOL["fp32"]["F"], "F")
+    assert_parity(g["phi"][sel], phi_r, TOL["fp32"]["phi"], "phi")
 
 
 @pytest.mark.parametrize("fp64", [True, False])
@@ -308,7 +310,8 @@ def test_super_cell_bricks(fp64, geom):
     ref = O.OracleMSM(box, per, p, h, a, L).compute(pos, q)
     t = TOL["fp64" if fp64 else "fp32"]
     assert abs(res[4]["E"] - ref["E"]) <= t["E"] * abs(ref["E"])
-    assert rel_rms(res[4]["F"], ref["F"]) <= t["F"]
+    assert_parity(res[4]["F"], ref["F"], t["F"], "F")
+    assert_parity(res[4]["phi"], ref["phi"], t["phi"], "phi")
 
 
 @pytest.mark.parametrize("fp64", [True, False])
@@ -353,7 +356,8 @@ def test_anterp_tiles(fp64, geom):
     ref = O.OracleMSM(box, per, p, h, a, L).compute(pos, q)
     t = TOL["fp64" if fp64 else "fp32"]
     assert abs(res["1"]["E"] - ref["E"]) <= t["E"] * abs(ref["E"])
-    assert rel_rms(res["1"]["F"], ref["F"]) <= t["F"]
+    assert_parity(res["1"]["F"], ref["F"], t["F"], "F")
+    assert_parity(res["1"]["phi"], ref["phi"], t["phi"], "phi")
 
 
 @pytest.mark.parametrize("fp64", [True, False])

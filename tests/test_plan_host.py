@@ -131,3 +131,27 @@ def test_parameter_errors():
                                None, None)
     assert rc == 10
     assert lib.msm_plan_destroy(h) == 0
+
+
+def test_workspace_and_batch_boundary_errors():
+    """Host-side argument checks of the workspace query and the batched
+    entry points (no GPU is touched: they fail before any device call)."""
+    lib = msm.lib()
+    h = ctypes.c_void_p()
+    box = (ctypes.c_double * 3)(10, 10, 10)
+    assert lib.msm_plan_create_host(ctypes.byref(h), box, 0, 4, 1.0, 3.0, 2, 0, 100, -1) == 0
+    assert lib.msm_workspace_bytes(h, 100, 0) > 0
+    assert lib.msm_workspace_bytes(h, 100, 1) == 0   # reserved flags
+    assert lib.msm_workspace_bytes(h, -1, 0) == 0
+    assert lib.msm_workspace_bytes(None, 100, 0) == 0
+    lib.msm_plan_destroy(h)
+    boxes = (ctypes.c_double * 6)(10, 10, 10, 12, 12, 12)
+    levels = (ctypes.c_int * 2)(2, 2)
+    args = (4, 1.0, 3.0, 0, 100, -1)
+    assert lib.msm_batch_plan_create(ctypes.byref(h), 2, boxes, levels, 7, *args) == 2
+    assert lib.msm_batch_plan_create(ctypes.byref(h), 2, boxes, levels, 3, *args) == 2
+    oblong = (ctypes.c_double * 6)(10, 10, 10, 12, 12, 13)
+    assert lib.msm_batch_plan_create(ctypes.byref(h), 2, oblong, levels, 0, *args) == 2
+    bad = (ctypes.c_double * 6)(10, 10, 10, -1, -1, -1)
+    assert lib.msm_batch_plan_create(ctypes.byref(h), 2, bad, levels, 0, *args) == 1
+    assert lib.msm_batch_plan_create(ctypes.byref(h), 0, boxes, levels, 0, *args) == 1
