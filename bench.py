@@ -1,20 +1,32 @@
 #!/usr/bin/env python3
 """MSM energy+forces throughput on one MI355X (libmsm, HIP kernels).
 
-Workload: the periodic water box -- 33,333 rigid 3-site molecules (99,999
-charges) in a 100 A cubic box (0.1 sites/A^3), FP32, cubic B-splines (p = 4),
-h = 1.5 A requested (1.5625 A on the 64^3 level-1 grid), cutoff a = 10 A,
-L = 5 grid levels (top grid 4^3).  Inputs are synthetic (seeded) and resident
-in HBM before the timed region.  One step = one msm_energy_forces call (all
-stages: binning, pair sum, anterpolation, restriction, stencil convolution
-per level, top level, prolongation, interpolation, FP64 energy).
+Headline workload: the mixed-periodicity slab -- 10^6 point charges +-1
+(neutral) uniform in a 100 x 100 x 60 A box, periodic in x and y, free in z,
+FP32, quintic B-splines (p = 6), h = 1.25 A, cutoff a = 12 A, L = 5 grid
+levels: the largest configuration that fits one GPU.  Inputs are synthetic
+(seeded) and resident in HBM before the timed region.  One step = one
+msm_energy_forces call (all stages: binning and cluster layout, pair sum,
+anterpolation, restriction, stencil convolution per level, top level,
+prolongation, interpolation, FP64 energy), timed with profiling off.
 
-Prints ONE JSON line (see the keys below).  --gpus N with N > 1 exits: this
-build runs on one GPU.
+The roofline of the dominant kernel comes from per-stage HIP events with
+every stage on one stream (no overlap), so each duration is the kernel's
+own; algorithmic work: 28 + 4p flops per unique pair within the cutoff for
+the pair sum, 2 flops per (output, in-grid input) pair with a non-zero
+coefficient for a convolution.
+
+Extras (each with its error against the FP64 oracle): the periodic water box,
+the learnable-charge box forward vs forward + backward (and through
+torch.autograd), the 4,096-cluster batch vs one plan per system, the
+free-space FP64 ion cloud, and the grid-pass HBM sweep.
+
+Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,21 +44,42 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
-def _pair_count(pos, box, a):
-    """Unique pairs closer than a (minimum image) for the algorithmic pair work."""
-    from scipy.spatial import cKDTree
+def _pos_key(pos32):
     import numpy as np
-    p = np.mod(pos, box)
-    t = cKDTree(p, boxsize=box)
-    return int((t.count_neighbors(t, a) - len(p)) // 2)
+    return hashlib.sha256(np.ascontiguousarray(pos32, dtype=np.float32).tobytes()).hexdigest()[:16]
 
 
-def _measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE
-    counter runs recorded in profiles/, or None when that kernel's source has
-    changed since (first 16 hex digits of the file's SHA-256 differ)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_water100k_fp32.md")
+def _pair_count(cfg, pos32):
+    """Unique pairs within the cutoff of workload cfg's FP32 input, from
+    tests/golden/pair_counts.json (exact k-d tree counts written by
+    tests/golden/make_pair_counts.py), or None if the input differs."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "tests", "golden", "pair_counts.json")))[str(cfg)]
+    except (OSError, KeyError, ValueError):
+        return None
+    return int(rec["pairs"]) if rec.get("positions_sha256_16") == _pos_key(pos32) else None
+
+
+def _golden_energy(cfg, pos32, q32):
+    """FP64 oracle energy of the full-size workload (tests/golden), or None."""
+    import numpy as np
+    try:
+        rec = json.load(open(os.path.join(ROOT, "tests", "golden",
+                                          "full_size_energies.json")))[str(cfg)]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(pos32, dtype=np.float32).tobytes())
+    h.update(np.ascontiguousarray(q32, dtype=np.float32).tobytes())
+    return float(rec["E"]) if rec.get("input_sha256_16") == h.hexdigest()[:16] else None
+
+
+def _measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the FETCH_SIZE /
+    WRITE_SIZE counter runs in profiles/traffic_<workload>.md, or None when
+    that kernel's source has changed since (first 16 hex digits of the
+    file's SHA-256 differ)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
     try:
         line = next(l for l in open(path) if l.startswith("traffic-json: "))
         rec = json.loads(line[len("traffic-json: "):])[kernel]
@@ -68,72 +101,251 @@ def _time(fn, torch, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def _autograd_vs_plain(torch, msm, WL, np):
+def _rel(a, b):
+    import numpy as np
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _worst(a, b):
+    """Worst particle's error over the RMS reference magnitude."""
+    import numpy as np
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    if b.ndim == 1:
+        a, b = a[:, None], b[:, None]
+    return float(np.linalg.norm(a - b, axis=1).max() / np.sqrt(np.mean(np.sum(b * b, axis=1))))
+
+
+class Workload:
+    """One single-system workload on the GPU: seeded inputs, plan, outputs."""
+
+    def __init__(self, cfg, torch, msm, WL, np):
+        self.cfg = cfg
+        self.c = c = WL.WORKLOADS[cfg]
+        pos64, q64, self.box = WL.make_config(cfg, 1.0)
+        dt = np.float64 if c["fp64"] else np.float32
+        self.pos_t, self.q_t = pos64.astype(dt), q64.astype(dt)
+        self.pos64, self.q64 = self.pos_t.astype(np.float64), self.q_t.astype(np.float64)
+        self.n = n = len(q64)
+        tdt = torch.float64 if c["fp64"] else torch.float32
+        dev = torch.device("cuda:0")
+        self.P = torch.from_numpy(self.pos_t).to(dev).contiguous()
+        self.Q = torch.from_numpy(self.q_t).to(dev).contiguous()
+        self.plan = msm.Plan(self.box, c["periodic"], c["p"], c["h"], c["a"], c["L"],
+                             msm.MSM_FP64 if c["fp64"] else msm.MSM_FP32, n)
+        self.E = torch.empty(1, dtype=torch.float64, device=dev)
+        self.F = torch.empty((n, 3), dtype=tdt, device=dev)
+        self.dq = torch.empty(n, dtype=tdt, device=dev)
+        self.torch = torch
+
+    def step(self):
+        self.plan.energy_forces(self.P, self.Q, out=(self.E, self.F, self.dq))
+
+    def timed(self, steps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        if self.plan.status() != 0:
+            raise RuntimeError(f"device error flag set in workload {self.cfg}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    def stages(self, steps, names=None, one_stream=True):
+        """Per-stage ms per call from the plan's HIP events (one stream: each
+        stage's own duration)."""
+        torch = self.torch
+        if one_stream:
+            os.environ["MSM_STREAMS"] = "0"
+        try:
+            self.plan.set_profile_stages(names)
+            self.plan.profile(reset=True)
+            self.plan.set_profiling(True)
+            for _ in range(steps):
+                self.step()
+            torch.cuda.synchronize()
+            self.plan.set_profiling(False)
+            prof = self.plan.profile(reset=True)
+        finally:
+            if one_stream:
+                del os.environ["MSM_STREAMS"]
+        return prof
+
+    def oracle(self, O):
+        c = self.c
+        per = [bool((c["periodic"] >> k) & 1) for k in range(3)]
+        return O.OracleMSM(self.box, per, c["p"], c["h"], c["a"], c["L"])
+
+
+def _rooflines(w, stages, npairs):
+    """Kernel rooflines from the one-stream stage times: the pair sum
+    against FP32 peak, the level-1 convolution against FP64 peak (it
+    accumulates in FP64)."""
+    desc = w.plan.describe()
+    l1 = desc["levels_info"][0]
+    G1 = l1["n"][0] * l1["n"][1] * l1["n"][2]
+    if l1.get("factored"):
+        conv_flops = 2.0 * l1["ext"][0] * l1["ext"][1] * l1["ext"][2] * l1["samples_nnz"]
+    else:
+        conv_flops = 2.0 * G1 * l1["stencil_nnz"]
+    per = {k: v["ms"] / max(v["launches"], 1) for k, v in stages.items()}
+    out = {}
+    if npairs is not None and "pair" in per:
+        fl = (28 + 4 * w.c["p"]) * npairs
+        a = fl / (per["pair"] * 1e-3) / 1e12
+        out["pair"] = {"bound": "alu", "kernel": f"k_pair_pc<{'double' if w.c['fp64'] else 'float'}, "
+                                                 f"{w.c['p']}>",
+                       "achieved": round(a, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(a / PEAK_FP32_VECTOR_TFLOPS, 4),
+                       "algorithmic_per_launch": fl, "unique_pairs_in_cutoff": npairs,
+                       "flops_per_pair": 28 + 4 * w.c["p"], "avg_launch_ms": round(per["pair"], 5)}
+    if "conv_l1" in per:
+        a = conv_flops / (per["conv_l1"] * 1e-3) / 1e12
+        out["conv_l1"] = {"bound": "alu", "kernel": "k_conv (level 1)", "achieved": round(a, 3),
+                          "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                          "frac": round(a / PEAK_FP64_TFLOPS, 4),
+                          "algorithmic_per_launch": conv_flops,
+                          "avg_launch_ms": round(per["conv_l1"], 5)}
+    return out
+
+
+def _oracle_sampled_error(w, O, np, nsel, seed):
+    sel = np.sort(np.random.default_rng(seed).choice(w.n, nsel, replace=False))
+    o = w.oracle(O)
+    phi_r, F_r = o.sampled(w.pos64, w.q64, sel)
+    Fg = w.F.double().cpu().numpy()[sel]
+    pg = w.dq.double().cpu().numpy()[sel]
+    return {"sampled_particles": nsel, "force_rel_rms": _rel(Fg, F_r),
+            "force_worst_particle": _worst(Fg, F_r), "phi_rel_rms": _rel(pg, phi_r)}
+
+
+def _cpu_baseline(w, O, np, S, threads):
+    """The oracle (FP64, unchanged) on a linear 1/k share of every part of
+    one full evaluation of the workload: the short-range sums of S random
+    target charges (cell list, all partners), the anterpolation of those S
+    charges onto every level, the level potentials at a random S/N share of
+    every level's grid points, and the interpolation at the S targets.  Each
+    part's work is its full-size work times S/N, so S / time is the full
+    evaluation's particles/s extrapolated linearly."""
+    o = w.oracle(O)
+    L = w.c["L"]
+    for l in range(1, L + 1):
+        o.stencil(l)  # plan-time work, not timed (as on the GPU)
+    rng = np.random.default_rng(1234 + S)
+    sel = np.sort(rng.choice(w.n, S, replace=False))
+    ps, qs = np.ascontiguousarray(w.pos64[sel]), np.ascontiguousarray(w.q64[sel])
+    pts = []
+    for l in range(1, L + 1):
+        G = int(np.prod(o.grid_shape(l)))
+        pts.append(np.sort(rng.choice(G, max(1, round(G * S / w.n)), replace=False)))
+    old = O.num_threads()
+    O.set_num_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        o.short_range(w.pos64, w.q64, sel=sel, cells=True)
+        phi = np.zeros(S)
+        F = np.zeros((S, 3))
+        for l in range(1, L + 1):
+            qg = o.grid_charge(l, ps, qs)
+            eg = o.level_potential(l, qg, points=pts[l - 1])
+            O.lib().orc_interpolate(o._gp, l, S, O._ptr(ps), O._ptr(qs), O._ptr(eg),
+                                    O._ptr(phi), O._ptr(F))
+        dt = time.perf_counter() - t0
+    finally:
+        O.set_num_threads(old)
+    return S / dt, dt
+
+
+def _water(torch, msm, WL, np, O, steps, check):
+    """The periodic water box: 33,333 rigid 3-site molecules (99,999
+    charges), 100 A cube, p = 4, h = 1.5625, a = 10, L = 5, FP32."""
+    w = Workload(2, torch, msm, WL, np)
+    t = w.timed(steps, 5)
+    st = w.stages(min(steps, 20))
+    out = {"workload": "periodic water box, 33,333 rigid 3-site molecules (99,999 charges), "
+                       "100 A cube, p=4, h=1.5625, a=10, L=5, FP32", "n": w.n,
+           "particles_per_s": round(w.n / t, 1), "ms_per_step": round(t * 1e3, 4),
+           "stages_ms_one_stream": {k: round(v["ms"] / v["launches"], 5) for k, v in st.items()},
+           "rooflines": _rooflines(w, st, _pair_count(2, w.pos_t))}
+    if check:
+        ref = w.oracle(O).compute(w.pos64, w.q64)
+        out["energy_rel_err_vs_fp64_oracle"] = abs(w.E.item() - ref["E"]) / abs(ref["E"])
+        out["force_rel_err_vs_fp64_oracle"] = _rel(w.F.double().cpu().numpy(), ref["F"])
+        out["force_worst_particle_vs_fp64_oracle"] = _worst(w.F.double().cpu().numpy(), ref["F"])
+    return out
+
+
+def _free_ions(torch, msm, WL, np, O, check):
+    """The free-space ion cloud: 1,000 charges +-1 in a 20 A cube, FP64, p = 4,
+    h = 2, a = 8, L = 3."""
+    w = Workload(1, torch, msm, WL, np)
+    t = w.timed(50, 5)
+    out = {"workload": "free-space ion cloud, 1,000 charges +-1, 20 A cube, p=4, h=2, a=8, L=3, "
+                       "FP64", "n": w.n, "particles_per_s": round(w.n / t, 1),
+           "ms_per_step": round(t * 1e3, 4)}
+    if check:
+        ref = w.oracle(O).compute(w.pos64, w.q64)
+        out["energy_rel_err_vs_fp64_oracle"] = abs(w.E.item() - ref["E"]) / abs(ref["E"])
+        out["force_rel_err_vs_fp64_oracle"] = _rel(w.F.double().cpu().numpy(), ref["F"])
+        # the MSM's own error: against the exact all-pairs Coulomb sum
+        _, F_exact = O.direct_coulomb(w.pos64, w.q64)
+        out["msm_force_rel_err_vs_exact_coulomb"] = _rel(w.F.double().cpu().numpy(), F_exact)
+    return out
+
+
+def _autograd_vs_plain(torch, msm, WL, np, O, check):
     """Learnable-charge workload (200,000 Gaussian charges, 60 A periodic
     cube, p=4, h=1.5, a=10, L=4, FP32): plain forward vs forward + backward
-    of L = E + sum v.F (v ~ N(0,1))."""
-    cfg = WL.WORKLOADS[4]
-    pos64, q64, box = WL.make_config(4, 1.0)
-    n = len(q64)
-    dev = torch.device("cuda:0")
-    P = torch.tensor(pos64, dtype=torch.float32, device=dev)
-    Q = torch.tensor(q64, dtype=torch.float32, device=dev)
-    v = torch.tensor(WL.force_cotangent(n, seed=40), dtype=torch.float32, device=dev)
-    plan = msm.Plan(box, cfg["periodic"], cfg["p"], cfg["h"], cfg["a"], cfg["L"],
-                    msm.MSM_FP32, n)
-    ws = torch.empty(plan.workspace_bytes(n), dtype=torch.uint8, device=dev)
-    E = torch.empty(1, dtype=torch.float64, device=dev)
-    F = torch.empty((n, 3), dtype=torch.float32, device=dev)
-    dq = torch.empty(n, dtype=torch.float32, device=dev)
+    of L = E + sum v.F (v ~ N(0,1)), and the same through torch.autograd."""
+    w = Workload(4, torch, msm, WL, np)
+    n, dev = w.n, torch.device("cuda:0")
+    v64 = WL.force_cotangent(n, seed=40)
+    v = torch.tensor(v64, dtype=torch.float32, device=dev)
+    ws = torch.empty(w.plan.workspace_bytes(n), dtype=torch.uint8, device=dev)
     gE = torch.ones(1, dtype=torch.float64, device=dev)
-    t_fwd = _time(lambda: plan.energy_forces(P, Q, out=(E, F, dq)), torch, 20)
+    t_fwd = _time(w.step, torch, 20)
+    grads = {}
 
     def fwd_bwd():
-        plan.energy_forces(P, Q, ws=ws, out=(E, F, dq))
-        plan.backward(P, Q, ws, gE=gE, gF=v)
+        w.plan.energy_forces(w.P, w.Q, ws=ws, out=(w.E, w.F, w.dq))
+        grads["pos"], grads["q"] = w.plan.backward(w.P, w.Q, ws, gE=gE, gF=v)
     t_fb = _time(fwd_bwd, torch, 20)
-    # the same through torch.autograd
-    Pg = P.clone().requires_grad_(True)
-    Qg = Q.clone().requires_grad_(True)
+    Pg = w.P.clone().requires_grad_(True)
+    Qg = w.Q.clone().requires_grad_(True)
 
     def autograd_step():
         Pg.grad = None
         Qg.grad = None
-        e, f, _ = msm.energy_forces(Pg, Qg, plan)
+        e, f, _ = msm.energy_forces(Pg, Qg, w.plan)
         (e.sum() + (f * v).sum()).backward()
     t_ag = _time(autograd_step, torch, 10)
-    return {"workload": "200,000 Gaussian charges, 60 A periodic cube, p=4, h=1.5, a=10, L=4, "
-                        "FP32", "n": n,
-            "forward_particles_per_s": round(n / t_fwd, 1),
-            "forward_backward_particles_per_s": round(n / t_fb, 1),
-            "torch_autograd_particles_per_s": round(n / t_ag, 1),
-            "forward_backward_over_forward_time": round(t_fb / t_fwd, 3)}
+    out = {"workload": "200,000 Gaussian charges, 60 A periodic cube, p=4, h=1.5, a=10, L=4, "
+                       "FP32", "n": n,
+           "forward_particles_per_s": round(n / t_fwd, 1),
+           "forward_backward_particles_per_s": round(n / t_fb, 1),
+           "torch_autograd_particles_per_s": round(n / t_ag, 1),
+           "forward_backward_over_forward_time": round(t_fb / t_fwd, 3)}
+    if check:
+        sel = np.sort(np.random.default_rng(41).choice(n, 16, replace=False))
+        o = w.oracle(O)
+        v_t = v64.astype(np.float32).astype(np.float64)
+        rq, rpos = o.sampled_backward(w.pos64, w.q64, 1.0, v_t, sel)
+        gq = grads["q"].double().cpu().numpy()[sel]
+        gp = grads["pos"].double().cpu().numpy()[sel]
+        out["grad_q_rel_err_vs_fp64_oracle_sampled"] = _rel(gq, rq)
+        out["grad_pos_rel_err_vs_fp64_oracle_sampled"] = _rel(gp, rpos)
+        out["sampled_particles"] = len(sel)
+        Eg = _golden_energy(4, w.pos_t, w.q_t)
+        if Eg is not None:
+            out["energy_rel_err_vs_fp64_oracle"] = abs(w.E.item() - Eg) / abs(Eg)
+    return out
 
 
-def _slab(torch, msm, WL, np):
-    """The slab workload: 10^6 charges +-1, 100 x 100 x 60 A, periodic in x
-    and y, p = 6, h = 1.25, a = 12, L = 5, FP32 (pair-dominated: about 5.5e9
-    unique pairs within a)."""
-    cfg = WL.WORKLOADS[3]
-    pos64, q64, box = WL.make_config(3, 1.0)
-    n = len(q64)
-    dev = torch.device("cuda:0")
-    P = torch.tensor(pos64, dtype=torch.float32, device=dev)
-    Q = torch.tensor(q64, dtype=torch.float32, device=dev)
-    plan = msm.Plan(box, cfg["periodic"], cfg["p"], cfg["h"], cfg["a"], cfg["L"],
-                    msm.MSM_FP32, n)
-    E = torch.empty(1, dtype=torch.float64, device=dev)
-    F = torch.empty((n, 3), dtype=torch.float32, device=dev)
-    dq = torch.empty(n, dtype=torch.float32, device=dev)
-    t = _time(lambda: plan.energy_forces(P, Q, out=(E, F, dq)), torch, 10)
-    if plan.status() != 0:
-        raise RuntimeError("device error flag set in the slab workload")
-    return {"workload": "slab, 10^6 charges +-1, 100 x 100 x 60 A, periodic x and y, p=6, "
-                        "h=1.25, a=12, L=5, FP32", "n": n,
-            "particles_per_s": round(n / t, 1), "ms_per_step": round(t * 1e3, 3)}
-
-
-def _batched_vs_plain(torch, msm, WL, np):
+def _batched_vs_plain(torch, msm, WL, np, O, check):
     """4,096 free-space clusters of 8-256 charges in 10-30 A boxes (p=4, h=1,
     a=6, FP32): one batched launch sequence vs one plan per system run one
     after another (timed on the first 256 systems, per particle)."""
@@ -156,19 +368,38 @@ def _batched_vs_plain(torch, msm, WL, np):
                       max(b - a, 1))
         plans.append(pl)
         args_.append((P[a:b], Q[a:b], (torch.empty(1, dtype=torch.float64, device=dev),
-                                       F[a:b], dq[a:b])))
+                                       torch.empty((b - a, 3), dtype=torch.float32, device=dev),
+                                       torch.empty(b - a, dtype=torch.float32, device=dev))))
 
     def plain():
         for pl, (pp, qq, o) in zip(plans, args_):
             pl.energy_forces(pp, qq, out=o)
     t_p = _time(plain, torch, 3)
     n_sub = int(off[ns])
-    return {"workload": "4,096 free-space clusters, 8-256 charges, 10-30 A boxes, p=4, h=1, "
-                        "a=6, FP32", "n_systems": len(boxes), "n": ntot,
-            "batched_particles_per_s": round(ntot / t_b, 1),
-            "plain_particles_per_s": round(n_sub / t_p, 1),
-            "plain_sample_systems": ns,
-            "batched_over_plain": round((ntot / t_b) / (n_sub / t_p), 2)}
+    out = {"workload": "4,096 free-space clusters, 8-256 charges, 10-30 A boxes, p=4, h=1, "
+                       "a=6, FP32", "n_systems": len(boxes), "n": ntot,
+           "batched_particles_per_s": round(ntot / t_b, 1),
+           "plain_particles_per_s": round(n_sub / t_p, 1),
+           "plain_sample_systems": ns,
+           "batched_over_plain": round((ntot / t_b) / (n_sub / t_p), 2)}
+    if check:
+        bp.energy_forces(O_, P, Q, out=(E, F, dq))
+        torch.cuda.synchronize()
+        Eg, Fg = E.cpu().numpy(), F.double().cpu().numpy()
+        sys_sel = np.random.default_rng(6).choice(len(boxes), 8, replace=False)
+        eE, eF = [], []
+        for s in sys_sel:
+            a, b = int(off[s]), int(off[s + 1])
+            p32 = pos[a:b].astype(np.float32).astype(np.float64)
+            q32 = q[a:b].astype(np.float32).astype(np.float64)
+            o = O.OracleMSM((float(boxes[s]),) * 3, [False] * 3, 4, 1.0, 6.0, int(levels[s]))
+            r = o.compute(p32, q32)
+            eE.append(abs(Eg[s] - r["E"]) / abs(r["E"]))
+            eF.append(_rel(Fg[a:b], r["F"]))
+        out["sampled_systems"] = len(sys_sel)
+        out["energy_rel_err_vs_fp64_oracle_max"] = float(max(eE))
+        out["force_rel_err_vs_fp64_oracle_max"] = float(max(eF))
+    return out
 
 
 def _grid_pass_sweep(torch, msm, steps):
@@ -242,15 +473,12 @@ def _grid_pass_sweep(torch, msm, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the autograd, batched and slab workloads")
-    ap.add_argument("--standalone", action="store_true",
-                    help="after the timed region, time every stage with all kernels on one "
-                         "stream (no overlap) and report those durations too")
+                    help="skip the water, autograd, batched and free-ion workloads")
     ap.add_argument("--no-grid-sweep", action="store_true",
                     help="skip the grid-pass timing on 128^3-512^3 level-1 grids with 1e7-6e7 "
                          "charges (HBM fraction of anterpolation, restriction, prolongation, "
@@ -269,140 +497,44 @@ def main():
     from paper_2510_05961_amd import msm
     from paper_2510_05961_amd import workloads as WL
 
-    cfg = WL.WORKLOADS[2]
-    pos64, q64, box = WL.make_config(2, 1.0)
-    n = len(q64)
-    pos32, q32 = pos64.astype(np.float32), q64.astype(np.float32)
-    dev = torch.device("cuda:0")
-    P = torch.from_numpy(pos32).to(dev).contiguous()
-    Q = torch.from_numpy(q32).to(dev).contiguous()
-    plan = msm.Plan(box, cfg["periodic"], cfg["p"], cfg["h"], cfg["a"], cfg["L"], msm.MSM_FP32, n)
-    desc = plan.describe()
-    E = torch.empty(1, dtype=torch.float64, device=dev)
-    F = torch.empty((n, 3), dtype=torch.float32, device=dev)
-    dq = torch.empty(n, dtype=torch.float32, device=dev)
-    out = (E, F, dq)
-
-    for _ in range(args.warmup):
-        plan.energy_forces(P, Q, out=out)
-    torch.cuda.synchronize()
-    if plan.status() != 0:
-        raise RuntimeError("device error flag set during warm-up")
-
+    w = Workload(3, torch, msm, WL, np)
     # timed region: the production forward (pair sum and coarse levels on
-    # their own streams); HIP events recorded live around the two heavy
-    # kernels only, on the stream each runs on
-    heavy = ["conv_l1", "pair"]
-    plan.profile(reset=True)
-    plan.set_profile_stages(heavy)
-    plan.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.energy_forces(P, Q, out=out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan.set_profiling(False)
-    stages = plan.profile(reset=True)
-    dt = t1 - t0
-    ms_per_step = dt / args.steps * 1e3
-    value = n * args.steps / dt
-
-    # the cell-list build (binning and the cluster layout) opens every call on
-    # the caller's stream before any other stage can start; the paper's timings
-    # leave the neighbour list out, so the step is also reported without it
-    plan.set_profile_stages(["bin", "cluster"])
-    plan.set_profiling(True)
-    for _ in range(args.steps):
-        plan.energy_forces(P, Q, out=out)
-    torch.cuda.synchronize()
-    plan.set_profiling(False)
-    nl = plan.profile(reset=True)
-    nl_ms = (nl["cluster"]["end_ms"] / max(nl["cluster"]["launches"], 1)
-             if "cluster" in nl else 0.0)
-
-    standalone = None
-    if args.standalone:
-        # every stage, one stream, no overlap: per-kernel durations alone
-        os.environ["MSM_STREAMS"] = "0"
-        plan.set_profile_stages(None)
-        plan.set_profiling(True)
-        for _ in range(args.steps):
-            plan.energy_forces(P, Q, out=out)
-        torch.cuda.synchronize()
-        plan.set_profiling(False)
-        standalone = {k: v["ms"] / args.steps for k, v in plan.profile(reset=True).items()}
-        del os.environ["MSM_STREAMS"]
-
-    # algorithmic work per launch (per unit: 2 flops per in-grid (output,
-    # input) pair with a non-zero coefficient for a convolution, all periodic
-    # here; 28 + 4p flops per unique in-cutoff pair for the pair sum)
-    lev = desc["levels_info"]
-    l1 = lev[0]
-    G1 = l1["n"][0] * l1["n"][1] * l1["n"][2]
-    direct_flops_l1 = 2.0 * G1 * l1["stencil_nnz"]
-    if l1.get("factored"):
-        Gext = l1["ext"][0] * l1["ext"][1] * l1["ext"][2]
-        conv_l1_flops = 2.0 * Gext * l1["samples_nnz"]
-    else:
-        conv_l1_flops = direct_flops_l1
-    npairs = _pair_count(pos32.astype(np.float64), 100.0, cfg["a"])
-    pair_flops = (28 + 4 * cfg["p"]) * npairs
-    per_launch = {k: v["ms"] / max(v["launches"], 1) for k, v in stages.items()}
-    # kernel -> (algorithmic flops per launch, peak of its arithmetic type)
-    candidates = {"conv_l1": (conv_l1_flops, PEAK_FP64_TFLOPS, "fp64"),
-                  "pair": (pair_flops, PEAK_FP32_VECTOR_TFLOPS, "fp32")}
-    dom = max(candidates, key=lambda k: per_launch.get(k, 0.0))
-    flops, peak, adt = candidates[dom]
-    dur_s = per_launch[dom] * 1e-3
-    achieved = flops / dur_s / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": _measured_traffic(dom), "arith": adt,
-                "algorithmic_per_launch": flops,
-                "avg_launch_ms": round(per_launch[dom], 5)}
-    kernels = {}
-    for k, (fl, pk, at) in candidates.items():
-        if k in per_launch:
-            a_ = fl / (per_launch[k] * 1e-3) / 1e12
-            kernels[k] = {"achieved": round(a_, 3), "peak": pk, "arith": at,
-                          "frac": round(a_ / pk, 4), "avg_launch_ms": round(per_launch[k], 5),
-                          "traffic": _measured_traffic(k)}
-    if standalone:
-        for k, (fl, pk, at) in candidates.items():
-            if k in standalone:
-                a_ = fl / (standalone[k] * 1e-3) / 1e12
-                kernels[k + "_standalone"] = {"achieved": round(a_, 3), "peak": pk,
-                                              "frac": round(a_ / pk, 4),
-                                              "avg_launch_ms": round(standalone[k], 5)}
-        # the level-1 stencil as the method defines it (direct-form flops)
-        # over the whole level-1 application (sample convolution + omega')
-        t_l1 = standalone.get("conv_l1", 0.0) + standalone.get("omega_l1", 0.0)
-        if t_l1 > 0:
-            kernels["level1_stencil_direct_equivalent_standalone"] = {
-                "tflops": round(direct_flops_l1 / (t_l1 * 1e-3) / 1e12, 3), "ms": round(t_l1, 5)}
-
+    # their own streams), no profiling events
+    t_step = w.timed(args.steps, args.warmup)
+    value = w.n / t_step
+    # each stage on its own (one stream, HIP events around every stage)
+    st = w.stages(min(args.steps, 10))
+    stage_ms = {k: v["ms"] / max(v["launches"], 1) for k, v in st.items()}
+    npairs = _pair_count(3, w.pos_t)
+    roofs = _rooflines(w, st, npairs)
+    dom = max(stage_ms, key=stage_ms.get)
+    roofline = dict(roofs.get(dom, {}))
+    if roofline:
+        roofline["stage"] = dom
+        roofline["traffic"] = _measured_traffic("slab1m_fp32", dom)
+    # the cell-list build (binning, cluster layout) opens every call on the
+    # caller's stream; the paper's timings leave the neighbour list out
+    nl_ms = stage_ms.get("bin", 0.0) + stage_ms.get("cluster", 0.0)
+    desc = w.plan.describe()
     result = {
         "metric": METRIC, "value": round(value, 1), "unit": "particles/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "periodic water box, 33,333 rigid 3-site molecules "
-                               "(99,999 charges), 100 A cube, p=4, h=1.5625, a=10, L=5, FP32",
-                   "n": n, "box": box[0], "order": cfg["p"], "h": lev[0]["h"][0],
-                   "cutoff": cfg["a"], "levels": cfg["L"], "precision": "fp32"},
+        "config": {"workload": "slab, 10^6 charges +-1, 100 x 100 x 60 A, periodic x and y, "
+                               "free z, p=6, h=1.25, a=12, L=5, FP32",
+                   "n": w.n, "box": list(w.box), "periodic": "xy", "order": w.c["p"],
+                   "h": desc["levels_info"][0]["h"][0], "cutoff": w.c["a"],
+                   "levels": w.c["L"], "precision": "fp32"},
         "roofline": roofline,
-        "kernels": kernels,
-        "pairs_in_cutoff": npairs,
-        "neighbour_list_ms": round(nl_ms, 4),
-        "ms_per_step_excluding_neighbour_list": round(ms_per_step - nl_ms, 4),
+        "kernels": roofs,
+        "stages_ms_one_stream": {k: round(v, 5) for k, v in stage_ms.items()},
+        "neighbour_list_ms_one_stream": round(nl_ms, 4),
     }
-    if standalone:
-        result["stages_ms_standalone"] = {k: round(v, 5) for k, v in standalone.items()}
 
     if args.calib_copy_mb > 0:
         nb = args.calib_copy_mb * (1 << 20)
-        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
@@ -410,45 +542,49 @@ def main():
         result["calib_copy_bytes"] = nb
         del src, dst
 
+    check = not args.no_error_check
+    if check or not args.no_cpu_baseline or not args.no_extras:
+        from oracle import oracle as O
+    if check:
+        w.step()
+        torch.cuda.synchronize()
+        err = _oracle_sampled_error(w, O, np, 32, seed=0)
+        Eg = _golden_energy(3, w.pos_t, w.q_t)
+        if Eg is not None:
+            err["energy_rel_err_vs_fp64_oracle"] = abs(w.E.item() - Eg) / abs(Eg)
+        phi = w.dq.double().cpu().numpy()
+        e2 = 0.5 * float(np.dot(w.q64, phi))
+        err["energy_vs_half_sum_q_phi"] = abs(w.E.item() - e2) / abs(e2)
+        result["error_vs_fp64_oracle"] = err
+
+    if not args.no_cpu_baseline:
+        runs = [_cpu_baseline(w, O, np, 20000, O.num_threads()) for _ in range(3)]
+        one = _cpu_baseline(w, O, np, 2000, 1)
+        vals = sorted(r[0] for r in runs)
+        result["cpu_baseline"] = {
+            "value": round(vals[1], 1), "unit": "particles/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": "the FP64 oracle on a linear 20,000/10^6 share of every part of one full "
+                      "evaluation of the same slab input (short-range sums of 20,000 random "
+                      "targets over all partners by cell list, anterpolation of those charges on "
+                      "all 5 levels, level potentials at the same share of every level's grid "
+                      "points, interpolation at the targets); value = targets / seconds, median "
+                      "of 3 runs",
+            "runs_seconds": [round(r[1], 3) for r in runs],
+            "one_thread": {"value": round(one[0], 1), "cores": 1, "targets": 2000,
+                           "seconds": round(one[1], 3)}}
+
+    if not args.no_extras:
+        result["water"] = _water(torch, msm, WL, np, O if check else None, args.steps, check)
+        result["autograd"] = _autograd_vs_plain(torch, msm, WL, np, O if check else None, check)
+        result["batched"] = _batched_vs_plain(torch, msm, WL, np, O if check else None, check)
+        result["free_ions_fp64"] = _free_ions(torch, msm, WL, np, O if check else None, check)
+
     if not args.no_grid_sweep:
         try:
             result["grid_pass_sweep"] = _grid_pass_sweep(torch, msm, max(args.steps // 10, 3))
         except RuntimeError as e:  # (MSMError and out-of-memory included) keep the headline line
             result["grid_pass_sweep"] = {"error": str(e)}
-
-    if not args.no_extras:
-        result["autograd"] = _autograd_vs_plain(torch, msm, WL, np)
-        result["batched"] = _batched_vs_plain(torch, msm, WL, np)
-        result["slab"] = _slab(torch, msm, WL, np)
-
-    if not args.no_error_check:
-        from oracle import oracle as O
-        sel = np.random.default_rng(0).choice(n, 32, replace=False)
-        p64, q64c = pos32.astype(np.float64), q32.astype(np.float64)
-        o = O.OracleMSM(box, [True] * 3, cfg["p"], cfg["h"], cfg["a"], cfg["L"])
-        phi_r, F_r = o.sampled(p64, q64c, sel)
-        Fg = F.double().cpu().numpy()[sel]
-        result["force_rel_err_vs_fp64_oracle_sampled"] = float(
-            np.linalg.norm(Fg - F_r) / np.linalg.norm(F_r))
-
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        p64, q64c = pos32.astype(np.float64), q32.astype(np.float64)
-        o = O.OracleMSM(box, [True] * 3, cfg["p"], cfg["h"], cfg["a"], cfg["L"])
-        for l in range(1, cfg["L"] + 1):
-            o.stencil(l)  # plan-time work, not timed (as on the GPU)
-        c0 = time.perf_counter()
-        ref = o.compute(p64, q64c)
-        c1 = time.perf_counter()
-        result["cpu_baseline"] = {"value": round(n / (c1 - c0), 1), "unit": "particles/s",
-                                  "cores": O.num_threads(), "kind": "oracle",
-                                  "sample": "one full energy+forces evaluation of the same "
-                                            "99,999-charge workload (FP64, OpenMP)",
-                                  "seconds": round(c1 - c0, 3)}
-        Eg = float(E.item())
-        result["energy_rel_err_vs_fp64_oracle"] = abs(Eg - ref["E"]) / abs(ref["E"])
-        result["force_rel_err_vs_fp64_oracle"] = float(
-            np.linalg.norm(F.double().cpu().numpy() - ref["F"]) / np.linalg.norm(ref["F"]))
 
     print(json.dumps(result), flush=True)
 

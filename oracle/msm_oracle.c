@@ -27,6 +27,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Sets that number (n >= 1). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * Softening function (Sec. "Splitting for Coulomb kernels"): gamma(rho) is
  * 1/rho for rho >= 1 and, below 1, the Taylor polynomial of s^(-1/2) about
@@ -544,21 +554,23 @@ static int sr_pair(const orc_geom* g, const double* pos, const double* q, int i,
 }
 
 void orc_short_range_cells(const orc_geom* g, int n, const double* pos,
-                           const double* q, double* phi, double* F)
+                           const double* q, int nsel, const int* sel, double* phi, double* F)
 {
   cell_list cl;
   cell_list_build(g, n, pos, &cl);
+  const int cnt = nsel < 0 ? n : nsel;
 #pragma omp parallel for schedule(dynamic, 16)
-  for (int i = 0; i < n; ++i) {
+  for (int s = 0; s < cnt; ++s) {
+    int i = nsel < 0 ? s : sel[s];
     long nb[27];
     int m = cell_list_neighbours(g, &cl, i, nb);
     double ph = 0.0, f[3] = {0, 0, 0};
     for (int u = 0; u < m; ++u)
       for (int j = cl.head[nb[u]]; j >= 0; j = cl.next[j])
         if (j != i) sr_pair(g, pos, q, i, j, &ph, f);
-    if (phi) phi[i] += ph;
+    if (phi) phi[s] += ph;
     if (F)
-      for (int k = 0; k < 3; ++k) F[3 * i + k] += f[k];
+      for (int k = 0; k < 3; ++k) F[3 * s + k] += f[k];
   }
   cell_list_free(&cl);
 }

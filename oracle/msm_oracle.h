@@ -35,6 +35,7 @@ typedef struct {
 } orc_geom;
 
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* Softening function and its rho-derivatives (Sec. Coulomb splitting). */
 double orc_gamma(int p, double rho);
@@ -76,9 +77,10 @@ int orc_interpolate_vjp(const orc_geom* g, int level, int n, const double* pos,
  * listed particles (nsel < 0: all). */
 void orc_short_range(const orc_geom* g, int n, const double* pos, const double* q,
                      int nsel, const int* sel, double* phi, double* F);
-/* Same sum through a plain cell list (all particles). */
+/* Same sum through a plain cell list, for the listed particles (nsel < 0:
+ * all; outputs indexed like sel). */
 void orc_short_range_cells(const orc_geom* g, int n, const double* pos,
-                           const double* q, double* phi, double* F);
+                           const double* q, int nsel, const int* sel, double* phi, double* F);
 /* VJP of the short-range forces against cotangent v: adds d(sum_k v_k.F0_k)/dq_i
  * and /dr_i.  Brute force over all pairs for the listed particles (nsel < 0:
  * all; output row s belongs to particle sel[s]). */

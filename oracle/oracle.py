@@ -85,6 +85,8 @@ def lib():
             getattr(L, name).argtypes = [i, d]
             getattr(L, name).restype = d
         L.orc_num_threads.restype = i
+        L.orc_set_num_threads.argtypes = [i]
+        L.orc_set_num_threads.restype = None
         L.orc_kernel.argtypes = [i, i, d, i, d]
         L.orc_kernel.restype = d
         for name in ("orc_k0_d1", "orc_k0_d2"):
@@ -107,7 +109,7 @@ def lib():
         L.orc_interpolate_vjp.restype = i
         L.orc_short_range.argtypes = [G, i, P, P, i, P, P, P]
         L.orc_short_range.restype = None
-        L.orc_short_range_cells.argtypes = [G, i, P, P, P, P]
+        L.orc_short_range_cells.argtypes = [G, i, P, P, i, P, P, P]
         L.orc_short_range_cells.restype = None
         L.orc_short_range_vjp.argtypes = [G, i, P, P, P, i, P, P, P]
         L.orc_short_range_vjp.restype = None
@@ -137,6 +139,11 @@ def _f64(a):
 # --------------------------------------------------------------------------
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """Threads of the oracle's OpenMP loops from now on (n >= 1)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def gamma(p, rho):
@@ -429,7 +436,8 @@ class OracleMSM:
             if cells is None:
                 cells = n > 4000
             if cells:
-                lib().orc_short_range_cells(self._gp, n, _ptr(pos), _ptr(q), _ptr(phi), _ptr(F))
+                lib().orc_short_range_cells(self._gp, n, _ptr(pos), _ptr(q), -1, None, _ptr(phi),
+                                            _ptr(F))
             else:
                 lib().orc_short_range(self._gp, n, _ptr(pos), _ptr(q), -1, None, _ptr(phi),
                                       _ptr(F))
@@ -437,8 +445,10 @@ class OracleMSM:
             sel = np.ascontiguousarray(sel, dtype=np.int32)
             phi = np.zeros(len(sel))
             F = np.zeros((len(sel), 3))
-            lib().orc_short_range(self._gp, n, _ptr(pos), _ptr(q), len(sel), _ptr(sel), _ptr(phi),
-                                  _ptr(F))
+            if cells is None:
+                cells = n > 4000
+            fn = lib().orc_short_range_cells if cells else lib().orc_short_range
+            fn(self._gp, n, _ptr(pos), _ptr(q), len(sel), _ptr(sel), _ptr(phi), _ptr(F))
         return phi, F
 
     def compute(self, pos, q):

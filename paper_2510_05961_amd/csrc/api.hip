@@ -500,8 +500,9 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
                            P->counts, s);
   pf.end(ev, s);
 
-  // a2 short-range pairs (8 x 4 blocks), on its own stream: it only
-  // needs the cluster layout, and interpolation waits for it
+  // a2 short-range pairs (i-clusters against culled j particles), on its
+  // own stream: it only needs the cluster layout, and interpolation waits
+  // for it
   const bool dag = use_streams();
   hipStream_t sp = dag ? P->sc : s;
   if (dag) {
@@ -511,8 +512,7 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   const PairParams<T> pp = pair_params<T>(hp);
   ev = pf.begin("pair", sp);
   launch_pair_cl<T>(p, n, P->ncell, P->cl_start, (const vec4_t<T>*)P->cpos,
-                    (const vec4_t<T>*)P->cbox, P->cinfo, pp, P->null_h, (double*)P->phi0,
-                    (T*)P->F0, sp);
+                    (const vec4_t<T>*)P->cbox, P->cinfo, pp, (double*)P->phi0, (T*)P->F0, sp);
   pf.end(ev, sp);
   if (dag) (void)hipEventRecord(P->ev[1], sp);
 

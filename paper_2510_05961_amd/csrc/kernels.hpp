@@ -102,8 +102,8 @@ void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int
                     int* cl_start, vec4_t<T>* sorted, int* perm, int* flag, int* scan_tmp,
                     const ZeroJobs& zero, hipStream_t s);
 // Cluster layout of the cell-sorted particles (sort != 0: also reorders each
-// cell along a Morton curve, in place) and the short-range pair sum over 8 x 4
-// blocks (an i-cluster against a j-group, half a cluster).  Buffers hold
+// cell along a Morton curve, in place) and the short-range pair sum (an
+// i-cluster against the j particles within the cutoff of its box).  Buffers hold
 // cluster_capacity(n, ncell) clusters: 8 slots each in cpos and cv, two
 // boxes (lo, hi per j-group) in cbox; cpos and cv hold one more j-group, the
 // null group (far-away zero charges, zero vectors) at index null_h, set once
@@ -119,7 +119,7 @@ void launch_cluster_layout(int sort, int scan, int ncell, const int* start, int*
 template <typename T>
 void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
                     const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
-                    int null_h, double* phi0, T* F0, hipStream_t s);
+                    double* phi0, T* F0, hipStream_t s);
 // cell list geometry in FP64 (bricks of the staged anterpolation)
 struct CellGrid {
   int nc[3];

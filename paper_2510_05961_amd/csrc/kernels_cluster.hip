@@ -1,5 +1,5 @@
-// kernels_cluster.hip -- the short-range part U^0 (eq. U_zero) as a sum over
-// 8 x 4 cluster blocks, and its vector-Jacobian product.
+// kernels_cluster.hip -- the short-range part U^0 (eq. U_zero): the cluster
+// layout of the cell list, the pair sum and its vector-Jacobian product.
 //
 // Layout.  Binning sorts particles by cell (cells of edge >= a).  Inside
 // every cell the particles are then ordered along a Morton curve of a 16^3
@@ -8,16 +8,23 @@
 // cluster of a cell is padded with far-away zero charges.  Each half of a
 // cluster (4 particles, a "j-group") keeps its bounding box.
 //
-// Pair sum.  One wave per i-cluster.  Every j-group of the 27 neighbour
-// cells whose box lies within the cutoff of the i-cluster's box goes into a
-// per-wave list; the wave then takes two list entries per step, lane
-// (slot, il, jl) = (lane / 32, lane / 4 % 8, lane % 4) evaluating i-member il
-// against member jl of entry slot.  Periodic images are handled by a uniform
-// shift per neighbour cell (27 offsets, each (cell, shift) combination
-// distinct), which is exact whenever the cell edge is >= a and every
-// periodic edge is >= 2a: then at most one image of a particle lies inside
-// the cutoff and it lies in one of the 27 shifted neighbour cells.
-#include "kernels.hpp"
+// Pair sum.  One wave per i-cluster.  Over the 27 neighbour cells, the
+// j-groups whose box lies within the cutoff of the i-cluster's box are
+// listed, then each of their members whose distance to that box is below
+// the cutoff is moved into the i-cluster's frame and put in a per-wave ring;
+// the wave evaluates eight ring entries per step, lane (il, jj) =
+// (lane / 8, lane % 8) taking i-member il against entry jj.  Every pair is
+// evaluated from both sides (each particle's sums stay in its own lanes).
+// Periodic images are handled by a uniform shift per neighbour cell (27
+// offsets, each (cell, shift) combination distinct), which is exact whenever
+// the cell edge is >= a and every periodic edge is >= 2a: then at most one
+// image of a particle lies inside the cutoff and it lies in one of the 27
+// shifted neighbour cells.
+//
+// Pair VJP.  As the pair sum but on j-groups (8 x 4 blocks, two groups per
+// step, lane (slot, il, jl) = (lane / 32, lane / 4 % 8, lane % 4)), with the
+// force cotangents of both particles.
+#include "cluster_dev.hpp"
 
 namespace msm {
 
@@ -27,6 +34,8 @@ constexpr int kSlots = 64 / (8 * kGroup);  // j-groups per wave step
 constexpr int kPrepThreads = 256;
 constexpr int kPrepSortMax = 4096;    // cells larger than this keep their order
 constexpr int kSmallCell = 128;       // cells up to this size are staged in LDS
+constexpr int kRing = 128;            // per-wave ring of culled j particles
+constexpr int kStepJ = 8;             // j particles per wave step (8 x 8 lanes)
 
 // Cluster offsets: cl_start[c] = sum_{c' < c} ceil(count_c' / 8), one workgroup.
 __global__ void __launch_bounds__(1024) k_cluster_scan(int ncell, const int* __restrict__ start,
@@ -262,48 +271,6 @@ __global__ void __launch_bounds__(kPrepThreads)
     cinfo[cbeg + c] = make_int4(beg + 8 * c, min(8, cnt - 8 * c), cell, 0);
 }
 
-// Neighbour cell along one axis at offset o in {-1, 0, 1}: the cell index
-// (or -1 outside a free axis) and the image shift in units of the box edge.
-__device__ inline int neighbour_shift(int c, int o, int nc, int per, int& sh) {
-  const int v = c + o;
-  sh = 0;
-  if (per) {
-    if (v < 0) {
-      sh = -1;
-      return v + nc;
-    }
-    if (v >= nc) {
-      sh = 1;
-      return v - nc;
-    }
-    return v;
-  }
-  return (v >= 0 && v < nc) ? v : -1;
-}
-
-template <typename T>
-__device__ inline T box_gap2(T jlo_x, T jlo_y, T jlo_z, T jhi_x, T jhi_y, T jhi_z, T ilo_x,
-                             T ilo_y, T ilo_z, T ihi_x, T ihi_y, T ihi_z) {
-  const T gx = max(T(0), max(jlo_x - ihi_x, ilo_x - jhi_x));
-  const T gy = max(T(0), max(jlo_y - ihi_y, ilo_y - jhi_y));
-  const T gz = max(T(0), max(jlo_z - ihi_z, ilo_z - jhi_z));
-  return gx * gx + gy * gy + gz * gz;
-}
-
-// A wave-uniform value held in a VGPR: one VALU instruction may read only
-// one SGPR, so the leading Horner coefficient lives in a VGPR (loaded once)
-// instead of being copied from its SGPR at every pair block.
-__device__ inline float in_vgpr(float x) {
-  float r;
-  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
-  return r;
-}
-__device__ inline double in_vgpr(double x) {
-  double r;
-  asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "s"(x));
-  return r;
-}
-
 // Sum over the 8 lanes of one i-member (jl and slot: lane bits 0, 1 and 5).
 template <typename V>
 __device__ inline V sum_i(V v) {
@@ -418,56 +385,148 @@ struct JData {
   vec4_t<T> p, v;
 };
 
-// Box of i-cluster ic: the union of its j-groups' boxes (an empty second
-// group is left out).
-template <typename T>
-__device__ inline void cluster_box(const vec4_t<T>* cbox, int ic, int m, vec4_t<T>& lo,
-                                   vec4_t<T>& hi) {
-  lo = cbox[4 * (size_t)ic];
-  hi = cbox[4 * (size_t)ic + 1];
-  if (m > kGroup) {
-    const vec4_t<T> l2 = cbox[4 * (size_t)ic + 2], h2 = cbox[4 * (size_t)ic + 3];
-    lo.x = min(lo.x, l2.x);
-    lo.y = min(lo.y, l2.y);
-    lo.z = min(lo.z, l2.z);
-    hi.x = max(hi.x, h2.x);
-    hi.y = max(hi.y, h2.y);
-    hi.z = max(hi.z, h2.z);
+// Visits every j particle within the cutoff of the i-cluster's box, over the
+// 27 neighbour cells with their image shifts: per cell, the j-groups whose
+// box lies within a of the i-box, then their members whose own distance to
+// the i-box is below a.  Survivors go, moved into the i-cluster's frame
+// (position + shift, charge), to the wave's LDS ring; step(head) runs on
+// ring entries [head, head + 8) whenever eight are waiting, and once more at
+// the end on the remainder (the rest of that step reads a far-away zero
+// charge).  flush() runs after each neighbour cell.
+template <typename T, typename Step, typename Flush>
+__device__ inline void for_each_j_culled(const PairParams<T>& pp, const int* cl_start,
+                                         const vec4_t<T>* cpos, const vec4_t<T>* cbox, int cell,
+                                         const vec4_t<T>& blo, const vec4_t<T>& bhi,
+                                         vec4_t<T>* ring, int* gl, const vec4_t<T>& far,
+                                         Step&& step, Flush&& flush) {
+  const int lane = threadIdx.x & 63, jj = lane & (kStepJ - 1);
+  const int cx = cell % pp.nc[0];
+  const int cy = (cell / pp.nc[0]) % pp.nc[1];
+  const int cz = cell / (pp.nc[0] * pp.nc[1]);
+  int head = 0, tail = 0;
+  for (int oz = -1; oz <= 1; ++oz) {
+    int shz;
+    const int nz = neighbour_shift(cz, oz, pp.nc[2], pp.per[2], shz);
+    if (nz < 0) continue;
+    const T sz = (T)shz * pp.box[2];
+    for (int oy = -1; oy <= 1; ++oy) {
+      int shy;
+      const int ny = neighbour_shift(cy, oy, pp.nc[1], pp.per[1], shy);
+      if (ny < 0) continue;
+      const T sy = (T)shy * pp.box[1];
+      for (int ox = -1; ox <= 1; ++ox) {
+        int shx;
+        const int nx = neighbour_shift(cx, ox, pp.nc[0], pp.per[0], shx);
+        if (nx < 0) continue;
+        const T sx = (T)shx * pp.box[0];
+        // i-box moved by minus the shift of the j image
+        const T ilx = blo.x - sx, ily = blo.y - sy, ilz = blo.z - sz;
+        const T ihx = bhi.x - sx, ihy = bhi.y - sy, ihz = bhi.z - sz;
+        {  // whole-cell test with a margin for the rounding of the binning
+          const T mx = pp.cs[0] * T(1e-3), my = pp.cs[1] * T(1e-3), mz = pp.cs[2] * T(1e-3);
+          const T g2 = box_gap2<T>((T)nx * pp.cs[0] - mx, (T)ny * pp.cs[1] - my,
+                                   (T)nz * pp.cs[2] - mz, (T)(nx + 1) * pp.cs[0] + mx,
+                                   (T)(ny + 1) * pp.cs[1] + my, (T)(nz + 1) * pp.cs[2] + mz,
+                                   ilx, ily, ilz, ihx, ihy, ihz);
+          if (!(g2 < pp.a2)) continue;
+        }
+        const int ncell = (nz * pp.nc[1] + ny) * pp.nc[0] + nx;
+        const int jb0 = 2 * cl_start[ncell], jb1 = 2 * cl_start[ncell + 1];
+        for (int jb = jb0; jb < jb1; jb += 64) {
+          const int h = jb + lane;
+          bool hit = false;
+          if (h < jb1) {
+            const vec4_t<T> lo = cbox[2 * (size_t)h], hi = cbox[2 * (size_t)h + 1];
+            hit = box_gap2<T>(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, ilx, ily, ilz, ihx, ihy, ihz) <
+                  pp.a2;
+          }
+          const unsigned long long mask = __ballot(hit);
+          if (mask == 0) continue;
+          const int ng = __popcll(mask);
+          const int pos = (int)__builtin_amdgcn_mbcnt_hi(
+              (unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+          if (hit) gl[pos] = h;
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          for (int e0 = 0; e0 < ng; e0 += 64 / kGroup) {
+            const int e = e0 + lane / kGroup;
+            bool hit2 = false;
+            vec4_t<T> pj;
+            if (e < ng) {
+              pj = group_member<T>(cpos, gl[e], lane & (kGroup - 1));
+              const T gx = max(T(0), max(ilx - pj.x, pj.x - ihx));
+              const T gy = max(T(0), max(ily - pj.y, pj.y - ihy));
+              const T gz = max(T(0), max(ilz - pj.z, pj.z - ihz));
+              hit2 = gx * gx + gy * gy + gz * gz < pp.a2;
+            }
+            const unsigned long long m2 = __ballot(hit2);
+            const int pos2 = (int)__builtin_amdgcn_mbcnt_hi(
+                (unsigned)(m2 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m2, 0u));
+            if (hit2) {
+              pj.x += sx;
+              pj.y += sy;
+              pj.z += sz;
+              ring[(tail + pos2) & (kRing - 1)] = pj;
+            }
+            tail += __popcll(m2);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // the waiting full steps, each one's ring read issued a step ahead
+            const int nst = (tail - head) / kStepJ;
+            if (nst > 0) {
+              vec4_t<T> cur = ring[(head + jj) & (kRing - 1)];
+              for (int st = 0; st < nst; ++st) {
+                head += kStepJ;
+                const vec4_t<T> nxt = st + 1 < nst ? ring[(head + jj) & (kRing - 1)] : cur;
+                step(cur);
+                cur = nxt;
+              }
+            }
+            __builtin_amdgcn_wave_barrier();
+          }
+        }
+        flush();
+      }
+    }
   }
+  if (tail > head) step(jj < tail - head ? ring[(head + jj) & (kRing - 1)] : far);
 }
 
-// U^0 per particle: phi0_i = sum_j q_j (1/r - gamma(r/a)/a) over j != i with
-// r < a, and F0_i = q_i sum_j q_j f(r) d_ij with f = -(1/r) d/dr of that
-// kernel.  Both polynomials are taken in r^2 directly (PairParams er, fr).
+// U^0 per particle (eq. U_zero) over the culled j particles: lane (il, jj)
+// = (lane / 8, lane % 8) evaluates i-member il against ring entry head + jj
+// of each step.
+// The self pair (the same particle, shift 0) is the only pair at distance
+// exactly zero and is left out by r^2 > 0.
 template <typename T, int P>
 __global__ void __launch_bounds__(kClusterThreads)
-    k_pair_cl(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
+    k_pair_pc(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
               const vec4_t<T>* __restrict__ cbox, const int4* __restrict__ cinfo,
-              PairParams<T> pp, int null_h, double* __restrict__ phi0, T* __restrict__ F0) {
-  __shared__ int lists[kClusterThreads / 64][64];
-  const int lane = threadIdx.x & 63;
-  const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * (kClusterThreads / 64) +
-                                                (int)(threadIdx.x >> 6));
+              PairParams<T> pp, double* __restrict__ phi0, T* __restrict__ F0) {
+  __shared__ vec4_t<T> rings[kClusterThreads / 64][kRing];
+  __shared__ int glists[kClusterThreads / 64][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * (kClusterThreads / 64) + wv);
   if (ic >= cl_start[pp.ncell]) return;
-  const int il = (lane >> 2) & 7, jl = lane & 3;
+  const int il = lane >> 3, jj = lane & 7;
   const int4 inf = cinfo[ic];
   const vec4_t<T> pi = cpos[(size_t)ic * 8 + il];
   vec4_t<T> blo, bhi;
   cluster_box<T>(cbox, ic, inf.y, blo, bhi);
   const T e_top = in_vgpr(pp.er[P - 1]), f_top = in_vgpr(pp.fr[P - 2]);
   const T a2v = in_vgpr(pp.a2);
+  vec4_t<T>* ring = rings[wv];
+  vec4_t<T> far;
+  far.x = far.y = far.z = T(1e15);
+  far.w = T(0);
   double ph = 0.0;  // the potential is carried in FP64 up to the energy sum
   T phc = T(0);     // ... after a partial sum over one neighbour cell
   T fx = T(0), fy = T(0), fz = T(0);
-  for_each_group_block<T>(
-      pp, cl_start, cbox, ic, inf.z, blo, bhi, lists[threadIdx.x >> 6], null_h,
-      [&](int h) { return group_member<T>(cpos, h, jl); },
-      [&](int h, const vec4_t<T>& pj, T sx, T sy, T sz, int self_h) {
-        const T dx = (pi.x - sx) - pj.x, dy = (pi.y - sy) - pj.y, dz = (pi.z - sz) - pj.z;
+  for_each_j_culled<T>(
+      pp, cl_start, cpos, cbox, inf.z, blo, bhi, ring, glists[wv], far,
+      [&](const vec4_t<T>& pj) {
+        const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
         const T r2 = dx * dx + dy * dy + dz * dz;
-        const bool ok = r2 < pp.a2 && h != self_h;
-        // pairs outside the cutoff (and the self pair) get r = a and a zero
-        // charge, so every intermediate stays finite
+        const bool ok = r2 < pp.a2 && r2 > T(0);
         const T r2c = ok ? r2 : a2v;
         const T qj = ok ? pj.w : T(0);
         const T rinv = rsqrt_t(r2c);
@@ -476,10 +535,8 @@ __global__ void __launch_bounds__(kClusterThreads)
         for (int k = P - 2; k >= 0; --k) pe = pe * r2c + pp.er[k];
 #pragma unroll
         for (int k = P - 3; k >= 0; --k) pf = pf * r2c + pp.fr[k];
-        const T e = rinv - pe;
-        const T f = rinv * rinv * rinv + pf;
-        const T fs = qj * f;
-        phc += qj * e;
+        const T fs = qj * (rinv * rinv * rinv + pf);
+        phc += qj * (rinv - pe);
         fx += fs * dx;
         fy += fs * dy;
         fz += fs * dz;
@@ -488,11 +545,15 @@ __global__ void __launch_bounds__(kClusterThreads)
         ph += (double)phc;
         phc = T(0);
       });
-  ph = sum_i(ph);
-  fx = sum_i(fx);
-  fy = sum_i(fy);
-  fz = sum_i(fz);
-  if ((lane & ~0x1C) == 0 && il < inf.y) {  // slot 0, jl 0
+  ph += (double)phc;
+#pragma unroll
+  for (int d = 1; d < 8; d <<= 1) {
+    ph += __shfl_xor(ph, d);
+    fx += __shfl_xor(fx, d);
+    fy += __shfl_xor(fy, d);
+    fz += __shfl_xor(fz, d);
+  }
+  if (jj == 0 && il < inf.y) {
     const int i = inf.x + il;
     phi0[i] = ph;
     F0[3 * (size_t)i] = pi.w * fx;
@@ -604,14 +665,14 @@ int cluster_capacity(int n, int ncell) { return n / 8 + ncell + 1; }
 template <typename T>
 void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
                     const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
-                    int nh, double* phi0, T* F0, hipStream_t s) {
+                    double* phi0, T* F0, hipStream_t s) {
   if (n <= 0) return;
   const int ncl = cluster_capacity(n, ncell);
   const dim3 grid((ncl + 3) / 4), block(kClusterThreads);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_pair_cl<T, 4>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, nh, phi0, F0); break;
-    case 6: hipLaunchKernelGGL((k_pair_cl<T, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, nh, phi0, F0); break;
-    case 8: hipLaunchKernelGGL((k_pair_cl<T, 8>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, nh, phi0, F0); break;
+    case 4: hipLaunchKernelGGL((k_pair_pc<T, 4>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+    case 6: hipLaunchKernelGGL((k_pair_pc<T, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+    case 8: hipLaunchKernelGGL((k_pair_pc<T, 8>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
   }
 }
 
@@ -637,7 +698,7 @@ void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4
                                          const vec4_t<T>*, vec4_t<T>*, int*, vec4_t<T>*,       \
                                          vec4_t<T>*, int4*, int*, hipStream_t);                \
   template void launch_pair_cl<T>(int, int, int, const int*, const vec4_t<T>*,                 \
-                                  const vec4_t<T>*, const int4*, const PairParams<T>&, int,    \
+                                  const vec4_t<T>*, const int4*, const PairParams<T>&,         \
                                   double*, T*, hipStream_t);                                   \
   template void launch_pair_vjp_cl<T>(int, int, int, const int*, const int4*, const int*,      \
                                       const T*, const vec4_t<T>*, vec4_t<T>*,                  \

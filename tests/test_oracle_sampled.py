@@ -92,3 +92,22 @@ def test_short_range_vjp_cell_list_equals_brute_force(periodic):
     c_q, c_r = o.short_range_vjp(pos, q, v, sel=sel)
     _close(c_q, a_q[sel], 1e-13)
     _close(c_r, a_r[sel], 1e-13)
+
+
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 1), (1, 1, 0)])
+def test_short_range_selected_cell_list_equals_brute_force(periodic):
+    """The cell-list short range for listed particles (as the sampled
+    parity and the CPU baseline use it) against the brute-force pair loop,
+    with particles near every face of the box among the listed ones."""
+    box = (21.0, 19.0, 23.0)
+    o = O.OracleMSM(box, periodic, 4, 1.0, 6.5, 2)
+    pos, q = WL.random_ions(1500, box, seed=12)
+    near = np.flatnonzero(np.any((pos < 0.7) | (pos > np.array(box) - 0.7), axis=1))[:20]
+    sel = np.concatenate([near, [0, 3, 700, 1499]]).astype(np.int64)
+    a_phi, a_F = o.short_range(pos, q, cells=False)
+    b_phi, b_F = o.short_range(pos, q, sel=sel, cells=True)
+    c_phi, c_F = o.short_range(pos, q, sel=sel, cells=False)
+    _close(b_phi, a_phi[sel], 1e-12)
+    _close(b_F, a_F[sel], 1e-12)
+    _close(c_phi, a_phi[sel], 1e-13)
+    _close(c_F, a_F[sel], 1e-13)
