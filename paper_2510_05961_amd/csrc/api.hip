@@ -126,6 +126,81 @@ static ConvParams level_conv(const msm_plan P, int l, bool samples) {
                  : make_conv_params(g.n, g.n, zero3, hp.periodic, c.off, c.len, sizeof(T), c.fold);
 }
 
+// The working memory of calls with up to n particles, carved from base in
+// 256-byte aligned pieces (base = null: sizes only); returns its bytes, or 0
+// when the cluster slots would not be addressable with 32-bit byte offsets.
+template <typename T>
+size_t work_layout(const msm_plan P, int n, char* base, WorkBufs* wb) {
+  const HostPlan& hp = P->hp;
+  const size_t nn = (size_t)std::max(n, 1), nc = (size_t)P->ncell;
+  const size_t ncl = (size_t)cluster_capacity((int)nn, P->ncell);
+  // cluster slots plus the null j-group, addressed with 32-bit byte offsets
+  const size_t slots = ncl * 8 + kGroupSize;
+  if (slots * 4 * sizeof(T) >= (size_t(1) << 32)) return 0;
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + o : nullptr;
+    o += (std::max(bytes, size_t(16)) + 255) & ~size_t(255);
+    return p;
+  };
+  WorkBufs w;
+  for (int l = 1; l <= hp.L; ++l) {
+    const LevelGeom& g = hp.lev[l - 1];
+    w.qg[l - 1] = take((size_t)g.G * sizeof(T));
+    w.eg[l - 1] = take((size_t)g.G * sizeof(T));
+    // FP64 accumulation buffer of the level's convolution
+    const long long gbuf = std::max(g.G, g.factored ? g.Gext : 0LL);
+    w.ug[l - 1] = (double*)take((size_t)gbuf * sizeof(double));
+    if (g.factored) w.ut[l - 1] = (double*)take((size_t)g.Gext * sizeof(double));
+  }
+  w.cell_of = (int*)take(nn * sizeof(int));
+  w.rank = (int*)take(nn * sizeof(int));
+  w.counts = (int*)take(nc * kCountCopies * sizeof(int));
+  w.start = (int*)take((nc + 1) * sizeof(int));
+  w.scan_tmp = (int*)take((size_t)scan_tmp_ints(P->ncell) * sizeof(int));
+  w.perm = (int*)take(nn * sizeof(int));
+  w.wrapped = take(nn * 4 * sizeof(T));
+  w.sorted = take(nn * 4 * sizeof(T));
+  w.cl_start = (int*)take((nc + 1) * sizeof(int));
+  w.cpos = take(slots * 4 * sizeof(T));
+  w.cv = take(slots * 4 * sizeof(T));
+  w.cbox = take(ncl * 2 * 2 * 4 * sizeof(T));
+  w.cinfo = (int4*)take(ncl * sizeof(int4));
+  w.phi0 = take(nn * sizeof(double));
+  w.F0 = take(nn * 3 * sizeof(T));
+  w.null_h = (int)(2 * ncl);
+  if (wb) *wb = w;
+  return o;
+}
+
+// The null j-group (far-away zero charges, zero vectors) and zero cell
+// counters: what a call expects of its working memory on entry.
+template <typename T>
+__global__ void k_prepare_work(vec4_t<T>* cpos_null, vec4_t<T>* cv_null, int* counts,
+                               long long ncount) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kGroupSize) {
+    vec4_t<T> far, zero;
+    far.x = far.y = far.z = T(1e15);
+    far.w = T(0);
+    zero.x = zero.y = zero.z = zero.w = T(0);
+    cpos_null[i] = far;
+    cv_null[i] = zero;
+  }
+  for (long long k = i; k < ncount; k += (long long)gridDim.x * blockDim.x) counts[k] = 0;
+}
+
+template <typename T>
+msm_status prepare_work(const msm_plan P, const WorkBufs& w, hipStream_t s) {
+  const long long ncount = (long long)P->ncell * kCountCopies;
+  const int blocks = (int)std::min<long long>(1024, (ncount + 255) / 256 + 1);
+  const size_t null_slot = (size_t)w.null_h * kGroupSize;
+  hipLaunchKernelGGL(k_prepare_work<T>, dim3(blocks), dim3(256), 0, s,
+                     (vec4_t<T>*)w.cpos + null_slot, (vec4_t<T>*)w.cv + null_slot, w.counts,
+                     ncount);
+  return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
+}
+
 template <typename T>
 msm_status upload_plan(msm_plan P) {
   HostPlan& hp = P->hp;
@@ -171,13 +246,6 @@ msm_status upload_plan(msm_plan P) {
     LevelGeom& g = hp.lev[l - 1];
     if ((st = upload_stencil(g.K, g.off, g.len, g.n[2], &P->K64[l - 1], &P->rowext64[l - 1],
                              &P->kgeom[l - 1]))) return st;
-    if ((st = hip_alloc(P, &P->qg[l - 1], (size_t)g.G * sizeof(T)))) return st;
-    if ((st = hip_alloc(P, &P->eg[l - 1], (size_t)g.G * sizeof(T)))) return st;
-    // FP64 accumulation buffer of the level's convolution
-    const long long gbuf = std::max(g.G, g.factored ? g.Gext : 0LL);
-    if ((st = hip_alloc(P, (void**)&P->ug[l - 1], (size_t)gbuf * sizeof(double)))) return st;
-    if (g.factored && (st = hip_alloc(P, (void**)&P->ut[l - 1], (size_t)g.Gext * sizeof(double))))
-      return st;
     ConvParams cp = level_conv<T>(P, l, false);
     if (conv_lds_bytes(cp, sizeof(T)) > 64 * 1024 || cp.lds_w > kConvMaxLW) return MSM_ERR_GRID;
     if (g.factored) {
@@ -193,41 +261,14 @@ msm_status upload_plan(msm_plan P) {
   if (hipMemcpy(P->Jd, J, sizeof(J), hipMemcpyHostToDevice)) return MSM_ERR_HIP;
   P->ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
   if ((long long)P->ncell * kCountCopies > (1LL << 30)) return MSM_ERR_GRID;
-  const size_t nmax = (size_t)std::max(hp.max_n, 1);
-  if ((st = hip_alloc(P, (void**)&P->cell_of, nmax * sizeof(int)))) return st;
-  if ((st = hip_alloc(P, (void**)&P->rank, nmax * sizeof(int)))) return st;
-  if ((st = hip_alloc(P, (void**)&P->counts, (size_t)P->ncell * kCountCopies * sizeof(int))))
-    return st;
-  // zero on entry to every binning (the cluster layout clears them after use)
-  if (hipMemset(P->counts, 0, (size_t)P->ncell * kCountCopies * sizeof(int))) return MSM_ERR_HIP;
-  if ((st = hip_alloc(P, (void**)&P->start, (size_t)(P->ncell + 1) * sizeof(int)))) return st;
-  if ((st = hip_alloc(P, (void**)&P->scan_tmp, (size_t)scan_tmp_ints(P->ncell) * sizeof(int))))
-    return st;
-  if ((st = hip_alloc(P, (void**)&P->perm, nmax * sizeof(int)))) return st;
-  if ((st = hip_alloc(P, &P->wrapped, nmax * 4 * sizeof(T)))) return st;
-  if ((st = hip_alloc(P, &P->sorted, nmax * 4 * sizeof(T)))) return st;
   {
-    const size_t ncl = (size_t)cluster_capacity((int)nmax, P->ncell);
-    // cluster slots plus the null j-group, addressed with 32-bit byte offsets
-    const size_t slots = ncl * 8 + kGroupSize;
-    if (slots * 4 * sizeof(T) >= (size_t(1) << 32)) return MSM_ERR_CAPACITY;
-    if ((st = hip_alloc(P, (void**)&P->cl_start, (size_t)(P->ncell + 1) * sizeof(int)))) return st;
-    if ((st = hip_alloc(P, &P->cpos, slots * 4 * sizeof(T)))) return st;
-    if ((st = hip_alloc(P, &P->cv, slots * 4 * sizeof(T)))) return st;
-    if ((st = hip_alloc(P, &P->cbox, ncl * 2 * 2 * 4 * sizeof(T)))) return st;
-    if ((st = hip_alloc(P, (void**)&P->cinfo, ncl * sizeof(int4)))) return st;
-    // the null j-group: zero charges far outside every cutoff, zero vectors
-    P->null_h = (int)(2 * ncl);
-    std::vector<T> far(4 * kGroupSize, T(1e15)), zero(4 * kGroupSize, T(0));
-    for (int r = 0; r < kGroupSize; ++r) far[4 * r + 3] = T(0);
-    if (hipMemcpy((T*)P->cpos + ncl * 8 * 4, far.data(), far.size() * sizeof(T),
-                  hipMemcpyHostToDevice) ||
-        hipMemcpy((T*)P->cv + ncl * 8 * 4, zero.data(), zero.size() * sizeof(T),
-                  hipMemcpyHostToDevice))
-      return MSM_ERR_HIP;
+    const size_t bytes = work_layout<T>(P, std::max(hp.max_n, 1), nullptr, nullptr);
+    if (bytes == 0) return MSM_ERR_CAPACITY;
+    void* base = nullptr;
+    if ((st = hip_alloc(P, &base, bytes))) return st;
+    work_layout<T>(P, std::max(hp.max_n, 1), (char*)base, &P->own);
+    if ((st = prepare_work<T>(P, P->own, nullptr))) return st;
   }
-  if ((st = hip_alloc(P, &P->phi0, nmax * sizeof(double)))) return st;
-  if ((st = hip_alloc(P, &P->F0, nmax * 3 * sizeof(T)))) return st;
   if ((st = hip_alloc(P, (void**)&P->flag, sizeof(int)))) return st;
   if (hipMemset(P->flag, 0, sizeof(int))) return MSM_ERR_HIP;
   if (hipStreamCreateWithFlags(&P->sb, hipStreamNonBlocking) ||
@@ -301,7 +342,7 @@ void grid_zero_jobs(msm_plan P, ZeroJobs& z) {
     const LevelGeom& g = hp.lev[l - 1];
     const ConvParams cp = level_conv<T>(P, l, g.factored);
     if (cp.nsplit > 1 && z.n < kZeroJobs) {
-      z.ptr[z.n] = P->ug[l - 1];
+      z.ptr[z.n] = P->w->ug[l - 1];
       z.words[z.n] = 2 * (g.factored ? g.Gext : g.G);
       z.n += 1;
     }
@@ -329,8 +370,8 @@ void conv_level(msm_plan P, int l, hipStream_t s) {
     // K^l q = omega' * (S^l * q): FP64 sample convolution, then omega' per axis
     ConvParams cs = level_conv<T>(P, l, true);
     int ev = pf.begin(cname, s);
-    launch_conv<T, double>(cs, P->S[l - 1], P->srowext[l - 1], (const T*)P->qg[l - 1],
-                           P->ug[l - 1], s);
+    launch_conv<T, double>(cs, P->S[l - 1], P->srowext[l - 1], (const T*)P->w->qg[l - 1],
+                           P->w->ug[l - 1], s);
     pf.end(ev, s);
     OmegaParams op;
     for (int k = 0; k < 3; ++k) {
@@ -341,15 +382,15 @@ void conv_level(msm_plan P, int l, hipStream_t s) {
     op.M = hp.M;
     for (int k = 0; k < 25; ++k) op.omega[k] = k <= hp.M ? hp.omega[k] : 0.0;
     ev = pf.begin(omega_names[l - 1], s);
-    launch_omega<T>(op, P->ug[l - 1], P->ut[l - 1], (T*)P->eg[l - 1], s);
+    launch_omega<T>(op, P->w->ug[l - 1], P->w->ut[l - 1], (T*)P->w->eg[l - 1], s);
     pf.end(ev, s);
   } else {
     // direct stencil, accumulated in FP64 (sums of thousands of terms with
     // cancellation)
     ConvParams cp = level_conv<T>(P, l, false);
     int ev = pf.begin(cname, s);
-    launch_conv<T, double>(cp, P->K64[l - 1], P->rowext64[l - 1], (const T*)P->qg[l - 1],
-                           P->ug[l - 1], s);
+    launch_conv<T, double>(cp, P->K64[l - 1], P->rowext64[l - 1], (const T*)P->w->qg[l - 1],
+                           P->w->ug[l - 1], s);
     pf.end(ev, s);
   }
 }
@@ -379,8 +420,8 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb, hipStream_t sd) {
   hipStream_t sc = fork ? sb : sa;
   if (L > 1) {
     int ev = pf.begin("restrict", sc);
-    launch_restrict<T>(p, grid_dev<T>(hp, 1), grid_dev<T>(hp, 2), hp.J, (const T*)P->qg[0],
-                       (T*)P->qg[1], sc);
+    launch_restrict<T>(p, grid_dev<T>(hp, 1), grid_dev<T>(hp, 2), hp.J, (const T*)P->w->qg[0],
+                       (T*)P->w->qg[1], sc);
     pf.end(ev, sc);
   }
   const bool fork2 = fork && sd != sc && L > 2;
@@ -394,7 +435,7 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb, hipStream_t sd) {
     int ev = pf.begin("restrict", se);
     for (int l = 2; l < L; ++l)
       launch_restrict<T>(p, grid_dev<T>(hp, l), grid_dev<T>(hp, l + 1), hp.J,
-                         (const T*)P->qg[l - 1], (T*)P->qg[l], se);
+                         (const T*)P->w->qg[l - 1], (T*)P->w->qg[l], se);
     pf.end(ev, se);
   }
   for (int l = 3; l <= L; ++l) conv_level<T>(P, l, se);
@@ -405,15 +446,15 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb, hipStream_t sd) {
   // 0-based level l of the output e^l: grid precision in eg[l] for a factored
   // level, FP64 in ug[l] for a direct one (until its prolongation)
   auto coarse_src64 = [&](int l) -> const double* {
-    return (l == L - 1 && !hp.lev[l].factored) ? P->ug[l] : nullptr;
+    return (l == L - 1 && !hp.lev[l].factored) ? P->w->ug[l] : nullptr;
   };
   auto fine_src64 = [&](int l) -> const double* {
-    return hp.lev[l].factored ? nullptr : P->ug[l];
+    return hp.lev[l].factored ? nullptr : P->w->ug[l];
   };
   int ev = pf.begin("prolong", sc);
   for (int l = L - 2; l >= 1; --l)
     launch_prolong<T>(p, grid_dev<T>(hp, l + 1), grid_dev<T>(hp, l + 2), hp.J,
-                      (const T*)P->eg[l + 1], coarse_src64(l + 1), (T*)P->eg[l],
+                      (const T*)P->w->eg[l + 1], coarse_src64(l + 1), (T*)P->w->eg[l],
                       fine_src64(l), sc);
   pf.end(ev, sc);
   if (fork) {
@@ -422,12 +463,12 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb, hipStream_t sd) {
   }
   if (L > 1) {
     ev = pf.begin("prolong", sa);
-    launch_prolong<T>(p, grid_dev<T>(hp, 1), grid_dev<T>(hp, 2), hp.J, (const T*)P->eg[1],
-                      coarse_src64(1), (T*)P->eg[0], fine_src64(0), sa);
+    launch_prolong<T>(p, grid_dev<T>(hp, 1), grid_dev<T>(hp, 2), hp.J, (const T*)P->w->eg[1],
+                      coarse_src64(1), (T*)P->w->eg[0], fine_src64(0), sa);
     pf.end(ev, sa);
   } else if (!hp.lev[0].factored) {
     int e2 = pf.begin("grid_cast", sa);
-    launch_cast<T>(P->ug[0], (T*)P->eg[0], hp.lev[0].G, sa);
+    launch_cast<T>(P->w->ug[0], (T*)P->w->eg[0], hp.lev[0].G, sa);
     pf.end(e2, sa);
   }
 }
@@ -445,9 +486,9 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   const HostPlan& hp = P->hp;
   const int L = hp.L, p = hp.p;
   // where the cell list goes: the caller's workspace if given (saved state)
-  vec4_t<T>* sorted = (vec4_t<T>*)P->sorted;
-  int* perm = P->perm;
-  int* start = P->start;
+  vec4_t<T>* sorted = (vec4_t<T>*)P->w->sorted;
+  int* perm = P->w->perm;
+  int* start = P->w->start;
   T* save_phi = nullptr;
   T* save_F = nullptr;
   T* save_e1 = nullptr;
@@ -473,7 +514,7 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   ZeroJobs z;
   z.n = 0;
   if (!anterp_tiled(p, n, cg, g1.n, g1.per, g1.hd)) {  // (tiles write every value)
-    z.ptr[z.n] = P->qg[0];
+    z.ptr[z.n] = P->w->qg[0];
     z.words[z.n++] = hp.lev[0].G * (long long)(sizeof(T) / 4);
   }
   z.ptr[z.n] = energy;
@@ -490,14 +531,14 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
     bp.per[k] = hp.periodic[k];
   }
   int ev = pf.begin("bin", s);
-  launch_binning<T>(n, pos, q, bp, P->ncell, P->cell_of, P->rank, P->counts,
-                    (vec4_t<T>*)P->wrapped, start, P->cl_start, sorted, perm, P->flag,
-                    P->scan_tmp, z, s);
+  launch_binning<T>(n, pos, q, bp, P->ncell, P->w->cell_of, P->w->rank, P->w->counts,
+                    (vec4_t<T>*)P->w->wrapped, start, P->w->cl_start, sorted, perm, P->flag,
+                    P->w->scan_tmp, z, s);
   pf.end(ev, s);
   ev = pf.begin("cluster", s);
-  launch_cluster_layout<T>(1, 0, P->ncell, start, P->cl_start, bp, (const vec4_t<T>*)P->wrapped,
-                           sorted, perm, (vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cbox, P->cinfo,
-                           P->counts, s);
+  launch_cluster_layout<T>(1, 0, P->ncell, start, P->w->cl_start, bp, (const vec4_t<T>*)P->w->wrapped,
+                           sorted, perm, (vec4_t<T>*)P->w->cpos, (vec4_t<T>*)P->w->cbox, P->w->cinfo,
+                           P->w->counts, s);
   pf.end(ev, s);
 
   // a2 short-range pairs (i-clusters against culled j particles), on its
@@ -511,25 +552,25 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   }
   const PairParams<T> pp = pair_params<T>(hp);
   ev = pf.begin("pair", sp);
-  launch_pair_cl<T>(p, n, P->ncell, P->cl_start, (const vec4_t<T>*)P->cpos,
-                    (const vec4_t<T>*)P->cbox, P->cinfo, pp, (double*)P->phi0, (T*)P->F0, sp);
+  launch_pair_cl<T>(p, n, P->ncell, P->w->cl_start, (const vec4_t<T>*)P->w->cpos,
+                    (const vec4_t<T>*)P->w->cbox, P->w->cinfo, pp, (double*)P->w->phi0, (T*)P->w->F0, sp);
   pf.end(ev, sp);
   if (dag) (void)hipEventRecord(P->ev[1], sp);
 
   // a3 anterpolation onto level 1
   ev = pf.begin("anterp", s);
-  launch_anterp<T>(p, n, P->ncell, start, cg, sorted, g1, (T*)P->qg[0], s);
+  launch_anterp<T>(p, n, P->ncell, start, cg, sorted, g1, (T*)P->w->qg[0], s);
   pf.end(ev, s);
   // a4 restriction, a5 per-level stencils, a6 top level, a7 prolongation
   grid_pass<T>(P, s, dag ? P->sb : s, dag ? P->sd : s);
   if (dag) (void)hipStreamWaitEvent(s, P->ev[1], 0);
   // a8 + a9 interpolation, combination, energy
   ev = pf.begin("interp", s);
-  launch_interp<T>(p, n, sorted, perm, g1, (const T*)P->eg[0], (const double*)P->phi0,
-                   (const T*)P->F0, hp.self_const, dEdq, F, save_phi, save_F, energy, s);
+  launch_interp<T>(p, n, sorted, perm, g1, (const T*)P->w->eg[0], (const double*)P->w->phi0,
+                   (const T*)P->w->F0, hp.self_const, dEdq, F, save_phi, save_F, energy, s);
   pf.end(ev, s);
   if (save_e1)
-    if (hipMemcpyAsync(save_e1, P->eg[0], sizeof(T) * hp.lev[0].G, hipMemcpyDeviceToDevice, s))
+    if (hipMemcpyAsync(save_e1, P->w->eg[0], sizeof(T) * hp.lev[0].G, hipMemcpyDeviceToDevice, s))
       return MSM_ERR_HIP;
   if (hipGetLastError() != hipSuccess) return MSM_ERR_HIP;
   return MSM_OK;
@@ -555,9 +596,9 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
     pf.end(ev, s);
     return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
   }
-  vec4_t<T>* v = (vec4_t<T>*)P->wrapped;  // cotangent in cell order
-  T* gq_sr = (T*)P->phi0;
-  T* gr_sr = (T*)P->F0;
+  vec4_t<T>* v = (vec4_t<T>*)P->w->wrapped;  // cotangent in cell order
+  T* gq_sr = (T*)P->w->phi0;
+  T* gr_sr = (T*)P->w->F0;
   int ev = pf.begin("bwd_layout", s);
   launch_gather_v<T>(n, perm, gF, v, s);
   {
@@ -569,9 +610,9 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
       bp.nc[k] = hp.nc[k];
       bp.per[k] = hp.periodic[k];
     }
-    launch_cluster_layout<T>(0, 1, P->ncell, start, P->cl_start, bp, nullptr,
+    launch_cluster_layout<T>(0, 1, P->ncell, start, P->w->cl_start, bp, nullptr,
                              const_cast<vec4_t<T>*>(sorted), const_cast<int*>(perm),
-                             (vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cbox, P->cinfo, nullptr, s);
+                             (vec4_t<T>*)P->w->cpos, (vec4_t<T>*)P->w->cbox, P->w->cinfo, nullptr, s);
   }
   pf.end(ev, s);
   // the pair-sum VJP beside the grid part (as in the forward)
@@ -582,9 +623,9 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
     (void)hipStreamWaitEvent(sp, P->ev[0], 0);
   }
   ev = pf.begin("bwd_pair", sp);
-  launch_pair_vjp_cl<T>(p, n, P->ncell, P->cl_start, P->cinfo, perm, gF,
-                        (const vec4_t<T>*)P->cpos, (vec4_t<T>*)P->cv, (const vec4_t<T>*)P->cbox,
-                        pair_params<T>(hp), P->null_h, gq_sr, gr_sr, sp);
+  launch_pair_vjp_cl<T>(p, n, P->ncell, P->w->cl_start, P->w->cinfo, perm, gF,
+                        (const vec4_t<T>*)P->w->cpos, (vec4_t<T>*)P->w->cv, (const vec4_t<T>*)P->w->cbox,
+                        pair_params<T>(hp), P->w->null_h, gq_sr, gr_sr, sp);
   pf.end(ev, sp);
   if (dag) (void)hipEventRecord(P->ev[1], sp);
   const GridDev<T> g1 = grid_dev<T>(hp, 1);
@@ -592,7 +633,7 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
   {
     ZeroJobs z;
     z.n = 0;
-    z.ptr[z.n] = P->qg[0];
+    z.ptr[z.n] = P->w->qg[0];
     z.words[z.n++] = hp.lev[0].G * (long long)(sizeof(T) / 4);
     grid_zero_jobs<T>(P, z);
     launch_zero_multi(z, s);
@@ -603,13 +644,13 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
       cg.nc[k] = hp.nc[k];
       cg.cs[k] = hp.cs[k];
     }
-    launch_anterp_dipole<T>(p, n, P->ncell, start, cg, sorted, v, g1, (T*)P->qg[0], s);
+    launch_anterp_dipole<T>(p, n, P->ncell, start, cg, sorted, v, g1, (T*)P->w->qg[0], s);
   }
   pf.end(ev, s);
   grid_pass<T>(P, s, dag ? P->sb : s, dag ? P->sd : s);  // eg[0] = (A D)^{1+}
   if (dag) (void)hipStreamWaitEvent(s, P->ev[1], 0);
   ev = pf.begin("bwd_interp", s);
-  launch_interp_vjp<T>(p, n, sorted, v, perm, g1, save_e1, (const T*)P->eg[0], save_phi, save_F,
+  launch_interp_vjp<T>(p, n, sorted, v, perm, g1, save_e1, (const T*)P->w->eg[0], save_phi, save_F,
                        gq_sr, gr_sr, gE, grad_q, grad_pos, s);
   pf.end(ev, s);
   return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
@@ -777,11 +818,11 @@ msm_status msm_plan_get_grid(msm_plan plan, int level, int which, void* dst, voi
   if (which == 1 && level == hp.L && hp.L > 1 && !hp.lev[level - 1].factored) {
     // the top level's potential lives in its FP64 buffer (prolongation reads
     // it there); hand it out in the grid precision
-    if (hp.precision == MSM_FP64) launch_cast<double>(plan->ug[level - 1], (double*)dst, G, (hipStream_t)stream);
-    else launch_cast<float>(plan->ug[level - 1], (float*)dst, G, (hipStream_t)stream);
+    if (hp.precision == MSM_FP64) launch_cast<double>(plan->w->ug[level - 1], (double*)dst, G, (hipStream_t)stream);
+    else launch_cast<float>(plan->w->ug[level - 1], (float*)dst, G, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
   }
-  const void* src = which == 0 ? plan->qg[level - 1] : plan->eg[level - 1];
+  const void* src = which == 0 ? plan->w->qg[level - 1] : plan->w->eg[level - 1];
   if (hipMemcpyAsync(dst, src, tsize(hp) * G, hipMemcpyDeviceToDevice, (hipStream_t)stream) !=
       hipSuccess)
     return MSM_ERR_HIP;

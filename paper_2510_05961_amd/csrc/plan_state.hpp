@@ -19,6 +19,41 @@ void destroy_batch(BatchState* b);
 constexpr int kFlagOffsets = 4;
 }  // namespace msm
 
+namespace msm {
+// Working memory of one forward or backward call, overwritten by every call:
+// per level the grid charge and potential (plan precision) and the FP64
+// convolution buffers (ug: the convolution's output or atomic target; ut:
+// the x pass of omega' on factored levels); the cell list and cluster
+// layout of the particles; the short-range outputs.  counts must be zero on
+// entry to a call (the cluster layout leaves it so), and cpos / cv hold the
+// null j-group (far-away zero charges, zero vectors) at index null_h.
+struct WorkBufs {
+  void* qg[kMaxLevels] = {};
+  void* eg[kMaxLevels] = {};
+  double* ug[kMaxLevels] = {};
+  double* ut[kMaxLevels] = {};
+  int* cell_of = nullptr;
+  int* rank = nullptr;
+  int* counts = nullptr;
+  int* start = nullptr;
+  int* perm = nullptr;
+  // 8-particle clusters of the short-range sum: offsets per cell, padded
+  // slots (x, y, z, q), boxes (lo, hi), info (first sorted index, count,
+  // cell), force cotangent in slot order (backward)
+  int* cl_start = nullptr;
+  int* scan_tmp = nullptr;  // block totals of the many-workgroup cell scan
+  void* cpos = nullptr;
+  void* cbox = nullptr;
+  int4* cinfo = nullptr;
+  void* cv = nullptr;
+  void* wrapped = nullptr;
+  void* sorted = nullptr;
+  void* phi0 = nullptr;
+  void* F0 = nullptr;
+  int null_h = 0;  // index of the null j-group in cpos / cv
+};
+}  // namespace msm
+
 // Event-pair stage timer (enabled by msm_plan_set_profiling).
 struct StageProfiler {
   bool on = false;
@@ -101,39 +136,20 @@ struct msm_plan_s {
   bool device = false;
   bool batch = false;
   int ncell = 0;
-  int null_h = 0;  // index of the null j-group in cpos / cv
   // device buffers (T = plan precision); stencils in FP64 with zero-padded
   // rows (conv_row_stride) and per-row non-zero x ranges
   double* K64[msm::kMaxLevels] = {};
   int2* rowext64[msm::kMaxLevels] = {};
   // geometry of the uploaded stencils (direct K, factored-level samples S)
   msm::ConvGeom kgeom[msm::kMaxLevels] = {}, sgeom[msm::kMaxLevels] = {};
-  void* qg[msm::kMaxLevels] = {};
-  void* eg[msm::kMaxLevels] = {};
-  // factored levels: FP64 k-samples, their row extents, FP64 partial grid
+  // factored levels: FP64 k-samples and their row extents
   double* S[msm::kMaxLevels] = {};
   int2* srowext[msm::kMaxLevels] = {};
-  double* ug[msm::kMaxLevels] = {};
-  double* ut[msm::kMaxLevels] = {};  // omega' x-pass output (factored levels)
+  // working memory of the calls (own: allocated with the plan for max_n;
+  // w points at the set the current call uses)
+  msm::WorkBufs own;
+  msm::WorkBufs* w = &own;
   void* Jd = nullptr;
-  int* cell_of = nullptr;
-  int* rank = nullptr;
-  int* counts = nullptr;
-  int* start = nullptr;
-  int* perm = nullptr;
-  // 8-particle clusters of the short-range sum: offsets per cell, padded
-  // slots (x, y, z, q), boxes (lo, hi), info (first sorted index, count,
-  // cell), force cotangent in slot order (backward)
-  int* cl_start = nullptr;
-  int* scan_tmp = nullptr;  // block totals of the many-workgroup cell scan
-  void* cpos = nullptr;
-  void* cbox = nullptr;
-  int4* cinfo = nullptr;
-  void* cv = nullptr;
-  void* wrapped = nullptr;
-  void* sorted = nullptr;
-  void* phi0 = nullptr;
-  void* F0 = nullptr;
   int* flag = nullptr;
   // side streams of the forward DAG (default priority, non-blocking) and the
   // fork/join events between them and the caller's stream
