@@ -130,6 +130,27 @@ msm_status msm_energy_forces(msm_plan plan, int n, const void* pos, const void* 
                              double* energy, void* forces, void* dEdq, void* stream);
 
 /*
+ * msm_energy_forces_noalloc -- msm_energy_forces for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the call allocates nothing.  Its working
+ * memory (grids, cell list, cluster layout, short-range sums) is a static
+ * array of the library, 64 MiB per GPU, held from the library's load until
+ * the process ends, instead of the plan's own working buffers; the plan's
+ * stencils and streams are used as they are.  Arguments as for
+ * msm_energy_forces, except that n is bounded by that array instead of
+ * max_n: MSM_ERR_CAPACITY when the call's working memory (plan grids plus
+ * about 200 bytes per particle in FP32) would exceed 64 MiB.  The plan's
+ * GPU must be the current device (else MSM_ERR_INVALID_ARG).  ws, if given,
+ * receives the saved state as in msm_energy_forces, for msm_backward.
+ * Every such call on one GPU uses the same array: calls that overlap on one
+ * GPU (several streams or host threads) race, and msm_plan_get_grid keeps
+ * reporting the plan's own grids.  Stage profiling is not recorded.
+ */
+msm_status msm_energy_forces_noalloc(msm_plan plan, int n, const void* pos, const void* q,
+                                     void* ws, double* energy, void* forces, void* dEdq,
+                                     void* stream);
+
+/*
  * msm_backward -- vector-Jacobian product of the forward outputs.
  * For the scalar L = gE * U + sum_i gF_i . F_i it writes
  *   grad_q[i]   = dL/dq_i   = gE dU/dq_i + d(sum gF.F)/dq_i

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -205,6 +206,7 @@ template <typename T>
 msm_status upload_plan(msm_plan P) {
   HostPlan& hp = P->hp;
   msm_status st;
+  if (hipGetDevice(&P->device_id) != hipSuccess) return MSM_ERR_HIP;
   // an FP64 stencil [len2][len1][len0] as the convolution reads it: rows
   // padded with zeros to conv_row_stride(len0), kConvRowPad zero rows before
   // and after every plane, plus the [first, last] non-zero x range of every
@@ -695,6 +697,52 @@ msm_status create_common(msm_plan* out, const double box[3], unsigned mask, int 
   return MSM_OK;
 }
 
+// Working memory of msm_energy_forces_noalloc: one array per GPU, held from
+// the library's load until the process ends.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex scratch_mutex;
+void* scratch_ptr[kScratchDevices] = {};
+
+msm_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kScratchDevices) return MSM_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return MSM_ERR_HIP;
+    }
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return MSM_OK;
+}
+
+template <typename T>
+msm_status forward_noalloc(msm_plan P, int n, const T* pos, const T* q, void* ws,
+                           double* energy, T* F, T* dEdq, hipStream_t s) {
+  const size_t need = work_layout<T>(P, n, nullptr, nullptr);
+  if (need == 0 || need > kScratchBytes) return MSM_ERR_CAPACITY;
+  void* base = nullptr;
+  msm_status st = scratch_address(P->device_id, &base);
+  if (st != MSM_OK) return st;
+  WorkBufs w;
+  work_layout<T>(P, n, (char*)base, &w);
+  if ((st = prepare_work<T>(P, w, s))) return st;
+  // no stage events either (their creation would allocate)
+  const bool prof = P->prof.on;
+  P->prof.on = false;
+  P->w = &w;
+  st = forward<T>(P, n, pos, q, ws, energy, F, dEdq, s);
+  P->w = &P->own;
+  P->prof.on = prof;
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -773,6 +821,22 @@ msm_status msm_energy_forces(msm_plan plan, int n, const void* pos, const void* 
                            (double*)forces, (double*)dEdq, s);
   return forward<float>(plan, n, (const float*)pos, (const float*)q, ws, energy, (float*)forces,
                         (float*)dEdq, s);
+}
+
+msm_status msm_energy_forces_noalloc(msm_plan plan, int n, const void* pos, const void* q,
+                                     void* ws, double* energy, void* forces, void* dEdq,
+                                     void* stream) {
+  if (!plan || plan->batch) return MSM_ERR_INVALID_ARG;
+  if (!plan->device) return MSM_ERR_NO_DEVICE;
+  if (n < 0 || !energy || (n > 0 && (!pos || !q))) return MSM_ERR_INVALID_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device_id) return MSM_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->hp.precision == MSM_FP64)
+    return forward_noalloc<double>(plan, n, (const double*)pos, (const double*)q, ws, energy,
+                                   (double*)forces, (double*)dEdq, s);
+  return forward_noalloc<float>(plan, n, (const float*)pos, (const float*)q, ws, energy,
+                                (float*)forces, (float*)dEdq, s);
 }
 
 msm_status msm_backward(msm_plan plan, int n, const void* pos, const void* q, const void* ws,

@@ -134,6 +134,7 @@ struct msm_plan_s {
   msm::HostPlan hp;
   StageProfiler prof;
   bool device = false;
+  int device_id = -1;  // the GPU the plan's memory lives on
   bool batch = false;
   int ncell = 0;
   // device buffers (T = plan precision); stencils in FP64 with zero-padded

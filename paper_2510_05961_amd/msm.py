@@ -23,7 +23,7 @@ _lib = None
 # every symbol declared in include/msm.h
 EXPORTS = ("msm_plan_create", "msm_plan_create_host", "msm_plan_destroy", "msm_plan_describe",
            "msm_plan_get_stencil", "msm_plan_grid_dims", "msm_workspace_bytes",
-           "msm_energy_forces", "msm_backward", "msm_plan_status", "msm_plan_get_grid",
+           "msm_energy_forces", "msm_energy_forces_noalloc", "msm_backward", "msm_plan_status", "msm_plan_get_grid",
            "msm_batch_plan_create", "msm_batch_energy_forces", "msm_status_string",
            "msm_plan_set_profiling", "msm_plan_get_profile", "msm_plan_set_profile_stages")
 
@@ -56,6 +56,7 @@ def lib():
         L.msm_workspace_bytes.argtypes = [P, i, i]
         L.msm_workspace_bytes.restype = sz
         L.msm_energy_forces.argtypes = [P, i, P, P, P, P, P, P, P]
+        L.msm_energy_forces_noalloc.argtypes = [P, i, P, P, P, P, P, P, P]
         L.msm_backward.argtypes = [P, i, P, P, P, P, P, P, P, P]
         L.msm_plan_status.argtypes = [P, P]
         L.msm_plan_get_grid.argtypes = [P, i, i, P, P]
@@ -165,6 +166,18 @@ class Plan:
             E, F, dq = out
         _check(lib().msm_energy_forces(self._h, n, _ptr(pos), _ptr(q), _ptr(ws), _ptr(E),
                                        _ptr(F), _ptr(dq), _stream(stream)), "msm_energy_forces")
+        return E, F, dq
+
+    def energy_forces_noalloc(self, pos, q, out, ws=None, stream=None):
+        """msm_energy_forces_noalloc into the caller's outputs out = (E[1] f64,
+        F [n,3] or None, dEdq [n] or None); the call allocates nothing."""
+        n = q.shape[0]
+        assert pos.is_cuda and q.is_cuda and pos.dtype == self.dtype and q.dtype == self.dtype
+        assert pos.is_contiguous() and q.is_contiguous() and tuple(pos.shape) == (n, 3)
+        E, F, dq = out
+        _check(lib().msm_energy_forces_noalloc(self._h, n, _ptr(pos), _ptr(q), _ptr(ws), _ptr(E),
+                                               _ptr(F), _ptr(dq), _stream(stream)),
+               "msm_energy_forces_noalloc")
         return E, F, dq
 
     def backward(self, pos, q, ws, gE=None, gF=None, stream=None):
