@@ -189,6 +189,31 @@ static int basis_axis(const orc_geom* g, int level, int ax, double x, axis_basis
   return 0;
 }
 
+/* Grid coordinates of a position: r itself in an orthorhombic box; in a
+ * triclinic cell the fractional coordinates s = H^{-1} r, in which the grids
+ * are rectangular (the unit-cube transform, Sec. MSM core algorithm). */
+static void grid_position(const orc_geom* g, const double* r, double s[3])
+{
+  for (int k = 0; k < 3; ++k)
+    s[k] = g->tri ? g->Hinv[3 * k] * r[0] + g->Hinv[3 * k + 1] * r[1] + g->Hinv[3 * k + 2] * r[2]
+                  : r[k];
+}
+
+/* A vector v in grid coordinates: H^{-1} v in a triclinic cell (so that
+ * v . grad_r f = (H^{-1} v) . grad_s f), v itself otherwise. */
+static void grid_vector(const orc_geom* g, const double* v, double vs[3])
+{
+  grid_position(g, v, vs);
+}
+
+/* A gradient taken in grid coordinates, made Cartesian: grad_r = H^{-T} grad_s. */
+static void cart_gradient(const orc_geom* g, const double gs[3], double gr[3])
+{
+  for (int j = 0; j < 3; ++j)
+    gr[j] = g->tri ? g->Hinv[j] * gs[0] + g->Hinv[3 + j] * gs[1] + g->Hinv[6 + j] * gs[2]
+                   : gs[j];
+}
+
 static long flat(const orc_geom* g, int level, int ix, int iy, int iz)
 {
   const int* n = g->n[level - 1];
@@ -203,9 +228,10 @@ int orc_anterpolate(const orc_geom* g, int level, int n, const double* pos,
   const int p = g->p;
   for (int i = 0; i < n; ++i) {
     axis_basis bx, by, bz;
-    if (basis_axis(g, level, 0, pos[3 * i + 0], &bx) ||
-        basis_axis(g, level, 1, pos[3 * i + 1], &by) ||
-        basis_axis(g, level, 2, pos[3 * i + 2], &bz))
+    double x[3];
+    grid_position(g, pos + 3 * i, x);
+    if (basis_axis(g, level, 0, x[0], &bx) || basis_axis(g, level, 1, x[1], &by) ||
+        basis_axis(g, level, 2, x[2], &bz))
       return -1;
     for (int c = 0; c < p; ++c)
       for (int b = 0; b < p; ++b)
@@ -224,9 +250,11 @@ int orc_anterpolate_dipole(const orc_geom* g, int level, int n, const double* po
   const int p = g->p;
   for (int i = 0; i < n; ++i) {
     axis_basis bx, by, bz;
-    if (basis_axis(g, level, 0, pos[3 * i + 0], &bx) ||
-        basis_axis(g, level, 1, pos[3 * i + 1], &by) ||
-        basis_axis(g, level, 2, pos[3 * i + 2], &bz))
+    double x[3], vs[3];
+    grid_position(g, pos + 3 * i, x);
+    grid_vector(g, v + 3 * i, vs);
+    if (basis_axis(g, level, 0, x[0], &bx) || basis_axis(g, level, 1, x[1], &by) ||
+        basis_axis(g, level, 2, x[2], &bz))
       return -1;
     for (int c = 0; c < p; ++c)
       for (int b = 0; b < p; ++b)
@@ -236,7 +264,7 @@ int orc_anterpolate_dipole(const orc_geom* g, int level, int n, const double* po
           double gy = bx.w[a] * by.dw[b] * bz.w[c];
           double gz = bx.w[a] * by.w[b] * bz.dw[c];
           grid[flat(g, level, bx.idx[a], by.idx[b], bz.idx[c])] +=
-              q[i] * (v[3 * i] * gx + v[3 * i + 1] * gy + v[3 * i + 2] * gz);
+              q[i] * (vs[0] * gx + vs[1] * gy + vs[2] * gz);
         }
   }
   return 0;
@@ -246,7 +274,9 @@ int orc_anterpolate_dipole(const orc_geom* g, int level, int n, const double* po
  * Stencil (eq. kernel_stencil_by_conv_with_universal_coeff):
  *   K^l_m = sum_n omega'_{mx-nx} omega'_{my-ny} omega'_{mz-nz} k_l(|h_l o n|)
  * written as the plain triple sum over the omega' support.  The samples of
- * k_l are tabulated first on the box |n_k| <= W_k + M.
+ * k_l are tabulated first on the box |n_k| <= W_k + M.  In a triclinic cell
+ * the grid offset n is the Cartesian vector H (h_l o n) (fractional spacing
+ * h_l = 1/n_l along each lattice vector).
  * ---------------------------------------------------------------------- */
 static double omega_at(const orc_geom* g, int j)
 {
@@ -268,8 +298,11 @@ void orc_stencil(const orc_geom* g, int level, const int W[3], double* K)
   for (int z = -S[2]; z <= S[2]; ++z)
     for (int y = -S[1]; y <= S[1]; ++y)
       for (int x = -S[0]; x <= S[0]; ++x) {
-        double rx = x * h[0], ry = y * h[1], rz = z * h[2];
-        double r = sqrt(rx * rx + ry * ry + rz * rz);
+        double u[3] = {x * h[0], y * h[1], z * h[2]}, d[3];
+        for (int k = 0; k < 3; ++k)
+          d[k] = g->tri ? g->H[3 * k] * u[0] + g->H[3 * k + 1] * u[1] + g->H[3 * k + 2] * u[2]
+                        : u[k];
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         samp[((long)(z + S[2]) * ns[1] + (y + S[1])) * ns[0] + (x + S[0])] =
             orc_kernel(level, g->L, g->a, g->p, r);
       }
@@ -352,9 +385,10 @@ int orc_interpolate(const orc_geom* g, int level, int n, const double* pos,
 #pragma omp parallel for schedule(static) reduction(| : bad)
   for (int i = 0; i < n; ++i) {
     axis_basis bx, by, bz;
-    if (basis_axis(g, level, 0, pos[3 * i + 0], &bx) ||
-        basis_axis(g, level, 1, pos[3 * i + 1], &by) ||
-        basis_axis(g, level, 2, pos[3 * i + 2], &bz)) {
+    double x[3];
+    grid_position(g, pos + 3 * i, x);
+    if (basis_axis(g, level, 0, x[0], &bx) || basis_axis(g, level, 1, x[1], &by) ||
+        basis_axis(g, level, 2, x[2], &bz)) {
       bad = 1;
       continue;
     }
@@ -371,9 +405,11 @@ int orc_interpolate(const orc_geom* g, int level, int n, const double* pos,
         }
     if (phi) phi[i] += v;
     if (F) {
-      F[3 * i + 0] -= q[i] * gx;
-      F[3 * i + 1] -= q[i] * gy;
-      F[3 * i + 2] -= q[i] * gz;
+      double gs[3] = {gx, gy, gz}, gr[3];
+      cart_gradient(g, gs, gr);
+      F[3 * i + 0] -= q[i] * gr[0];
+      F[3 * i + 1] -= q[i] * gr[1];
+      F[3 * i + 2] -= q[i] * gr[2];
     }
   }
   return bad ? -1 : 0;
@@ -393,13 +429,15 @@ int orc_interpolate_vjp(const orc_geom* g, int level, int n, const double* pos,
 #pragma omp parallel for schedule(static) reduction(| : bad)
   for (int i = 0; i < n; ++i) {
     axis_basis bx, by, bz;
-    if (basis_axis(g, level, 0, pos[3 * i + 0], &bx) ||
-        basis_axis(g, level, 1, pos[3 * i + 1], &by) ||
-        basis_axis(g, level, 2, pos[3 * i + 2], &bz)) {
+    double x[3], vs[3];
+    grid_position(g, pos + 3 * i, x);
+    grid_vector(g, v + 3 * i, vs); /* grid-coordinate cotangent */
+    if (basis_axis(g, level, 0, x[0], &bx) || basis_axis(g, level, 1, x[1], &by) ||
+        basis_axis(g, level, 2, x[2], &bz)) {
       bad = 1;
       continue;
     }
-    const double vx = v[3 * i], vy = v[3 * i + 1], vz = v[3 * i + 2];
+    const double vx = vs[0], vy = vs[1], vz = vs[2];
     double sq = 0.0, sr[3] = {0, 0, 0};
     for (int c = 0; c < p; ++c)
       for (int b = 0; b < p; ++b)
@@ -423,7 +461,9 @@ int orc_interpolate_vjp(const orc_geom* g, int level, int n, const double* pos,
                      psi[f] * (H[k][0] * vx + H[k][1] * vy + H[k][2] * vz);
         }
     gq[i] -= sq;
-    for (int k = 0; k < 3; ++k) gr[3 * i + k] -= q[i] * sr[k];
+    double srr[3];
+    cart_gradient(g, sr, srr); /* grad_r = H^{-T} grad_s, Hess_r v = H^{-T} Hess_s H^{-1} v */
+    for (int k = 0; k < 3; ++k) gr[3 * i + k] -= q[i] * srr[k];
   }
   return bad ? -1 : 0;
 }
@@ -434,8 +474,35 @@ int orc_interpolate_vjp(const orc_geom* g, int level, int n, const double* pos,
  * ---------------------------------------------------------------------- */
 static void min_image(const orc_geom* g, double d[3])
 {
-  for (int k = 0; k < 3; ++k)
-    if (g->periodic[k]) d[k] -= g->box[k] * round(d[k] / g->box[k]);
+  if (!g->tri) {
+    for (int k = 0; k < 3; ++k)
+      if (g->periodic[k]) d[k] -= g->box[k] * round(d[k] / g->box[k]);
+    return;
+  }
+  /* triclinic: round the fractional difference, then take the shortest of
+   * that image and its 26 neighbours (rounding alone can miss the nearest
+   * image of a skewed cell) */
+  double ds[3];
+  grid_position(g, d, ds);
+  for (int k = 0; k < 3; ++k) ds[k] -= round(ds[k]);
+  double best[3] = {0, 0, 0}, b2 = INFINITY;
+  for (int jz = -1; jz <= 1; ++jz)
+    for (int jy = -1; jy <= 1; ++jy)
+      for (int jx = -1; jx <= 1; ++jx) {
+        double u[3] = {ds[0] + jx, ds[1] + jy, ds[2] + jz}, c[3];
+        for (int k = 0; k < 3; ++k)
+          c[k] = g->H[3 * k] * u[0] + g->H[3 * k + 1] * u[1] + g->H[3 * k + 2] * u[2];
+        double r2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        if (r2 < b2) {
+          b2 = r2;
+          best[0] = c[0];
+          best[1] = c[1];
+          best[2] = c[2];
+        }
+      }
+  d[0] = best[0];
+  d[1] = best[1];
+  d[2] = best[2];
 }
 
 void orc_short_range(const orc_geom* g, int n, const double* pos, const double* q,
@@ -476,8 +543,15 @@ typedef struct {
 
 static void cell_list_build(const orc_geom* g, int n, const double* pos, cell_list* cl)
 {
+  /* (triclinic: cells in fractional coordinates, as many per axis as the
+   * cell's width across that axis, V / |face|, holds whole cutoffs) */
   for (int k = 0; k < 3; ++k) {
-    cl->nc[k] = (int)floor(g->box[k] / g->a);
+    double w = g->box[k];
+    if (g->tri) {
+      const double* b = g->Hinv + 3 * k;
+      w = 1.0 / sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    }
+    cl->nc[k] = (int)floor(w / g->a);
     if (cl->nc[k] < 1) cl->nc[k] = 1;
     cl->cs[k] = g->box[k] / cl->nc[k];
   }
@@ -488,8 +562,10 @@ static void cell_list_build(const orc_geom* g, int n, const double* pos, cell_li
   for (long c = 0; c < ncell; ++c) cl->head[c] = -1;
   for (int i = n - 1; i >= 0; --i) {
     int ci[3];
+    double xs[3];
+    grid_position(g, pos + 3 * i, xs);
     for (int k = 0; k < 3; ++k) {
-      double x = pos[3 * i + k];
+      double x = xs[k];
       if (g->periodic[k]) x -= g->box[k] * floor(x / g->box[k]);
       int c = (int)floor(x / cl->cs[k]);
       if (c < 0) c = 0;
@@ -738,6 +814,84 @@ double orc_ewald2d(const double box[3], double alpha, const double x[3], int reg
   double k0 = -(2.0 * M_PI / A) *
               (z * erf(alpha * z) + exp(-alpha * alpha * z * z) / (alpha * sqrt(M_PI)));
   return real + recip + k0;
+}
+
+static double det3(const double A[9])
+{
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+         A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+/* The same sums for the lattice L = {H n}: real space over lattice vectors,
+ * reciprocal space over k = 2 pi H^{-T} m, V = |det H|. */
+double orc_ewald3d_cell(const double H[9], double alpha, const double x[3], int reg)
+{
+  const double det = det3(H), V = fabs(det);
+  double Hi[9]; /* H^{-1} by cofactors */
+  Hi[0] = (H[4] * H[8] - H[5] * H[7]) / det;
+  Hi[1] = (H[2] * H[7] - H[1] * H[8]) / det;
+  Hi[2] = (H[1] * H[5] - H[2] * H[4]) / det;
+  Hi[3] = (H[5] * H[6] - H[3] * H[8]) / det;
+  Hi[4] = (H[0] * H[8] - H[2] * H[6]) / det;
+  Hi[5] = (H[2] * H[3] - H[0] * H[5]) / det;
+  Hi[6] = (H[3] * H[7] - H[4] * H[6]) / det;
+  Hi[7] = (H[1] * H[6] - H[0] * H[7]) / det;
+  Hi[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+  const double rc = ORC_EWALD_X / alpha, kc = 2.0 * alpha * ORC_EWALD_X;
+  /* image range: |n_k| covers |s_k(x)| + rc |row k of H^{-1}| */
+  int nr[3], nk[3];
+  for (int k = 0; k < 3; ++k) {
+    double bk = sqrt(Hi[3 * k] * Hi[3 * k] + Hi[3 * k + 1] * Hi[3 * k + 1] +
+                     Hi[3 * k + 2] * Hi[3 * k + 2]);
+    double sk = Hi[3 * k] * x[0] + Hi[3 * k + 1] * x[1] + Hi[3 * k + 2] * x[2];
+    nr[k] = (int)ceil(rc * bk + fabs(sk)) + 1;
+    double ak = sqrt(H[k] * H[k] + H[3 + k] * H[3 + k] + H[6 + k] * H[6 + k]);
+    nk[k] = (int)ceil(kc * ak / (2.0 * M_PI)) + 1;
+  }
+  double real = 0.0;
+  for (int jz = -nr[2]; jz <= nr[2]; ++jz)
+    for (int jy = -nr[1]; jy <= nr[1]; ++jy)
+      for (int jx = -nr[0]; jx <= nr[0]; ++jx) {
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = x[k] + H[3 * k] * jx + H[3 * k + 1] * jy + H[3 * k + 2] * jz;
+        double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (r == 0.0) {
+          if (!reg) return INFINITY;
+          real -= 2.0 * alpha / sqrt(M_PI);
+          continue;
+        }
+        if (r > rc) continue;
+        real += erfc(alpha * r) / r;
+      }
+  double recip = 0.0;
+  for (int mz = -nk[2]; mz <= nk[2]; ++mz)
+    for (int my = -nk[1]; my <= nk[1]; ++my)
+      for (int mx = -nk[0]; mx <= nk[0]; ++mx) {
+        if (mx == 0 && my == 0 && mz == 0) continue;
+        double gk[3];
+        for (int j = 0; j < 3; ++j)
+          gk[j] = 2.0 * M_PI * (Hi[j] * mx + Hi[3 + j] * my + Hi[6 + j] * mz);
+        double k2 = gk[0] * gk[0] + gk[1] * gk[1] + gk[2] * gk[2];
+        if (k2 > kc * kc) continue;
+        recip += exp(-k2 / (4.0 * alpha * alpha)) * cos(gk[0] * x[0] + gk[1] * x[1] + gk[2] * x[2]) / k2;
+      }
+  recip *= 4.0 * M_PI / V;
+  return real + recip - M_PI / (alpha * alpha * V);
+}
+
+void orc_ewald_potentials_cell(const double H[9], double alpha, int n, const double* pos,
+                               const double* q, double* phi)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                     pos[3 * i + 2] - pos[3 * j + 2]};
+      s += q[j] * orc_ewald3d_cell(H, alpha, d, j == i);
+    }
+    phi[i] = s;
+  }
 }
 
 void orc_ewald_potentials(const double box[3], int slab, double alpha, int n,

@@ -32,6 +32,12 @@ typedef struct {
   int lo[ORC_MAXL][3];
   double h[ORC_MAXL][3];
   double omega[32];       /* omega'_0 .. omega'_M (symmetric sequence)      */
+  /* Triclinic cell (tri = 1, all axes periodic): the grids live in the unit
+   * cube of fractional coordinates s = H^{-1} r (box = 1, h = 1/n), H the
+   * cell matrix whose columns are the lattice vectors (H[3*row + col]). */
+  int tri;
+  double H[9];
+  double Hinv[9];
 } orc_geom;
 
 int orc_num_threads(void);
@@ -98,10 +104,14 @@ void orc_direct_coulomb(int n, const double* pos, const double* q, double* phi,
  * boundary and neutralising background; 3-D (all axes periodic) and 2-D
  * slab (x, y periodic, z free).  reg = 1 returns lim (psi - 1/|x|) at x = 0. */
 double orc_ewald3d(const double box[3], double alpha, const double x[3], int reg);
+/* The 3-D Ewald potential for the lattice spanned by the columns of H. */
+double orc_ewald3d_cell(const double H[9], double alpha, const double x[3], int reg);
 double orc_ewald2d(const double box[3], double alpha, const double x[3], int reg);
 /* phi_i = sum_j q_j psi(r_i - r_j), with psi_reg(0) for j = i. */
 void orc_ewald_potentials(const double box[3], int slab, double alpha, int n,
                           const double* pos, const double* q, double* phi);
+void orc_ewald_potentials_cell(const double H[9], double alpha, int n, const double* pos,
+                               const double* q, double* phi);
 
 #ifdef __cplusplus
 }

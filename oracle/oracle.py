@@ -67,7 +67,8 @@ class _Geom(ctypes.Structure):
                 ("a", ctypes.c_double), ("box", ctypes.c_double * 3),
                 ("periodic", ctypes.c_int * 3),
                 ("n", (ctypes.c_int * 3) * MAXL), ("lo", (ctypes.c_int * 3) * MAXL),
-                ("h", (ctypes.c_double * 3) * MAXL), ("omega", ctypes.c_double * 32)]
+                ("h", (ctypes.c_double * 3) * MAXL), ("omega", ctypes.c_double * 32),
+                ("tri", ctypes.c_int), ("H", ctypes.c_double * 9), ("Hinv", ctypes.c_double * 9)]
 
 
 _lib = None
@@ -117,11 +118,13 @@ def lib():
         L.orc_short_range_vjp_cells.restype = None
         L.orc_direct_coulomb.argtypes = [i, P, P, P, P]
         L.orc_direct_coulomb.restype = None
-        for name in ("orc_ewald3d", "orc_ewald2d"):
+        for name in ("orc_ewald3d", "orc_ewald2d", "orc_ewald3d_cell"):
             getattr(L, name).argtypes = [P, d, P, i]
             getattr(L, name).restype = d
         L.orc_ewald_potentials.argtypes = [P, i, d, i, P, P, P]
         L.orc_ewald_potentials.restype = None
+        L.orc_ewald_potentials_cell.argtypes = [P, d, i, P, P, P]
+        L.orc_ewald_potentials_cell.restype = None
         _lib = L
     return _lib
 
@@ -190,6 +193,34 @@ def ewald_potentials(box, pos, q, slab=False, alpha=None):
     return phi
 
 
+def cell_matrix(cell):
+    """H with the lattice vectors as columns, from cell = rows a, b, c."""
+    return np.ascontiguousarray(np.asarray(cell, dtype=np.float64).T)
+
+
+def ewald_alpha_cell(cell):
+    return math.sqrt(math.pi) / abs(np.linalg.det(np.asarray(cell, dtype=np.float64))) ** (1 / 3)
+
+
+def ewald_psi_cell(cell, x, alpha=None, reg=False):
+    """3-D Ewald potential of a unit charge and its images on the lattice
+    spanned by the rows of cell (tin-foil, neutralising background)."""
+    H = cell_matrix(cell)
+    if alpha is None:
+        alpha = ewald_alpha_cell(cell)
+    return lib().orc_ewald3d_cell(_ptr(H), float(alpha), _ptr(_f64(x)), int(reg))
+
+
+def ewald_potentials_cell(cell, pos, q, alpha=None):
+    H = cell_matrix(cell)
+    pos, q = _f64(pos), _f64(q)
+    if alpha is None:
+        alpha = ewald_alpha_cell(cell)
+    phi = np.zeros(len(q))
+    lib().orc_ewald_potentials_cell(_ptr(H), float(alpha), len(q), _ptr(pos), _ptr(q), _ptr(phi))
+    return phi
+
+
 def direct_coulomb(pos, q):
     """Exact all-pairs non-periodic Coulomb potentials and forces."""
     pos, q = _f64(pos), _f64(q)
@@ -203,15 +234,32 @@ def direct_coulomb(pos, q):
 # the MSM oracle
 # --------------------------------------------------------------------------
 class OracleMSM:
-    """Level-wise FP64 MSM for one orthorhombic box.
+    """Level-wise FP64 MSM for one orthorhombic box or triclinic cell.
 
     box: 3 lengths; periodic: 3 bools (all free, all periodic, or x,y periodic
     with z free); p: even B-spline order; h: requested level-1 spacing; a:
     level-zero cutoff; L: number of grid levels; M: half-width of omega'
     (default p).
+
+    cell: rows a, b, c of a triclinic cell (all axes periodic; box is then
+    ignored).  Positions are mapped to the unit cube, s = [a b c]^{-1} r, and
+    every grid lives there (Sec. MSM core algorithm, long-range part): N_l
+    points along each lattice vector by the periodic rule above with the
+    vector's length, basis functions of s, gradients taken back to r through
+    H^{-T}, stencil samples k_l(|H (n / N_l)|), the top level summed over the
+    lattice with the triclinic Ewald sum.  The cutoff must not exceed half
+    the cell's smallest width V / |face| (minimum image).
     """
 
-    def __init__(self, box, periodic, p, h, a, L, M=None):
+    def __init__(self, box, periodic, p, h, a, L, M=None, cell=None, ntop=None):
+        self.cell = None if cell is None else np.asarray(cell, dtype=np.float64).reshape(3, 3)
+        if self.cell is not None:
+            self.H = cell_matrix(self.cell)
+            self.Hinv = np.linalg.inv(self.H)
+            lengths = [float(np.linalg.norm(self.cell[k])) for k in range(3)]
+            widths = [1.0 / float(np.linalg.norm(self.Hinv[k])) for k in range(3)]
+            periodic = (True, True, True)
+            box = (1.0, 1.0, 1.0)
         self.box = [float(b) for b in box]
         self.periodic = [bool(x) for x in periodic]
         self.p, self.h, self.a, self.L = int(p), float(h), float(a), int(L)
@@ -221,16 +269,20 @@ class OracleMSM:
         assert npd in (0, 3) or self.periodic == [True, True, False], "unsupported periodicity"
         for k in range(3):
             if self.periodic[k]:
-                assert self.a <= self.box[k] / 2 + 1e-12, "cutoff exceeds half the box"
+                w = widths[k] if self.cell is not None else self.box[k]
+                assert self.a <= w / 2 + 1e-12, "cutoff exceeds half the box"
         self.omega_exact = C.omega_prime(self.p, self.M)
         self.omega = [float(w) for w in self.omega_exact]
-        self.levels = []  # per level: (n[3], lo[3], h[3])
+        self.levels = []  # per level: (n[3], lo[3], h[3]) (h: fractional in a cell)
         for l in range(1, self.L + 1):
             n, lo, hl = [], [], []
             for k in range(3):
                 if self.periodic[k]:
-                    ntop = max(1, int(math.floor(self.box[k] / (self.h * 2 ** (self.L - 1)) + 0.5)))
-                    nk = ntop * 2 ** (self.L - 1) // 2 ** (l - 1)
+                    edge = lengths[k] if self.cell is not None else self.box[k]
+                    nt = max(1, int(math.floor(edge / (self.h * 2 ** (self.L - 1)) + 0.5)))
+                    if ntop is not None:  # grid counts held fixed (cell derivatives)
+                        nt = int(ntop[k])
+                    nk = nt * 2 ** (self.L - 1) // 2 ** (l - 1)
                     n.append(nk)
                     lo.append(0)
                     hl.append(self.box[k] / nk)
@@ -252,6 +304,11 @@ class OracleMSM:
                 g.n[l][k], g.lo[l][k], g.h[l][k] = n[k], lo[k], hl[k]
         for j, w in enumerate(self.omega):
             g.omega[j] = w
+        g.tri = int(self.cell is not None)
+        if self.cell is not None:
+            for k in range(9):
+                g.H[k] = float(self.H.flat[k])
+                g.Hinv[k] = float(self.Hinv.flat[k])
         self._g = g
         self._gp = ctypes.pointer(g)
         self._stencils = {}
@@ -298,7 +355,10 @@ class OracleMSM:
         if level < self.L:
             W = []
             for k in range(3):
-                w = int(math.floor(2 ** level * self.a / hl[k])) + self.M
+                # |n_k| reach of the support |x| < 2^l a along grid axis k
+                reach = (2 ** level * self.a * n[k] * float(np.linalg.norm(self.Hinv[k]))
+                         if self.cell is not None else 2 ** level * self.a / hl[k])
+                w = int(math.floor(reach)) + self.M
                 if not self.periodic[k]:
                     w = min(w, n[k] - 1)
                 W.append(w)
@@ -317,9 +377,25 @@ class OracleMSM:
         if npd == 0:
             r = math.sqrt(x[0] ** 2 + x[1] ** 2 + x[2] ** 2)
             return kernel(L, L, a, p, r)
+        R = 2 ** (L - 1) * a
+        if self.cell is not None:
+            # x is Cartesian; images x + H j over the lattice
+            val = ewald_psi_cell(self.cell, x, reg=True)
+            s = self.Hinv @ np.asarray(x, dtype=np.float64)
+            nimg = [int(math.ceil(R * float(np.linalg.norm(self.Hinv[k])) + abs(s[k]))) + 1
+                    for k in range(3)]
+            for jz in range(-nimg[2], nimg[2] + 1):
+                for jy in range(-nimg[1], nimg[1] + 1):
+                    for jx in range(-nimg[0], nimg[0] + 1):
+                        d = np.asarray(x) + self.H @ np.array([jx, jy, jz], dtype=np.float64)
+                        r = float(np.sqrt(d @ d))
+                        if r == 0.0:
+                            val += gamma(p, 0.0) / R
+                        elif r < R:
+                            val -= 1.0 / r - gamma(p, r / R) / R
+            return val
         slab = npd == 2
         val = ewald_psi(self.box, x, slab=slab, reg=True)
-        R = 2 ** (L - 1) * a
         nimg = [int(math.ceil((R + abs(x[k])) / self.box[k])) + 1 if self.periodic[k] else 0
                 for k in range(3)]
         for jz in range(-nimg[2], nimg[2] + 1):
@@ -355,7 +431,10 @@ class OracleMSM:
                     key[k] %= n[k]
             key = tuple(key)
             if key not in cache:
-                cache[key] = self._G_top((key[0] * hl[0], key[1] * hl[1], key[2] * hl[2]))
+                u = (key[0] * hl[0], key[1] * hl[1], key[2] * hl[2])
+                if self.cell is not None:
+                    u = tuple(self.H @ np.asarray(u))
+                cache[key] = self._G_top(u)
             return cache[key]
 
         # table T over every offset d - k that occurs, then the plain sum
@@ -407,6 +486,8 @@ class OracleMSM:
         p = self.p
         pts = set()
         for r in np.atleast_2d(pos):
+            if self.cell is not None:
+                r = self.Hinv @ np.asarray(r, dtype=np.float64)
             idx = []
             for k in range(3):
                 x = r[k]
@@ -529,6 +610,26 @@ class OracleMSM:
             lib().orc_interpolate_vjp(self._gp, l, n, _ptr(pos), _ptr(q), _ptr(v), _ptr(psi),
                                       _ptr(psiD), _ptr(sq), _ptr(sr))
         return gq + sq, gr + sr
+
+    def cell_gradient(self, pos, q, eps=1e-5):
+        """dE/dH at fixed Cartesian positions (H: lattice vectors as columns),
+        by central differences of the energy with the grid counts held fixed:
+        the plain definition of the derivative, in FP64."""
+        assert self.cell is not None, "a triclinic oracle (cell=...) is needed"
+        ntop = [self.levels[self.L - 1][0][k] for k in range(3)]
+        scale = float(np.abs(self.H).max())
+        out = np.zeros((3, 3))
+        for r in range(3):
+            for c in range(3):
+                E = []
+                for sgn in (1.0, -1.0):
+                    Hp = self.H.copy()
+                    Hp[r, c] += sgn * eps * scale
+                    o = OracleMSM(None, None, self.p, self.h, self.a, self.L, self.M,
+                                  cell=Hp.T, ntop=ntop)
+                    E.append(o.compute(pos, q)["E"])
+                out[r, c] = (E[0] - E[1]) / (2 * eps * scale)
+        return out
 
     def sampled_backward(self, pos, q, gE, v, sel):
         """backward() for the listed particles only: the grid charges and
