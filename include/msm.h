@@ -80,6 +80,42 @@ msm_status msm_plan_create(msm_plan* out, const double box[3], unsigned periodic
                            double h, double cutoff_a, int levels, int precision, int max_n,
                            int quasi_degree_M);
 
+/*
+ * msm_plan_create_cell -- msm_plan_create for a triclinic cell (Sec. "MSM core
+ * algorithm", long-range part: positions are mapped to the unit cube,
+ * s = [a b c]^{-1} r, and the grids are set up there).
+ *   cell[9]         host, the lattice vectors a, b, c as consecutive rows
+ *                   (cell[0..2] = a, ...), any orientation, non-singular.
+ *   periodic_mask   must be 7 (all axes periodic; else MSM_ERR_UNSUPPORTED).
+ * Each grid has N_l points along each lattice vector, chosen from the
+ * vector's length as for a periodic box edge; stencils sample k_l at the
+ * Cartesian grid offsets H (n / N_l) and the top level sums k_L's tail over
+ * the lattice with a triclinic Ewald sum.  The cutoff must not exceed half
+ * the cell's smallest width V / |face| (minimum image, else
+ * MSM_ERR_CUTOFF_TOO_LARGE).  Positions may take any finite value (they are
+ * wrapped into the cell); forces and dE/dq are Cartesian.  All other
+ * arguments and every compute call are as for msm_plan_create; a diagonal
+ * cell gives the orthorhombic plan's results up to rounding.
+ */
+msm_status msm_plan_create_cell(msm_plan* out, const double cell[9], unsigned periodic_mask,
+                                int order, double h, double cutoff_a, int levels, int precision,
+                                int max_n, int quasi_degree_M);
+
+/*
+ * msm_plan_set_cell -- a new cell for a plan made by msm_plan_create_cell
+ * (a cell that changes between calls, as under constant pressure): the
+ * grids keep their point counts, so their spacings follow the cell, and the
+ * stencils and the top-level table are rebuilt from the new cell on the
+ * host and uploaded again (Sec. "MSM core algorithm": stencils computed from
+ * the current cell).  Synchronises the device; not for the hot path.  The
+ * cell list keeps at most its number of cells per axis (a thinner cell gets
+ * fewer).  MSM_ERR_INVALID_ARG for other plans; MSM_ERR_CUTOFF_TOO_LARGE if
+ * the new cell is too thin for the cutoff; MSM_ERR_GRID if a stencil outgrows
+ * the convolution's limits (create a new plan then).  On an error the plan's
+ * stencils are undefined.
+ */
+msm_status msm_plan_set_cell(msm_plan plan, const double cell[9]);
+
 /* Same as msm_plan_create but touches no GPU: only the host-side plan
  * (geometry, softener, omega', J, stencils) is built, for inspection with
  * msm_plan_describe / msm_plan_get_stencil.  Compute calls return

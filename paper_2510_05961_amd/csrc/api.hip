@@ -49,7 +49,28 @@ GridDev<T> grid_dev(const HostPlan& hp, int level) {
     d.inv_h[k] = (T)(1.0 / g.h[k]);
     d.hd[k] = g.h[k];
   }
+  d.tri = hp.tri;
+  for (int k = 0; k < 9; ++k) d.Hi[k] = hp.tri ? hp.Hinv[k] : 0.0;
   return d;
+}
+
+// Binning parameters: the cell list in the box, or in the unit cube of a
+// triclinic cell.
+template <typename T>
+BinParams<T> bin_params(const HostPlan& hp) {
+  BinParams<T> bp;
+  for (int k = 0; k < 3; ++k) {
+    bp.box[k] = (T)hp.box[k];
+    bp.cs[k] = (T)hp.cs[k];
+    bp.nc[k] = hp.nc[k];
+    bp.per[k] = hp.periodic[k];
+  }
+  bp.tri = hp.tri;
+  for (int k = 0; k < 9; ++k) {
+    bp.H[k] = hp.tri ? hp.H[k] : 0.0;
+    bp.Hi[k] = hp.tri ? hp.Hinv[k] : 0.0;
+  }
+  return bp;
 }
 
 size_t tsize(const HostPlan& hp) { return hp.precision == MSM_FP64 ? 8 : 4; }
@@ -202,11 +223,13 @@ msm_status prepare_work(const msm_plan P, const WorkBufs& w, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
 }
 
+// Uploads every level's stencil (and the k-samples of factored levels) in the
+// padded form the convolution reads; fails when a stencil exceeds the
+// convolution's LDS window.
 template <typename T>
-msm_status upload_plan(msm_plan P) {
+msm_status upload_stencils(msm_plan P) {
   HostPlan& hp = P->hp;
   msm_status st;
-  if (hipGetDevice(&P->device_id) != hipSuccess) return MSM_ERR_HIP;
   // an FP64 stencil [len2][len1][len0] as the convolution reads it: rows
   // padded with zeros to conv_row_stride(len0), kConvRowPad zero rows before
   // and after every plane, plus the [first, last] non-zero x range of every
@@ -257,6 +280,15 @@ msm_status upload_plan(msm_plan P) {
       if (conv_lds_bytes(cs, sizeof(T)) > 64 * 1024 || cs.lds_w > kConvMaxLW) return MSM_ERR_GRID;
     }
   }
+  return MSM_OK;
+}
+
+template <typename T>
+msm_status upload_plan(msm_plan P) {
+  HostPlan& hp = P->hp;
+  msm_status st;
+  if (hipGetDevice(&P->device_id) != hipSuccess) return MSM_ERR_HIP;
+  if ((st = upload_stencils<T>(P))) return st;
   T J[9] = {};
   for (int k = 0; k <= hp.p; ++k) J[k] = (T)hp.J[k];
   if ((st = hip_alloc(P, &P->Jd, sizeof(J)))) return st;
@@ -331,6 +363,8 @@ PairParams<T> pair_params(const HostPlan& hp) {
     pp.fr[k] = (T)(2.0 * dc / (a2k * a * a * a));
     pp.gr[k] = (T)(4.0 * d2c / (a2k * a * a * a * a * a));
   }
+  pp.tri = hp.tri;
+  for (int k = 0; k < 9; ++k) pp.H[k] = hp.tri ? (T)hp.H[k] : T(0);
   return pp;
 }
 
@@ -525,13 +559,7 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
 
   // a1 binning (cell counts, scans of cell starts and cluster offsets,
   // scatter), then Morton order inside cells and the 8-particle clusters
-  BinParams<T> bp;
-  for (int k = 0; k < 3; ++k) {
-    bp.box[k] = (T)hp.box[k];
-    bp.cs[k] = (T)hp.cs[k];
-    bp.nc[k] = hp.nc[k];
-    bp.per[k] = hp.periodic[k];
-  }
+  const BinParams<T> bp = bin_params<T>(hp);
   int ev = pf.begin("bin", s);
   launch_binning<T>(n, pos, q, bp, P->ncell, P->w->cell_of, P->w->rank, P->w->counts,
                     (vec4_t<T>*)P->w->wrapped, start, P->w->cl_start, sorted, perm, P->flag,
@@ -602,16 +630,10 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
   T* gq_sr = (T*)P->w->phi0;
   T* gr_sr = (T*)P->w->F0;
   int ev = pf.begin("bwd_layout", s);
-  launch_gather_v<T>(n, perm, gF, v, s);
+  launch_gather_v<T>(n, perm, gF, grid_dev<T>(hp, 1), v, s);
   {
     // cluster layout of the saved (already Morton-ordered) cell list
-    BinParams<T> bp;
-    for (int k = 0; k < 3; ++k) {
-      bp.box[k] = (T)hp.box[k];
-      bp.cs[k] = (T)hp.cs[k];
-      bp.nc[k] = hp.nc[k];
-      bp.per[k] = hp.periodic[k];
-    }
+    const BinParams<T> bp = bin_params<T>(hp);
     launch_cluster_layout<T>(0, 1, P->ncell, start, P->w->cl_start, bp, nullptr,
                              const_cast<vec4_t<T>*>(sorted), const_cast<int*>(perm),
                              (vec4_t<T>*)P->w->cpos, (vec4_t<T>*)P->w->cbox, P->w->cinfo, nullptr, s);
@@ -659,14 +681,15 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
 }
 
 msm_status create_common(msm_plan* out, const double box[3], unsigned mask, int order, double h,
-                         double a, int levels, int precision, int max_n, int M, bool device) {
+                         double a, int levels, int precision, int max_n, int M, bool device,
+                         const double* cell = nullptr) {
   if (!out) return MSM_ERR_INVALID_ARG;
   *out = nullptr;
   msm_plan P = new (std::nothrow) msm_plan_s;
   if (!P) return MSM_ERR_OOM;
   int rc;
   try {
-    rc = build_host_plan(P->hp, box, mask, order, h, a, levels, precision, max_n, M);
+    rc = build_host_plan(P->hp, box, mask, order, h, a, levels, precision, max_n, M, cell);
   } catch (...) {
     rc = MSM_ERR_OOM;
   }
@@ -697,7 +720,57 @@ msm_status create_common(msm_plan* out, const double box[3], unsigned mask, int 
   return MSM_OK;
 }
 
-// Working memory of msm_energy_forces_noalloc: one array per GPU, held from
+// Frees one device buffer of the plan (and forgets it).
+void free_plan_buffer(msm_plan P, void* ptr) {
+  if (!ptr) return;
+  for (size_t k = 0; k < P->allocs.size(); ++k)
+    if (P->allocs[k] == ptr) {
+      (void)hipFree(ptr);
+      P->allocs.erase(P->allocs.begin() + k);
+      return;
+    }
+}
+
+// A new cell for a triclinic plan: the grids keep their point counts (so the
+// spacings follow the cell) and the cell list its size (fewer cells per axis
+// if the new cell is thinner); stencils and the top-level table are rebuilt
+// from the new cell on the host and uploaded again.
+template <typename T>
+msm_status set_cell(msm_plan P, const double cell[9]) {
+  const HostPlan& old = P->hp;
+  int ntop[3];
+  for (int k = 0; k < 3; ++k) ntop[k] = old.lev[old.L - 1].n[k];
+  HostPlan hp;
+  int rc;
+  try {
+    rc = build_host_plan(hp, nullptr, 7, old.p, old.h_req, old.a, old.L, old.precision, old.max_n,
+                         old.M, cell, ntop);
+  } catch (...) {
+    rc = MSM_ERR_OOM;
+  }
+  if (rc != MSM_OK) return (msm_status)rc;
+  for (int k = 0; k < 3; ++k) {  // the cell list never grows past its buffers
+    if (hp.nc[k] > old.nc[k]) hp.nc[k] = old.nc[k];
+    hp.cs[k] = hp.box[k] / hp.nc[k];
+  }
+  for (int l = 1; l <= hp.L; ++l) hp.lev[l - 1].factored = old.lev[l - 1].factored;
+  if (hipDeviceSynchronize() != hipSuccess) return MSM_ERR_HIP;
+  for (int l = 0; l < old.L; ++l) {
+    free_plan_buffer(P, P->K64[l]);
+    free_plan_buffer(P, P->rowext64[l]);
+    free_plan_buffer(P, P->S[l]);
+    free_plan_buffer(P, P->srowext[l]);
+    P->K64[l] = nullptr;
+    P->rowext64[l] = nullptr;
+    P->S[l] = nullptr;
+    P->srowext[l] = nullptr;
+  }
+  P->hp = hp;
+  P->ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
+  return upload_stencils<T>(P);
+}
+
+// Working memory of msm_energy_forces_noalloc: one array per GPU, held from// Working memory of msm_energy_forces_noalloc: one array per GPU, held from
 // the library's load until the process ends.  Host code never uses the
 // array's name as an address: the device address comes from
 // hipGetSymbolAddress, once per device, with that device current.
@@ -752,6 +825,20 @@ msm_status msm_plan_create(msm_plan* out, const double box[3], unsigned periodic
                            int quasi_degree_M) {
   return create_common(out, box, periodic_mask, order, h, cutoff_a, levels, precision, max_n,
                        quasi_degree_M, true);
+}
+
+msm_status msm_plan_create_cell(msm_plan* out, const double cell[9], unsigned periodic_mask,
+                                int order, double h, double cutoff_a, int levels, int precision,
+                                int max_n, int quasi_degree_M) {
+  if (!cell) return MSM_ERR_INVALID_ARG;
+  return create_common(out, nullptr, periodic_mask, order, h, cutoff_a, levels, precision, max_n,
+                       quasi_degree_M, true, cell);
+}
+
+msm_status msm_plan_set_cell(msm_plan plan, const double cell[9]) {
+  if (!plan || plan->batch || !cell || !plan->hp.tri) return MSM_ERR_INVALID_ARG;
+  if (!plan->device) return MSM_ERR_NO_DEVICE;
+  return plan->hp.precision == MSM_FP64 ? set_cell<double>(plan, cell) : set_cell<float>(plan, cell);
 }
 
 msm_status msm_plan_create_host(msm_plan* out, const double box[3], unsigned periodic_mask,

@@ -23,9 +23,11 @@
 namespace msm {
 
 // v in sorted order (vec4 with w = 0) from the caller's [n][3] cotangent.
+// On a triclinic grid the cotangent is taken to the grid frame, H^{-1} v, so
+// that v . grad_r = (H^{-1} v) . grad_s.
 template <typename T>
 __global__ void k_gather_v(int n, const int* __restrict__ perm, const T* __restrict__ gF,
-                           vec4_t<T>* __restrict__ v) {
+                           GridDev<T> g, vec4_t<T>* __restrict__ v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int o = perm[i];
@@ -34,6 +36,12 @@ __global__ void k_gather_v(int n, const int* __restrict__ perm, const T* __restr
   t.y = gF[3 * o + 1];
   t.z = gF[3 * o + 2];
   t.w = T(0);
+  if (g.tri) {
+    const T a = t.x, b = t.y, c = t.z;
+    t.x = (T)g.Hi[0] * a + (T)g.Hi[1] * b + (T)g.Hi[2] * c;
+    t.y = (T)g.Hi[3] * a + (T)g.Hi[4] * b + (T)g.Hi[5] * c;
+    t.z = (T)g.Hi[6] * a + (T)g.Hi[7] * b + (T)g.Hi[8] * c;
+  }
   v[i] = t;
 }
 
@@ -80,7 +88,8 @@ __global__ void __launch_bounds__(256)
     const int i = brick_particle(runs, nruns, jp);
     const vec4_t<T> pi = sorted[i];
     const vec4_t<T> vi = v[i];
-    const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    grid_frame(g, xs);
     double w[3][P], dw[3][P];
     int m0[3];
 #pragma unroll
@@ -165,7 +174,8 @@ __global__ void __launch_bounds__(256)
   if (i >= n) return;
   const vec4_t<T> pi = sorted[i];
   const vec4_t<T> vi = v[i];
-  const T xs[3] = {pi.x, pi.y, pi.z};
+  T xs[3] = {pi.x, pi.y, pi.z};
+  grid_frame(g, xs);
   T w[3][P], dw[3][P], d2w[3][P];
   int idx[3][P];
 #pragma unroll
@@ -247,9 +257,11 @@ __global__ void __launch_bounds__(256)
   (void)M000;
   const T vx = vi.x, vy = vi.y, vz = vi.z, qi = pi.w;
   const T sq = N000 + vx * M100 + vy * M010 + vz * M001;
-  const T sx = N100 + vx * M200 + vy * M110 + vz * M101;
-  const T sy = N010 + vx * M110 + vy * M020 + vz * M011;
-  const T sz = N001 + vx * M101 + vy * M011 + vz * M002;
+  T sx = N100 + vx * M200 + vy * M110 + vz * M101;
+  T sy = N010 + vx * M110 + vy * M020 + vz * M011;
+  T sz = N001 + vx * M101 + vy * M011 + vz * M002;
+  // (triclinic: v is in the grid frame; the gradient goes back through H^{-T})
+  grid_to_cartesian(g, sx, sy, sz);
   const T ge = gE ? (T)(*gE) : T(0);
   const int o = perm[i];
   if (grad_q) grad_q[o] = ge * save_phi[i] + gq_sr[i] - sq;
@@ -280,9 +292,10 @@ __global__ void k_grad_energy_only(int n, const int* __restrict__ perm,
 
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_gather_v(int n, const int* perm, const T* gF, vec4_t<T>* v, hipStream_t s) {
+void launch_gather_v(int n, const int* perm, const T* gF, const GridDev<T>& g, vec4_t<T>* v,
+                     hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gather_v<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, gF, v);
+  hipLaunchKernelGGL(k_gather_v<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, gF, g, v);
 }
 
 template <typename T>
@@ -324,7 +337,8 @@ void launch_grad_energy_only(int n, const int* perm, const T* save_phi, const T*
 }
 
 #define MSM_INST_BACKWARD(T)                                                                      \
-  template void launch_gather_v<T>(int, const int*, const T*, vec4_t<T>*, hipStream_t);           \
+  template void launch_gather_v<T>(int, const int*, const T*, const GridDev<T>&, vec4_t<T>*,      \
+                                   hipStream_t);                                                   \
   template void launch_anterp_dipole<T>(int, int, int, const int*, const CellGrid&,                \
                                         const vec4_t<T>*, const vec4_t<T>*, const GridDev<T>&, T*,  \
                                         hipStream_t);                                             \

@@ -594,6 +594,8 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
     pp.nc[k] = 1;
     pp.cs[k] = 0;
   }
+  pp.tri = 0;
+  for (int k = 0; k < 9; ++k) pp.H[k] = 0;
   const T* boxes = (const T*)B.d_box;
   int ev = P->prof.begin("batch_pair", s);
   switch (p) {

@@ -25,6 +25,22 @@ __device__ inline int neighbour_shift(int c, int o, int nc, int per, int& sh) {
   return (v >= 0 && v < nc) ? v : -1;
 }
 
+// Cartesian image shift of a neighbour cell reached across sh periods:
+// sh o box, or H sh in a triclinic cell.
+template <typename T>
+__device__ inline void image_shift(const PairParams<T>& pp, int shx, int shy, int shz, T& sx,
+                                   T& sy, T& sz) {
+  if (pp.tri) {
+    sx = pp.H[0] * (T)shx + pp.H[1] * (T)shy + pp.H[2] * (T)shz;
+    sy = pp.H[3] * (T)shx + pp.H[4] * (T)shy + pp.H[5] * (T)shz;
+    sz = pp.H[6] * (T)shx + pp.H[7] * (T)shy + pp.H[8] * (T)shz;
+  } else {
+    sx = (T)shx * pp.box[0];
+    sy = (T)shy * pp.box[1];
+    sz = (T)shz * pp.box[2];
+  }
+}
+
 template <typename T>
 __device__ inline T box_gap2(T jlo_x, T jlo_y, T jlo_z, T jhi_x, T jhi_y, T jhi_z, T ilo_x,
                              T ilo_y, T ilo_z, T ihi_x, T ihi_y, T ihi_z) {

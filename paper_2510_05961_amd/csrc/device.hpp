@@ -36,7 +36,33 @@ struct GridDev {
   T h[3];      // spacing
   T inv_h[3];
   double hd[3];  // spacing in FP64 (grid coordinates of particles)
+  // triclinic cell: particle coordinates are fractional, s = H^{-1} r, and
+  // a gradient in s is taken back to r through H^{-T} (Hi = H^{-1}, row-major)
+  int tri;
+  double Hi[9];
 };
+
+// Grid-frame coordinates of a particle at Cartesian x (in place): x itself,
+// or on a triclinic grid its fractional coordinates s = H^{-1} x, formed in
+// FP64.
+template <typename T, typename V>
+__device__ inline void grid_frame(const GridDev<T>& g, V* x) {
+  if (!g.tri) return;
+  const double a = (double)x[0], b = (double)x[1], c = (double)x[2];
+  x[0] = (V)(g.Hi[0] * a + g.Hi[1] * b + g.Hi[2] * c);
+  x[1] = (V)(g.Hi[3] * a + g.Hi[4] * b + g.Hi[5] * c);
+  x[2] = (V)(g.Hi[6] * a + g.Hi[7] * b + g.Hi[8] * c);
+}
+
+// grad_r = H^{-T} grad_s on a triclinic grid (in place; no-op otherwise).
+template <typename T, typename V>
+__device__ inline void grid_to_cartesian(const GridDev<T>& g, V& x, V& y, V& z) {
+  if (!g.tri) return;
+  const V a = x, b = y, c = z;
+  x = (V)g.Hi[0] * a + (V)g.Hi[3] * b + (V)g.Hi[6] * c;
+  y = (V)g.Hi[1] * a + (V)g.Hi[4] * b + (V)g.Hi[7] * c;
+  z = (V)g.Hi[2] * a + (V)g.Hi[5] * b + (V)g.Hi[8] * c;
+}
 
 // Fractional grid coordinate of x on an axis of spacing h: returns the
 // integer part (floor of x/h) and f in [0,1), with the rounding error of the

@@ -11,6 +11,11 @@ struct BinParams {
   T cs[3];     // cell edge
   int nc[3];   // cells per axis
   int per[3];
+  // triclinic cell: cells live in the unit cube of s = H^{-1} r (box 1);
+  // positions are wrapped by whole lattice vectors and stay Cartesian
+  // (row-major matrices, lattice vectors as the columns of H)
+  int tri;
+  double H[9], Hi[9];
 };
 
 template <typename T>
@@ -27,6 +32,11 @@ struct PairParams {
   // the same in r^2: gamma(r/a)/a = sum er[k] r^2k, 2 gamma'(t)/a^3 =
   // sum fr[k] r^2k, 4 gamma''(t)/a^5 = sum gr[k] r^2k
   T er[8], fr[8], gr[8];
+  // triclinic cell: cells in fractional coordinates, the image shift of a
+  // neighbour cell is H (shx, shy, shz) (H row-major, lattice vectors as
+  // columns)
+  int tri;
+  T H[9];
 };
 
 // One stencil convolution e_o = sum_d K_d q_{o+shift-d} (a5, a6).
@@ -183,8 +193,10 @@ template <typename T>
 void launch_cast(const double* src, T* dst, long long count, hipStream_t s);
 
 // backward (vector-Jacobian product)
+// (g.tri: the cotangent in the grid frame, H^{-1} v)
 template <typename T>
-void launch_gather_v(int n, const int* perm, const T* gF, vec4_t<T>* v, hipStream_t s);
+void launch_gather_v(int n, const int* perm, const T* gF, const GridDev<T>& g, vec4_t<T>* v,
+                     hipStream_t s);
 template <typename T>
 void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4* cinfo,
                         const int* perm, const T* gF, const vec4_t<T>* cpos, vec4_t<T>* cv,

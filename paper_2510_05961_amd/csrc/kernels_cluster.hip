@@ -101,7 +101,12 @@ __global__ void __launch_bounds__(kPrepThreads)
   const int cz = cell / (bp.nc[0] * bp.nc[1]);
   const T lo3[3] = {(T)cx * bp.cs[0], (T)cy * bp.cs[1], (T)cz * bp.cs[2]};
   auto morton = [&](const vec4_t<T>& v) {
-    const T x[3] = {v.x, v.y, v.z};
+    T x[3] = {v.x, v.y, v.z};
+    if (bp.tri) {  // cells of a triclinic cell are in fractional coordinates
+      const double a = v.x, b = v.y, c = v.z;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) x[d] = (T)(bp.Hi[3 * d] * a + bp.Hi[3 * d + 1] * b + bp.Hi[3 * d + 2] * c);
+    }
     unsigned m = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -314,22 +319,22 @@ __device__ inline void for_each_group_block(const PairParams<T>& pp, const int* 
     int shz;
     const int nz = neighbour_shift(cz, oz, pp.nc[2], pp.per[2], shz);
     if (nz < 0) continue;
-    const T sz = (T)shz * pp.box[2];
     for (int oy = -1; oy <= 1; ++oy) {
       int shy;
       const int ny = neighbour_shift(cy, oy, pp.nc[1], pp.per[1], shy);
       if (ny < 0) continue;
-      const T sy = (T)shy * pp.box[1];
       for (int ox = -1; ox <= 1; ++ox) {
         int shx;
         const int nx = neighbour_shift(cx, ox, pp.nc[0], pp.per[0], shx);
         if (nx < 0) continue;
-        const T sx = (T)shx * pp.box[0];
+        T sx, sy, sz;
+        image_shift(pp, shx, shy, shz, sx, sy, sz);
         // i-box moved by minus the shift of the j image
         const T ilx = blo.x - sx, ily = blo.y - sy, ilz = blo.z - sz;
         const T ihx = bhi.x - sx, ihy = bhi.y - sy, ihz = bhi.z - sz;
-        // whole-cell test with a margin for the rounding of the binning
-        {
+        // whole-cell test with a margin for the rounding of the binning (the
+        // cells of a triclinic cell are not boxes: skipped there)
+        if (!pp.tri) {
           const T mx = pp.cs[0] * T(1e-3), my = pp.cs[1] * T(1e-3), mz = pp.cs[2] * T(1e-3);
           const T g2 = box_gap2<T>((T)nx * pp.cs[0] - mx, (T)ny * pp.cs[1] - my,
                                    (T)nz * pp.cs[2] - mz, (T)(nx + 1) * pp.cs[0] + mx,
@@ -408,21 +413,20 @@ __device__ inline void for_each_j_culled(const PairParams<T>& pp, const int* cl_
     int shz;
     const int nz = neighbour_shift(cz, oz, pp.nc[2], pp.per[2], shz);
     if (nz < 0) continue;
-    const T sz = (T)shz * pp.box[2];
     for (int oy = -1; oy <= 1; ++oy) {
       int shy;
       const int ny = neighbour_shift(cy, oy, pp.nc[1], pp.per[1], shy);
       if (ny < 0) continue;
-      const T sy = (T)shy * pp.box[1];
       for (int ox = -1; ox <= 1; ++ox) {
         int shx;
         const int nx = neighbour_shift(cx, ox, pp.nc[0], pp.per[0], shx);
         if (nx < 0) continue;
-        const T sx = (T)shx * pp.box[0];
+        T sx, sy, sz;
+        image_shift(pp, shx, shy, shz, sx, sy, sz);
         // i-box moved by minus the shift of the j image
         const T ilx = blo.x - sx, ily = blo.y - sy, ilz = blo.z - sz;
         const T ihx = bhi.x - sx, ihy = bhi.y - sy, ihz = bhi.z - sz;
-        {  // whole-cell test with a margin for the rounding of the binning
+        if (!pp.tri) {  // whole-cell test with a margin for the rounding of the binning
           const T mx = pp.cs[0] * T(1e-3), my = pp.cs[1] * T(1e-3), mz = pp.cs[2] * T(1e-3);
           const T g2 = box_gap2<T>((T)nx * pp.cs[0] - mx, (T)ny * pp.cs[1] - my,
                                    (T)nz * pp.cs[2] - mz, (T)(nx + 1) * pp.cs[0] + mx,

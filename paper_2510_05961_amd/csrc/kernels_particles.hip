@@ -29,14 +29,49 @@ __global__ void k_bin_count(int n, const T* __restrict__ pos, const T* __restric
     bad |= kFlagNonfinite;
     qi = T(0);
   }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (!isfinite(x[k])) {
+      bad |= kFlagNonfinite;
+      x[k] = T(0);
+    }
+  if (bp.tri) {
+    // the cell from the fractional coordinates s = H^{-1} r (FP64); the
+    // position is wrapped by the whole lattice vectors floor(s) and stays
+    // Cartesian (unchanged inside the cell)
+    const double r[3] = {(double)x[0], (double)x[1], (double)x[2]};
+    double sf[3], nw[3];
+    int ct[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      sf[k] = bp.Hi[3 * k] * r[0] + bp.Hi[3 * k + 1] * r[1] + bp.Hi[3 * k + 2] * r[2];
+      nw[k] = floor(sf[k]);
+      const int ci = (int)((sf[k] - nw[k]) * (double)bp.nc[k]);
+      ct[k] = ci < 0 ? 0 : (ci >= bp.nc[k] ? bp.nc[k] - 1 : ci);
+    }
+    vec4_t<T> w;
+    if (nw[0] != 0.0 || nw[1] != 0.0 || nw[2] != 0.0) {
+      w.x = (T)(r[0] - (bp.H[0] * nw[0] + bp.H[1] * nw[1] + bp.H[2] * nw[2]));
+      w.y = (T)(r[1] - (bp.H[3] * nw[0] + bp.H[4] * nw[1] + bp.H[5] * nw[2]));
+      w.z = (T)(r[2] - (bp.H[6] * nw[0] + bp.H[7] * nw[1] + bp.H[8] * nw[2]));
+    } else {
+      w.x = x[0];
+      w.y = x[1];
+      w.z = x[2];
+    }
+    w.w = qi;
+    if (bad) atomicOr(flag, bad);
+    const int cell = (ct[2] * bp.nc[1] + ct[1]) * bp.nc[0] + ct[0];
+    const int slot = cell * kCountCopies + (i & (kCountCopies - 1));
+    cell_of[i] = slot;
+    rank[i] = atomicAdd(&counts[slot], 1);
+    wrapped[i] = w;
+    return;
+  }
   int c[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     T v = x[k];
-    if (!isfinite(v)) {
-      bad |= kFlagNonfinite;
-      v = T(0);
-    }
     if (bp.per[k]) {
       v = v - bp.box[k] * floor(v / bp.box[k]);
       if (!(v >= T(0) && v < bp.box[k])) v = T(0);
@@ -270,7 +305,8 @@ __global__ void __launch_bounds__(256)
   }
   for (int jp = threadIdx.x; jp < count; jp += blockDim.x) {
     const vec4_t<T> pi = sorted[brick_particle(runs, nruns, jp)];
-    const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    grid_frame(g, xs);
     double w[3][P];
     int m0[3];
 #pragma unroll
@@ -355,7 +391,8 @@ __global__ void __launch_bounds__(256)
   double ep = 0.0;
   if (i < n) {
     const vec4_t<T> pi = sorted[i];
-    const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    grid_frame(g, xs);
     // weights and sums in FP64 (the energy needs the grid self-interaction
     // below FP32 rounding); outputs are rounded to T at the end
     double w[3][P], dw[3][P];
@@ -403,6 +440,7 @@ __global__ void __launch_bounds__(256)
         gz += sv * w[1][b] * dw[2][c];
       }
     }
+    grid_to_cartesian(g, gx, gy, gz);
     const double qd = (double)pi.w;
     const T qi = pi.w;
     const double phid = phi0[i] + v - qd * self_const;
@@ -580,7 +618,8 @@ __global__ void __launch_bounds__(256)
   for (int j = threadIdx.x; j < count; j += blockDim.x) {
     int r;
     const vec4_t<T> pi = sorted[particle(j, r)];
-    const double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
+    grid_frame(g, xs);
     double w[3][P];
     bool in[3][P];
     int i0[3];  // tile-local index of support point 0 per axis

@@ -150,13 +150,49 @@ static void conv_axis(const std::vector<double>& in, const int nin[3], int axis,
       }
 }
 
+static void inverse3(const double A[9], double B[9]) {
+  const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                     A[2] * (A[3] * A[7] - A[4] * A[6]);
+  B[0] = (A[4] * A[8] - A[5] * A[7]) / det;
+  B[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+  B[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+  B[3] = (A[5] * A[6] - A[3] * A[8]) / det;
+  B[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+  B[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+  B[6] = (A[3] * A[7] - A[4] * A[6]) / det;
+  B[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+  B[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+}
+
+// Distance of the grid offset d: |A d| for a grid whose steps are the columns
+// of A, else |h o d|.
+static double offset_length(const double* A, const double h[3], double dx, double dy, double dz) {
+  if (!A) {
+    const double x = dx * h[0], y = dy * h[1], z = dz * h[2];
+    return std::sqrt(x * x + y * y + z * z);
+  }
+  double v[3];
+  for (int k = 0; k < 3; ++k) v[k] = A[3 * k] * dx + A[3 * k + 1] * dy + A[3 * k + 2] * dz;
+  return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+}
+
+// Largest |d_k| with a grid offset of length below r: r / h_k, or r times the
+// length of row k of A^{-1} (the component of A^{-1} x is at most that
+// row's length times |x|).
+static double offset_reach(const double* A, const double h[3], int k, double r) {
+  if (!A) return r / h[k];
+  double B[9];
+  inverse3(A, B);
+  return r * std::sqrt(B[3 * k] * B[3 * k] + B[3 * k + 1] * B[3 * k + 1] + B[3 * k + 2] * B[3 * k + 2]);
+}
+
 // Unfolded K^1 on |d_k| <= W_k = R_k + M, R_k = ceil(2a/h_k) - 1 (k_1 vanishes
-// for r >= 2a).
+// for r >= 2a; on a triclinic grid the reach of 2a along each grid axis).
 void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::vector<double>& K,
-                    const double* gcoef) {
+                    const double* gcoef, const double* A) {
   int R[3], ns[3];
   for (int k = 0; k < 3; ++k) {
-    R[k] = (int)std::ceil(2.0 * a / h[k] - 1e-12) - 1;
+    R[k] = (int)std::ceil(offset_reach(A, h, k, 2.0 * a) - 1e-12) - 1;
     if (R[k] < 0) R[k] = 0;
     W[k] = R[k] + M;
     ns[k] = 2 * (R[k] + 2 * M) + 1;  // samples padded by M for the free-axis passes
@@ -165,9 +201,7 @@ void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::ve
   for (int z = 0; z < ns[2]; ++z)
     for (int y = 0; y < ns[1]; ++y)
       for (int x = 0; x < ns[0]; ++x) {
-        double dx = (x - R[0] - 2 * M) * h[0], dy = (y - R[1] - 2 * M) * h[1],
-               dz = (z - R[2] - 2 * M) * h[2];
-        double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+        const double r = offset_length(A, h, x - R[0] - 2 * M, y - R[1] - 2 * M, z - R[2] - 2 * M);
         s[((size_t)z * ns[1] + y) * ns[0] + x] = split_kernel(gcoef, p, 1, 2, a, r);
       }
   std::vector<double> om = quasi_sequence(p, M), t1, t2;
@@ -257,11 +291,78 @@ static double ewald2d(const double box[3], const double x[3]) {
   return real + M_PI / A * rec + k0;
 }
 
+// The 3-D sum for the lattice {H n}: real space over the lattice vectors,
+// reciprocal space over k = 2 pi H^{-T} m, V = |det H| (tin-foil boundary,
+// neutralising background; alpha balances the two sums).
+static double ewald3d_cell(const double H[9], const double Hinv[9], const double x[3]) {
+  const double det = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                     H[2] * (H[3] * H[7] - H[4] * H[6]);
+  const double V = std::fabs(det);
+  const double alpha = 1.25 * std::sqrt(M_PI) / std::cbrt(V);
+  const double rc = 6.7 / alpha, kc = 2.0 * alpha * 6.7;  // erfc(6.7) < 4e-21
+  int nr[3], nk[3];
+  for (int k = 0; k < 3; ++k) {
+    const double* b = Hinv + 3 * k;
+    const double bk = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    const double sk = b[0] * x[0] + b[1] * x[1] + b[2] * x[2];
+    nr[k] = (int)std::ceil(rc * bk + std::fabs(sk)) + 1;
+    const double ak = std::sqrt(H[k] * H[k] + H[3 + k] * H[3 + k] + H[6 + k] * H[6 + k]);
+    nk[k] = (int)std::ceil(kc * ak / (2.0 * M_PI)) + 1;
+  }
+  double real = 0.0;
+  for (int i = -nr[0]; i <= nr[0]; ++i)
+    for (int j = -nr[1]; j <= nr[1]; ++j)
+      for (int k = -nr[2]; k <= nr[2]; ++k) {
+        double d[3];
+        for (int c = 0; c < 3; ++c) d[c] = x[c] + H[3 * c] * i + H[3 * c + 1] * j + H[3 * c + 2] * k;
+        const double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (r == 0.0) {
+          real -= 2.0 * alpha / std::sqrt(M_PI);
+          continue;
+        }
+        if (r < rc) real += std::erfc(alpha * r) / r;
+      }
+  double rec = 0.0;
+  for (int i = -nk[0]; i <= nk[0]; ++i)
+    for (int j = -nk[1]; j <= nk[1]; ++j)
+      for (int k = -nk[2]; k <= nk[2]; ++k) {
+        if (i == 0 && j == 0 && k == 0) continue;
+        double g[3];
+        for (int c = 0; c < 3; ++c) g[c] = 2.0 * M_PI * (Hinv[c] * i + Hinv[3 + c] * j + Hinv[6 + c] * k);
+        const double k2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        if (k2 > kc * kc) continue;
+        rec += std::exp(-k2 / (4.0 * alpha * alpha)) * std::cos(g[0] * x[0] + g[1] * x[1] + g[2] * x[2]) / k2;
+      }
+  return real + 4.0 * M_PI / V * rec - M_PI / (alpha * alpha * V);
+}
+
 // Top-level kernel summed over periodic images: G(x) = psi(x) - sum_j s(|x+j|)
 // with s(r) = 1/r - gamma(r/R)/R for r < R (zero beyond), R = 2^(L-1) a, i.e.
 // the periodic sum of k_L(r) = gamma(r/R)/R with the 1/r tail Ewald-summed.
 static double periodic_top_G(const HostPlan& P, const double x[3]) {
   const double R = std::ldexp(P.a, P.L - 1);
+  if (P.tri) {  // x Cartesian; images x + H j
+    double val = ewald3d_cell(P.H, P.Hinv, x);
+    int ni[3];
+    for (int k = 0; k < 3; ++k) {
+      const double* b = P.Hinv + 3 * k;
+      const double bk = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      ni[k] = (int)std::ceil(R * bk + std::fabs(b[0] * x[0] + b[1] * x[1] + b[2] * x[2])) + 1;
+    }
+    for (int i = -ni[0]; i <= ni[0]; ++i)
+      for (int j = -ni[1]; j <= ni[1]; ++j)
+        for (int k = -ni[2]; k <= ni[2]; ++k) {
+          double d[3];
+          for (int c = 0; c < 3; ++c)
+            d[c] = x[c] + P.H[3 * c] * i + P.H[3 * c + 1] * j + P.H[3 * c + 2] * k;
+          const double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+          if (r == 0.0)
+            val += P.gamma0 / R;
+          else if (r < R)
+            val -= 1.0 / r - gamma_t(P.gcoef, P.p, r / R) / R;
+        }
+    return val;
+  }
   bool slab = !P.periodic[2];
   double val = slab ? ewald2d(P.box, x) : ewald3d(P.box, x);
   int ni[3];
@@ -303,13 +404,41 @@ void free_top_kernel(int p, int M, double a, int L, const double hL[3], const in
   conv_axis(t2, n2, 2, false, omega, K, n3);
 }
 
-int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, int order, double h,
-                    double a, int levels, int precision, int max_n, int M) {
-  if (!box || !(h > 0) || !(a > 0) || levels < 1 || levels > kMaxLevels || max_n < 0)
+int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask, int order,
+                    double h, double a, int levels, int precision, int max_n, int M,
+                    const double* cell, const int* ntop_fixed) {
+  if ((!box_in && !cell) || !(h > 0) || !(a > 0) || levels < 1 || levels > kMaxLevels ||
+      max_n < 0)
     return MSM_ERR_INVALID_ARG;
   if (precision != MSM_FP32 && precision != MSM_FP64) return MSM_ERR_INVALID_ARG;
-  for (int k = 0; k < 3; ++k)
-    if (!(box[k] > 0) || !std::isfinite(box[k])) return MSM_ERR_INVALID_ARG;
+  // edges: the box lengths, or the lattice vector lengths of a cell (whose
+  // grids live in the unit cube, box (1, 1, 1))
+  double box[3], edge[3], width[3];
+  P.tri = cell != nullptr;
+  if (P.tri) {
+    if (periodic_mask != 7) return MSM_ERR_UNSUPPORTED;
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(cell[k])) return MSM_ERR_INVALID_ARG;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) P.H[3 * r + c] = cell[3 * c + r];  // columns a, b, c
+    const double det = P.H[0] * (P.H[4] * P.H[8] - P.H[5] * P.H[7]) -
+                       P.H[1] * (P.H[3] * P.H[8] - P.H[5] * P.H[6]) +
+                       P.H[2] * (P.H[3] * P.H[7] - P.H[4] * P.H[6]);
+    if (!(std::fabs(det) > 0)) return MSM_ERR_INVALID_ARG;
+    inverse3(P.H, P.Hinv);
+    for (int k = 0; k < 3; ++k) {
+      box[k] = 1.0;
+      edge[k] = std::sqrt(cell[3 * k] * cell[3 * k] + cell[3 * k + 1] * cell[3 * k + 1] +
+                          cell[3 * k + 2] * cell[3 * k + 2]);
+      const double* b = P.Hinv + 3 * k;
+      width[k] = 1.0 / std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    }
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      if (!(box_in[k] > 0) || !std::isfinite(box_in[k])) return MSM_ERR_INVALID_ARG;
+      box[k] = edge[k] = width[k] = box_in[k];
+    }
+  }
   if (order != 4 && order != 6 && order != 8) return MSM_ERR_UNSUPPORTED;
   if (periodic_mask != 0 && periodic_mask != 7 && periodic_mask != 3) return MSM_ERR_UNSUPPORTED;
   if (M < 0) M = order;
@@ -317,7 +446,9 @@ int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, in
   for (int k = 0; k < 3; ++k) {
     P.box[k] = box[k];
     P.periodic[k] = (periodic_mask >> k) & 1;
-    if (P.periodic[k] && a > 0.5 * box[k] * (1.0 + 1e-12)) return MSM_ERR_CUTOFF_TOO_LARGE;
+    // minimum image: the cutoff within half the box (half the cell's width
+    // V / |face| across each axis of a triclinic cell)
+    if (P.periodic[k] && a > 0.5 * width[k] * (1.0 + 1e-12)) return MSM_ERR_CUTOFF_TOO_LARGE;
   }
   P.p = order;
   P.L = levels;
@@ -339,9 +470,10 @@ int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, in
     g.G = 1;
     for (int k = 0; k < 3; ++k) {
       if (P.periodic[k]) {
-        double q = box[k] / std::ldexp(h, levels - 1);
+        double q = edge[k] / std::ldexp(h, levels - 1);
         long long ntop = (long long)std::floor(q + 0.5);
         if (ntop < 1) ntop = 1;
+        if (ntop_fixed) ntop = ntop_fixed[k];
         long long n1 = ntop << (levels - 1);
         if (n1 > (1 << 14)) return MSM_ERR_GRID;
         g.n[k] = (int)(n1 >> (l - 1));
@@ -360,9 +492,19 @@ int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, in
     if (g.G > (1LL << 30)) return MSM_ERR_GRID;
   }
 
+  // Cartesian step of one grid point along each grid axis at level l (columns):
+  // H diag(h_l) in a triclinic cell
+  auto steps = [&](int l, double A[9]) {
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) A[3 * r + c] = P.H[3 * r + c] * P.lev[l - 1].h[c];
+  };
+  double A1[9];
+  if (P.tri) steps(1, A1);
+  const double* A1p = P.tri ? A1 : nullptr;
+
   // level-1 stencil, unfolded
   std::vector<double> K1;
-  level1_stencil(order, M, a, P.lev[0].h, P.W1, K1, P.gcoef);
+  level1_stencil(order, M, a, P.lev[0].h, P.W1, K1, P.gcoef, A1p);
   const int u[3] = {2 * P.W1[0] + 1, 2 * P.W1[1] + 1, 2 * P.W1[2] + 1};
 
   // levels 1..L-1: K^l = K^1 / 2^(l-1) (Sec. "Splitting for Coulomb kernels"),
@@ -419,8 +561,7 @@ int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, in
     for (int z = -R[2]; z <= R[2]; ++z)
       for (int y = -R[1]; y <= R[1]; ++y)
         for (int x = -R[0]; x <= R[0]; ++x) {
-          double dx = x * g1.h[0], dy = y * g1.h[1], dz = z * g1.h[2];
-          double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+          const double r = offset_length(A1p, g1.h, x, y, z);
           S1[((size_t)(z + R[2]) * (2 * R[1] + 1) + (y + R[1])) * (2 * R[0] + 1) + (x + R[0])] =
               split_kernel(P.gcoef, order, 1, 2, a, r);
         }
@@ -498,15 +639,19 @@ int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, in
     std::vector<double> T((size_t)next[0] * next[1] * next[2]);
     const bool anyp = P.periodic[0] || P.periodic[1] || P.periodic[2];
     const double R = std::ldexp(a, levels - 1);
+    double AL[9];
+    if (P.tri) steps(levels, AL);
     for (int z = 0; z < next[2]; ++z)
       for (int y = 0; y < next[1]; ++y)
         for (int x = 0; x < next[0]; ++x) {
-          int i3[3] = {x, y, z};
+          int i3[3] = {x, y, z}, d[3];
           double xv[3];
           for (int k = 0; k < 3; ++k) {
-            int d = P.periodic[k] ? i3[k] : i3[k] - (g.n[k] - 1 + Mq);
-            xv[k] = d * g.h[k];
+            d[k] = P.periodic[k] ? i3[k] : i3[k] - (g.n[k] - 1 + Mq);
+            xv[k] = d[k] * g.h[k];
           }
+          if (P.tri)  // Cartesian offset of the grid step d
+            for (int k = 0; k < 3; ++k) xv[k] = AL[3 * k] * d[0] + AL[3 * k + 1] * d[1] + AL[3 * k + 2] * d[2];
           double val;
           if (anyp) {
             val = periodic_top_G(P, xv);
@@ -538,9 +683,10 @@ int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, in
         }
   }
 
-  // cell list
+  // cell list (triclinic: in the unit cube, as many cells per axis as the
+  // cell's width across that axis holds whole cutoffs)
   for (int k = 0; k < 3; ++k) {
-    int n = (int)std::floor(box[k] / a);
+    int n = (int)std::floor(width[k] / a);
     if (n < 1) n = 1;
     if (n > 1024) n = 1024;
     P.nc[k] = n;
@@ -554,6 +700,12 @@ std::string describe_json(const HostPlan& P) {
   o.precision(17);
   o << "{\"box\":[" << P.box[0] << "," << P.box[1] << "," << P.box[2] << "],";
   o << "\"periodic\":[" << P.periodic[0] << "," << P.periodic[1] << "," << P.periodic[2] << "],";
+  if (P.tri) {  // lattice vectors a, b, c as rows (the grids' box is the unit cube)
+    o << "\"cell\":[";
+    for (int c = 0; c < 3; ++c)
+      o << (c ? "," : "") << "[" << P.H[c] << "," << P.H[3 + c] << "," << P.H[6 + c] << "]";
+    o << "],";
+  }
   o << "\"order\":" << P.p << ",\"levels\":" << P.L << ",\"M\":" << P.M << ",\"h\":" << P.h_req
     << ",\"cutoff\":" << P.a << ",\"precision\":\"" << (P.precision ? "fp64" : "fp32") << "\",";
   o << "\"max_n\":" << P.max_n << ",\"self_const\":" << P.self_const << ",";

@@ -32,8 +32,12 @@ struct LevelGeom {
 };
 
 struct HostPlan {
-  double box[3];
+  double box[3];   // edge lengths; (1, 1, 1) in a triclinic cell (grids in the unit cube)
   int periodic[3];
+  // triclinic cell (all axes periodic): H has the lattice vectors as columns
+  // (H[3*row + col]); positions map to the unit cube, s = H^{-1} r
+  int tri = 0;
+  double H[9], Hinv[9];
   int p, L, M;
   double h_req, a;
   int precision;   // 0 fp32, 1 fp64
@@ -52,8 +56,12 @@ struct HostPlan {
 };
 
 // Builds geometry and every stencil; returns 0 or an msm_status code.
+// cell (optional, 9 doubles: rows a, b, c) makes a triclinic plan (box is
+// then ignored and periodic_mask must be 7); ntop (optional) fixes the
+// top-grid point counts (a cell that changes keeps its grids).
 int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, int order,
-                    double h, double a, int levels, int precision, int max_n, int M);
+                    double h, double a, int levels, int precision, int max_n, int M,
+                    const double* cell = nullptr, const int* ntop = nullptr);
 
 std::string describe_json(const HostPlan& P);
 
@@ -61,8 +69,11 @@ std::string describe_json(const HostPlan& P);
 void softener_coefficients(int p, double* c);
 std::vector<double> quasi_sequence(int p, int M);
 // Unfolded level-1 stencil of a free-space system with spacing h (all axes).
+// A (optional): the Cartesian step of one grid point along each axis as the
+// columns of a 3x3 matrix (a triclinic grid); else the steps are h_k along
+// the Cartesian axes.
 void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::vector<double>& K,
-                    const double* gcoef);
+                    const double* gcoef, const double* A = nullptr);
 // Dense top-level kernel of a free-space system: offsets |d_k| <= n_k - 1.
 void free_top_kernel(int p, int M, double a, int L, const double hL[3], const int n[3],
                      const std::vector<double>& omega, const double* gcoef,

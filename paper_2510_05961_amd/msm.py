@@ -21,9 +21,11 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "cutoff too large
 _lib = None
 
 # every symbol declared in include/msm.h
-EXPORTS = ("msm_plan_create", "msm_plan_create_host", "msm_plan_destroy", "msm_plan_describe",
+EXPORTS = ("msm_plan_create", "msm_plan_create_cell", "msm_plan_set_cell",
+           "msm_plan_create_host", "msm_plan_destroy", "msm_plan_describe",
            "msm_plan_get_stencil", "msm_plan_grid_dims", "msm_workspace_bytes",
-           "msm_energy_forces", "msm_energy_forces_noalloc", "msm_backward", "msm_plan_status", "msm_plan_get_grid",
+           "msm_energy_forces", "msm_energy_forces_noalloc", "msm_backward", "msm_plan_status",
+           "msm_plan_get_grid",
            "msm_batch_plan_create", "msm_batch_energy_forces", "msm_status_string",
            "msm_plan_set_profiling", "msm_plan_get_profile", "msm_plan_set_profile_stages")
 
@@ -49,6 +51,8 @@ def lib():
         pp = ctypes.POINTER(ctypes.c_void_p)
         L.msm_plan_create.argtypes = [pp, P, u, i, d, d, i, i, i, i]
         L.msm_plan_create_host.argtypes = [pp, P, u, i, d, d, i, i, i, i]
+        L.msm_plan_create_cell.argtypes = [pp, P, u, i, d, d, i, i, i, i]
+        L.msm_plan_set_cell.argtypes = [P, P]
         L.msm_plan_destroy.argtypes = [P]
         L.msm_plan_describe.argtypes = [P, ctypes.c_char_p, sz]
         L.msm_plan_get_stencil.argtypes = [P, i, P, P, sz]
@@ -79,6 +83,12 @@ def _check(code, where):
         raise MSMError(code, where)
 
 
+def _flat9(cell):
+    rows = [list(r) for r in cell]
+    assert len(rows) == 3 and all(len(r) == 3 for r in rows)
+    return [x for r in rows for x in r]
+
+
 def _dbl3(v):
     return (ctypes.c_double * 3)(*[float(x) for x in v])
 
@@ -97,12 +107,23 @@ class Plan:
     """An MSM plan for one orthorhombic box (msm_plan_create)."""
 
     def __init__(self, box, periodic_mask, order, h, cutoff, levels, precision=MSM_FP32,
-                 max_n=1, quasi_degree=-1, device=True):
+                 max_n=1, quasi_degree=-1, device=True, cell=None):
+        """cell: rows a, b, c of a triclinic cell (msm_plan_create_cell; box is
+        then ignored and periodic_mask must be 7)."""
         self._h = ctypes.c_void_p()
-        f = lib().msm_plan_create if device else lib().msm_plan_create_host
-        _check(f(ctypes.byref(self._h), _dbl3(box), int(periodic_mask), int(order), float(h),
-                 float(cutoff), int(levels), int(precision), int(max_n), int(quasi_degree)),
-               "msm_plan_create")
+        if cell is not None:
+            c9 = (ctypes.c_double * 9)(*[float(x) for x in _flat9(cell)])
+            _check(lib().msm_plan_create_cell(ctypes.byref(self._h), c9, int(periodic_mask),
+                                              int(order), float(h), float(cutoff), int(levels),
+                                              int(precision), int(max_n), int(quasi_degree)),
+                   "msm_plan_create_cell")
+            box = (1.0, 1.0, 1.0)
+        else:
+            f = lib().msm_plan_create if device else lib().msm_plan_create_host
+            _check(f(ctypes.byref(self._h), _dbl3(box), int(periodic_mask), int(order),
+                     float(h), float(cutoff), int(levels), int(precision), int(max_n),
+                     int(quasi_degree)), "msm_plan_create")
+        self.cell = cell
         self.box = tuple(float(b) for b in box)
         self.periodic_mask = int(periodic_mask)
         self.order, self.levels = int(order), int(levels)
@@ -147,6 +168,12 @@ class Plan:
         n = (ctypes.c_int * 3)()
         _check(lib().msm_plan_grid_dims(self._h, level, n), "grid_dims")
         return tuple(n)
+
+    def set_cell(self, cell):
+        """msm_plan_set_cell: a new triclinic cell (stencils rebuilt)."""
+        c9 = (ctypes.c_double * 9)(*[float(x) for x in _flat9(cell)])
+        _check(lib().msm_plan_set_cell(self._h, c9), "msm_plan_set_cell")
+        self.cell = cell
 
     def workspace_bytes(self, n):
         return int(lib().msm_workspace_bytes(self._h, int(n), 0))
