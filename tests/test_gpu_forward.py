@@ -4,7 +4,10 @@ Element by element on the same seeded inputs (the oracle gets the inputs
 rounded to the run's precision), at sizes the oracle finishes in seconds;
 sampled outputs at the full workload sizes.
 """
+import hashlib
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -175,6 +178,15 @@ def test_full_size_sampled(cfg):
     e_half = 0.5 * float(np.dot(q, g["phi"]))
     scale = 0.5 * float(np.sum(np.abs(q * g["phi"])))
     assert abs(g["E"] - e_half) <= 1e-6 * scale
+    # the oracle's full-size FP64 energy of these FP32 inputs (tests/golden)
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "full_size_energies.json")))[str(cfg)]
+    digest = hashlib.sha256(np.ascontiguousarray(pos, dtype=np.float32).tobytes() +
+                            np.ascontiguousarray(q, dtype=np.float32).tobytes()).hexdigest()[:16]
+    assert digest == rec["input_sha256_16"]
+    eE = abs(g["E"] - rec["E"]) / abs(rec["E"])
+    print(f"  relE vs full-size oracle energy {eE:.2e}", flush=True)
+    assert eE <= TOL["fp32"]["E"]
     sel = np.random.default_rng(cfg).choice(len(q), 16 if cfg == 3 else 32, replace=False)
     phi_r, F_r = O.OracleMSM(box, per, p, h, a, L).sampled(pos, q, sel)
     eF = rel_rms(g["F"][sel], F_r)
