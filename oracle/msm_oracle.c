@@ -909,3 +909,110 @@ void orc_ewald_potentials(const double box[3], int slab, double alpha, int n,
     phi[i] = s;
   }
 }
+
+/* ------------------------------------------------------------------------
+ * The same 3-D Ewald sum for a whole system at once, with forces: the
+ * reciprocal part through the structure factor S(k) = sum_j q_j e^{i k.r_j}
+ * (Ewald 1921, in the textbook form of e.g. Frenkel and Smit,
+ * "Understanding Molecular Simulation", ch. 12), so that N = 10^4 takes
+ * seconds instead of N^2 lattice sums.  phi_i is the potential of
+ * orc_ewald_potentials (self term regular, neutralising background), and
+ * F_i = -q_i grad_i phi_i with the self term held fixed:
+ *   real space   F_i += q_i q_j (erfc(a r)/r + 2a/sqrt(pi) e^{-a^2 r^2}) d/r^2
+ *                over images d = r_i - r_j - j L with 0 < |d| < rc,
+ *   reciprocal   phi_i += (4 pi / V) sum_{k != 0} e^{-k^2/4a^2}/k^2 Re[e^{i k.r_i} S*(k)],
+ *                F_i += q_i (4 pi / V) sum_k e^{-k^2/4a^2}/k^2 k Im[e^{i k.r_i} S*(k)],
+ *   constants    phi_i += -2 a/sqrt(pi) q_i - pi/(a^2 V) sum_j q_j.
+ * alpha <= 0 picks the splitting whose real-space cutoff is half the shortest
+ * edge (one image per pair, the fewest k vectors).
+ * ------------------------------------------------------------------------ */
+void orc_ewald3d_system(const double box[3], double alpha, int n, const double* pos,
+                        const double* q, double* phi, double* F)
+{
+  const double V = box[0] * box[1] * box[2];
+  const double minbox = fmin(box[0], fmin(box[1], box[2]));
+  if (!(alpha > 0.0)) alpha = ORC_EWALD_X / (0.5 * minbox); /* rc = half the shortest edge */
+  const double rc = ORC_EWALD_X / alpha, kc = 2.0 * alpha * ORC_EWALD_X;
+  /* real space, over the images of the minimum-image difference: with rc at
+   * most half the shortest edge only the minimum image itself can lie within
+   * rc, otherwise every image within rc + half an edge per axis is visited */
+  int nr[3], nk[3];
+  for (int k = 0; k < 3; ++k) {
+    nr[k] = rc <= 0.5 * minbox ? 0 : (int)ceil(rc / box[k]) + 1;
+    nk[k] = (int)ceil(kc * box[k] / (2.0 * M_PI)) + 1;
+  }
+  double qsum = 0.0;
+  for (int j = 0; j < n; ++j) qsum += q[j];
+
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int i = 0; i < n; ++i) {
+    double ph = 0.0, f[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < n; ++j) {
+      double m[3];
+      for (int k = 0; k < 3; ++k) {
+        m[k] = pos[3 * i + k] - pos[3 * j + k];
+        m[k] -= box[k] * nearbyint(m[k] / box[k]);
+      }
+      for (int jz = -nr[2]; jz <= nr[2]; ++jz)
+        for (int jy = -nr[1]; jy <= nr[1]; ++jy)
+          for (int jx = -nr[0]; jx <= nr[0]; ++jx) {
+            double d[3] = {m[0] + jx * box[0], m[1] + jy * box[1], m[2] + jz * box[2]};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 == 0.0 || r2 >= rc * rc) continue;
+            double r = sqrt(r2), e = erfc(alpha * r) / r;
+            ph += q[j] * e;
+            double c = q[j] * (e + 2.0 * alpha / sqrt(M_PI) * exp(-alpha * alpha * r2)) / r2;
+            for (int k = 0; k < 3; ++k) f[k] += c * d[k];
+          }
+    }
+    phi[i] = ph - 2.0 * alpha / sqrt(M_PI) * q[i] - M_PI / (alpha * alpha * V) * qsum;
+    for (int k = 0; k < 3; ++k) F[3 * i + k] = q[i] * f[k];
+  }
+
+  /* reciprocal space: every k = 2 pi (mx/Lx, my/Ly, mz/Lz), m != 0, |k| <= kc */
+  int nvec = 0;
+  const int mx = 2 * nk[0] + 1, my = 2 * nk[1] + 1, mz = 2 * nk[2] + 1;
+  double* kv = (double*)malloc(sizeof(double) * 4 * (size_t)mx * my * mz);
+  for (int a = -nk[0]; a <= nk[0]; ++a)
+    for (int b = -nk[1]; b <= nk[1]; ++b)
+      for (int c = -nk[2]; c <= nk[2]; ++c) {
+        if (a == 0 && b == 0 && c == 0) continue;
+        double g[3] = {2.0 * M_PI * a / box[0], 2.0 * M_PI * b / box[1], 2.0 * M_PI * c / box[2]};
+        double k2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        if (k2 > kc * kc) continue;
+        kv[4 * nvec] = g[0];
+        kv[4 * nvec + 1] = g[1];
+        kv[4 * nvec + 2] = g[2];
+        kv[4 * nvec + 3] = 4.0 * M_PI / V * exp(-k2 / (4.0 * alpha * alpha)) / k2;
+        ++nvec;
+      }
+  double* S = (double*)malloc(sizeof(double) * 2 * (size_t)(nvec > 0 ? nvec : 1));
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int v = 0; v < nvec; ++v) {
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double t = kv[4 * v] * pos[3 * j] + kv[4 * v + 1] * pos[3 * j + 1] + kv[4 * v + 2] * pos[3 * j + 2];
+      re += q[j] * cos(t);
+      im += q[j] * sin(t);
+    }
+    S[2 * v] = re;
+    S[2 * v + 1] = im;
+  }
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int i = 0; i < n; ++i) {
+    double ph = 0.0, f[3] = {0.0, 0.0, 0.0};
+    for (int v = 0; v < nvec; ++v) {
+      double t = kv[4 * v] * pos[3 * i] + kv[4 * v + 1] * pos[3 * i + 1] + kv[4 * v + 2] * pos[3 * i + 2];
+      double c = cos(t), s = sin(t);
+      /* e^{i t} S* = (c + i s)(Sr - i Si) */
+      double re = c * S[2 * v] + s * S[2 * v + 1];
+      double im = s * S[2 * v] - c * S[2 * v + 1];
+      ph += kv[4 * v + 3] * re;
+      for (int k = 0; k < 3; ++k) f[k] += kv[4 * v + 3] * kv[4 * v + k] * im;
+    }
+    phi[i] += ph;
+    for (int k = 0; k < 3; ++k) F[3 * i + k] += q[i] * f[k];
+  }
+  free(S);
+  free(kv);
+}

@@ -112,6 +112,10 @@ void orc_ewald_potentials(const double box[3], int slab, double alpha, int n,
                           const double* pos, const double* q, double* phi);
 void orc_ewald_potentials_cell(const double H[9], double alpha, int n, const double* pos,
                                const double* q, double* phi);
+/* The same potentials for a 3-D periodic box, and the forces, through the
+ * structure factor (O(N K) reciprocal space instead of a lattice sum per pair). */
+void orc_ewald3d_system(const double box[3], double alpha, int n, const double* pos,
+                        const double* q, double* phi, double* F);
 
 #ifdef __cplusplus
 }

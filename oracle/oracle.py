@@ -125,6 +125,8 @@ def lib():
         L.orc_ewald_potentials.restype = None
         L.orc_ewald_potentials_cell.argtypes = [P, d, i, P, P, P]
         L.orc_ewald_potentials_cell.restype = None
+        L.orc_ewald3d_system.argtypes = [P, d, i, P, P, P, P]
+        L.orc_ewald3d_system.restype = None
         _lib = L
     return _lib
 
@@ -191,6 +193,20 @@ def ewald_potentials(box, pos, q, slab=False, alpha=None):
     lib().orc_ewald_potentials(_ptr(box), int(slab), float(alpha), len(q), _ptr(pos), _ptr(q),
                                _ptr(phi))
     return phi
+
+
+def ewald3d_system(box, pos, q, alpha=None):
+    """Potentials and forces of a 3-D periodic box by the structure-factor
+    Ewald sum; the potentials are those of ewald_potentials(box, pos, q).
+    alpha=None puts the real-space cutoff at half the shortest edge."""
+    box, pos, q = _f64(box), _f64(pos), _f64(q)
+    if alpha is None:
+        alpha = 0.0
+    phi = np.zeros(len(q))
+    F = np.zeros((len(q), 3))
+    lib().orc_ewald3d_system(_ptr(box), float(alpha), len(q), _ptr(pos), _ptr(q), _ptr(phi),
+                             _ptr(F))
+    return phi, F
 
 
 def cell_matrix(cell):
@@ -595,9 +611,15 @@ class OracleMSM:
                                       _ptr(sel), _ptr(sq), _ptr(sr))
         return sq, sr
 
-    def backward(self, pos, q, gE, v, cells=None):
-        """Cotangents (dL/dq, dL/dr) of L = gE * E + sum_i v_i . F_i."""
+    def backward(self, pos, q, gE, v, cells=None, w=None):
+        """Cotangents (dL/dq, dL/dr) of L = gE * E + sum_i v_i . F_i
+        (+ sum_i w_i phi_i when w, the cotangent of phi = dE/dq, is given:
+        see _phi_cotangent)."""
         pos, q, v = _f64(pos), _f64(q), _f64(v)
+        if w is not None:
+            dq, dr = self._phi_cotangent(pos, q, _f64(w), lambda c: self.compute(pos, c))
+            gq, gr = self.backward(pos, q, gE, v, cells=cells)
+            return gq + dq, gr + dr
         res = self.compute(pos, q)
         n = len(q)
         gq = gE * res["phi"].copy()
@@ -631,7 +653,19 @@ class OracleMSM:
                 out[r, c] = (E[0] - E[1]) / (2 * eps * scale)
         return out
 
-    def sampled_backward(self, pos, q, gE, v, sel):
+    @staticmethod
+    def _phi_cotangent(pos, q, w, run):
+        """Cotangents of sum_i w_i phi_i.  The MSM energy is a quadratic form,
+        E(q) = q^T G q / 2 with G symmetric (the interpolated level kernels,
+        the short-range pairs and the constant self term), so phi = G q and
+        sum_i w_i phi_i = w^T G q is bilinear: its q-gradient is G w, the
+        potentials computed with charges w, and its r-gradient follows from
+        polarising E, w^T G q = E(q + w) - E(q) - E(w), as
+        F(q) + F(w) - F(q + w).  run(c) evaluates phi and F for charges c."""
+        a, b, c = run(q), run(w), run(q + w)
+        return b["phi"], a["F"] + b["F"] - c["F"]
+
+    def sampled_backward(self, pos, q, gE, v, sel, w=None):
         """backward() for the listed particles only: the grid charges and
         dipole grids of every level come from all particles, the level
         potentials are evaluated only at the grid points the listed
@@ -639,6 +673,13 @@ class OracleMSM:
         pos, q, v = _f64(pos), _f64(q), _f64(v)
         self.check_domain(pos)
         sel = np.asarray(sel, dtype=np.int64)
+        if w is not None:
+            def run(c):
+                phi, F = self.sampled(pos, c, sel)
+                return {"phi": phi, "F": F}
+            dq, dr = self._phi_cotangent(pos, q, _f64(w), run)
+            gq, gr = self.sampled_backward(pos, q, gE, v, sel)
+            return gq + dq, gr + dr
         phi, F = self.sampled(pos, q, sel)
         sq, sr = self.short_range_vjp(pos, q, v, sel=sel)
         ps, qs, vs = _f64(pos[sel]), _f64(q[sel]), _f64(v[sel])
