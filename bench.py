@@ -470,6 +470,77 @@ def _grid_pass_sweep(torch, msm, steps):
     return out
 
 
+def _accuracy_sweep(torch, msm, WL, np, O, reps):
+    """Cost against accuracy over the method's parameters (Sec.
+    Accuracy-performance tradeoff): 10^4 charges no two closer than 0.6 d
+    (d = (V/N)^(1/3) = 2 A), uniform charges in [-1, 1] minus their mean, in a
+    free cube and in a periodic one; h = d; interpolation order p = 4, 6, 8,
+    cutoff a = 3..10 d, FP32 and FP64; then the degree M of omega' at a = 6 d
+    in FP64.  The exact reference is the all-pairs Coulomb sum (free) or the
+    Ewald sum (periodic), both from the FP64 oracle.  Error: force RMSE over
+    the reference forces' standard deviation (the paper's metric), with the
+    relative RMS of F and phi beside it; time: one msm_energy_forces call
+    (cell-list build included) replayed from a graph, the median of five
+    means over `reps` replays."""
+    n, dbar = 10_000, 2.0
+    L = dbar * n ** (1.0 / 3.0)
+    dev = torch.device("cuda:0")
+    out = {"workload": f"{n} charges, minimum distance 0.6 d, d = {dbar} A, cube of {L:.2f} A, "
+                       "charges U[-1, 1] minus the mean; h = d; levels 3",
+           "systems": {}}
+    for periodic in (False, True):
+        pos, q = WL.spaced_charges(n, L, periodic, seed=900 + int(periodic))
+        t0 = time.perf_counter()
+        if periodic:
+            phi_r, F_r = O.ewald3d_system((L, L, L), pos, q)
+        else:
+            phi_r, F_r = O.direct_coulomb(pos, q)
+        ref_s = time.perf_counter() - t0
+        std = float(np.std(F_r))
+        points = []
+
+        def run(p, a, fp64, M=-1):
+            dt = np.float64 if fp64 else np.float32
+            P = torch.from_numpy(pos.astype(dt)).to(dev)
+            Q = torch.from_numpy(q.astype(dt)).to(dev)
+            plan = msm.Plan((L, L, L), 7 if periodic else 0, p, dbar, a * dbar, 3,
+                            msm.MSM_FP64 if fp64 else msm.MSM_FP32, n, quasi_degree=M)
+            E, F, dq = plan.energy_forces(P, Q)
+            torch.cuda.synchronize()
+            # one call captured in a graph and replayed: the GPU's time per
+            # call, without the host's launch cost of ~30 small kernels
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                plan.energy_forces(P, Q, out=(E, F, dq), stream=torch.cuda.current_stream())
+            ts = sorted(_time(g.replay, torch, reps) for _ in range(5))
+            t = ts[2]
+            if plan.status() != 0:
+                raise RuntimeError("device error flag set in the accuracy sweep")
+            Fg, pg = F.double().cpu().numpy(), dq.double().cpu().numpy()
+            rec = {"p": p, "a_over_d": a, "precision": "fp64" if fp64 else "fp32",
+                   "M": plan.describe()["M"], "ms": round(t * 1e3, 4),
+                   "force_rmse_over_std": float(np.sqrt(np.mean((Fg - F_r) ** 2)) / std),
+                   "force_rel_rms": _rel(Fg, F_r), "phi_rel_rms": _rel(pg, phi_r)}
+            plan.close()
+            return rec
+
+        for fp64 in (False, True):
+            for p in (4, 6, 8):
+                for a in range(3, 11):
+                    points.append(run(p, a, fp64))
+        msweep = []
+        for p in (4, 6, 8):
+            for M in (p // 2 - 1, p // 2, p, 2 * p):
+                msweep.append(run(p, 6, True, M))
+        print(f"accuracy sweep: {'periodic' if periodic else 'free'} system done",
+              file=sys.stderr, flush=True)
+        out["systems"]["periodic" if periodic else "free"] = {
+            "reference": "Ewald sum (structure factors)" if periodic else "all-pairs Coulomb",
+            "reference_seconds": round(ref_s, 2), "force_std": std,
+            "points": points, "quasi_degree_sweep": msweep}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -483,6 +554,9 @@ def main():
                     help="skip the grid-pass timing on 128^3-512^3 level-1 grids with 1e7-6e7 "
                          "charges (HBM fraction of anterpolation, restriction, prolongation, "
                          "interpolation)")
+    ap.add_argument("--accuracy-sweep", action="store_true",
+                    help="add the cost-vs-accuracy sweep (p = 4/6/8, cutoff 3-10 mean spacings, "
+                         "FP32/FP64, degree of omega') on 10^4 spaced charges, free and periodic")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, one device-to-device copy of this many MiB "
                          "(reference kernel for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -585,6 +659,10 @@ def main():
             result["grid_pass_sweep"] = _grid_pass_sweep(torch, msm, max(args.steps // 10, 3))
         except RuntimeError as e:  # (MSMError and out-of-memory included) keep the headline line
             result["grid_pass_sweep"] = {"error": str(e)}
+
+    if args.accuracy_sweep:
+        from oracle import oracle as O
+        result["accuracy_sweep"] = _accuracy_sweep(torch, msm, WL, np, O, 20)
 
     print(json.dumps(result), flush=True)
 

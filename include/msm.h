@@ -112,7 +112,8 @@ msm_status msm_plan_create_cell(msm_plan* out, const double cell[9], unsigned pe
  * fewer).  MSM_ERR_INVALID_ARG for other plans; MSM_ERR_CUTOFF_TOO_LARGE if
  * the new cell is too thin for the cutoff; MSM_ERR_GRID if a stencil outgrows
  * the convolution's limits (create a new plan then).  On an error the plan's
- * stencils are undefined.
+ * stencils are undefined.  The stencils move to new device buffers: a graph
+ * captured from this plan's calls before must be captured again.
  */
 msm_status msm_plan_set_cell(msm_plan plan, const double cell[9]);
 
@@ -203,6 +204,49 @@ msm_status msm_backward(msm_plan plan, int n, const void* pos, const void* q, co
                         const double* gE, const void* gF, void* grad_pos, void* grad_q,
                         void* stream);
 
+/*
+ * msm_backward_full -- the same product with a cotangent on the third output,
+ * the charge gradient dE/dq = phi (Sec. Fundamentals; losses on the
+ * potentials, as in charge equilibration).  For
+ *   L = gE * U + sum_i gF_i . F_i + sum_i gdEdq_i phi_i
+ * it writes grad_q = dL/dq and grad_pos = dL/dr.  U = q^T G q / 2 with G
+ * symmetric, so the last term is w^T G q (w = gdEdq): its q-gradient is the
+ * potential of charges w, G w, and its r-gradient is
+ * w_i grad phi^q(r_i) + q_i grad phi^w(r_i) (both fields taken at r_i, the
+ * short-range pairs and every level included).
+ *   gdEdq      device [n] (plan precision), or NULL (= 0; the call is then
+ *              msm_backward).
+ * The other arguments, the errors and the stream are those of msm_backward.
+ */
+msm_status msm_backward_full(msm_plan plan, int n, const void* pos, const void* q,
+                             const void* ws, const double* gE, const void* gF, const void* gdEdq,
+                             void* grad_pos, void* grad_q, void* stream);
+
+/*
+ * msm_plan_set_skin -- Verlet skin for the short-range cell list (molecular
+ * dynamics: the neighbour structure kept over steps while no charge has
+ * moved far; Sec. MD simulation of charged Lennard-Jonesium uses a
+ * neighbour list refreshed this way).  With skin > 0 the cells have edge
+ * >= cutoff_a + skin, and a call rebuilds the cell list only when some
+ * charge moved more than skin/2 (Euclidean, in the caller's coordinates)
+ * since the last rebuild; otherwise it reuses the cell assignment and the
+ * cluster layout with the new positions and charges.  The decision is made
+ * on the device, so a captured graph of msm_energy_forces stays valid over
+ * steps.  Results equal those of a rebuilt list up to the summation order.
+ * A call with a different n, a call with a workspace (msm_backward's saved
+ * state) and the call after it, and the first call after msm_plan_set_skin or
+ * msm_plan_set_cell always rebuild.  skin = 0 (the default) rebuilds on every
+ * call.  The cell count changes, so msm_workspace_bytes may too; the cell
+ * list never has more cells per axis than at plan creation.
+ * msm_energy_forces_noalloc returns MSM_ERR_UNSUPPORTED on a plan with a
+ * skin.  Errors: MSM_ERR_INVALID_ARG (skin < 0 or not finite), MSM_ERR_OOM.
+ */
+msm_status msm_plan_set_skin(msm_plan plan, double skin);
+/* Calls of msm_energy_forces since msm_plan_set_skin and how many of them
+ * rebuilt the cell list (synchronises `stream`; both 0 without a skin). */
+msm_status msm_plan_skin_stats(msm_plan plan, long long* calls, long long* rebuilds,
+                               void* stream);
+
 /* Synchronises `stream`, returns the sticky device error of the plan
  * (MSM_OK, MSM_ERR_OUT_OF_DOMAIN or MSM_ERR_NONFINITE) and clears it. */
 msm_status msm_plan_status(msm_plan plan, void* stream);
@@ -271,6 +315,44 @@ msm_status msm_plan_get_profile(msm_plan plan, char* json, size_t cap, int reset
 msm_status msm_plan_set_profile_stages(msm_plan plan, const char* stages);
 
 const char* msm_status_string(msm_status status);
+
+/*
+ * Molecular dynamics around the forward (Sec. "MD simulation of charged
+ * Lennard-Jonesium"): n charged Lennard-Jones particles in the plan's box,
+ * integrated with velocity Verlet,
+ *   v += dt/2 F/m;  x += dt v;  F = F_MSM(x) + F_LJ(x);  v += dt/2 F/m,
+ * where F_MSM comes from msm_energy_forces on `plan` and
+ *   u_LJ(r) = 4 eps [(sigma/r)^12 - (sigma/r)^6] S(r)
+ * with the smooth switch S = 1 - 10 x^3 + 15 x^4 - 6 x^5,
+ * x = (r - switch_on)/(cutoff - switch_on) between switch_on and cutoff
+ * (S = 1 below, 0 beyond), minimum images on periodic axes.  The driver owns
+ * its state (device, plan precision) and a stream; the plan (orthorhombic,
+ * max_n >= n) stays the caller's and must outlive the driver.  Set a Verlet
+ * skin on the plan (msm_plan_set_skin) to keep its cell list over steps.
+ *   log_steps   steps whose energies are kept (msm_md_energies).
+ * Errors: MSM_ERR_INVALID_ARG, MSM_ERR_UNSUPPORTED (triclinic plan),
+ * MSM_ERR_CAPACITY (n > max_n), MSM_ERR_CUTOFF_TOO_LARGE (cutoff above half a
+ * periodic edge), MSM_ERR_OOM.
+ */
+typedef struct msm_md_s* msm_md;
+msm_status msm_md_create(msm_md* out, msm_plan plan, int n, double dt, double lj_epsilon,
+                         double lj_sigma, double lj_cutoff, double lj_switch_on, int log_steps);
+msm_status msm_md_destroy(msm_md md);
+/* Copies the state in (device pos [n][3], vel [n][3], q [n], mass [n]),
+ * evaluates the forces of pos and clears the energy log; ordered after
+ * `stream`, and `stream` after it. */
+msm_status msm_md_set_state(msm_md md, const void* pos, const void* vel, const void* q,
+                            const void* mass, void* stream);
+/* nsteps velocity-Verlet steps.  use_graph != 0: the first such call
+ * captures one step in a HIP graph and every step replays it (the plan must
+ * then not be used with another n, or re-celled, while the driver lives). */
+msm_status msm_md_run(msm_md md, int nsteps, int use_graph, void* stream);
+/* Copies positions, velocities and total forces out (device; NULL skips). */
+msm_status msm_md_get_state(msm_md md, void* pos, void* vel, void* forces, void* stream);
+/* Host copy of the energies after each step since msm_md_set_state:
+ * host[3 k + 0..2] = kinetic, Lennard-Jones, MSM energy of step k, for
+ * k < min(steps, log_steps, max_steps); *steps = steps run (synchronises). */
+msm_status msm_md_energies(msm_md md, double* host, int max_steps, int* steps);
 
 #ifdef __cplusplus
 }

@@ -690,3 +690,58 @@ class OracleMSM:
             lib().orc_interpolate_vjp(self._gp, l, len(sel), _ptr(ps), _ptr(qs), _ptr(vs),
                                       _ptr(psi), _ptr(psiD), _ptr(sq), _ptr(sr))
         return gE * phi + sq, -gE * F + sr
+
+
+# --------------------------------------------------------------------------
+# molecular dynamics of charged Lennard-Jones particles (Sec. MD simulation
+# of charged Lennard-Jonesium): the short-range partner of the MSM energy
+# and the velocity-Verlet integrator, written out plainly
+# --------------------------------------------------------------------------
+def lj_switch(r, rc, ron):
+    """S(r): 1 up to ron, 1 - 10 x^3 + 15 x^4 - 6 x^5 with x = (r - ron)/(rc -
+    ron) between, 0 from rc on (S, S', S'' continuous), and dS/dr."""
+    r = np.asarray(r, dtype=np.float64)
+    x = np.clip((r - ron) / (rc - ron), 0.0, 1.0)
+    S = 1.0 - 10.0 * x ** 3 + 15.0 * x ** 4 - 6.0 * x ** 5
+    dS = (-30.0 * x ** 2 + 60.0 * x ** 3 - 30.0 * x ** 4) / (rc - ron)
+    return S, dS
+
+
+def lj_energy_forces(box, periodic, pos, eps, sigma, rc, ron):
+    """E = sum over pairs i < j of 4 eps [(sigma/r)^12 - (sigma/r)^6] S(r),
+    minimum image on periodic axes (rc at most half a periodic edge), and
+    F_i = -dE/dr_i; all pairs, FP64."""
+    pos = _f64(pos)
+    box = np.asarray(box, dtype=np.float64)
+    per = np.asarray(periodic, dtype=bool)
+    d = pos[:, None, :] - pos[None, :, :]
+    d[..., per] -= box[per] * np.round(d[..., per] / box[per])
+    r = np.sqrt(np.sum(d * d, axis=-1))
+    np.fill_diagonal(r, np.inf)
+    inside = r < rc
+    rr = np.where(inside, r, 1.0)
+    sr6 = (sigma / rr) ** 6
+    u = 4.0 * eps * (sr6 * sr6 - sr6)
+    du = 4.0 * eps * (-12.0 * sr6 * sr6 + 6.0 * sr6) / rr
+    S, dS = lj_switch(rr, rc, ron)
+    E = 0.5 * float(np.sum(np.where(inside, u * S, 0.0)))
+    c = np.where(inside, -(du * S + u * dS) / rr, 0.0)
+    F = np.sum(c[..., None] * d, axis=1)
+    return E, F
+
+
+def velocity_verlet(x, v, m, forces, dt, nsteps):
+    """nsteps of v += dt/2 F/m, x += dt v, F = forces(x), v += dt/2 F/m from
+    (x, v) with forces F = forces(x)[0]; forces returns (F, energies).
+    Returns x, v and the list of (kinetic energy, energies) after each step."""
+    x, v = _f64(x).copy(), _f64(v).copy()
+    m = _f64(m)[:, None]
+    F, _ = forces(x)
+    log = []
+    for _ in range(nsteps):
+        v += 0.5 * dt * F / m
+        x += dt * v
+        F, e = forces(x)
+        v += 0.5 * dt * F / m
+        log.append((0.5 * float(np.sum(m * v * v)), e))
+    return x, v, log

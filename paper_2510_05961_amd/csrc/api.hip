@@ -294,6 +294,7 @@ msm_status upload_plan(msm_plan P) {
   if ((st = hip_alloc(P, &P->Jd, sizeof(J)))) return st;
   if (hipMemcpy(P->Jd, J, sizeof(J), hipMemcpyHostToDevice)) return MSM_ERR_HIP;
   P->ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
+  for (int k = 0; k < 3; ++k) P->nc_cap[k] = hp.nc[k];
   if ((long long)P->ncell * kCountCopies > (1LL << 30)) return MSM_ERR_GRID;
   {
     const size_t bytes = work_layout<T>(P, std::max(hp.max_n, 1), nullptr, nullptr);
@@ -344,6 +345,7 @@ PairParams<T> pair_params(const HostPlan& hp) {
     pp.nc[k] = hp.nc[k];
   }
   pp.ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
+  pp.margin = (T)(0.5 * hp.skin);
   const double a = hp.a;
   pp.a2 = (T)(a * a);
   pp.inv_a2 = (T)(1.0 / (a * a));
@@ -509,11 +511,20 @@ void grid_pass(msm_plan P, hipStream_t sa, hipStream_t sb, hipStream_t sd) {
   }
 }
 
-// Whether the forward runs as a DAG over four streams (MSM_STREAMS=0: one;
-// read on every call).
-static bool use_streams() {
+// Whether a call runs as a DAG over four streams (MSM_STREAMS=0: one; read
+// on every call).  A call recorded into a graph (the caller's stream is
+// capturing) stays on the caller's stream: a capture of the four-stream
+// fork and join ended in a crash inside the runtime's end of capture, so
+// graphs hold the one-stream sequence.
+static bool use_streams(hipStream_t s) {
   const char* e = getenv("MSM_STREAMS");
-  return !(e && atoi(e) == 0);
+  if (e && atoi(e) == 0) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs == hipStreamCaptureStatusNone;
 }
 
 template <typename T>
@@ -547,6 +558,7 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
     cg.nc[k] = hp.nc[k];
     cg.cs[k] = hp.cs[k];
   }
+  cg.margin = 0.5 * hp.skin;
   ZeroJobs z;
   z.n = 0;
   if (!anterp_tiled(p, n, cg, g1.n, g1.per, g1.hd)) {  // (tiles write every value)
@@ -560,21 +572,35 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
   // a1 binning (cell counts, scans of cell starts and cluster offsets,
   // scatter), then Morton order inside cells and the 8-particle clusters
   const BinParams<T> bp = bin_params<T>(hp);
+  // Verlet skin: the device decides whether this call rebuilds the cell
+  // list; a new n or a call that keeps its list in a workspace always does,
+  // and the call after one with a workspace too
+  SkinDev<T> sk{};
+  int force = 0;
+  if (hp.skin > 0 && P->skin_state) {
+    sk.state = P->skin_state;
+    sk.ref = (vec4_t<T>*)P->skin_ref;
+    sk.shift = (vec4_t<T>*)P->skin_shift;
+    sk.half2 = (T)(0.25 * hp.skin * hp.skin);
+    sk.keep_force = ws ? 1 : 0;
+    force = (n != P->skin_n || ws) ? 1 : 0;
+    P->skin_n = n;
+  }
   int ev = pf.begin("bin", s);
   launch_binning<T>(n, pos, q, bp, P->ncell, P->w->cell_of, P->w->rank, P->w->counts,
                     (vec4_t<T>*)P->w->wrapped, start, P->w->cl_start, sorted, perm, P->flag,
-                    P->w->scan_tmp, z, s);
+                    P->w->scan_tmp, z, sk, force, s);
   pf.end(ev, s);
   ev = pf.begin("cluster", s);
   launch_cluster_layout<T>(1, 0, P->ncell, start, P->w->cl_start, bp, (const vec4_t<T>*)P->w->wrapped,
                            sorted, perm, (vec4_t<T>*)P->w->cpos, (vec4_t<T>*)P->w->cbox, P->w->cinfo,
-                           P->w->counts, s);
+                           P->w->counts, sk.state, n, s);
   pf.end(ev, s);
 
   // a2 short-range pairs (i-clusters against culled j particles), on its
   // own stream: it only needs the cluster layout, and interpolation waits
   // for it
-  const bool dag = use_streams();
+  const bool dag = use_streams(s);
   hipStream_t sp = dag ? P->sc : s;
   if (dag) {
     (void)hipEventRecord(P->ev[0], s);
@@ -607,8 +633,8 @@ msm_status forward(msm_plan P, int n, const T* pos, const T* q, void* ws, double
 }
 
 template <typename T>
-msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T* gF, T* grad_pos,
-                    T* grad_q, hipStream_t s) {
+msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T* gF,
+                    const T* gphi, T* grad_pos, T* grad_q, hipStream_t s) {
   const HostPlan& hp = P->hp;
   const int p = hp.p;
   WsLayout w = ws_layout(P, n);
@@ -620,7 +646,7 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
   const T* save_F = (const T*)(b + w.F);
   const T* save_e1 = (const T*)(b + w.e1);
   StageProfiler& pf = P->prof;
-  if (!gF) {
+  if (!gF && !gphi) {
     int ev = pf.begin("bwd_energy_only", s);
     launch_grad_energy_only<T>(n, perm, save_phi, save_F, gE, grad_q, grad_pos, s);
     pf.end(ev, s);
@@ -630,24 +656,25 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
   T* gq_sr = (T*)P->w->phi0;
   T* gr_sr = (T*)P->w->F0;
   int ev = pf.begin("bwd_layout", s);
-  launch_gather_v<T>(n, perm, gF, grid_dev<T>(hp, 1), v, s);
+  launch_gather_v<T>(n, perm, gF, gphi, grid_dev<T>(hp, 1), v, s);
   {
     // cluster layout of the saved (already Morton-ordered) cell list
     const BinParams<T> bp = bin_params<T>(hp);
     launch_cluster_layout<T>(0, 1, P->ncell, start, P->w->cl_start, bp, nullptr,
                              const_cast<vec4_t<T>*>(sorted), const_cast<int*>(perm),
-                             (vec4_t<T>*)P->w->cpos, (vec4_t<T>*)P->w->cbox, P->w->cinfo, nullptr, s);
+                             (vec4_t<T>*)P->w->cpos, (vec4_t<T>*)P->w->cbox, P->w->cinfo, nullptr,
+                             nullptr, n, s);
   }
   pf.end(ev, s);
   // the pair-sum VJP beside the grid part (as in the forward)
-  const bool dag = use_streams();
+  const bool dag = use_streams(s);
   hipStream_t sp = dag ? P->sc : s;
   if (dag) {
     (void)hipEventRecord(P->ev[0], s);
     (void)hipStreamWaitEvent(sp, P->ev[0], 0);
   }
   ev = pf.begin("bwd_pair", sp);
-  launch_pair_vjp_cl<T>(p, n, P->ncell, P->w->cl_start, P->w->cinfo, perm, gF,
+  launch_pair_vjp_cl<T>(p, n, P->ncell, P->w->cl_start, P->w->cinfo, perm, gF, gphi,
                         (const vec4_t<T>*)P->w->cpos, (vec4_t<T>*)P->w->cv, (const vec4_t<T>*)P->w->cbox,
                         pair_params<T>(hp), P->w->null_h, gq_sr, gr_sr, sp);
   pf.end(ev, sp);
@@ -668,6 +695,7 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
       cg.nc[k] = hp.nc[k];
       cg.cs[k] = hp.cs[k];
     }
+    cg.margin = 0.5 * hp.skin;
     launch_anterp_dipole<T>(p, n, P->ncell, start, cg, sorted, v, g1, (T*)P->w->qg[0], s);
   }
   pf.end(ev, s);
@@ -675,7 +703,7 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
   if (dag) (void)hipStreamWaitEvent(s, P->ev[1], 0);
   ev = pf.begin("bwd_interp", s);
   launch_interp_vjp<T>(p, n, sorted, v, perm, g1, save_e1, (const T*)P->w->eg[0], save_phi, save_F,
-                       gq_sr, gr_sr, gE, grad_q, grad_pos, s);
+                       gq_sr, gr_sr, gE, hp.self_const, grad_q, grad_pos, s);
   pf.end(ev, s);
   return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
 }
@@ -744,14 +772,20 @@ msm_status set_cell(msm_plan P, const double cell[9]) {
   int rc;
   try {
     rc = build_host_plan(hp, nullptr, 7, old.p, old.h_req, old.a, old.L, old.precision, old.max_n,
-                         old.M, cell, ntop);
+                         old.M, cell, ntop, old.skin);
   } catch (...) {
     rc = MSM_ERR_OOM;
   }
   if (rc != MSM_OK) return (msm_status)rc;
   for (int k = 0; k < 3; ++k) {  // the cell list never grows past its buffers
-    if (hp.nc[k] > old.nc[k]) hp.nc[k] = old.nc[k];
+    if (hp.nc[k] > P->nc_cap[k]) hp.nc[k] = P->nc_cap[k];
     hp.cs[k] = hp.box[k] / hp.nc[k];
+  }
+  if (P->skin_state) {  // the next call rebuilds the cell list
+    const int one = 1;
+    if (hipDeviceSynchronize() ||
+        hipMemcpy(P->skin_state + kSkinForce, &one, sizeof(int), hipMemcpyHostToDevice))
+      return MSM_ERR_HIP;
   }
   for (int l = 1; l <= hp.L; ++l) hp.lev[l - 1].factored = old.lev[l - 1].factored;
   if (hipDeviceSynchronize() != hipSuccess) return MSM_ERR_HIP;
@@ -770,7 +804,7 @@ msm_status set_cell(msm_plan P, const double cell[9]) {
   return upload_stencils<T>(P);
 }
 
-// Working memory of msm_energy_forces_noalloc: one array per GPU, held from// Working memory of msm_energy_forces_noalloc: one array per GPU, held from
+// Working memory of msm_energy_forces_noalloc: one array per GPU, held from
 // the library's load until the process ends.  Host code never uses the
 // array's name as an address: the device address comes from
 // hipGetSymbolAddress, once per device, with that device current.
@@ -798,6 +832,7 @@ msm_status scratch_address(int dev, void** out) {
 template <typename T>
 msm_status forward_noalloc(msm_plan P, int n, const T* pos, const T* q, void* ws,
                            double* energy, T* F, T* dEdq, hipStream_t s) {
+  if (P->hp.skin > 0) return MSM_ERR_UNSUPPORTED;  // (its cell list lives in the plan)
   const size_t need = work_layout<T>(P, n, nullptr, nullptr);
   if (need == 0 || need > kScratchBytes) return MSM_ERR_CAPACITY;
   void* base = nullptr;
@@ -839,6 +874,53 @@ msm_status msm_plan_set_cell(msm_plan plan, const double cell[9]) {
   if (!plan || plan->batch || !cell || !plan->hp.tri) return MSM_ERR_INVALID_ARG;
   if (!plan->device) return MSM_ERR_NO_DEVICE;
   return plan->hp.precision == MSM_FP64 ? set_cell<double>(plan, cell) : set_cell<float>(plan, cell);
+}
+
+msm_status msm_plan_set_skin(msm_plan plan, double skin) {
+  if (!plan || plan->batch || !(skin >= 0) || !std::isfinite(skin)) return MSM_ERR_INVALID_ARG;
+  HostPlan& hp = plan->hp;
+  if (!plan->device) {  // a host plan: the cell-list geometry only
+    hp.skin = skin;
+    cell_list_geometry(hp);
+    return MSM_OK;
+  }
+  const size_t vec = (size_t)std::max(hp.max_n, 1) * 4 *
+                     (hp.precision == MSM_FP64 ? sizeof(double) : sizeof(float));
+  if (skin > 0 && !plan->skin_state) {
+    msm_status st;
+    if ((st = hip_alloc(plan, (void**)&plan->skin_state, 4 * sizeof(int))) ||
+        (st = hip_alloc(plan, &plan->skin_ref, vec)) ||
+        (st = hip_alloc(plan, &plan->skin_shift, vec)))
+      return st;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return MSM_ERR_HIP;
+  hp.skin = skin;
+  cell_list_geometry(hp);
+  for (int k = 0; k < 3; ++k) {  // the cell list never grows past its buffers
+    if (hp.nc[k] > plan->nc_cap[k]) hp.nc[k] = plan->nc_cap[k];
+    hp.cs[k] = hp.box[k] / hp.nc[k];
+  }
+  plan->ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
+  if (plan->skin_state) {
+    const int init[4] = {1, 1, 0, 0};  // force a rebuild; no calls yet
+    if (hipMemcpy(plan->skin_state, init, sizeof(init), hipMemcpyHostToDevice))
+      return MSM_ERR_HIP;
+  }
+  return MSM_OK;
+}
+
+msm_status msm_plan_skin_stats(msm_plan plan, long long* calls, long long* rebuilds,
+                               void* stream) {
+  if (!plan || plan->batch || !calls || !rebuilds) return MSM_ERR_INVALID_ARG;
+  *calls = *rebuilds = 0;
+  if (!plan->skin_state) return MSM_OK;
+  int st[4];
+  if (hipStreamSynchronize((hipStream_t)stream) ||
+      hipMemcpy(st, plan->skin_state, sizeof(st), hipMemcpyDeviceToHost))
+    return MSM_ERR_HIP;
+  *calls = (unsigned)st[kSkinCalls];
+  *rebuilds = (unsigned)st[kSkinRebuilds];
+  return MSM_OK;
 }
 
 msm_status msm_plan_create_host(msm_plan* out, const double box[3], unsigned periodic_mask,
@@ -926,9 +1008,9 @@ msm_status msm_energy_forces_noalloc(msm_plan plan, int n, const void* pos, cons
                                 (float*)forces, (float*)dEdq, s);
 }
 
-msm_status msm_backward(msm_plan plan, int n, const void* pos, const void* q, const void* ws,
-                        const double* gE, const void* gF, void* grad_pos, void* grad_q,
-                        void* stream) {
+msm_status msm_backward_full(msm_plan plan, int n, const void* pos, const void* q,
+                             const void* ws, const double* gE, const void* gF, const void* gdEdq,
+                             void* grad_pos, void* grad_q, void* stream) {
   (void)pos;
   (void)q;
   if (!plan || plan->batch) return MSM_ERR_INVALID_ARG;
@@ -937,9 +1019,16 @@ msm_status msm_backward(msm_plan plan, int n, const void* pos, const void* q, co
   if (n > plan->hp.max_n) return MSM_ERR_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
   if (plan->hp.precision == MSM_FP64)
-    return backward<double>(plan, n, ws, gE, (const double*)gF, (double*)grad_pos,
-                            (double*)grad_q, s);
-  return backward<float>(plan, n, ws, gE, (const float*)gF, (float*)grad_pos, (float*)grad_q, s);
+    return backward<double>(plan, n, ws, gE, (const double*)gF, (const double*)gdEdq,
+                            (double*)grad_pos, (double*)grad_q, s);
+  return backward<float>(plan, n, ws, gE, (const float*)gF, (const float*)gdEdq,
+                         (float*)grad_pos, (float*)grad_q, s);
+}
+
+msm_status msm_backward(msm_plan plan, int n, const void* pos, const void* q, const void* ws,
+                        const double* gE, const void* gF, void* grad_pos, void* grad_q,
+                        void* stream) {
+  return msm_backward_full(plan, n, pos, q, ws, gE, gF, nullptr, grad_pos, grad_q, stream);
 }
 
 msm_status msm_plan_status(msm_plan plan, void* stream) {

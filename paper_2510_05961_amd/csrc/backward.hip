@@ -1,5 +1,5 @@
 // backward.hip -- adjoint kernels of the MSM (vector-Jacobian product of the
-// forward outputs E and F with respect to charges and positions).
+// forward outputs E, F and phi = dE/dq with respect to charges and positions).
 //
 // For L = gE * U + sum_i v_i . F_i (v = cotangent of the forces):
 //  * dU/dq_i = phi_i and dU/dr_i = -F_i are the forward's own outputs;
@@ -14,6 +14,15 @@
 //      d(v.F0)/dq_i = sum_j q_j f (v_i - v_j) . d_ij
 //      d(v.F0)/dr_i = sum_j q_i q_j [f (v_i - v_j) + (f'/r) ((v_i - v_j) . d_ij) d_ij]
 //    with f = 1/r^3 + 2 P'(t)/a^3 and f'/r = -3/r^5 + 4 P''(t)/a^5.
+// A cotangent w of phi adds sum_i w_i phi_i = w^T G q, bilinear in (w, q)
+// with the same symmetric G as U = q^T G q / 2:
+//  * d/dq_i = (G w)_i: the potential of charges w, i.e. w_i enters the
+//    adjoint grid source like a charge (source S = D - W, W_m = sum_i w_i
+//    phi_m(r_i), so that -(A S) gives -(A D) + (A W)), plus the short-range
+//    sum_j w_j k0(r_ij) and the self term -w_i gamma(0)/a;
+//  * d/dr_i = w_i grad phi^q(r_i) + q_i grad phi^w(r_i): the first from the
+//    forward's e (its gradient moments), the second from A S as above, and
+//    in the pair sum -sum_j (w_i q_j + q_i w_j) f d_ij.
 #include <algorithm>
 #include <cmath>
 
@@ -22,20 +31,21 @@
 
 namespace msm {
 
-// v in sorted order (vec4 with w = 0) from the caller's [n][3] cotangent.
-// On a triclinic grid the cotangent is taken to the grid frame, H^{-1} v, so
-// that v . grad_r = (H^{-1} v) . grad_s.
+// Cotangents in sorted order: v from the caller's [n][3] force cotangent in
+// x, y, z (zero without one), the cotangent w of phi in .w (zero without one).
+// On a triclinic grid v is taken to the grid frame, H^{-1} v, so that
+// v . grad_r = (H^{-1} v) . grad_s.
 template <typename T>
 __global__ void k_gather_v(int n, const int* __restrict__ perm, const T* __restrict__ gF,
-                           GridDev<T> g, vec4_t<T>* __restrict__ v) {
+                           const T* __restrict__ gphi, GridDev<T> g, vec4_t<T>* __restrict__ v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int o = perm[i];
   vec4_t<T> t;
-  t.x = gF[3 * o];
-  t.y = gF[3 * o + 1];
-  t.z = gF[3 * o + 2];
-  t.w = T(0);
+  t.x = gF ? gF[3 * o] : T(0);
+  t.y = gF ? gF[3 * o + 1] : T(0);
+  t.z = gF ? gF[3 * o + 2] : T(0);
+  t.w = gphi ? gphi[o] : T(0);
   if (g.tri) {
     const T a = t.x, b = t.y, c = t.z;
     t.x = (T)g.Hi[0] * a + (T)g.Hi[1] * b + (T)g.Hi[2] * c;
@@ -45,10 +55,12 @@ __global__ void k_gather_v(int n, const int* __restrict__ perm, const T* __restr
   v[i] = t;
 }
 
-// The dipole grid in the brick form of the forward anterpolation: one
-// workgroup per super-cell (as in the forward), 64-bit fixed-point sums in LDS (exact integer adds; the
+// The adjoint grid source S_m = sum_i [q_i v_i . grad phi_m(r_i) - w_i phi_m(r_i)]
+// (the dipole grid, less the grid charge of the phi cotangent) in the brick
+// form of the forward anterpolation: one workgroup per super-cell (as in the
+// forward), 64-bit fixed-point sums in LDS (exact integer adds; the
 // power-of-two scale bounds every sum by 2^62, since |contribution| <=
-// |q| (|vx| + |vy| + |vz|) max(1/h) for B-spline weights in [0, 1] and
+// |q| (|vx| + |vy| + |vz|) max(1/h) + |w| for B-spline weights in [0, 1] and
 // derivatives in [-1/h, 1/h]), then one atomic per non-zero point.  Bricks
 // larger than brick_cap points fall back to per-particle atomics.
 template <typename T, int P>
@@ -60,31 +72,34 @@ __global__ void __launch_bounds__(256)
   __shared__ double bsum[4];
   __shared__ BrickRuns runs;
   int c0[3], c1[3], nruns;
-  const int count = brick_runs(blockIdx.x, start, cg, bg, c0, c1, runs, nruns);
-  if (count == 0) return;
+  const int part = blockIdx.x % bg.split, stride = blockDim.x * bg.split;  // (as the forward)
+  const int count = brick_runs(blockIdx.x / bg.split, start, cg, bg, c0, c1, runs, nruns);
+  if (count <= part * (int)blockDim.x) return;
   int lo[3], ext[3];
   const int vol = brick_box<P>(c0, c1, cg, g.hd, lo, ext);
   const bool staged = vol <= brick_cap;
   const double ih[3] = {1.0 / g.hd[0], 1.0 / g.hd[1], 1.0 / g.hd[2]};
+  const double ihmax = fmax(ih[0], fmax(ih[1], ih[2]));
   double scale = 1.0;
   if (staged) {
     for (int b = threadIdx.x; b < vol; b += blockDim.x) brick[b] = 0;
     double bound = 0.0;
-    for (int j = threadIdx.x; j < count; j += blockDim.x) {
+    for (int j = part * blockDim.x + threadIdx.x; j < count; j += stride) {
       const int i = brick_particle(runs, nruns, j);
       const vec4_t<T> vi = v[i];
       bound += fabs((double)sorted[i].w) *
-               (fabs((double)vi.x) + fabs((double)vi.y) + fabs((double)vi.z));
+                   (fabs((double)vi.x) + fabs((double)vi.y) + fabs((double)vi.z)) * ihmax +
+               fabs((double)vi.w);
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) bound += __shfl_xor(bound, o);
     if ((threadIdx.x & 63) == 0) bsum[threadIdx.x >> 6] = bound;
     __syncthreads();
     int ex;
-    (void)frexp((bsum[0] + bsum[1] + bsum[2] + bsum[3]) * fmax(ih[0], fmax(ih[1], ih[2])), &ex);
+    (void)frexp(bsum[0] + bsum[1] + bsum[2] + bsum[3], &ex);
     scale = ldexp(1.0, 62 - max(ex, -900));
   }
-  for (int jp = threadIdx.x; jp < count; jp += blockDim.x) {
+  for (int jp = part * blockDim.x + threadIdx.x; jp < count; jp += stride) {
     const int i = brick_particle(runs, nruns, jp);
     const vec4_t<T> pi = sorted[i];
     const vec4_t<T> vi = v[i];
@@ -104,16 +119,17 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int k = 0; k < 3; ++k) inside = inside && m0[k] >= lo[k] && m0[k] + P - 1 < lo[k] + ext[k];
     const double qd = (double)pi.w;
-    const double vx = (double)vi.x, vy = (double)vi.y, vz = (double)vi.z;
+    const double vx = (double)vi.x, vy = (double)vi.y, vz = (double)vi.z, wd = (double)vi.w;
     if (inside) {
-      const double qs = qd * scale;
+      const double qs = qd * scale, ws = wd * scale;
       const int b0 = ((m0[2] - lo[2]) * ext[1] + (m0[1] - lo[1])) * ext[0] + (m0[0] - lo[0]);
 #pragma unroll
       for (int c = 0; c < P; ++c) {
 #pragma unroll
         for (int b = 0; b < P; ++b) {
           const double syz = qs * vx * w[1][b] * w[2][c];
-          const double tyz = qs * (vy * dw[1][b] * w[2][c] + vz * w[1][b] * dw[2][c]);
+          const double tyz = (qs * (vy * dw[1][b] * w[2][c] + vz * w[1][b] * dw[2][c])) -
+                             ws * w[1][b] * w[2][c];
           const int row = b0 + (c * ext[1] + b) * ext[0];
 #pragma unroll
           for (int a = 0; a < P; ++a)
@@ -134,7 +150,8 @@ __global__ void __launch_bounds__(256)
         for (int b = 0; b < P; ++b) {
           if (idx[1][b] < 0) continue;
           const double syz = qd * vx * w[1][b] * w[2][c];
-          const double tyz = qd * (vy * dw[1][b] * w[2][c] + vz * w[1][b] * dw[2][c]);
+          const double tyz = (qd * (vy * dw[1][b] * w[2][c] + vz * w[1][b] * dw[2][c])) -
+                             wd * w[1][b] * w[2][c];
           const long long row = ((long long)idx[2][c] * g.n[1] + idx[1][b]) * g.n[0];
 #pragma unroll
           for (int a = 0; a < P; ++a) {
@@ -160,15 +177,16 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Interpolation adjoint with B-spline Hessians, combined with the gE terms
-// and the short-range VJP, scattered to the caller's order.
+// Interpolation adjoint with B-spline Hessians, combined with the gE terms,
+// the phi-cotangent terms and the short-range VJP, scattered to the caller's
+// order.
 template <typename T, int P>
 __global__ void __launch_bounds__(256)
     k_interp_vjp(int n, const vec4_t<T>* __restrict__ sorted, const vec4_t<T>* __restrict__ v,
                  const int* __restrict__ perm, GridDev<T> g, const T* __restrict__ psi,
                  const T* __restrict__ psiD, const T* __restrict__ save_phi,
                  const T* __restrict__ save_F, const T* __restrict__ gq_sr,
-                 const T* __restrict__ gr_sr, const double* __restrict__ gE,
+                 const T* __restrict__ gr_sr, const double* __restrict__ gE, double self_const,
                  T* __restrict__ grad_q, T* __restrict__ grad_pos) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -255,20 +273,21 @@ __global__ void __launch_bounds__(256)
     N001 += Z0 * dwz;
   }
   (void)M000;
-  const T vx = vi.x, vy = vi.y, vz = vi.z, qi = pi.w;
+  const T vx = vi.x, vy = vi.y, vz = vi.z, wi = vi.w, qi = pi.w;
   const T sq = N000 + vx * M100 + vy * M010 + vz * M001;
-  T sx = N100 + vx * M200 + vy * M110 + vz * M101;
-  T sy = N010 + vx * M110 + vy * M020 + vz * M011;
-  T sz = N001 + vx * M101 + vy * M011 + vz * M002;
+  // q_i grad(phi of A S) + q_i Hess(e) v_i - w_i grad(e), all in the grid frame
+  T sx = qi * (N100 + vx * M200 + vy * M110 + vz * M101) - wi * M100;
+  T sy = qi * (N010 + vx * M110 + vy * M020 + vz * M011) - wi * M010;
+  T sz = qi * (N001 + vx * M101 + vy * M011 + vz * M002) - wi * M001;
   // (triclinic: v is in the grid frame; the gradient goes back through H^{-T})
   grid_to_cartesian(g, sx, sy, sz);
   const T ge = gE ? (T)(*gE) : T(0);
   const int o = perm[i];
-  if (grad_q) grad_q[o] = ge * save_phi[i] + gq_sr[i] - sq;
+  if (grad_q) grad_q[o] = ge * save_phi[i] + gq_sr[i] - sq - (T)(self_const * (double)wi);
   if (grad_pos) {
-    grad_pos[3 * o] = -ge * save_F[3 * i] + gr_sr[3 * i] - qi * sx;
-    grad_pos[3 * o + 1] = -ge * save_F[3 * i + 1] + gr_sr[3 * i + 1] - qi * sy;
-    grad_pos[3 * o + 2] = -ge * save_F[3 * i + 2] + gr_sr[3 * i + 2] - qi * sz;
+    grad_pos[3 * o] = -ge * save_F[3 * i] + gr_sr[3 * i] - sx;
+    grad_pos[3 * o + 1] = -ge * save_F[3 * i + 1] + gr_sr[3 * i + 1] - sy;
+    grad_pos[3 * o + 2] = -ge * save_F[3 * i + 2] + gr_sr[3 * i + 2] - sz;
   }
 }
 
@@ -292,10 +311,11 @@ __global__ void k_grad_energy_only(int n, const int* __restrict__ perm,
 
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_gather_v(int n, const int* perm, const T* gF, const GridDev<T>& g, vec4_t<T>* v,
-                     hipStream_t s) {
+void launch_gather_v(int n, const int* perm, const T* gF, const T* gphi, const GridDev<T>& g,
+                     vec4_t<T>* v, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gather_v<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, gF, g, v);
+  hipLaunchKernelGGL(k_gather_v<T>, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, gF, gphi, g,
+                     v);
 }
 
 template <typename T>
@@ -306,7 +326,7 @@ void launch_anterp_dipole(int p, int n, int ncell, const int* start, const CellG
   const BrickGeom bg = brick_geom(p, n, ncell, cg, g.hd);
   const int bc = brick_lds_cap(p, bg, cg, g.hd);
   const size_t lds = (size_t)bc * sizeof(long long);
-  const unsigned nb = (unsigned)bg.nsc[0] * bg.nsc[1] * bg.nsc[2];
+  const unsigned nb = (unsigned)bg.nsc[0] * bg.nsc[1] * bg.nsc[2] * bg.split;
   switch (p) {
     case 4: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 4>), dim3(nb), dim3(256), lds, s, start, sorted, v, g, cg, bg, bc, grid); break;
     case 6: hipLaunchKernelGGL((k_anterp_dipole_brick<T, 6>), dim3(nb), dim3(256), lds, s, start, sorted, v, g, cg, bg, bc, grid); break;
@@ -318,13 +338,13 @@ template <typename T>
 void launch_interp_vjp(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v, const int* perm,
                        const GridDev<T>& g, const T* psi, const T* psiD, const T* save_phi,
                        const T* save_F, const T* gq_sr, const T* gr_sr, const double* gE,
-                       T* grad_q, T* grad_pos, hipStream_t s) {
+                       double self_const, T* grad_q, T* grad_pos, hipStream_t s) {
   if (n <= 0) return;
   const int nb = (n + 255) / 256;
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_interp_vjp<T, 4>), dim3(nb), dim3(256), 0, s, n, sorted, v, perm, g, psi, psiD, save_phi, save_F, gq_sr, gr_sr, gE, grad_q, grad_pos); break;
-    case 6: hipLaunchKernelGGL((k_interp_vjp<T, 6>), dim3(nb), dim3(256), 0, s, n, sorted, v, perm, g, psi, psiD, save_phi, save_F, gq_sr, gr_sr, gE, grad_q, grad_pos); break;
-    case 8: hipLaunchKernelGGL((k_interp_vjp<T, 8>), dim3(nb), dim3(256), 0, s, n, sorted, v, perm, g, psi, psiD, save_phi, save_F, gq_sr, gr_sr, gE, grad_q, grad_pos); break;
+    case 4: hipLaunchKernelGGL((k_interp_vjp<T, 4>), dim3(nb), dim3(256), 0, s, n, sorted, v, perm, g, psi, psiD, save_phi, save_F, gq_sr, gr_sr, gE, self_const, grad_q, grad_pos); break;
+    case 6: hipLaunchKernelGGL((k_interp_vjp<T, 6>), dim3(nb), dim3(256), 0, s, n, sorted, v, perm, g, psi, psiD, save_phi, save_F, gq_sr, gr_sr, gE, self_const, grad_q, grad_pos); break;
+    case 8: hipLaunchKernelGGL((k_interp_vjp<T, 8>), dim3(nb), dim3(256), 0, s, n, sorted, v, perm, g, psi, psiD, save_phi, save_F, gq_sr, gr_sr, gE, self_const, grad_q, grad_pos); break;
   }
 }
 
@@ -337,14 +357,15 @@ void launch_grad_energy_only(int n, const int* perm, const T* save_phi, const T*
 }
 
 #define MSM_INST_BACKWARD(T)                                                                      \
-  template void launch_gather_v<T>(int, const int*, const T*, const GridDev<T>&, vec4_t<T>*,      \
-                                   hipStream_t);                                                   \
+  template void launch_gather_v<T>(int, const int*, const T*, const T*, const GridDev<T>&,        \
+                                   vec4_t<T>*, hipStream_t);                                       \
   template void launch_anterp_dipole<T>(int, int, int, const int*, const CellGrid&,                \
                                         const vec4_t<T>*, const vec4_t<T>*, const GridDev<T>&, T*,  \
                                         hipStream_t);                                             \
   template void launch_interp_vjp<T>(int, int, const vec4_t<T>*, const vec4_t<T>*, const int*,    \
                                      const GridDev<T>&, const T*, const T*, const T*, const T*,   \
-                                     const T*, const T*, const double*, T*, T*, hipStream_t);     \
+                                     const T*, const T*, const double*, double, T*, T*,           \
+                                     hipStream_t);                                                 \
   template void launch_grad_energy_only<T>(int, const int*, const T*, const T*, const double*,    \
                                            T*, T*, hipStream_t);
 MSM_INST_BACKWARD(float)

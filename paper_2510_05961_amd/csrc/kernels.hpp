@@ -37,6 +37,8 @@ struct PairParams {
   // columns)
   int tri;
   T H[9];
+  // how far a charge may lie outside its cell (half the Verlet skin)
+  T margin;
 };
 
 // One stencil convolution e_o = sum_d K_d q_{o+shift-d} (a5, a6).
@@ -106,11 +108,28 @@ void launch_zero_multi(const ZeroJobs& jobs, hipStream_t s);
 // be scanned by many workgroups.
 constexpr int kCountCopies = 8;
 int scan_tmp_ints(int ncell);
+// Verlet-skin state of a plan (device): ints [force, rebuild, calls,
+// rebuilds], each charge's position at the last rebuild and its wrap
+// (position minus wrapped position) in the caller's order; half2 = (skin/2)^2.
+// state == null: no skin, every call rebuilds.
+constexpr int kSkinForce = 0, kSkinRebuild = 1, kSkinCalls = 2, kSkinRebuilds = 3;
+template <typename T>
+struct SkinDev {
+  int* state;
+  vec4_t<T>* ref;
+  vec4_t<T>* shift;
+  T half2;
+  int keep_force;  // this call's rebuild leaves force set (its list goes to a workspace)
+};
+// With a skin the binning first decides (on the device) whether this call
+// rebuilds: force != 0, a pending forced rebuild, or a charge that moved
+// more than skin/2; without a rebuild the binning kernels return at once
+// and the cell-ordered list is refreshed instead.
 template <typename T>
 void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
                     int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
                     int* cl_start, vec4_t<T>* sorted, int* perm, int* flag, int* scan_tmp,
-                    const ZeroJobs& zero, hipStream_t s);
+                    const ZeroJobs& zero, const SkinDev<T>& sk, int force, hipStream_t s);
 // Cluster layout of the cell-sorted particles (sort != 0: also reorders each
 // cell along a Morton curve, in place) and the short-range pair sum (an
 // i-cluster against the j particles within the cutoff of its box).  Buffers hold
@@ -121,11 +140,13 @@ void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int
 int cluster_capacity(int n, int ncell);
 constexpr int kGroupSize = 4;  // particles per j-group
 // scan != 0: compute cl_start from start here (else it is already there)
+// skin != null (a SkinState): on a call without rebuild only the cluster
+// slots and j-group boxes are refreshed from the cell-ordered list
 template <typename T>
 void launch_cluster_layout(int sort, int scan, int ncell, const int* start, int* cl_start,
                            const BinParams<T>& bp, const vec4_t<T>* wrapped, vec4_t<T>* sorted,
                            int* perm, vec4_t<T>* cpos, vec4_t<T>* cbox, int4* cinfo,
-                           int* counts, hipStream_t s);
+                           int* counts, const int* skin, int n, hipStream_t s);
 template <typename T>
 void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
                     const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
@@ -134,6 +155,9 @@ void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T
 struct CellGrid {
   int nc[3];
   double cs[3];
+  // how far a charge may lie outside its cell (half a Verlet skin: the
+  // tiled anterpolation, which finds charges by their cells, is then off)
+  double margin = 0.0;
 };
 // Cells of one anterpolation brick: kc^3 cells of the cell list (a
 // super-cell), nsc super-cells per axis.  Sparse cells share a brick so
@@ -141,6 +165,7 @@ struct CellGrid {
 struct BrickGeom {
   int kc;
   int nsc[3];
+  int split;  // workgroups per brick, each over a share of its charges
 };
 constexpr int kBrickMaxCells = 8;  // kc limit (kc^2 runs of cells per brick)
 // kc for a call with n charges: BrickGeom of the cell grid (MSM_BRICK_CELLS=k
@@ -195,11 +220,12 @@ void launch_cast(const double* src, T* dst, long long count, hipStream_t s);
 // backward (vector-Jacobian product)
 // (g.tri: the cotangent in the grid frame, H^{-1} v)
 template <typename T>
-void launch_gather_v(int n, const int* perm, const T* gF, const GridDev<T>& g, vec4_t<T>* v,
-                     hipStream_t s);
+void launch_gather_v(int n, const int* perm, const T* gF, const T* gphi, const GridDev<T>& g,
+                     vec4_t<T>* v, hipStream_t s);
 template <typename T>
 void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4* cinfo,
-                        const int* perm, const T* gF, const vec4_t<T>* cpos, vec4_t<T>* cv,
+                        const int* perm, const T* gF, const T* gphi, const vec4_t<T>* cpos,
+                        vec4_t<T>* cv,
                         const vec4_t<T>* cbox, const PairParams<T>& pp, int null_h, T* gq,
                         T* gr, hipStream_t s);
 template <typename T>
@@ -210,7 +236,7 @@ template <typename T>
 void launch_interp_vjp(int p, int n, const vec4_t<T>* sorted, const vec4_t<T>* v, const int* perm,
                        const GridDev<T>& g, const T* psi, const T* psiD, const T* save_phi,
                        const T* save_F, const T* gq_sr, const T* gr_sr, const double* gE,
-                       T* grad_q, T* grad_pos, hipStream_t s);
+                       double self_const, T* grad_q, T* grad_pos, hipStream_t s);
 template <typename T>
 void launch_grad_energy_only(int n, const int* perm, const T* save_phi, const T* save_F,
                              const double* gE, T* grad_q, T* grad_pos, hipStream_t s);

@@ -86,8 +86,10 @@ __global__ void __launch_bounds__(kPrepThreads)
                    BinParams<T> bp, const vec4_t<T>* __restrict__ wrapped,
                    vec4_t<T>* __restrict__ sorted, int* __restrict__ perm,
                    vec4_t<T>* __restrict__ cpos, vec4_t<T>* __restrict__ cbox,
-                   int4* __restrict__ cinfo, int* __restrict__ counts) {
+                   int4* __restrict__ cinfo, int* __restrict__ counts,
+                   const int* __restrict__ gate) {
   __shared__ unsigned long long key[kPrepSortMax];
+  if (gate && !gate[kSkinRebuild]) return;  // (Verlet skin: the layout is kept)
   const int cell = blockIdx.x;
   const int t = threadIdx.x;
   // the binning's counters of this cell (read by the scatter, which ran
@@ -332,10 +334,12 @@ __device__ inline void for_each_group_block(const PairParams<T>& pp, const int* 
         // i-box moved by minus the shift of the j image
         const T ilx = blo.x - sx, ily = blo.y - sy, ilz = blo.z - sz;
         const T ihx = bhi.x - sx, ihy = bhi.y - sy, ihz = bhi.z - sz;
-        // whole-cell test with a margin for the rounding of the binning (the
+        // whole-cell test with a margin for the rounding of the binning and
+        // for charges that moved out of their cell under a Verlet skin (the
         // cells of a triclinic cell are not boxes: skipped there)
         if (!pp.tri) {
-          const T mx = pp.cs[0] * T(1e-3), my = pp.cs[1] * T(1e-3), mz = pp.cs[2] * T(1e-3);
+          const T mx = pp.cs[0] * T(1e-3) + pp.margin, my = pp.cs[1] * T(1e-3) + pp.margin,
+                  mz = pp.cs[2] * T(1e-3) + pp.margin;
           const T g2 = box_gap2<T>((T)nx * pp.cs[0] - mx, (T)ny * pp.cs[1] - my,
                                    (T)nz * pp.cs[2] - mz, (T)(nx + 1) * pp.cs[0] + mx,
                                    (T)(ny + 1) * pp.cs[1] + my, (T)(nz + 1) * pp.cs[2] + mz,
@@ -426,8 +430,9 @@ __device__ inline void for_each_j_culled(const PairParams<T>& pp, const int* cl_
         // i-box moved by minus the shift of the j image
         const T ilx = blo.x - sx, ily = blo.y - sy, ilz = blo.z - sz;
         const T ihx = bhi.x - sx, ihy = bhi.y - sy, ihz = bhi.z - sz;
-        if (!pp.tri) {  // whole-cell test with a margin for the rounding of the binning
-          const T mx = pp.cs[0] * T(1e-3), my = pp.cs[1] * T(1e-3), mz = pp.cs[2] * T(1e-3);
+        if (!pp.tri) {  // whole-cell test, margins as in for_each_group_block
+          const T mx = pp.cs[0] * T(1e-3) + pp.margin, my = pp.cs[1] * T(1e-3) + pp.margin,
+                  mz = pp.cs[2] * T(1e-3) + pp.margin;
           const T g2 = box_gap2<T>((T)nx * pp.cs[0] - mx, (T)ny * pp.cs[1] - my,
                                    (T)nz * pp.cs[2] - mz, (T)(nx + 1) * pp.cs[0] + mx,
                                    (T)(ny + 1) * pp.cs[1] + my, (T)(nz + 1) * pp.cs[2] + mz,
@@ -566,11 +571,13 @@ __global__ void __launch_bounds__(kClusterThreads)
   }
 }
 
-// Cotangent of the forces in cluster-slot order (zero in padding slots).
+// Cotangents in cluster-slot order (zero in padding slots): the force
+// cotangent in x, y, z, the cotangent of phi in w (each zero without one).
 template <typename T>
 __global__ void k_gather_v_cl(int nslot_max, const int* __restrict__ cl_start, int ncell,
                               const int4* __restrict__ cinfo, const int* __restrict__ perm,
-                              const T* __restrict__ gF, vec4_t<T>* __restrict__ cv) {
+                              const T* __restrict__ gF, const T* __restrict__ gphi,
+                              vec4_t<T>* __restrict__ cv) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nslot_max || s >= 8 * cl_start[ncell]) return;
   const int4 inf = cinfo[s >> 3];
@@ -579,9 +586,12 @@ __global__ void k_gather_v_cl(int nslot_max, const int* __restrict__ cl_start, i
   v.x = v.y = v.z = v.w = T(0);
   if (r < inf.y) {
     const int u = perm[inf.x + r];
-    v.x = gF[3 * (size_t)u];
-    v.y = gF[3 * (size_t)u + 1];
-    v.z = gF[3 * (size_t)u + 2];
+    if (gF) {
+      v.x = gF[3 * (size_t)u];
+      v.y = gF[3 * (size_t)u + 1];
+      v.z = gF[3 * (size_t)u + 2];
+    }
+    if (gphi) v.w = gphi[u];
   }
   cv[s] = v;
 }
@@ -589,8 +599,11 @@ __global__ void k_gather_v_cl(int nslot_max, const int* __restrict__ cl_start, i
 // VJP of the short-range part for a force cotangent v (eq. U_zero):
 //   d/dq_i  sum_k v_k . F0_k   = sum_j q_j f(r) (v_i - v_j) . d_ij
 //   d/dr_i  sum_k v_k . F0_k   = q_i sum_j q_j [f (v_i - v_j) + (f'/r) ((v_i - v_j) . d) d]
-// with f = 1/r^3 + 2 P'(t)/a^3 and f'/r = -3/r^5 + 4 P''(t)/a^5.
-template <typename T, int P>
+// with f = 1/r^3 + 2 P'(t)/a^3 and f'/r = -3/r^5 + 4 P''(t)/a^5; and, with
+// W, for a cotangent w of the short-range potential phi0:
+//   d/dq_i  sum_k w_k phi0_k   = sum_j w_j k0(r)
+//   d/dr_i  sum_k w_k phi0_k   = -q_i sum_j w_j f d_ij - w_i sum_j q_j f d_ij.
+template <typename T, int P, bool W>
 __global__ void __launch_bounds__(kClusterThreads)
     k_pair_vjp_cl(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
                   const vec4_t<T>* __restrict__ cv, const vec4_t<T>* __restrict__ cbox,
@@ -608,8 +621,10 @@ __global__ void __launch_bounds__(kClusterThreads)
   vec4_t<T> blo, bhi;
   cluster_box<T>(cbox, ic, inf.y, blo, bhi);
   const T f_top = in_vgpr(pp.fr[P - 2]), g_top = in_vgpr(pp.gr[P - 3]);
+  const T e_top = in_vgpr(pp.er[P - 1]);
   const T a2v = in_vgpr(pp.a2);
   T sq = T(0), rx = T(0), ry = T(0), rz = T(0);
+  T bx = T(0), by = T(0), bz = T(0);  // sum_j q_j f d_ij (W only)
   for_each_group_block<T>(
       pp, cl_start, cbox, ic, inf.z, blo, bhi, lists[threadIdx.x >> 6], null_h,
       [&](int h) { return JData<T>{group_member<T>(cpos, h, jl), group_member<T>(cv, h, jl)}; },
@@ -638,33 +653,88 @@ __global__ void __launch_bounds__(kClusterThreads)
         rx += qf * wx + c2 * dx;
         ry += qf * wy + c2 * dy;
         rz += qf * wz + c2 * dz;
+        if constexpr (W) {
+          const T wj = ok ? vj.w : T(0);
+          T pe = e_top;
+#pragma unroll
+          for (int k = P - 2; k >= 0; --k) pe = pe * r2c + pp.er[k];
+          sq += wj * (rinv - pe);
+          const T wf = wj * f;
+          rx -= wf * dx;
+          ry -= wf * dy;
+          rz -= wf * dz;
+          bx += qf * dx;
+          by += qf * dy;
+          bz += qf * dz;
+        }
       },
       []() {});
   sq = sum_i(sq);
   rx = sum_i(rx);
   ry = sum_i(ry);
   rz = sum_i(rz);
+  if constexpr (W) {
+    bx = sum_i(bx);
+    by = sum_i(by);
+    bz = sum_i(bz);
+  }
   if ((lane & ~0x1C) == 0 && il < inf.y) {  // slot 0, jl 0
     const int i = inf.x + il;
     gq[i] = sq;
-    gr[3 * (size_t)i] = pi.w * rx;
-    gr[3 * (size_t)i + 1] = pi.w * ry;
-    gr[3 * (size_t)i + 2] = pi.w * rz;
+    gr[3 * (size_t)i] = pi.w * rx - vi.w * bx;
+    gr[3 * (size_t)i + 1] = pi.w * ry - vi.w * by;
+    gr[3 * (size_t)i + 2] = pi.w * rz - vi.w * bz;
   }
 }
+
+// Verlet skin, a call without rebuild: the cluster slots and j-group boxes
+// of the kept layout from the refreshed cell-ordered list (one thread per
+// j-group; padding slots and empty groups keep their far-away values).
+template <typename T>
+__global__ void k_cluster_refresh(int ngroup_max, const int* __restrict__ cl_start, int ncell,
+                                  const int4* __restrict__ cinfo,
+                                  const vec4_t<T>* __restrict__ sorted,
+                                  vec4_t<T>* __restrict__ cpos, vec4_t<T>* __restrict__ cbox,
+                                  const int* __restrict__ gate) {
+  if (gate[kSkinRebuild]) return;
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= ngroup_max || h >= 2 * cl_start[ncell]) return;
+  const int4 inf = cinfo[h >> 1];
+  const int r0 = (h & 1) * kGroup, m = min(kGroup, inf.y - r0);
+  if (m <= 0) return;
+  vec4_t<T> lo = sorted[inf.x + r0], hi = lo;
+  cpos[(size_t)kGroup * h] = lo;
+  for (int r = 1; r < m; ++r) {
+    const vec4_t<T> v = sorted[inf.x + r0 + r];
+    cpos[(size_t)kGroup * h + r] = v;
+    lo.x = min(lo.x, v.x);
+    lo.y = min(lo.y, v.y);
+    lo.z = min(lo.z, v.z);
+    hi.x = max(hi.x, v.x);
+    hi.y = max(hi.y, v.y);
+    hi.z = max(hi.z, v.z);
+  }
+  cbox[2 * (size_t)h] = lo;
+  cbox[2 * (size_t)h + 1] = hi;
+}
+
+int cluster_capacity(int n, int ncell) { return n / 8 + ncell + 1; }
 
 template <typename T>
 void launch_cluster_layout(int sort, int scan, int ncell, const int* start, int* cl_start,
                            const BinParams<T>& bp, const vec4_t<T>* wrapped, vec4_t<T>* sorted,
                            int* perm, vec4_t<T>* cpos, vec4_t<T>* cbox, int4* cinfo,
-                           int* counts, hipStream_t s) {
+                           int* counts, const int* skin, int n, hipStream_t s) {
   if (ncell <= 0) return;
   if (scan) hipLaunchKernelGGL(k_cluster_scan, dim3(1), dim3(1024), 0, s, ncell, start, cl_start);
   hipLaunchKernelGGL(k_cluster_prep<T>, dim3(ncell), dim3(kPrepThreads), 0, s, sort, start,
-                     cl_start, bp, wrapped, sorted, perm, cpos, cbox, cinfo, counts);
+                     cl_start, bp, wrapped, sorted, perm, cpos, cbox, cinfo, counts, skin);
+  if (skin && n > 0) {
+    const int ng = 2 * cluster_capacity(n, ncell);
+    hipLaunchKernelGGL(k_cluster_refresh<T>, dim3((ng + 255) / 256), dim3(256), 0, s, ng,
+                       cl_start, ncell, cinfo, sorted, cpos, cbox, skin);
+  }
 }
-
-int cluster_capacity(int n, int ncell) { return n / 8 + ncell + 1; }
 
 template <typename T>
 void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
@@ -680,32 +750,43 @@ void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T
   }
 }
 
+template <typename T, bool W>
+void launch_pair_vjp_p(int p, dim3 grid, const int* cl_start, const vec4_t<T>* cpos,
+                       const vec4_t<T>* cv, const vec4_t<T>* cbox, const int4* cinfo,
+                       const PairParams<T>& pp, int nh, T* gq, T* gr, hipStream_t s) {
+  const dim3 block(kClusterThreads);
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_pair_vjp_cl<T, 4, W>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
+    case 6: hipLaunchKernelGGL((k_pair_vjp_cl<T, 6, W>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
+    case 8: hipLaunchKernelGGL((k_pair_vjp_cl<T, 8, W>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
+  }
+}
+
 template <typename T>
 void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4* cinfo,
-                        const int* perm, const T* gF, const vec4_t<T>* cpos, vec4_t<T>* cv,
-                        const vec4_t<T>* cbox, const PairParams<T>& pp, int nh, T* gq, T* gr,
-                        hipStream_t s) {
+                        const int* perm, const T* gF, const T* gphi, const vec4_t<T>* cpos,
+                        vec4_t<T>* cv, const vec4_t<T>* cbox, const PairParams<T>& pp, int nh,
+                        T* gq, T* gr, hipStream_t s) {
   if (n <= 0) return;
   const int ncl = cluster_capacity(n, ncell);
   hipLaunchKernelGGL(k_gather_v_cl<T>, dim3((8 * ncl + 255) / 256), dim3(256), 0, s, 8 * ncl,
-                     cl_start, ncell, cinfo, perm, gF, cv);
-  const dim3 grid((ncl + 3) / 4), block(kClusterThreads);
-  switch (p) {
-    case 4: hipLaunchKernelGGL((k_pair_vjp_cl<T, 4>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
-    case 6: hipLaunchKernelGGL((k_pair_vjp_cl<T, 6>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
-    case 8: hipLaunchKernelGGL((k_pair_vjp_cl<T, 8>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
-  }
+                     cl_start, ncell, cinfo, perm, gF, gphi, cv);
+  const dim3 grid((ncl + 3) / 4);
+  if (gphi)
+    launch_pair_vjp_p<T, true>(p, grid, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr, s);
+  else
+    launch_pair_vjp_p<T, false>(p, grid, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr, s);
 }
 
 #define MSM_INST_CLUSTER(T)                                                                    \
   template void launch_cluster_layout<T>(int, int, int, const int*, int*, const BinParams<T>&, \
                                          const vec4_t<T>*, vec4_t<T>*, int*, vec4_t<T>*,       \
-                                         vec4_t<T>*, int4*, int*, hipStream_t);                \
+                                         vec4_t<T>*, int4*, int*, const int*, int, hipStream_t); \
   template void launch_pair_cl<T>(int, int, int, const int*, const vec4_t<T>*,                 \
                                   const vec4_t<T>*, const int4*, const PairParams<T>&,         \
                                   double*, T*, hipStream_t);                                   \
   template void launch_pair_vjp_cl<T>(int, int, int, const int*, const int4*, const int*,      \
-                                      const T*, const vec4_t<T>*, vec4_t<T>*,                  \
+                                      const T*, const T*, const vec4_t<T>*, vec4_t<T>*,        \
                                       const vec4_t<T>*, const PairParams<T>&, int, T*, T*,     \
                                       hipStream_t);
 MSM_INST_CLUSTER(float)

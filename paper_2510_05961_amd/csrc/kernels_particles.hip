@@ -11,16 +11,108 @@
 namespace msm {
 
 // ---------------------------------------------------------------------------
+// Verlet skin.  The cell list (cell edge >= a + skin) is rebuilt only when
+// some charge has moved more than skin/2 since the last rebuild: a pair
+// within the cutoff then still lies in neighbouring cells of that cell list,
+// so only the positions in it are refreshed.  Every kernel is launched on
+// every call and reads the decision from device memory (a graph of the
+// call replays unchanged).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void skin_keep(const SkinDev<T>& sk, int i, const T (&raw)[3],
+                                 const vec4_t<T>& w) {
+  vec4_t<T> r, d;
+  r.x = raw[0];
+  r.y = raw[1];
+  r.z = raw[2];
+  r.w = T(0);
+  d.x = raw[0] - w.x;
+  d.y = raw[1] - w.y;
+  d.z = raw[2] - w.z;
+  d.w = T(0);
+  sk.ref[i] = r;
+  sk.shift[i] = d;
+}
+
+// rebuild = force (a new n, a call with a workspace, a new cell or skin)
+__global__ void k_skin_begin(int* __restrict__ state, int force) {
+  if (threadIdx.x == 0) {
+    if (force) state[kSkinForce] = 1;
+    state[kSkinRebuild] = state[kSkinForce];
+    state[kSkinCalls] += 1;
+  }
+}
+
+// ... or any displacement beyond skin/2 (non-finite ones included)
+template <typename T>
+__global__ void k_skin_check(int n, const T* __restrict__ pos, SkinDev<T> sk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool far = false;
+  if (i < n) {
+    const vec4_t<T> r = sk.ref[i];
+    const T dx = pos[3 * i] - r.x, dy = pos[3 * i + 1] - r.y, dz = pos[3 * i + 2] - r.z;
+    far = !(dx * dx + dy * dy + dz * dz <= sk.half2);
+  }
+  if (__ballot(far) != 0 && (threadIdx.x & 63) == 0) atomicOr(&sk.state[kSkinRebuild], 1);
+}
+
+// No rebuild: the cell-ordered list gets the new positions, moved by each
+// charge's wrap of the last rebuild (continuous across periodic faces, so
+// the cell list and its image shifts stay valid), and the new charges.
+template <typename T>
+__global__ void k_skin_refresh(int n, const T* __restrict__ pos, const T* __restrict__ q,
+                               const int* __restrict__ perm, BinParams<T> bp, SkinDev<T> sk,
+                               vec4_t<T>* __restrict__ sorted, int* __restrict__ flag) {
+  if (sk.state[kSkinRebuild]) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int o = perm[i];
+  const vec4_t<T> d = sk.shift[o];
+  T x[3] = {pos[3 * o] - d.x, pos[3 * o + 1] - d.y, pos[3 * o + 2] - d.z};
+  T qi = q[o];
+  int bad = 0;
+  if (!isfinite(qi)) {
+    bad |= kFlagNonfinite;
+    qi = T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (!bp.tri && !bp.per[k] && (x[k] < T(0) || x[k] > bp.box[k])) {
+      bad |= kFlagDomain;
+      x[k] = x[k] < T(0) ? T(0) : bp.box[k];
+    }
+  if (bad) atomicOr(flag, bad);
+  vec4_t<T> w;
+  w.x = x[0];
+  w.y = x[1];
+  w.z = x[2];
+  w.w = qi;
+  sorted[i] = w;
+}
+
+// ---------------------------------------------------------------------------
 // a1: binning.  Periodic coordinates are wrapped into [0, box); free ones are
 // checked against [0, box] (flag + clamp, so every later index stays in
 // bounds); non-finite values are flagged and replaced by 0.
 // ---------------------------------------------------------------------------
+//
+// With a Verlet skin (sk != null, the plan's SkinState) the binning kernels
+// run only on calls that rebuild the cell list; the count kernel then also
+// keeps each caller's position and its wrap (raw minus wrapped) for the
+// refresh of later calls, and marks the rebuild as done.
 template <typename T>
 __global__ void k_bin_count(int n, const T* __restrict__ pos, const T* __restrict__ q,
                             BinParams<T> bp, int* __restrict__ cell_of, int* __restrict__ rank,
                             int* __restrict__ counts, vec4_t<T>* __restrict__ wrapped,
-                            int* __restrict__ flag) {
+                            int* __restrict__ flag, SkinDev<T> sk) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sk.state) {
+    if (!sk.state[kSkinRebuild]) return;
+    if (i == 0) {
+      sk.state[kSkinForce] = sk.keep_force;
+      sk.state[kSkinRebuilds] += 1;
+    }
+  }
   if (i >= n) return;
   T x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
   T qi = q[i];
@@ -66,6 +158,10 @@ __global__ void k_bin_count(int n, const T* __restrict__ pos, const T* __restric
     cell_of[i] = slot;
     rank[i] = atomicAdd(&counts[slot], 1);
     wrapped[i] = w;
+    if (sk.state) {
+      const T raw[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+      skin_keep(sk, i, raw, w);
+    }
     return;
   }
   int c[3];
@@ -95,6 +191,10 @@ __global__ void k_bin_count(int n, const T* __restrict__ pos, const T* __restric
   w.z = x[2];
   w.w = qi;
   wrapped[i] = w;
+  if (sk.state) {
+    const T raw[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    skin_keep(sk, i, raw, w);
+  }
 }
 
 // Exclusive scans of the cell counts into start[0..ncell] and of the
@@ -144,7 +244,9 @@ __device__ inline void cell_store(int cell, int o, int co, int* counts, int* sta
 
 __global__ void __launch_bounds__(1024) k_scan(int ncell, int* __restrict__ counts,
                                                int* __restrict__ start,
-                                               int* __restrict__ cl_start) {
+                                               int* __restrict__ cl_start,
+                                               const int* __restrict__ gate) {
+  if (gate && !gate[kSkinRebuild]) return;
   __shared__ int buf[1024], cbuf[1024];
   int carry = 0, ccarry = 0;  // the same in every thread
   for (int base = 0; base < ncell; base += 1024) {
@@ -168,7 +270,9 @@ __global__ void __launch_bounds__(1024) k_scan(int ncell, int* __restrict__ coun
 // (block totals; their exclusive scan in one workgroup; the blocks' own
 // scans plus their offsets).  tmp holds 2 ints per block.
 __global__ void __launch_bounds__(1024) k_scan_totals(int ncell, const int* __restrict__ counts,
-                                                      int* __restrict__ tmp) {
+                                                      int* __restrict__ tmp,
+                                                      const int* __restrict__ gate) {
+  if (gate && !gate[kSkinRebuild]) return;
   __shared__ int buf[1024], cbuf[1024];
   const int cell = blockIdx.x * 1024 + threadIdx.x;
   int sub[kCountCopies];
@@ -180,7 +284,9 @@ __global__ void __launch_bounds__(1024) k_scan_totals(int ncell, const int* __re
   }
 }
 
-__global__ void __launch_bounds__(1024) k_scan_offsets(int nblk, int* __restrict__ tmp) {
+__global__ void __launch_bounds__(1024) k_scan_offsets(int nblk, int* __restrict__ tmp,
+                                                       const int* __restrict__ gate) {
+  if (gate && !gate[kSkinRebuild]) return;
   __shared__ int buf[1024], cbuf[1024];
   int carry = 0, ccarry = 0;
   for (int base = 0; base < nblk; base += 1024) {
@@ -202,7 +308,9 @@ __global__ void __launch_bounds__(1024) k_scan_offsets(int nblk, int* __restrict
 __global__ void __launch_bounds__(1024) k_scan_apply(int ncell, int* __restrict__ counts,
                                                      int* __restrict__ start,
                                                      int* __restrict__ cl_start,
-                                                     const int* __restrict__ tmp) {
+                                                     const int* __restrict__ tmp,
+                                                     const int* __restrict__ gate) {
+  if (gate && !gate[kSkinRebuild]) return;
   __shared__ int buf[1024], cbuf[1024];
   const int cell = blockIdx.x * 1024 + threadIdx.x;
   int sub[kCountCopies];
@@ -246,14 +354,14 @@ __global__ void k_bin_scatter(int n, const int* __restrict__ cell_of, const int*
                               const int* __restrict__ slot_base,
                               const vec4_t<T>* __restrict__ wrapped,
                               vec4_t<T>* __restrict__ sorted, int* __restrict__ perm,
-                              ZeroJobs zero) {
+                              ZeroJobs zero, const int* __restrict__ gate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (int j = 0; j < zero.n; ++j) {
     unsigned* p = reinterpret_cast<unsigned*>(zero.ptr[j]);
     for (long long k = i; k < zero.words[j]; k += stride) p[k] = 0u;
   }
-  if (i >= n) return;
+  if (i >= n || (gate && !gate[kSkinRebuild])) return;
   const int dst = slot_base[cell_of[i]] + rank[i];
   sorted[dst] = wrapped[i];
   perm[dst] = i;
@@ -284,8 +392,11 @@ __global__ void __launch_bounds__(256)
   __shared__ double qsum[4];
   __shared__ BrickRuns runs;
   int c0[3], c1[3], nruns;
-  const int count = brick_runs(blockIdx.x, start, cg, bg, c0, c1, runs, nruns);
-  if (count == 0) return;
+  // brick blockIdx.x / split; this workgroup takes every split-th block of
+  // 256 of its charges
+  const int part = blockIdx.x % bg.split, stride = blockDim.x * bg.split;
+  const int count = brick_runs(blockIdx.x / bg.split, start, cg, bg, c0, c1, runs, nruns);
+  if (count <= part * (int)blockDim.x) return;
   int lo[3], ext[3];
   const int vol = brick_box<P>(c0, c1, cg, g.hd, lo, ext);
   const bool staged = vol <= brick_cap;
@@ -293,7 +404,7 @@ __global__ void __launch_bounds__(256)
   if (staged) {
     for (int b = threadIdx.x; b < vol; b += blockDim.x) brick[b] = 0;
     double aq = 0.0;
-    for (int j = threadIdx.x; j < count; j += blockDim.x)
+    for (int j = part * blockDim.x + threadIdx.x; j < count; j += stride)
       aq += fabs((double)sorted[brick_particle(runs, nruns, j)].w);
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) aq += __shfl_xor(aq, o);
@@ -303,7 +414,7 @@ __global__ void __launch_bounds__(256)
     (void)frexp(qsum[0] + qsum[1] + qsum[2] + qsum[3], &ex);  // total < 2^ex
     scale = ldexp(1.0, 62 - max(ex, -900));  // stays a finite power of two
   }
-  for (int jp = threadIdx.x; jp < count; jp += blockDim.x) {
+  for (int jp = part * blockDim.x + threadIdx.x; jp < count; jp += stride) {
     const vec4_t<T> pi = sorted[brick_particle(runs, nruns, jp)];
     double xs[3] = {(double)pi.x, (double)pi.y, (double)pi.z};
     grid_frame(g, xs);
@@ -483,25 +594,33 @@ template <typename T>
 void launch_binning(int n, const T* pos, const T* q, const BinParams<T>& bp, int ncell,
                     int* cell_of, int* rank, int* counts, vec4_t<T>* wrapped, int* start,
                     int* cl_start, vec4_t<T>* sorted, int* perm, int* flag, int* scan_tmp,
-                    const ZeroJobs& zero, hipStream_t s) {
+                    const ZeroJobs& zero, const SkinDev<T>& sk, int force, hipStream_t s) {
   const int nb = (n + 255) / 256;
+  const int* gate = sk.state;
+  if (sk.state) {
+    hipLaunchKernelGGL(k_skin_begin, dim3(1), dim3(64), 0, s, sk.state, force);
+    if (n > 0) hipLaunchKernelGGL(k_skin_check<T>, dim3(nb), dim3(256), 0, s, n, pos, sk);
+  }
   if (n > 0)
     hipLaunchKernelGGL(k_bin_count<T>, dim3(nb), dim3(256), 0, s, n, pos, q, bp, cell_of, rank,
-                       counts, wrapped, flag);
+                       counts, wrapped, flag, sk);
   if (ncell <= kScanOneBlock || !scan_tmp) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ncell, counts, start, cl_start);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ncell, counts, start, cl_start, gate);
   } else {
     const int nblk = (ncell + 1023) / 1024;
-    hipLaunchKernelGGL(k_scan_totals, dim3(nblk), dim3(1024), 0, s, ncell, counts, scan_tmp);
-    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, s, nblk, scan_tmp);
+    hipLaunchKernelGGL(k_scan_totals, dim3(nblk), dim3(1024), 0, s, ncell, counts, scan_tmp, gate);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, s, nblk, scan_tmp, gate);
     hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(1024), 0, s, ncell, counts, start, cl_start,
-                       scan_tmp);
+                       scan_tmp, gate);
   }
   if (n > 0)
     hipLaunchKernelGGL(k_bin_scatter<T>, dim3(nb), dim3(256), 0, s, n, cell_of, rank, counts,
-                       wrapped, sorted, perm, zero);
+                       wrapped, sorted, perm, zero, gate);
   else
     launch_zero_multi(zero, s);
+  if (sk.state && n > 0)
+    hipLaunchKernelGGL(k_skin_refresh<T>, dim3(nb), dim3(256), 0, s, n, pos, q, perm, bp, sk,
+                       sorted, flag);
 }
 
 // Large level-1 grids: one workgroup owns a tile of kTileX x kTileY x kTileZ
@@ -662,7 +781,7 @@ __global__ void __launch_bounds__(256)
 // so the caller need not clear the grid first.
 bool anterp_tiled(int p, int n, const CellGrid& cg, const int gn[3], const int gper[3],
                   const double hd[3]) {
-  if (n <= 0) return false;
+  if (n <= 0 || cg.margin > 0) return false;
   // measured on periodic 128^3-512^3 grids: tiles win where charges are
   // sparse (0.075 per grid point: 1.6 against 3.5 ms), bricks where they are
   // dense (0.45 per point: 5.1 against 6.5 ms; 0.6: 0.96 against 1.13 ms),
@@ -726,6 +845,16 @@ BrickGeom brick_geom(int p, int n, int ncell, const CellGrid& cg, const double h
   BrickGeom bg;
   bg.kc = kc;
   for (int k = 0; k < 3; ++k) bg.nsc[k] = (cg.nc[k] + kc - 1) / kc;
+  // few bricks (a small box, or cells of several cutoffs' worth of charges):
+  // split each brick's charges over several workgroups, each with a brick
+  // of its own, so that the launch still spreads over the chip; at least
+  // kMinShare charges per workgroup keep the extra clears and flushes small
+  constexpr long long kSplitBelow = 512, kMinShare = 128;
+  const long long nb = bricks(kc);
+  bg.split = 1;
+  if (nb < kSplitBelow)
+    bg.split = (int)std::max<long long>(
+        1, std::min<long long>((kSplitBelow + nb - 1) / nb, (long long)n / (nb * kMinShare)));
   return bg;
 }
 
@@ -754,7 +883,7 @@ void launch_anterp(int p, int n, int ncell, const int* start, const CellGrid& cg
   const BrickGeom bg = brick_geom(p, n, ncell, cg, g.hd);
   const int bc = brick_lds_cap(p, bg, cg, g.hd);
   const size_t lds = (size_t)bc * sizeof(long long);
-  const unsigned nb = (unsigned)bg.nsc[0] * bg.nsc[1] * bg.nsc[2];
+  const unsigned nb = (unsigned)bg.nsc[0] * bg.nsc[1] * bg.nsc[2] * bg.split;
   switch (p) {
     case 4: hipLaunchKernelGGL((k_anterp_brick<T, 4>), dim3(nb), dim3(256), lds, s, start, sorted, g, cg, bg, bc, grid); break;
     case 6: hipLaunchKernelGGL((k_anterp_brick<T, 6>), dim3(nb), dim3(256), lds, s, start, sorted, g, cg, bg, bc, grid); break;
@@ -778,7 +907,7 @@ void launch_interp(int p, int n, const vec4_t<T>* sorted, const int* perm, const
 #define MSM_INST_PARTICLES(T)                                                                    \
   template void launch_binning<T>(int, const T*, const T*, const BinParams<T>&, int, int*, int*, \
                                   int*, vec4_t<T>*, int*, int*, vec4_t<T>*, int*, int*, int*,   \
-                                  const ZeroJobs&, hipStream_t);                                \
+                                  const ZeroJobs&, const SkinDev<T>&, int, hipStream_t);        \
   template void launch_anterp<T>(int, int, int, const int*, const CellGrid&, const vec4_t<T>*,   \
                                  const GridDev<T>&, T*, hipStream_t);                             \
   template void launch_interp<T>(int, int, const vec4_t<T>*, const int*, const GridDev<T>&,      \

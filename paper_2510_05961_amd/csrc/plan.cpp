@@ -406,7 +406,7 @@ void free_top_kernel(int p, int M, double a, int L, const double hL[3], const in
 
 int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask, int order,
                     double h, double a, int levels, int precision, int max_n, int M,
-                    const double* cell, const int* ntop_fixed) {
+                    const double* cell, const int* ntop_fixed, double skin) {
   if ((!box_in && !cell) || !(h > 0) || !(a > 0) || levels < 1 || levels > kMaxLevels ||
       max_n < 0)
     return MSM_ERR_INVALID_ARG;
@@ -683,16 +683,22 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
         }
   }
 
-  // cell list (triclinic: in the unit cube, as many cells per axis as the
-  // cell's width across that axis holds whole cutoffs)
+  P.skin = skin;
+  for (int k = 0; k < 3; ++k) P.width[k] = width[k];
+  cell_list_geometry(P);
+  return MSM_OK;
+}
+
+// cell list (triclinic: in the unit cube, as many cells per axis as the
+// cell's width across that axis holds whole cutoffs plus the skin)
+void cell_list_geometry(HostPlan& P) {
   for (int k = 0; k < 3; ++k) {
-    int n = (int)std::floor(width[k] / a);
+    int n = (int)std::floor(P.width[k] / (P.a + P.skin));
     if (n < 1) n = 1;
     if (n > 1024) n = 1024;
     P.nc[k] = n;
-    P.cs[k] = box[k] / n;
+    P.cs[k] = P.box[k] / n;
   }
-  return MSM_OK;
 }
 
 std::string describe_json(const HostPlan& P) {
@@ -715,7 +721,8 @@ std::string describe_json(const HostPlan& P) {
   for (size_t k = 0; k < P.omega.size(); ++k) o << (k ? "," : "") << P.omega[k];
   o << "],\"J\":[";
   for (int k = 0; k <= P.p; ++k) o << (k ? "," : "") << P.J[k];
-  o << "],\"cells\":[" << P.nc[0] << "," << P.nc[1] << "," << P.nc[2] << "],";
+  o << "],\"cells\":[" << P.nc[0] << "," << P.nc[1] << "," << P.nc[2] << "],\"skin\":" << P.skin
+    << ",";
   o << "\"stencil1_halfwidth\":[" << P.W1[0] << "," << P.W1[1] << "," << P.W1[2] << "],";
   o << "\"levels_info\":[";
   for (int l = 0; l < P.L; ++l) {

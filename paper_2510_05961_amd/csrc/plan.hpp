@@ -50,10 +50,17 @@ struct HostPlan {
   double J[kMaxOrder + 1];    // restriction taps J_{-p/2..p/2}
   LevelGeom lev[kMaxLevels];
   int W1[3];            // unfolded level-1 stencil half-widths (R + M)
-  // cell list for the short-range part
+  // cell list for the short-range part: cells of edge >= a + skin (a
+  // Verlet skin keeps the list between calls), width = the box's (or the
+  // cell's) width across each axis
+  double skin = 0.0;
+  double width[3];
   int nc[3];
   double cs[3];
 };
+
+// nc and cs from width, a and skin (at most 1024 cells per axis)
+void cell_list_geometry(HostPlan& P);
 
 // Builds geometry and every stencil; returns 0 or an msm_status code.
 // cell (optional, 9 doubles: rows a, b, c) makes a triclinic plan (box is
@@ -61,7 +68,8 @@ struct HostPlan {
 // top-grid point counts (a cell that changes keeps its grids).
 int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, int order,
                     double h, double a, int levels, int precision, int max_n, int M,
-                    const double* cell = nullptr, const int* ntop = nullptr);
+                    const double* cell = nullptr, const int* ntop = nullptr,
+                    double skin = 0.0);
 
 std::string describe_json(const HostPlan& P);
 

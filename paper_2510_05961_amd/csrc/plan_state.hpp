@@ -152,6 +152,17 @@ struct msm_plan_s {
   msm::WorkBufs* w = &own;
   void* Jd = nullptr;
   int* flag = nullptr;
+  // Verlet skin (msm_plan_set_skin): device state [force, rebuild, calls,
+  // rebuilds] (force: the next call rebuilds, after a new cell or skin or a
+  // call that kept its cell list in a workspace), each charge's position and
+  // wrap at the last rebuild (max_n vec4 each), and the n of the last call
+  int* skin_state = nullptr;
+  void* skin_ref = nullptr;
+  void* skin_shift = nullptr;
+  int skin_n = -1;
+  // cells per axis the working memory was laid out for (later cell lists
+  // never have more)
+  int nc_cap[3] = {0, 0, 0};
   // side streams of the forward DAG (default priority, non-blocking) and the
   // fork/join events between them and the caller's stream
   hipStream_t sb = nullptr, sc = nullptr, sd = nullptr;

@@ -24,10 +24,13 @@ _lib = None
 EXPORTS = ("msm_plan_create", "msm_plan_create_cell", "msm_plan_set_cell",
            "msm_plan_create_host", "msm_plan_destroy", "msm_plan_describe",
            "msm_plan_get_stencil", "msm_plan_grid_dims", "msm_workspace_bytes",
-           "msm_energy_forces", "msm_energy_forces_noalloc", "msm_backward", "msm_plan_status",
+           "msm_energy_forces", "msm_energy_forces_noalloc", "msm_backward", "msm_backward_full",
+           "msm_plan_status", "msm_plan_set_skin", "msm_plan_skin_stats",
            "msm_plan_get_grid",
            "msm_batch_plan_create", "msm_batch_energy_forces", "msm_status_string",
-           "msm_plan_set_profiling", "msm_plan_get_profile", "msm_plan_set_profile_stages")
+           "msm_plan_set_profiling", "msm_plan_get_profile", "msm_plan_set_profile_stages",
+           "msm_md_create", "msm_md_destroy", "msm_md_set_state", "msm_md_run",
+           "msm_md_get_state", "msm_md_energies")
 
 
 class MSMError(RuntimeError):
@@ -62,6 +65,10 @@ def lib():
         L.msm_energy_forces.argtypes = [P, i, P, P, P, P, P, P, P]
         L.msm_energy_forces_noalloc.argtypes = [P, i, P, P, P, P, P, P, P]
         L.msm_backward.argtypes = [P, i, P, P, P, P, P, P, P, P]
+        L.msm_backward_full.argtypes = [P, i, P, P, P, P, P, P, P, P, P]
+        L.msm_plan_set_skin.argtypes = [P, d]
+        L.msm_plan_skin_stats.argtypes = [P, ctypes.POINTER(ctypes.c_longlong),
+                                          ctypes.POINTER(ctypes.c_longlong), P]
         L.msm_plan_status.argtypes = [P, P]
         L.msm_plan_get_grid.argtypes = [P, i, i, P, P]
         L.msm_batch_plan_create.argtypes = [pp, i, P, P, u, i, d, d, i, i, i]
@@ -69,6 +76,12 @@ def lib():
         L.msm_plan_set_profiling.argtypes = [P, i]
         L.msm_plan_get_profile.argtypes = [P, ctypes.c_char_p, sz, i]
         L.msm_plan_set_profile_stages.argtypes = [P, ctypes.c_char_p]
+        L.msm_md_create.argtypes = [pp, P, i, d, d, d, d, d, i]
+        L.msm_md_destroy.argtypes = [P]
+        L.msm_md_set_state.argtypes = [P, P, P, P, P, P]
+        L.msm_md_run.argtypes = [P, i, i, P]
+        L.msm_md_get_state.argtypes = [P, P, P, P, P]
+        L.msm_md_energies.argtypes = [P, P, i, ctypes.POINTER(ctypes.c_int)]
         L.msm_status_string.argtypes = [i]
         L.msm_status_string.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -175,6 +188,16 @@ class Plan:
         _check(lib().msm_plan_set_cell(self._h, c9), "msm_plan_set_cell")
         self.cell = cell
 
+    def set_skin(self, skin):
+        _check(lib().msm_plan_set_skin(self._h, float(skin)), "msm_plan_set_skin")
+
+    def skin_stats(self, stream=None):
+        """(calls, rebuilds) since set_skin."""
+        c, r = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(lib().msm_plan_skin_stats(self._h, ctypes.byref(c), ctypes.byref(r),
+                                         _stream(stream)), "msm_plan_skin_stats")
+        return c.value, r.value
+
     def workspace_bytes(self, n):
         return int(lib().msm_workspace_bytes(self._h, int(n), 0))
 
@@ -207,13 +230,19 @@ class Plan:
                "msm_energy_forces_noalloc")
         return E, F, dq
 
-    def backward(self, pos, q, ws, gE=None, gF=None, stream=None):
+    def backward(self, pos, q, ws, gE=None, gF=None, gdEdq=None, stream=None):
         import torch
         n = q.shape[0]
         gpos = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
         gq = torch.empty(n, dtype=self.dtype, device=pos.device)
-        _check(lib().msm_backward(self._h, n, _ptr(pos), _ptr(q), _ptr(ws), _ptr(gE), _ptr(gF),
-                                  _ptr(gpos), _ptr(gq), _stream(stream)), "msm_backward")
+        if gdEdq is None:
+            _check(lib().msm_backward(self._h, n, _ptr(pos), _ptr(q), _ptr(ws), _ptr(gE),
+                                      _ptr(gF), _ptr(gpos), _ptr(gq), _stream(stream)),
+                   "msm_backward")
+        else:
+            _check(lib().msm_backward_full(self._h, n, _ptr(pos), _ptr(q), _ptr(ws), _ptr(gE),
+                                           _ptr(gF), _ptr(gdEdq), _ptr(gpos), _ptr(gq),
+                                           _stream(stream)), "msm_backward_full")
         return gpos, gq
 
     def status(self, stream=None):
@@ -291,21 +320,71 @@ class BatchPlan:
         return E, F, dq
 
 
+class MD:
+    """Velocity-Verlet dynamics of charged Lennard-Jones particles around a
+    plan (msm_md_*): state on the device in the plan's precision."""
+
+    def __init__(self, plan, n, dt, epsilon, sigma, cutoff, switch_on, log_steps=0):
+        self._h = ctypes.c_void_p()
+        _check(lib().msm_md_create(ctypes.byref(self._h), plan._h, int(n), float(dt),
+                                   float(epsilon), float(sigma), float(cutoff),
+                                   float(switch_on), int(log_steps)), "msm_md_create")
+        self.plan, self.n, self.log_steps = plan, int(n), int(log_steps)
+
+    def close(self):
+        if self._h:
+            lib().msm_md_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, pos, vel, q, mass, stream=None):
+        for t in (pos, vel, q, mass):
+            assert t.is_cuda and t.dtype == self.plan.dtype and t.is_contiguous()
+        _check(lib().msm_md_set_state(self._h, _ptr(pos), _ptr(vel), _ptr(q), _ptr(mass),
+                                      _stream(stream)), "msm_md_set_state")
+
+    def run(self, nsteps, graph=True, stream=None):
+        _check(lib().msm_md_run(self._h, int(nsteps), 1 if graph else 0, _stream(stream)),
+               "msm_md_run")
+
+    def state(self, stream=None):
+        import torch
+        pos = torch.empty((self.n, 3), dtype=self.plan.dtype, device="cuda")
+        vel, F = torch.empty_like(pos), torch.empty_like(pos)
+        _check(lib().msm_md_get_state(self._h, _ptr(pos), _ptr(vel), _ptr(F), _stream(stream)),
+               "msm_md_get_state")
+        return pos, vel, F
+
+    def energies(self):
+        """[steps, 3] numpy array: kinetic, Lennard-Jones, MSM energy after
+        each step."""
+        import numpy as np
+        buf = np.zeros((max(self.log_steps, 1), 3))
+        steps = ctypes.c_int()
+        _check(lib().msm_md_energies(self._h, buf.ctypes.data_as(ctypes.c_void_p),
+                                     self.log_steps, ctypes.byref(steps)), "msm_md_energies")
+        return buf[:min(steps.value, self.log_steps)]
+
+
 def _autograd_function():
     import torch
 
     class MSMFunction(torch.autograd.Function):
-        """(pos, q) -> (E, F, dEdq).  Differentiable in E and F; dEdq is
-        returned for convenience and carries no gradient."""
+        """(pos, q) -> (E, F, dEdq), differentiable in all three outputs."""
 
         @staticmethod
         def forward(ctx, pos, q, plan):
             ws = torch.empty(plan.workspace_bytes(q.shape[0]), dtype=torch.uint8,
                              device=pos.device)
             E, F, dq = plan.energy_forces(pos, q, ws=ws)
+            ctx.set_materialize_grads(False)  # unused outputs: NULL cotangents, no extra passes
             ctx.plan = plan
             ctx.save_for_backward(pos, q, ws)
-            ctx.mark_non_differentiable(dq)
             return E, F, dq
 
         @staticmethod
@@ -314,7 +393,8 @@ def _autograd_function():
             plan = ctx.plan
             gE = gE.to(torch.float64).contiguous() if gE is not None else None
             gF = gF.to(plan.dtype).contiguous() if gF is not None else None
-            gpos, gq = plan.backward(pos, q, ws, gE=gE, gF=gF)
+            gdq = gdq.to(plan.dtype).contiguous() if gdq is not None else None
+            gpos, gq = plan.backward(pos, q, ws, gE=gE, gF=gF, gdEdq=gdq)
             return gpos, gq, None
 
     return MSMFunction

@@ -155,3 +155,21 @@ def test_workspace_and_batch_boundary_errors():
     bad = (ctypes.c_double * 6)(10, 10, 10, -1, -1, -1)
     assert lib.msm_batch_plan_create(ctypes.byref(h), 2, bad, levels, 0, *args) == 1
     assert lib.msm_batch_plan_create(ctypes.byref(h), 0, boxes, levels, 0, *args) == 1
+
+
+def test_skin_cell_geometry():
+    """msm_plan_set_skin on a host plan: cells of edge >= a + skin, never more
+    cells per axis than before; argument errors."""
+    plan = msm.Plan((30.0, 24.0, 17.0), 7, 4, 1.0, 4.0, 2, msm.MSM_FP32, 100, device=False)
+    assert plan.describe()["cells"] == [7, 6, 4]
+    plan.set_skin(1.0)
+    d = plan.describe()
+    assert d["skin"] == 1.0 and d["cells"] == [6, 4, 3]
+    for k, L in enumerate((30.0, 24.0, 17.0)):
+        assert L / d["cells"][k] >= 5.0
+    plan.set_skin(0.0)
+    assert plan.describe()["cells"] == [7, 6, 4]
+    lib = msm.lib()
+    assert lib.msm_plan_set_skin(plan._h, -0.5) == 1
+    assert lib.msm_plan_set_skin(plan._h, float("nan")) == 1
+    assert lib.msm_plan_set_skin(None, 1.0) == 1
