@@ -470,6 +470,62 @@ def _grid_pass_sweep(torch, msm, steps):
     return out
 
 
+def _md(torch, msm, np, steps=2000):
+    """Charged Lennard-Jonesium (Sec. MD simulation of charged
+    Lennard-Jonesium) in reduced units: 1,000 particles at density 0.85,
+    |q| = sqrt(50), rock-salt start, velocities at 2 x 3.15; LJ cutoff 4,
+    switch from 3.5; MSM p = 6, h = 0.5, a = 4, L = 3, skin 0.3; dt = 5e-4.
+    Velocity-Verlet steps per second replayed from a graph and launched
+    eagerly, the Verlet-skin rebuilds, and the NVE stability measure."""
+    n_side = 10
+    n = n_side ** 3
+    L = (n / 0.85) ** (1.0 / 3.0)
+    rng = np.random.default_rng(31)
+    g = (np.arange(n_side) + 0.5) * (L / n_side)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pos += rng.normal(scale=0.02, size=pos.shape)
+    q = np.where(np.indices((n_side,) * 3).sum(0).ravel() % 2 == 0, 1.0, -1.0) * np.sqrt(50.0)
+    vel = np.random.default_rng(32).normal(scale=np.sqrt(2 * 3.15), size=pos.shape)
+    vel -= vel.mean(axis=0)
+    out = {"workload": "charged Lennard-Jonesium, 1,000 particles, density 0.85, |q| = sqrt(50), "
+                       "reduced units, dt = 5e-4, LJ cutoff 4 (switch from 3.5), MSM p=6 h=0.5 "
+                       "a=4 L=3, skin 0.3"}
+    for name, prec, dt_ in (("fp32", msm.MSM_FP32, torch.float32),
+                            ("fp64", msm.MSM_FP64, torch.float64)):
+        rec = {}
+        for graph in (True, False):
+            plan = msm.Plan((L, L, L), 7, 6, 0.5, 4.0, 3, prec, n)
+            plan.set_skin(0.3)
+            md = msm.MD(plan, n, 5e-4, 1.0, 1.0, 4.0, 3.5, log_steps=steps)
+            T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=dt_, device="cuda")  # noqa
+            md.set_state(T(pos), T(vel), T(q), T(np.ones(n)))
+            md.run(1, graph=graph)  # (the capture, when graph)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            md.run(steps - 1, graph=graph)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / (steps - 1)
+            if plan.status() != 0:
+                raise RuntimeError("device error flag set in the MD run")
+            key = "graph" if graph else "eager"
+            rec[f"{key}_ms_per_step"] = round(t * 1e3, 4)
+            rec[f"{key}_steps_per_s"] = round(1.0 / t, 1)
+            if graph:
+                log = md.energies()
+                tot = log.sum(axis=1)
+                half = len(tot) // 2
+                calls, rebuilds = plan.skin_stats()
+                rec.update({"steps": int(len(log)), "cell_list_rebuilds": rebuilds,
+                            "msm_calls": calls,
+                            "std_total_over_std_kinetic": float(tot.std() / log[:, 0].std()),
+                            "mean_total_change_over_std_kinetic":
+                                float(abs(tot[half:].mean() - tot[:half].mean()) / log[:, 0].std())})
+            md.close()
+            plan.close()
+        out[name] = rec
+    return out
+
+
 def _accuracy_sweep(torch, msm, WL, np, O, reps):
     """Cost against accuracy over the method's parameters (Sec.
     Accuracy-performance tradeoff): 10^4 charges no two closer than 0.6 d
@@ -549,7 +605,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the water, autograd, batched and free-ion workloads")
+                    help="skip the water, autograd, batched, free-ion and MD workloads")
     ap.add_argument("--no-grid-sweep", action="store_true",
                     help="skip the grid-pass timing on 128^3-512^3 level-1 grids with 1e7-6e7 "
                          "charges (HBM fraction of anterpolation, restriction, prolongation, "
@@ -653,6 +709,7 @@ def main():
         result["autograd"] = _autograd_vs_plain(torch, msm, WL, np, O if check else None, check)
         result["batched"] = _batched_vs_plain(torch, msm, WL, np, O if check else None, check)
         result["free_ions_fp64"] = _free_ions(torch, msm, WL, np, O if check else None, check)
+        result["md"] = _md(torch, msm, np)
 
     if not args.no_grid_sweep:
         try:
