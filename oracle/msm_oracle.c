@@ -40,65 +40,79 @@ void orc_set_num_threads(int n)
 /* ------------------------------------------------------------------------
  * Softening function (Sec. "Splitting for Coulomb kernels"): gamma(rho) is
  * 1/rho for rho >= 1 and, below 1, the Taylor polynomial of s^(-1/2) about
- * s = 1 up to degree p-1 in s, evaluated at s = rho^2.
+ * s = 1 up to degree p-1 in s, evaluated at s = rho^2.  The same
+ * construction splits k(r) = r^-nu for other powers (the paper's splitting
+ * applies to any such kernel; nu = 6 is the dispersion kernel): gamma_nu is
+ * rho^-nu for rho >= 1 and the Taylor polynomial of s^(-nu/2) below.
  * ---------------------------------------------------------------------- */
-static double binom_mhalf(int k) /* binomial coefficient C(-1/2, k) */
+static double binom_gen(double x, int k) /* binomial coefficient C(x, k) */
 {
   double c = 1.0;
-  for (int j = 0; j < k; ++j) c *= (-0.5 - j) / (double)(j + 1);
+  for (int j = 0; j < k; ++j) c *= (x - j) / (double)(j + 1);
   return c;
 }
 
-/* g(s) = sum_{k<p} C(-1/2,k) (s-1)^k and its s-derivatives */
-static double taylor_g(int p, double s, int deriv)
+/* g(s) = sum_{k<p} C(-nu/2,k) (s-1)^k and its s-derivatives */
+static double taylor_g(int nu, int p, double s, int deriv)
 {
   double sum = 0.0;
   for (int k = deriv; k < p; ++k) {
     double fall = 1.0; /* k (k-1) ... (k-deriv+1) */
     for (int j = 0; j < deriv; ++j) fall *= (double)(k - j);
-    sum += binom_mhalf(k) * fall * pow(s - 1.0, k - deriv);
+    sum += binom_gen(-0.5 * nu, k) * fall * pow(s - 1.0, k - deriv);
   }
   return sum;
 }
 
-double orc_gamma(int p, double rho)
+/* gamma_nu(rho) (deriv = 0) and its first two rho-derivatives */
+double orc_gamma_nu(int nu, int p, double rho, int deriv)
 {
-  if (rho >= 1.0) return 1.0 / rho;
-  return taylor_g(p, rho * rho, 0);
-}
-
-double orc_gamma_d1(int p, double rho)
-{
-  if (rho >= 1.0) return -1.0 / (rho * rho);
-  return 2.0 * rho * taylor_g(p, rho * rho, 1);
-}
-
-double orc_gamma_d2(int p, double rho)
-{
-  if (rho >= 1.0) return 2.0 / (rho * rho * rho);
+  if (rho >= 1.0) {
+    if (deriv == 0) return pow(rho, -nu);
+    if (deriv == 1) return -nu * pow(rho, -nu - 1);
+    return nu * (nu + 1.0) * pow(rho, -nu - 2);
+  }
   double s = rho * rho;
-  return 2.0 * taylor_g(p, s, 1) + 4.0 * s * taylor_g(p, s, 2);
+  if (deriv == 0) return taylor_g(nu, p, s, 0);
+  if (deriv == 1) return 2.0 * rho * taylor_g(nu, p, s, 1);
+  return 2.0 * taylor_g(nu, p, s, 1) + 4.0 * s * taylor_g(nu, p, s, 2);
 }
 
-/* Partial kernels (eq. coulomb_splitting_with_softener). */
+double orc_gamma(int p, double rho) { return orc_gamma_nu(1, p, rho, 0); }
+double orc_gamma_d1(int p, double rho) { return orc_gamma_nu(1, p, rho, 1); }
+double orc_gamma_d2(int p, double rho) { return orc_gamma_nu(1, p, rho, 2); }
+
+/* Partial kernels of r^-nu (eq. coulomb_splitting_with_softener):
+ * k_0 = r^-nu - gamma(r/a)/a^nu, k_l = gamma(r/a_l)/a_l^nu -
+ * gamma(r/a_{l+1})/a_{l+1}^nu, k_L = gamma(r/a_L)/a_L^nu, a_l = 2^(l-1) a. */
+double orc_kernel_nu(int nu, int l, int L, double a, int p, double r)
+{
+  if (l == 0) return pow(r, -nu) - orc_gamma_nu(nu, p, r / a, 0) / pow(a, nu);
+  double s0 = ldexp(a, l - 1); /* 2^(l-1) a */
+  if (l == L) return orc_gamma_nu(nu, p, r / s0, 0) / pow(s0, nu);
+  double s1 = ldexp(a, l); /* 2^l a */
+  return orc_gamma_nu(nu, p, r / s0, 0) / pow(s0, nu) -
+         orc_gamma_nu(nu, p, r / s1, 0) / pow(s1, nu);
+}
+
 double orc_kernel(int l, int L, double a, int p, double r)
 {
-  if (l == 0) return 1.0 / r - orc_gamma(p, r / a) / a;
-  double s0 = ldexp(a, l - 1); /* 2^(l-1) a */
-  if (l == L) return orc_gamma(p, r / s0) / s0;
-  double s1 = ldexp(a, l); /* 2^l a */
-  return orc_gamma(p, r / s0) / s0 - orc_gamma(p, r / s1) / s1;
+  return orc_kernel_nu(1, l, L, a, p, r);
 }
 
-double orc_k0_d1(double a, int p, double r)
+/* First (deriv = 1) and second r-derivatives of k_0 */
+double orc_k0_nu(int nu, double a, int p, double r, int deriv)
 {
-  return -1.0 / (r * r) - orc_gamma_d1(p, r / a) / (a * a);
+  if (deriv == 1)
+    return -nu * pow(r, -nu - 1) - orc_gamma_nu(nu, p, r / a, 1) / pow(a, nu + 1);
+  return nu * (nu + 1.0) * pow(r, -nu - 2) - orc_gamma_nu(nu, p, r / a, 2) / pow(a, nu + 2);
 }
 
-double orc_k0_d2(double a, int p, double r)
-{
-  return 2.0 / (r * r * r) - orc_gamma_d2(p, r / a) / (a * a * a);
-}
+double orc_k0_d1(double a, int p, double r) { return orc_k0_nu(1, a, p, r, 1); }
+double orc_k0_d2(double a, int p, double r) { return orc_k0_nu(1, a, p, r, 2); }
+
+/* the power of the geometry's kernel (0 stands for Coulomb, nu = 1) */
+static int geom_nu(const orc_geom* g) { return g->nu > 0 ? g->nu : 1; }
 
 /* ------------------------------------------------------------------------
  * Cardinal B-splines (Sec. "B-spline interpolation"): M_1 is the indicator
@@ -304,7 +318,7 @@ void orc_stencil(const orc_geom* g, int level, const int W[3], double* K)
                         : u[k];
         double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         samp[((long)(z + S[2]) * ns[1] + (y + S[1])) * ns[0] + (x + S[0])] =
-            orc_kernel(level, g->L, g->a, g->p, r);
+            orc_kernel_nu(geom_nu(g), level, g->L, g->a, g->p, r);
       }
   int nk[3] = {2 * W[0] + 1, 2 * W[1] + 1, 2 * W[2] + 1};
 #pragma omp parallel for collapse(2) schedule(static)
@@ -520,8 +534,8 @@ void orc_short_range(const orc_geom* g, int n, const double* pos, const double* 
       min_image(g, d);
       double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       if (!(r < g->a)) continue;
-      ph += q[j] * orc_kernel(0, g->L, g->a, g->p, r);
-      double c = -q[i] * q[j] * orc_k0_d1(g->a, g->p, r) / r;
+      ph += q[j] * orc_kernel_nu(geom_nu(g), 0, g->L, g->a, g->p, r);
+      double c = -q[i] * q[j] * orc_k0_nu(geom_nu(g), g->a, g->p, r, 1) / r;
       for (int k = 0; k < 3; ++k) f[k] += c * d[k];
     }
     if (phi) phi[s] += ph;
@@ -623,8 +637,8 @@ static int sr_pair(const orc_geom* g, const double* pos, const double* q, int i,
   min_image(g, d);
   double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   if (!(r < g->a)) return 0;
-  *ph += q[j] * orc_kernel(0, g->L, g->a, g->p, r);
-  double c = -q[i] * q[j] * orc_k0_d1(g->a, g->p, r) / r;
+  *ph += q[j] * orc_kernel_nu(geom_nu(g), 0, g->L, g->a, g->p, r);
+  double c = -q[i] * q[j] * orc_k0_nu(geom_nu(g), g->a, g->p, r, 1) / r;
   for (int k = 0; k < 3; ++k) f[k] += c * d[k];
   return 1;
 }
@@ -664,7 +678,7 @@ static void vjp_pair(const orc_geom* g, const double* pos, const double* q, cons
   min_image(g, d);
   double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   if (!(r < g->a)) return;
-  double k1 = orc_k0_d1(g->a, g->p, r), k2 = orc_k0_d2(g->a, g->p, r);
+  double k1 = orc_k0_nu(geom_nu(g), g->a, g->p, r, 1), k2 = orc_k0_nu(geom_nu(g), g->a, g->p, r, 2);
   double f = -k1 / r;
   double fp = -k2 / r + k1 / (r * r);
   double dv[3] = {v[3 * i] - v[3 * j], v[3 * i + 1] - v[3 * j + 1],
@@ -712,6 +726,11 @@ void orc_short_range_vjp_cells(const orc_geom* g, int n, const double* pos,
 void orc_direct_coulomb(int n, const double* pos, const double* q, double* phi,
                         double* F)
 {
+  orc_direct_nu(1, n, pos, q, phi, F);
+}
+
+void orc_direct_nu(int nu, int n, const double* pos, const double* q, double* phi, double* F)
+{
 #pragma omp parallel for schedule(dynamic, 16)
   for (int i = 0; i < n; ++i) {
     double ph = 0.0, f[3] = {0, 0, 0};
@@ -720,8 +739,8 @@ void orc_direct_coulomb(int n, const double* pos, const double* q, double* phi,
       double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
                      pos[3 * i + 2] - pos[3 * j + 2]};
       double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      ph += q[j] / r;
-      double c = q[i] * q[j] / (r * r * r);
+      ph += q[j] * pow(r, -nu);
+      double c = nu * q[i] * q[j] * pow(r, -nu - 2);
       for (int k = 0; k < 3; ++k) f[k] += c * d[k];
     }
     if (phi) phi[i] = ph;

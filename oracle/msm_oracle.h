@@ -38,6 +38,9 @@ typedef struct {
   int tri;
   double H[9];
   double Hinv[9];
+  /* the kernel k(r) = r^-nu (1 or 0: Coulomb; 6: dispersion; free space
+   * only for nu != 1) */
+  int nu;
 } orc_geom;
 
 int orc_num_threads(void);
@@ -52,6 +55,11 @@ double orc_kernel(int l, int L, double a, int p, double r);
 /* First and second r-derivatives of k_0. */
 double orc_k0_d1(double a, int p, double r);
 double orc_k0_d2(double a, int p, double r);
+/* The same for k(r) = r^-nu: softener (deriv 0..2 in rho), partial kernels
+ * k_l, and k_0' (deriv 1) / k_0'' (deriv 2). */
+double orc_gamma_nu(int nu, int p, double rho, int deriv);
+double orc_kernel_nu(int nu, int l, int L, double a, int p, double r);
+double orc_k0_nu(int nu, double a, int p, double r, int deriv);
 /* Centred cardinal B-spline of order p and its first two derivatives. */
 double orc_bspline(int p, double t);
 double orc_bspline_d1(int p, double t);
@@ -99,6 +107,8 @@ void orc_short_range_vjp_cells(const orc_geom* g, int n, const double* pos,
 /* Exact non-periodic Coulomb sums: phi_i = sum_{j!=i} q_j / r, F_i. */
 void orc_direct_coulomb(int n, const double* pos, const double* q, double* phi,
                         double* F);
+/* phi_i = sum_{j!=i} q_j r^-nu, F_i = -q_i grad_i phi_i. */
+void orc_direct_nu(int nu, int n, const double* pos, const double* q, double* phi, double* F);
 
 /* Ewald potential of a unit charge plus its periodic images, tin-foil
  * boundary and neutralising background; 3-D (all axes periodic) and 2-D

@@ -68,7 +68,8 @@ class _Geom(ctypes.Structure):
                 ("periodic", ctypes.c_int * 3),
                 ("n", (ctypes.c_int * 3) * MAXL), ("lo", (ctypes.c_int * 3) * MAXL),
                 ("h", (ctypes.c_double * 3) * MAXL), ("omega", ctypes.c_double * 32),
-                ("tri", ctypes.c_int), ("H", ctypes.c_double * 9), ("Hinv", ctypes.c_double * 9)]
+                ("tri", ctypes.c_int), ("H", ctypes.c_double * 9), ("Hinv", ctypes.c_double * 9),
+                ("nu", ctypes.c_int)]
 
 
 _lib = None
@@ -90,6 +91,14 @@ def lib():
         L.orc_set_num_threads.restype = None
         L.orc_kernel.argtypes = [i, i, d, i, d]
         L.orc_kernel.restype = d
+        L.orc_gamma_nu.argtypes = [i, i, d, i]
+        L.orc_gamma_nu.restype = d
+        L.orc_kernel_nu.argtypes = [i, i, i, d, i, d]
+        L.orc_kernel_nu.restype = d
+        L.orc_k0_nu.argtypes = [i, d, i, d, i]
+        L.orc_k0_nu.restype = d
+        L.orc_direct_nu.argtypes = [i, i, P, P, P, P]
+        L.orc_direct_nu.restype = None
         for name in ("orc_k0_d1", "orc_k0_d2"):
             getattr(L, name).argtypes = [d, i, d]
             getattr(L, name).restype = d
@@ -155,8 +164,24 @@ def gamma(p, rho):
     return lib().orc_gamma(p, float(rho))
 
 
-def kernel(l, L, a, p, r):
-    return lib().orc_kernel(l, L, float(a), p, float(r))
+def kernel(l, L, a, p, r, nu=1):
+    """Partial kernel k_l(r) of r^-nu (nu = 1: Coulomb)."""
+    if nu == 1:
+        return lib().orc_kernel(l, L, float(a), p, float(r))
+    return lib().orc_kernel_nu(int(nu), l, L, float(a), p, float(r))
+
+
+def gamma_nu(nu, p, rho, deriv=0):
+    return lib().orc_gamma_nu(int(nu), int(p), float(rho), int(deriv))
+
+
+def direct_sum(pos, q, nu):
+    """Exact all-pairs non-periodic sums of q_j r^-nu: potentials and forces."""
+    pos, q = _f64(pos), _f64(q)
+    phi = np.zeros(len(q))
+    F = np.zeros((len(q), 3))
+    lib().orc_direct_nu(int(nu), len(q), _ptr(pos), _ptr(q), _ptr(phi), _ptr(F))
+    return phi, F
 
 
 def bspline(p, t, deriv=0):
@@ -265,9 +290,13 @@ class OracleMSM:
     H^{-T}, stencil samples k_l(|H (n / N_l)|), the top level summed over the
     lattice with the triclinic Ewald sum.  The cutoff must not exceed half
     the cell's smallest width V / |face| (minimum image).
+
+    nu: the kernel k(r) = r^-nu split the same way (gamma_nu: the Taylor
+    polynomial of s^(-nu/2)); 1 is Coulomb, 6 the dispersion kernel, for
+    which only free space is supported (its top level is the plain dense sum).
     """
 
-    def __init__(self, box, periodic, p, h, a, L, M=None, cell=None, ntop=None):
+    def __init__(self, box, periodic, p, h, a, L, M=None, cell=None, ntop=None, nu=1):
         self.cell = None if cell is None else np.asarray(cell, dtype=np.float64).reshape(3, 3)
         if self.cell is not None:
             self.H = cell_matrix(self.cell)
@@ -280,6 +309,8 @@ class OracleMSM:
         self.periodic = [bool(x) for x in periodic]
         self.p, self.h, self.a, self.L = int(p), float(h), float(a), int(L)
         self.M = self.p if M is None else int(M)
+        self.nu = int(nu)  # kernel r^-nu; other powers than 1 in free space only
+        assert self.nu >= 1 and (self.nu == 1 or not any(self.periodic))
         assert self.p % 2 == 0 and self.p >= 2 and 1 <= self.L <= MAXL
         npd = sum(self.periodic)
         assert npd in (0, 3) or self.periodic == [True, True, False], "unsupported periodicity"
@@ -312,6 +343,7 @@ class OracleMSM:
             self.levels.append((n, lo, hl))
         g = _Geom()
         g.p, g.L, g.M, g.a = self.p, self.L, self.M, self.a
+        g.nu = self.nu
         for k in range(3):
             g.box[k] = self.box[k]
             g.periodic[k] = int(self.periodic[k])
@@ -392,7 +424,7 @@ class OracleMSM:
         npd = sum(self.periodic)
         if npd == 0:
             r = math.sqrt(x[0] ** 2 + x[1] ** 2 + x[2] ** 2)
-            return kernel(L, L, a, p, r)
+            return kernel(L, L, a, p, r, self.nu)
         R = 2 ** (L - 1) * a
         if self.cell is not None:
             # x is Cartesian; images x + H j over the lattice
@@ -494,7 +526,7 @@ class OracleMSM:
 
     def self_constant(self):
         """sum_{l=1..L} k_l(0) (eq. U_zero, second term)."""
-        return sum(kernel(l, self.L, self.a, self.p, 0.0) for l in range(1, self.L + 1))
+        return sum(kernel(l, self.L, self.a, self.p, 0.0, self.nu) for l in range(1, self.L + 1))
 
     def support_points(self, level, pos):
         """Flat indices of the grid points whose basis is non-zero at pos."""
