@@ -81,6 +81,29 @@ msm_status msm_plan_create(msm_plan* out, const double box[3], unsigned periodic
                            int quasi_degree_M);
 
 /*
+ * msm_plan_create_kernel -- msm_plan_create for the kernel k(r) = r^-nu,
+ * nu = kernel: MSM_KERNEL_COULOMB (1, the same plan as msm_plan_create) or
+ * MSM_KERNEL_DISPERSION (6).  The paper's splitting carries over unchanged
+ * (Sec. "Splitting for Coulomb kernels"; the package's core is meant to take
+ * other kernels): k_0 = r^-nu - gamma(r/a)/a^nu, k_l = gamma(r/a_l)/a_l^nu -
+ * gamma(r/a_{l+1})/a_{l+1}^nu (a_l = 2^(l-1) a), k_L = gamma(r/a_L)/a_L^nu,
+ * with gamma the degree-(p-1) Taylor polynomial of s^(-nu/2) about s = 1 at
+ * s = (r/a)^2 below 1 and r^-nu above; the intermediate stencils are
+ * K^1 / 2^((l-1) nu).  For nu = 6 "charges" are per-particle coefficients c_i
+ * (E = 1/2 sum_{i != j} c_i c_j r^-6, geometric mixing; negate the result
+ * for an attractive dispersion energy); only free space is supported
+ * (periodic_mask != 0: MSM_ERR_UNSUPPORTED), and a/h of about 8 or more
+ * is needed before the higher orders pay (the softened r^-6 is stiff).
+ * Every compute call, the backward included, works as for Coulomb plans;
+ * batched plans are Coulomb only.
+ */
+#define MSM_KERNEL_COULOMB 1
+#define MSM_KERNEL_DISPERSION 6
+msm_status msm_plan_create_kernel(msm_plan* out, int kernel, const double box[3],
+                                  unsigned periodic_mask, int order, double h, double cutoff_a,
+                                  int levels, int precision, int max_n, int quasi_degree_M);
+
+/*
  * msm_plan_create_cell -- msm_plan_create for a triclinic cell (Sec. "MSM core
  * algorithm", long-range part: positions are mapped to the unit cube,
  * s = [a b c]^{-1} r, and the grids are set up there).

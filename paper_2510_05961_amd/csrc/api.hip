@@ -335,7 +335,7 @@ void free_plan(msm_plan P) {
 
 template <typename T>
 PairParams<T> pair_params(const HostPlan& hp) {
-  PairParams<T> pp;
+  PairParams<T> pp{};
   const int p = hp.p;
   for (int k = 0; k < 3; ++k) {
     pp.box[k] = (T)hp.box[k];
@@ -346,6 +346,7 @@ PairParams<T> pair_params(const HostPlan& hp) {
   }
   pp.ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
   pp.margin = (T)(0.5 * hp.skin);
+  pp.nu = hp.nu;
   const double a = hp.a;
   pp.a2 = (T)(a * a);
   pp.inv_a2 = (T)(1.0 / (a * a));
@@ -359,11 +360,12 @@ PairParams<T> pair_params(const HostPlan& hp) {
     pp.c[k] = (T)c;
     pp.dc[k] = (T)dc;
     pp.d2c[k] = (T)d2c;
-    // t^k = r^2k / a^2k, scaled in FP64 before the cast
-    const double a2k = std::pow(a, 2 * k);
-    pp.er[k] = (T)(c / (a2k * a));
-    pp.fr[k] = (T)(2.0 * dc / (a2k * a * a * a));
-    pp.gr[k] = (T)(4.0 * d2c / (a2k * a * a * a * a * a));
+    // t^k = r^2k / a^2k, scaled in FP64 before the cast; the kernel r^-nu
+    // softens as gamma(r/a)/a^nu
+    const double a2k = std::pow(a, 2 * k), anu = std::pow(a, hp.nu);
+    pp.er[k] = (T)(c / (a2k * anu));
+    pp.fr[k] = (T)(2.0 * dc / (a2k * anu * a * a));
+    pp.gr[k] = (T)(4.0 * d2c / (a2k * anu * a * a * a * a));
   }
   pp.tri = hp.tri;
   for (int k = 0; k < 9; ++k) pp.H[k] = hp.tri ? (T)hp.H[k] : T(0);
@@ -710,14 +712,15 @@ msm_status backward(msm_plan P, int n, const void* ws, const double* gE, const T
 
 msm_status create_common(msm_plan* out, const double box[3], unsigned mask, int order, double h,
                          double a, int levels, int precision, int max_n, int M, bool device,
-                         const double* cell = nullptr) {
+                         const double* cell = nullptr, int nu = 1) {
   if (!out) return MSM_ERR_INVALID_ARG;
   *out = nullptr;
   msm_plan P = new (std::nothrow) msm_plan_s;
   if (!P) return MSM_ERR_OOM;
   int rc;
   try {
-    rc = build_host_plan(P->hp, box, mask, order, h, a, levels, precision, max_n, M, cell);
+    rc = build_host_plan(P->hp, box, mask, order, h, a, levels, precision, max_n, M, cell,
+                         nullptr, 0.0, nu);
   } catch (...) {
     rc = MSM_ERR_OOM;
   }
@@ -772,7 +775,7 @@ msm_status set_cell(msm_plan P, const double cell[9]) {
   int rc;
   try {
     rc = build_host_plan(hp, nullptr, 7, old.p, old.h_req, old.a, old.L, old.precision, old.max_n,
-                         old.M, cell, ntop, old.skin);
+                         old.M, cell, ntop, old.skin, old.nu);
   } catch (...) {
     rc = MSM_ERR_OOM;
   }
@@ -860,6 +863,17 @@ msm_status msm_plan_create(msm_plan* out, const double box[3], unsigned periodic
                            int quasi_degree_M) {
   return create_common(out, box, periodic_mask, order, h, cutoff_a, levels, precision, max_n,
                        quasi_degree_M, true);
+}
+
+msm_status msm_plan_create_kernel(msm_plan* out, int kernel, const double box[3],
+                                  unsigned periodic_mask, int order, double h, double cutoff_a,
+                                  int levels, int precision, int max_n, int quasi_degree_M) {
+  if (kernel != MSM_KERNEL_COULOMB && kernel != MSM_KERNEL_DISPERSION) {
+    if (out) *out = nullptr;
+    return MSM_ERR_INVALID_ARG;
+  }
+  return create_common(out, box, periodic_mask, order, h, cutoff_a, levels, precision, max_n,
+                       quasi_degree_M, true, nullptr, kernel);
 }
 
 msm_status msm_plan_create_cell(msm_plan* out, const double cell[9], unsigned periodic_mask,

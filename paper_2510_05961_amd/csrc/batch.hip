@@ -576,7 +576,7 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
   launch_fill<T>((T*)B.qcat[0], B.Gtot[0], T(0), s);
   launch_fill<double>(energies, NS, 0.0, s);
   hipLaunchKernelGGL(k_batch_sysid, dim3(NS), dim3(256), 0, s, NS, off, maxn, B.sys_of, B.flag);
-  PairParams<T> pp;
+  PairParams<T> pp{};
   const double a = B.a;
   pp.a2 = (T)(a * a);
   pp.inv_a2 = (T)(1.0 / (a * a));

@@ -39,6 +39,7 @@ struct PairParams {
   T H[9];
   // how far a charge may lie outside its cell (half the Verlet skin)
   T margin;
+  int nu;  // the kernel r^-nu (1: Coulomb, 6: dispersion)
 };
 
 // One stencil convolution e_o = sum_d K_d q_{o+shift-d} (a5, a6).

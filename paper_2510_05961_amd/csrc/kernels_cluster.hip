@@ -506,7 +506,21 @@ __device__ inline void for_each_j_culled(const PairParams<T>& pp, const int* cl_
 // of each step.
 // The self pair (the same particle, shift 0) is the only pair at distance
 // exactly zero and is left out by r^2 > 0.
-template <typename T, int P>
+// r^-nu and nu r^-(nu+2) from 1/r (nu = 1: Coulomb, 6: dispersion)
+template <int NU, typename T>
+__device__ inline void power_terms(T rinv, T& k, T& f) {
+  const T rinv2 = rinv * rinv;
+  if constexpr (NU == 1) {
+    k = rinv;
+    f = rinv * rinv2;
+  } else {
+    const T r6 = rinv2 * rinv2 * rinv2;
+    k = r6;
+    f = T(NU) * r6 * rinv2;
+  }
+}
+
+template <typename T, int P, int NU>
 __global__ void __launch_bounds__(kClusterThreads)
     k_pair_pc(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
               const vec4_t<T>* __restrict__ cbox, const int4* __restrict__ cinfo,
@@ -544,8 +558,10 @@ __global__ void __launch_bounds__(kClusterThreads)
         for (int k = P - 2; k >= 0; --k) pe = pe * r2c + pp.er[k];
 #pragma unroll
         for (int k = P - 3; k >= 0; --k) pf = pf * r2c + pp.fr[k];
-        const T fs = qj * (rinv * rinv * rinv + pf);
-        phc += qj * (rinv - pe);
+        T kr, fr;
+        power_terms<NU>(rinv, kr, fr);
+        const T fs = qj * (fr + pf);
+        phc += qj * (kr - pe);
         fx += fs * dx;
         fy += fs * dy;
         fz += fs * dz;
@@ -603,7 +619,7 @@ __global__ void k_gather_v_cl(int nslot_max, const int* __restrict__ cl_start, i
 // W, for a cotangent w of the short-range potential phi0:
 //   d/dq_i  sum_k w_k phi0_k   = sum_j w_j k0(r)
 //   d/dr_i  sum_k w_k phi0_k   = -q_i sum_j w_j f d_ij - w_i sum_j q_j f d_ij.
-template <typename T, int P, bool W>
+template <typename T, int P, bool W, int NU>
 __global__ void __launch_bounds__(kClusterThreads)
     k_pair_vjp_cl(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
                   const vec4_t<T>* __restrict__ cv, const vec4_t<T>* __restrict__ cbox,
@@ -643,8 +659,11 @@ __global__ void __launch_bounds__(kClusterThreads)
         for (int k = P - 3; k >= 0; --k) pf = pf * r2c + pp.fr[k];
 #pragma unroll
         for (int k = P - 4; k >= 0; --k) pg = pg * r2c + pp.gr[k];
-        const T f = rinv * rinv2 + pf;
-        const T fpr = T(-3) * rinv2 * rinv2 * rinv + pg;
+        // f = nu r^-(nu+2) + pf, f'/r = -nu (nu+2) r^-(nu+4) + pg
+        T kr, fr;
+        power_terms<NU>(rinv, kr, fr);
+        const T f = fr + pf;
+        const T fpr = T(-(NU + 2)) * fr * rinv2 + pg;
         const T wx = vi.x - vj.x, wy = vi.y - vj.y, wz = vi.z - vj.z;
         const T wd = wx * dx + wy * dy + wz * dz;
         const T qf = qj * f;
@@ -658,7 +677,7 @@ __global__ void __launch_bounds__(kClusterThreads)
           T pe = e_top;
 #pragma unroll
           for (int k = P - 2; k >= 0; --k) pe = pe * r2c + pp.er[k];
-          sq += wj * (rinv - pe);
+          sq += wj * (kr - pe);
           const T wf = wj * f;
           rx -= wf * dx;
           ry -= wf * dy;
@@ -743,22 +762,30 @@ void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T
   if (n <= 0) return;
   const int ncl = cluster_capacity(n, ncell);
   const dim3 grid((ncl + 3) / 4), block(kClusterThreads);
+  if (pp.nu == 6) {
+    switch (p) {
+      case 4: hipLaunchKernelGGL((k_pair_pc<T, 4, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+      case 6: hipLaunchKernelGGL((k_pair_pc<T, 6, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+      case 8: hipLaunchKernelGGL((k_pair_pc<T, 8, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+    }
+    return;
+  }
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_pair_pc<T, 4>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
-    case 6: hipLaunchKernelGGL((k_pair_pc<T, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
-    case 8: hipLaunchKernelGGL((k_pair_pc<T, 8>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+    case 4: hipLaunchKernelGGL((k_pair_pc<T, 4, 1>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+    case 6: hipLaunchKernelGGL((k_pair_pc<T, 6, 1>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
+    case 8: hipLaunchKernelGGL((k_pair_pc<T, 8, 1>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, phi0, F0); break;
   }
 }
 
-template <typename T, bool W>
+template <typename T, bool W, int NU>
 void launch_pair_vjp_p(int p, dim3 grid, const int* cl_start, const vec4_t<T>* cpos,
                        const vec4_t<T>* cv, const vec4_t<T>* cbox, const int4* cinfo,
                        const PairParams<T>& pp, int nh, T* gq, T* gr, hipStream_t s) {
   const dim3 block(kClusterThreads);
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_pair_vjp_cl<T, 4, W>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
-    case 6: hipLaunchKernelGGL((k_pair_vjp_cl<T, 6, W>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
-    case 8: hipLaunchKernelGGL((k_pair_vjp_cl<T, 8, W>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
+    case 4: hipLaunchKernelGGL((k_pair_vjp_cl<T, 4, W, NU>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
+    case 6: hipLaunchKernelGGL((k_pair_vjp_cl<T, 6, W, NU>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
+    case 8: hipLaunchKernelGGL((k_pair_vjp_cl<T, 8, W, NU>), grid, block, 0, s, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr); break;
   }
 }
 
@@ -772,10 +799,16 @@ void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4
   hipLaunchKernelGGL(k_gather_v_cl<T>, dim3((8 * ncl + 255) / 256), dim3(256), 0, s, 8 * ncl,
                      cl_start, ncell, cinfo, perm, gF, gphi, cv);
   const dim3 grid((ncl + 3) / 4);
-  if (gphi)
-    launch_pair_vjp_p<T, true>(p, grid, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr, s);
-  else
-    launch_pair_vjp_p<T, false>(p, grid, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr, s);
+  if (pp.nu == 6) {
+    if (gphi)
+      launch_pair_vjp_p<T, true, 6>(p, grid, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr, s);
+    else
+      launch_pair_vjp_p<T, false, 6>(p, grid, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr, s);
+  } else if (gphi) {
+    launch_pair_vjp_p<T, true, 1>(p, grid, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr, s);
+  } else {
+    launch_pair_vjp_p<T, false, 1>(p, grid, cl_start, cpos, cv, cbox, cinfo, pp, nh, gq, gr, s);
+  }
 }
 
 #define MSM_INST_CLUSTER(T)                                                                    \

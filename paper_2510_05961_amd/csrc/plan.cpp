@@ -42,12 +42,13 @@ long double bspline_at(int p, long double x) {
 // gamma(rho) for rho < 1 is the degree-(p-1) Taylor polynomial of s^(-1/2)
 // about s = 1 at s = rho^2 (Sec. "Splitting for Coulomb kernels").  Expanded
 // in powers of t = rho^2: c_k = sum_{j>=k} C(-1/2, j) C(j, k) (-1)^(j-k).
-void softener_coefficients(int p, double* c) {
+// The kernel r^-nu is split the same way, with s^(-nu/2) (nu = 1: Coulomb).
+void softener_coefficients(int p, double* c, int nu) {
   std::vector<double> b(p);
   double v = 1.0;
   for (int j = 0; j < p; ++j) {
-    b[j] = v;  // C(-1/2, j)
-    v *= (-0.5 - j) / (j + 1.0);
+    b[j] = v;  // C(-nu/2, j)
+    v *= (-0.5 * nu - j) / (j + 1.0);
   }
   for (int k = 0; k < p; ++k) {
     double s = 0.0;
@@ -56,20 +57,22 @@ void softener_coefficients(int p, double* c) {
   }
 }
 
-static double gamma_t(const double* c, int p, double rho) {
-  if (rho >= 1.0) return 1.0 / rho;
+static double gamma_t(const double* c, int p, double rho, int nu = 1) {
+  if (rho >= 1.0) return nu == 1 ? 1.0 / rho : std::pow(rho, -nu);
   double t = rho * rho, s = c[p - 1];
   for (int k = p - 2; k >= 0; --k) s = s * t + c[k];
   return s;
 }
 
-// Partial kernels k_l, 1 <= l <= L (eq. coulomb_splitting_with_softener).
-static double split_kernel(const double* c, int p, int l, int L, double a, double r) {
+// Partial kernels k_l, 1 <= l <= L (eq. coulomb_splitting_with_softener) of
+// r^-nu: gamma(r/a_l)/a_l^nu - gamma(r/a_{l+1})/a_{l+1}^nu, a_l = 2^(l-1) a.
+static double split_kernel(const double* c, int p, int l, int L, double a, double r,
+                           int nu = 1) {
   double s0 = std::ldexp(a, l - 1);
-  if (l == L) return gamma_t(c, p, r / s0) / s0;
+  if (l == L) return gamma_t(c, p, r / s0, nu) / std::pow(s0, nu);
   double s1 = std::ldexp(a, l);
   if (r >= s1) return 0.0;
-  return gamma_t(c, p, r / s0) / s0 - gamma_t(c, p, r / s1) / s1;
+  return gamma_t(c, p, r / s0, nu) / std::pow(s0, nu) - gamma_t(c, p, r / s1, nu) / std::pow(s1, nu);
 }
 
 // Quasi-interpolation sequence (eq. kernel_stencil_by_conv_with_universal_coeff).
@@ -189,7 +192,7 @@ static double offset_reach(const double* A, const double h[3], int k, double r) 
 // Unfolded K^1 on |d_k| <= W_k = R_k + M, R_k = ceil(2a/h_k) - 1 (k_1 vanishes
 // for r >= 2a; on a triclinic grid the reach of 2a along each grid axis).
 void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::vector<double>& K,
-                    const double* gcoef, const double* A) {
+                    const double* gcoef, const double* A, int nu) {
   int R[3], ns[3];
   for (int k = 0; k < 3; ++k) {
     R[k] = (int)std::ceil(offset_reach(A, h, k, 2.0 * a) - 1e-12) - 1;
@@ -202,7 +205,7 @@ void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::ve
     for (int y = 0; y < ns[1]; ++y)
       for (int x = 0; x < ns[0]; ++x) {
         const double r = offset_length(A, h, x - R[0] - 2 * M, y - R[1] - 2 * M, z - R[2] - 2 * M);
-        s[((size_t)z * ns[1] + y) * ns[0] + x] = split_kernel(gcoef, p, 1, 2, a, r);
+        s[((size_t)z * ns[1] + y) * ns[0] + x] = split_kernel(gcoef, p, 1, 2, a, r, nu);
       }
   std::vector<double> om = quasi_sequence(p, M), t1, t2;
   int n1[3], n2[3], n3[3];
@@ -384,7 +387,7 @@ static double periodic_top_G(const HostPlan& P, const double x[3]) {
 // Dense top kernel of a free-space system: offsets |d_k| <= n_k - 1.
 void free_top_kernel(int p, int M, double a, int L, const double hL[3], const int n[3],
                      const std::vector<double>& omega, const double* gcoef,
-                     std::vector<double>& K) {
+                     std::vector<double>& K, int nu) {
   int ns[3];
   for (int k = 0; k < 3; ++k) ns[k] = 2 * (n[k] - 1 + M) + 1;
   std::vector<double> s((size_t)ns[0] * ns[1] * ns[2]);
@@ -395,7 +398,7 @@ void free_top_kernel(int p, int M, double a, int L, const double hL[3], const in
         double dx = (x - (ns[0] - 1) / 2) * hL[0], dy = (y - (ns[1] - 1) / 2) * hL[1],
                dz = (z - (ns[2] - 1) / 2) * hL[2];
         double r = std::sqrt(dx * dx + dy * dy + dz * dz);
-        s[((size_t)z * ns[1] + y) * ns[0] + x] = gamma_t(gcoef, p, r / R) / R;
+        s[((size_t)z * ns[1] + y) * ns[0] + x] = gamma_t(gcoef, p, r / R, nu) / std::pow(R, nu);
       }
   std::vector<double> t1, t2;
   int n1[3], n2[3], n3[3];
@@ -406,7 +409,7 @@ void free_top_kernel(int p, int M, double a, int L, const double hL[3], const in
 
 int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask, int order,
                     double h, double a, int levels, int precision, int max_n, int M,
-                    const double* cell, const int* ntop_fixed, double skin) {
+                    const double* cell, const int* ntop_fixed, double skin, int nu) {
   if ((!box_in && !cell) || !(h > 0) || !(a > 0) || levels < 1 || levels > kMaxLevels ||
       max_n < 0)
     return MSM_ERR_INVALID_ARG;
@@ -440,6 +443,11 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
     }
   }
   if (order != 4 && order != 6 && order != 8) return MSM_ERR_UNSUPPORTED;
+  // kernels r^-nu: Coulomb (1) anywhere, dispersion (6) in free space (its
+  // periodic top level would need its own Ewald-type sum)
+  if (nu != 1 && nu != 6) return MSM_ERR_INVALID_ARG;
+  if (nu != 1 && (periodic_mask != 0 || P.tri)) return MSM_ERR_UNSUPPORTED;
+  P.nu = nu;
   if (periodic_mask != 0 && periodic_mask != 7 && periodic_mask != 3) return MSM_ERR_UNSUPPORTED;
   if (M < 0) M = order;
   if (M > 24) return MSM_ERR_INVALID_ARG;
@@ -457,9 +465,9 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
   P.a = a;
   P.precision = precision;
   P.max_n = max_n;
-  softener_coefficients(order, P.gcoef);
+  softener_coefficients(order, P.gcoef, nu);
   P.gamma0 = P.gcoef[0];
-  P.self_const = P.gamma0 / a;
+  P.self_const = P.gamma0 / std::pow(a, nu);
   P.omega = quasi_sequence(order, M);
   for (int n = -order / 2; n <= order / 2; ++n)
     P.J[n + order / 2] = std::ldexp(binom(order, n + order / 2), 1 - order);
@@ -504,14 +512,15 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
 
   // level-1 stencil, unfolded
   std::vector<double> K1;
-  level1_stencil(order, M, a, P.lev[0].h, P.W1, K1, P.gcoef, A1p);
+  level1_stencil(order, M, a, P.lev[0].h, P.W1, K1, P.gcoef, A1p, nu);
   const int u[3] = {2 * P.W1[0] + 1, 2 * P.W1[1] + 1, 2 * P.W1[2] + 1};
 
-  // levels 1..L-1: K^l = K^1 / 2^(l-1) (Sec. "Splitting for Coulomb kernels"),
+  // levels 1..L-1: K^l = K^1 / 2^((l-1) nu) (Sec. "Splitting for Coulomb
+  // kernels": k_l(r) = 2^-(l-1)nu k_1(r / 2^(l-1)) on a grid twice as coarse),
   // folded onto periodic axes, cropped on free axes.
   for (int l = 1; l < levels; ++l) {
     LevelGeom& g = P.lev[l - 1];
-    const double scale = std::ldexp(1.0, -(l - 1));
+    const double scale = std::ldexp(1.0, -(l - 1) * nu);
     for (int k = 0; k < 3; ++k) {
       const int W = P.W1[k];
       if (P.periodic[k]) {
@@ -563,11 +572,11 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
         for (int x = -R[0]; x <= R[0]; ++x) {
           const double r = offset_length(A1p, g1.h, x, y, z);
           S1[((size_t)(z + R[2]) * (2 * R[1] + 1) + (y + R[1])) * (2 * R[0] + 1) + (x + R[0])] =
-              split_kernel(P.gcoef, order, 1, 2, a, r);
+              split_kernel(P.gcoef, order, 1, 2, a, r, nu);
         }
     for (int l = 1; l < levels; ++l) {
       LevelGeom& g = P.lev[l - 1];
-      const double scale = std::ldexp(1.0, -(l - 1));
+      const double scale = std::ldexp(1.0, -(l - 1) * nu);
       g.Gext = 1;
       for (int k = 0; k < 3; ++k) {
         if (P.periodic[k]) {
@@ -657,7 +666,7 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
             val = periodic_top_G(P, xv);
           } else {
             double r = std::sqrt(xv[0] * xv[0] + xv[1] * xv[1] + xv[2] * xv[2]);
-            val = gamma_t(P.gcoef, P.p, r / R) / R;
+            val = gamma_t(P.gcoef, P.p, r / R, nu) / std::pow(R, nu);
           }
           T[((size_t)z * next[1] + y) * next[0] + x] = val;
         }
@@ -714,7 +723,8 @@ std::string describe_json(const HostPlan& P) {
   }
   o << "\"order\":" << P.p << ",\"levels\":" << P.L << ",\"M\":" << P.M << ",\"h\":" << P.h_req
     << ",\"cutoff\":" << P.a << ",\"precision\":\"" << (P.precision ? "fp64" : "fp32") << "\",";
-  o << "\"max_n\":" << P.max_n << ",\"self_const\":" << P.self_const << ",";
+  o << "\"max_n\":" << P.max_n << ",\"self_const\":" << P.self_const << ",\"kernel_power\":"
+    << P.nu << ",";
   o << "\"gamma_t_coeffs\":[";
   for (int k = 0; k < P.p; ++k) o << (k ? "," : "") << P.gcoef[k];
   o << "],\"omega\":[";

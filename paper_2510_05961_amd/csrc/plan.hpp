@@ -40,6 +40,7 @@ struct HostPlan {
   double H[9], Hinv[9];
   int p, L, M;
   double h_req, a;
+  int nu = 1;      // the kernel r^-nu (1: Coulomb, 6: dispersion, free space only)
   int precision;   // 0 fp32, 1 fp64
   int max_n;
   // softener gamma(rho) = sum_k gcoef[k] t^k, t = rho^2, rho < 1
@@ -69,22 +70,22 @@ void cell_list_geometry(HostPlan& P);
 int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, int order,
                     double h, double a, int levels, int precision, int max_n, int M,
                     const double* cell = nullptr, const int* ntop = nullptr,
-                    double skin = 0.0);
+                    double skin = 0.0, int nu = 1);
 
 std::string describe_json(const HostPlan& P);
 
 // Softener pieces used by the batch planner as well.
-void softener_coefficients(int p, double* c);
+void softener_coefficients(int p, double* c, int nu = 1);
 std::vector<double> quasi_sequence(int p, int M);
 // Unfolded level-1 stencil of a free-space system with spacing h (all axes).
 // A (optional): the Cartesian step of one grid point along each axis as the
 // columns of a 3x3 matrix (a triclinic grid); else the steps are h_k along
 // the Cartesian axes.
 void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::vector<double>& K,
-                    const double* gcoef, const double* A = nullptr);
+                    const double* gcoef, const double* A = nullptr, int nu = 1);
 // Dense top-level kernel of a free-space system: offsets |d_k| <= n_k - 1.
 void free_top_kernel(int p, int M, double a, int L, const double hL[3], const int n[3],
                      const std::vector<double>& omega, const double* gcoef,
-                     std::vector<double>& K);
+                     std::vector<double>& K, int nu = 1);
 
 }  // namespace msm

@@ -21,7 +21,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "cutoff too large
 _lib = None
 
 # every symbol declared in include/msm.h
-EXPORTS = ("msm_plan_create", "msm_plan_create_cell", "msm_plan_set_cell",
+EXPORTS = ("msm_plan_create", "msm_plan_create_kernel", "msm_plan_create_cell", "msm_plan_set_cell",
            "msm_plan_create_host", "msm_plan_destroy", "msm_plan_describe",
            "msm_plan_get_stencil", "msm_plan_grid_dims", "msm_workspace_bytes",
            "msm_energy_forces", "msm_energy_forces_noalloc", "msm_backward", "msm_backward_full",
@@ -55,6 +55,7 @@ def lib():
         L.msm_plan_create.argtypes = [pp, P, u, i, d, d, i, i, i, i]
         L.msm_plan_create_host.argtypes = [pp, P, u, i, d, d, i, i, i, i]
         L.msm_plan_create_cell.argtypes = [pp, P, u, i, d, d, i, i, i, i]
+        L.msm_plan_create_kernel.argtypes = [pp, i, P, u, i, d, d, i, i, i, i]
         L.msm_plan_set_cell.argtypes = [P, P]
         L.msm_plan_destroy.argtypes = [P]
         L.msm_plan_describe.argtypes = [P, ctypes.c_char_p, sz]
@@ -120,11 +121,18 @@ class Plan:
     """An MSM plan for one orthorhombic box (msm_plan_create)."""
 
     def __init__(self, box, periodic_mask, order, h, cutoff, levels, precision=MSM_FP32,
-                 max_n=1, quasi_degree=-1, device=True, cell=None):
+                 max_n=1, quasi_degree=-1, device=True, cell=None, kernel=1):
         """cell: rows a, b, c of a triclinic cell (msm_plan_create_cell; box is
-        then ignored and periodic_mask must be 7)."""
+        then ignored and periodic_mask must be 7).  kernel: the power nu of
+        k(r) = r^-nu (1 Coulomb, 6 dispersion: msm_plan_create_kernel)."""
         self._h = ctypes.c_void_p()
-        if cell is not None:
+        if kernel != 1:
+            _check(lib().msm_plan_create_kernel(ctypes.byref(self._h), int(kernel), _dbl3(box),
+                                                int(periodic_mask), int(order), float(h),
+                                                float(cutoff), int(levels), int(precision),
+                                                int(max_n), int(quasi_degree)),
+                   "msm_plan_create_kernel")
+        elif cell is not None:
             c9 = (ctypes.c_double * 9)(*[float(x) for x in _flat9(cell)])
             _check(lib().msm_plan_create_cell(ctypes.byref(self._h), c9, int(periodic_mask),
                                               int(order), float(h), float(cutoff), int(levels),
