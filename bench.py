@@ -604,6 +604,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-error-check", action="store_true")
+    ap.add_argument("--extras", default="water,autograd,batched,free_ions,md",
+                    help="comma-separated extra workloads to run beside the headline")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the water, autograd, batched, free-ion and MD workloads")
     ap.add_argument("--no-grid-sweep", action="store_true",
@@ -705,11 +707,18 @@ def main():
                            "seconds": round(one[1], 3)}}
 
     if not args.no_extras:
-        result["water"] = _water(torch, msm, WL, np, O if check else None, args.steps, check)
-        result["autograd"] = _autograd_vs_plain(torch, msm, WL, np, O if check else None, check)
-        result["batched"] = _batched_vs_plain(torch, msm, WL, np, O if check else None, check)
-        result["free_ions_fp64"] = _free_ions(torch, msm, WL, np, O if check else None, check)
-        result["md"] = _md(torch, msm, np)
+        want = set(args.extras.split(","))
+        Oc = O if check else None
+        if "water" in want:
+            result["water"] = _water(torch, msm, WL, np, Oc, args.steps, check)
+        if "autograd" in want:
+            result["autograd"] = _autograd_vs_plain(torch, msm, WL, np, Oc, check)
+        if "batched" in want:
+            result["batched"] = _batched_vs_plain(torch, msm, WL, np, Oc, check)
+        if "free_ions" in want:
+            result["free_ions_fp64"] = _free_ions(torch, msm, WL, np, Oc, check)
+        if "md" in want:
+            result["md"] = _md(torch, msm, np)
 
     if not args.no_grid_sweep:
         try:
