@@ -81,6 +81,32 @@ msm_status msm_plan_create(msm_plan* out, const double box[3], unsigned periodic
                            int quasi_degree_M);
 
 /*
+ * msm_energy_forces_cell_gradient -- msm_energy_forces plus the derivative
+ * of the energy with respect to the cell, for plans made by
+ * msm_plan_create_cell (Sec. "MSM core algorithm", long-range part: the
+ * stencils follow the current cell; their derivative gives the stress):
+ *   dEdH     device double[9], dE/dH[3 r + c] with H the matrix whose
+ *            columns are the lattice vectors (H[r][c] = component r of
+ *            vector c), taken at fixed Cartesian positions.
+ * The derivative is that of the MSM energy with the grid counts held: the
+ * short-range pairs' virial, each level's derivative stencils
+ * k_l'(r)/r x x^T applied to omega'-filtered grid charges, and the top
+ * level's table differentiated in H (central differences on the host,
+ * relative step 1e-5, built on the first call after each cell change);
+ * with the particles' term sum_i F_i (H^{-1} r_i)^T.  The stress tensor is
+ * -(1/V) dE/dH H^T.  forces is required; energy, dEdq and the stream as for
+ * msm_energy_forces.  One stream; allocates on its first call per cell
+ * (stencils) and per plan (three FP64 level-1 grids).  The cutoff must stay
+ * below half the cell's smallest width under a relative change of 1e-5 of
+ * the cell (the top derivative builds such plans).  Errors: as
+ * msm_energy_forces, MSM_ERR_UNSUPPORTED for non-triclinic plans,
+ * MSM_ERR_GRID when a derivative stencil exceeds the convolution's window.
+ */
+msm_status msm_energy_forces_cell_gradient(msm_plan plan, int n, const void* pos, const void* q,
+                                           double* energy, void* forces, void* dEdq,
+                                           double* dEdH, void* stream);
+
+/*
  * msm_plan_create_kernel -- msm_plan_create for the kernel k(r) = r^-nu,
  * nu = kernel: MSM_KERNEL_COULOMB (1, the same plan as msm_plan_create) or
  * MSM_KERNEL_DISPERSION (6).  The paper's splitting carries over unchanged

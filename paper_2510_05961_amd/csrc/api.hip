@@ -226,16 +226,15 @@ msm_status prepare_work(const msm_plan P, const WorkBufs& w, hipStream_t s) {
 // Uploads every level's stencil (and the k-samples of factored levels) in the
 // padded form the convolution reads; fails when a stencil exceeds the
 // convolution's LDS window.
-template <typename T>
-msm_status upload_stencils(msm_plan P) {
-  HostPlan& hp = P->hp;
-  msm_status st;
-  // an FP64 stencil [len2][len1][len0] as the convolution reads it: rows
-  // padded with zeros to conv_row_stride(len0), kConvRowPad zero rows before
-  // and after every plane, plus the [first, last] non-zero x range of every
-  // (unpadded) row
-  auto upload_stencil = [&](const std::vector<double>& A0, const int off[3], const int len0[3],
-                            int nz, double** dA, int2** dext, ConvGeom* cg) -> msm_status {
+// An FP64 stencil [len2][len1][len0] as the convolution reads it: rows
+// padded with zeros to conv_row_stride(len0), kConvRowPad zero rows before
+// and after every plane, plus the [first, last] non-zero x range of every
+// (unpadded) row; mirrored z-planes folded when they are mirrored.
+static msm_status upload_padded(msm_plan P, const std::vector<double>& A0, const int off[3],
+                                const int len0[3], int nz, double** dA, int2** dext,
+                                ConvGeom* cg) {
+  const HostPlan& hp = P->hp;
+  {
     std::vector<double> A;
     *cg = mirror_stencil(A0, off, len0, hp.periodic[2] != 0, nz, A);
     const int* len = cg->len;
@@ -266,6 +265,16 @@ msm_status upload_stencils(msm_plan P) {
         hipMemcpy(*dext, ext.data(), ext.size() * sizeof(int2), hipMemcpyHostToDevice))
       return MSM_ERR_HIP;
     return MSM_OK;
+  }
+}
+
+template <typename T>
+msm_status upload_stencils(msm_plan P) {
+  HostPlan& hp = P->hp;
+  msm_status st;
+  auto upload_stencil = [&](const std::vector<double>& A0, const int off[3], const int len0[3],
+                            int nz, double** dA, int2** dext, ConvGeom* cg) -> msm_status {
+    return upload_padded(P, A0, off, len0, nz, dA, dext, cg);
   };
   for (int l = 1; l <= hp.L; ++l) {
     LevelGeom& g = hp.lev[l - 1];
@@ -802,9 +811,137 @@ msm_status set_cell(msm_plan P, const double cell[9]) {
     P->S[l] = nullptr;
     P->srowext[l] = nullptr;
   }
+  // the cell-derivative stencils follow the cell (rebuilt at the next such call)
+  for (int l = 0; l < kMaxLevels; ++l)
+    for (int k = 0; k < 6; ++k) {
+      free_plan_buffer(P, P->TS[l][k]);
+      free_plan_buffer(P, P->TSext[l][k]);
+      P->TS[l][k] = nullptr;
+      P->TSext[l][k] = nullptr;
+    }
+  for (int k = 0; k < 9; ++k) {
+    free_plan_buffer(P, P->dKd[k]);
+    free_plan_buffer(P, P->dKext[k]);
+    P->dKd[k] = nullptr;
+    P->dKext[k] = nullptr;
+  }
+  P->stress_ready = false;
   P->hp = hp;
   P->ncell = hp.nc[0] * hp.nc[1] * hp.nc[2];
   return upload_stencils<T>(P);
+}
+
+// Cell derivative of a triclinic plan, dE/dH at fixed Cartesian positions
+// (H with the lattice vectors as columns): at fixed fractional coordinates s
+// the grid charges do not move and
+//   dE/dH|_s = (V0 + sum_{l<L} V_l) H^{-T} + dE_L/dH,
+// V0 = -1/2 sum_i q_i sum_j q_j f(r) d d^T (the short-range virial),
+// V_l = 1/2 sum_m q~_m (T^l * w)_m with w = omega' * q~^l (the level's
+// derivative stencils), dE_L/dH = 1/2 sum_m q~^L_m (dK^L * q~^L)_m; then
+// dE/dH|_r = dE/dH|_s + sum_i F_i s_i^T.  The stencils are built and uploaded
+// on the first call after a cell change.
+template <typename T>
+msm_status stress_setup(msm_plan P) {
+  if (P->stress_ready) return MSM_OK;
+  const HostPlan& hp = P->hp;
+  const int zero3[3] = {0, 0, 0};
+  msm_status st;
+  auto check = [&](const LevelGeom& g, const ConvGeom& c) -> msm_status {
+    ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, c.off, c.len, sizeof(T), c.fold);
+    if (conv_lds_bytes(cp, sizeof(T)) > 64 * 1024 || cp.lds_w > kConvMaxLW) return MSM_ERR_GRID;
+    return MSM_OK;
+  };
+  try {
+    for (int l = 1; l < hp.L; ++l) {
+      const LevelGeom& g = hp.lev[l - 1];
+      std::vector<double> Tv[6];
+      cell_stress_stencils(hp, l, Tv);
+      for (int k = 0; k < 6; ++k) {
+        if ((st = upload_padded(P, Tv[k], g.s_off, g.s_len, g.n[2], &P->TS[l - 1][k],
+                                &P->TSext[l - 1][k], &P->tsgeom[l - 1][k])))
+          return st;
+        if ((st = check(g, P->tsgeom[l - 1][k]))) return st;
+      }
+    }
+    std::vector<double> dK[9];
+    const int rc = top_cell_derivative(hp, dK);
+    if (rc != MSM_OK) return (msm_status)rc;
+    const LevelGeom& gL = hp.lev[hp.L - 1];
+    for (int k = 0; k < 9; ++k) {
+      if ((st = upload_padded(P, dK[k], gL.off, gL.len, gL.n[2], &P->dKd[k], &P->dKext[k],
+                              &P->dkgeom[k])))
+        return st;
+      if ((st = check(gL, P->dkgeom[k]))) return st;
+    }
+  } catch (...) {
+    return MSM_ERR_OOM;
+  }
+  if (!P->sgrid) {  // u, t, y (FP64) and w (plan precision) of level 1's size, then 30 sums
+    const size_t G1 = (size_t)hp.lev[0].G;
+    if ((st = hip_alloc(P, (void**)&P->sgrid, sizeof(double) * (4 * G1 + 32)))) return st;
+    if ((st = hip_alloc(P, (void**)&P->cellm, 9 * sizeof(double)))) return st;
+  }
+  if (hipMemcpy(P->cellm, hp.Hinv, 9 * sizeof(double), hipMemcpyHostToDevice)) return MSM_ERR_HIP;
+  P->stress_ready = true;
+  return MSM_OK;
+}
+
+template <typename T>
+msm_status cell_gradient(msm_plan P, int n, const T* pos, const T* q, double* energy, T* F,
+                         T* dEdq, double* dEdH, hipStream_t s) {
+  msm_status st = stress_setup<T>(P);
+  if (st != MSM_OK) return st;
+  if ((st = forward<T>(P, n, pos, q, nullptr, energy, F, dEdq, s))) return st;
+  const HostPlan& hp = P->hp;
+  const int zero3[3] = {0, 0, 0};
+  const long long G1 = hp.lev[0].G;
+  double* u = P->sgrid;
+  double* t = u + G1;
+  double* y = t + G1;
+  T* w = reinterpret_cast<T*>(y + G1);
+  double* acc = u + 4 * G1;
+  launch_fill<double>(acc, 30, 0.0, s);
+  // short-range virial (the forward's cluster layout)
+  launch_pair_virial<T>(hp.p, n, P->ncell, P->w->cl_start, (const vec4_t<T>*)P->w->cpos,
+                        (const vec4_t<T>*)P->w->cbox, P->w->cinfo, pair_params<T>(hp), acc, s);
+  // levels 1..L-1: w = omega' * q~, then six derivative stencils on w
+  for (int l = 1; l < hp.L; ++l) {
+    const LevelGeom& g = hp.lev[l - 1];
+    const T* qg = (const T*)P->w->qg[l - 1];
+    launch_to_double<T>(qg, u, g.G, s);
+    OmegaParams op;
+    for (int k = 0; k < 3; ++k) {
+      op.n[k] = g.n[k];
+      op.next[k] = g.n[k];
+      op.per[k] = 1;
+    }
+    op.M = hp.M;
+    for (int k = 0; k < 25; ++k) op.omega[k] = k <= hp.M ? hp.omega[k] : 0.0;
+    launch_omega<T>(op, u, t, w, s);
+    for (int k = 0; k < 6; ++k) {
+      const ConvGeom& c = P->tsgeom[l - 1][k];
+      ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, c.off, c.len, sizeof(T), c.fold);
+      if (cp.nsplit > 1) launch_fill<double>(y, g.G, 0.0, s);
+      launch_conv<T, double>(cp, P->TS[l - 1][k], P->TSext[l - 1][k], w, y, s);
+      launch_dot<T>(qg, y, g.G, acc + 6 + k, s);
+    }
+  }
+  // top level: dK^L/dH_rc on q~^L
+  {
+    const LevelGeom& g = hp.lev[hp.L - 1];
+    const T* qg = (const T*)P->w->qg[hp.L - 1];
+    for (int k = 0; k < 9; ++k) {
+      const ConvGeom& c = P->dkgeom[k];
+      ConvParams cp = make_conv_params(g.n, g.n, zero3, hp.periodic, c.off, c.len, sizeof(T), c.fold);
+      if (cp.nsplit > 1) launch_fill<double>(y, g.G, 0.0, s);
+      launch_conv<T, double>(cp, P->dKd[k], P->dKext[k], qg, y, s);
+      launch_dot<T>(qg, y, g.G, acc + 12 + k, s);
+    }
+  }
+  // the particles' term, then the combination
+  launch_cell_fs<T>(n, pos, F, P->cellm, acc + 21, s);
+  launch_cell_combine(acc, P->cellm, dEdH, s);
+  return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
 }
 
 // Working memory of msm_energy_forces_noalloc: one array per GPU, held from
@@ -888,6 +1025,22 @@ msm_status msm_plan_set_cell(msm_plan plan, const double cell[9]) {
   if (!plan || plan->batch || !cell || !plan->hp.tri) return MSM_ERR_INVALID_ARG;
   if (!plan->device) return MSM_ERR_NO_DEVICE;
   return plan->hp.precision == MSM_FP64 ? set_cell<double>(plan, cell) : set_cell<float>(plan, cell);
+}
+
+msm_status msm_energy_forces_cell_gradient(msm_plan plan, int n, const void* pos, const void* q,
+                                           double* energy, void* forces, void* dEdq,
+                                           double* dEdH, void* stream) {
+  if (!plan || plan->batch) return MSM_ERR_INVALID_ARG;
+  if (!plan->device) return MSM_ERR_NO_DEVICE;
+  if (!plan->hp.tri) return MSM_ERR_UNSUPPORTED;
+  if (n < 0 || !energy || !forces || !dEdH || (n > 0 && (!pos || !q))) return MSM_ERR_INVALID_ARG;
+  if (n > plan->hp.max_n) return MSM_ERR_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->hp.precision == MSM_FP64)
+    return cell_gradient<double>(plan, n, (const double*)pos, (const double*)q, energy,
+                                 (double*)forces, (double*)dEdq, dEdH, s);
+  return cell_gradient<float>(plan, n, (const float*)pos, (const float*)q, energy, (float*)forces,
+                              (float*)dEdq, dEdH, s);
 }
 
 msm_status msm_plan_set_skin(msm_plan plan, double skin) {

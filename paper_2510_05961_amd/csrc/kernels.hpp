@@ -152,6 +152,24 @@ template <typename T>
 void launch_pair_cl(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
                     const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
                     double* phi0, T* F0, hipStream_t s);
+// sum_i q_i sum_j q_j f(r) d d^T of the short-range pairs (cell derivative),
+// added to acc[0..5] (xx, yy, zz, xy, xz, yz), FP64, Coulomb kernel
+template <typename T>
+void launch_pair_virial(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
+                        const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
+                        double* acc, hipStream_t s);
+// Cell-derivative helpers (csrc/stress.hip): FP64 copy of a grid; acc[k] +=
+// sum_m a_m b_m; acc9 += sum_i F_i (Hinv r_i)^T; and the final combination
+// dEdH = (-A0/2 + Vg/2) H^{-T} + D/2 + FS (A0, Vg symmetric 6-vectors; D,
+// FS 3 x 3 row-major) from acc = [A0 6, Vg 6, D 9, FS 9].
+template <typename T>
+void launch_to_double(const T* a, double* b, long long count, hipStream_t s);
+template <typename T>
+void launch_dot(const T* a, const double* b, long long count, double* acc, hipStream_t s);
+template <typename T>
+void launch_cell_fs(int n, const T* pos, const T* F, const double* Hinv, double* acc9,
+                    hipStream_t s);
+void launch_cell_combine(const double* acc, const double* Hinv, double* dEdH, hipStream_t s);
 // cell list geometry in FP64 (bricks of the staged anterpolation)
 struct CellGrid {
   int nc[3];

@@ -587,6 +587,70 @@ __global__ void __launch_bounds__(kClusterThreads)
   }
 }
 
+// Virial of the short-range part, sum_i q_i sum_j q_j f(r) d d^T over every
+// pair within a (both orders; f = -k0'(r)/r, d = r_i - r_j of the image),
+// for the cell derivative: the same culled walk as k_pair_pc, six sums per
+// lane, reduced over the wave and added to acc[0..5] (xx, yy, zz, xy, xz, yz)
+// in FP64.
+template <typename T, int P>
+__global__ void __launch_bounds__(kClusterThreads)
+    k_pair_virial(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
+                  const vec4_t<T>* __restrict__ cbox, const int4* __restrict__ cinfo,
+                  PairParams<T> pp, double* __restrict__ acc) {
+  __shared__ vec4_t<T> rings[kClusterThreads / 64][kRing];
+  __shared__ int glists[kClusterThreads / 64][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * (kClusterThreads / 64) + wv);
+  if (ic >= cl_start[pp.ncell]) return;
+  const int il = lane >> 3;
+  const int4 inf = cinfo[ic];
+  const vec4_t<T> pi = cpos[(size_t)ic * 8 + il];
+  vec4_t<T> blo, bhi;
+  cluster_box<T>(cbox, ic, inf.y, blo, bhi);
+  const T f_top = in_vgpr(pp.fr[P - 2]);
+  const T a2v = in_vgpr(pp.a2);
+  vec4_t<T> far;
+  far.x = far.y = far.z = T(1e15);
+  far.w = T(0);
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  T vc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};  // one neighbour cell's part
+  for_each_j_culled<T>(
+      pp, cl_start, cpos, cbox, inf.z, blo, bhi, rings[wv], glists[wv], far,
+      [&](const vec4_t<T>& pj) {
+        const T dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const bool ok = r2 < pp.a2 && r2 > T(0);
+        const T r2c = ok ? r2 : a2v;
+        const T qj = ok ? pj.w : T(0);
+        const T rinv = rsqrt_t(r2c);
+        T pf = f_top;
+#pragma unroll
+        for (int k = P - 3; k >= 0; --k) pf = pf * r2c + pp.fr[k];
+        const T fs = qj * (rinv * rinv * rinv + pf);
+        vc[0] += fs * dx * dx;
+        vc[1] += fs * dy * dy;
+        vc[2] += fs * dz * dz;
+        vc[3] += fs * dx * dy;
+        vc[4] += fs * dx * dz;
+        vc[5] += fs * dy * dz;
+      },
+      [&]() {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          v[k] += (double)vc[k];
+          vc[k] = T(0);
+        }
+      });
+  const double qi = (double)pi.w;  // zero in padding slots
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double t = (v[k] + (double)vc[k]) * qi;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) atomicAdd(&acc[k], t);
+  }
+}
+
 // Cotangents in cluster-slot order (zero in padding slots): the force
 // cotangent in x, y, z, the cotangent of phi in w (each zero without one).
 template <typename T>
@@ -811,10 +875,27 @@ void launch_pair_vjp_cl(int p, int n, int ncell, const int* cl_start, const int4
   }
 }
 
+template <typename T>
+void launch_pair_virial(int p, int n, int ncell, const int* cl_start, const vec4_t<T>* cpos,
+                        const vec4_t<T>* cbox, const int4* cinfo, const PairParams<T>& pp,
+                        double* acc, hipStream_t s) {
+  if (n <= 0) return;
+  const int ncl = cluster_capacity(n, ncell);
+  const dim3 grid((ncl + 3) / 4), block(kClusterThreads);
+  switch (p) {
+    case 4: hipLaunchKernelGGL((k_pair_virial<T, 4>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
+    case 6: hipLaunchKernelGGL((k_pair_virial<T, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
+    case 8: hipLaunchKernelGGL((k_pair_virial<T, 8>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
+  }
+}
+
 #define MSM_INST_CLUSTER(T)                                                                    \
   template void launch_cluster_layout<T>(int, int, int, const int*, int*, const BinParams<T>&, \
                                          const vec4_t<T>*, vec4_t<T>*, int*, vec4_t<T>*,       \
                                          vec4_t<T>*, int4*, int*, const int*, int, hipStream_t); \
+  template void launch_pair_virial<T>(int, int, int, const int*, const vec4_t<T>*,             \
+                                      const vec4_t<T>*, const int4*, const PairParams<T>&,     \
+                                      double*, hipStream_t);                                   \
   template void launch_pair_cl<T>(int, int, int, const int*, const vec4_t<T>*,                 \
                                   const vec4_t<T>*, const int4*, const PairParams<T>&,         \
                                   double*, T*, hipStream_t);                                   \

@@ -710,6 +710,98 @@ void cell_list_geometry(HostPlan& P) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Cell derivatives of a triclinic plan (dE/dH at fixed fractional
+// coordinates).  Level l < L: E_l = 1/2 sum_m q~_m (S^l * w)_m with
+// w = omega' * q~ (eq. kernel_stencil_by_conv_with_universal_coeff) and
+// S^l(d) = k_l(|A_l d|), A_l = H diag(1/N_l); at fixed d, d/dH of k_l(|x|)
+// with x = A_l d is k_l'(|x|)/|x| x (H^{-1} x)^T, so the level contributes
+// 1/2 sum_m q~_m (T^l_ab * w)_m (H^{-T}) with T^l_ab(d) = k_l'(r)/r x_a x_b;
+// and T^l = T^1 / 2^(l-1) as for S.
+
+// d gamma / d rho from the coefficients in t = rho^2
+static double gamma_t_d1(const double* c, int p, double rho) {
+  if (rho >= 1.0) return -1.0 / (rho * rho);
+  const double t = rho * rho;
+  double s = 2.0 * (p - 1) * c[p - 1];
+  for (int k = p - 2; k >= 1; --k) s = s * t + 2.0 * k * c[k];
+  return rho * s;
+}
+
+void cell_stress_stencils(const HostPlan& P, int l, std::vector<double> T[6]) {
+  const LevelGeom& g1 = P.lev[0];
+  const LevelGeom& g = P.lev[l - 1];
+  int R[3];
+  for (int k = 0; k < 3; ++k) R[k] = P.W1[k] - P.M;
+  double A1[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) A1[3 * r + c] = P.H[3 * r + c] * g1.h[c];
+  const size_t vol = (size_t)g.s_len[0] * g.s_len[1] * g.s_len[2];
+  for (int i = 0; i < 6; ++i) T[i].assign(vol, 0.0);
+  const double scale = std::ldexp(1.0, -(l - 1)), a = P.a;
+  for (int z = -R[2]; z <= R[2]; ++z)
+    for (int y = -R[1]; y <= R[1]; ++y)
+      for (int x = -R[0]; x <= R[0]; ++x) {
+        const int d[3] = {x, y, z};
+        double v[3];
+        for (int k = 0; k < 3; ++k) v[k] = A1[3 * k] * x + A1[3 * k + 1] * y + A1[3 * k + 2] * z;
+        const double r = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (r == 0.0 || r >= 2.0 * a) continue;  // k_1 vanishes beyond 2a
+        // k_1 = gamma(r/a)/a - gamma(r/2a)/2a
+        const double kp = gamma_t_d1(P.gcoef, P.p, r / a) / (a * a) -
+                          gamma_t_d1(P.gcoef, P.p, r / (2.0 * a)) / (4.0 * a * a);
+        const double f = scale * kp / r;
+        int idx[3];
+        for (int k = 0; k < 3; ++k) {
+          const int e = d[k] - g.s_off[k];
+          idx[k] = ((e % g.n[k]) + g.n[k]) % g.n[k];
+        }
+        const size_t o = ((size_t)idx[2] * g.s_len[1] + idx[1]) * g.s_len[0] + idx[0];
+        T[0][o] += f * v[0] * v[0];
+        T[1][o] += f * v[1] * v[1];
+        T[2][o] += f * v[2] * v[2];
+        T[3][o] += f * v[0] * v[1];
+        T[4][o] += f * v[0] * v[2];
+        T[5][o] += f * v[1] * v[2];
+      }
+}
+
+// The top level's K^L differentiated in H_rc at fixed fractional offsets, by
+// central differences of plans built for H +- eps e_rc with the grid counts
+// held (the top table includes the triclinic Ewald sum, whose every part
+// depends on the cell); dK[3 r + c] has K^L's layout.
+int top_cell_derivative(const HostPlan& P, std::vector<double> dK[9]) {
+  const int L = P.L;
+  int ntop[3];
+  for (int k = 0; k < 3; ++k) ntop[k] = P.lev[L - 1].n[k];
+  double scale = 0.0;
+  for (int k = 0; k < 9; ++k) scale = std::max(scale, std::fabs(P.H[k]));
+  const double eps = 1e-5 * scale;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      std::vector<double> Kpm[2];
+      for (int sgn = 0; sgn < 2; ++sgn) {
+        double cell[9];  // rows: lattice vectors (columns of H)
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k) cell[3 * k + j] = P.H[3 * j + k];
+        cell[3 * c + r] += sgn == 0 ? eps : -eps;
+        HostPlan Q;
+        const int rc = build_host_plan(Q, nullptr, 7, P.p, P.h_req, P.a, P.L, P.precision,
+                                       P.max_n, P.M, cell, ntop, P.skin, P.nu);
+        if (rc != MSM_OK) return rc;
+        const LevelGeom& q = Q.lev[L - 1];
+        for (int k = 0; k < 3; ++k)
+          if (q.len[k] != P.lev[L - 1].len[k] || q.off[k] != P.lev[L - 1].off[k])
+            return MSM_ERR_GRID;
+        Kpm[sgn] = q.K;
+      }
+      dK[3 * r + c].resize(Kpm[0].size());
+      for (size_t i = 0; i < Kpm[0].size(); ++i)
+        dK[3 * r + c][i] = (Kpm[0][i] - Kpm[1][i]) / (2.0 * eps);
+    }
+  return MSM_OK;
+}
+
 std::string describe_json(const HostPlan& P) {
   std::ostringstream o;
   o.precision(17);

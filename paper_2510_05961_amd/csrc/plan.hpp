@@ -74,6 +74,13 @@ int build_host_plan(HostPlan& P, const double box[3], unsigned periodic_mask, in
 
 std::string describe_json(const HostPlan& P);
 
+// Cell-derivative stencils of a triclinic plan: T^l_ab(d) = k_l'(r)/r x_a x_b
+// (ab = xx, yy, zz, xy, xz, yz) in level l's sample layout (s_off, s_len),
+// 1 <= l < L; and the top level's dK^L/dH_rc (K^L's layout) by central
+// differences of plans for H +- eps e_rc.
+void cell_stress_stencils(const HostPlan& P, int l, std::vector<double> T[6]);
+int top_cell_derivative(const HostPlan& P, std::vector<double> dK[9]);
+
 // Softener pieces used by the batch planner as well.
 void softener_coefficients(int p, double* c, int nu = 1);
 std::vector<double> quasi_sequence(int p, int M);

@@ -163,6 +163,19 @@ struct msm_plan_s {
   // cells per axis the working memory was laid out for (later cell lists
   // never have more)
   int nc_cap[3] = {0, 0, 0};
+  // cell derivative (msm_energy_forces_cell_gradient, triclinic plans): the
+  // levels' derivative stencils T^l_ab and the top level's dK^L/dH_rc as
+  // uploaded (built at the first such call after a cell change), and FP64
+  // working grids plus the accumulators
+  double* TS[msm::kMaxLevels][6] = {};
+  int2* TSext[msm::kMaxLevels][6] = {};
+  msm::ConvGeom tsgeom[msm::kMaxLevels][6] = {};
+  double* dKd[9] = {};
+  int2* dKext[9] = {};
+  msm::ConvGeom dkgeom[9] = {};
+  double* sgrid = nullptr;  // 3 FP64 grids of level 1's size, then 30 accumulators
+  double* cellm = nullptr;  // H^{-1} (9 doubles, device)
+  bool stress_ready = false;
   // side streams of the forward DAG (default priority, non-blocking) and the
   // fork/join events between them and the caller's stream
   hipStream_t sb = nullptr, sc = nullptr, sd = nullptr;

@@ -26,6 +26,7 @@ EXPORTS = ("msm_plan_create", "msm_plan_create_kernel", "msm_plan_create_cell", 
            "msm_plan_get_stencil", "msm_plan_grid_dims", "msm_workspace_bytes",
            "msm_energy_forces", "msm_energy_forces_noalloc", "msm_backward", "msm_backward_full",
            "msm_plan_status", "msm_plan_set_skin", "msm_plan_skin_stats",
+           "msm_energy_forces_cell_gradient",
            "msm_plan_get_grid",
            "msm_batch_plan_create", "msm_batch_energy_forces", "msm_status_string",
            "msm_plan_set_profiling", "msm_plan_get_profile", "msm_plan_set_profile_stages",
@@ -68,6 +69,7 @@ def lib():
         L.msm_backward.argtypes = [P, i, P, P, P, P, P, P, P, P]
         L.msm_backward_full.argtypes = [P, i, P, P, P, P, P, P, P, P, P]
         L.msm_plan_set_skin.argtypes = [P, d]
+        L.msm_energy_forces_cell_gradient.argtypes = [P, i, P, P, P, P, P, P, P]
         L.msm_plan_skin_stats.argtypes = [P, ctypes.POINTER(ctypes.c_longlong),
                                           ctypes.POINTER(ctypes.c_longlong), P]
         L.msm_plan_status.argtypes = [P, P]
@@ -225,6 +227,21 @@ class Plan:
         _check(lib().msm_energy_forces(self._h, n, _ptr(pos), _ptr(q), _ptr(ws), _ptr(E),
                                        _ptr(F), _ptr(dq), _stream(stream)), "msm_energy_forces")
         return E, F, dq
+
+    def energy_forces_cell_gradient(self, pos, q, stream=None):
+        """(E, F, dEdq, dE/dH [3, 3] f64) of a triclinic plan; dE/dH at fixed
+        Cartesian positions, H with the lattice vectors as columns."""
+        import torch
+        n = q.shape[0]
+        E = torch.empty(1, dtype=torch.float64, device=pos.device)
+        F = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+        dq = torch.empty(n, dtype=self.dtype, device=pos.device)
+        G = torch.empty((3, 3), dtype=torch.float64, device=pos.device)
+        _check(lib().msm_energy_forces_cell_gradient(self._h, n, _ptr(pos), _ptr(q), _ptr(E),
+                                                     _ptr(F), _ptr(dq), _ptr(G),
+                                                     _stream(stream)),
+               "msm_energy_forces_cell_gradient")
+        return E, F, dq, G
 
     def energy_forces_noalloc(self, pos, q, out, ws=None, stream=None):
         """msm_energy_forces_noalloc into the caller's outputs out = (E[1] f64,
