@@ -43,7 +43,7 @@ typedef struct msm_plan_s* msm_plan;
 typedef enum {
   MSM_OK = 0,
   MSM_ERR_INVALID_ARG = 1,       /* bad parameter, NULL pointer, wrong plan kind */
-  MSM_ERR_UNSUPPORTED = 2,       /* odd/unsupported order, periodicity other than none/xyz/xy */
+  MSM_ERR_UNSUPPORTED = 2,       /* unsupported order, kernel or periodicity for the call */
   MSM_ERR_CUTOFF_TOO_LARGE = 3,  /* a > box/2 on a periodic axis (minimum image) */
   MSM_ERR_GRID = 4,              /* grid or stencil too large for the plan limits */
   MSM_ERR_OUT_OF_DOMAIN = 5,     /* device flag: coordinate outside [0, box] on a free axis */
@@ -60,7 +60,16 @@ enum { MSM_FP32 = 0, MSM_FP64 = 1 };
  * msm_plan_create -- set up the MSM for one orthorhombic box (Sec. "High-level
  * interface": cell, pbc, level_one_spacings, level_zero_cutoff, p).
  *   box[3]          host, box edge lengths (> 0).
- *   periodic_mask   bit k set = axis k periodic; allowed: 0, 7, 3 (x,y periodic).
+ *   periodic_mask   bit k set = axis k periodic (0..7, any combination; 8 or
+ *                   more: MSM_ERR_INVALID_ARG).  The top level sums the
+ *                   periodic images with the Ewald method of the periodic
+ *                   axes: 3-D (tin-foil boundary, neutralising background),
+ *                   2-D (alpha = 3 / the shorter periodic edge, which fixes
+ *                   the constant of a non-neutral slab) or 1-D (the constant
+ *                   of a non-neutral line is the one for which a unit charge's
+ *                   potential tends to -(2/L) ln(rho/L) far from the axis,
+ *                   L its period, rho the distance to the axis).  Neutral
+ *                   systems depend on neither convention.
  *   order           B-spline order p (Sec. "B-spline interpolation"): 4, 6 or 8.
  *   h               requested level-1 spacing.  Free axes use h exactly; a
  *                   periodic axis uses box/N_1 with N_1 = N_top 2^(L-1),

@@ -835,6 +835,154 @@ double orc_ewald2d(const double box[3], double alpha, const double x[3], int reg
   return real + recip + k0;
 }
 
+/* ------------------------------------------------------------------------
+ * 1-D Ewald sum: one periodic axis of length L, the other two free.  With
+ * rho the distance from the periodic axis and z the coordinate along it,
+ * Poisson summation of the smooth part erf(alpha r)/r along the axis gives
+ *   psi(x) = sum_n erfc(alpha r_n)/r_n
+ *          + (1/L) [gamma_E + 2 ln(alpha L) - Ein(alpha^2 rho^2)]
+ *          + (2/L) sum_{m >= 1} cos(k_m z) F(k_m, rho),     k_m = 2 pi m / L,
+ *   F(k, rho) = int_{k^2/(4 alpha^2)}^inf exp(-s - rho^2 k^2/(4 s)) ds / s
+ *             = int_0^inf exp(-b e^t - alpha^2 rho^2 e^-t) dt,  b = k^2/(4 alpha^2),
+ * (the incomplete Bessel function; 2 K0(k rho) as alpha -> inf).  The k = 0
+ * term diverges logarithmically; the constant kept is the one for which
+ * psi -> -(2/L) ln(rho/L) far from the axis, the same for every alpha, so
+ * non-neutral systems get that convention and neutral ones are free of it.
+ * Ein(x) = int_0^x (1 - e^-v)/v dv = gamma_E + ln x + E1(x).
+ * ---------------------------------------------------------------------- */
+#define ORC_EULER_GAMMA 0.57721566490153286061
+
+/* Ein by its power series (Abramowitz and Stegun 5.1.11) for x <= 2, else
+ * through E1 by its continued fraction (A&S 5.1.22, evaluated from the tail
+ * with a fixed depth that is ample for x > 2). */
+static double orc_ein(double x)
+{
+  if (x <= 2.0) {
+    double term = x, sum = x;
+    for (int k = 2; k < 200 && fabs(term) > 1e-20 * fabs(sum); ++k) {
+      term *= -x * (k - 1) / ((double)k * k);
+      sum += term;
+    }
+    return sum;
+  }
+  /* E1(x) = e^-x / (x + 1 - 1^2/(x + 3 - 2^2/(x + 5 - ...))) */
+  double f = x + 2.0 * 400 + 1.0;
+  for (int k = 400; k >= 1; --k) f = x + 2.0 * k - 1.0 - (double)k * k / f;
+  const double e1 = exp(-x) / f;
+  return e1 + ORC_EULER_GAMMA + log(x);
+}
+
+/* 16-point Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on
+ * P_16 from the Chebyshev-like first guess). */
+static void orc_gauss16(double xg[16], double wg[16])
+{
+  const int n = 16;
+  for (int i = 0; i < n; ++i) {
+    double x = cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-17) break;
+    }
+    xg[i] = x;
+    wg[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+}
+
+/* F(k, rho) above, over the t-range where the exponent b e^t + c e^-t stays
+ * below 45 (outside it the integrand is below e^-45 and the tails add less
+ * than 1e-18), in panels of width <= 1/8 with 16 Gauss points each. */
+static double orc_incomplete_bessel(double b, double c, const double xg[16],
+                                    const double wg[16])
+{
+  const double E = 45.0, D = E * E - 4.0 * b * c;
+  if (D <= 0.0) return 0.0;
+  const double t1 = log((E + sqrt(D)) / (2.0 * b));
+  if (t1 <= 0.0) return 0.0;
+  double t0 = log((E - sqrt(D)) / (2.0 * b));
+  if (t0 < 0.0) t0 = 0.0;
+  const int np = (int)ceil((t1 - t0) * 8.0);
+  const double w = (t1 - t0) / np;
+  double sum = 0.0;
+  for (int j = 0; j < np; ++j) {
+    const double mid = t0 + (j + 0.5) * w;
+    for (int i = 0; i < 16; ++i) {
+      const double t = mid + 0.5 * w * xg[i];
+      sum += 0.5 * w * wg[i] * exp(-b * exp(t) - c * exp(-t));
+    }
+  }
+  return sum;
+}
+
+double orc_ewald1d(const double box[3], int axis, double alpha, const double x[3], int reg)
+{
+  const double L = box[axis], z = x[axis];
+  double rho2 = 0.0;
+  for (int k = 0; k < 3; ++k)
+    if (k != axis) rho2 += x[k] * x[k];
+  const double rc = ORC_EWALD_X / alpha;
+  const int nr = (int)ceil((rc + fabs(z)) / L) + 1;
+  double real = 0.0;
+  for (int j = -nr; j <= nr; ++j) {
+    const double dz = z + j * L;
+    const double r = sqrt(rho2 + dz * dz);
+    if (r == 0.0) {
+      if (!reg) return INFINITY;
+      real -= 2.0 * alpha / sqrt(M_PI);
+      continue;
+    }
+    if (r > rc) continue;
+    real += erfc(alpha * r) / r;
+  }
+  const double c = alpha * alpha * rho2;
+  const double k0 = (ORC_EULER_GAMMA + 2.0 * log(alpha * L) - orc_ein(c)) / L;
+  double xg[16], wg[16];
+  orc_gauss16(xg, wg);
+  double recip = 0.0;
+  for (int m = 1;; ++m) {
+    const double k = 2.0 * M_PI * m / L, b = k * k / (4.0 * alpha * alpha);
+    if (b > 45.0) break; /* F <= E1(b) < 1e-21 from here on */
+    recip += cos(k * z) * orc_incomplete_bessel(b, c, xg, wg);
+  }
+  return real + k0 + 2.0 * recip / L;
+}
+
+/* psi for any set of periodic axes (bit k of mask = axis k periodic): the
+ * 3-D sum, the slab sum with the free axis moved to z, or the 1-D sum. */
+double orc_ewald_psi(const double box[3], unsigned mask, double alpha, const double x[3],
+                     int reg)
+{
+  if (mask == 7) return orc_ewald3d(box, alpha, x, reg);
+  int np = 0, axis = 0, freeax = 0;
+  for (int k = 0; k < 3; ++k) {
+    if ((mask >> k) & 1) {
+      ++np;
+      axis = k;
+    } else {
+      freeax = k;
+    }
+  }
+  if (np == 1) return orc_ewald1d(box, axis, alpha, x, reg);
+  if (np != 2) return NAN;
+  double b2[3], x2[3];
+  int o = 0;
+  for (int k = 0; k < 3; ++k)
+    if (k != freeax) {
+      b2[o] = box[k];
+      x2[o++] = x[k];
+    }
+  b2[2] = box[freeax];
+  x2[2] = x[freeax];
+  return orc_ewald2d(b2, alpha, x2, reg);
+}
+
 static double det3(const double A[9])
 {
   return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
@@ -908,6 +1056,21 @@ void orc_ewald_potentials_cell(const double H[9], double alpha, int n, const dou
       double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
                      pos[3 * i + 2] - pos[3 * j + 2]};
       s += q[j] * orc_ewald3d_cell(H, alpha, d, j == i);
+    }
+    phi[i] = s;
+  }
+}
+
+void orc_ewald_potentials_mask(const double box[3], unsigned mask, double alpha, int n,
+                               const double* pos, const double* q, double* phi)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                     pos[3 * i + 2] - pos[3 * j + 2]};
+      s += q[j] * orc_ewald_psi(box, mask, alpha, d, j == i);
     }
     phi[i] = s;
   }

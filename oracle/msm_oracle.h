@@ -112,12 +112,21 @@ void orc_direct_nu(int nu, int n, const double* pos, const double* q, double* ph
 
 /* Ewald potential of a unit charge plus its periodic images, tin-foil
  * boundary and neutralising background; 3-D (all axes periodic) and 2-D
- * slab (x, y periodic, z free).  reg = 1 returns lim (psi - 1/|x|) at x = 0. */
+ * slab (x, y periodic, z free); the 1-D sum below.  reg = 1 returns
+ * lim (psi - 1/|x|) at x = 0. */
 double orc_ewald3d(const double box[3], double alpha, const double x[3], int reg);
 /* The 3-D Ewald potential for the lattice spanned by the columns of H. */
 double orc_ewald3d_cell(const double H[9], double alpha, const double x[3], int reg);
 double orc_ewald2d(const double box[3], double alpha, const double x[3], int reg);
+/* 1-D sum: axis periodic (length box[axis]), the other two free; the
+ * constant is the one for which psi -> -(2/L) ln(rho/L) far from the axis. */
+double orc_ewald1d(const double box[3], int axis, double alpha, const double x[3], int reg);
+/* psi for the periodic axes of mask (bit k = axis k): 7, any two, any one. */
+double orc_ewald_psi(const double box[3], unsigned mask, double alpha, const double x[3],
+                     int reg);
 /* phi_i = sum_j q_j psi(r_i - r_j), with psi_reg(0) for j = i. */
+void orc_ewald_potentials_mask(const double box[3], unsigned mask, double alpha, int n,
+                               const double* pos, const double* q, double* phi);
 void orc_ewald_potentials(const double box[3], int slab, double alpha, int n,
                           const double* pos, const double* q, double* phi);
 void orc_ewald_potentials_cell(const double H[9], double alpha, int n, const double* pos,

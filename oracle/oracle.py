@@ -32,8 +32,11 @@ Readings where the paper is silent:
     (tin-foil boundary, neutralising background):
         G_L(x) = psi(x) - sum_images s(|x + j|),
         s(r)   = (1/r - gamma(r/R)/R) [r < R],  R = 2^(L-1) a.
-  * slab (x, y periodic, z free): 2-D Ewald with alpha = 3/min(Lx, Ly);
+  * two periodic axes: 2-D Ewald with alpha = 3/min of their lengths;
     only non-neutral slabs depend on that convention.
+  * one periodic axis: 1-D Ewald (Fourier part through the incomplete
+    Bessel function); the divergent constant of a non-neutral line is fixed
+    so that psi -> -(2/L) ln(rho/L) far from the axis.
 """
 from __future__ import annotations
 
@@ -130,6 +133,12 @@ def lib():
         for name in ("orc_ewald3d", "orc_ewald2d", "orc_ewald3d_cell"):
             getattr(L, name).argtypes = [P, d, P, i]
             getattr(L, name).restype = d
+        L.orc_ewald1d.argtypes = [P, i, d, P, i]
+        L.orc_ewald1d.restype = d
+        L.orc_ewald_psi.argtypes = [P, ctypes.c_uint, d, P, i]
+        L.orc_ewald_psi.restype = d
+        L.orc_ewald_potentials_mask.argtypes = [P, ctypes.c_uint, d, i, P, P, P]
+        L.orc_ewald_potentials_mask.restype = None
         L.orc_ewald_potentials.argtypes = [P, i, d, i, P, P, P]
         L.orc_ewald_potentials.restype = None
         L.orc_ewald_potentials_cell.argtypes = [P, d, i, P, P, P]
@@ -200,23 +209,47 @@ def ewald_alpha_slab(box):
     return 3.0 / min(box[0], box[1])
 
 
-def ewald_psi(box, x, slab=False, alpha=None, reg=False):
+def ewald_alpha_line(L):
+    """1-D sum: any alpha gives the same result; alpha L = 1 keeps both the
+    image sum (about 14 images) and the Fourier sum (2 terms) short."""
+    return 1.0 / L
+
+
+def _mask(periodic, slab):
+    if periodic is None:
+        return 3 if slab else 7
+    return sum(1 << k for k in range(3) if periodic[k])
+
+
+def _default_alpha(box, mask):
+    per = [k for k in range(3) if (mask >> k) & 1]
+    if len(per) == 3:
+        return ewald_alpha_3d(box)
+    if len(per) == 2:
+        return 3.0 / min(box[per[0]], box[per[1]])
+    return ewald_alpha_line(box[per[0]])
+
+
+def ewald_psi(box, x, slab=False, alpha=None, reg=False, periodic=None):
+    """Potential of a unit charge and its images along the periodic axes
+    (periodic: 3 bools; default all, or x and y with slab=True)."""
     box = _f64(box)
     x = _f64(x)
+    mask = _mask(periodic, slab)
     if alpha is None:
-        alpha = ewald_alpha_slab(box) if slab else ewald_alpha_3d(box)
-    f = lib().orc_ewald2d if slab else lib().orc_ewald3d
-    return f(_ptr(box), float(alpha), _ptr(x), int(reg))
+        alpha = _default_alpha(box, mask)
+    return lib().orc_ewald_psi(_ptr(box), mask, float(alpha), _ptr(x), int(reg))
 
 
-def ewald_potentials(box, pos, q, slab=False, alpha=None):
+def ewald_potentials(box, pos, q, slab=False, alpha=None, periodic=None):
     """phi_i = sum_j q_j psi(r_i - r_j) (j = i uses the regular part)."""
     box, pos, q = _f64(box), _f64(pos), _f64(q)
+    mask = _mask(periodic, slab)
     if alpha is None:
-        alpha = ewald_alpha_slab(box) if slab else ewald_alpha_3d(box)
+        alpha = _default_alpha(box, mask)
     phi = np.zeros(len(q))
-    lib().orc_ewald_potentials(_ptr(box), int(slab), float(alpha), len(q), _ptr(pos), _ptr(q),
-                               _ptr(phi))
+    lib().orc_ewald_potentials_mask(_ptr(box), mask, float(alpha), len(q), _ptr(pos), _ptr(q),
+                                    _ptr(phi))
     return phi
 
 
@@ -277,8 +310,7 @@ def direct_coulomb(pos, q):
 class OracleMSM:
     """Level-wise FP64 MSM for one orthorhombic box or triclinic cell.
 
-    box: 3 lengths; periodic: 3 bools (all free, all periodic, or x,y periodic
-    with z free); p: even B-spline order; h: requested level-1 spacing; a:
+    box: 3 lengths; periodic: 3 bools (any combination); p: even B-spline order; h: requested level-1 spacing; a:
     level-zero cutoff; L: number of grid levels; M: half-width of omega'
     (default p).
 
@@ -312,8 +344,6 @@ class OracleMSM:
         self.nu = int(nu)  # kernel r^-nu; other powers than 1 in free space only
         assert self.nu >= 1 and (self.nu == 1 or not any(self.periodic))
         assert self.p % 2 == 0 and self.p >= 2 and 1 <= self.L <= MAXL
-        npd = sum(self.periodic)
-        assert npd in (0, 3) or self.periodic == [True, True, False], "unsupported periodicity"
         for k in range(3):
             if self.periodic[k]:
                 w = widths[k] if self.cell is not None else self.box[k]
@@ -442,8 +472,7 @@ class OracleMSM:
                         elif r < R:
                             val -= 1.0 / r - gamma(p, r / R) / R
             return val
-        slab = npd == 2
-        val = ewald_psi(self.box, x, slab=slab, reg=True)
+        val = ewald_psi(self.box, x, periodic=self.periodic, reg=True)
         nimg = [int(math.ceil((R + abs(x[k])) / self.box[k])) + 1 if self.periodic[k] else 0
                 for k in range(3)]
         for jz in range(-nimg[2], nimg[2] + 1):

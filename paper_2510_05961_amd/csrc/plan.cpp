@@ -294,6 +294,80 @@ static double ewald2d(const double box[3], const double x[3]) {
   return real + M_PI / A * rec + k0;
 }
 
+// One periodic axis ax (length L, coordinate z along it, distance rho from
+// it), two free axes: the 1-D Ewald sum.  Real space is erfc(alpha r)/r over
+// the images along the axis.  Fourier space along the axis: the m = 0 term is
+// (1/L) [gamma_E + 2 ln(alpha L) - Ein(alpha^2 rho^2)], the logarithm of a
+// line charge with its constant chosen so that psi -> -(2/L) ln(rho/L) far
+// from the axis, for every alpha; the m != 0 terms are (2/L) cos(k z) F with
+// the incomplete Bessel function F = int_0^inf exp(-b e^t - c e^-t) dt,
+// b = k^2/(4 alpha^2), c = alpha^2 rho^2, taken by tanh-sinh quadrature over
+// the t-range where the exponent stays below 46.  alpha = 2/L.
+static double ein(double x) {  // int_0^x (1 - e^-v)/v dv
+  if (x > 0.75) return 0.57721566490153286061 + std::log(x) - std::expint(-x);
+  double t = -1.0, s = 0.0;
+  for (int k = 1; k < 60; ++k) {
+    t *= -x / k;
+    s += t / k;
+  }
+  return s;
+}
+
+static double incomplete_bessel(double b, double c) {
+  const double E = 46.0, D = E * E - 4.0 * b * c;
+  if (D <= 0.0) return 0.0;
+  const double hi = std::log((E + std::sqrt(D)) / (2.0 * b));
+  if (hi <= 0.0) return 0.0;
+  const double lo = std::max(0.0, std::log((E - std::sqrt(D)) / (2.0 * b)));
+  const double mid = 0.5 * (hi + lo), half = 0.5 * (hi - lo), step = 1.0 / 32.0;
+  double sum = 0.0;
+  for (int k = -112; k <= 112; ++k) {  // |u| <= 3.5: weights below 1e-30 beyond
+    const double u = k * step, v = 0.5 * M_PI * std::sinh(u);
+    const double w = 0.5 * M_PI * std::cosh(u) / (std::cosh(v) * std::cosh(v));
+    const double t = mid + half * std::tanh(v);
+    sum += w * std::exp(-b * std::exp(t) - c * std::exp(-t));
+  }
+  return sum * half * step;
+}
+
+static double ewald1d(const double box[3], int ax, const double x[3]) {
+  const double L = box[ax], z = x[ax];
+  const double alpha = 2.0 / L;
+  double rho2 = 0.0;
+  for (int k = 0; k < 3; ++k)
+    if (k != ax) rho2 += x[k] * x[k];
+  const double rc = 6.7 / alpha;
+  const int nr = (int)std::ceil((rc + std::fabs(z)) / L) + 1;
+  double val = 0.0;
+  for (int i = -nr; i <= nr; ++i) {
+    const double dz = z + i * L, r = std::sqrt(rho2 + dz * dz);
+    if (r == 0.0)
+      val += -2.0 * alpha / std::sqrt(M_PI);
+    else if (r < rc)
+      val += std::erfc(alpha * r) / r;
+  }
+  const double c = alpha * alpha * rho2;
+  val += (0.57721566490153286061 + 2.0 * std::log(alpha * L) - ein(c)) / L;
+  for (int m = 1;; ++m) {
+    const double k = 2.0 * M_PI * m / L, b = k * k / (4.0 * alpha * alpha);
+    if (b > 46.0) break;
+    val += 2.0 / L * std::cos(k * z) * incomplete_bessel(b, c);
+  }
+  return val;
+}
+
+// Ewald potential for the periodic axes of the plan (not triclinic): all
+// three, two (the free axis moved to z for the slab sum), or one.
+static double ewald_axes(const HostPlan& P, const double x[3]) {
+  const int np = P.periodic[0] + P.periodic[1] + P.periodic[2];
+  if (np == 3) return ewald3d(P.box, x);
+  if (np == 1) return ewald1d(P.box, P.periodic[0] ? 0 : (P.periodic[1] ? 1 : 2), x);
+  const int f = !P.periodic[0] ? 0 : (!P.periodic[1] ? 1 : 2);
+  const int a0 = f == 0 ? 1 : 0, a1 = f == 2 ? 1 : 2;
+  const double b[3] = {P.box[a0], P.box[a1], P.box[f]}, y[3] = {x[a0], x[a1], x[f]};
+  return ewald2d(b, y);
+}
+
 // The 3-D sum for the lattice {H n}: real space over the lattice vectors,
 // reciprocal space over k = 2 pi H^{-T} m, V = |det H| (tin-foil boundary,
 // neutralising background; alpha balances the two sums).
@@ -366,8 +440,7 @@ static double periodic_top_G(const HostPlan& P, const double x[3]) {
         }
     return val;
   }
-  bool slab = !P.periodic[2];
-  double val = slab ? ewald2d(P.box, x) : ewald3d(P.box, x);
+  double val = ewald_axes(P, x);
   int ni[3];
   for (int k = 0; k < 3; ++k)
     ni[k] = P.periodic[k] ? (int)std::ceil((R + std::fabs(x[k])) / P.box[k]) + 1 : 0;
@@ -448,7 +521,7 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
   if (nu != 1 && nu != 6) return MSM_ERR_INVALID_ARG;
   if (nu != 1 && (periodic_mask != 0 || P.tri)) return MSM_ERR_UNSUPPORTED;
   P.nu = nu;
-  if (periodic_mask != 0 && periodic_mask != 7 && periodic_mask != 3) return MSM_ERR_UNSUPPORTED;
+  if (periodic_mask > 7) return MSM_ERR_INVALID_ARG;
   if (M < 0) M = order;
   if (M > 24) return MSM_ERR_INVALID_ARG;
   for (int k = 0; k < 3; ++k) {

@@ -47,6 +47,13 @@ CASES = [
     ((16.0, 16.0, 16.0), (1, 1, 1), 4, 1.0, 4.0, 4),
     ((12.0, 12.0, 9.0), (1, 1, 0), 6, 0.75, 3.0, 3),
     ((10.0, 11.0, 12.0), (0, 0, 0), 6, 1.0, 3.0, 2),
+    # one periodic axis (1-D Ewald top level), each axis in turn
+    ((9.0, 10.0, 7.5), (0, 0, 1), 6, 0.75, 3.0, 3),
+    ((7.5, 9.0, 10.0), (1, 0, 0), 4, 0.75, 3.0, 3),
+    ((9.0, 7.0, 8.0), (0, 1, 0), 4, 1.0, 3.0, 2),
+    # two periodic axes with the free one along x or y
+    ((12.0, 9.0, 12.0), (1, 0, 1), 6, 0.75, 3.0, 3),
+    ((9.0, 12.0, 12.0), (0, 1, 1), 4, 1.0, 3.0, 3),
 ]
 
 
@@ -119,7 +126,7 @@ def test_parameter_errors():
     assert create() == 0
     lib.msm_plan_destroy(h)
     assert create(p=5) == 2            # odd order
-    assert create(mask=1) == 2         # 1-periodic
+    assert create(mask=8) == 1         # no such axis
     assert create(mask=7, a=6.0) == 3  # a > L/2
     assert create(h=-1.0) == 1
     assert create(L=0) == 1
