@@ -121,6 +121,10 @@ double orc_ewald2d(const double box[3], double alpha, const double x[3], int reg
 /* 1-D sum: axis periodic (length box[axis]), the other two free; the
  * constant is the one for which psi -> -(2/L) ln(rho/L) far from the axis. */
 double orc_ewald1d(const double box[3], int axis, double alpha, const double x[3], int reg);
+/* The lattice sum of r^-6 over a 3-D periodic box, sum_n |x + n|^-6, by the
+ * Ewald method (absolutely convergent: no boundary term); reg = 1 at x = 0
+ * leaves out the n = 0 term. */
+double orc_ewald3d_r6(const double box[3], double alpha, const double x[3], int reg);
 /* psi for the periodic axes of mask (bit k = axis k): 7, any two, any one. */
 double orc_ewald_psi(const double box[3], unsigned mask, double alpha, const double x[3],
                      int reg);

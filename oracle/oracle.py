@@ -133,6 +133,8 @@ def lib():
         for name in ("orc_ewald3d", "orc_ewald2d", "orc_ewald3d_cell"):
             getattr(L, name).argtypes = [P, d, P, i]
             getattr(L, name).restype = d
+        L.orc_ewald3d_r6.argtypes = [P, d, P, i]
+        L.orc_ewald3d_r6.restype = d
         L.orc_ewald1d.argtypes = [P, i, d, P, i]
         L.orc_ewald1d.restype = d
         L.orc_ewald_psi.argtypes = [P, ctypes.c_uint, d, P, i]
@@ -253,6 +255,25 @@ def ewald_potentials(box, pos, q, slab=False, alpha=None, periodic=None):
     return phi
 
 
+def ewald_psi_r6(box, x, alpha=None, reg=False):
+    """sum_n |x + n|^-6 over the lattice of a 3-D periodic box (Ewald method;
+    reg=True at x = 0 leaves out n = 0)."""
+    box = _f64(box)
+    if alpha is None:
+        alpha = ewald_alpha_3d(box)
+    return lib().orc_ewald3d_r6(_ptr(box), float(alpha), _ptr(_f64(x)), int(reg))
+
+
+def ewald_potentials_r6(box, pos, q, alpha=None):
+    """phi_i = sum_j q_j sum_n' |r_i - r_j + n|^-6 (n = 0 left out for j = i)."""
+    pos, q = _f64(pos), _f64(q)
+    phi = np.zeros(len(q))
+    for i in range(len(q)):
+        for j in range(len(q)):
+            phi[i] += q[j] * ewald_psi_r6(box, pos[i] - pos[j], alpha, reg=(i == j))
+    return phi
+
+
 def ewald3d_system(box, pos, q, alpha=None):
     """Potentials and forces of a 3-D periodic box by the structure-factor
     Ewald sum; the potentials are those of ewald_potentials(box, pos, q).
@@ -310,8 +331,8 @@ def direct_coulomb(pos, q):
 class OracleMSM:
     """Level-wise FP64 MSM for one orthorhombic box or triclinic cell.
 
-    box: 3 lengths; periodic: 3 bools (any combination); p: even B-spline order; h: requested level-1 spacing; a:
-    level-zero cutoff; L: number of grid levels; M: half-width of omega'
+    box: 3 lengths; periodic: 3 bools (any combination); p: even B-spline
+    order; h: requested level-1 spacing; a: level-zero cutoff; L: number of grid levels; M: half-width of omega'
     (default p).
 
     cell: rows a, b, c of a triclinic cell (all axes periodic; box is then
@@ -324,8 +345,10 @@ class OracleMSM:
     the cell's smallest width V / |face| (minimum image).
 
     nu: the kernel k(r) = r^-nu split the same way (gamma_nu: the Taylor
-    polynomial of s^(-nu/2)); 1 is Coulomb, 6 the dispersion kernel, for
-    which only free space is supported (its top level is the plain dense sum).
+    polynomial of s^(-nu/2)); 1 is Coulomb, 6 the dispersion kernel, in free
+    space (the top level is the plain dense sum) or in an orthorhombic box
+    periodic along all three axes (the top level sums k_L over the lattice with
+    the Ewald method for r^-6).
     """
 
     def __init__(self, box, periodic, p, h, a, L, M=None, cell=None, ntop=None, nu=1):
@@ -341,8 +364,9 @@ class OracleMSM:
         self.periodic = [bool(x) for x in periodic]
         self.p, self.h, self.a, self.L = int(p), float(h), float(a), int(L)
         self.M = self.p if M is None else int(M)
-        self.nu = int(nu)  # kernel r^-nu; other powers than 1 in free space only
-        assert self.nu >= 1 and (self.nu == 1 or not any(self.periodic))
+        self.nu = int(nu)  # kernel r^-nu: 1 anywhere, 6 in free space or an orthorhombic 3-D box
+        assert self.nu in (1, 6)
+        assert self.nu == 1 or (self.cell is None and sum(self.periodic) in (0, 3))
         assert self.p % 2 == 0 and self.p >= 2 and 1 <= self.L <= MAXL
         for k in range(3):
             if self.periodic[k]:
@@ -472,7 +496,12 @@ class OracleMSM:
                         elif r < R:
                             val -= 1.0 / r - gamma(p, r / R) / R
             return val
-        val = ewald_psi(self.box, x, periodic=self.periodic, reg=True)
+        nu = self.nu
+        if nu == 1:
+            val = ewald_psi(self.box, x, periodic=self.periodic, reg=True)
+        else:
+            val = ewald_psi_r6(self.box, x, reg=True)
+        # k_L = gamma_nu(r/R)/R^nu = r^-nu - (r^-nu - gamma_nu(r/R)/R^nu) for r < R
         nimg = [int(math.ceil((R + abs(x[k])) / self.box[k])) + 1 if self.periodic[k] else 0
                 for k in range(3)]
         for jz in range(-nimg[2], nimg[2] + 1):
@@ -481,9 +510,9 @@ class OracleMSM:
                     d = (x[0] + jx * self.box[0], x[1] + jy * self.box[1], x[2] + jz * self.box[2])
                     r = math.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
                     if r == 0.0:
-                        val += gamma(p, 0.0) / R
+                        val += gamma_nu(nu, p, 0.0) / R ** nu
                     elif r < R:
-                        val -= 1.0 / r - gamma(p, r / R) / R
+                        val -= r ** -nu - gamma_nu(nu, p, r / R) / R ** nu
         return val
 
     def _top_stencil(self):

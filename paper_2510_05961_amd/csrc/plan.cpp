@@ -356,6 +356,49 @@ static double ewald1d(const double box[3], int ax, const double x[3]) {
   return val;
 }
 
+// Lattice sum of r^-6 over a 3-D periodic box by the Ewald method: with
+// r^-6 = (1/2) int_0^inf t^2 e^{-r^2 t} dt split at t = alpha^2, real space
+// keeps e^{-y}(1 + y + y^2/2)/r^6 (y = alpha^2 r^2), Fourier space the rest,
+// pi^{3/2} alpha^3 / (3V) [(1 - 2 b^2) e^{-b^2} + 2 sqrt(pi) b^3 erfc(b)]
+// per wave vector k (b = |k| / (2 alpha), k = 0 included).  The sum
+// converges absolutely: no boundary term.  At x = 0 the n = 0 term is left
+// out (its real-space part tends to -alpha^6/6 after r^-6 is removed).
+static double ewald3d_r6(const double box[3], const double x[3]) {
+  const double V = box[0] * box[1] * box[2];
+  const double alpha = 1.3 / std::cbrt(V);
+  const double rc = 7.2 / alpha, bc = 6.8;  // dropped terms below 1e-18 of the sum
+  int nr[3], nk[3];
+  for (int k = 0; k < 3; ++k) {
+    nr[k] = (int)std::ceil((rc + std::fabs(x[k])) / box[k]) + 1;
+    nk[k] = (int)std::ceil(2.0 * alpha * bc * box[k] / (2.0 * M_PI)) + 1;
+  }
+  double val = 0.0;
+  for (int i = -nr[0]; i <= nr[0]; ++i)
+    for (int j = -nr[1]; j <= nr[1]; ++j)
+      for (int k = -nr[2]; k <= nr[2]; ++k) {
+        const double d[3] = {x[0] + i * box[0], x[1] + j * box[1], x[2] + k * box[2]};
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 == 0.0) {
+          val -= std::pow(alpha, 6) / 6.0;
+        } else if (r2 < rc * rc) {
+          const double y = alpha * alpha * r2;
+          val += std::exp(-y) * (1.0 + y + 0.5 * y * y) / (r2 * r2 * r2);
+        }
+      }
+  double rec = 0.0;
+  for (int i = -nk[0]; i <= nk[0]; ++i)
+    for (int j = -nk[1]; j <= nk[1]; ++j)
+      for (int k = -nk[2]; k <= nk[2]; ++k) {
+        const double g[3] = {2 * M_PI * i / box[0], 2 * M_PI * j / box[1], 2 * M_PI * k / box[2]};
+        const double b = std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / (2.0 * alpha);
+        if (b >= bc) continue;
+        const double w = (1.0 - 2.0 * b * b) * std::exp(-b * b) +
+                         2.0 * std::sqrt(M_PI) * b * b * b * std::erfc(b);
+        rec += w * std::cos(g[0] * x[0] + g[1] * x[1] + g[2] * x[2]);
+      }
+  return val + std::pow(M_PI, 1.5) * alpha * alpha * alpha / (3.0 * V) * rec;
+}
+
 // Ewald potential for the periodic axes of the plan (not triclinic): all
 // three, two (the free axis moved to z for the slab sum), or one.
 static double ewald_axes(const HostPlan& P, const double x[3]) {
@@ -440,7 +483,10 @@ static double periodic_top_G(const HostPlan& P, const double x[3]) {
         }
     return val;
   }
-  double val = ewald_axes(P, x);
+  // kernel r^-nu: Coulomb for every set of periodic axes, r^-6 with all three
+  const int nu = P.nu;
+  const double Rn = std::pow(R, nu);
+  double val = nu == 1 ? ewald_axes(P, x) : ewald3d_r6(P.box, x);
   int ni[3];
   for (int k = 0; k < 3; ++k)
     ni[k] = P.periodic[k] ? (int)std::ceil((R + std::fabs(x[k])) / P.box[k]) + 1 : 0;
@@ -450,9 +496,9 @@ static double periodic_top_G(const HostPlan& P, const double x[3]) {
         double d[3] = {x[0] + i * P.box[0], x[1] + j * P.box[1], x[2] + k * P.box[2]};
         double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         if (r == 0.0)
-          val += P.gamma0 / R;  // regular part: psi - 1/r already taken, + gamma(0)/R
+          val += P.gamma0 / Rn;  // regular part: psi - r^-nu already taken, + gamma(0)/R^nu
         else if (r < R)
-          val -= 1.0 / r - gamma_t(P.gcoef, P.p, r / R) / R;
+          val -= std::pow(r, -nu) - gamma_t(P.gcoef, P.p, r / R, nu) / Rn;
       }
   return val;
 }
@@ -516,10 +562,10 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
     }
   }
   if (order != 4 && order != 6 && order != 8) return MSM_ERR_UNSUPPORTED;
-  // kernels r^-nu: Coulomb (1) anywhere, dispersion (6) in free space (its
-  // periodic top level would need its own Ewald-type sum)
+  // kernels r^-nu: Coulomb (1) anywhere, dispersion (6) in free space or an
+  // orthorhombic box periodic along all three axes (its 3-D Ewald sum)
   if (nu != 1 && nu != 6) return MSM_ERR_INVALID_ARG;
-  if (nu != 1 && (periodic_mask != 0 || P.tri)) return MSM_ERR_UNSUPPORTED;
+  if (nu != 1 && ((periodic_mask != 0 && periodic_mask != 7) || P.tri)) return MSM_ERR_UNSUPPORTED;
   P.nu = nu;
   if (periodic_mask > 7) return MSM_ERR_INVALID_ARG;
   if (M < 0) M = order;

@@ -1,8 +1,9 @@
 """CPU pins of the oracle's MSM for the dispersion kernel k(r) = r^-6, the
 paper's splitting applied to another power (Sec. Splitting for Coulomb
 kernels; the package's core is meant to take other kernels): the softener's
-contact with r^-6, the telescoping split, and the MSM against the exact
-all-pairs sum (free space)."""
+contact with r^-6, the telescoping split, the MSM against the exact
+all-pairs sum (free space); the 3-D Ewald sum of r^-6 against brute-force
+lattice sums, and the periodic MSM against that sum."""
 import numpy as np
 import pytest
 
@@ -106,6 +107,100 @@ def test_msm_r6_sampled_equals_full():
     np.testing.assert_allclose(F, full["F"][sel], rtol=1e-12, atol=1e-14)
 
 
-def test_periodic_r6_is_refused():
+def test_r6_other_periodicities_are_refused():
+    # the r^-6 top level is summed by the 3-D Ewald method only
+    for per in ((1, 1, 0), (0, 0, 1)):
+        with pytest.raises(AssertionError):
+            O.OracleMSM((10.0,) * 3, per, 4, 1.0, 3.0, 2, nu=NU)
     with pytest.raises(AssertionError):
-        O.OracleMSM((10.0,) * 3, (1, 1, 1), 4, 1.0, 3.0, 2, nu=NU)
+        O.OracleMSM(None, (1, 1, 1), 4, 1.0, 3.0, 2, nu=NU, cell=np.diag([10.0] * 3))
+
+
+# --------------------------------------------------------------------------
+# periodic r^-6: the 3-D Ewald sum of the dispersion kernel and the MSM on it
+# --------------------------------------------------------------------------
+def _lattice_brute(box, x, reg, Ns=(16, 32, 64)):
+    """sum over |n_k| <= N of |x + n o box|^-6 at three N, extrapolated in the
+    half-width M = N + 1/2 of the summed block: the missing tail is
+    c3/M^3 + c5/M^5 + O(M^-7) (the sum over a block's complement against its
+    integral, symmetric in the shift x)."""
+    box = np.asarray(box, dtype=np.float64)
+    T = []
+    for N in Ns:
+        r = np.arange(-N, N + 1, dtype=np.float64)
+        gx, gy, gz = np.meshgrid(r * box[0] + x[0], r * box[1] + x[1], r * box[2] + x[2],
+                                 indexing="ij")
+        r2 = gx * gx + gy * gy + gz * gz
+        if reg:
+            r2 = r2[r2 > 0]
+        T.append(float(np.sum(r2 ** -3)))
+    A = np.array([[1.0, (N + 0.5) ** -3, (N + 0.5) ** -5] for N in Ns])
+    return float(np.linalg.solve(A, T)[0])
+
+
+R6_POINTS = [((3.0, 3.5, 4.0), (0.3, -0.7, 1.1), False), ((3.0, 3.5, 4.0), (1.4, 1.6, 1.9), False),
+             ((4.0, 4.0, 5.0), (0.0, 0.0, 0.0), True), ((1.0, 1.0, 1.0), (0.0, 0.0, 0.0), True)]
+
+
+@pytest.mark.parametrize("box,x,reg", R6_POINTS)
+def test_r6_lattice_sum_alpha_independent(box, x, reg):
+    # (a large alpha makes the sum a difference of terms of order alpha^6 / 6
+    # and alpha^3 / V: the bound allows that rounding)
+    vals = [O.ewald_psi_r6(box, x, alpha=a, reg=reg) for a in (0.2, 0.3, 0.5, 0.8)]
+    assert max(vals) - min(vals) <= 1e-12 * abs(vals[0])
+
+
+@pytest.mark.parametrize("box,x,reg", R6_POINTS)
+def test_r6_lattice_sum_equals_brute_force(box, x, reg):
+    # absolutely convergent: the Ewald value is the plain lattice sum (for the
+    # unit cube at 0, the simple cubic lattice's sum of |n|^-6 over n != 0)
+    assert O.ewald_psi_r6(box, x, reg=reg) == pytest.approx(_lattice_brute(box, x, reg),
+                                                              rel=1e-10)
+
+
+def test_r6_lattice_sum_sublattices():
+    # the lattice of box is the union of the 8 shifted lattices of 2 box
+    box = np.array([3.0, 3.5, 4.0])
+    x = np.array([0.3, -0.7, 1.1])
+    whole = O.ewald_psi_r6(box, x)
+    parts = sum(O.ewald_psi_r6(2 * box, x + box * np.array(s))
+                for s in np.ndindex(2, 2, 2))
+    assert parts == pytest.approx(whole, rel=1e-13)
+
+
+def _periodic_system(n, L, seed):
+    pos, _ = WL.spaced_charges(n, L, True, seed=seed)
+    c = np.random.default_rng(seed + 1).uniform(0.5, 1.5, n)
+    return pos, c
+
+
+def test_msm_r6_periodic_converges_to_ewald():
+    box = (8.0, 8.0, 8.0)
+    pos, c = _periodic_system(60, 8.0, 5)
+    phie = O.ewald_potentials_r6(box, pos, c)
+    errs = []
+    for p, h in ((4, 0.5), (6, 0.5), (6, 0.4)):
+        r = O.OracleMSM(box, (1, 1, 1), p, h, 4.0, 3, nu=NU).compute(pos, c)
+        errs.append(np.linalg.norm(r["phi"] - phie) / np.linalg.norm(phie))
+        assert abs(r["E"] - 0.5 * c @ phie) <= 3 * errs[-1] * abs(0.5 * c @ phie)
+    assert errs[0] < 2e-5 and errs[0] > errs[1] > errs[2] and errs[2] < 2e-6, errs
+
+
+def test_msm_r6_periodic_derivatives():
+    box = (7.0, 7.0, 7.0)
+    pos, c = _periodic_system(30, 7.0, 9)
+    o = O.OracleMSM(box, (1, 1, 1), 4, 0.45, 3.5, 2, nu=NU)
+    r = o.compute(pos, c)
+    eps = 1e-5
+    for i in (0, 13, 29):
+        for k in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[i, k] += eps
+            pm[i, k] -= eps
+            dE = (o.compute(pp, c)["E"] - o.compute(pm, c)["E"]) / (2 * eps)
+            assert -dE == pytest.approx(r["F"][i, k], rel=1e-5, abs=1e-7)
+        cp, cm = c.copy(), c.copy()
+        cp[i] += eps
+        cm[i] -= eps
+        dq = (o.compute(pos, cp)["E"] - o.compute(pos, cm)["E"]) / (2 * eps)
+        assert dq == pytest.approx(r["phi"][i], rel=1e-6)
