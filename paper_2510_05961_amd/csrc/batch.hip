@@ -9,6 +9,10 @@
 //   output tiles across systems; shared K^1, K^2 = K^1/2 and one dense top
 //   table per level count) -> prolongation -> interpolation with per-system
 //   FP64 energies.
+// An intermediate level may run factored (K^l = omega' x omega' x omega' *
+// S^l, eq. kernel_stencil_by_conv_with_universal_coeff): three omega' passes
+// over the charges, onto grids extended by M on every side, then the ball
+// S^l of k-samples from the extended grid back to the level grid.
 // The launch sequence is captured once in a hipGraph and replayed; the conv
 // tile shape is chosen at plan time by timing the candidates (autotuner).
 #include <hip/hip_runtime.h>
@@ -33,9 +37,12 @@ namespace msm {
 constexpr int kPairThreads = 128;  // brute-force pair kernel of the batch path
 
 struct ConvTask {
-  long long goff;  // grid offset of the system's level grid
-  int n;           // cubic grid size
-  int x0, y0, z;   // output tile origin
+  long long goff;     // output: offset of the system's level grid (n^3)
+  long long goff_in;  // input: the same grid, or its omega'-filtered extension
+  int n;              // cubic output grid size
+  int n_in;           // cubic input grid size: n, or n + 2M
+  int shift;          // input index of output index 0: 0, or M
+  int x0, y0, z;      // output tile origin
 };
 
 struct BatchConv {
@@ -45,6 +52,8 @@ struct BatchConv {
   int off, len;  // cubic stencil box: offsets off .. off+len-1 per axis
   int fold = 0;  // z-planes j and len-1-j share coefficients
   int cfg = 0;   // tile shape (kTiles), chosen per convolution by the autotuner
+  int fact = 0;  // 1: K is the ball S^l, read from the omega'-filtered extension
+  int group = 0;  // candidates of one group (a level's direct and factored forms): one is kept
   void* K = nullptr;
   int2* rowext = nullptr;
   ConvTask* tasks = nullptr;
@@ -71,6 +80,15 @@ struct BatchState {
   void* F0 = nullptr;
   int* flag = nullptr;
   std::vector<BatchConv> convs;
+  // factored intermediate levels: per level, each system's offset in the
+  // extended buffers (n + 2M)^3 (zero size where the system does not take
+  // part) and, per omega' pass, the first workgroup of each system
+  std::vector<long long> goffe[kMaxLevels];
+  long long* d_goffe[kMaxLevels] = {};
+  int* d_bfirst[kMaxLevels][3] = {};  // first workgroup of each system, per pass
+  int pass_blocks[kMaxLevels][3] = {};
+  void* xbuf = nullptr;  // omega' pass buffers, max over levels of sum (n + 2M)^3
+  void* ybuf = nullptr;
   int tile_cfg = 0;
   std::string tuning;
   // graph cache
@@ -346,6 +364,61 @@ __global__ void k_batch_prolong(int n_sys, long long Gf, const long long* __rest
 
 constexpr int kBConvCH = 8;
 
+// omega' taps w_0..w_M (w_-k = w_k), M <= 24
+struct OmegaTaps {
+  double w[25];
+  int M;
+};
+
+// One omega' pass of a factored level over every taking-part system: along
+// `axis`, out[c] = sum_{|k| <= M} w_|k| in[c - M - k] over input indices
+// 0..n-1 (zero outside), c = 0..n+2M-1; the axes before `axis` are already
+// extended to n + 2M, the axes after it not yet.  One thread per output
+// point, kOmegaBlock points per workgroup; bfirst[s] = first workgroup of
+// system s (systems that do not take part have none, so the last s with
+// bfirst[s] <= blockIdx.x owns the workgroup: a search uniform over it).
+// FP64 sums, stored in the grid precision.
+constexpr int kOmegaBlock = 256;
+template <typename T>
+__global__ void __launch_bounds__(kOmegaBlock)
+    k_batch_omega(int n_sys, const int* __restrict__ bfirst, const int* __restrict__ nn,
+                  const long long* __restrict__ goff_in, const long long* __restrict__ goff_out,
+                  int axis, OmegaTaps w, const T* __restrict__ in, T* __restrict__ out) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n_sys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bfirst[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int s = lo, n = nn[s], M = w.M, ne = n + 2 * M;
+  int dout[3], din[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    dout[k] = k <= axis ? ne : n;
+    din[k] = k < axis ? ne : n;
+  }
+  // within one system every index fits 32 bits (n <= 512, M <= 24)
+  const int t = (b - bfirst[s]) * kOmegaBlock + (int)threadIdx.x;
+  if (t >= dout[0] * dout[1] * dout[2]) return;
+  int c[3];
+  c[0] = t % dout[0];
+  c[1] = (t / dout[0]) % dout[1];
+  c[2] = t / (dout[0] * dout[1]);
+  const int stride_in[3] = {1, din[0], din[0] * din[1]};
+  int base = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k != axis) base += c[k] * stride_in[k];
+  const T* src = in + goff_in[s] + base;
+  double acc = 0.0;
+  for (int k = -M; k <= M; ++k) {
+    const int i = c[axis] - M - k;
+    if (i >= 0 && i < n) acc += w.w[k < 0 ? -k : k] * (double)src[i * stride_in[axis]];
+  }
+  out[goff_out[s] + t] = (T)acc;
+}
+
 // Stencil convolution over a task list: each workgroup computes one output
 // tile (one z plane) of one system's grid, all stencil planes; free axes.
 // With fold, plane jz and its mirror len-1-jz hold the same coefficients:
@@ -358,30 +431,31 @@ __global__ void __launch_bounds__(TXT * TYT)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   const ConvTask tk = tasks[blockIdx.x];
-  const int n = tk.n;
+  const int n = tk.n, ni = tk.n_in, sh = tk.shift;
   const int tx = threadIdx.x % TXT, ty = threadIdx.x / TXT;
   const int LW = lds_w, LH = TYT + len - 1;
-  const int xs = tk.x0 - (off + len - 1), ys = tk.y0 - (off + len - 1);
-  const T* q = qcat + tk.goff;
+  // input index of output m at stencil offset d: m + sh - d
+  const int xs = tk.x0 + sh - (off + len - 1), ys = tk.y0 + sh - (off + len - 1);
+  const T* q = qcat + tk.goff_in;
   double total[R];  // FP64 accumulation (long sums with cancellation)
 #pragma unroll
   for (int r = 0; r < R; ++r) total[r] = 0;
   const int nplanes = fold ? (len + 1) / 2 : len;
   for (int jz = 0; jz < nplanes; ++jz) {
-    const int za = tk.z - (off + jz), jm = len - 1 - jz;
-    const int zb = (fold && jm != jz) ? tk.z - (off + jm) : -1;
-    const bool va = za >= 0 && za < n, vb = zb >= 0 && zb < n;
+    const int za = tk.z + sh - (off + jz), jm = len - 1 - jz;
+    const int zb = (fold && jm != jz) ? tk.z + sh - (off + jm) : -1;
+    const bool va = za >= 0 && za < ni, vb = zb >= 0 && zb < ni;
     if (!va && !vb) continue;  // uniform over the workgroup
     __syncthreads();
-    const T* qa = q + (long long)(va ? za : zb) * n * n;
-    const T* qb = q + (long long)(vb ? zb : 0) * n * n;
+    const T* qa = q + (long long)(va ? za : zb) * ni * ni;
+    const T* qb = q + (long long)(vb ? zb : 0) * ni * ni;
     const bool two = va && vb;
     for (int idx = threadIdx.x; idx < LW * LH; idx += TXT * TYT) {
       const int ry = idx / LW, rx = idx - ry * LW;
       const int yi = ys + ry, xi = xs + rx;
       T v = T(0);
-      if (yi >= 0 && yi < n && xi >= 0 && xi < n) {
-        const long long o = (long long)yi * n + xi;
+      if (yi >= 0 && yi < ni && xi >= 0 && xi < ni) {
+        const long long o = (long long)yi * ni + xi;
         v = two ? qa[o] + qb[o] : qa[o];
       }
       lds[idx] = v;
@@ -390,16 +464,16 @@ __global__ void __launch_bounds__(TXT * TYT)
     const double* Kz = K + (long long)jz * len * len;
     const int2* ext_z = rowext + jz * len;
     // rows whose input y lies inside the grid for some output row of the tile
-    const int jy_lo = max(0, tk.y0 - off - (n - 1));
-    const int jy_hi = min(len - 1, tk.y0 + TYT - 1 - off);
+    const int jy_lo = max(0, tk.y0 + sh - off - (ni - 1));
+    const int jy_hi = min(len - 1, tk.y0 + TYT - 1 + sh - off);
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0;
     for (int jy = jy_lo; jy <= jy_hi; ++jy) {
       int2 ext = ext_z[jy];
       // x offsets whose inputs can lie inside the grid for this tile
-      ext.x = max(ext.x, tk.x0 - off - (n - 1));
-      ext.y = min(ext.y, tk.x0 + TXT * R - 1 - off);
+      ext.x = max(ext.x, tk.x0 + sh - off - (ni - 1));
+      ext.y = min(ext.y, tk.x0 + TXT * R - 1 + sh - off);
       if (ext.x > ext.y) continue;
       const T* lrow = lds + (ty - jy + len - 1) * LW + tx * R;
       const double* Krow = Kz + jy * len;
@@ -524,18 +598,42 @@ static void launch_batch_conv(const BatchConv& bc, int cfg, const T* qcat, T* ec
   }
 }
 
-static std::vector<ConvTask> build_tasks(const BatchState& B, int level, int top, int cfg) {
+static std::vector<ConvTask> build_tasks(const BatchState& B, const BatchConv& bc, int cfg) {
   std::vector<ConvTask> t;
+  const int level = bc.level;
   const int TXo = kTiles[cfg].TXT * kTiles[cfg].R, TY = kTiles[cfg].TYT;
   for (int s = 0; s < B.n_sys; ++s) {
     if (level > B.L[s]) continue;
-    if ((B.L[s] == level) != (top != 0)) continue;
+    if ((B.L[s] == level) != (bc.top != 0)) continue;
     const int n = B.n[level - 1][s];
+    const long long go = B.goff[level - 1][s];
+    const long long gi = bc.fact ? B.goffe[level - 1][s] : go;
+    const int ni = bc.fact ? n + 2 * B.M : n, sh = bc.fact ? B.M : 0;
     for (int z = 0; z < n; ++z)
       for (int y0 = 0; y0 < n; y0 += TY)
-        for (int x0 = 0; x0 < n; x0 += TXo) t.push_back({B.goff[level - 1][s], n, x0, y0, z});
+        for (int x0 = 0; x0 < n; x0 += TXo) t.push_back({go, gi, n, ni, sh, x0, y0, z});
   }
   return t;
+}
+
+// The three omega' passes of factored level l: level grid -> ybuf (x
+// extended) -> xbuf (x, y) -> ybuf (all three), which the ball convolution
+// reads.
+template <typename T>
+static void launch_omega_passes(const BatchState& B, int l, hipStream_t s) {
+  OmegaTaps w{};
+  w.M = B.M;
+  for (int k = 0; k <= B.M; ++k) w.w[k] = B.omega[k];
+  const long long* gin[3] = {B.d_goff[l - 1], B.d_goffe[l - 1], B.d_goffe[l - 1]};
+  const T* in[3] = {(const T*)B.qcat[l - 1], (const T*)B.ybuf, (const T*)B.xbuf};
+  T* out[3] = {(T*)B.ybuf, (T*)B.xbuf, (T*)B.ybuf};
+  for (int ax = 0; ax < 3; ++ax) {
+    const int g = B.pass_blocks[l - 1][ax];
+    if (g <= 0) continue;
+    hipLaunchKernelGGL(k_batch_omega<T>, dim3(g), dim3(kOmegaBlock), 0, s, B.n_sys,
+                       B.d_bfirst[l - 1][ax], B.d_n[l - 1], gin[ax], B.d_goffe[l - 1], ax, w,
+                       in[ax], out[ax]);
+  }
 }
 
 // A cubic stencil [len]^3 to the device; *fold says whether its z-planes
@@ -629,7 +727,9 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
   P->prof.end(ev, s);
   for (const BatchConv& bc : B.convs) {
     ev = P->prof.begin(bc.level == 1 ? "batch_conv_l1" : (bc.top ? "batch_conv_top" : "batch_conv_l2+"), s);
-    launch_batch_conv<T>(bc, bc.cfg, (const T*)B.qcat[bc.level - 1], (T*)B.ecat[bc.level - 1], s);
+    if (bc.fact) launch_omega_passes<T>(B, bc.level, s);
+    launch_batch_conv<T>(bc, bc.cfg, bc.fact ? (const T*)B.ybuf : (const T*)B.qcat[bc.level - 1],
+                         (T*)B.ecat[bc.level - 1], s);
     P->prof.end(ev, s);
   }
   ev = P->prof.begin("batch_prolong", s);
@@ -656,25 +756,17 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
   return hipGetLastError() == hipSuccess ? MSM_OK : MSM_ERR_HIP;
 }
 
-// Times every convolution of the plan (each level's intermediate and top
-// kernels: their grids differ in size) for every tile shape on the plan's
-// (zero) grids and keeps the fastest shape per convolution.
-// MSM_BATCH_TILE=c (0, 1 or 2) pins shape c for every convolution instead.
+// Times every candidate convolution of the plan (each level's intermediate
+// forms and top kernels: their grids differ in size) for every tile shape on
+// the plan's (zero) grids, a factored form with its three omega' passes;
+// keeps the fastest shape per candidate and the fastest candidate per group
+// (a level's direct and factored forms).  MSM_BATCH_TILE=c (0, 1 or 2) pins
+// shape c; the forms are still timed against each other.
 template <typename T>
 static msm_status autotune(msm_plan P) {
   BatchState& B = *P->bs;
   const char* pin = std::getenv("MSM_BATCH_TILE");
-  if (pin && pin[0] >= '0' && pin[0] <= '2' && pin[1] == 0) {
-    std::ostringstream log;
-    for (size_t ci = 0; ci < B.convs.size(); ++ci) {
-      B.convs[ci].cfg = pin[0] - '0';
-      log << (ci ? "," : "") << "{\"level\":" << B.convs[ci].level << ",\"top\":"
-          << B.convs[ci].top << ",\"pinned\":true,\"cfg\":" << B.convs[ci].cfg << "}";
-    }
-    B.tile_cfg = B.convs.empty() ? 0 : B.convs[0].cfg;
-    B.tuning = "[" + log.str() + "]";
-    return MSM_OK;
-  }
+  const bool pinned = pin && pin[0] >= '0' && pin[0] <= '2' && pin[1] == 0;
   hipStream_t s = nullptr;
   hipEvent_t a = nullptr, b = nullptr;
   ConvTask* dt = nullptr;
@@ -687,13 +779,14 @@ static msm_status autotune(msm_plan P) {
   };
   if (hipEventCreate(&a) || hipEventCreate(&b)) return done(MSM_ERR_HIP);
   std::ostringstream log;
+  std::vector<float> best(B.convs.size(), 1e30f);
   for (size_t ci = 0; ci < B.convs.size(); ++ci) {
     BatchConv& bc = B.convs[ci];
-    float best = 1e30f;
-    int best_cfg = 0;
-    log << (ci ? "," : "") << "{\"level\":" << bc.level << ",\"top\":" << bc.top << ",\"ms\":[";
-    for (int cfg = 0; cfg < 3; ++cfg) {
-      std::vector<ConvTask> t = build_tasks(B, bc.level, bc.top, cfg);
+    int best_cfg = pinned ? pin[0] - '0' : 0;
+    log << (ci ? "," : "") << "{\"level\":" << bc.level << ",\"top\":" << bc.top
+        << ",\"factored\":" << bc.fact << ",\"ms\":[";
+    for (int cfg = pinned ? best_cfg : 0; cfg < (pinned ? best_cfg + 1 : 3); ++cfg) {
+      std::vector<ConvTask> t = build_tasks(B, bc, cfg);
       if (hipMalloc((void**)&dt, std::max<size_t>(t.size(), 1) * sizeof(ConvTask))) {
         dt = nullptr;
         (void)hipGetLastError();
@@ -705,20 +798,24 @@ static msm_status autotune(msm_plan P) {
       BatchConv trial = bc;
       trial.tasks = dt;
       trial.ntasks = (int)t.size();
-      const T* q = (const T*)B.qcat[bc.level - 1];
+      const T* q = bc.fact ? (const T*)B.ybuf : (const T*)B.qcat[bc.level - 1];
       T* e = (T*)B.ecat[bc.level - 1];
-      launch_batch_conv<T>(trial, cfg, q, e, s);  // warm-up
+      auto run = [&]() {
+        if (bc.fact) launch_omega_passes<T>(B, bc.level, s);
+        launch_batch_conv<T>(trial, cfg, q, e, s);
+      };
+      run();  // warm-up
       (void)hipEventRecord(a, s);
-      for (int r = 0; r < 3; ++r) launch_batch_conv<T>(trial, cfg, q, e, s);
+      for (int r = 0; r < 3; ++r) run();
       (void)hipEventRecord(b, s);
       if (hipEventSynchronize(b)) return done(MSM_ERR_HIP);
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, a, b);
       (void)hipFree(dt);
       dt = nullptr;
-      log << (cfg ? "," : "") << ms / 3;
-      if (ms < best) {
-        best = ms;
+      log << (cfg > (pinned ? best_cfg : 0) ? "," : "") << ms / 3;
+      if (ms < best[ci]) {
+        best[ci] = ms;
         best_cfg = cfg;
       }
     }
@@ -726,6 +823,17 @@ static msm_status autotune(msm_plan P) {
     log << "],\"cfg\":" << best_cfg << "}";
   }
   if (hipGetLastError() != hipSuccess) return done(MSM_ERR_HIP);
+  // one candidate per group: the fastest
+  std::vector<BatchConv> kept;
+  for (size_t ci = 0; ci < B.convs.size(); ++ci) {
+    bool keep = true;
+    for (size_t cj = 0; cj < B.convs.size(); ++cj)
+      if (cj != ci && B.convs[cj].group == B.convs[ci].group &&
+          (best[cj] < best[ci] || (best[cj] == best[ci] && cj < ci)))
+        keep = false;
+    if (keep) kept.push_back(B.convs[ci]);
+  }
+  B.convs.swap(kept);
   B.tile_cfg = B.convs.empty() ? 0 : B.convs[0].cfg;
   B.tuning = "[" + log.str() + "]";
   return done(MSM_OK);
@@ -733,6 +841,7 @@ static msm_status autotune(msm_plan P) {
 
 template <typename T>
 static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1,
+                               const std::vector<double>& S1, int R1,
                                const std::vector<std::vector<double>>& tops,
                                const std::vector<int>& top_len) {
   BatchState& B = *P->bs;
@@ -767,28 +876,99 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
   int2* dK1ext = nullptr;
   int fold1 = 0;
   if ((st = upload_stencil<double>(P, K1, 2 * W1 + 1, &dK1, &dK1ext, &fold1))) return st;
+  // factored intermediate levels: both forms of each intermediate level are
+  // candidates and the autotuner keeps the faster (on small grids the direct
+  // stencil, cropped at the grid, can win); MSM_FACTORED=0 keeps only the
+  // direct form, MSM_FACTORED=1 only the factored one
+  void* dS1 = nullptr;
+  int2* dS1ext = nullptr;
+  int foldS = 0;
+  const char* fenv = std::getenv("MSM_FACTORED");
+  const bool want_direct = !(fenv && fenv[0] == '1');
+  const bool want_fact = !(fenv && fenv[0] == '0');
+  bool fact[kMaxLevels] = {};
+  {
+    long long ext_max = 0;
+    for (int l = 1; l < B.Lmax && want_fact; ++l) {
+      bool any = false;
+      for (int s = 0; s < B.n_sys; ++s) any |= B.L[s] > l;
+      fact[l - 1] = any;
+      if (!any) continue;
+      B.goffe[l - 1].assign(B.n_sys + 1, 0);
+      std::vector<int> bfirst[3];
+      for (int ax = 0; ax < 3; ++ax) bfirst[ax].assign(B.n_sys, 0);
+      long long acc = 0, pa[3] = {0, 0, 0};
+      for (int s = 0; s < B.n_sys; ++s) {
+        B.goffe[l - 1][s] = acc;
+        for (int ax = 0; ax < 3; ++ax) bfirst[ax][s] = (int)pa[ax];
+        if (B.L[s] <= l) continue;
+        const long long n = B.n[l - 1][s], ne = n + 2 * B.M;
+        acc += ne * ne * ne;
+        const long long cnt[3] = {ne * n * n, ne * ne * n, ne * ne * ne};
+        for (int ax = 0; ax < 3; ++ax) pa[ax] += (cnt[ax] + kOmegaBlock - 1) / kOmegaBlock;
+      }
+      if (pa[2] > (1LL << 31) - 1) return MSM_ERR_GRID;
+      B.goffe[l - 1][B.n_sys] = acc;
+      ext_max = std::max(ext_max, acc);
+      if ((st = hip_alloc(P, (void**)&B.d_goffe[l - 1], (B.n_sys + 1) * sizeof(long long))))
+        return st;
+      if (hipMemcpy(B.d_goffe[l - 1], B.goffe[l - 1].data(), (B.n_sys + 1) * sizeof(long long),
+                    hipMemcpyHostToDevice))
+        return MSM_ERR_HIP;
+      for (int ax = 0; ax < 3; ++ax) {
+        B.pass_blocks[l - 1][ax] = (int)pa[ax];
+        if ((st = hip_alloc(P, (void**)&B.d_bfirst[l - 1][ax], B.n_sys * sizeof(int))))
+          return st;
+        if (hipMemcpy(B.d_bfirst[l - 1][ax], bfirst[ax].data(), B.n_sys * sizeof(int),
+                      hipMemcpyHostToDevice))
+          return MSM_ERR_HIP;
+      }
+    }
+    if (ext_max > 0) {
+      if ((st = upload_stencil<double>(P, S1, 2 * R1 + 1, &dS1, &dS1ext, &foldS))) return st;
+      if ((st = hip_alloc(P, &B.xbuf, (size_t)ext_max * sizeof(T)))) return st;
+      if ((st = hip_alloc(P, &B.ybuf, (size_t)ext_max * sizeof(T)))) return st;
+      launch_fill<T>((T*)B.xbuf, ext_max, T(0), nullptr);
+      launch_fill<T>((T*)B.ybuf, ext_max, T(0), nullptr);
+    }
+  }
+  int group = 0;
   for (int l = 1; l <= B.Lmax; ++l) {
     BatchConv inter;
     inter.level = l;
     inter.top = 0;
     inter.scale = std::ldexp(1.0, -(l - 1));
+    inter.group = group++;
     inter.off = -W1;
     inter.len = 2 * W1 + 1;
     inter.K = dK1;
     inter.rowext = dK1ext;
     inter.fold = fold1;
+    BatchConv interf = inter;
+    const bool has_fact = l < B.Lmax && fact[l - 1];
+    if (has_fact) {
+      interf.fact = 1;
+      interf.off = -R1;
+      interf.len = 2 * R1 + 1;
+      interf.K = dS1;
+      interf.rowext = dS1ext;
+      interf.fold = foldS;
+    }
     BatchConv top;
     top.level = l;
     top.top = 1;
     top.scale = 1.0;
+    top.group = group++;
     top.len = top_len[l];
     top.off = -(top_len[l] - 1) / 2;
     if (top_len[l] > 0) {
       if ((st = upload_stencil<double>(P, tops[l], top_len[l], &top.K, &top.rowext, &top.fold)))
         return st;
     }
-    for (BatchConv* bc : {&inter, &top}) {
+    for (BatchConv* bc : {&inter, &interf, &top}) {
       if (bc->top && top_len[l] == 0) continue;
+      if (bc == &interf && !has_fact) continue;
+      if (bc == &inter && has_fact && !want_direct) continue;
       bool any = false;
       for (int s = 0; s < B.n_sys; ++s)
         if (l <= B.L[s] && ((B.L[s] == l) == (bc->top != 0))) any = true;
@@ -806,8 +986,20 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
   if (hipDeviceSynchronize()) return MSM_ERR_HIP;
   // autotune the tile shape of each convolution, then build the task lists
   if ((st = autotune<T>(P))) return st;
+  bool any_fact = false;
+  for (const BatchConv& bc : B.convs) any_fact |= bc.fact != 0;
+  if (!any_fact)  // the pass buffers are not needed
+    for (void** buf : {&B.xbuf, &B.ybuf}) {
+      for (size_t k = 0; k < P->allocs.size(); ++k)
+        if (P->allocs[k] == *buf) {
+          (void)hipFree(*buf);
+          P->allocs.erase(P->allocs.begin() + k);
+          break;
+        }
+      *buf = nullptr;
+    }
   for (BatchConv& bc : B.convs) {
-    std::vector<ConvTask> t = build_tasks(B, bc.level, bc.top, bc.cfg);
+    std::vector<ConvTask> t = build_tasks(B, bc, bc.cfg);
     if ((st = hip_alloc(P, (void**)&bc.tasks, std::max<size_t>(t.size(), 1) * sizeof(ConvTask))))
       return st;
     if (!t.empty() &&
@@ -905,13 +1097,15 @@ extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const doub
         B.Gtot[l - 1] = acc;
       }
     }
-    std::vector<double> K1;
+    std::vector<double> K1, S1;
     int W[3] = {0, 0, 0};
     std::vector<std::vector<double>> tops(kMaxLevels + 1);
     std::vector<int> top_len(kMaxLevels + 1, 0);
     if (st == MSM_OK) {
       const double h3[3] = {h, h, h};
       level1_stencil(order, M, cutoff_a, h3, W, K1, B.gcoef);
+      const int R1[3] = {W[0] - M, W[1] - M, W[2] - M};
+      level1_samples(order, cutoff_a, h3, R1, B.gcoef, S1);
       for (int l = 1; l <= B.Lmax; ++l) {
         int nmax = 0;
         for (int s = 0; s < n_sys; ++s)
@@ -923,8 +1117,8 @@ extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const doub
         free_top_kernel(order, M, cutoff_a, l, hl3, n3, B.omega, B.gcoef, tops[l]);
         top_len[l] = 2 * nmax - 1;
       }
-      st = precision == MSM_FP64 ? upload_batch<double>(P, K1, W[0], tops, top_len)
-                                 : upload_batch<float>(P, K1, W[0], tops, top_len);
+      st = precision == MSM_FP64 ? upload_batch<double>(P, K1, W[0], S1, W[0] - M, tops, top_len)
+                                 : upload_batch<float>(P, K1, W[0], S1, W[0] - M, tops, top_len);
     }
   } catch (...) {
     st = MSM_ERR_OOM;
@@ -998,7 +1192,8 @@ std::string describe_batch(const msm::BatchState& B) {
     << ",\"convs\":[";
   for (size_t i = 0; i < B.convs.size(); ++i)
     o << (i ? "," : "") << "{\"level\":" << B.convs[i].level << ",\"top\":" << B.convs[i].top
-      << ",\"len\":" << B.convs[i].len << ",\"tasks\":" << B.convs[i].ntasks
+      << ",\"len\":" << B.convs[i].len << ",\"factored\":" << B.convs[i].fact
+      << ",\"tasks\":" << B.convs[i].ntasks
       << ",\"tile_cfg\":" << B.convs[i].cfg << "}";
   o << "]}";
   return o.str();

@@ -214,6 +214,21 @@ void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::ve
   conv_axis(t2, n2, 2, false, om, K, n3);
 }
 
+// The ball of the factored level-1 stencil on an orthorhombic grid: S^1(d) =
+// k_1(|h o d|) on |d_k| <= R_k, [2R_2+1][2R_1+1][2R_0+1] (K^1 = omega' x
+// omega' x omega' * S^1, eq. kernel_stencil_by_conv_with_universal_coeff).
+void level1_samples(int p, double a, const double h[3], const int R[3], const double* gcoef,
+                    std::vector<double>& S, int nu) {
+  const int n0 = 2 * R[0] + 1, n1 = 2 * R[1] + 1, n2 = 2 * R[2] + 1;
+  S.assign((size_t)n0 * n1 * n2, 0.0);
+  for (int z = 0; z < n2; ++z)
+    for (int y = 0; y < n1; ++y)
+      for (int x = 0; x < n0; ++x)
+        S[((size_t)z * n1 + y) * n0 + x] =
+            split_kernel(gcoef, p, 1, 2, a, offset_length(nullptr, h, x - R[0], y - R[1], z - R[2]),
+                         nu);
+}
+
 // ---------------------------------------------------------------------------
 // Ewald sums for the periodic top level.  psi is the potential of a unit
 // charge and all its periodic images with tin-foil boundary conditions (and a

@@ -90,6 +90,10 @@ std::vector<double> quasi_sequence(int p, int M);
 // the Cartesian axes.
 void level1_stencil(int p, int M, double a, const double h[3], int W[3], std::vector<double>& K,
                     const double* gcoef, const double* A = nullptr, int nu = 1);
+// The ball of the factored level-1 stencil, S^1(d) = k_1(|h o d|) on
+// |d_k| <= R_k (orthorhombic grid), [2R_2+1][2R_1+1][2R_0+1].
+void level1_samples(int p, double a, const double h[3], const int R[3], const double* gcoef,
+                    std::vector<double>& S, int nu = 1);
 // Dense top-level kernel of a free-space system: offsets |d_k| <= n_k - 1.
 void free_top_kernel(int p, int M, double a, int L, const double hL[3], const int n[3],
                      const std::vector<double>& omega, const double* gcoef,

@@ -68,6 +68,48 @@ def test_batch_equals_single_system_plans():
             np.testing.assert_allclose(F[a:b], Fs.cpu().numpy(), rtol=1e-9, atol=1e-11)
 
 
+@pytest.mark.parametrize("fp64", [True, False])
+def test_batch_factored_levels_match_direct(fp64):
+    """Intermediate levels in the factored form (three omega' passes onto
+    grids extended by M, then the ball of k-samples; forced with
+    MSM_FACTORED=1) against the direct stencil (MSM_FACTORED=0) on the same
+    batch, and the oracle per system.  By default the autotuner keeps the
+    faster form per level."""
+    off, boxes, pos, q = WL.clusters(10, 20, 120, 12.0, 26.0, 0.5, seed=14)
+    levels = np.where(boxes <= 20.0, 2, 3).astype(np.int32)
+    dt = np.float64 if fp64 else np.float32
+    pos, q = pos.astype(dt).astype(np.float64), q.astype(dt).astype(np.float64)
+    prec = msm.MSM_FP64 if fp64 else msm.MSM_FP32
+    print(f"case batch factored vs direct {'fp64' if fp64 else 'fp32'}", flush=True)
+    os.environ["MSM_FACTORED"] = "1"
+    try:
+        bp = msm.BatchPlan(boxes, levels, 4, 1.0, 6.0, prec, int(off[-1]))
+    finally:
+        del os.environ["MSM_FACTORED"]
+    convs = bp.describe()["convs"]
+    assert sum(c["factored"] for c in convs) == 2, convs  # levels 1 and 2
+    E, F, dq = _run_batch(bp, off, pos, q)
+    assert bp.status() == 0
+    os.environ["MSM_FACTORED"] = "0"
+    try:
+        bd = msm.BatchPlan(boxes, levels, 4, 1.0, 6.0, prec, int(off[-1]))
+    finally:
+        del os.environ["MSM_FACTORED"]
+    assert not any(c["factored"] for c in bd.describe()["convs"])
+    Ed, Fd, dqd = _run_batch(bd, off, pos, q)
+    tol = 1e-12 if fp64 else 1e-6
+    print(f"  relE {np.max(np.abs(E - Ed) / np.abs(Ed)):.1e} relF {rel_rms(F, Fd):.1e}", flush=True)
+    assert np.all(np.abs(E - Ed) <= tol * np.abs(Ed))
+    assert rel_rms(F, Fd) <= tol and rel_rms(dq, dqd) <= tol
+    bars = TOL["fp64" if fp64 else "fp32"]
+    for s in (0, 4, 9):
+        a, b = off[s], off[s + 1]
+        ref = O.OracleMSM((boxes[s],) * 3, (0, 0, 0), 4, 1.0, 6.0, int(levels[s])).compute(
+            pos[a:b], q[a:b])
+        assert_parity(F[a:b], ref["F"], bars["F"], f"F of system {s}")
+        assert abs(E[s] - ref["E"]) <= bars["E"] * abs(ref["E"]), s
+
+
 def test_batch_graph_replays_match_eager():
     import torch
     off, boxes, pos, q, levels = _small_batch(30, seed=13)
