@@ -126,13 +126,12 @@ msm_status msm_energy_forces_cell_gradient(msm_plan plan, int n, const void* pos
  * s = (r/a)^2 below 1 and r^-nu above; the intermediate stencils are
  * K^1 / 2^((l-1) nu).  For nu = 6 "charges" are per-particle coefficients c_i
  * (E = 1/2 sum_{i != j} c_i c_j r^-6, geometric mixing; negate the result
- * for an attractive dispersion energy).  nu = 6 takes periodic_mask 0
- * (free space) or 7: the top level then sums k_L over the lattice with the
- * Ewald method for r^-6, which converges absolutely (no boundary term; with
- * periodic images, E = 1/2 sum_{i,j} c_i c_j sum_n' |r_i - r_j + n|^-6, the
- * n = 0 term left out for i = j).  Other masks: MSM_ERR_UNSUPPORTED.  a/h of
- * about 8 or more is needed before the higher orders pay (the softened r^-6
- * is stiff).
+ * for an attractive dispersion energy).  nu = 6 takes every periodic_mask:
+ * with periodic axes the top level sums k_L over the lattice of those axes
+ * with the Ewald method for r^-6 (3-D, slab or line form), which converges
+ * absolutely (no boundary term; E = 1/2 sum_{i,j} c_i c_j sum_n' |r_i - r_j
+ * + n|^-6, the n = 0 term left out for i = j).  a/h of about 8 or more is
+ * needed before the higher orders pay (the softened r^-6 is stiff).
  * Every compute call, the backward included, works as for Coulomb plans;
  * batched plans are Coulomb only.
  */

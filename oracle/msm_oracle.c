@@ -896,11 +896,12 @@ static void orc_gauss16(double xg[16], double wg[16])
   }
 }
 
-/* F(k, rho) above, over the t-range where the exponent b e^t + c e^-t stays
- * below 45 (outside it the integrand is below e^-45 and the tails add less
- * than 1e-18), in panels of width <= 1/8 with 16 Gauss points each. */
-static double orc_incomplete_bessel(double b, double c, const double xg[16],
-                                    const double wg[16])
+/* int_0^inf e^{-w t} exp(-b e^t - c e^-t) dt (w >= 0, b > 0) over the t-range
+ * where the exponent b e^t + c e^-t stays below 45 (outside it the integrand
+ * is below e^-45 and the tails add less than 1e-18), in panels of width
+ * <= 1/8 with 16 Gauss points each.  w = 0 is F(k, rho) above. */
+static double orc_exp_integral(double wexp, double b, double c, const double xg[16],
+                               const double wg[16])
 {
   const double E = 45.0, D = E * E - 4.0 * b * c;
   if (D <= 0.0) return 0.0;
@@ -915,10 +916,16 @@ static double orc_incomplete_bessel(double b, double c, const double xg[16],
     const double mid = t0 + (j + 0.5) * w;
     for (int i = 0; i < 16; ++i) {
       const double t = mid + 0.5 * w * xg[i];
-      sum += 0.5 * w * wg[i] * exp(-b * exp(t) - c * exp(-t));
+      sum += 0.5 * w * wg[i] * exp(-wexp * t - b * exp(t) - c * exp(-t));
     }
   }
   return sum;
+}
+
+static double orc_incomplete_bessel(double b, double c, const double xg[16],
+                                    const double wg[16])
+{
+  return orc_exp_integral(0.0, b, c, xg, wg);
 }
 
 double orc_ewald1d(const double box[3], int axis, double alpha, const double x[3], int reg)
@@ -1005,6 +1012,154 @@ double orc_ewald3d_r6(const double box[3], double alpha, const double x[3], int 
         recip += f * cos(gx * x[0] + gy * x[1] + gz * x[2]);
       }
   return real + pow(M_PI, 1.5) * alpha * alpha * alpha / (3.0 * V) * recip;
+}
+
+/* ------------------------------------------------------------------------
+ * Lattice sums of r^-6 over two periodic axes (slab) or one (line), by the
+ * same split as the 3-D sum: real space e^{-y}(1 + y + y^2/2)/r^6 over the
+ * images, y = alpha^2 r^2; the rest, f(r) = (1/2) int_0^{alpha^2} t^2
+ * e^{-r^2 t} dt, by Poisson summation over the periodic axes only.
+ *   slab (cell area A, z the free coordinate, k over the 2-D reciprocal
+ *   lattice): (1/A) sum_k cos(k.x) (pi/2) int_0^{alpha^2} t e^{-t z^2 - k^2/(4t)} dt;
+ *   line (period L, rho the distance from the axis, k = 2 pi m / L):
+ *   (1/L) sum_m cos(k z) (sqrt(pi)/2) int_0^{alpha^2} t^{3/2} e^{-t rho^2 - k^2/(4t)} dt.
+ * With t = alpha^2 e^{-u} the k != 0 integrals become alpha^4 (slab), alpha^5
+ * (line) times int_0^inf e^{-w u} exp(-b e^u - c e^-u) du, w = 2 or 5/2,
+ * b = k^2/(4 alpha^2), c = alpha^2 z^2 or alpha^2 rho^2; the k = 0 ones are
+ * elementary.  Both sums converge absolutely (no boundary term).
+ * ---------------------------------------------------------------------- */
+/* int_0^{alpha^2} t e^{-t z^2} dt */
+static double orc_r6_slab_k0(double alpha, double z)
+{
+  const double a2 = alpha * alpha, y = a2 * z * z;
+  if (y < 1.0) { /* series: alpha^4 sum_j (-y)^j / (j! (j + 2)) */
+    double term = 1.0, sum = 0.5;
+    for (int j = 1; j < 60; ++j) {
+      term *= -y / j;
+      sum += term / (j + 2);
+    }
+    return a2 * a2 * sum;
+  }
+  const double z4 = z * z * z * z;
+  return (1.0 - exp(-y) * (1.0 + y)) / z4;
+}
+
+/* int_0^{alpha^2} t^{3/2} e^{-t rho^2} dt */
+static double orc_r6_line_k0(double alpha, double rho)
+{
+  const double a2 = alpha * alpha, x = a2 * rho * rho;
+  if (x < 1.0) { /* series: alpha^5 sum_j (-x)^j / (j! (j + 5/2)) */
+    double term = 1.0, sum = 0.4;
+    for (int j = 1; j < 60; ++j) {
+      term *= -x / j;
+      sum += term / (j + 2.5);
+    }
+    return a2 * a2 * alpha * sum;
+  }
+  /* lower incomplete gamma: gamma(5/2, x) / rho^5, with
+   * Gamma(1/2, x) = sqrt(pi) erfc(sqrt x), Gamma(s+1, x) = s Gamma(s, x) + x^s e^-x */
+  const double g12 = sqrt(M_PI) * erfc(sqrt(x));
+  const double g32 = 0.5 * g12 + sqrt(x) * exp(-x);
+  const double g52 = 1.5 * g32 + x * sqrt(x) * exp(-x);
+  const double lower = 0.75 * sqrt(M_PI) - g52;
+  const double r5 = rho * rho * rho * rho * rho;
+  return lower / r5;
+}
+
+static double orc_r6_real(double alpha, double r2)
+{
+  const double y = alpha * alpha * r2;
+  return exp(-y) * (1.0 + y + 0.5 * y * y) / (r2 * r2 * r2);
+}
+
+/* slab: free axis f, the other two periodic */
+double orc_ewald2d_r6(const double box[3], int f, double alpha, const double x[3], int reg)
+{
+  const int a0 = f == 0 ? 1 : 0, a1 = f == 2 ? 1 : 2;
+  const double La = box[a0], Lb = box[a1], A = La * Lb, z = x[f];
+  const double rc = 7.0 / alpha;
+  const int na = (int)ceil((rc + fabs(x[a0])) / La) + 1, nb = (int)ceil((rc + fabs(x[a1])) / Lb) + 1;
+  double real = 0.0;
+  for (int j = -nb; j <= nb; ++j)
+    for (int i = -na; i <= na; ++i) {
+      const double da = x[a0] + i * La, db = x[a1] + j * Lb;
+      const double r2 = da * da + db * db + z * z;
+      if (r2 == 0.0) {
+        if (!reg) return INFINITY;
+        real -= pow(alpha, 6) / 6.0;
+        continue;
+      }
+      if (r2 > rc * rc) continue;
+      real += orc_r6_real(alpha, r2);
+    }
+  double xg[16], wg[16];
+  orc_gauss16(xg, wg);
+  const double c = alpha * alpha * z * z, a4 = pow(alpha, 4);
+  /* b <= 45 bounds the Fourier terms kept */
+  const double kc = 2.0 * alpha * sqrt(45.0);
+  const int ma = (int)ceil(kc * La / (2.0 * M_PI)) + 1, mb = (int)ceil(kc * Lb / (2.0 * M_PI)) + 1;
+  double recip = orc_r6_slab_k0(alpha, z);
+  for (int j = -mb; j <= mb; ++j)
+    for (int i = -ma; i <= ma; ++i) {
+      if (i == 0 && j == 0) continue;
+      const double ka = 2.0 * M_PI * i / La, kb = 2.0 * M_PI * j / Lb;
+      const double b = (ka * ka + kb * kb) / (4.0 * alpha * alpha);
+      if (b > 45.0) continue;
+      recip += a4 * cos(ka * x[a0] + kb * x[a1]) * orc_exp_integral(2.0, b, c, xg, wg);
+    }
+  return real + 0.5 * M_PI / A * recip;
+}
+
+/* line: axis periodic, the other two free */
+double orc_ewald1d_r6(const double box[3], int axis, double alpha, const double x[3], int reg)
+{
+  const double L = box[axis], z = x[axis];
+  double rho2 = 0.0;
+  for (int k = 0; k < 3; ++k)
+    if (k != axis) rho2 += x[k] * x[k];
+  const double rc = 7.0 / alpha;
+  const int nr = (int)ceil((rc + fabs(z)) / L) + 1;
+  double real = 0.0;
+  for (int j = -nr; j <= nr; ++j) {
+    const double dz = z + j * L, r2 = rho2 + dz * dz;
+    if (r2 == 0.0) {
+      if (!reg) return INFINITY;
+      real -= pow(alpha, 6) / 6.0;
+      continue;
+    }
+    if (r2 > rc * rc) continue;
+    real += orc_r6_real(alpha, r2);
+  }
+  double xg[16], wg[16];
+  orc_gauss16(xg, wg);
+  const double c = alpha * alpha * rho2, a5 = pow(alpha, 5);
+  double recip = 0.0;
+  for (int m = 1;; ++m) {
+    const double k = 2.0 * M_PI * m / L, b = k * k / (4.0 * alpha * alpha);
+    if (b > 45.0) break;
+    recip += 2.0 * a5 * cos(k * z) * orc_exp_integral(2.5, b, c, xg, wg);
+  }
+  recip += orc_r6_line_k0(alpha, sqrt(rho2));
+  return real + 0.5 * sqrt(M_PI) / L * recip;
+}
+
+/* sum_n |x + n|^-6 over the lattice of the periodic axes of mask (1..7) */
+double orc_ewald_r6(const double box[3], unsigned mask, double alpha, const double x[3],
+                    int reg)
+{
+  if (mask == 7) return orc_ewald3d_r6(box, alpha, x, reg);
+  int np = 0, axis = 0, freeax = 0;
+  for (int k = 0; k < 3; ++k) {
+    if ((mask >> k) & 1) {
+      ++np;
+      axis = k;
+    } else {
+      freeax = k;
+    }
+  }
+  if (np == 2) return orc_ewald2d_r6(box, freeax, alpha, x, reg);
+  if (np == 1) return orc_ewald1d_r6(box, axis, alpha, x, reg);
+  return NAN;
 }
 
 /* psi for any set of periodic axes (bit k of mask = axis k periodic): the

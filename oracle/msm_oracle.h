@@ -125,6 +125,12 @@ double orc_ewald1d(const double box[3], int axis, double alpha, const double x[3
  * Ewald method (absolutely convergent: no boundary term); reg = 1 at x = 0
  * leaves out the n = 0 term. */
 double orc_ewald3d_r6(const double box[3], double alpha, const double x[3], int reg);
+/* The same lattice sum of r^-6 over two periodic axes (free axis f) or one
+ * (axis), and for any mask 1..7. */
+double orc_ewald2d_r6(const double box[3], int f, double alpha, const double x[3], int reg);
+double orc_ewald1d_r6(const double box[3], int axis, double alpha, const double x[3], int reg);
+double orc_ewald_r6(const double box[3], unsigned mask, double alpha, const double x[3],
+                    int reg);
 /* psi for the periodic axes of mask (bit k = axis k): 7, any two, any one. */
 double orc_ewald_psi(const double box[3], unsigned mask, double alpha, const double x[3],
                      int reg);

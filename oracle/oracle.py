@@ -135,6 +135,8 @@ def lib():
             getattr(L, name).restype = d
         L.orc_ewald3d_r6.argtypes = [P, d, P, i]
         L.orc_ewald3d_r6.restype = d
+        L.orc_ewald_r6.argtypes = [P, ctypes.c_uint, d, P, i]
+        L.orc_ewald_r6.restype = d
         L.orc_ewald1d.argtypes = [P, i, d, P, i]
         L.orc_ewald1d.restype = d
         L.orc_ewald_psi.argtypes = [P, ctypes.c_uint, d, P, i]
@@ -255,22 +257,32 @@ def ewald_potentials(box, pos, q, slab=False, alpha=None, periodic=None):
     return phi
 
 
-def ewald_psi_r6(box, x, alpha=None, reg=False):
-    """sum_n |x + n|^-6 over the lattice of a 3-D periodic box (Ewald method;
+def _default_alpha_r6(box, mask):
+    """Any alpha gives the same r^-6 lattice sum; these keep both parts short."""
+    per = [box[k] for k in range(3) if (mask >> k) & 1]
+    if len(per) == 3:
+        return ewald_alpha_3d(box)
+    return (3.0 if len(per) == 2 else 2.0) / min(per)
+
+
+def ewald_psi_r6(box, x, alpha=None, reg=False, periodic=(True, True, True)):
+    """sum_n |x + n|^-6 over the lattice of the periodic axes (Ewald method;
     reg=True at x = 0 leaves out n = 0)."""
     box = _f64(box)
+    mask = _mask(periodic, False)
     if alpha is None:
-        alpha = ewald_alpha_3d(box)
-    return lib().orc_ewald3d_r6(_ptr(box), float(alpha), _ptr(_f64(x)), int(reg))
+        alpha = _default_alpha_r6(box, mask)
+    return lib().orc_ewald_r6(_ptr(box), mask, float(alpha), _ptr(_f64(x)), int(reg))
 
 
-def ewald_potentials_r6(box, pos, q, alpha=None):
+def ewald_potentials_r6(box, pos, q, alpha=None, periodic=(True, True, True)):
     """phi_i = sum_j q_j sum_n' |r_i - r_j + n|^-6 (n = 0 left out for j = i)."""
     pos, q = _f64(pos), _f64(q)
     phi = np.zeros(len(q))
     for i in range(len(q)):
         for j in range(len(q)):
-            phi[i] += q[j] * ewald_psi_r6(box, pos[i] - pos[j], alpha, reg=(i == j))
+            phi[i] += q[j] * ewald_psi_r6(box, pos[i] - pos[j], alpha, reg=(i == j),
+                                          periodic=periodic)
     return phi
 
 
@@ -347,8 +359,8 @@ class OracleMSM:
     nu: the kernel k(r) = r^-nu split the same way (gamma_nu: the Taylor
     polynomial of s^(-nu/2)); 1 is Coulomb, 6 the dispersion kernel, in free
     space (the top level is the plain dense sum) or in an orthorhombic box
-    periodic along all three axes (the top level sums k_L over the lattice with
-    the Ewald method for r^-6).
+    with any periodic axes (the top level sums k_L over the lattice of the
+    periodic axes with the Ewald method for r^-6).
     """
 
     def __init__(self, box, periodic, p, h, a, L, M=None, cell=None, ntop=None, nu=1):
@@ -364,9 +376,9 @@ class OracleMSM:
         self.periodic = [bool(x) for x in periodic]
         self.p, self.h, self.a, self.L = int(p), float(h), float(a), int(L)
         self.M = self.p if M is None else int(M)
-        self.nu = int(nu)  # kernel r^-nu: 1 anywhere, 6 in free space or an orthorhombic 3-D box
+        self.nu = int(nu)  # kernel r^-nu: 1 anywhere, 6 in orthorhombic boxes
         assert self.nu in (1, 6)
-        assert self.nu == 1 or (self.cell is None and sum(self.periodic) in (0, 3))
+        assert self.nu == 1 or self.cell is None
         assert self.p % 2 == 0 and self.p >= 2 and 1 <= self.L <= MAXL
         for k in range(3):
             if self.periodic[k]:
@@ -500,7 +512,7 @@ class OracleMSM:
         if nu == 1:
             val = ewald_psi(self.box, x, periodic=self.periodic, reg=True)
         else:
-            val = ewald_psi_r6(self.box, x, reg=True)
+            val = ewald_psi_r6(self.box, x, reg=True, periodic=self.periodic)
         # k_L = gamma_nu(r/R)/R^nu = r^-nu - (r^-nu - gamma_nu(r/R)/R^nu) for r < R
         nimg = [int(math.ceil((R + abs(x[k])) / self.box[k])) + 1 if self.periodic[k] else 0
                 for k in range(3)]

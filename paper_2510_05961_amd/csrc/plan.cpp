@@ -328,22 +328,34 @@ static double ein(double x) {  // int_0^x (1 - e^-v)/v dv
   return s;
 }
 
-static double incomplete_bessel(double b, double c) {
-  const double E = 46.0, D = E * E - 4.0 * b * c;
-  if (D <= 0.0) return 0.0;
-  const double hi = std::log((E + std::sqrt(D)) / (2.0 * b));
-  if (hi <= 0.0) return 0.0;
-  const double lo = std::max(0.0, std::log((E - std::sqrt(D)) / (2.0 * b)));
+// int_0^inf e^{-wt} exp(-b e^t - c e^-t) dt by tanh-sinh quadrature over the
+// t-range where the exponent stays below 46: bounded by b e^t + c e^-t when
+// b > 0, by w t and c e^-t when b = 0 (then w > 0).
+static double exp_integral(double w, double b, double c) {
+  const double E = 46.0;
+  double lo, hi;
+  if (b > 0.0) {
+    const double D = E * E - 4.0 * b * c;
+    if (D <= 0.0) return 0.0;
+    hi = std::log((E + std::sqrt(D)) / (2.0 * b));
+    lo = std::max(0.0, std::log((E - std::sqrt(D)) / (2.0 * b)));
+  } else {
+    hi = E / w;
+    lo = c > E ? std::log(c / E) : 0.0;
+  }
+  if (hi <= lo) return 0.0;
   const double mid = 0.5 * (hi + lo), half = 0.5 * (hi - lo), step = 1.0 / 32.0;
   double sum = 0.0;
   for (int k = -112; k <= 112; ++k) {  // |u| <= 3.5: weights below 1e-30 beyond
     const double u = k * step, v = 0.5 * M_PI * std::sinh(u);
-    const double w = 0.5 * M_PI * std::cosh(u) / (std::cosh(v) * std::cosh(v));
+    const double wt = 0.5 * M_PI * std::cosh(u) / (std::cosh(v) * std::cosh(v));
     const double t = mid + half * std::tanh(v);
-    sum += w * std::exp(-b * std::exp(t) - c * std::exp(-t));
+    sum += wt * std::exp(-w * t - b * std::exp(t) - c * std::exp(-t));
   }
   return sum * half * step;
 }
+
+static double incomplete_bessel(double b, double c) { return exp_integral(0.0, b, c); }
 
 static double ewald1d(const double box[3], int ax, const double x[3]) {
   const double L = box[ax], z = x[ax];
@@ -412,6 +424,80 @@ static double ewald3d_r6(const double box[3], const double x[3]) {
         rec += w * std::cos(g[0] * x[0] + g[1] * x[1] + g[2] * x[2]);
       }
   return val + std::pow(M_PI, 1.5) * alpha * alpha * alpha / (3.0 * V) * rec;
+}
+
+// Lattice sums of r^-6 over two periodic axes (slab, free axis f) or one
+// (line): real space e^{-y}(1 + y + y^2/2)/r^6 over the images as in 3-D;
+// the smooth rest (1/2) int_0^{alpha^2} t^2 e^{-r^2 t} dt summed over the
+// periodic axes by Poisson summation, where the 2-D (1-D) transform of
+// e^{-t rho^2} is (pi/t) e^{-k^2/4t} (sqrt(pi/t) e^{-k^2/4t}).  With t =
+// alpha^2 e^{-u} every Fourier term, k = 0 included, is alpha^4 (alpha^5)
+// times int_0^inf e^{-w u} exp(-b e^u - c e^-u) du with w = 2 (5/2),
+// b = k^2/(4 alpha^2) and c = alpha^2 z^2 (alpha^2 rho^2).
+static double r6_real(double alpha, double r2) {
+  const double y = alpha * alpha * r2;
+  return std::exp(-y) * (1.0 + y + 0.5 * y * y) / (r2 * r2 * r2);
+}
+
+static double ewald2d_r6(const double box[3], int f, const double x[3]) {
+  const int a0 = f == 0 ? 1 : 0, a1 = f == 2 ? 1 : 2;
+  const double La = box[a0], Lb = box[a1], z = x[f];
+  const double alpha = 1.5 / std::min(La, Lb), rc = 7.2 / alpha;
+  const int na = (int)std::ceil((rc + std::fabs(x[a0])) / La) + 1;
+  const int nb = (int)std::ceil((rc + std::fabs(x[a1])) / Lb) + 1;
+  double val = 0.0;
+  for (int i = -na; i <= na; ++i)
+    for (int j = -nb; j <= nb; ++j) {
+      const double da = x[a0] + i * La, db = x[a1] + j * Lb, r2 = da * da + db * db + z * z;
+      if (r2 == 0.0)
+        val -= std::pow(alpha, 6) / 6.0;
+      else if (r2 < rc * rc)
+        val += r6_real(alpha, r2);
+    }
+  const double c = alpha * alpha * z * z;
+  const int ma = (int)std::ceil(2.0 * alpha * std::sqrt(46.0) * La / (2.0 * M_PI)) + 1;
+  const int mb = (int)std::ceil(2.0 * alpha * std::sqrt(46.0) * Lb / (2.0 * M_PI)) + 1;
+  double rec = 0.0;
+  for (int i = -ma; i <= ma; ++i)
+    for (int j = -mb; j <= mb; ++j) {
+      const double ka = 2.0 * M_PI * i / La, kb = 2.0 * M_PI * j / Lb;
+      const double b = (ka * ka + kb * kb) / (4.0 * alpha * alpha);
+      if (b > 46.0) continue;
+      rec += std::cos(ka * x[a0] + kb * x[a1]) * exp_integral(2.0, b, c);
+    }
+  return val + M_PI / (2.0 * La * Lb) * std::pow(alpha, 4) * rec;
+}
+
+static double ewald1d_r6(const double box[3], int ax, const double x[3]) {
+  const double L = box[ax], z = x[ax];
+  const double alpha = 1.0 / L, rc = 7.2 / alpha;
+  double rho2 = 0.0;
+  for (int k = 0; k < 3; ++k)
+    if (k != ax) rho2 += x[k] * x[k];
+  const int nr = (int)std::ceil((rc + std::fabs(z)) / L) + 1;
+  double val = 0.0;
+  for (int i = -nr; i <= nr; ++i) {
+    const double dz = z + i * L, r2 = rho2 + dz * dz;
+    if (r2 == 0.0)
+      val -= std::pow(alpha, 6) / 6.0;
+    else if (r2 < rc * rc)
+      val += r6_real(alpha, r2);
+  }
+  const double c = alpha * alpha * rho2;
+  double rec = exp_integral(2.5, 0.0, c);
+  for (int m = 1;; ++m) {
+    const double k = 2.0 * M_PI * m / L, b = k * k / (4.0 * alpha * alpha);
+    if (b > 46.0) break;
+    rec += 2.0 * std::cos(k * z) * exp_integral(2.5, b, c);
+  }
+  return val + std::sqrt(M_PI) / (2.0 * L) * std::pow(alpha, 5) * rec;
+}
+
+static double ewald_r6_axes(const HostPlan& P, const double x[3]) {
+  const int np = P.periodic[0] + P.periodic[1] + P.periodic[2];
+  if (np == 3) return ewald3d_r6(P.box, x);
+  if (np == 1) return ewald1d_r6(P.box, P.periodic[0] ? 0 : (P.periodic[1] ? 1 : 2), x);
+  return ewald2d_r6(P.box, !P.periodic[0] ? 0 : (!P.periodic[1] ? 1 : 2), x);
 }
 
 // Ewald potential for the periodic axes of the plan (not triclinic): all
@@ -498,10 +584,10 @@ static double periodic_top_G(const HostPlan& P, const double x[3]) {
         }
     return val;
   }
-  // kernel r^-nu: Coulomb for every set of periodic axes, r^-6 with all three
+  // kernel r^-nu (Coulomb or r^-6), every set of periodic axes
   const int nu = P.nu;
   const double Rn = std::pow(R, nu);
-  double val = nu == 1 ? ewald_axes(P, x) : ewald3d_r6(P.box, x);
+  double val = nu == 1 ? ewald_axes(P, x) : ewald_r6_axes(P, x);
   int ni[3];
   for (int k = 0; k < 3; ++k)
     ni[k] = P.periodic[k] ? (int)std::ceil((R + std::fabs(x[k])) / P.box[k]) + 1 : 0;
@@ -577,10 +663,10 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
     }
   }
   if (order != 4 && order != 6 && order != 8) return MSM_ERR_UNSUPPORTED;
-  // kernels r^-nu: Coulomb (1) anywhere, dispersion (6) in free space or an
-  // orthorhombic box periodic along all three axes (its 3-D Ewald sum)
+  // kernels r^-nu: Coulomb (1) anywhere, dispersion (6) in orthorhombic boxes
+  // with any periodic axes (the top level by its lattice sums)
   if (nu != 1 && nu != 6) return MSM_ERR_INVALID_ARG;
-  if (nu != 1 && ((periodic_mask != 0 && periodic_mask != 7) || P.tri)) return MSM_ERR_UNSUPPORTED;
+  if (nu != 1 && P.tri) return MSM_ERR_UNSUPPORTED;
   P.nu = nu;
   if (periodic_mask > 7) return MSM_ERR_INVALID_ARG;
   if (M < 0) M = order;

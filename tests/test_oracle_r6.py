@@ -2,8 +2,9 @@
 paper's splitting applied to another power (Sec. Splitting for Coulomb
 kernels; the package's core is meant to take other kernels): the softener's
 contact with r^-6, the telescoping split, the MSM against the exact
-all-pairs sum (free space); the 3-D Ewald sum of r^-6 against brute-force
-lattice sums, and the periodic MSM against that sum."""
+all-pairs sum (free space); the Ewald sums of r^-6 over three, two or one
+periodic axes against brute-force lattice sums, and the periodic MSM
+against them."""
 import numpy as np
 import pytest
 
@@ -107,11 +108,7 @@ def test_msm_r6_sampled_equals_full():
     np.testing.assert_allclose(F, full["F"][sel], rtol=1e-12, atol=1e-14)
 
 
-def test_r6_other_periodicities_are_refused():
-    # the r^-6 top level is summed by the 3-D Ewald method only
-    for per in ((1, 1, 0), (0, 0, 1)):
-        with pytest.raises(AssertionError):
-            O.OracleMSM((10.0,) * 3, per, 4, 1.0, 3.0, 2, nu=NU)
+def test_r6_triclinic_is_refused():
     with pytest.raises(AssertionError):
         O.OracleMSM(None, (1, 1, 1), 4, 1.0, 3.0, 2, nu=NU, cell=np.diag([10.0] * 3))
 
@@ -119,22 +116,28 @@ def test_r6_other_periodicities_are_refused():
 # --------------------------------------------------------------------------
 # periodic r^-6: the 3-D Ewald sum of the dispersion kernel and the MSM on it
 # --------------------------------------------------------------------------
-def _lattice_brute(box, x, reg, Ns=(16, 32, 64)):
-    """sum over |n_k| <= N of |x + n o box|^-6 at three N, extrapolated in the
-    half-width M = N + 1/2 of the summed block: the missing tail is
-    c3/M^3 + c5/M^5 + O(M^-7) (the sum over a block's complement against its
-    integral, symmetric in the shift x)."""
+def _lattice_brute(box, x, reg, periodic=(1, 1, 1), Ns=None):
+    """sum over |n_k| <= N (periodic axes k) of |x + n o box|^-6 at three N,
+    extrapolated in the half-width M = N + 1/2 of the summed block: with d
+    periodic axes the missing tail is c/M^(6-d) + c'/M^(8-d) + ... (the sum
+    over a block's complement against its integral, symmetric in the shift x)."""
     box = np.asarray(box, dtype=np.float64)
+    axes = [k for k in range(3) if periodic[k]]
+    d = len(axes)
+    if Ns is None:
+        Ns = {3: (16, 32, 64), 2: (200, 400, 800), 1: (2000, 4000, 8000)}[d]
     T = []
     for N in Ns:
         r = np.arange(-N, N + 1, dtype=np.float64)
-        gx, gy, gz = np.meshgrid(r * box[0] + x[0], r * box[1] + x[1], r * box[2] + x[2],
-                                 indexing="ij")
-        r2 = gx * gx + gy * gy + gz * gz
+        grids = np.meshgrid(*[r * box[k] for k in axes], indexing="ij")
+        comp = [np.full(grids[0].shape, float(x[k])) for k in range(3)]
+        for g, k in zip(grids, axes):
+            comp[k] = comp[k] + g
+        r2 = comp[0] ** 2 + comp[1] ** 2 + comp[2] ** 2
         if reg:
             r2 = r2[r2 > 0]
         T.append(float(np.sum(r2 ** -3)))
-    A = np.array([[1.0, (N + 0.5) ** -3, (N + 0.5) ** -5] for N in Ns])
+    A = np.array([[1.0, (N + 0.5) ** -(6 - d), (N + 0.5) ** -(8 - d)] for N in Ns])
     return float(np.linalg.solve(A, T)[0])
 
 
@@ -158,6 +161,21 @@ def test_r6_lattice_sum_equals_brute_force(box, x, reg):
                                                               rel=1e-10)
 
 
+R6_AXES = [((1, 1, 0), (0.3, -0.7, 1.1), False), ((1, 1, 0), (0.0, 0.0, 0.0), True),
+           ((1, 0, 1), (1.4, 1.6, 1.9), False), ((0, 0, 1), (0.3, -0.7, 1.1), False),
+           ((0, 0, 1), (0.0, 0.0, 0.0), True), ((0, 1, 0), (0.2, 0.1, 0.0), False)]
+
+
+@pytest.mark.parametrize("per,x,reg", R6_AXES)
+def test_r6_slab_and_line_sums(per, x, reg):
+    """Two periodic axes or one: alpha-independence and brute-force lattice
+    sums, as for three."""
+    box = (3.0, 3.5, 4.0)
+    vals = [O.ewald_psi_r6(box, x, alpha=a, reg=reg, periodic=per) for a in (0.3, 0.5, 0.8)]
+    assert max(vals) - min(vals) <= 1e-12 * abs(vals[0])
+    assert vals[0] == pytest.approx(_lattice_brute(box, x, reg, per), rel=1e-12)
+
+
 def test_r6_lattice_sum_sublattices():
     # the lattice of box is the union of the 8 shifted lattices of 2 box
     box = np.array([3.0, 3.5, 4.0])
@@ -174,13 +192,14 @@ def _periodic_system(n, L, seed):
     return pos, c
 
 
-def test_msm_r6_periodic_converges_to_ewald():
+@pytest.mark.parametrize("per", [(1, 1, 1), (1, 1, 0), (0, 0, 1)])
+def test_msm_r6_periodic_converges_to_ewald(per):
     box = (8.0, 8.0, 8.0)
     pos, c = _periodic_system(60, 8.0, 5)
-    phie = O.ewald_potentials_r6(box, pos, c)
+    phie = O.ewald_potentials_r6(box, pos, c, periodic=per)
     errs = []
     for p, h in ((4, 0.5), (6, 0.5), (6, 0.4)):
-        r = O.OracleMSM(box, (1, 1, 1), p, h, 4.0, 3, nu=NU).compute(pos, c)
+        r = O.OracleMSM(box, per, p, h, 4.0, 3, nu=NU).compute(pos, c)
         errs.append(np.linalg.norm(r["phi"] - phie) / np.linalg.norm(phie))
         assert abs(r["E"] - 0.5 * c @ phie) <= 3 * errs[-1] * abs(0.5 * c @ phie)
     assert errs[0] < 2e-5 and errs[0] > errs[1] > errs[2] and errs[2] < 2e-6, errs
