@@ -108,7 +108,8 @@ msm_status msm_plan_create(msm_plan* out, const double box[3], unsigned periodic
  * (stencils) and per plan (three FP64 level-1 grids).  The cutoff must stay
  * below half the cell's smallest width under a relative change of 1e-5 of
  * the cell (the top derivative builds such plans).  Errors: as
- * msm_energy_forces, MSM_ERR_UNSUPPORTED for non-triclinic plans,
+ * msm_energy_forces, MSM_ERR_UNSUPPORTED for non-triclinic plans and for
+ * r^-6 plans (msm_plan_create_cell_kernel),
  * MSM_ERR_GRID when a derivative stencil exceeds the convolution's window.
  */
 msm_status msm_energy_forces_cell_gradient(msm_plan plan, int n, const void* pos, const void* q,
@@ -140,6 +141,22 @@ msm_status msm_energy_forces_cell_gradient(msm_plan plan, int n, const void* pos
 msm_status msm_plan_create_kernel(msm_plan* out, int kernel, const double box[3],
                                   unsigned periodic_mask, int order, double h, double cutoff_a,
                                   int levels, int precision, int max_n, int quasi_degree_M);
+
+/*
+ * msm_plan_create_cell_kernel -- msm_plan_create_cell for the kernel
+ * k(r) = r^-nu, nu = kernel (MSM_KERNEL_COULOMB or MSM_KERNEL_DISPERSION;
+ * other values: MSM_ERR_INVALID_ARG), with the splitting described at
+ * msm_plan_create_kernel and the triclinic geometry of msm_plan_create_cell
+ * (Sec. "MSM core algorithm", long-range part).  For r^-6 the top level sums
+ * k_L over the lattice H n with the Ewald method for r^-6 (real space over
+ * H n, reciprocal space over 2 pi H^{-T} m; no boundary term).  Every
+ * compute call and msm_plan_set_cell work as for a Coulomb cell plan;
+ * msm_energy_forces_cell_gradient is Coulomb only (MSM_ERR_UNSUPPORTED).
+ */
+msm_status msm_plan_create_cell_kernel(msm_plan* out, int kernel, const double cell[9],
+                                       unsigned periodic_mask, int order, double h,
+                                       double cutoff_a, int levels, int precision, int max_n,
+                                       int quasi_degree_M);
 
 /*
  * msm_plan_create_cell -- msm_plan_create for a triclinic cell (Sec. "MSM core

@@ -1254,6 +1254,62 @@ double orc_ewald3d_cell(const double H[9], double alpha, const double x[3], int 
   return real + recip - M_PI / (alpha * alpha * V);
 }
 
+/* The lattice sum of r^-6 over the lattice spanned by the columns of H: the
+ * 3-D r^-6 Ewald sum above with images H n and wave vectors 2 pi H^{-T} m. */
+double orc_ewald3d_cell_r6(const double H[9], double alpha, const double x[3], int reg)
+{
+  const double det = det3(H), V = fabs(det);
+  double Hi[9]; /* H^{-1} by cofactors */
+  Hi[0] = (H[4] * H[8] - H[5] * H[7]) / det;
+  Hi[1] = (H[2] * H[7] - H[1] * H[8]) / det;
+  Hi[2] = (H[1] * H[5] - H[2] * H[4]) / det;
+  Hi[3] = (H[5] * H[6] - H[3] * H[8]) / det;
+  Hi[4] = (H[0] * H[8] - H[2] * H[6]) / det;
+  Hi[5] = (H[2] * H[3] - H[0] * H[5]) / det;
+  Hi[6] = (H[3] * H[7] - H[4] * H[6]) / det;
+  Hi[7] = (H[1] * H[6] - H[0] * H[7]) / det;
+  Hi[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+  const double rc = 7.0 / alpha, kc = 2.0 * alpha * ORC_EWALD_X;
+  int nr[3], nk[3];
+  for (int k = 0; k < 3; ++k) {
+    double bk = sqrt(Hi[3 * k] * Hi[3 * k] + Hi[3 * k + 1] * Hi[3 * k + 1] +
+                     Hi[3 * k + 2] * Hi[3 * k + 2]);
+    double sk = Hi[3 * k] * x[0] + Hi[3 * k + 1] * x[1] + Hi[3 * k + 2] * x[2];
+    nr[k] = (int)ceil(rc * bk + fabs(sk)) + 1;
+    double ak = sqrt(H[k] * H[k] + H[3 + k] * H[3 + k] + H[6 + k] * H[6 + k]);
+    nk[k] = (int)ceil(kc * ak / (2.0 * M_PI)) + 1;
+  }
+  double real = 0.0;
+  for (int jz = -nr[2]; jz <= nr[2]; ++jz)
+    for (int jy = -nr[1]; jy <= nr[1]; ++jy)
+      for (int jx = -nr[0]; jx <= nr[0]; ++jx) {
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = x[k] + H[3 * k] * jx + H[3 * k + 1] * jy + H[3 * k + 2] * jz;
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 == 0.0) {
+          if (!reg) return INFINITY;
+          real -= pow(alpha, 6) / 6.0;
+          continue;
+        }
+        if (r2 > rc * rc) continue;
+        real += orc_r6_real(alpha, r2);
+      }
+  double recip = 0.0;
+  for (int mz = -nk[2]; mz <= nk[2]; ++mz)
+    for (int my = -nk[1]; my <= nk[1]; ++my)
+      for (int mx = -nk[0]; mx <= nk[0]; ++mx) {
+        double gk[3];
+        for (int j = 0; j < 3; ++j)
+          gk[j] = 2.0 * M_PI * (Hi[j] * mx + Hi[3 + j] * my + Hi[6 + j] * mz);
+        const double k = sqrt(gk[0] * gk[0] + gk[1] * gk[1] + gk[2] * gk[2]);
+        if (k > kc) continue;
+        const double b = k / (2.0 * alpha);
+        const double f = (1.0 - 2.0 * b * b) * exp(-b * b) + 2.0 * sqrt(M_PI) * b * b * b * erfc(b);
+        recip += f * cos(gk[0] * x[0] + gk[1] * x[1] + gk[2] * x[2]);
+      }
+  return real + pow(M_PI, 1.5) * alpha * alpha * alpha / (3.0 * V) * recip;
+}
+
 void orc_ewald_potentials_cell(const double H[9], double alpha, int n, const double* pos,
                                const double* q, double* phi)
 {

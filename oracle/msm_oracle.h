@@ -131,6 +131,8 @@ double orc_ewald2d_r6(const double box[3], int f, double alpha, const double x[3
 double orc_ewald1d_r6(const double box[3], int axis, double alpha, const double x[3], int reg);
 double orc_ewald_r6(const double box[3], unsigned mask, double alpha, const double x[3],
                     int reg);
+/* ... and over the lattice spanned by the columns of H. */
+double orc_ewald3d_cell_r6(const double H[9], double alpha, const double x[3], int reg);
 /* psi for the periodic axes of mask (bit k = axis k): 7, any two, any one. */
 double orc_ewald_psi(const double box[3], unsigned mask, double alpha, const double x[3],
                      int reg);

@@ -137,6 +137,8 @@ def lib():
         L.orc_ewald3d_r6.restype = d
         L.orc_ewald_r6.argtypes = [P, ctypes.c_uint, d, P, i]
         L.orc_ewald_r6.restype = d
+        L.orc_ewald3d_cell_r6.argtypes = [P, d, P, i]
+        L.orc_ewald3d_cell_r6.restype = d
         L.orc_ewald1d.argtypes = [P, i, d, P, i]
         L.orc_ewald1d.restype = d
         L.orc_ewald_psi.argtypes = [P, ctypes.c_uint, d, P, i]
@@ -318,6 +320,24 @@ def ewald_psi_cell(cell, x, alpha=None, reg=False):
     return lib().orc_ewald3d_cell(_ptr(H), float(alpha), _ptr(_f64(x)), int(reg))
 
 
+def ewald_psi_cell_r6(cell, x, alpha=None, reg=False):
+    """sum_n |x + H n|^-6 over the lattice spanned by the rows of cell."""
+    H = cell_matrix(cell)
+    if alpha is None:
+        alpha = ewald_alpha_cell(cell)
+    return lib().orc_ewald3d_cell_r6(_ptr(H), float(alpha), _ptr(_f64(x)), int(reg))
+
+
+def ewald_potentials_cell_r6(cell, pos, q, alpha=None):
+    """phi_i = sum_j q_j sum_n' |r_i - r_j + H n|^-6 (n = 0 left out for j = i)."""
+    pos, q = _f64(pos), _f64(q)
+    phi = np.zeros(len(q))
+    for i in range(len(q)):
+        for j in range(len(q)):
+            phi[i] += q[j] * ewald_psi_cell_r6(cell, pos[i] - pos[j], alpha, reg=(i == j))
+    return phi
+
+
 def ewald_potentials_cell(cell, pos, q, alpha=None):
     H = cell_matrix(cell)
     pos, q = _f64(pos), _f64(q)
@@ -358,9 +378,9 @@ class OracleMSM:
 
     nu: the kernel k(r) = r^-nu split the same way (gamma_nu: the Taylor
     polynomial of s^(-nu/2)); 1 is Coulomb, 6 the dispersion kernel, in free
-    space (the top level is the plain dense sum) or in an orthorhombic box
-    with any periodic axes (the top level sums k_L over the lattice of the
-    periodic axes with the Ewald method for r^-6).
+    space (the top level is the plain dense sum), in an orthorhombic box with
+    any periodic axes or in a triclinic cell (the top level sums k_L over the
+    lattice of the periodic axes with the Ewald method for r^-6).
     """
 
     def __init__(self, box, periodic, p, h, a, L, M=None, cell=None, ntop=None, nu=1):
@@ -376,9 +396,8 @@ class OracleMSM:
         self.periodic = [bool(x) for x in periodic]
         self.p, self.h, self.a, self.L = int(p), float(h), float(a), int(L)
         self.M = self.p if M is None else int(M)
-        self.nu = int(nu)  # kernel r^-nu: 1 anywhere, 6 in orthorhombic boxes
+        self.nu = int(nu)  # kernel r^-nu: 1 (Coulomb) or 6 (dispersion), any geometry
         assert self.nu in (1, 6)
-        assert self.nu == 1 or self.cell is None
         assert self.p % 2 == 0 and self.p >= 2 and 1 <= self.L <= MAXL
         for k in range(3):
             if self.periodic[k]:
@@ -494,7 +513,9 @@ class OracleMSM:
         R = 2 ** (L - 1) * a
         if self.cell is not None:
             # x is Cartesian; images x + H j over the lattice
-            val = ewald_psi_cell(self.cell, x, reg=True)
+            nu = self.nu
+            val = (ewald_psi_cell(self.cell, x, reg=True) if nu == 1
+                   else ewald_psi_cell_r6(self.cell, x, reg=True))
             s = self.Hinv @ np.asarray(x, dtype=np.float64)
             nimg = [int(math.ceil(R * float(np.linalg.norm(self.Hinv[k])) + abs(s[k]))) + 1
                     for k in range(3)]
@@ -504,9 +525,9 @@ class OracleMSM:
                         d = np.asarray(x) + self.H @ np.array([jx, jy, jz], dtype=np.float64)
                         r = float(np.sqrt(d @ d))
                         if r == 0.0:
-                            val += gamma(p, 0.0) / R
+                            val += gamma_nu(nu, p, 0.0) / R ** nu
                         elif r < R:
-                            val -= 1.0 / r - gamma(p, r / R) / R
+                            val -= r ** -nu - gamma_nu(nu, p, r / R) / R ** nu
             return val
         nu = self.nu
         if nu == 1:
@@ -750,7 +771,7 @@ class OracleMSM:
                     Hp = self.H.copy()
                     Hp[r, c] += sgn * eps * scale
                     o = OracleMSM(None, None, self.p, self.h, self.a, self.L, self.M,
-                                  cell=Hp.T, ntop=ntop)
+                                  cell=Hp.T, ntop=ntop, nu=self.nu)
                     E.append(o.compute(pos, q)["E"])
                 out[r, c] = (E[0] - E[1]) / (2 * eps * scale)
         return out

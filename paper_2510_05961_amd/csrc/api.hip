@@ -1021,6 +1021,19 @@ msm_status msm_plan_create_cell(msm_plan* out, const double cell[9], unsigned pe
                        quasi_degree_M, true, cell);
 }
 
+msm_status msm_plan_create_cell_kernel(msm_plan* out, int kernel, const double cell[9],
+                                       unsigned periodic_mask, int order, double h,
+                                       double cutoff_a, int levels, int precision, int max_n,
+                                       int quasi_degree_M) {
+  if (kernel != MSM_KERNEL_COULOMB && kernel != MSM_KERNEL_DISPERSION) {
+    if (out) *out = nullptr;
+    return MSM_ERR_INVALID_ARG;
+  }
+  if (!cell) return MSM_ERR_INVALID_ARG;
+  return create_common(out, nullptr, periodic_mask, order, h, cutoff_a, levels, precision, max_n,
+                       quasi_degree_M, true, cell, kernel);
+}
+
 msm_status msm_plan_set_cell(msm_plan plan, const double cell[9]) {
   if (!plan || plan->batch || !cell || !plan->hp.tri) return MSM_ERR_INVALID_ARG;
   if (!plan->device) return MSM_ERR_NO_DEVICE;
@@ -1032,7 +1045,8 @@ msm_status msm_energy_forces_cell_gradient(msm_plan plan, int n, const void* pos
                                            double* dEdH, void* stream) {
   if (!plan || plan->batch) return MSM_ERR_INVALID_ARG;
   if (!plan->device) return MSM_ERR_NO_DEVICE;
-  if (!plan->hp.tri) return MSM_ERR_UNSUPPORTED;
+  // the virial and derivative stencils are those of the Coulomb kernel
+  if (!plan->hp.tri || plan->hp.nu != 1) return MSM_ERR_UNSUPPORTED;
   if (n < 0 || !energy || !forces || !dEdH || (n > 0 && (!pos || !q))) return MSM_ERR_INVALID_ARG;
   if (n > plan->hp.max_n) return MSM_ERR_CAPACITY;
   hipStream_t s = (hipStream_t)stream;

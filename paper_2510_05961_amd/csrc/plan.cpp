@@ -557,13 +557,57 @@ static double ewald3d_cell(const double H[9], const double Hinv[9], const double
   return real + 4.0 * M_PI / V * rec - M_PI / (alpha * alpha * V);
 }
 
+// The lattice sum of r^-6 over {H n}: the terms of ewald3d_r6 with images H n
+// and wave vectors 2 pi H^{-T} m, V = |det H|.
+static double ewald3d_cell_r6(const double H[9], const double Hinv[9], const double x[3]) {
+  const double V = std::fabs(H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) +
+                             H[2] * (H[3] * H[7] - H[4] * H[6]));
+  const double alpha = 1.3 / std::cbrt(V);
+  const double rc = 7.2 / alpha, bc = 6.8;
+  int nr[3], nk[3];
+  for (int k = 0; k < 3; ++k) {
+    const double* b = Hinv + 3 * k;
+    const double bk = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    nr[k] = (int)std::ceil(rc * bk + std::fabs(b[0] * x[0] + b[1] * x[1] + b[2] * x[2])) + 1;
+    const double ak = std::sqrt(H[k] * H[k] + H[3 + k] * H[3 + k] + H[6 + k] * H[6 + k]);
+    nk[k] = (int)std::ceil(2.0 * alpha * bc * ak / (2.0 * M_PI)) + 1;
+  }
+  double val = 0.0;
+  for (int i = -nr[0]; i <= nr[0]; ++i)
+    for (int j = -nr[1]; j <= nr[1]; ++j)
+      for (int k = -nr[2]; k <= nr[2]; ++k) {
+        double d[3];
+        for (int c = 0; c < 3; ++c) d[c] = x[c] + H[3 * c] * i + H[3 * c + 1] * j + H[3 * c + 2] * k;
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 == 0.0)
+          val -= std::pow(alpha, 6) / 6.0;
+        else if (r2 < rc * rc)
+          val += r6_real(alpha, r2);
+      }
+  double rec = 0.0;
+  for (int i = -nk[0]; i <= nk[0]; ++i)
+    for (int j = -nk[1]; j <= nk[1]; ++j)
+      for (int k = -nk[2]; k <= nk[2]; ++k) {
+        double g[3];
+        for (int c = 0; c < 3; ++c) g[c] = 2.0 * M_PI * (Hinv[c] * i + Hinv[3 + c] * j + Hinv[6 + c] * k);
+        const double b = std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]) / (2.0 * alpha);
+        if (b >= bc) continue;
+        const double w = (1.0 - 2.0 * b * b) * std::exp(-b * b) +
+                         2.0 * std::sqrt(M_PI) * b * b * b * std::erfc(b);
+        rec += w * std::cos(g[0] * x[0] + g[1] * x[1] + g[2] * x[2]);
+      }
+  return val + std::pow(M_PI, 1.5) * alpha * alpha * alpha / (3.0 * V) * rec;
+}
+
 // Top-level kernel summed over periodic images: G(x) = psi(x) - sum_j s(|x+j|)
 // with s(r) = 1/r - gamma(r/R)/R for r < R (zero beyond), R = 2^(L-1) a, i.e.
 // the periodic sum of k_L(r) = gamma(r/R)/R with the 1/r tail Ewald-summed.
 static double periodic_top_G(const HostPlan& P, const double x[3]) {
   const double R = std::ldexp(P.a, P.L - 1);
   if (P.tri) {  // x Cartesian; images x + H j
-    double val = ewald3d_cell(P.H, P.Hinv, x);
+    const int nu = P.nu;
+    const double Rn = std::pow(R, nu);
+    double val = nu == 1 ? ewald3d_cell(P.H, P.Hinv, x) : ewald3d_cell_r6(P.H, P.Hinv, x);
     int ni[3];
     for (int k = 0; k < 3; ++k) {
       const double* b = P.Hinv + 3 * k;
@@ -578,9 +622,9 @@ static double periodic_top_G(const HostPlan& P, const double x[3]) {
             d[c] = x[c] + P.H[3 * c] * i + P.H[3 * c + 1] * j + P.H[3 * c + 2] * k;
           const double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
           if (r == 0.0)
-            val += P.gamma0 / R;
+            val += P.gamma0 / Rn;
           else if (r < R)
-            val -= 1.0 / r - gamma_t(P.gcoef, P.p, r / R) / R;
+            val -= std::pow(r, -nu) - gamma_t(P.gcoef, P.p, r / R, nu) / Rn;
         }
     return val;
   }
@@ -663,10 +707,9 @@ int build_host_plan(HostPlan& P, const double box_in[3], unsigned periodic_mask,
     }
   }
   if (order != 4 && order != 6 && order != 8) return MSM_ERR_UNSUPPORTED;
-  // kernels r^-nu: Coulomb (1) anywhere, dispersion (6) in orthorhombic boxes
-  // with any periodic axes (the top level by its lattice sums)
+  // kernels r^-nu: Coulomb (1) and dispersion (6), every geometry (the
+  // periodic top level by the lattice sums of each)
   if (nu != 1 && nu != 6) return MSM_ERR_INVALID_ARG;
-  if (nu != 1 && P.tri) return MSM_ERR_UNSUPPORTED;
   P.nu = nu;
   if (periodic_mask > 7) return MSM_ERR_INVALID_ARG;
   if (M < 0) M = order;

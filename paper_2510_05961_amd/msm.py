@@ -21,7 +21,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "cutoff too large
 _lib = None
 
 # every symbol declared in include/msm.h
-EXPORTS = ("msm_plan_create", "msm_plan_create_kernel", "msm_plan_create_cell", "msm_plan_set_cell",
+EXPORTS = ("msm_plan_create", "msm_plan_create_kernel", "msm_plan_create_cell",
+           "msm_plan_create_cell_kernel", "msm_plan_set_cell",
            "msm_plan_create_host", "msm_plan_destroy", "msm_plan_describe",
            "msm_plan_get_stencil", "msm_plan_grid_dims", "msm_workspace_bytes",
            "msm_energy_forces", "msm_energy_forces_noalloc", "msm_backward", "msm_backward_full",
@@ -57,6 +58,7 @@ def lib():
         L.msm_plan_create_host.argtypes = [pp, P, u, i, d, d, i, i, i, i]
         L.msm_plan_create_cell.argtypes = [pp, P, u, i, d, d, i, i, i, i]
         L.msm_plan_create_kernel.argtypes = [pp, i, P, u, i, d, d, i, i, i, i]
+        L.msm_plan_create_cell_kernel.argtypes = [pp, i, P, u, i, d, d, i, i, i, i]
         L.msm_plan_set_cell.argtypes = [P, P]
         L.msm_plan_destroy.argtypes = [P]
         L.msm_plan_describe.argtypes = [P, ctypes.c_char_p, sz]
@@ -126,9 +128,18 @@ class Plan:
                  max_n=1, quasi_degree=-1, device=True, cell=None, kernel=1):
         """cell: rows a, b, c of a triclinic cell (msm_plan_create_cell; box is
         then ignored and periodic_mask must be 7).  kernel: the power nu of
-        k(r) = r^-nu (1 Coulomb, 6 dispersion: msm_plan_create_kernel)."""
+        k(r) = r^-nu (1 Coulomb, 6 dispersion: msm_plan_create_kernel, or
+        msm_plan_create_cell_kernel with a cell)."""
         self._h = ctypes.c_void_p()
-        if kernel != 1:
+        if kernel != 1 and cell is not None:
+            c9 = (ctypes.c_double * 9)(*[float(x) for x in _flat9(cell)])
+            _check(lib().msm_plan_create_cell_kernel(ctypes.byref(self._h), int(kernel), c9,
+                                                     int(periodic_mask), int(order), float(h),
+                                                     float(cutoff), int(levels), int(precision),
+                                                     int(max_n), int(quasi_degree)),
+                   "msm_plan_create_cell_kernel")
+            box = (1.0, 1.0, 1.0)
+        elif kernel != 1:
             _check(lib().msm_plan_create_kernel(ctypes.byref(self._h), int(kernel), _dbl3(box),
                                                 int(periodic_mask), int(order), float(h),
                                                 float(cutoff), int(levels), int(precision),

@@ -31,21 +31,49 @@ def _run_batch(bp, off, pos, q):
     return E.cpu().numpy(), F.double().cpu().numpy(), dq.double().cpu().numpy()
 
 
+_ORACLE_CACHE = {}  # (fp64, system) -> oracle result of the fixed small batch
+
+
+@pytest.mark.parametrize("form", ["auto", "direct", "factored"])
+@pytest.mark.parametrize("tile", [None, "0", "1", "2"])
 @pytest.mark.parametrize("fp64", [True, False])
-def test_batch_matches_oracle_per_system(fp64):
+def test_batch_matches_oracle_per_system(fp64, tile, form):
+    """Every convolution tile shape (MSM_BATCH_TILE pins one; None lets the
+    autotuner choose) and both forms of the intermediate levels
+    (MSM_FACTORED) against the oracle, system by system."""
     off, boxes, pos, q, levels = _small_batch(40, seed=11)
     dt = np.float64 if fp64 else np.float32
     pos, q = pos.astype(dt).astype(np.float64), q.astype(dt).astype(np.float64)
-    bp = msm.BatchPlan(boxes, levels, 4, 1.0, 3.0, msm.MSM_FP64 if fp64 else msm.MSM_FP32,
-                       int(off[-1]))
-    print(bp.describe(), flush=True)
+    env = {}
+    if tile is not None:
+        env["MSM_BATCH_TILE"] = tile
+    if form != "auto":
+        env["MSM_FACTORED"] = "1" if form == "factored" else "0"
+    print(f"case batch oracle {'fp64' if fp64 else 'fp32'} tile={tile} form={form}", flush=True)
+    os.environ.update(env)
+    try:
+        bp = msm.BatchPlan(boxes, levels, 4, 1.0, 3.0, msm.MSM_FP64 if fp64 else msm.MSM_FP32,
+                           int(off[-1]))
+    finally:
+        for k in env:
+            del os.environ[k]
+    convs = bp.describe()["convs"]
+    if tile is not None:
+        assert all(c["tile_cfg"] == int(tile) for c in convs), convs
+    if form != "auto":
+        inter = [c for c in convs if not c["top"]]
+        assert all(c["factored"] == (form == "factored") for c in inter), convs
     E, F, dq = _run_batch(bp, off, pos, q)
     assert bp.status() == 0
     tol = TOL["fp64" if fp64 else "fp32"]
     for s in range(len(boxes)):
         a, b = off[s], off[s + 1]
-        b3 = (boxes[s],) * 3
-        ref = O.OracleMSM(b3, (0, 0, 0), 4, 1.0, 3.0, int(levels[s])).compute(pos[a:b], q[a:b])
+        key = (fp64, s)
+        if key not in _ORACLE_CACHE:
+            b3 = (boxes[s],) * 3
+            _ORACLE_CACHE[key] = O.OracleMSM(b3, (0, 0, 0), 4, 1.0, 3.0, int(levels[s])).compute(
+                pos[a:b], q[a:b])
+        ref = _ORACLE_CACHE[key]
         if b - a >= 2:
             assert_parity(F[a:b], ref["F"], tol["F"], f"F of system {s}")
         assert abs(E[s] - ref["E"]) <= tol["E"] * max(abs(ref["E"]), 1e-3), s

@@ -152,3 +152,46 @@ def test_r6_periodic_backward_matches_oracle(fp64):
     e1 = assert_parity(gpos.double().cpu().numpy(), rpos, tol, "grad_pos")
     e2 = assert_parity(gq.double().cpu().numpy(), rq, tol, "grad_q")
     print(f"  grad_pos {e1[0]:.1e} grad_q {e2[0]:.1e}", flush=True)
+
+
+TRI_CELL = np.array([[9.0, 0.0, 0.0], [2.1, 8.5, 0.0], [-1.3, 1.7, 9.4]])  # rows a, b, c
+
+
+def _tri_system(cell, n, seed):
+    s, _ = WL.spaced_charges(n, 1.0, True, seed=seed)  # spaced fractional positions
+    c = np.random.default_rng(seed + 1).uniform(0.5, 1.5, n)
+    return s @ np.asarray(cell), c
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_r6_triclinic_matches_oracle(fp64):
+    """A triclinic cell (msm_plan_create_cell_kernel): the top level sums k_L
+    over the lattice H n with the r^-6 Ewald method; then the plan moved to a
+    strained cell (msm_plan_set_cell) against the oracle of that cell."""
+    import torch
+    n, p, h, a, lev = 500, 4, 0.5, 4.0, 3
+    pos, c = _tri_system(TRI_CELL, n, seed=61)
+    pos, c = cast(pos, c, fp64)
+    prec = msm.MSM_FP64 if fp64 else msm.MSM_FP32
+    print(f"case r6 triclinic {'fp64' if fp64 else 'fp32'}", flush=True)
+    plan = msm.Plan(None, 7, p, h, a, lev, prec, n, cell=TRI_CELL, kernel=6)
+    assert plan.describe()["kernel_power"] == 6
+    tol = TOL["fp64" if fp64 else "fp32"]
+    for cell in (TRI_CELL, TRI_CELL @ np.array([[1.02, 0.01, 0.0], [0.0, 0.99, -0.02],
+                                                [0.01, 0.0, 1.01]])):
+        if cell is not TRI_CELL:
+            plan.set_cell(cell)
+            pos = (pos @ np.linalg.inv(TRI_CELL)) @ cell  # the same fractional positions
+        g = gpu_forward(plan, pos, c)
+        assert plan.status() == 0
+        ref = O.OracleMSM(None, None, p, h, a, lev, cell=cell, nu=6).compute(pos, c)
+        eE = abs(g["E"] - ref["E"]) / abs(ref["E"])
+        eF = assert_parity(g["F"], ref["F"], tol["F"], "F")
+        eP = assert_parity(g["phi"], ref["phi"], tol["phi"], "phi")
+        print(f"  relE {eE:.1e} relF {eF[0]:.1e} relPhi {eP[0]:.1e}", flush=True)
+        assert eE <= tol["E"]
+    # the cell derivative is built for the Coulomb kernel only
+    P = torch.tensor(pos, dtype=plan.dtype, device="cuda")
+    Q = torch.tensor(c, dtype=plan.dtype, device="cuda")
+    with pytest.raises(msm.MSMError):
+        plan.energy_forces_cell_gradient(P, Q)

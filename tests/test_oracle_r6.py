@@ -108,9 +108,50 @@ def test_msm_r6_sampled_equals_full():
     np.testing.assert_allclose(F, full["F"][sel], rtol=1e-12, atol=1e-14)
 
 
-def test_r6_triclinic_is_refused():
-    with pytest.raises(AssertionError):
-        O.OracleMSM(None, (1, 1, 1), 4, 1.0, 3.0, 2, nu=NU, cell=np.diag([10.0] * 3))
+CELL = np.array([[8.0, 0.0, 0.0], [1.5, 8.2, 0.0], [-1.0, 0.8, 8.4]])  # rows a, b, c
+
+
+def _cell_brute(cell, x, Ns=(16, 32, 64)):
+    """sum over |n_k| <= N of |x + H n|^-6, extrapolated in M = N + 1/2 as for
+    the orthorhombic blocks (a parallelepiped block is centrally symmetric)."""
+    H = np.asarray(cell, dtype=np.float64).T
+    T = []
+    for N in Ns:
+        r = np.arange(-N, N + 1, dtype=np.float64)
+        n = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+        d = n @ H.T + np.asarray(x, dtype=np.float64)
+        r2 = np.einsum("ij,ij->i", d, d)
+        T.append(float(np.sum(r2 ** -3)))
+    A = np.array([[1.0, (N + 0.5) ** -3, (N + 0.5) ** -5] for N in Ns])
+    return float(np.linalg.solve(A, T)[0])
+
+
+def test_r6_cell_lattice_sum():
+    x = (0.3, -0.7, 1.1)
+    # a diagonal cell is the orthorhombic box
+    box = (3.0, 3.5, 4.0)
+    assert O.ewald_psi_cell_r6(np.diag(box), x) == pytest.approx(O.ewald_psi_r6(box, x),
+                                                                   rel=1e-13)
+    vals = [O.ewald_psi_cell_r6(CELL, x, alpha=a) for a in (0.3, 0.5, 0.8)]
+    assert max(vals) - min(vals) <= 1e-13 * abs(vals[0])
+    # another basis of the same lattice, and the brute-force sum
+    cell2 = CELL.copy()
+    cell2[1] = CELL[1] + CELL[0]
+    cell2[2] = CELL[2] - CELL[1]
+    assert O.ewald_psi_cell_r6(cell2, x) == pytest.approx(vals[0], rel=1e-13)
+    assert vals[0] == pytest.approx(_cell_brute(CELL, x), rel=1e-10)
+
+
+def test_msm_r6_triclinic_converges_to_ewald():
+    pos, _ = WL.spaced_charges(60, 1.0, True, seed=23)
+    pos = pos @ CELL  # spaced fractional positions into the cell
+    c = np.random.default_rng(24).uniform(0.5, 1.5, 60)
+    phie = O.ewald_potentials_cell_r6(CELL, pos, c)
+    errs = []
+    for p, h in ((4, 0.5), (6, 0.5), (6, 0.4)):
+        r = O.OracleMSM(None, (1, 1, 1), p, h, 3.5, 3, cell=CELL, nu=NU).compute(pos, c)
+        errs.append(np.linalg.norm(r["phi"] - phie) / np.linalg.norm(phie))
+    assert errs[0] < 5e-5 and errs[0] > errs[1] > errs[2], errs
 
 
 # --------------------------------------------------------------------------
