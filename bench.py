@@ -19,7 +19,8 @@ coefficient for a convolution.
 Extras (each with its error against the FP64 oracle): the periodic water box,
 the learnable-charge box forward vs forward + backward (and through
 torch.autograd), the 4,096-cluster batch vs one plan per system, the
-free-space FP64 ion cloud, and the grid-pass HBM sweep.
+free-space FP64 ion cloud, the charged Lennard-Jonesium MD loop (steps/s
+and its NVE energy measure), and the grid-pass HBM sweep.
 
 Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -270,7 +271,8 @@ def _water(torch, msm, WL, np, O, steps, check):
                        "100 A cube, p=4, h=1.5625, a=10, L=5, FP32", "n": w.n,
            "particles_per_s": round(w.n / t, 1), "ms_per_step": round(t * 1e3, 4),
            "stages_ms_one_stream": {k: round(v["ms"] / v["launches"], 5) for k, v in st.items()},
-           "rooflines": _rooflines(w, st, _pair_count(2, w.pos_t))}
+           "rooflines": {k: dict(v, traffic=_measured_traffic("water100k_fp32", k))
+                         for k, v in _rooflines(w, st, _pair_count(2, w.pos_t)).items()}}
     if check:
         ref = w.oracle(O).compute(w.pos64, w.q64)
         out["energy_rel_err_vs_fp64_oracle"] = abs(w.E.item() - ref["E"]) / abs(ref["E"])
