@@ -40,7 +40,7 @@ struct HostPlan {
   double H[9], Hinv[9];
   int p, L, M;
   double h_req, a;
-  int nu = 1;      // the kernel r^-nu (1: Coulomb, 6: dispersion, free space only)
+  int nu = 1;      // the kernel r^-nu (1: Coulomb, 6: dispersion)
   int precision;   // 0 fp32, 1 fp64
   int max_n;
   // softener gamma(rho) = sum_k gcoef[k] t^k, t = rho^2, rho < 1
