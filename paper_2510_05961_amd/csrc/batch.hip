@@ -113,7 +113,8 @@ void destroy_batch(BatchState* b) {
 struct TileCfg {
   int R, TXT, TYT;
 };
-static const TileCfg kTiles[3] = {{4, 4, 16}, {4, 8, 16}, {2, 8, 8}};
+static const TileCfg kTiles[] = {{4, 4, 16}, {4, 8, 16}, {2, 8, 8}, {8, 4, 16}};
+constexpr int kNumTiles = 4;
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -594,7 +595,8 @@ static void launch_batch_conv(const BatchConv& bc, int cfg, const T* qcat, T* ec
   switch (cfg) {
     case 0: hipLaunchKernelGGL((k_batch_conv<T, 4, 4, 16>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, bc.fold, lds_w, scale, K, bc.rowext, qcat, ecat); break;
     case 1: hipLaunchKernelGGL((k_batch_conv<T, 4, 8, 16>), dim3(bc.ntasks), dim3(128), lds, s, bc.tasks, bc.off, bc.len, bc.fold, lds_w, scale, K, bc.rowext, qcat, ecat); break;
-    default: hipLaunchKernelGGL((k_batch_conv<T, 2, 8, 8>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, bc.fold, lds_w, scale, K, bc.rowext, qcat, ecat); break;
+    case 2: hipLaunchKernelGGL((k_batch_conv<T, 2, 8, 8>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, bc.fold, lds_w, scale, K, bc.rowext, qcat, ecat); break;
+    default: hipLaunchKernelGGL((k_batch_conv<T, 8, 4, 16>), dim3(bc.ntasks), dim3(64), lds, s, bc.tasks, bc.off, bc.len, bc.fold, lds_w, scale, K, bc.rowext, qcat, ecat); break;
   }
 }
 
@@ -760,13 +762,13 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
 // forms and top kernels: their grids differ in size) for every tile shape on
 // the plan's (zero) grids, a factored form with its three omega' passes;
 // keeps the fastest shape per candidate and the fastest candidate per group
-// (a level's direct and factored forms).  MSM_BATCH_TILE=c (0, 1 or 2) pins
+// (a level's direct and factored forms).  MSM_BATCH_TILE=c (0 .. 3) pins
 // shape c; the forms are still timed against each other.
 template <typename T>
 static msm_status autotune(msm_plan P) {
   BatchState& B = *P->bs;
   const char* pin = std::getenv("MSM_BATCH_TILE");
-  const bool pinned = pin && pin[0] >= '0' && pin[0] <= '2' && pin[1] == 0;
+  const bool pinned = pin && pin[0] >= '0' && pin[0] < '0' + kNumTiles && pin[1] == 0;
   hipStream_t s = nullptr;
   hipEvent_t a = nullptr, b = nullptr;
   ConvTask* dt = nullptr;
@@ -785,7 +787,7 @@ static msm_status autotune(msm_plan P) {
     int best_cfg = pinned ? pin[0] - '0' : 0;
     log << (ci ? "," : "") << "{\"level\":" << bc.level << ",\"top\":" << bc.top
         << ",\"factored\":" << bc.fact << ",\"ms\":[";
-    for (int cfg = pinned ? best_cfg : 0; cfg < (pinned ? best_cfg + 1 : 3); ++cfg) {
+    for (int cfg = pinned ? best_cfg : 0; cfg < (pinned ? best_cfg + 1 : kNumTiles); ++cfg) {
       std::vector<ConvTask> t = build_tasks(B, bc, cfg);
       if (hipMalloc((void**)&dt, std::max<size_t>(t.size(), 1) * sizeof(ConvTask))) {
         dt = nullptr;
@@ -974,7 +976,7 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
         if (l <= B.L[s] && ((B.L[s] == l) == (bc->top != 0))) any = true;
       if (!any) continue;
       int lw = kTiles[0].TXT * kTiles[0].R + bc->len - 1;
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < kNumTiles; ++c) {
         int w = kTiles[c].TXT * kTiles[c].R + bc->len - 1;
         if ((size_t)(w | 1) * (kTiles[c].TYT + bc->len - 1) * sizeof(T) > 160 * 1024)
           return MSM_ERR_GRID;

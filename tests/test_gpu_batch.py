@@ -35,7 +35,7 @@ _ORACLE_CACHE = {}  # (fp64, system) -> oracle result of the fixed small batch
 
 
 @pytest.mark.parametrize("form", ["auto", "direct", "factored"])
-@pytest.mark.parametrize("tile", [None, "0", "1", "2"])
+@pytest.mark.parametrize("tile", [None, "0", "1", "2", "3"])
 @pytest.mark.parametrize("fp64", [True, False])
 def test_batch_matches_oracle_per_system(fp64, tile, form):
     """Every convolution tile shape (MSM_BATCH_TILE pins one; None lets the
