@@ -372,19 +372,22 @@ struct OmegaTaps {
 };
 
 // One omega' pass of a factored level over every taking-part system: along
-// `axis`, out[c] = sum_{|k| <= M} w_|k| in[c - M - k] over input indices
-// 0..n-1 (zero outside), c = 0..n+2M-1; the axes before `axis` are already
-// extended to n + 2M, the axes after it not yet.  One thread per output
-// point, kOmegaBlock points per workgroup; bfirst[s] = first workgroup of
-// system s (systems that do not take part have none, so the last s with
-// bfirst[s] <= blockIdx.x owns the workgroup: a search uniform over it).
-// FP64 sums, stored in the grid precision.
+// axis AX, out[c] = sum_{|k| <= M} w_|k| in[c - M - k] over input indices
+// 0..n-1 (zero outside), c = 0..n+2M-1; the axes before AX are already
+// extended to n + 2M, the axes after it not yet.  Each thread computes OPT
+// consecutive outputs along AX from one register window of OPT + 2M inputs
+// (MT = M at compile time; MT = 0 takes M from w, one output per thread);
+// kOmegaBlock threads per workgroup; bfirst[s] = first workgroup of system s
+// (systems that do not take part have none, so the last s with bfirst[s] <=
+// blockIdx.x owns the workgroup: a search uniform over it).  FP64 sums,
+// stored in the grid precision.
 constexpr int kOmegaBlock = 256;
-template <typename T>
+constexpr int kOmegaOut = 4;  // outputs per thread when M is 4, 6 or 8
+template <typename T, int AX, int OPT, int MT>
 __global__ void __launch_bounds__(kOmegaBlock)
     k_batch_omega(int n_sys, const int* __restrict__ bfirst, const int* __restrict__ nn,
                   const long long* __restrict__ goff_in, const long long* __restrict__ goff_out,
-                  int axis, OmegaTaps w, const T* __restrict__ in, T* __restrict__ out) {
+                  OmegaTaps w, const T* __restrict__ in, T* __restrict__ out) {
   const int b = blockIdx.x;
   int lo = 0, hi = n_sys - 1;
   while (lo < hi) {
@@ -392,32 +395,52 @@ __global__ void __launch_bounds__(kOmegaBlock)
     if (bfirst[mid] <= b) lo = mid;
     else hi = mid - 1;
   }
-  const int s = lo, n = nn[s], M = w.M, ne = n + 2 * M;
-  int dout[3], din[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    dout[k] = k <= axis ? ne : n;
-    din[k] = k < axis ? ne : n;
-  }
-  // within one system every index fits 32 bits (n <= 512, M <= 24)
+  const int s = lo, n = nn[s], M = MT > 0 ? MT : w.M, ne = n + 2 * M;
+  // extents (within one system every index fits 32 bits: n <= 512, M <= 24)
+  const int o0 = ne, o1 = AX >= 1 ? ne : n, o2 = AX >= 2 ? ne : n;  // output
+  const int i0 = AX > 0 ? ne : n, i1 = AX > 1 ? ne : n;              // input (x, y)
+  const int na = (ne + OPT - 1) / OPT;  // thread positions along AX
+  const int t0 = AX == 0 ? na : o0, t1 = AX == 1 ? na : o1, t2 = AX == 2 ? na : o2;
   const int t = (b - bfirst[s]) * kOmegaBlock + (int)threadIdx.x;
-  if (t >= dout[0] * dout[1] * dout[2]) return;
-  int c[3];
-  c[0] = t % dout[0];
-  c[1] = (t / dout[0]) % dout[1];
-  c[2] = t / (dout[0] * dout[1]);
-  const int stride_in[3] = {1, din[0], din[0] * din[1]};
-  int base = 0;
+  if (t >= t0 * t1 * t2) return;
+  const int x = t % t0, y = (t / t0) % t1, z = t / (t0 * t1);
+  const int ca = (AX == 0 ? x : (AX == 1 ? y : z)) * OPT;  // first output along AX
+  // input offset of the line (AX coordinate 0) and its stride along AX
+  const int sa = AX == 0 ? 1 : (AX == 1 ? i0 : i0 * i1);
+  const int line_in = AX == 0 ? (y + z * i1) * i0 : (AX == 1 ? x + z * i0 * i1 : x + y * i0);
+  // output offset of the line and its stride along AX
+  const int so = AX == 0 ? 1 : (AX == 1 ? o0 : o0 * o1);
+  const int line_out = AX == 0 ? (y + z * o1) * o0 : (AX == 1 ? x + z * o0 * o1 : x + y * o0);
+  const T* src = in + goff_in[s] + line_in;
+  T* dst = out + goff_out[s] + line_out;
+  if constexpr (MT > 0) {
+    double win[OPT + 2 * MT];
 #pragma unroll
-  for (int k = 0; k < 3; ++k)
-    if (k != axis) base += c[k] * stride_in[k];
-  const T* src = in + goff_in[s] + base;
-  double acc = 0.0;
-  for (int k = -M; k <= M; ++k) {
-    const int i = c[axis] - M - k;
-    if (i >= 0 && i < n) acc += w.w[k < 0 ? -k : k] * (double)src[i * stride_in[axis]];
+    for (int j = 0; j < OPT + 2 * MT; ++j) {
+      const int i = ca - 2 * MT + j;
+      win[j] = (i >= 0 && i < n) ? (double)src[i * sa] : 0.0;
+    }
+#pragma unroll
+    for (int o = 0; o < OPT; ++o) {
+      if (ca + o >= ne) break;
+      double acc = 0.0;
+#pragma unroll
+      for (int k = -MT; k <= MT; ++k) acc += w.w[k < 0 ? -k : k] * win[o + MT - k];
+      dst[(ca + o) * so] = (T)acc;
+    }
+  } else {
+    double acc = 0.0;
+    for (int k = -M; k <= M; ++k) {
+      const int i = ca - M - k;
+      if (i >= 0 && i < n) acc += w.w[k < 0 ? -k : k] * (double)src[i * sa];
+    }
+    dst[ca * so] = (T)acc;
   }
-  out[goff_out[s] + t] = (T)acc;
+}
+
+// outputs per thread of k_batch_omega for a given M (its compile-time cases)
+inline int omega_outputs_per_thread(int M) {
+  return (M == 4 || M == 6 || M == 8) ? kOmegaOut : 1;
 }
 
 // Stencil convolution over a task list: each workgroup computes one output
@@ -632,9 +655,25 @@ static void launch_omega_passes(const BatchState& B, int l, hipStream_t s) {
   for (int ax = 0; ax < 3; ++ax) {
     const int g = B.pass_blocks[l - 1][ax];
     if (g <= 0) continue;
-    hipLaunchKernelGGL(k_batch_omega<T>, dim3(g), dim3(kOmegaBlock), 0, s, B.n_sys,
-                       B.d_bfirst[l - 1][ax], B.d_n[l - 1], gin[ax], B.d_goffe[l - 1], ax, w,
-                       in[ax], out[ax]);
+    const dim3 grid(g), block(kOmegaBlock);
+    const int* bf = B.d_bfirst[l - 1][ax];
+    const int* nn = B.d_n[l - 1];
+    const long long* go = B.d_goffe[l - 1];
+#define MSM_OMEGA_LAUNCH(AXV)                                                                   \
+  switch (B.M) {                                                                                \
+    case 4: hipLaunchKernelGGL((k_batch_omega<T, AXV, kOmegaOut, 4>), grid, block, 0, s, B.n_sys, bf, nn, gin[ax], go, w, in[ax], out[ax]); break; \
+    case 6: hipLaunchKernelGGL((k_batch_omega<T, AXV, kOmegaOut, 6>), grid, block, 0, s, B.n_sys, bf, nn, gin[ax], go, w, in[ax], out[ax]); break; \
+    case 8: hipLaunchKernelGGL((k_batch_omega<T, AXV, kOmegaOut, 8>), grid, block, 0, s, B.n_sys, bf, nn, gin[ax], go, w, in[ax], out[ax]); break; \
+    default: hipLaunchKernelGGL((k_batch_omega<T, AXV, 1, 0>), grid, block, 0, s, B.n_sys, bf, nn, gin[ax], go, w, in[ax], out[ax]); break; \
+  }
+    if (ax == 0) {
+      MSM_OMEGA_LAUNCH(0)
+    } else if (ax == 1) {
+      MSM_OMEGA_LAUNCH(1)
+    } else {
+      MSM_OMEGA_LAUNCH(2)
+    }
+#undef MSM_OMEGA_LAUNCH
   }
 }
 
@@ -906,7 +945,10 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
         if (B.L[s] <= l) continue;
         const long long n = B.n[l - 1][s], ne = n + 2 * B.M;
         acc += ne * ne * ne;
-        const long long cnt[3] = {ne * n * n, ne * ne * n, ne * ne * ne};
+        // threads per pass: OPT outputs each along the pass's axis
+        const int opt = omega_outputs_per_thread(B.M);
+        const long long na = (ne + opt - 1) / opt;
+        const long long cnt[3] = {na * n * n, ne * na * n, ne * ne * na};
         for (int ax = 0; ax < 3; ++ax) pa[ax] += (cnt[ax] + kOmegaBlock - 1) / kOmegaBlock;
       }
       if (pa[2] > (1LL << 31) - 1) return MSM_ERR_GRID;
