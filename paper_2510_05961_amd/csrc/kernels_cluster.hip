@@ -480,15 +480,26 @@ __device__ inline void for_each_j_culled(const PairParams<T>& pp, const int* cl_
             tail += __popcll(m2);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // the waiting full steps, each one's ring read issued a step ahead
+            // the waiting full steps, two per trip, each one's ring read issued
+            // a step ahead.  head is a multiple of kStepJ here, so a step's
+            // eight entries never wrap: lane jj reads ring[(head mod kRing) +
+            // jj], a per-lane base plus a wave-uniform offset.  The read ahead
+            // past the last step lands on an old slot of the ring and is unused.
             const int nst = (tail - head) / kStepJ;
             if (nst > 0) {
-              vec4_t<T> cur = ring[(head + jj) & (kRing - 1)];
-              for (int st = 0; st < nst; ++st) {
+              const vec4_t<T>* rl = ring + jj;
+              vec4_t<T> a = rl[head & (kRing - 1)];
+              int st = 0;
+              for (; st + 2 <= nst; st += 2) {
+                const vec4_t<T> b = rl[(head + kStepJ) & (kRing - 1)];
+                step(a);
+                a = rl[(head + 2 * kStepJ) & (kRing - 1)];
+                step(b);
+                head += 2 * kStepJ;
+              }
+              if (st < nst) {
+                step(a);
                 head += kStepJ;
-                const vec4_t<T> nxt = st + 1 < nst ? ring[(head + jj) & (kRing - 1)] : cur;
-                step(cur);
-                cur = nxt;
               }
             }
             __builtin_amdgcn_wave_barrier();
