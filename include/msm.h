@@ -107,9 +107,10 @@ msm_status msm_plan_create(msm_plan* out, const double box[3], unsigned periodic
  * msm_energy_forces.  One stream; allocates on its first call per cell
  * (stencils) and per plan (three FP64 level-1 grids).  The cutoff must stay
  * below half the cell's smallest width under a relative change of 1e-5 of
- * the cell (the top derivative builds such plans).  Errors: as
- * msm_energy_forces, MSM_ERR_UNSUPPORTED for non-triclinic plans and for
- * r^-6 plans (msm_plan_create_cell_kernel),
+ * the cell (the top derivative builds such plans).  r^-6 cell plans
+ * (msm_plan_create_cell_kernel) take the same call with their own kernel
+ * in every term (degree -6 homogeneity in place of -1).  Errors: as
+ * msm_energy_forces, MSM_ERR_UNSUPPORTED for non-triclinic plans,
  * MSM_ERR_GRID when a derivative stencil exceeds the convolution's window.
  */
 msm_status msm_energy_forces_cell_gradient(msm_plan plan, int n, const void* pos, const void* q,
@@ -150,8 +151,8 @@ msm_status msm_plan_create_kernel(msm_plan* out, int kernel, const double box[3]
  * (Sec. "MSM core algorithm", long-range part).  For r^-6 the top level sums
  * k_L over the lattice H n with the Ewald method for r^-6 (real space over
  * H n, reciprocal space over 2 pi H^{-T} m; no boundary term).  Every
- * compute call and msm_plan_set_cell work as for a Coulomb cell plan;
- * msm_energy_forces_cell_gradient is Coulomb only (MSM_ERR_UNSUPPORTED).
+ * compute call, msm_plan_set_cell and msm_energy_forces_cell_gradient work
+ * as for a Coulomb cell plan.
  */
 msm_status msm_plan_create_cell_kernel(msm_plan* out, int kernel, const double cell[9],
                                        unsigned periodic_mask, int order, double h,

@@ -1045,8 +1045,7 @@ msm_status msm_energy_forces_cell_gradient(msm_plan plan, int n, const void* pos
                                            double* dEdH, void* stream) {
   if (!plan || plan->batch) return MSM_ERR_INVALID_ARG;
   if (!plan->device) return MSM_ERR_NO_DEVICE;
-  // the virial and derivative stencils are those of the Coulomb kernel
-  if (!plan->hp.tri || plan->hp.nu != 1) return MSM_ERR_UNSUPPORTED;
+  if (!plan->hp.tri) return MSM_ERR_UNSUPPORTED;
   if (n < 0 || !energy || !forces || !dEdH || (n > 0 && (!pos || !q))) return MSM_ERR_INVALID_ARG;
   if (n > plan->hp.max_n) return MSM_ERR_CAPACITY;
   hipStream_t s = (hipStream_t)stream;

@@ -602,8 +602,8 @@ __global__ void __launch_bounds__(kClusterThreads)
 // pair within a (both orders; f = -k0'(r)/r, d = r_i - r_j of the image),
 // for the cell derivative: the same culled walk as k_pair_pc, six sums per
 // lane, reduced over the wave and added to acc[0..5] (xx, yy, zz, xy, xz, yz)
-// in FP64.
-template <typename T, int P>
+// in FP64.  NU: the kernel r^-NU.
+template <typename T, int P, int NU>
 __global__ void __launch_bounds__(kClusterThreads)
     k_pair_virial(const int* __restrict__ cl_start, const vec4_t<T>* __restrict__ cpos,
                   const vec4_t<T>* __restrict__ cbox, const int4* __restrict__ cinfo,
@@ -637,7 +637,9 @@ __global__ void __launch_bounds__(kClusterThreads)
         T pf = f_top;
 #pragma unroll
         for (int k = P - 3; k >= 0; --k) pf = pf * r2c + pp.fr[k];
-        const T fs = qj * (rinv * rinv * rinv + pf);
+        T kr, fr;
+        power_terms<NU>(rinv, kr, fr);
+        const T fs = qj * (fr + pf);
         vc[0] += fs * dx * dx;
         vc[1] += fs * dy * dy;
         vc[2] += fs * dz * dz;
@@ -893,10 +895,18 @@ void launch_pair_virial(int p, int n, int ncell, const int* cl_start, const vec4
   if (n <= 0) return;
   const int ncl = cluster_capacity(n, ncell);
   const dim3 grid((ncl + 3) / 4), block(kClusterThreads);
+  if (pp.nu == 6) {
+    switch (p) {
+      case 4: hipLaunchKernelGGL((k_pair_virial<T, 4, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
+      case 6: hipLaunchKernelGGL((k_pair_virial<T, 6, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
+      case 8: hipLaunchKernelGGL((k_pair_virial<T, 8, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
+    }
+    return;
+  }
   switch (p) {
-    case 4: hipLaunchKernelGGL((k_pair_virial<T, 4>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
-    case 6: hipLaunchKernelGGL((k_pair_virial<T, 6>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
-    case 8: hipLaunchKernelGGL((k_pair_virial<T, 8>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
+    case 4: hipLaunchKernelGGL((k_pair_virial<T, 4, 1>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
+    case 6: hipLaunchKernelGGL((k_pair_virial<T, 6, 1>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
+    case 8: hipLaunchKernelGGL((k_pair_virial<T, 8, 1>), grid, block, 0, s, cl_start, cpos, cbox, cinfo, pp, acc); break;
   }
 }
 

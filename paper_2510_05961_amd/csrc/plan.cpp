@@ -980,11 +980,11 @@ void cell_list_geometry(HostPlan& P) {
 // S^l(d) = k_l(|A_l d|), A_l = H diag(1/N_l); at fixed d, d/dH of k_l(|x|)
 // with x = A_l d is k_l'(|x|)/|x| x (H^{-1} x)^T, so the level contributes
 // 1/2 sum_m q~_m (T^l_ab * w)_m (H^{-T}) with T^l_ab(d) = k_l'(r)/r x_a x_b;
-// and T^l = T^1 / 2^(l-1) as for S.
+// and T^l = T^1 / 2^((l-1) nu) as for S (kernel r^-nu).
 
-// d gamma / d rho from the coefficients in t = rho^2
-static double gamma_t_d1(const double* c, int p, double rho) {
-  if (rho >= 1.0) return -1.0 / (rho * rho);
+// d gamma / d rho from the coefficients in t = rho^2 (kernel rho^-nu)
+static double gamma_t_d1(const double* c, int p, double rho, int nu) {
+  if (rho >= 1.0) return -nu * std::pow(rho, -nu - 1);
   const double t = rho * rho;
   double s = 2.0 * (p - 1) * c[p - 1];
   for (int k = p - 2; k >= 1; --k) s = s * t + 2.0 * k * c[k];
@@ -1001,7 +1001,8 @@ void cell_stress_stencils(const HostPlan& P, int l, std::vector<double> T[6]) {
     for (int c = 0; c < 3; ++c) A1[3 * r + c] = P.H[3 * r + c] * g1.h[c];
   const size_t vol = (size_t)g.s_len[0] * g.s_len[1] * g.s_len[2];
   for (int i = 0; i < 6; ++i) T[i].assign(vol, 0.0);
-  const double scale = std::ldexp(1.0, -(l - 1)), a = P.a;
+  const int nu = P.nu;
+  const double scale = std::ldexp(1.0, -(l - 1) * nu), a = P.a;
   for (int z = -R[2]; z <= R[2]; ++z)
     for (int y = -R[1]; y <= R[1]; ++y)
       for (int x = -R[0]; x <= R[0]; ++x) {
@@ -1010,9 +1011,9 @@ void cell_stress_stencils(const HostPlan& P, int l, std::vector<double> T[6]) {
         for (int k = 0; k < 3; ++k) v[k] = A1[3 * k] * x + A1[3 * k + 1] * y + A1[3 * k + 2] * z;
         const double r = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
         if (r == 0.0 || r >= 2.0 * a) continue;  // k_1 vanishes beyond 2a
-        // k_1 = gamma(r/a)/a - gamma(r/2a)/2a
-        const double kp = gamma_t_d1(P.gcoef, P.p, r / a) / (a * a) -
-                          gamma_t_d1(P.gcoef, P.p, r / (2.0 * a)) / (4.0 * a * a);
+        // k_1 = gamma(r/a)/a^nu - gamma(r/2a)/(2a)^nu
+        const double kp = gamma_t_d1(P.gcoef, P.p, r / a, nu) / std::pow(a, nu + 1) -
+                          gamma_t_d1(P.gcoef, P.p, r / (2.0 * a), nu) / std::pow(2.0 * a, nu + 1);
         const double f = scale * kp / r;
         int idx[3];
         for (int k = 0; k < 3; ++k) {

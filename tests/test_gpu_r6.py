@@ -190,8 +190,18 @@ def test_r6_triclinic_matches_oracle(fp64):
         eP = assert_parity(g["phi"], ref["phi"], tol["phi"], "phi")
         print(f"  relE {eE:.1e} relF {eF[0]:.1e} relPhi {eP[0]:.1e}", flush=True)
         assert eE <= tol["E"]
-    # the cell derivative is built for the Coulomb kernel only
+    # the cell derivative after the cell change: Euler's relation for an
+    # energy homogeneous of degree -6 (sum_ab H_ab dE/dH_ab at fixed
+    # fractional coordinates = -6 E, within the MSM error); its element-wise
+    # parity with the oracle is in the cell-gradient tests
     P = torch.tensor(pos, dtype=plan.dtype, device="cuda")
     Q = torch.tensor(c, dtype=plan.dtype, device="cuda")
-    with pytest.raises(msm.MSMError):
-        plan.energy_forces_cell_gradient(P, Q)
+    E, F, _, G = plan.energy_forces_cell_gradient(P, Q)
+    torch.cuda.synchronize()
+    assert plan.status() == 0
+    H = np.asarray(cell, dtype=np.float64).T
+    s = (np.linalg.inv(H) @ pos.T).T
+    G_s = G.cpu().numpy() - np.einsum("ia,ib->ab", F.double().cpu().numpy(), s)
+    euler = float(np.sum(H * G_s)) / (-6.0 * E.item())
+    print(f"  Euler relation {euler - 1:.1e}", flush=True)
+    assert abs(euler - 1) < 1e-3

@@ -7,6 +7,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2510_05961_amd import msm
+from paper_2510_05961_amd import workloads as WL
 
 from helpers import cast
 
@@ -55,6 +56,34 @@ def test_cell_gradient_matches_oracle(case):
     err = np.linalg.norm(G - ref) / np.linalg.norm(ref)
     print(f"  rel |dE/dH - FD| = {err:.2e}", flush=True)
     assert err < (1e-6 if fp64 else 2e-5)
+
+
+_R6_REF = {}
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_r6_cell_gradient_matches_oracle(fp64):
+    """The r^-6 kernel (msm_plan_create_cell_kernel): its own virial,
+    derivative stencils and top table in every term.  Spaced positions (no
+    pair closer than about 0.8: at 0.1 the stiff r^-6 pair terms of the
+    fixed-fractional derivative and of sum_i F_i s_i^T are 10^3 times the
+    result and cancel, beyond FP32); the inputs are FP32 values, so that
+    both precisions share one oracle derivative."""
+    n, p, h, a, L = 300, 4, 0.5, 4.0, 2
+    s, _ = WL.spaced_charges(n, 1.0, True, seed=71)
+    pos = s @ CELL
+    c = np.random.default_rng(72).uniform(0.5, 1.5, n)
+    pos, c = cast(pos, c, False)
+    print(f"case r6 cell gradient {'fp64' if fp64 else 'fp32'}", flush=True)
+    plan = msm.Plan(None, 7, p, h, a, L, msm.MSM_FP64 if fp64 else msm.MSM_FP32, n, cell=CELL,
+                    kernel=6)
+    _, _, G = _gpu(plan, pos, c)
+    if "G" not in _R6_REF:
+        _R6_REF["G"] = O.OracleMSM(None, None, p, h, a, L, cell=CELL, nu=6).cell_gradient(pos, c)
+    ref = _R6_REF["G"]
+    err = np.linalg.norm(G - ref) / np.linalg.norm(ref)
+    print(f"  rel |dE/dH - FD| = {err:.2e}", flush=True)
+    assert err < (1e-6 if fp64 else 1e-4)
 
 
 def test_cell_gradient_after_set_cell():

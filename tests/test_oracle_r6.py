@@ -154,6 +154,42 @@ def test_msm_r6_triclinic_converges_to_ewald():
     assert errs[0] < 5e-5 and errs[0] > errs[1] > errs[2], errs
 
 
+def test_msm_r6_cell_gradient():
+    """dE/dH of the r^-6 MSM energy (central differences in H, grid counts
+    held): the energy is homogeneous of degree -6 under r -> lambda r,
+    H -> lambda H, so sum_ab H_ab dE/dH_ab at fixed fractional coordinates
+    is -6 E for the exact lattice sum and, within the MSM error, for the MSM
+    one; and the whole 3x3 derivative approaches that of the exact sum
+    (the Ewald energy differentiated in H) as the order rises."""
+    n = 40
+    pos, _ = WL.spaced_charges(n, 1.0, True, seed=23)
+    pos = pos @ CELL
+    c = np.random.default_rng(24).uniform(0.5, 1.5, n)
+
+    def exact_energy(H):
+        return 0.5 * float(c @ O.ewald_potentials_cell_r6(H.T, pos, c))
+
+    errs = []
+    for p in (4, 6):
+        o = O.OracleMSM(None, (1, 1, 1), p, 0.5, 3.5, 3, cell=CELL, nu=NU)
+        r = o.compute(pos, c)
+        G = o.cell_gradient(pos, c)
+        s = (np.linalg.inv(o.H) @ pos.T).T
+        G_s = G - np.einsum("ia,ib->ab", r["F"], s)
+        assert float(np.sum(o.H * G_s)) == pytest.approx(-NU * r["E"], rel=1e-4)
+        if p == 4:
+            eps = 1e-5 * float(np.abs(o.H).max())
+            Gx = np.zeros((3, 3))
+            for a in range(3):
+                for b in range(3):
+                    Hp, Hm = o.H.copy(), o.H.copy()
+                    Hp[a, b] += eps
+                    Hm[a, b] -= eps
+                    Gx[a, b] = (exact_energy(Hp) - exact_energy(Hm)) / (2 * eps)
+        errs.append(np.linalg.norm(G - Gx) / np.linalg.norm(Gx))
+    assert errs[0] < 5e-4 and errs[1] < errs[0], errs
+
+
 # --------------------------------------------------------------------------
 # periodic r^-6: the 3-D Ewald sum of the dispersion kernel and the MSM on it
 # --------------------------------------------------------------------------
