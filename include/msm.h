@@ -135,7 +135,7 @@ msm_status msm_energy_forces_cell_gradient(msm_plan plan, int n, const void* pos
  * + n|^-6, the n = 0 term left out for i = j).  a/h of about 8 or more is
  * needed before the higher orders pay (the softened r^-6 is stiff).
  * Every compute call, the backward included, works as for Coulomb plans;
- * batched plans are Coulomb only.
+ * batched plans take r^-6 through msm_batch_plan_create_kernel.
  */
 #define MSM_KERNEL_COULOMB 1
 #define MSM_KERNEL_DISPERSION 6
@@ -353,6 +353,21 @@ msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const double* boxes,
                                  const int* levels, unsigned periodic_mask, int order, double h,
                                  double cutoff_a, int precision, int max_total_n,
                                  int quasi_degree_M);
+/*
+ * msm_batch_plan_create_kernel -- msm_batch_plan_create for the kernel
+ * k(r) = r^-nu, nu = kernel (MSM_KERNEL_COULOMB or MSM_KERNEL_DISPERSION;
+ * other values: MSM_ERR_INVALID_ARG), with the splitting described at
+ * msm_plan_create_kernel (Sec. "Splitting for Coulomb kernels": the softened
+ * pair part, K^1 and its k-sample ball, K^l = K^1 / 2^((l-1) nu) and each
+ * system's dense top table, all from the same softener of r^-nu).  Every
+ * system of the plan uses that kernel; msm_batch_energy_forces works as for
+ * a Coulomb batch.
+ */
+msm_status msm_batch_plan_create_kernel(msm_plan* out, int kernel, int n_sys,
+                                        const double* boxes, const int* levels,
+                                        unsigned periodic_mask, int order, double h,
+                                        double cutoff_a, int precision, int max_total_n,
+                                        int quasi_degree_M);
 /* offsets: device int32 [n_sys+1] CSR ranges into pos/q/forces/dEdq, with
  * offsets[0] = 0, non-decreasing, offsets[n_sys] <= max_total_n (checked on the
  * device: malformed offsets set the sticky flag, msm_plan_status then returns

@@ -48,7 +48,7 @@ struct ConvTask {
 struct BatchConv {
   int level;
   int top;       // 1: dense top kernel of the systems whose top level is `level`
-  double scale;  // multiplies the stencil (K^l = K^1 / 2^(l-1))
+  double scale;  // multiplies the stencil (K^l = K^1 / 2^((l-1) nu))
   int off, len;  // cubic stencil box: offsets off .. off+len-1 per axis
   int fold = 0;  // z-planes j and len-1-j share coefficients
   int cfg = 0;   // tile shape (kTiles), chosen per convolution by the autotuner
@@ -62,6 +62,7 @@ struct BatchConv {
 
 struct BatchState {
   int n_sys = 0, Lmax = 0, p = 0, M = 0, precision = 0, max_total_n = 0;
+  int nu = 1;  // the kernel r^-nu (1: Coulomb, 6: dispersion)
   double h = 0, a = 0, self_const = 0;
   double gcoef[kMaxOrder] = {};
   double J[kMaxOrder + 1] = {};
@@ -148,7 +149,7 @@ __device__ inline void load_clamped(const T* pos, int i, T box, T& x, T& y, T& z
   z = v[2];
 }
 
-template <typename T, int P>
+template <typename T, int P, int NU>
 __global__ void __launch_bounds__(kPairThreads)
     k_batch_pair(const int* __restrict__ off, int max_n, const T* __restrict__ pos,
                  const T* __restrict__ q, const T* __restrict__ boxes, PairParams<T> pp,
@@ -191,14 +192,29 @@ __global__ void __launch_bounds__(kPairThreads)
         const T r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < pp.a2 && jb + jj != i) {
           const T rinv = rsqrt_t(r2);
-          const T t = r2 * pp.inv_a2;
-          T Pt = pp.c[P - 1], dP = pp.dc[P - 2];
+          T fs;
+          if constexpr (NU == 1) {  // the softener in t = r^2 / a^2
+            const T t = r2 * pp.inv_a2;
+            T Pt = pp.c[P - 1], dP = pp.dc[P - 2];
 #pragma unroll
-          for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
+            for (int k = P - 2; k >= 0; --k) Pt = Pt * t + pp.c[k];
 #pragma unroll
-          for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
-          ph += (double)(pj.w * (rinv - Pt * pp.inv_a));
-          const T fs = pj.w * (rinv * rinv * rinv + T(2) * dP * pp.inv_a3);
+            for (int k = P - 3; k >= 0; --k) dP = dP * t + pp.dc[k];
+            ph += (double)(pj.w * (rinv - Pt * pp.inv_a));
+            fs = pj.w * (rinv * rinv * rinv + T(2) * dP * pp.inv_a3);
+          } else {
+            // r^-NU: the softener in r^2 with pre-scaled coefficients,
+            // gamma(r/a)/a^NU = sum er[k] r^2k, 2 gamma'(t)/a^(NU+2) = sum fr[k] r^2k
+            T pe = pp.er[P - 1], pf = pp.fr[P - 2];
+#pragma unroll
+            for (int k = P - 2; k >= 0; --k) pe = pe * r2 + pp.er[k];
+#pragma unroll
+            for (int k = P - 3; k >= 0; --k) pf = pf * r2 + pp.fr[k];
+            const T rinv2 = rinv * rinv;
+            const T kr = rinv2 * rinv2 * rinv2;
+            ph += (double)(pj.w * (kr - pe));
+            fs = pj.w * (T(NU) * kr * rinv2 + pf);
+          }
           fx += fs * dx;
           fy += fs * dy;
           fz += fs * dz;
@@ -722,10 +738,16 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
   pp.inv_a = (T)(1.0 / a);
   pp.inv_a3 = (T)(1.0 / (a * a * a));
   pp.inv_a5 = (T)(1.0 / (a * a * a * a * a));
+  pp.nu = B.nu;
   for (int k = 0; k < 8; ++k) {
     pp.c[k] = k < p ? (T)B.gcoef[k] : T(0);
     pp.dc[k] = (k + 1 < p) ? (T)((k + 1) * B.gcoef[k + 1]) : T(0);
     pp.d2c[k] = 0;
+    // t^k = r^2k / a^2k, scaled in FP64 before the cast
+    const double a2k = std::pow(a, 2 * k), anu = std::pow(a, B.nu);
+    pp.er[k] = k < p ? (T)(B.gcoef[k] / (a2k * anu)) : T(0);
+    pp.fr[k] = (k + 1 < p) ? (T)(2.0 * (k + 1) * B.gcoef[k + 1] / (a2k * anu * a * a)) : T(0);
+    pp.gr[k] = 0;
   }
   for (int k = 0; k < 3; ++k) {
     pp.box[k] = pp.inv_box[k] = 0;
@@ -737,10 +759,18 @@ static msm_status enqueue_batch(msm_plan P, const int* off, const T* pos, const 
   for (int k = 0; k < 9; ++k) pp.H[k] = 0;
   const T* boxes = (const T*)B.d_box;
   int ev = P->prof.begin("batch_pair", s);
-  switch (p) {
-    case 4: hipLaunchKernelGGL((k_batch_pair<T, 4>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
-    case 6: hipLaunchKernelGGL((k_batch_pair<T, 6>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
-    default: hipLaunchKernelGGL((k_batch_pair<T, 8>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
+  if (B.nu == 6) {
+    switch (p) {
+      case 4: hipLaunchKernelGGL((k_batch_pair<T, 4, 6>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
+      case 6: hipLaunchKernelGGL((k_batch_pair<T, 6, 6>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
+      default: hipLaunchKernelGGL((k_batch_pair<T, 8, 6>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
+    }
+  } else {
+    switch (p) {
+      case 4: hipLaunchKernelGGL((k_batch_pair<T, 4, 1>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
+      case 6: hipLaunchKernelGGL((k_batch_pair<T, 6, 1>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
+      default: hipLaunchKernelGGL((k_batch_pair<T, 8, 1>), dim3(NS), dim3(kPairThreads), 0, s, off, maxn, pos, q, boxes, pp, (double*)B.phi0, (T*)B.F0, B.flag); break;
+    }
   }
   P->prof.end(ev, s);
   const int nb = (std::max(maxn, 1) + 255) / 256;
@@ -981,7 +1011,7 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
     BatchConv inter;
     inter.level = l;
     inter.top = 0;
-    inter.scale = std::ldexp(1.0, -(l - 1));
+    inter.scale = std::ldexp(1.0, -(l - 1) * B.nu);
     inter.group = group++;
     inter.off = -W1;
     inter.len = 2 * W1 + 1;
@@ -1062,11 +1092,14 @@ static msm_status upload_batch(msm_plan P, const std::vector<double>& K1, int W1
 
 using namespace msm;
 
-extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const double* boxes,
-                                            const int* levels, unsigned periodic_mask, int order,
-                                            double h, double cutoff_a, int precision,
-                                            int max_total_n, int quasi_degree_M) {
+extern "C" msm_status msm_batch_plan_create_kernel(msm_plan* out, int kernel, int n_sys,
+                                                   const double* boxes, const int* levels,
+                                                   unsigned periodic_mask, int order, double h,
+                                                   double cutoff_a, int precision,
+                                                   int max_total_n, int quasi_degree_M) {
   if (!out) return MSM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (kernel != MSM_KERNEL_COULOMB && kernel != MSM_KERNEL_DISPERSION) return MSM_ERR_INVALID_ARG;
   *out = nullptr;
   if (n_sys < 1 || !boxes || !levels || !(h > 0) || !(cutoff_a > 0) || max_total_n < 0)
     return MSM_ERR_INVALID_ARG;
@@ -1105,6 +1138,7 @@ extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const doub
     B.h = h;
     B.a = cutoff_a;
     B.precision = precision;
+    B.nu = kernel;
     B.max_total_n = max_total_n;
     B.box.resize(n_sys);
     for (int s = 0; s < n_sys; ++s) B.box[s] = boxes[3 * (size_t)s];
@@ -1115,8 +1149,8 @@ extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const doub
       B.Lmax = std::max(B.Lmax, B.L[s]);
     }
     if (st == MSM_OK) {
-      softener_coefficients(order, B.gcoef);
-      B.self_const = B.gcoef[0] / cutoff_a;
+      softener_coefficients(order, B.gcoef, B.nu);
+      B.self_const = B.gcoef[0] / std::pow(cutoff_a, B.nu);
       B.omega = quasi_sequence(order, M);
       for (int k = 0; k <= order; ++k) {
         double c = 1.0;
@@ -1147,9 +1181,9 @@ extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const doub
     std::vector<int> top_len(kMaxLevels + 1, 0);
     if (st == MSM_OK) {
       const double h3[3] = {h, h, h};
-      level1_stencil(order, M, cutoff_a, h3, W, K1, B.gcoef);
+      level1_stencil(order, M, cutoff_a, h3, W, K1, B.gcoef, nullptr, B.nu);
       const int R1[3] = {W[0] - M, W[1] - M, W[2] - M};
-      level1_samples(order, cutoff_a, h3, R1, B.gcoef, S1);
+      level1_samples(order, cutoff_a, h3, R1, B.gcoef, S1, B.nu);
       for (int l = 1; l <= B.Lmax; ++l) {
         int nmax = 0;
         for (int s = 0; s < n_sys; ++s)
@@ -1158,7 +1192,7 @@ extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const doub
         const double hl = std::ldexp(h, l - 1);
         const double hl3[3] = {hl, hl, hl};
         const int n3[3] = {nmax, nmax, nmax};
-        free_top_kernel(order, M, cutoff_a, l, hl3, n3, B.omega, B.gcoef, tops[l]);
+        free_top_kernel(order, M, cutoff_a, l, hl3, n3, B.omega, B.gcoef, tops[l], B.nu);
         top_len[l] = 2 * nmax - 1;
       }
       st = precision == MSM_FP64 ? upload_batch<double>(P, K1, W[0], S1, W[0] - M, tops, top_len)
@@ -1224,13 +1258,23 @@ extern "C" msm_status msm_batch_energy_forces(msm_plan plan, const int* offsets,
   return MSM_OK;
 }
 
+extern "C" msm_status msm_batch_plan_create(msm_plan* out, int n_sys, const double* boxes,
+                                            const int* levels, unsigned periodic_mask, int order,
+                                            double h, double cutoff_a, int precision,
+                                            int max_total_n, int quasi_degree_M) {
+  return msm_batch_plan_create_kernel(out, MSM_KERNEL_COULOMB, n_sys, boxes, levels,
+                                      periodic_mask, order, h, cutoff_a, precision, max_total_n,
+                                      quasi_degree_M);
+}
+
 // JSON of the batch plan (systems, grids, autotuner result) for describe.
 std::string describe_batch(const msm::BatchState& B) {
   std::ostringstream o;
   o.precision(17);
   long long G1 = B.Gtot[0];
   o << "{\"batch\":true,\"n_sys\":" << B.n_sys << ",\"order\":" << B.p << ",\"M\":" << B.M
-    << ",\"h\":" << B.h << ",\"cutoff\":" << B.a << ",\"max_levels\":" << B.Lmax
+    << ",\"h\":" << B.h << ",\"cutoff\":" << B.a << ",\"kernel_power\":" << B.nu
+    << ",\"max_levels\":" << B.Lmax
     << ",\"precision\":\"" << (B.precision ? "fp64" : "fp32") << "\",\"grid1_points\":" << G1
     << ",\"tile_cfg\":" << B.tile_cfg << ",\"autotune\":" << (B.tuning.empty() ? "[]" : B.tuning)
     << ",\"convs\":[";

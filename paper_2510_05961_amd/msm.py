@@ -29,7 +29,8 @@ EXPORTS = ("msm_plan_create", "msm_plan_create_kernel", "msm_plan_create_cell",
            "msm_plan_status", "msm_plan_set_skin", "msm_plan_skin_stats",
            "msm_energy_forces_cell_gradient",
            "msm_plan_get_grid",
-           "msm_batch_plan_create", "msm_batch_energy_forces", "msm_status_string",
+           "msm_batch_plan_create", "msm_batch_plan_create_kernel", "msm_batch_energy_forces",
+           "msm_status_string",
            "msm_plan_set_profiling", "msm_plan_get_profile", "msm_plan_set_profile_stages",
            "msm_md_create", "msm_md_destroy", "msm_md_set_state", "msm_md_run",
            "msm_md_get_state", "msm_md_energies")
@@ -77,6 +78,7 @@ def lib():
         L.msm_plan_status.argtypes = [P, P]
         L.msm_plan_get_grid.argtypes = [P, i, i, P, P]
         L.msm_batch_plan_create.argtypes = [pp, i, P, P, u, i, d, d, i, i, i]
+        L.msm_batch_plan_create_kernel.argtypes = [pp, i, i, P, P, u, i, d, d, i, i, i]
         L.msm_batch_energy_forces.argtypes = [P, P, P, P, P, P, P, P, P]
         L.msm_plan_set_profiling.argtypes = [P, i]
         L.msm_plan_get_profile.argtypes = [P, ctypes.c_char_p, sz, i]
@@ -310,8 +312,9 @@ class BatchPlan:
     """Many free-space systems in one launch sequence (msm_batch_plan_create)."""
 
     def __init__(self, boxes, levels, order, h, cutoff, precision=MSM_FP32, max_total_n=1,
-                 quasi_degree=-1, periodic_mask=0):
-        """boxes: [n_sys, 3] edge lengths, or [n_sys] edges of cubes."""
+                 quasi_degree=-1, periodic_mask=0, kernel=1):
+        """boxes: [n_sys, 3] edge lengths, or [n_sys] edges of cubes; kernel:
+        the power nu of k(r) = r^-nu (1 Coulomb, 6 dispersion)."""
         import numpy as np
         self._h = ctypes.c_void_p()
         b = np.asarray(boxes, dtype=np.float64)
@@ -320,13 +323,23 @@ class BatchPlan:
         b = np.ascontiguousarray(b)
         lv = np.ascontiguousarray(levels, dtype=np.int32)
         self.n_sys = len(b)
-        _check(lib().msm_batch_plan_create(ctypes.byref(self._h), self.n_sys,
-                                           b.ctypes.data_as(ctypes.c_void_p),
-                                           lv.ctypes.data_as(ctypes.c_void_p),
-                                           int(periodic_mask), int(order),
-                                           float(h), float(cutoff), int(precision),
-                                           int(max_total_n), int(quasi_degree)),
-               "msm_batch_plan_create")
+        if kernel == 1:
+            _check(lib().msm_batch_plan_create(ctypes.byref(self._h), self.n_sys,
+                                               b.ctypes.data_as(ctypes.c_void_p),
+                                               lv.ctypes.data_as(ctypes.c_void_p),
+                                               int(periodic_mask), int(order),
+                                               float(h), float(cutoff), int(precision),
+                                               int(max_total_n), int(quasi_degree)),
+                   "msm_batch_plan_create")
+        else:
+            _check(lib().msm_batch_plan_create_kernel(ctypes.byref(self._h), int(kernel),
+                                                      self.n_sys,
+                                                      b.ctypes.data_as(ctypes.c_void_p),
+                                                      lv.ctypes.data_as(ctypes.c_void_p),
+                                                      int(periodic_mask), int(order),
+                                                      float(h), float(cutoff), int(precision),
+                                                      int(max_total_n), int(quasi_degree)),
+                   "msm_batch_plan_create_kernel")
         self.precision = int(precision)
 
     close = Plan.close
